@@ -1,0 +1,188 @@
+/*
+ * tplbm.h -- C ABI of the MI355X (gfx950) thermal pseudopotential lattice
+ * Boltzmann library.
+ *
+ * The method is the per-step lattice update of Czelusniak, Cabezas Gomez and
+ * Wagner, arXiv 2301.12869, Sec. III ("Pseudopotential lattice Boltzmann
+ * method"): the lattice Boltzmann equation (Eq. LBE) with the MRT collision
+ * (Eqs. OperatorMRT, MatrixMRT, RelaxationMatrix), Li's forcing scheme
+ * (Eq. LiFS), the force-corrected velocity (Eqs. Density, Momentum), the
+ * second-order equilibrium (Eq. EquilibriumDistribution), the Shan-Chen
+ * nearest-neighbour force (Eq. ShanChenForce) on the Yuan-Schaefer
+ * pseudopotential (Eq. InteractionPotential) of the Carnahan-Starling EOS
+ * (Eq. EOS), the two gravity forms of Sec. II (Eqs. Gravity_1, Gravity_2),
+ * Zou-He no-slip wet-node walls with zero interaction force at the wall, and
+ * the energy equation (Eq. Energy_Equation) with isotropic second-order
+ * differences and a two-stage Runge-Kutta step.
+ *
+ * Conventions shared by every entry point
+ *  - Status: every int-returning call returns TPLBM_OK (0) or one of the
+ *    TPLBM_E* codes below; no call aborts the process or throws.  After a
+ *    failure tplbm_last_error() gives a message.
+ *  - Memory: the library never allocates device memory.  The caller passes
+ *    one device workspace (size from the *_workspace_bytes call), keeps it
+ *    alive until the matching destroy, and owns it.  Host arrays passed in
+ *    are read or written during the call only and stay owned by the caller.
+ *  - Streams: all device work is enqueued on the HIP stream given at create
+ *    time (NULL = the legacy default stream).  Calls documented as
+ *    synchronous wait for that stream before returning.
+ *  - Layout (structure of arrays, x fastest): D2Q9 node (x, y) has linear
+ *    index y*nx + x; D3Q19 node (x, y, z) has (z*ny + y)*nx + x; a D1Q3
+ *    column node y has index y.  The wall-normal axis (walls at its first
+ *    and last layer) is y in 2-D, z in 3-D and the column axis in 1-D; the
+ *    other axes are periodic.  Gravity g > 0 points toward the first layer
+ *    ("down").
+ *  - Units: lattice units throughout; temperatures are absolute (multiply a
+ *    reduced T/T_c by tplbm_eos_critical()'s T_c).
+ */
+#ifndef TPLBM_H
+#define TPLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define TPLBM_OK 0
+#define TPLBM_EINVAL 1          /* bad argument or parameter value */
+#define TPLBM_ESHAPE 2          /* sizes do not fit the lattice or buffer */
+#define TPLBM_EUNSUPPORTED 3    /* valid but not implemented (e.g. tau != 1 on D3Q19) */
+#define TPLBM_EHIP 4            /* a HIP runtime call failed */
+#define TPLBM_EUNPHYSICAL 5     /* NaN, rho <= 0, eta >= 1 or negative psi radicand seen */
+#define TPLBM_ENOTCONVERGED 6   /* a host solve did not converge */
+
+/* ---- enumerations ---- */
+#define TPLBM_D1Q3 1
+#define TPLBM_D2Q9 2
+#define TPLBM_D3Q19 3
+
+#define TPLBM_FP64 0            /* populations stored in FP64 */
+#define TPLBM_FP32_DEV 1        /* populations stored in FP32 as f_i - w_i rho_ref */
+
+#define TPLBM_EOS_CARNAHAN_STARLING 0
+#define TPLBM_EOS_IDEAL_LATTICE 1 /* p = rho/3, psi = 0: for tests of the closed forms */
+
+/* fields for tplbm_read / tplbm_read_device */
+#define TPLBM_RHO 0
+#define TPLBM_UX 1
+#define TPLBM_UY 2
+#define TPLBM_UZ 3
+#define TPLBM_T 4
+#define TPLBM_P_EOS 5
+#define TPLBM_P_NN 6            /* normal pressure: wall-normal diagonal of Eq. GeneralPressureTensor */
+
+/* unphysical-state flags (tplbm_diag.flags) */
+#define TPLBM_FLAG_NAN 1u
+#define TPLBM_FLAG_RHO 2u       /* rho <= 0 */
+#define TPLBM_FLAG_ETA 4u       /* b rho / 4 >= 1 (EOS pole) */
+#define TPLBM_FLAG_PSI 8u       /* 2 (p_EOS - rho/3)/G < 0: psi undefined */
+
+/*
+ * Lattice parameters.  Paper values (Sec. IV.B): a = 0.5, b = 4, R = 1,
+ * sigma = 1.385, every tau = 1, c_v = 5, kappa = 0.02; G = -1 (the sign that
+ * makes psi real for this EOS; |G| enters only through the sigma term).
+ */
+typedef struct tplbm_params {
+    int32_t lattice;        /* TPLBM_D2Q9 or TPLBM_D3Q19 (columns: tplbm_batch_*) */
+    int32_t nx, ny, nz;     /* nodes per axis; nz ignored for D2Q9 */
+    int32_t walls;          /* 1: wet-node walls on the wall-normal axis; 0: periodic */
+    int32_t precision;      /* TPLBM_FP64 or TPLBM_FP32_DEV */
+    int32_t eos;            /* TPLBM_EOS_* */
+    int32_t gravity_form;   /* 1: F_g = rho g (Eq. Gravity_1); 2: (rho - <rho>) g (Eq. Gravity_2) */
+    double a, b, R;         /* Carnahan-Starling constants (Eq. EOS) */
+    double G;               /* Eq. InteractionPotential, c = 1; must be < 0 for C-S */
+    double sigma;           /* Eq. LiFS */
+    double tau[6];          /* tau_rho, tau_e, tau_varsigma, tau_j, tau_q, tau_nu (> 1/2) */
+    double cv, kappa;       /* Eq. Energy_Equation */
+    double g;               /* gravity magnitude along -(wall-normal axis) */
+    double rho_ref;         /* FP32_DEV reference density; ignored for FP64 */
+} tplbm_params;
+
+/* Diagnostics of the time level `step` (the level the last step started from). */
+typedef struct tplbm_diag {
+    int64_t step;           /* number of completed steps */
+    int64_t first_bad_step; /* level at which a flag was first raised, -1 if none */
+    double mass;            /* sum of rho over all nodes at level `step` */
+    double mean_rho;        /* <rho> at level `step` (wall nodes included) */
+    double max_u;           /* max |u| at level step-1 (the last step's velocity) */
+    double min_rho;         /* min rho at level step-1 */
+    uint32_t flags;         /* OR of TPLBM_FLAG_* over every step since set_state */
+    uint32_t pad;
+} tplbm_diag;
+
+typedef struct tplbm_ctx tplbm_ctx;
+
+/* Bytes of device workspace for a lattice with these parameters (pure). */
+int tplbm_workspace_bytes(const tplbm_params *p, size_t *bytes);
+
+/* Validate p, bind the workspace and stream, compute host constants.
+ * dev_workspace must be at least tplbm_workspace_bytes() bytes, 256-byte
+ * aligned.  *out receives a host handle owned by the library.
+ * Errors: EINVAL (parameters), ESHAPE (sizes), EUNSUPPORTED, EHIP. */
+int tplbm_create(const tplbm_params *p, void *dev_workspace, size_t bytes, void *hip_stream,
+                 tplbm_ctx **out);
+
+/* Set the state at level 0 from host arrays of N doubles each (N = node
+ * count): populations at rest, f_i = w_i rho0 (reading of the paper's
+ * unstated initial condition), and T0.  T0 on the wall layers is kept fixed
+ * as Dirichlet data (the paper's T_bot / T_top, Sec. IV).  Synchronous.
+ * Errors: EINVAL on NULL, EHIP. */
+int tplbm_set_state(tplbm_ctx *ctx, const double *rho0, const double *T0);
+
+/* Advance nsteps >= 0 steps (one fused kernel launch per step), then wait
+ * and check the flags: returns TPLBM_EUNPHYSICAL if any step raised one
+ * (tplbm_diagnostics gives the first such level).  Synchronous. */
+int tplbm_step(tplbm_ctx *ctx, int64_t nsteps);
+
+/* Same, without waiting or checking (for timing and capture by callers). */
+int tplbm_step_async(tplbm_ctx *ctx, int64_t nsteps);
+
+/* Macroscopic field of the current level into a host array of N doubles
+ * (TPLBM_RHO, TPLBM_UX/UY/UZ: force-corrected velocity of Eq. Momentum,
+ * TPLBM_T, TPLBM_P_EOS, TPLBM_P_NN: normal pressure with plain central
+ * differences, interior nodes only; wall nodes report p_EOS).  Synchronous.
+ * Errors: EINVAL (field), EHIP. */
+int tplbm_read(tplbm_ctx *ctx, int field, double *host_out);
+
+/* Same into a device array of N doubles, enqueued on the stream (async). */
+int tplbm_read_device(tplbm_ctx *ctx, int field, double *dev_out);
+
+/* Diagnostics of the last completed step.  Synchronous. */
+int tplbm_diagnostics(tplbm_ctx *ctx, tplbm_diag *out);
+
+/* Exact checkpoint of the state (populations, temperature, <rho>, step
+ * count) to a host blob of tplbm_state_bytes() bytes and back.
+ * Synchronous.  Restoring and stepping reproduces an uninterrupted run bit
+ * for bit. */
+int tplbm_state_bytes(const tplbm_ctx *ctx, size_t *bytes);
+int tplbm_save_state(tplbm_ctx *ctx, void *host_blob);
+int tplbm_load_state(tplbm_ctx *ctx, const void *host_blob);
+
+/* Release the host handle (the workspace stays the caller's). NULL is a no-op. */
+void tplbm_destroy(tplbm_ctx *ctx);
+
+/* Message of the last failure on ctx, or of the last failed call made with
+ * no context when ctx is NULL.  Never NULL. */
+const char *tplbm_last_error(const tplbm_ctx *ctx);
+
+/* ---- host FP64 equation-of-state utilities (Eq. EOS, Eq. MaxwellRule) ---- */
+
+/* Critical point of Carnahan-Starling with constants a, b, R (the point
+ * where dp/drho = d2p/drho2 = 0): out3 = {rho_c, T_c, p_c}. */
+int tplbm_eos_critical(double a, double b, double R, double *out3);
+
+/* Coexistence at absolute temperature T by the equal-area rule
+ * (Eq. MaxwellRule): out3 = {rho_v, rho_l, p_sat}.  EINVAL at or above T_c. */
+int tplbm_eos_coexistence(double a, double b, double R, double T, double *out3);
+
+/* Spinodal densities at T (local extrema of p_EOS, Sec. V):
+ * out2 = {vapour spinodal, liquid spinodal}.  EINVAL at or above T_c. */
+int tplbm_eos_spinodal(double a, double b, double R, double T, double *out2);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TPLBM_H */

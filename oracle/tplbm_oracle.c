@@ -465,9 +465,12 @@ static void d2q9_step_once(const orc_params *P, double *f, double *T, d2_work *w
         }
 
     /* MRT collision with Li's forcing (Eqs. LBE, OperatorMRT, LiFS) */
-    double Minv[9][9], L[9];
-    m2_inverse(Minv);
+    double L[9], nrm[9];
     d2q9_lambda(P, L);
+    for (int k = 0; k < 9; ++k) {
+        nrm[k] = 0;
+        for (int i = 0; i < 9; ++i) nrm[k] += M2[k][i] * M2[k][i];
+    }
     for (int n = 0; n < N; ++n) {
         double fl[9], fe[9], m[9], me[9], S[9], ms[9];
         for (int i = 0; i < 9; ++i) fl[i] = f[i * N + n];
@@ -479,11 +482,15 @@ static void d2q9_step_once(const orc_params *P, double *f, double *T, d2_work *w
             m[k] = 0; me[k] = 0;
             for (int i = 0; i < 9; ++i) { m[k] += M2[k][i] * fl[i]; me[k] += M2[k][i] * fe[i]; }
         }
+        /* the mass moment is a collision invariant (Sec. III, after Eq.
+         * RelaxationMatrix): its equilibrium value is the density itself */
+        me[0] = m[0];
         for (int k = 0; k < 9; ++k)
             ms[k] = m[k] - L[k] * (m[k] - me[k]) + (1.0 - L[k] / 2.0) * S[k];
+        /* f* = M^{-1} m* = M^T diag(1/|row_k|^2) m*, dividing by the row norms */
         for (int i = 0; i < 9; ++i) {
             double s = 0;
-            for (int k = 0; k < 9; ++k) s += Minv[i][k] * ms[k];
+            for (int k = 0; k < 9; ++k) s += M2[k][i] * (ms[k] / nrm[k]);
             w->fs[i * N + n] = s;
         }
     }
@@ -611,7 +618,7 @@ static void d1q3_step_once(const orc_params *P, double *f, double *T, d1_work *w
         double r = w->rho[y], u = w->u[y], F = w->F[y];
         double Xp = (w->Fi[y] != 0) ? w->Fi[y] * w->Fi[y] / (w->psi[y] * w->psi[y]) : 0.0;
         double q = u * F + P->sigma * Xp / 6.0;
-        w->fs[y] = 2.0 / 3.0 * r * (1.0 - 1.5 * u * u) - q;
+        w->fs[y] = 2.0 * r / 3.0 * (1.0 - 1.5 * u * u) - q;
         w->fs[ny + y] = r / 6.0 * (1.0 + 3.0 * u + 3.0 * u * u) + q / 2.0 + F / 4.0;
         w->fs[2 * ny + y] = r / 6.0 * (1.0 - 3.0 * u + 3.0 * u * u) + q / 2.0 - F / 4.0;
     }
@@ -897,6 +904,7 @@ int orc_collide(const orc_params *P, const double *f, const double *T, double *f
  * ====================================================================== */
 static int C3X[19], C3Y[19], C3Z[19];
 static double W3[19];
+static double W3DEN[19]; /* w_i = 1 / W3DEN[i] */
 static int d3_ready = 0;
 static void d3_init(void)
 {
@@ -915,6 +923,7 @@ static void d3_init(void)
                 int c2 = x * x + y * y + z * z;
                 if (c2 == 2) { C3X[k] = x; C3Y[k] = y; C3Z[k] = z; W3[k] = 1.0 / 36.0; ++k; }
             }
+    for (int i = 0; i < 19; ++i) W3DEN[i] = (i == 0) ? 3.0 : (i < 7 ? 18.0 : 36.0);
     d3_ready = 1;
 }
 void orc_d3q19_velocities(int *out57, double *w19)
@@ -1067,7 +1076,7 @@ static void d3q19_step_once(const orc_params *P, double *f, double *T, d3_work *
             double cu = C3X[i] * ux + C3Y[i] * uy + C3Z[i] * uz;
             double cF = C3X[i] * Fx + C3Y[i] * Fy + C3Z[i] * Fz;
             double uF = ux * Fx + uy * Fy + uz * Fz;
-            double feq = W3[i] * r * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+            double feq = r / W3DEN[i] * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
             /* Guo: (1 - 1/(2 tau)) w_i [3 (c - u).F + 9 (c.u)(c.F)] at tau = 1 */
             double guo = 0.5 * W3[i] * (3.0 * (cF - uF) + 9.0 * cu * cF);
             int c2 = C3X[i] * C3X[i] + C3Y[i] * C3Y[i] + C3Z[i] * C3Z[i];

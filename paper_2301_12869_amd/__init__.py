@@ -1,0 +1,218 @@
+"""Python binding of the MI355X thermal pseudopotential LBM library (libtplbm.so).
+
+Argument marshalling only: every step of the lattice update runs in the HIP
+kernels behind the C ABI of ``include/tplbm.h``.  PyTorch supplies device
+memory (one workspace tensor per lattice) and the HIP stream.  There is no CPU
+fallback: if the library is missing, importing works but every constructor
+raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtplbm.so")
+
+OK, EINVAL, ESHAPE, EUNSUPPORTED, EHIP, EUNPHYSICAL, ENOTCONVERGED = range(7)
+STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ESHAPE", 3: "EUNSUPPORTED", 4: "EHIP",
+                5: "EUNPHYSICAL", 6: "ENOTCONVERGED"}
+D1Q3, D2Q9, D3Q19 = 1, 2, 3
+FP64, FP32_DEV = 0, 1
+FIELDS = {"rho": 0, "ux": 1, "uy": 2, "uz": 3, "T": 4, "p_eos": 5, "p_nn": 6}
+FLAG_NAMES = {1: "nan", 2: "rho<=0", 4: "eta>=1", 8: "psi undefined"}
+
+PAPER = dict(a=0.5, b=4.0, R=1.0, G=-1.0, sigma=1.385, tau=(1.0,) * 6, cv=5.0, kappa=0.02)
+
+
+class TplbmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("lattice", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("nz", ctypes.c_int32), ("walls", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("eos", ctypes.c_int32), ("gravity_form", ctypes.c_int32),
+        ("a", ctypes.c_double), ("b", ctypes.c_double), ("R", ctypes.c_double),
+        ("G", ctypes.c_double), ("sigma", ctypes.c_double), ("tau", ctypes.c_double * 6),
+        ("cv", ctypes.c_double), ("kappa", ctypes.c_double), ("g", ctypes.c_double),
+        ("rho_ref", ctypes.c_double),
+    ]
+
+
+class Diag(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("first_bad_step", ctypes.c_int64),
+                ("mass", ctypes.c_double), ("mean_rho", ctypes.c_double),
+                ("max_u", ctypes.c_double), ("min_rho", ctypes.c_double),
+                ("flags", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
+
+
+_lib = None
+
+# (name, argtypes, restype) of every entry point declared in include/tplbm.h
+_VP, _DP, _SZ = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_size_t)
+_PP = ctypes.POINTER(Params)
+SIGNATURES = {
+    "tplbm_workspace_bytes": ([_PP, _SZ], ctypes.c_int),
+    "tplbm_create": ([_PP, _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)], ctypes.c_int),
+    "tplbm_set_state": ([_VP, _DP, _DP], ctypes.c_int),
+    "tplbm_step": ([_VP, ctypes.c_int64], ctypes.c_int),
+    "tplbm_step_async": ([_VP, ctypes.c_int64], ctypes.c_int),
+    "tplbm_read": ([_VP, ctypes.c_int, _DP], ctypes.c_int),
+    "tplbm_read_device": ([_VP, ctypes.c_int, _VP], ctypes.c_int),
+    "tplbm_diagnostics": ([_VP, ctypes.POINTER(Diag)], ctypes.c_int),
+    "tplbm_state_bytes": ([_VP, _SZ], ctypes.c_int),
+    "tplbm_save_state": ([_VP, _VP], ctypes.c_int),
+    "tplbm_load_state": ([_VP, _VP], ctypes.c_int),
+    "tplbm_destroy": ([_VP], None),
+    "tplbm_last_error": ([_VP], ctypes.c_char_p),
+    "tplbm_eos_critical": ([ctypes.c_double] * 3 + [_DP], ctypes.c_int),
+    "tplbm_eos_coexistence": ([ctypes.c_double] * 4 + [_DP], ctypes.c_int),
+    "tplbm_eos_spinodal": ([ctypes.c_double] * 4 + [_DP], ctypes.c_int),
+}
+
+
+def load_library():
+    """Load libtplbm.so (built by paper_2301_12869_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2301_12869_amd.build` (no CPU fallback exists)")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            fn = getattr(lib, name, None)
+            if fn is None:
+                continue
+            fn.argtypes = args
+            fn.restype = res
+        _lib = lib
+    return _lib
+
+
+def _check(rc: int, ctx=None):
+    if rc != OK:
+        msg = load_library().tplbm_last_error(ctx).decode()
+        raise TplbmError(rc, msg)
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(_DP)
+
+
+# ---------------------------------------------------------------------------
+# host FP64 equation-of-state utilities
+# ---------------------------------------------------------------------------
+def eos_critical(a=0.5, b=4.0, R=1.0):
+    out = np.zeros(3)
+    _check(load_library().tplbm_eos_critical(a, b, R, _dp(out)))
+    return tuple(float(v) for v in out)  # rho_c, T_c, p_c
+
+
+def eos_coexistence(T, a=0.5, b=4.0, R=1.0):
+    out = np.zeros(3)
+    _check(load_library().tplbm_eos_coexistence(a, b, R, float(T), _dp(out)))
+    return tuple(float(v) for v in out)  # rho_v, rho_l, p_sat
+
+
+def eos_spinodal(T, a=0.5, b=4.0, R=1.0):
+    out = np.zeros(2)
+    _check(load_library().tplbm_eos_spinodal(a, b, R, float(T), _dp(out)))
+    return tuple(float(v) for v in out)
+
+
+def make_params(lattice=D2Q9, nx=1, ny=1, nz=1, walls=True, precision=FP64, eos="cs",
+                gravity_form=1, g=0.0, rho_ref=0.0, **over) -> Params:
+    d = dict(PAPER)
+    d.update(over)
+    p = Params()
+    p.lattice = int(lattice)
+    p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
+    p.walls = 1 if walls else 0
+    p.precision = int(precision)
+    p.eos = {"cs": 0, "ideal": 1}[eos]
+    p.gravity_form = int(gravity_form)
+    p.a, p.b, p.R, p.G, p.sigma = d["a"], d["b"], d["R"], d["G"], d["sigma"]
+    for k in range(6):
+        p.tau[k] = float(d["tau"][k])
+    p.cv, p.kappa, p.g, p.rho_ref = d["cv"], d["kappa"], float(g), float(rho_ref)
+    return p
+
+
+class Lattice:
+    """A D2Q9 (or D3Q19) lattice living in one device workspace."""
+
+    def __init__(self, params: Params, device=None, stream=None):
+        import torch
+
+        lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the HIP lattice needs an MI355X")
+        self.params = params
+        nbytes = ctypes.c_size_t()
+        _check(lib.tplbm_workspace_bytes(ctypes.byref(params), ctypes.byref(nbytes)))
+        self.device = torch.device(device or "cuda")
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        h = _VP()
+        _check(lib.tplbm_create(ctypes.byref(params), self.workspace.data_ptr(), int(nbytes.value),
+                                self.stream.cuda_stream, ctypes.byref(h)))
+        self._h = h
+        self.n = params.nx * params.ny * (params.nz if params.lattice == D3Q19 else 1)
+
+    # -- state -------------------------------------------------------------
+    def set_state(self, rho0, T0):
+        rho0 = np.ascontiguousarray(rho0, dtype=np.float64).ravel()
+        T0 = np.ascontiguousarray(T0, dtype=np.float64).ravel()
+        if rho0.size != self.n or T0.size != self.n:
+            raise ValueError(f"expected {self.n} values, got {rho0.size} and {T0.size}")
+        _check(load_library().tplbm_set_state(self._h, _dp(rho0), _dp(T0)), self._h)
+
+    def step(self, n: int = 1):
+        _check(load_library().tplbm_step(self._h, int(n)), self._h)
+
+    def step_async(self, n: int = 1):
+        _check(load_library().tplbm_step_async(self._h, int(n)), self._h)
+
+    def read(self, field: str) -> np.ndarray:
+        out = np.empty(self.n)
+        _check(load_library().tplbm_read(self._h, FIELDS[field], _dp(out)), self._h)
+        return out
+
+    def read_device(self, field: str, out):
+        """Enqueue a readout into a float64 device tensor of n elements."""
+        assert out.dtype.itemsize == 8 and out.numel() == self.n and out.is_contiguous()
+        _check(load_library().tplbm_read_device(self._h, FIELDS[field], out.data_ptr()), self._h)
+
+    def diagnostics(self) -> dict:
+        d = Diag()
+        _check(load_library().tplbm_diagnostics(self._h, ctypes.byref(d)), self._h)
+        return dict(step=d.step, first_bad_step=d.first_bad_step, mass=d.mass,
+                    mean_rho=d.mean_rho, max_u=d.max_u, min_rho=d.min_rho, flags=d.flags)
+
+    def save_state(self) -> bytes:
+        nb = ctypes.c_size_t()
+        _check(load_library().tplbm_state_bytes(self._h, ctypes.byref(nb)), self._h)
+        buf = ctypes.create_string_buffer(int(nb.value))
+        _check(load_library().tplbm_save_state(self._h, buf), self._h)
+        return buf.raw
+
+    def load_state(self, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _check(load_library().tplbm_load_state(self._h, buf), self._h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().tplbm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,30 @@
+// Internal interface between the host API and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm_common.hpp"
+
+namespace tplbm {
+
+// Everything one lattice launch needs.
+struct LatticeLaunch {
+    const void *fin;
+    void *fout;
+    const double *Tin;
+    double *Tout;
+    Phys phys;
+    int nx, ny, nz;
+    bool fp32, tau1, walls;
+    int tile;             // tile shape selector (0: default)
+    double *partials;     // 5 doubles per block
+    StepState *st;
+    int64_t step;         // level the launch starts from
+    hipStream_t stream;
+};
+
+int d2q9_num_blocks(int nx, int ny, int tile);
+hipError_t d2q9_launch_step(const LatticeLaunch &L);
+hipError_t d2q9_launch_readout(const LatticeLaunch &L, int field, double *scratch, double *out);
+
+}  // namespace tplbm

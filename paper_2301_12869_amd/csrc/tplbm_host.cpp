@@ -1,0 +1,580 @@
+// Host side of the C ABI declared in include/tplbm.h: parameter validation,
+// workspace layout, kernel launches, checkpoints, and the FP64
+// equation-of-state utilities (critical point, coexistence, spinodals).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/tplbm.h"
+#include "lbm_internal.hpp"
+
+using namespace tplbm;
+
+struct tplbm_ctx {
+    tplbm_params p;
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    void *f[2] = {nullptr, nullptr};
+    double *T[2] = {nullptr, nullptr};
+    double *partials = nullptr;
+    StepState *st = nullptr;
+    int cur = 0;
+    int64_t step = 0;
+    int nblocks = 0;
+    int tile = 0;
+    size_t N = 0;
+    int Q = 9;
+    Phys phys;
+    bool have_state = false;
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+int fail(tplbm_ctx *c, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c)
+        c->err = buf;
+    else
+        g_err = buf;
+    return code;
+}
+
+#define HIP_OK(ctx, expr)                                                                  \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail((ctx), TPLBM_EHIP, "%s: %s", #expr, hipGetErrorString(e_));        \
+    } while (0)
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+bool tau_one(const tplbm_params &p)
+{
+    for (double t : p.tau)
+        if (t != 1.0) return false;
+    return true;
+}
+
+int validate(const tplbm_params *p)
+{
+    if (!p) return fail(nullptr, TPLBM_EINVAL, "params is NULL");
+    if (p->lattice != TPLBM_D2Q9 && p->lattice != TPLBM_D3Q19)
+        return fail(nullptr, TPLBM_EINVAL, "lattice must be TPLBM_D2Q9 or TPLBM_D3Q19 (columns use tplbm_batch_*)");
+    if (p->lattice == TPLBM_D3Q19) return fail(nullptr, TPLBM_EUNSUPPORTED, "D3Q19 lattices are not built into this library");
+    if (p->nx < 1 || p->ny < 3) return fail(nullptr, TPLBM_ESHAPE, "need nx >= 1 and ny >= 3");
+    if ((int64_t)p->nx * p->ny > (int64_t)1 << 31) return fail(nullptr, TPLBM_ESHAPE, "lattice too large");
+    if (p->precision != TPLBM_FP64 && p->precision != TPLBM_FP32_DEV)
+        return fail(nullptr, TPLBM_EINVAL, "precision must be TPLBM_FP64 or TPLBM_FP32_DEV");
+    if (p->eos != TPLBM_EOS_CARNAHAN_STARLING && p->eos != TPLBM_EOS_IDEAL_LATTICE)
+        return fail(nullptr, TPLBM_EINVAL, "unknown eos");
+    if (p->gravity_form != 1 && p->gravity_form != 2)
+        return fail(nullptr, TPLBM_EINVAL, "gravity_form must be 1 or 2");
+    for (int k = 0; k < 6; ++k)
+        if (!(p->tau[k] > 0.5)) return fail(nullptr, TPLBM_EINVAL, "tau[%d] must exceed 1/2", k);
+    if (p->eos == TPLBM_EOS_CARNAHAN_STARLING) {
+        if (!(p->G < 0)) return fail(nullptr, TPLBM_EINVAL, "G must be negative for the Carnahan-Starling pseudopotential");
+        if (!(p->a > 0 && p->b > 0 && p->R > 0)) return fail(nullptr, TPLBM_EINVAL, "a, b, R must be positive");
+    } else if (p->G == 0) {
+        return fail(nullptr, TPLBM_EINVAL, "G must be nonzero");
+    }
+    if (!(p->cv > 0) || !(p->kappa >= 0)) return fail(nullptr, TPLBM_EINVAL, "need c_v > 0, kappa >= 0");
+    if (!std::isfinite(p->g) || !std::isfinite(p->sigma)) return fail(nullptr, TPLBM_EINVAL, "g and sigma must be finite");
+    if (p->precision == TPLBM_FP32_DEV && !std::isfinite(p->rho_ref))
+        return fail(nullptr, TPLBM_EINVAL, "rho_ref must be finite");
+    return TPLBM_OK;
+}
+
+Phys make_phys(const tplbm_params &p)
+{
+    Phys c;
+    std::memset(&c, 0, sizeof c);
+    c.a = p.a;
+    c.b_quarter = p.b / 4.0;
+    c.R = p.R;
+    c.two_over_G = 2.0 / p.G;
+    c.G = p.G;
+    c.G2 = p.G * p.G;
+    c.sigma = p.sigma;
+    c.kappa_over_cv = p.kappa / p.cv;
+    c.R_over_cv = p.R / p.cv;
+    c.g = p.g;
+    c.rho_ref = p.precision == TPLBM_FP32_DEV ? p.rho_ref : 0.0;
+    const double t[9] = {p.tau[0], p.tau[1], p.tau[2], p.tau[3], p.tau[4],
+                         p.tau[3], p.tau[4], p.tau[5], p.tau[5]};
+    for (int k = 0; k < 9; ++k) c.lam[k] = 1.0 / t[k];
+    c.sig_e = p.sigma / p.tau[1];
+    c.sig_s = p.sigma / p.tau[2];
+    c.eos = p.eos;
+    c.form = p.gravity_form;
+    return c;
+}
+
+struct Layout {
+    size_t f_bytes, T_bytes, part_bytes, st_bytes, total;
+    int nblocks;
+};
+
+Layout layout_of(const tplbm_params &p, int tile)
+{
+    Layout L;
+    const size_t N = (size_t)p.nx * p.ny;
+    const size_t elem = p.precision == TPLBM_FP32_DEV ? 4 : 8;
+    L.f_bytes = align256(9 * N * elem);
+    // readout scratch reuses the idle population buffer: it needs 4N doubles
+    if (L.f_bytes < align256(4 * N * 8)) L.f_bytes = align256(4 * N * 8);
+    L.T_bytes = align256(N * 8);
+    L.nblocks = d2q9_num_blocks(p.nx, p.ny, tile);
+    L.part_bytes = align256((size_t)L.nblocks * 5 * 8);
+    L.st_bytes = align256(sizeof(StepState));
+    L.total = 2 * L.f_bytes + 2 * L.T_bytes + L.part_bytes + L.st_bytes;
+    return L;
+}
+
+int tile_choice()
+{
+    const char *e = std::getenv("TPLBM_D2Q9_TILE");
+    return e ? std::atoi(e) : 0;
+}
+
+LatticeLaunch launch_of(tplbm_ctx *c)
+{
+    LatticeLaunch L;
+    L.fin = c->f[c->cur];
+    L.fout = c->f[1 - c->cur];
+    L.Tin = c->T[c->cur];
+    L.Tout = c->T[1 - c->cur];
+    L.phys = c->phys;
+    L.nx = c->p.nx;
+    L.ny = c->p.ny;
+    L.nz = 1;
+    L.fp32 = c->p.precision == TPLBM_FP32_DEV;
+    L.tau1 = tau_one(c->p);
+    L.walls = c->p.walls != 0;
+    L.tile = c->tile;
+    L.partials = c->partials;
+    L.st = c->st;
+    L.step = c->step;
+    L.stream = c->stream;
+    return L;
+}
+
+// D2Q9 velocity set in the paper's order (Eq. VelocitySet) and weights.
+const int kCx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+const int kCy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+const double kW[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+
+}  // namespace
+
+extern "C" {
+
+int tplbm_workspace_bytes(const tplbm_params *p, size_t *bytes)
+{
+    int rc = validate(p);
+    if (rc) return rc;
+    if (!bytes) return fail(nullptr, TPLBM_EINVAL, "bytes is NULL");
+    *bytes = layout_of(*p, tile_choice()).total;
+    return TPLBM_OK;
+}
+
+int tplbm_create(const tplbm_params *p, void *dev_workspace, size_t bytes, void *hip_stream,
+                 tplbm_ctx **out)
+{
+    int rc = validate(p);
+    if (rc) return rc;
+    if (!out) return fail(nullptr, TPLBM_EINVAL, "out is NULL");
+    if (!dev_workspace) return fail(nullptr, TPLBM_EINVAL, "workspace is NULL");
+    if (((uintptr_t)dev_workspace & 255) != 0) return fail(nullptr, TPLBM_EINVAL, "workspace must be 256-byte aligned");
+    const int tile = tile_choice();
+    const Layout L = layout_of(*p, tile);
+    if (bytes < L.total) return fail(nullptr, TPLBM_ESHAPE, "workspace has %zu bytes, need %zu", bytes, L.total);
+    tplbm_ctx *c = new tplbm_ctx();
+    c->p = *p;
+    c->stream = (hipStream_t)hip_stream;
+    c->ws = (char *)dev_workspace;
+    c->ws_bytes = bytes;
+    c->tile = tile;
+    c->N = (size_t)p->nx * p->ny;
+    c->nblocks = L.nblocks;
+    char *q = c->ws;
+    c->f[0] = q; q += L.f_bytes;
+    c->f[1] = q; q += L.f_bytes;
+    c->T[0] = (double *)q; q += L.T_bytes;
+    c->T[1] = (double *)q; q += L.T_bytes;
+    c->partials = (double *)q; q += L.part_bytes;
+    c->st = (StepState *)q;
+    c->phys = make_phys(*p);
+    StepState s;
+    std::memset(&s, 0, sizeof s);
+    s.first_bad = -1;
+    hipError_t e = hipMemcpyAsync(c->st, &s, sizeof s, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        delete c;
+        return fail(nullptr, TPLBM_EHIP, "initialising the step state: %s", hipGetErrorString(e));
+    }
+    *out = c;
+    return TPLBM_OK;
+}
+
+int tplbm_set_state(tplbm_ctx *c, const double *rho0, const double *T0)
+{
+    if (!c) return fail(nullptr, TPLBM_EINVAL, "ctx is NULL");
+    if (!rho0 || !T0) return fail(c, TPLBM_EINVAL, "rho0 and T0 must be non-NULL");
+    const int nx = c->p.nx, ny = c->p.ny;
+    const size_t N = c->N;
+    const bool walls = c->p.walls != 0, fp32 = c->p.precision == TPLBM_FP32_DEV;
+    const double rr = c->phys.rho_ref;
+    // The buffer holds post-collision populations that the first step pulls
+    // from: f*_i(x) = w_i rho0(x + c_i) makes the pulled level-0 state the
+    // rest state f_i = w_i rho0(x).  Sources beyond a wall are never pulled.
+    std::vector<double> fd;
+    std::vector<float> ff;
+    if (fp32) ff.resize(9 * N); else fd.resize(9 * N);
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x)
+            for (int i = 0; i < 9; ++i) {
+                int xs = (x + kCx[i] + nx) % nx;
+                int ys = y + kCy[i];
+                if (walls) {
+                    if (ys < 0 || ys >= ny) ys = y;
+                } else {
+                    ys = (ys + ny) % ny;
+                }
+                const double v = kW[i] * rho0[(size_t)ys * nx + xs];
+                const size_t k = (size_t)i * N + (size_t)y * nx + x;
+                if (fp32) ff[k] = (float)(v - kW[i] * rr); else fd[k] = v;
+            }
+    // <rho> of level 0 from the values the first step will see, index order
+    double tot = 0.0;
+    for (size_t n = 0; n < N; ++n) {
+        if (fp32) {
+            double r = 0.0;
+            for (int i = 0; i < 9; ++i) r += kW[i] * rr + (double)(float)(kW[i] * rho0[n] - kW[i] * rr);
+            tot += r;
+        } else {
+            tot += rho0[n];
+        }
+    }
+    c->cur = 0;
+    c->step = 0;
+    if (fp32)
+        HIP_OK(c, hipMemcpyAsync(c->f[0], ff.data(), 9 * N * 4, hipMemcpyHostToDevice, c->stream));
+    else
+        HIP_OK(c, hipMemcpyAsync(c->f[0], fd.data(), 9 * N * 8, hipMemcpyHostToDevice, c->stream));
+    HIP_OK(c, hipMemcpyAsync(c->T[0], T0, N * 8, hipMemcpyHostToDevice, c->stream));
+    StepState s;
+    std::memset(&s, 0, sizeof s);
+    s.mean[0] = tot / (double)N;
+    s.mass = tot;
+    s.first_bad = -1;
+    HIP_OK(c, hipMemcpyAsync(c->st, &s, sizeof s, hipMemcpyHostToDevice, c->stream));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    c->have_state = true;
+    return TPLBM_OK;
+}
+
+int tplbm_step_async(tplbm_ctx *c, int64_t nsteps)
+{
+    if (!c) return fail(nullptr, TPLBM_EINVAL, "ctx is NULL");
+    if (nsteps < 0) return fail(c, TPLBM_EINVAL, "nsteps must be >= 0");
+    if (!c->have_state) return fail(c, TPLBM_EINVAL, "call tplbm_set_state or tplbm_load_state first");
+    for (int64_t s = 0; s < nsteps; ++s) {
+        LatticeLaunch L = launch_of(c);
+        HIP_OK(c, d2q9_launch_step(L));
+        c->cur = 1 - c->cur;
+        c->step += 1;
+    }
+    return TPLBM_OK;
+}
+
+int tplbm_step(tplbm_ctx *c, int64_t nsteps)
+{
+    int rc = tplbm_step_async(c, nsteps);
+    if (rc) return rc;
+    StepState s;
+    HIP_OK(c, hipMemcpyAsync(&s, c->st, sizeof s, hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    if (s.flags)
+        return fail(c, TPLBM_EUNPHYSICAL, "unphysical state (flags 0x%x) first seen at level %lld",
+                    s.flags, (long long)s.first_bad);
+    return TPLBM_OK;
+}
+
+int tplbm_read_device(tplbm_ctx *c, int field, double *dev_out)
+{
+    if (!c) return fail(nullptr, TPLBM_EINVAL, "ctx is NULL");
+    if (!dev_out) return fail(c, TPLBM_EINVAL, "output is NULL");
+    if (field < TPLBM_RHO || field > TPLBM_P_NN) return fail(c, TPLBM_EINVAL, "unknown field %d", field);
+    if (!c->have_state) return fail(c, TPLBM_EINVAL, "no state");
+    LatticeLaunch L = launch_of(c);
+    HIP_OK(c, d2q9_launch_readout(L, field, (double *)c->f[1 - c->cur], dev_out));
+    return TPLBM_OK;
+}
+
+int tplbm_read(tplbm_ctx *c, int field, double *host_out)
+{
+    if (!c) return fail(nullptr, TPLBM_EINVAL, "ctx is NULL");
+    if (!host_out) return fail(c, TPLBM_EINVAL, "output is NULL");
+    // the readout writes its result into the tail of the idle population
+    // buffer (past the 4N-double scratch it uses), then it is copied out
+    if (field < TPLBM_RHO || field > TPLBM_P_NN) return fail(c, TPLBM_EINVAL, "unknown field %d", field);
+    if (!c->have_state) return fail(c, TPLBM_EINVAL, "no state");
+    double *scratch = (double *)c->f[1 - c->cur];
+    double *dst = c->T[1 - c->cur];  // idle temperature buffer, N doubles
+    LatticeLaunch L = launch_of(c);
+    HIP_OK(c, d2q9_launch_readout(L, field, scratch, dst));
+    HIP_OK(c, hipMemcpyAsync(host_out, dst, c->N * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    return TPLBM_OK;
+}
+
+int tplbm_diagnostics(tplbm_ctx *c, tplbm_diag *out)
+{
+    if (!c || !out) return fail(c, TPLBM_EINVAL, "NULL argument");
+    StepState s;
+    HIP_OK(c, hipMemcpyAsync(&s, c->st, sizeof s, hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    out->step = c->step;
+    out->first_bad_step = s.first_bad;
+    out->mass = s.mass;
+    out->mean_rho = s.mean[c->step & 1];
+    out->max_u = s.max_u;
+    out->min_rho = s.min_rho;
+    out->flags = s.flags;
+    out->pad = 0;
+    return TPLBM_OK;
+}
+
+int tplbm_state_bytes(const tplbm_ctx *c, size_t *bytes)
+{
+    if (!c || !bytes) return fail(nullptr, TPLBM_EINVAL, "NULL argument");
+    const size_t elem = c->p.precision == TPLBM_FP32_DEV ? 4 : 8;
+    *bytes = 64 + 9 * c->N * elem + c->N * 8 + sizeof(StepState);
+    return TPLBM_OK;
+}
+
+namespace {
+struct BlobHeader {
+    char magic[8];
+    int64_t step;
+    int64_t N;
+    int32_t Q, elem;
+    int32_t nx, ny;
+    char pad[24];
+};
+static_assert(sizeof(BlobHeader) == 64, "blob header");
+}  // namespace
+
+int tplbm_save_state(tplbm_ctx *c, void *host_blob)
+{
+    if (!c || !host_blob) return fail(c, TPLBM_EINVAL, "NULL argument");
+    if (!c->have_state) return fail(c, TPLBM_EINVAL, "no state");
+    const size_t elem = c->p.precision == TPLBM_FP32_DEV ? 4 : 8;
+    BlobHeader h;
+    std::memset(&h, 0, sizeof h);
+    std::memcpy(h.magic, "TPLBMST1", 8);
+    h.step = c->step;
+    h.N = (int64_t)c->N;
+    h.Q = 9;
+    h.elem = (int32_t)elem;
+    h.nx = c->p.nx;
+    h.ny = c->p.ny;
+    char *b = (char *)host_blob;
+    std::memcpy(b, &h, sizeof h);
+    HIP_OK(c, hipMemcpyAsync(b + 64, c->f[c->cur], 9 * c->N * elem, hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(c, hipMemcpyAsync(b + 64 + 9 * c->N * elem, c->T[c->cur], c->N * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(c, hipMemcpyAsync(b + 64 + 9 * c->N * elem + c->N * 8, c->st, sizeof(StepState),
+                             hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    return TPLBM_OK;
+}
+
+int tplbm_load_state(tplbm_ctx *c, const void *host_blob)
+{
+    if (!c || !host_blob) return fail(c, TPLBM_EINVAL, "NULL argument");
+    const size_t elem = c->p.precision == TPLBM_FP32_DEV ? 4 : 8;
+    BlobHeader h;
+    std::memcpy(&h, host_blob, sizeof h);
+    if (std::memcmp(h.magic, "TPLBMST1", 8) != 0 || h.N != (int64_t)c->N || h.elem != (int32_t)elem ||
+        h.nx != c->p.nx || h.ny != c->p.ny)
+        return fail(c, TPLBM_ESHAPE, "checkpoint does not match this lattice");
+    const char *b = (const char *)host_blob;
+    c->cur = 0;
+    c->step = h.step;
+    HIP_OK(c, hipMemcpyAsync(c->f[0], b + 64, 9 * c->N * elem, hipMemcpyHostToDevice, c->stream));
+    HIP_OK(c, hipMemcpyAsync(c->T[0], b + 64 + 9 * c->N * elem, c->N * 8, hipMemcpyHostToDevice, c->stream));
+    StepState s;
+    std::memcpy(&s, b + 64 + 9 * c->N * elem + c->N * 8, sizeof s);
+    s.counter = 0;
+    HIP_OK(c, hipMemcpyAsync(c->st, &s, sizeof s, hipMemcpyHostToDevice, c->stream));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    c->have_state = true;
+    return TPLBM_OK;
+}
+
+void tplbm_destroy(tplbm_ctx *c) { delete c; }
+
+const char *tplbm_last_error(const tplbm_ctx *c) { return c ? c->err.c_str() : g_err.c_str(); }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// FP64 equation-of-state utilities.  Carnahan-Starling (Eq. EOS):
+//   p = rho R T Z(eta) - a rho^2,  eta = b rho / 4,
+//   Z = (1 + eta + eta^2 - eta^3)/(1 - eta)^3.
+// With h(eta) = eta Z(eta): dp/drho = R T h'(eta) - 2 a rho and
+// d2p/drho2 = (b/4) R T h''(eta) - 2 a, where
+//   h'  = (1 + 4 eta + 4 eta^2 - 4 eta^3 + eta^4)/(1 - eta)^4,
+//   h'' = (8 + 20 eta - 4 eta^2)/(1 - eta)^5.
+// Coexistence (Eq. MaxwellRule) is solved as equal pressure and equal
+// chemical potential mu = p/rho + R T [ln eta + (4 eta - 3 eta^2)/(1-eta)^2]
+// - a rho (the equal-area rule written as mu_v = mu_l).
+// ---------------------------------------------------------------------------
+namespace {
+struct CS {
+    double a, b, R;
+    double Z(double e) const { return (1 + e + e * e - e * e * e) / ((1 - e) * (1 - e) * (1 - e)); }
+    double h1(double e) const
+    {
+        const double s = 1 - e;
+        return (1 + 4 * e + 4 * e * e - 4 * e * e * e + e * e * e * e) / (s * s * s * s);
+    }
+    double h2(double e) const
+    {
+        const double s = 1 - e;
+        return (8 + 20 * e - 4 * e * e) / (s * s * s * s * s);
+    }
+    double h3(double e) const  // derivative of h2
+    {
+        const double s = 1 - e;
+        return ((20 - 8 * e) * s + 5 * (8 + 20 * e - 4 * e * e)) / (s * s * s * s * s * s);
+    }
+    double p(double r, double T) const { return r * R * T * Z(b * r / 4) - a * r * r; }
+    double dp(double r, double T) const { return R * T * h1(b * r / 4) - 2 * a * r; }
+    double d2p(double r, double T) const { return b / 4 * R * T * h2(b * r / 4) - 2 * a; }
+    double mu(double r, double T) const
+    {
+        const double e = b * r / 4;
+        return p(r, T) / r + R * T * (std::log(e) + (4 * e - 3 * e * e) / ((1 - e) * (1 - e))) - a * r;
+    }
+    double rho_max() const { return 4.0 / b; }
+};
+
+// root of a monotone function on [lo, hi] by safeguarded Newton
+template <class F, class D>
+double newton_bracket(F f, D df, double lo, double hi, double target, int &ok)
+{
+    double flo = f(lo) - target, fhi = f(hi) - target;
+    ok = (flo <= 0) != (fhi <= 0) || flo == 0 || fhi == 0;
+    if (!ok) return 0.5 * (lo + hi);
+    const bool inc = fhi > flo;
+    double x = 0.5 * (lo + hi);
+    for (int it = 0; it < 200; ++it) {
+        const double fx = f(x) - target;
+        if (fx == 0) return x;
+        if ((fx > 0) == inc) hi = x; else lo = x;
+        const double d = df(x);
+        double xn = (d != 0) ? x - fx / d : 0.5 * (lo + hi);
+        if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+        if (std::fabs(xn - x) <= 1e-16 * std::fabs(x) || hi - lo <= 1e-17 * std::fabs(x)) return xn;
+        x = xn;
+    }
+    return x;
+}
+
+int cs_spinodal(const CS &m, double T, double &sv, double &sl)
+{
+    int ok;
+    const double top = m.rho_max() * (1 - 1e-12);
+    // inflection of p(rho): d2p/drho2 = 0, increasing in rho
+    const double ri = newton_bracket([&](double r) { return m.d2p(r, T); },
+                                     [&](double r) { return m.b * m.b / 16 * m.R * T * m.h3(m.b * r / 4); },
+                                     1e-12, top, 0.0, ok);
+    if (!ok || m.dp(ri, T) >= 0) return TPLBM_EINVAL;
+    sv = newton_bracket([&](double r) { return m.dp(r, T); }, [&](double r) { return m.d2p(r, T); },
+                        1e-14, ri, 0.0, ok);
+    if (!ok) return TPLBM_ENOTCONVERGED;
+    sl = newton_bracket([&](double r) { return m.dp(r, T); }, [&](double r) { return m.d2p(r, T); },
+                        ri, top, 0.0, ok);
+    if (!ok) return TPLBM_ENOTCONVERGED;
+    return TPLBM_OK;
+}
+}  // namespace
+
+extern "C" int tplbm_eos_critical(double a, double b, double R, double *out3)
+{
+    if (!out3 || !(a > 0 && b > 0 && R > 0)) return fail(nullptr, TPLBM_EINVAL, "bad EOS constants");
+    CS m{a, b, R};
+    // at the critical point rho d2p/drho2 = dp/drho, i.e. eta h''(eta) = h'(eta)
+    int ok;
+    const double eta = newton_bracket([&](double e) { return e * m.h2(e) - m.h1(e); },
+                                      [&](double e) { return e * m.h3(e); }, 1e-3, 0.5, 0.0, ok);
+    if (!ok) return fail(nullptr, TPLBM_ENOTCONVERGED, "critical point not bracketed");
+    const double rc = 4 * eta / b;
+    const double Tc = 8 * a / (b * R * m.h2(eta));
+    out3[0] = rc;
+    out3[1] = Tc;
+    out3[2] = m.p(rc, Tc);
+    return TPLBM_OK;
+}
+
+extern "C" int tplbm_eos_spinodal(double a, double b, double R, double T, double *out2)
+{
+    if (!out2 || !(a > 0 && b > 0 && R > 0 && T > 0)) return fail(nullptr, TPLBM_EINVAL, "bad arguments");
+    CS m{a, b, R};
+    double sv, sl;
+    int rc = cs_spinodal(m, T, sv, sl);
+    if (rc) return fail(nullptr, rc, "no spinodal at T = %g (at or above T_c?)", T);
+    out2[0] = sv;
+    out2[1] = sl;
+    return TPLBM_OK;
+}
+
+extern "C" int tplbm_eos_coexistence(double a, double b, double R, double T, double *out3)
+{
+    if (!out3 || !(a > 0 && b > 0 && R > 0 && T > 0)) return fail(nullptr, TPLBM_EINVAL, "bad arguments");
+    CS m{a, b, R};
+    double sv, sl;
+    int rc = cs_spinodal(m, T, sv, sl);
+    if (rc) return fail(nullptr, rc, "no coexistence at T = %g (at or above T_c?)", T);
+    const double top = m.rho_max() * (1 - 1e-13);
+    double plo = std::max(m.p(sl, T), 0.0), phi = m.p(sv, T);
+    auto branches = [&](double ps, double &rv, double &rl) {
+        int ok1, ok2;
+        rv = newton_bracket([&](double r) { return m.p(r, T); }, [&](double r) { return m.dp(r, T); },
+                            1e-15, sv, ps, ok1);
+        rl = newton_bracket([&](double r) { return m.p(r, T); }, [&](double r) { return m.dp(r, T); },
+                            sl, top, ps, ok2);
+        return ok1 && ok2;
+    };
+    // mu_l - mu_v decreases as the trial pressure rises between the spinodal
+    // pressures; bisection on the pressure with Newton roots on each branch
+    double rv = 0, rl = 0;
+    for (int it = 0; it < 400; ++it) {
+        const double ps = 0.5 * (plo + phi);
+        if (!branches(ps, rv, rl)) return fail(nullptr, TPLBM_ENOTCONVERGED, "branch root failed");
+        const double dmu = m.mu(rl, T) - m.mu(rv, T);
+        if (dmu > 0) plo = ps; else phi = ps;
+        if (phi - plo <= 1e-17 * phi) break;
+    }
+    const double ps = 0.5 * (plo + phi);
+    if (!branches(ps, rv, rl)) return fail(nullptr, TPLBM_ENOTCONVERGED, "branch root failed");
+    out3[0] = rv;
+    out3[1] = rl;
+    out3[2] = ps;
+    return TPLBM_OK;
+}

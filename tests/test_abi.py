@@ -1,0 +1,72 @@
+"""The C ABI library (CPU side): it loads, exports every entry point that
+include/tplbm.h declares, and its pure-host FP64 EOS utilities agree with the
+oracle's independent implementation.  No GPU work is started here."""
+import os
+import re
+
+import pytest
+
+import paper_2301_12869_amd as T
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(tplbm_\w+)\s*\(", src))
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(T.LIB_PATH):
+        pytest.fail("libtplbm.so is not built: run __graft_entry__.build()")
+    return T.load_library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 16
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert names <= set(T.SIGNATURES), names - set(T.SIGNATURES)
+
+
+def test_host_eos_utilities_match_the_oracle(lib, orc, crit):
+    rc, Tc, pc = T.eos_critical(0.5, 4.0, 1.0)
+    assert rc == pytest.approx(crit[0], rel=1e-12)
+    assert Tc == pytest.approx(crit[1], rel=1e-12)
+    assert pc == pytest.approx(crit[2], rel=1e-11)
+    P = orc.make_params()
+    for tr in (0.6, 0.75, 0.8, 0.9, 0.95, 0.99):
+        a = T.eos_coexistence(tr * Tc)
+        b = orc.coexistence(P, tr * crit[1])
+        assert a[0] == pytest.approx(b[0], rel=1e-9)
+        assert a[1] == pytest.approx(b[1], rel=1e-11)
+        assert a[2] == pytest.approx(b[2], rel=1e-10)
+        s1, s2 = T.eos_spinodal(tr * Tc), orc.spinodal(P, tr * crit[1])
+        assert s1 == pytest.approx(s2, rel=1e-9)
+    with pytest.raises(T.TplbmError):
+        T.eos_coexistence(1.01 * Tc)
+
+
+def test_invalid_parameters_are_rejected_on_the_host(lib):
+    import ctypes
+
+    nb = ctypes.c_size_t()
+    good = T.make_params(T.D2Q9, nx=4, ny=8)
+    assert lib.tplbm_workspace_bytes(ctypes.byref(good), ctypes.byref(nb)) == T.OK
+    assert nb.value > 2 * 9 * 32 * 8
+    cases = [dict(ny=2), dict(tau=(1, 1, 1, 1, 1, 0.5)), dict(G=1.0), dict(gravity_form=3),
+             dict(precision=7), dict(lattice=5)]
+    for over in cases:
+        kw = dict(lattice=T.D2Q9, nx=4, ny=8)
+        kw.update(over)
+        p = T.make_params(**kw)
+        rc = lib.tplbm_workspace_bytes(ctypes.byref(p), ctypes.byref(nb))
+        assert rc in (T.EINVAL, T.ESHAPE), (over, rc)
+        assert lib.tplbm_last_error(None)

@@ -1,0 +1,214 @@
+"""GPU parity of the fused D2Q9 update against the FP64 oracle.
+
+Bars: FP64 storage within 1e-12 relative (max |difference| over the field
+divided by max |field|; the oracle built with and without FMA contraction
+differs by about 3e-13 after 20 000 steps of the 4 x 256 case), FP32-deviation
+storage within 1e-5 relative in density.  Inputs come from the seeded
+generators; the expected values come from the oracle only."""
+import functools
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32_RHO_TOL = 1e-5
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+
+    import paper_2301_12869_amd as T
+
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible MI355X")
+    T.load_library()
+    return T
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def _run_oracle(orc, kw, rho0, T0, steps):
+    P = orc.make_params("D2Q9", **kw)
+    f = orc.init_rest(P, rho0.ravel())
+    TT = np.array(T0, dtype=np.float64).ravel().copy()
+    d = orc.step(P, f, TT, steps)
+    m = orc.macro(P, f, TT)
+    m["diag"] = d
+    return m
+
+
+def _run_gpu(T, kw, rho0, T0, steps, precision=0, rho_ref=0.0):
+    p = T.make_params(T.D2Q9, precision=precision, rho_ref=rho_ref, **kw)
+    lat = T.Lattice(p)
+    lat.set_state(rho0, T0)
+    lat.step(steps)
+    out = {k: lat.read(k) for k in ("rho", "ux", "uy", "T", "p_eos", "p_nn")}
+    out["diag"] = lat.diagnostics()
+    lat.close()
+    return out
+
+
+def _c1_inputs(orc, crit, form):
+    _, T_c, _ = crit
+    P = orc.make_params("D2Q9", nx=4, ny=256)
+    rv, rl, _ = orc.coexistence(P, 0.8 * T_c)
+    rho0 = W.layered_density((256, 4), 128, rl, rv, 1e-3, seed=1)
+    T0 = np.full((256, 4), 0.8 * T_c)
+    kw = dict(nx=4, ny=256, walls=True, g=1e-5, gravity_form=form)
+    return kw, rho0, T0
+
+
+@functools.lru_cache(maxsize=None)
+def _c1_oracle(form):
+    import oracle as orc
+
+    crit = orc.critical()
+    kw, rho0, T0 = _c1_inputs(orc, crit, form)
+    return _run_oracle(orc, kw, rho0, T0, 20000)
+
+
+@pytest.mark.parametrize("form", [1, 2])
+def test_c1_fp64_20000_steps(T, orc, crit, form):
+    """4 x 256, T/T_c = 0.8, g = 1e-5 downward, liquid bottom half, 1e-3
+    noise, 20 000 steps, FP64: every readout field within 1e-12."""
+    _log(f"case c1 fp64 form={form}")
+    kw, rho0, T0 = _c1_inputs(orc, crit, form)
+    want = _c1_oracle(form)
+    got = _run_gpu(T, kw, rho0, T0, 20000)
+    assert got["diag"]["flags"] == 0
+    for k in ("rho", "T", "p_eos", "p_nn"):
+        assert _rel(got[k], want[k]) < FP64_TOL, (k, _rel(got[k], want[k]))
+    # velocities are O(1e-4): compare on the density scale of momentum
+    for k in ("ux", "uy"):
+        assert np.abs(got[k] - want[k]).max() < FP64_TOL * 1e-2, k
+    assert got["diag"]["mass"] == pytest.approx(want["rho"].sum(), rel=1e-13)
+
+
+@pytest.mark.parametrize("form", [1, 2])
+def test_c1_fp32_deviation_storage(T, orc, crit, form):
+    """Same workload with populations stored as FP32 f_i - w_i rho_ref
+    (rho_ref = initial mean density): density within 1e-5 of the FP64 oracle."""
+    _log(f"case c1 fp32dev form={form}")
+    kw, rho0, T0 = _c1_inputs(orc, crit, form)
+    want = _c1_oracle(form)
+    got = _run_gpu(T, kw, rho0, T0, 20000, precision=1, rho_ref=float(rho0.mean()))
+    err = _rel(got["rho"], want["rho"])
+    _log(f"  fp32dev rho rel err {err:.3e}  T rel err {_rel(got['T'], want['T']):.3e}")
+    assert err < FP32_RHO_TOL
+    assert _rel(got["T"], want["T"]) < FP32_RHO_TOL
+
+
+@pytest.mark.parametrize("walls,form,taus,shape", [
+    (True, 2, (1.0,) * 6, (100, 37)),                          # ragged in x and y
+    (True, 1, (1.0, 0.8, 1.1, 1.0, 1.2, 0.7), (70, 19)),        # general relaxation times
+    (False, 2, (1.0, 1.0, 1.0, 1.0, 1.0, 1.0), (65, 33)),        # fully periodic, ragged
+    (False, 1, (1.0, 1.3, 0.9, 1.0, 1.1, 0.9), (33, 50)),        # periodic, general tau
+    (True, 2, (1.0,) * 6, (1, 40)),                             # one column
+    (True, 1, (1.0,) * 6, (5, 3)),                              # minimum height
+])
+def test_tiles_edges_and_relaxation_times(T, orc, crit, walls, form, taus, shape):
+    _log(f"case tiles walls={walls} form={form} taus={taus} shape={shape}")
+    _, T_c, _ = crit
+    nx, ny = shape
+    P = orc.make_params("D2Q9", nx=nx, ny=ny)
+    rv, rl, _ = orc.coexistence(P, 0.8 * T_c)
+    rho0 = W.layered_density((ny, nx), max(1, ny // 3), rl, rv, 2e-2, seed=nx * 1000 + ny)
+    T0 = (0.8 + 0.02 * W.uniform_pm1(7, nx * ny)).reshape(ny, nx) * T_c
+    if walls:
+        T0[0] = 0.85 * T_c
+        T0[-1] = 0.78 * T_c
+    kw = dict(nx=nx, ny=ny, walls=walls, g=3e-4, gravity_form=form, tau=taus)
+    steps = 300
+    want = _run_oracle(orc, kw, rho0, T0, steps)
+    got = _run_gpu(T, kw, rho0, T0, steps)
+    for k in ("rho", "T", "p_nn"):
+        assert _rel(got[k], want[k]) < FP64_TOL, (k, _rel(got[k], want[k]))
+    for k in ("ux", "uy"):
+        assert np.abs(got[k] - want[k]).max() < FP64_TOL * 1e-1, k
+
+
+def test_ideal_gas_and_strong_gravity(T, orc):
+    _log("case ideal gas")
+    nx, ny = 9, 30
+    rho0 = 1.0 + 0.05 * W.uniform_pm1(3, nx * ny).reshape(ny, nx)
+    T0 = np.ones((ny, nx))
+    kw = dict(nx=nx, ny=ny, walls=True, g=2e-3, gravity_form=1, eos="ideal")
+    want = _run_oracle(orc, kw, rho0, T0, 500)
+    got = _run_gpu(T, kw, rho0, T0, 500)
+    assert _rel(got["rho"], want["rho"]) < FP64_TOL
+    assert np.abs(got["uy"] - want["uy"]).max() < 1e-14
+
+
+def test_checkpoint_restart_is_bitwise(T, orc, crit):
+    _log("case checkpoint")
+    kw, rho0, T0 = _c1_inputs(orc, crit, 2)
+    p = T.make_params(T.D2Q9, **kw)
+    a = T.Lattice(p)
+    a.set_state(rho0, T0)
+    a.step(700)
+    ref = {k: a.read(k) for k in ("rho", "uy", "T")}
+    b = T.Lattice(p)
+    b.set_state(rho0, T0)
+    b.step(300)
+    blob = b.save_state()
+    c = T.Lattice(p)
+    c.load_state(blob)
+    c.step(400)
+    for k in ref:
+        assert np.array_equal(c.read(k), ref[k]), k
+    assert c.diagnostics()["step"] == 700
+    for x in (a, b, c):
+        x.close()
+
+
+def test_unphysical_state_is_reported(T, orc, crit):
+    """An initial density beyond the EOS pole (b rho / 4 >= 1) must come back
+    as EUNPHYSICAL with the level where it was seen, never as silent NaN."""
+    _log("case unphysical")
+    _, T_c, _ = crit
+    nx, ny = 8, 16
+    rho0 = np.full((ny, nx), 0.2)
+    rho0[5, 3] = 1.2
+    T0 = np.full((ny, nx), 0.8 * T_c)
+    p = T.make_params(T.D2Q9, nx=nx, ny=ny, g=1e-5)
+    lat = T.Lattice(p)
+    lat.set_state(rho0, T0)
+    with pytest.raises(T.TplbmError) as e:
+        lat.step(3)
+    assert e.value.code == T.EUNPHYSICAL
+    d = lat.diagnostics()
+    assert d["flags"] != 0 and d["first_bad_step"] == 0
+    lat.close()
+
+
+def test_full_size_1024x2048_against_the_oracle(T, orc, crit):
+    """The benchmark workload at its real size and launch configuration
+    (1024 x 2048, heated bottom wall, both gravity forms): a few steps, every
+    node compared with the oracle."""
+    _, T_c, _ = crit
+    nx, ny = 1024, 2048
+    P = orc.make_params("D2Q9", nx=nx, ny=ny)
+    rv, rl, _ = orc.coexistence(P, 0.8 * T_c)
+    rho0 = W.layered_density((ny, nx), 64, rl, rv, 1e-3, seed=2)
+    T0 = W.wall_temperature_field((ny, nx), 0.8 * T_c, 0.9 * T_c, 0.8 * T_c)
+    for form, g, prec in ((1, 1e-4, 0), (2, 1e-5, 1)):
+        _log(f"case full size form={form} precision={prec}")
+        kw = dict(nx=nx, ny=ny, walls=True, g=g, gravity_form=form)
+        want = _run_oracle(orc, kw, rho0, T0, 3)
+        got = _run_gpu(T, kw, rho0, T0, 3, precision=prec, rho_ref=float(rho0.mean()))
+        tol = FP64_TOL if prec == 0 else FP32_RHO_TOL
+        assert _rel(got["rho"], want["rho"]) < tol
+        assert _rel(got["T"], want["T"]) < tol
