@@ -86,10 +86,12 @@ def run_variant(T, torch, rho0, T0, precision, form, g, steps, warmup):
     wall = time.perf_counter() - t0
     d = lat.diagnostics()
     lat.close()
-    if d["flags"]:
-        raise RuntimeError(f"unphysical state during the benchmark: {d}")
+    # F = rho g with g = 1e-4 over 2048 rows drives the vapour beyond its
+    # spinodal within about 1300 steps: the method itself fails there (the
+    # oracle fails in the same step window), which is reported, not hidden
+    status = "ok" if not d["flags"] else f"unphysical from level {d['first_bad_step']}"
     ms_events = ev0.elapsed_time(ev1)
-    return dict(wall_s=wall, ms_per_step=1e3 * wall / steps,
+    return dict(wall_s=wall, ms_per_step=1e3 * wall / steps, status=status,
                 kernel_ms=ms_events / steps, mass=d["mass"], max_u=d["max_u"])
 
 
@@ -119,7 +121,9 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--variants", default="all", help="all | headline")
+    ap.add_argument("--variants", default="all", help="all | headline | fp32dev")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the lattice update "
@@ -134,11 +138,23 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.calibrate_copy:
+        # a plain copy kernel of known size: 1 GiB read + 1 GiB written
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30}))
+        return
     rho_c, T_c, _ = T.eos_critical()
     rho0, T0 = make_inputs(T)
     print(f"# inputs ready: {NX}x{NY}, mean rho {rho0.mean():.6f}", file=sys.stderr, flush=True)
 
     variants = [(0, 2, 1e-5)]
+    if args.variants == "fp32dev":
+        variants = [(1, 2, 1e-5)]
     if args.variants == "all":
         variants += [(0, 1, 1e-5), (0, 1, 1e-4), (0, 2, 1e-4), (1, 2, 1e-5), (1, 1, 1e-5),
                      (1, 1, 1e-4), (1, 2, 1e-4)]
@@ -152,11 +168,16 @@ def main():
         r["frac_hbm"] = r["achieved_GBs"] / HBM_PEAK_GBS
         results[key] = r
         print(f"# {key}: {r['kernel_ms']*1e3:.1f} us/step, {r['mlups']:.0f} MLUPS, "
-              f"{r['achieved_GBs']:.0f} GB/s ({100*r['frac_hbm']:.1f}% of HBM)", file=sys.stderr,
-              flush=True)
+              f"{r['achieved_GBs']:.0f} GB/s ({100*r['frac_hbm']:.1f}% of HBM) [{r['status']}]",
+              file=sys.stderr, flush=True)
 
     head_key = "fp64_form2_g1e-05"
+    if head_key not in results:
+        print(json.dumps({k: v for k, v in results.items()}))
+        return
     head = results[head_key]
+    if head["status"] != "ok":
+        raise RuntimeError(f"the headline workload became unphysical: {head['status']}")
     bpn = BYTES_PER_NODE[0]
     traffic = measured_traffic(head_key)
     line = {
@@ -180,6 +201,7 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(head["frac_hbm"], 4), "traffic": traffic},
         "variants": {k: {"mlups": round(v["mlups"], 1), "GBs": round(v["achieved_GBs"], 1),
+                         "status": v["status"],
                          "frac_hbm": round(v["frac_hbm"], 4),
                          "bytes_per_node_step": BYTES_PER_NODE[0 if k.startswith("fp64") else 1],
                          "traffic": measured_traffic(k)}

@@ -21,6 +21,10 @@
 // The last block to finish reduces the partials in block order and writes
 // <rho> of the next level, which is what the next launch's gravity form 2
 // uses: no second pass over the populations is needed for the mean.
+//
+// Launch shape: a persistent grid of one 1024-thread block per compute unit;
+// the blocks of each XCD walk a contiguous range of 64 x 32 tiles, so the
+// halo rows that neighbouring tiles share are served by that XCD's L2.
 #include <hip/hip_runtime.h>
 
 #include "lbm_common.hpp"
@@ -30,7 +34,6 @@ namespace tplbm {
 
 namespace {
 
-constexpr int kThreads = 256;
 
 template <class S>
 struct PopIO;
@@ -81,12 +84,16 @@ struct Stencil {
     {
         return (n - s) * (1.0 / 3.0) + ((ne + nw) - (se + sw)) * (1.0 / 12.0);
     }
-    // 6 sum_i w_i (phi_i - phi_0), as differences so that it vanishes
-    // exactly on a uniform field
-    __device__ __forceinline__ double lap(double c0) const
+    // gradient and 6 sum_i w_i (phi_i - phi_0) together.  The Laplacian sums
+    // equal neighbours pairwise before subtracting 4 phi_0, so it vanishes
+    // exactly on a uniform field (2 phi and 4 phi are exact).
+    __device__ __forceinline__ void grad_lap(double c0, double &gx, double &gy, double &lap) const
     {
-        return (((e - c0) + (w - c0)) + ((n - c0) + (s - c0))) * (2.0 / 3.0) +
-               (((ne - c0) + (nw - c0)) + ((sw - c0) + (se - c0))) * (1.0 / 6.0);
+        const double a = ne + se, b = nw + sw, p = ne + nw, q = se + sw;
+        gx = (e - w) * (1.0 / 3.0) + (a - b) * (1.0 / 12.0);
+        gy = (n - s) * (1.0 / 3.0) + (p - q) * (1.0 / 12.0);
+        const double c4 = 4.0 * c0;
+        lap = (((e + w) + (n + s)) - c4) * (2.0 / 3.0) + ((a + b) - c4) * (1.0 / 6.0);
     }
 };
 
@@ -95,8 +102,10 @@ struct Stencil {
 __device__ __forceinline__ double energy_rhs(const Phys &c, const Stencil &t, double T0, double ux,
                                              double uy, double divu, double inv_rho, double Z)
 {
-    const double adv = -(ux * t.dx() + uy * t.dy());
-    const double cond = c.kappa_over_cv * inv_rho * t.lap(T0);
+    double gx, gy, lap;
+    t.grad_lap(T0, gx, gy, lap);
+    const double adv = -(ux * gx + uy * gy);
+    const double cond = c.kappa_over_cv * inv_rho * lap;
     const double work = -T0 * c.R_over_cv * Z * divu;
     return adv + cond + work;
 }
@@ -115,353 +124,414 @@ __device__ __forceinline__ int wrapi(int v, int n)
     return v < 0 ? v + n : v;
 }
 
-template <class S, bool TAU1, bool WALLS, int TX, int TY>
-__global__ __launch_bounds__(kThreads) void d2q9_step(const S *__restrict__ fin,
-                                                      S *__restrict__ fout,
-                                                      const double *__restrict__ Tin,
-                                                      double *__restrict__ Tout, Phys c,
-                                                      int nx, int ny, int tiles_x,
-                                                      double *__restrict__ partials,
-                                                      StepState *__restrict__ st,
-                                                      int64_t step)
+// Register-resident pulled populations of the region nodes one thread owns
+// in phase 1 (raw stored values; converted when consumed).  All of them are
+// loaded before the first is used, so a tile costs one memory round trip.
+template <class S, int NSLOT>
+struct Prefetch {
+    S f[NSLOT][9];
+    double T[NSLOT];
+};
+
+// Geometry of one region node: global coordinates and the flat indices of
+// its own node and of the three rows the pull reads.  Rows beyond a wall are
+// clamped to the node's own row (those populations are reconstructed, never
+// used as loaded); nodes beyond a wall are clamped in-bounds and flagged.
+struct NodeGeom {
+    int gx, gy;
+    bool valid, bot, top;
+    unsigned row, rowm, rowp, xm, xp;
+};
+
+template <bool WALLS, int W3, int TY>
+__device__ __forceinline__ NodeGeom region_node(int r, int x0, int y0, int nx, int ny, bool small_x)
 {
+    NodeGeom q;
+    const int ry = r / W3, rx = r - ry * W3;
+    int gx = x0 + rx - 3;
+    if (small_x) {
+        gx %= nx;
+        if (gx < 0) gx += nx;
+    } else {
+        gx = gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx);
+    }
+    int gy = y0 + ry - 3;
+    q.valid = true;
+    if (WALLS) {
+        q.valid = (gy >= 0 && gy < ny);
+        gy = gy < 0 ? 0 : (gy >= ny ? ny - 1 : gy);
+        q.bot = q.valid && gy == 0;
+        q.top = q.valid && gy == ny - 1;
+        q.rowm = (unsigned)(gy == 0 ? gy : gy - 1) * (unsigned)nx;
+        q.rowp = (unsigned)(gy == ny - 1 ? gy : gy + 1) * (unsigned)nx;
+    } else {
+        if (small_x || ny < TY + 6) {  // tiny lattices: general wrap
+            gy %= ny;
+            if (gy < 0) gy += ny;
+        } else {
+            gy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
+        }
+        q.bot = q.top = false;
+        q.rowm = (unsigned)(gy == 0 ? ny - 1 : gy - 1) * (unsigned)nx;
+        q.rowp = (unsigned)(gy == ny - 1 ? 0 : gy + 1) * (unsigned)nx;
+    }
+    q.gx = gx;
+    q.gy = gy;
+    q.row = (unsigned)gy * (unsigned)nx;
+    q.xm = (unsigned)(gx == 0 ? nx - 1 : gx - 1);
+    q.xp = (unsigned)(gx == nx - 1 ? 0 : gx + 1);
+    return q;
+}
+
+// Issue the pull loads of one region node (all in-bounds).
+template <class S>
+__device__ __forceinline__ void pull_loads(const S *__restrict__ fin, const double *__restrict__ Tin,
+                                           size_t N, const NodeGeom &q, S (&f)[9], double &T)
+{
+    const unsigned gx = (unsigned)q.gx;
+    f[0] = fin[0 * N + q.row + gx];
+    f[1] = fin[1 * N + q.row + q.xm];
+    f[2] = fin[2 * N + q.rowm + gx];
+    f[3] = fin[3 * N + q.row + q.xp];
+    f[4] = fin[4 * N + q.rowp + gx];
+    f[5] = fin[5 * N + q.rowm + q.xm];
+    f[6] = fin[6 * N + q.rowm + q.xp];
+    f[7] = fin[7 * N + q.rowp + q.xp];
+    f[8] = fin[8 * N + q.rowp + q.xm];
+    T = Tin[q.row + gx];
+}
+
+template <class S, bool TAU1, bool WALLS, int TX, int TY, int NT, int MIN_WAVES_PER_EU>
+__global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step(const S *__restrict__ fin,
+                                                         S *__restrict__ fout,
+                                                         const double *__restrict__ Tin,
+                                                         double *__restrict__ Tout, Phys c,
+                                                         int nx, int ny, int tiles_x, int ntiles,
+                                                         double *__restrict__ partials,
+                                                         StepState *__restrict__ st,
+                                                         int64_t step)
+{
+    constexpr int kThreads = NT;
     constexpr int W3 = TX + 6, H3 = TY + 6;
     constexpr int W2 = TX + 4, H2 = TY + 4;
     constexpr int W1 = TX + 2, H1 = TY + 2;
-    __shared__ double s_psi[H3 * W3];
+    constexpr int R3N = H3 * W3;
+    constexpr int NSLOT = (R3N + kThreads - 1) / kThreads;
+    __shared__ double s_psi[R3N];
     __shared__ double s_rho[H2 * W2];
     __shared__ double s_T[H2 * W2];
     __shared__ double s_ux[H2 * W2];
     __shared__ double s_uy[H2 * W2];
+    __shared__ double s_Z[H2 * W2];
     __shared__ double s_k1[H1 * W1];  // first Heun stage K(T^n); T~ = T^n + k1
     __shared__ double s_red[4 * kThreads / 64];
     __shared__ unsigned s_ured[kThreads / 64];
 
     const int tid = threadIdx.x;
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
-    const int x0 = (tile % tiles_x) * TX;
-    const int y0 = (tile / tiles_x) * TY;
     const size_t N = (size_t)nx * ny;
     const double rr = c.rho_ref;
     const double mean = st->mean[step & 1];
+    const bool small_x = nx < W3;
+    const double wref[9] = {kW0 * rr, kW1 * rr, kW1 * rr, kW1 * rr, kW1 * rr,
+                            kW5 * rr, kW5 * rr, kW5 * rr, kW5 * rr};
 
-    // ---- phase 1: pull, density, momentum, pseudopotential on tile + 3 ----
-    for (int r = tid; r < H3 * W3; r += kThreads) {
-        const int ry = r / W3, rx = r - ry * W3;
-        int gy = y0 + ry - 3;
-        const int gx = wrapi(x0 + rx - 3, nx);
-        bool valid = true;
-        if (WALLS)
-            valid = (gy >= 0 && gy < ny);
-        else
-            gy = wrapi(gy, ny);
-        double rho = 0.0, jx = 0.0, jy = 0.0, psi = 0.0, T = 0.0;
-        if (valid) {
-            const int xm = (gx == 0) ? nx - 1 : gx - 1;
-            const int xp = (gx == nx - 1) ? 0 : gx + 1;
-            int ym = gy - 1, yp = gy + 1;
-            if (!WALLS) {
-                ym = (gy == 0) ? ny - 1 : ym;
-                yp = (gy == ny - 1) ? 0 : yp;
-            }
-            const bool bot = WALLS && gy == 0, top = WALLS && gy == ny - 1;
-            const size_t row = (size_t)gy * nx;
-            const size_t rowm = (size_t)(bot ? gy : ym) * nx;  // never read when bot
-            const size_t rowp = (size_t)(top ? gy : yp) * nx;  // never read when top
-            double f0 = PopIO<S>::load(fin, 0 * N + row + gx, kW0 * rr);
-            double f1 = PopIO<S>::load(fin, 1 * N + row + xm, kW1 * rr);
-            double f3 = PopIO<S>::load(fin, 3 * N + row + xp, kW1 * rr);
-            double f2 = 0.0, f4 = 0.0, f5 = 0.0, f6 = 0.0, f7 = 0.0, f8 = 0.0;
-            if (!bot) {
-                f2 = PopIO<S>::load(fin, 2 * N + rowm + gx, kW1 * rr);
-                f5 = PopIO<S>::load(fin, 5 * N + rowm + xm, kW5 * rr);
-                f6 = PopIO<S>::load(fin, 6 * N + rowm + xp, kW5 * rr);
-            }
-            if (!top) {
-                f4 = PopIO<S>::load(fin, 4 * N + rowp + gx, kW1 * rr);
-                f7 = PopIO<S>::load(fin, 7 * N + rowp + xp, kW5 * rr);
-                f8 = PopIO<S>::load(fin, 8 * N + rowp + xm, kW5 * rr);
-            }
-            if (bot) {  // Zou-He, zero wall velocity: unknowns 2, 5, 6
-                const double d = f1 - f3;
-                f2 = f4;
-                f5 = f7 - 0.5 * d;
-                f6 = f8 + 0.5 * d;
-            }
-            if (top) {  // unknowns 4, 7, 8
-                const double d = f1 - f3;
-                f4 = f2;
-                f7 = f5 + 0.5 * d;
-                f8 = f6 - 0.5 * d;
-            }
-            rho = ((f0 + f1) + (f2 + f3)) + ((f4 + f5) + (f6 + f7)) + f8;
-            jx = (f1 - f3) + (f5 - f6) + (f8 - f7);
-            jy = (f2 - f4) + (f5 + f6) - (f7 + f8);
-            T = Tin[row + gx];
-            double Zdummy;
-            psi = psi_and_Z(c, rho, T, Zdummy);
-        }
-        s_psi[r] = psi;
-        if (rx >= 1 && rx < W3 - 1 && ry >= 1 && ry < H3 - 1) {
-            const int q = (ry - 1) * W2 + (rx - 1);
-            s_rho[q] = rho;
-            s_T[q] = T;
-            s_ux[q] = jx;
-            s_uy[q] = jy;
-        }
-    }
-    __syncthreads();
+    // Tiles of this block: blocks are dispatched round-robin over the 8 XCDs;
+    // each XCD gets a contiguous range of tiles so that halos are shared in
+    // its L2, and the blocks of one XCD stride through that range.
+    const int nb = gridDim.x;
+    const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+    const int per_xcd_blocks = nb >> 3;  // nb is a multiple of 8
+    const int tiles_per_xcd = (ntiles + 7) >> 3;
+    const int t_begin = xcd * tiles_per_xcd;
+    const int t_end = min(ntiles, t_begin + tiles_per_xcd);
 
-    // ---- phase 2: force and force-corrected velocity on tile + 2 ----
-    for (int r = tid; r < H2 * W2; r += kThreads) {
-        const int ry = r / W2, rx = r - ry * W2;
-        int gy = y0 + ry - 2;
-        bool valid = true, wall = false;
-        if (WALLS) {
-            valid = (gy >= 0 && gy < ny);
-            wall = (gy == 0 || gy == ny - 1);
+    Prefetch<S, NSLOT> pre;
+    auto issue = [&](int t) {
+        const int x0 = (t % tiles_x) * TX, y0 = (t / tiles_x) * TY;
+#pragma unroll
+        for (int k = 0; k < NSLOT; ++k) {
+            const int r = tid + k * kThreads;
+            if (r < R3N) {
+                const NodeGeom q = region_node<WALLS, W3, TY>(r, x0, y0, nx, ny, small_x);
+                pull_loads<S>(fin, Tin, N, q, pre.f[k], pre.T[k]);
+            }
         }
-        if (!valid) continue;
-        const double rho = s_rho[r];
-        double Fx = 0.0, Fy = 0.0;
-        if (!wall) {
-            Stencil p;
-            const int c3 = (ry + 1) * W3 + (rx + 1);
-            p.load(s_psi, c3, W3);
-            // sum_i w(|c_i|^2) psi(x + c_i) c_i with w(1) = 1/3, w(2) = 1/12
-            const double sx = (p.e - p.w) * (1.0 / 3.0) + ((p.ne + p.se) - (p.nw + p.sw)) * (1.0 / 12.0);
-            const double sy = (p.n - p.s) * (1.0 / 3.0) + ((p.ne + p.nw) - (p.se + p.sw)) * (1.0 / 12.0);
-            const double mg = -c.G * s_psi[c3];
-            const double fg = (c.form == 2) ? -(rho - mean) * c.g : -rho * c.g;
-            Fx = mg * sx;
-            Fy = mg * sy + fg;
-        }
-        const double inv = 1.0 / rho;
-        s_ux[r] = (s_ux[r] + 0.5 * Fx) * inv;
-        s_uy[r] = (s_uy[r] + 0.5 * Fy) * inv;
-    }
-    __syncthreads();
+    };
 
-    // ---- phase 3: first Heun stage on tile + 1 ----
-    for (int r = tid; r < H1 * W1; r += kThreads) {
-        const int ry = r / W1, rx = r - ry * W1;
-        const int gy = y0 + ry - 1;
-        const int c2 = (ry + 1) * W2 + (rx + 1);
-        if (WALLS && (gy < 0 || gy >= ny || gy == 0 || gy == ny - 1)) {
-            s_k1[r] = 0.0;  // Dirichlet walls: T~ = T
-            continue;
-        }
-        const double rho = s_rho[c2];
-        double Z = 0.0;
-        if (c.eos == 0) Z = cs_Z(c.b_quarter * rho);
-        const double divu = divergence(s_ux, s_uy, c2, W2);
-        Stencil t;
-        t.load(s_T, c2, W2);
-        s_k1[r] = energy_rhs(c, t, s_T[c2], s_ux[c2], s_uy[c2], divu, 1.0 / rho, Z);
-    }
-    __syncthreads();
-
-    // ---- phase 4: second Heun stage, collision, stores, partials ----
     Partial part = {0.0, 0.0, 0.0, 1e300, 0u};
-    for (int r = tid; r < TY * TX; r += kThreads) {
-        const int ry = r / TX, rx = r - ry * TX;
-        const int gx = x0 + rx, gy = y0 + ry;
-        if (gx >= nx || gy >= ny) continue;
-        const int c2 = (ry + 2) * W2 + (rx + 2);
-        const int c1 = (ry + 1) * W1 + (rx + 1);
-        const int c3 = (ry + 3) * W3 + (rx + 3);
-        const size_t g = (size_t)gy * nx + gx;
-        const bool wall = WALLS && (gy == 0 || gy == ny - 1);
-        const double rho = s_rho[c2], ux = s_ux[c2], uy = s_uy[c2], T = s_T[c2];
-        const double eta = c.b_quarter * rho;
+    for (int t = t_begin + slot; t < t_end; t += per_xcd_blocks) {
+        const int x0 = (t % tiles_x) * TX, y0 = (t / tiles_x) * TY;
+        // every pull of the tile is issued before any is consumed
+        issue(t);
 
-        // temperature
-        double Tn;
-        if (wall) {
-            Tn = T;
-        } else {
-            double Z = 0.0;
-            if (c.eos == 0) Z = cs_Z(eta);
-            const double divu = divergence(s_ux, s_uy, c2, W2);
-            // T~ = T^n + k1 at the node and its neighbours
-            Stencil t, k;
-            t.load(s_T, c2, W2);
-            k.load(s_k1, c1, W1);
-            Stencil tt;
-            tt.e = t.e + k.e; tt.w = t.w + k.w; tt.n = t.n + k.n; tt.s = t.s + k.s;
-            tt.ne = t.ne + k.ne; tt.nw = t.nw + k.nw; tt.sw = t.sw + k.sw; tt.se = t.se + k.se;
-            const double k1 = s_k1[c1];
-            const double k2 = energy_rhs(c, tt, T + k1, ux, uy, divu, 1.0 / rho, Z);
-            Tn = T + 0.5 * (k1 + k2);
-        }
-        Tout[g] = Tn;
-
-        // forces (again, from the LDS psi) for the collision
-        double Fx = 0.0, Fy = 0.0, X = 0.0;
-        const double psi0 = s_psi[c3];
-        if (!wall) {
-            Stencil p;
-            p.load(s_psi, c3, W3);
-            const double sx = (p.e - p.w) * (1.0 / 3.0) + ((p.ne + p.se) - (p.nw + p.sw)) * (1.0 / 12.0);
-            const double sy = (p.n - p.s) * (1.0 / 3.0) + ((p.ne + p.nw) - (p.se + p.sw)) * (1.0 / 12.0);
-            const double mg = -c.G * psi0;
-            const double fg = (c.form == 2) ? -(rho - mean) * c.g : -rho * c.g;
-            Fx = mg * sx;
-            Fy = mg * sy + fg;
-            // |F_int|^2 / psi^2 = G^2 |sum w psi c|^2
-            X = c.G2 * (sx * sx + sy * sy);
-        }
-
-        double fs[9];
-        if (TAU1) {
-            // every rate 1: f* = f_eq(rho, u) + F', F' = M^-1 (S/2) =
-            // w_i [3/2 (c - u).F + 9/2 (c.u)(c.F)] + sigma X (-8, 1, ..., 1)/36
-            // w_i rho from one correctly rounded division (w_0 = 4/9, w_5 = 1/36
-            // are exact power-of-two multiples of 1/9): multiplying by the
-            // rounded constant 1/9 instead would bias the mass the same way at
-            // every node and make it drift linearly over many steps
-            const double r9 = rho / 9.0;
-            const double uu = ux * ux + uy * uy;
-            const double uF = ux * Fx + uy * Fy;
-            const double base = 1.0 - 1.5 * uu;
-            const double sx36 = c.sigma * X * (1.0 / 36.0);
-            fs[0] = 4.0 * r9 * base - kW0 * 1.5 * uF - 8.0 * sx36;
-            const int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-            const int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+        // ---- phase 1: density, momentum, psi on tile + 3 (from registers) ----
 #pragma unroll
-            for (int i = 1; i < 9; ++i) {
-                const double wi = (i < 5) ? kW1 : kW5;
-                const double wr = (i < 5) ? r9 : 0.25 * r9;
-                const double cu = cx[i] * ux + cy[i] * uy;
-                const double cF = cx[i] * Fx + cy[i] * Fy;
-                fs[i] = wr * (base + cu * (3.0 + 4.5 * cu)) + wi * (1.5 * (cF - uF) + 4.5 * cu * cF) + sx36;
-            }
-        } else {
-            // general relaxation times: moments m = M f of the pulled
-            // populations, relaxation toward m_eq, source (I - Lambda/2) S
-            const int xm = (gx == 0) ? nx - 1 : gx - 1;
-            const int xp = (gx == nx - 1) ? 0 : gx + 1;
-            int ym = gy - 1, yp = gy + 1;
-            if (!WALLS) {
-                ym = (gy == 0) ? ny - 1 : ym;
-                yp = (gy == ny - 1) ? 0 : yp;
-            }
-            const bool bot = WALLS && gy == 0, top = WALLS && gy == ny - 1;
-            const size_t row = (size_t)gy * nx;
-            const size_t rowm = (size_t)(bot ? gy : ym) * nx;
-            const size_t rowp = (size_t)(top ? gy : yp) * nx;
-            double f[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-            f[0] = PopIO<S>::load(fin, 0 * N + row + gx, kW0 * rr);
-            f[1] = PopIO<S>::load(fin, 1 * N + row + xm, kW1 * rr);
-            f[3] = PopIO<S>::load(fin, 3 * N + row + xp, kW1 * rr);
-            if (!bot) {
-                f[2] = PopIO<S>::load(fin, 2 * N + rowm + gx, kW1 * rr);
-                f[5] = PopIO<S>::load(fin, 5 * N + rowm + xm, kW5 * rr);
-                f[6] = PopIO<S>::load(fin, 6 * N + rowm + xp, kW5 * rr);
-            }
-            if (!top) {
-                f[4] = PopIO<S>::load(fin, 4 * N + rowp + gx, kW1 * rr);
-                f[7] = PopIO<S>::load(fin, 7 * N + rowp + xp, kW5 * rr);
-                f[8] = PopIO<S>::load(fin, 8 * N + rowp + xm, kW5 * rr);
-            }
-            if (bot) {
-                const double d = f[1] - f[3];
-                f[2] = f[4];
-                f[5] = f[7] - 0.5 * d;
-                f[6] = f[8] + 0.5 * d;
-            }
-            if (top) {
-                const double d = f[1] - f[3];
-                f[4] = f[2];
-                f[7] = f[5] + 0.5 * d;
-                f[8] = f[6] - 0.5 * d;
-            }
-            // m = M f (Eq. MatrixMRT)
-            const double a1 = f[1] + f[2] + f[3] + f[4];
-            const double a5 = f[5] + f[6] + f[7] + f[8];
-            double m[9];
-            m[0] = f[0] + a1 + a5;
-            m[1] = -4.0 * f[0] - a1 + 2.0 * a5;
-            m[2] = 4.0 * f[0] - 2.0 * a1 + a5;
-            m[3] = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
-            m[4] = -2.0 * (f[1] - f[3]) + f[5] - f[6] - f[7] + f[8];
-            m[5] = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
-            m[6] = -2.0 * (f[2] - f[4]) + f[5] + f[6] - f[7] - f[8];
-            m[7] = f[1] - f[2] + f[3] - f[4];
-            m[8] = f[5] - f[6] + f[7] - f[8];
-            // m_eq = M f_eq for the second-order equilibrium
-            const double uu = ux * ux + uy * uy;
-            double me[9];
-            me[0] = m[0];  // mass is a collision invariant
-            me[1] = rho * (-2.0 + 3.0 * uu);
-            me[2] = rho * (1.0 - 3.0 * uu);
-            me[3] = rho * ux;
-            me[4] = -rho * ux;
-            me[5] = rho * uy;
-            me[6] = -rho * uy;
-            me[7] = rho * (ux * ux - uy * uy);
-            me[8] = rho * ux * uy;
-            // (I - Lambda/2) S with S of Eq. LiFS; the sigma part reduces to
-            // +sigma X/tau_e and -sigma X/tau_varsigma
-            const double uF = ux * Fx + uy * Fy;
-            double s[9];
-            s[0] = 0.0;
-            s[1] = (1.0 - 0.5 * c.lam[1]) * 6.0 * uF + c.sig_e * X;
-            s[2] = -(1.0 - 0.5 * c.lam[2]) * 6.0 * uF - c.sig_s * X;
-            s[3] = (1.0 - 0.5 * c.lam[3]) * Fx;
-            s[4] = -(1.0 - 0.5 * c.lam[4]) * Fx;
-            s[5] = (1.0 - 0.5 * c.lam[5]) * Fy;
-            s[6] = -(1.0 - 0.5 * c.lam[6]) * Fy;
-            s[7] = (1.0 - 0.5 * c.lam[7]) * 2.0 * (ux * Fx - uy * Fy);
-            s[8] = (1.0 - 0.5 * c.lam[8]) * (ux * Fy + uy * Fx);
-            double ms[9];
+        for (int k = 0; k < NSLOT; ++k) {
+            const int r = tid + k * kThreads;
+            if (r < R3N) {
+                const NodeGeom q = region_node<WALLS, W3, TY>(r, x0, y0, nx, ny, small_x);
+                double f[9];
 #pragma unroll
-            for (int k = 0; k < 9; ++k) ms[k] = m[k] - c.lam[k] * (m[k] - me[k]) + s[k];
-            // f* = M^-1 m*, with M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4)
-            const double d0 = ms[0] / 9.0, d1 = ms[1] * (1.0 / 36.0), d2 = ms[2] * (1.0 / 36.0);
-            const double d3 = ms[3] * (1.0 / 6.0), d4 = ms[4] * (1.0 / 12.0);
-            const double d5 = ms[5] * (1.0 / 6.0), d6 = ms[6] * (1.0 / 12.0);
-            const double d7 = ms[7] * 0.25, d8 = ms[8] * 0.25;
-            fs[0] = d0 - 4.0 * d1 + 4.0 * d2;
-            fs[1] = d0 - d1 - 2.0 * d2 + d3 - 2.0 * d4 + d7;
-            fs[2] = d0 - d1 - 2.0 * d2 + d5 - 2.0 * d6 - d7;
-            fs[3] = d0 - d1 - 2.0 * d2 - d3 + 2.0 * d4 + d7;
-            fs[4] = d0 - d1 - 2.0 * d2 - d5 + 2.0 * d6 - d7;
-            fs[5] = d0 + 2.0 * d1 + d2 + d3 + d4 + d5 + d6 + d8;
-            fs[6] = d0 + 2.0 * d1 + d2 - d3 - d4 + d5 + d6 - d8;
-            fs[7] = d0 + 2.0 * d1 + d2 - d3 - d4 - d5 - d6 + d8;
-            fs[8] = d0 + 2.0 * d1 + d2 + d3 + d4 - d5 - d6 - d8;
+                for (int i = 0; i < 9; ++i) f[i] = PopIO<S>::load(pre.f[k], i, wref[i]);
+                if (WALLS && q.bot) {  // Zou-He, zero wall velocity: unknowns 2, 5, 6
+                    const double d = f[1] - f[3];
+                    f[2] = f[4];
+                    f[5] = f[7] - 0.5 * d;
+                    f[6] = f[8] + 0.5 * d;
+                }
+                if (WALLS && q.top) {  // unknowns 4, 7, 8
+                    const double d = f[1] - f[3];
+                    f[4] = f[2];
+                    f[7] = f[5] + 0.5 * d;
+                    f[8] = f[6] - 0.5 * d;
+                }
+                double rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+                double jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+                double jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+                double Z = 0.0, psi = 0.0, T = pre.T[k];
+                if (q.valid) {
+                    psi = psi_and_Z(c, rho, T, Z);
+                } else {
+                    rho = jx = jy = T = 0.0;
+                }
+                s_psi[r] = psi;
+                const int ry = r / W3, rx = r - ry * W3;
+                if (rx >= 1 && rx < W3 - 1 && ry >= 1 && ry < H3 - 1) {
+                    const int qi = (ry - 1) * W2 + (rx - 1);
+                    s_rho[qi] = rho;
+                    s_T[qi] = T;
+                    s_ux[qi] = jx;
+                    s_uy[qi] = jy;
+                    s_Z[qi] = Z;
+                }
+            }
         }
+        __syncthreads();
 
-        // stores and the next level's mass: a population moving toward a
-        // wall layer is counted twice by that wall's reconstruction; one
-        // leaving through a wall is not counted
-        double nm = 0.0;
-        const double wr[9] = {kW0, kW1, kW1, kW1, kW1, kW5, kW5, kW5, kW5};
-        const int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            const double v = PopIO<S>::store(fout, (size_t)i * N + g, fs[i], wr[i] * rr);
-            double mult = 1.0;
+        // ---- phase 2: force and force-corrected velocity on tile + 2 ----
+        for (int r = tid; r < H2 * W2; r += kThreads) {
+            const int ry = r / W2, rx = r - ry * W2;
+            const int gy = y0 + ry - 2;
+            bool valid = true, wall = false;
             if (WALLS) {
-                const int yd = gy + cy[i];
-                if (yd < 0 || yd >= ny)
-                    mult = 0.0;
-                else if ((yd == 0 && cy[i] == -1) || (yd == ny - 1 && cy[i] == 1))
-                    mult = 2.0;
+                valid = (gy >= 0 && gy < ny);
+                wall = (gy == 0 || gy == ny - 1);
             }
-            nm += mult * v;
+            if (!valid) continue;
+            const double rho = s_rho[r];
+            double Fx = 0.0, Fy = 0.0;
+            if (!wall) {
+                Stencil p;
+                const int c3 = (ry + 1) * W3 + (rx + 1);
+                p.load(s_psi, c3, W3);
+                // sum_i w(|c_i|^2) psi(x + c_i) c_i with w(1) = 1/3, w(2) = 1/12
+                const double sx = (p.e - p.w) * (1.0 / 3.0) + ((p.ne + p.se) - (p.nw + p.sw)) * (1.0 / 12.0);
+                const double sy = (p.n - p.s) * (1.0 / 3.0) + ((p.ne + p.nw) - (p.se + p.sw)) * (1.0 / 12.0);
+                const double mg = -c.G * s_psi[c3];
+                const double fg = (c.form == 2) ? -(rho - mean) * c.g : -rho * c.g;
+                Fx = mg * sx;
+                Fy = mg * sy + fg;
+            }
+            const double inv = rcp_pos(rho);
+            s_ux[r] = (s_ux[r] + 0.5 * Fx) * inv;
+            s_uy[r] = (s_uy[r] + 0.5 * Fy) * inv;
         }
-        part.mass_n += rho;
-        part.mass_next += nm;
-        part.umax = fmax(part.umax, sqrt(ux * ux + uy * uy));
-        part.rmin = fmin(part.rmin, rho);
-        unsigned fl = 0u;
-        if (!(rho > 0.0)) fl |= kFlagRho;
-        if (c.eos == 0 && eta >= 1.0) fl |= kFlagEta;
-        if (psi0 != psi0) fl |= kFlagPsi;
-        if (rho != rho || ux != ux || uy != uy || Tn != Tn || nm != nm) fl |= kFlagNaN;
-        part.flags |= fl;
+        __syncthreads();
+
+        // ---- phase 3: first Heun stage on tile + 1 ----
+        for (int r = tid; r < H1 * W1; r += kThreads) {
+            const int ry = r / W1, rx = r - ry * W1;
+            const int gy = y0 + ry - 1;
+            const int c2 = (ry + 1) * W2 + (rx + 1);
+            if (WALLS && (gy <= 0 || gy >= ny - 1)) {
+                s_k1[r] = 0.0;  // Dirichlet walls (and nodes beyond them): T~ = T
+                continue;
+            }
+            const double divu = divergence(s_ux, s_uy, c2, W2);
+            Stencil tt;
+            tt.load(s_T, c2, W2);
+            s_k1[r] = energy_rhs(c, tt, s_T[c2], s_ux[c2], s_uy[c2], divu, rcp_pos(s_rho[c2]), s_Z[c2]);
+        }
+        __syncthreads();
+
+        // ---- phase 4: second Heun stage, collision, stores, partials ----
+        for (int r = tid; r < TY * TX; r += kThreads) {
+            const int ry = r / TX, rx = r - ry * TX;
+            const int gx = x0 + rx, gy = y0 + ry;
+            if (gx >= nx || gy >= ny) continue;
+            const int c2 = (ry + 2) * W2 + (rx + 2);
+            const int c1 = (ry + 1) * W1 + (rx + 1);
+            const int c3 = (ry + 3) * W3 + (rx + 3);
+            const unsigned g = (unsigned)gy * (unsigned)nx + (unsigned)gx;
+            const bool wall = WALLS && (gy == 0 || gy == ny - 1);
+            const double rho = s_rho[c2], ux = s_ux[c2], uy = s_uy[c2], T = s_T[c2];
+
+            // temperature
+            double Tn = T;
+            if (!wall) {
+                const double divu = divergence(s_ux, s_uy, c2, W2);
+                Stencil tt, kk;  // T~ = T^n + k1 at the node and its neighbours
+                tt.load(s_T, c2, W2);
+                kk.load(s_k1, c1, W1);
+                tt.e += kk.e; tt.w += kk.w; tt.n += kk.n; tt.s += kk.s;
+                tt.ne += kk.ne; tt.nw += kk.nw; tt.sw += kk.sw; tt.se += kk.se;
+                const double k1 = s_k1[c1];
+                const double k2 = energy_rhs(c, tt, T + k1, ux, uy, divu, rcp_pos(rho), s_Z[c2]);
+                Tn = T + 0.5 * (k1 + k2);
+            }
+            Tout[g] = Tn;
+
+            // forces (again, from the LDS psi) for the collision
+            double Fx = 0.0, Fy = 0.0, X = 0.0;
+            const double psi0 = s_psi[c3];
+            if (!wall) {
+                Stencil p;
+                p.load(s_psi, c3, W3);
+                const double sx = (p.e - p.w) * (1.0 / 3.0) + ((p.ne + p.se) - (p.nw + p.sw)) * (1.0 / 12.0);
+                const double sy = (p.n - p.s) * (1.0 / 3.0) + ((p.ne + p.nw) - (p.se + p.sw)) * (1.0 / 12.0);
+                const double mg = -c.G * psi0;
+                const double fg = (c.form == 2) ? -(rho - mean) * c.g : -rho * c.g;
+                Fx = mg * sx;
+                Fy = mg * sy + fg;
+                // |F_int|^2 / psi^2 = G^2 |sum w psi c|^2
+                X = c.G2 * (sx * sx + sy * sy);
+            }
+
+            double fs[9];
+            if (TAU1) {
+                // every rate 1: f* = f_eq(rho, u) + F', F' = M^-1 (S/2) =
+                // w_i [3/2 (c - u).F + 9/2 (c.u)(c.F)] + sigma X (-8, 1, ..., 1)/36.
+                // The rest population is closed by mass conservation,
+                // f*_0 = rho - sum_{i>0} f*_i (exact in exact arithmetic), so
+                // the collision adds no systematic rounding drift to the mass.
+                // Opposite velocities share the even part of f_eq + F' and
+                // differ in the sign of the odd part: per pair (i, i')
+                // f*_i = E + O, f*_i' = E - O with
+                // E = w rho (1 - 3/2 u^2 + 9/2 (c.u)^2) + w (9/2 (c.u)(c.F) - 3/2 u.F) + sigma X/36
+                // O = w (3 rho c.u + 3/2 c.F)
+                const double uu = ux * ux + uy * uy;
+                const double uF = ux * Fx + uy * Fy;
+                const double sx36 = c.sigma * X * (1.0 / 36.0);
+                const double r1 = kW1 * rho, r5 = kW5 * rho;
+                const double b1 = r1 * (1.0 - 1.5 * uu) - kW1 * 1.5 * uF + sx36;
+                const double b5 = r5 * (1.0 - 1.5 * uu) - kW5 * 1.5 * uF + sx36;
+                auto pair = [&](double cu, double cF, double wr, double wi, double base, double &fp, double &fm) {
+                    const double E = base + 4.5 * cu * (wr * cu + wi * cF);
+                    const double O = 3.0 * wr * cu + 1.5 * wi * cF;
+                    fp = E + O;
+                    fm = E - O;
+                };
+                pair(ux, Fx, r1, kW1, b1, fs[1], fs[3]);
+                pair(uy, Fy, r1, kW1, b1, fs[2], fs[4]);
+                pair(ux + uy, Fx + Fy, r5, kW5, b5, fs[5], fs[7]);
+                pair(uy - ux, Fy - Fx, r5, kW5, b5, fs[6], fs[8]);
+                double rest = ((fs[1] + fs[2]) + (fs[3] + fs[4])) + ((fs[5] + fs[6]) + (fs[7] + fs[8]));
+                fs[0] = rho - rest;
+            } else {
+                // general relaxation times: moments m = M f of the pulled
+                // populations, relaxation toward m_eq, source (I - Lambda/2) S
+                const NodeGeom q = region_node<WALLS, W3, TY>((ry + 3) * W3 + (rx + 3), x0, y0, nx, ny, small_x);
+                S raw[9];
+                double Tdummy;
+                pull_loads<S>(fin, Tin, N, q, raw, Tdummy);
+                double f[9];
+#pragma unroll
+                for (int i = 0; i < 9; ++i) f[i] = PopIO<S>::load(raw, i, wref[i]);
+                if (WALLS && q.bot) {
+                    const double d = f[1] - f[3];
+                    f[2] = f[4];
+                    f[5] = f[7] - 0.5 * d;
+                    f[6] = f[8] + 0.5 * d;
+                }
+                if (WALLS && q.top) {
+                    const double d = f[1] - f[3];
+                    f[4] = f[2];
+                    f[7] = f[5] + 0.5 * d;
+                    f[8] = f[6] - 0.5 * d;
+                }
+                // m = M f (Eq. MatrixMRT)
+                const double a1 = f[1] + f[2] + f[3] + f[4];
+                const double a5 = f[5] + f[6] + f[7] + f[8];
+                double m[9];
+                m[0] = f[0] + a1 + a5;
+                m[1] = -4.0 * f[0] - a1 + 2.0 * a5;
+                m[2] = 4.0 * f[0] - 2.0 * a1 + a5;
+                m[3] = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
+                m[4] = -2.0 * (f[1] - f[3]) + f[5] - f[6] - f[7] + f[8];
+                m[5] = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
+                m[6] = -2.0 * (f[2] - f[4]) + f[5] + f[6] - f[7] - f[8];
+                m[7] = f[1] - f[2] + f[3] - f[4];
+                m[8] = f[5] - f[6] + f[7] - f[8];
+                // m_eq = M f_eq for the second-order equilibrium
+                const double uu = ux * ux + uy * uy;
+                double me[9];
+                me[0] = m[0];  // mass is a collision invariant
+                me[1] = rho * (-2.0 + 3.0 * uu);
+                me[2] = rho * (1.0 - 3.0 * uu);
+                me[3] = rho * ux;
+                me[4] = -rho * ux;
+                me[5] = rho * uy;
+                me[6] = -rho * uy;
+                me[7] = rho * (ux * ux - uy * uy);
+                me[8] = rho * ux * uy;
+                // (I - Lambda/2) S with S of Eq. LiFS; the sigma part reduces to
+                // +sigma X/tau_e and -sigma X/tau_varsigma
+                const double uF = ux * Fx + uy * Fy;
+                double sv[9];
+                sv[0] = 0.0;
+                sv[1] = (1.0 - 0.5 * c.lam[1]) * 6.0 * uF + c.sig_e * X;
+                sv[2] = -(1.0 - 0.5 * c.lam[2]) * 6.0 * uF - c.sig_s * X;
+                sv[3] = (1.0 - 0.5 * c.lam[3]) * Fx;
+                sv[4] = -(1.0 - 0.5 * c.lam[4]) * Fx;
+                sv[5] = (1.0 - 0.5 * c.lam[5]) * Fy;
+                sv[6] = -(1.0 - 0.5 * c.lam[6]) * Fy;
+                sv[7] = (1.0 - 0.5 * c.lam[7]) * 2.0 * (ux * Fx - uy * Fy);
+                sv[8] = (1.0 - 0.5 * c.lam[8]) * (ux * Fy + uy * Fx);
+                double ms[9];
+#pragma unroll
+                for (int k = 0; k < 9; ++k) ms[k] = m[k] - c.lam[k] * (m[k] - me[k]) + sv[k];
+                // f* = M^-1 m*, with M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4)
+                const double d0 = ms[0] / 9.0, d1 = ms[1] * (1.0 / 36.0), d2 = ms[2] * (1.0 / 36.0);
+                const double d3 = ms[3] * (1.0 / 6.0), d4 = ms[4] * (1.0 / 12.0);
+                const double d5 = ms[5] * (1.0 / 6.0), d6 = ms[6] * (1.0 / 12.0);
+                const double d7 = ms[7] * 0.25, d8 = ms[8] * 0.25;
+                fs[0] = d0 - 4.0 * d1 + 4.0 * d2;
+                fs[1] = d0 - d1 - 2.0 * d2 + d3 - 2.0 * d4 + d7;
+                fs[2] = d0 - d1 - 2.0 * d2 + d5 - 2.0 * d6 - d7;
+                fs[3] = d0 - d1 - 2.0 * d2 - d3 + 2.0 * d4 + d7;
+                fs[4] = d0 - d1 - 2.0 * d2 - d5 + 2.0 * d6 - d7;
+                fs[5] = d0 + 2.0 * d1 + d2 + d3 + d4 + d5 + d6 + d8;
+                fs[6] = d0 + 2.0 * d1 + d2 - d3 - d4 + d5 + d6 - d8;
+                fs[7] = d0 + 2.0 * d1 + d2 - d3 - d4 - d5 - d6 + d8;
+                fs[8] = d0 + 2.0 * d1 + d2 + d3 + d4 - d5 - d6 - d8;
+            }
+
+            // stores, and the next level's mass: a population moving into a
+            // wall layer is counted twice by that wall's reconstruction; one
+            // leaving through a wall is not counted
+            double v[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) v[i] = PopIO<S>::store(fout, (size_t)i * N + g, fs[i], wref[i]);
+            double nm = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7])) + v[8];
+            if (WALLS) {
+                const double down = (v[4] + v[7]) + v[8], up = (v[2] + v[5]) + v[6];
+                if (gy == 0) nm -= down;
+                if (gy == 1) nm += down;
+                if (gy == ny - 2) nm += up;
+                if (gy == ny - 1) nm -= up;
+            }
+            part.mass_n += rho;
+            part.mass_next += nm;
+            part.umax = fmax(part.umax, ux * ux + uy * uy);
+            part.rmin = fmin(part.rmin, rho);
+            unsigned fl = 0u;
+            if (!(rho > 0.0)) fl |= kFlagRho;
+            if (c.eos == 0 && c.b_quarter * rho >= 1.0) fl |= kFlagEta;
+            if (psi0 != psi0) fl |= kFlagPsi;
+            if (rho != rho || ux != ux || uy != uy || Tn != Tn || nm != nm) fl |= kFlagNaN;
+            part.flags |= fl;
+        }
+        __syncthreads();  // LDS is rewritten by the next tile's phase 1
     }
     part = block_reduce<kThreads>(part, s_red, s_ured);
     finish_launch<kThreads>(part, partials, st, step, (int)((step + 1) & 1),
@@ -582,45 +652,42 @@ __global__ void d2q9_readout_b(const double *__restrict__ scr, const double *__r
     }
 }
 
-template <class S, bool TAU1, bool WALLS, int TX, int TY>
-hipError_t launch_t(const LatticeLaunch &L)
-{
-    const int tiles_x = (L.nx + TX - 1) / TX, tiles_y = (L.ny + TY - 1) / TY;
-    const int nb = tiles_x * tiles_y;
-    hipLaunchKernelGGL((d2q9_step<S, TAU1, WALLS, TX, TY>), dim3(nb), dim3(kThreads), 0, L.stream,
-                       (const S *)L.fin, (S *)L.fout, L.Tin, L.Tout, L.phys, L.nx, L.ny, tiles_x,
-                       L.partials, L.st, L.step);
-    return hipGetLastError();
-}
+// Tile of 64 x 32 nodes per block of 1024 threads (16 wavefronts): the LDS
+// staging of a tile (about 137 KB) allows one block per compute unit.
+constexpr int kTX = 64, kTY = 32, kNT = 1024;
 
 template <class S, bool TAU1, bool WALLS>
-hipError_t launch_tile(const LatticeLaunch &L)
+hipError_t launch_t(const LatticeLaunch &L)
 {
-    switch (L.tile) {
-    case 1: return launch_t<S, TAU1, WALLS, 32, 32>(L);
-    case 2: return launch_t<S, TAU1, WALLS, 128, 8>(L);
-    default: return launch_t<S, TAU1, WALLS, 64, 16>(L);
-    }
+    const int tiles_x = (L.nx + kTX - 1) / kTX, tiles_y = (L.ny + kTY - 1) / kTY;
+    const int ntiles = tiles_x * tiles_y;
+    const int nb = d2q9_num_blocks(L.nx, L.ny, L.resident);
+    hipLaunchKernelGGL((d2q9_step<S, TAU1, WALLS, kTX, kTY, kNT, 4>), dim3(nb), dim3(kNT), 0, L.stream,
+                       (const S *)L.fin, (S *)L.fout, L.Tin, L.Tout, L.phys, L.nx, L.ny, tiles_x,
+                       ntiles, L.partials, L.st, L.step);
+    return hipGetLastError();
 }
 
 }  // namespace
 
-int d2q9_num_blocks(int nx, int ny, int tile)
+// Persistent grid: one block per compute unit (at most one per tile), a
+// multiple of 8 so that every XCD gets the same number of blocks.
+int d2q9_num_blocks(int nx, int ny, int cus)
 {
-    int TX = 64, TY = 16;
-    if (tile == 1) { TX = 32; TY = 32; }
-    if (tile == 2) { TX = 128; TY = 8; }
-    return ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY);
+    const int ntiles = ((nx + kTX - 1) / kTX) * ((ny + kTY - 1) / kTY);
+    int nb = ntiles < cus ? ntiles : cus;
+    nb = ((nb + 7) / 8) * 8;
+    return nb;
 }
 
 hipError_t d2q9_launch_step(const LatticeLaunch &L)
 {
     if (L.fp32) {
-        if (L.tau1) return L.walls ? launch_tile<float, true, true>(L) : launch_tile<float, true, false>(L);
-        return L.walls ? launch_tile<float, false, true>(L) : launch_tile<float, false, false>(L);
+        if (L.tau1) return L.walls ? launch_t<float, true, true>(L) : launch_t<float, true, false>(L);
+        return L.walls ? launch_t<float, false, true>(L) : launch_t<float, false, false>(L);
     }
-    if (L.tau1) return L.walls ? launch_tile<double, true, true>(L) : launch_tile<double, true, false>(L);
-    return L.walls ? launch_tile<double, false, true>(L) : launch_tile<double, false, false>(L);
+    if (L.tau1) return L.walls ? launch_t<double, true, true>(L) : launch_t<double, true, false>(L);
+    return L.walls ? launch_t<double, false, true>(L) : launch_t<double, false, false>(L);
 }
 
 hipError_t d2q9_launch_readout(const LatticeLaunch &L, int field, double *scratch, double *out)

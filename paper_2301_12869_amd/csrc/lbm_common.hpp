@@ -1,7 +1,6 @@
 // Device-side building blocks shared by the lattice kernels: physical
 // constants, the Carnahan-Starling EOS (Eq. EOS), the Yuan-Schaefer
-// pseudopotential (Eq. InteractionPotential), wavefront/block reductions and
-// the XCD-aware block remap.
+// pseudopotential (Eq. InteractionPotential) and wavefront/block reductions.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -27,12 +26,37 @@ struct Phys {
     int form;                 // 1: rho g, 2: (rho - <rho>) g
 };
 
+// Reciprocal of a positive normal double: hardware estimate refined by two
+// Newton steps (within about one ulp; no special-case handling, so callers
+// pass only finite positive arguments or accept a NaN for anything else).
+__device__ __forceinline__ double rcp_pos(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(fma(-x, r, 1.0), r, r);
+    r = fma(fma(-x, r, 1.0), r, r);
+    return r;
+}
+
+// Square root of a positive normal double by a refined reciprocal square
+// root (Goldschmidt-style); zero maps to zero, negative or NaN to NaN.
+__device__ __forceinline__ double sqrt_pos(double a)
+{
+    if (a == 0.0) return 0.0;
+    const double y = __builtin_amdgcn_rsq(a);
+    double g = a * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    const double d = fma(-g, g, a);
+    return fma(d, h, g);
+}
+
 // Carnahan-Starling compressibility factor Z(eta) = (1+eta+eta^2-eta^3)/(1-eta)^3.
 __device__ __forceinline__ double cs_Z(double eta)
 {
     const double s = 1.0 - eta;
     const double num = 1.0 + eta * (1.0 + eta * (1.0 - eta));
-    return num / (s * s * s);
+    return num * rcp_pos(s * s * s);
 }
 
 // p_EOS and psi at one node; Zout receives Z(eta) (1 for the ideal gas,
@@ -47,7 +71,7 @@ __device__ __forceinline__ double psi_and_Z(const Phys &c, double rho, double T,
     Zout = Z;
     const double p = rho * (c.R * T * Z - c.a * rho);
     // psi = sqrt(2 (p - rho c_s^2) / (G c^2)), c = 1, c_s^2 = 1/3
-    return sqrt(c.two_over_G * (p - rho * (1.0 / 3.0)));
+    return sqrt_pos(c.two_over_G * (p - rho * (1.0 / 3.0)));
 }
 
 __device__ __forceinline__ double p_eos(const Phys &c, double rho, double T)
@@ -83,7 +107,7 @@ __device__ __forceinline__ unsigned wave_or(unsigned v)
 }
 
 // Per-block diagnostic partials: sum of rho at level n, sum of the next
-// level's rho (multiplicity-weighted post-collision populations), max |u|,
+// level's rho (multiplicity-weighted post-collision populations), max |u|^2,
 // min rho, flags.
 struct Partial {
     double mass_n, mass_next, umax, rmin;
@@ -186,7 +210,7 @@ __device__ void finish_launch(const Partial &mine, double *partials, StepState *
     if (threadIdx.x == 0) {
         st->mean[mean_slot] = acc.mass_next * inv_nodes;
         st->mass = acc.mass_next;
-        st->max_u = acc.umax;
+        st->max_u = sqrt(acc.umax);
         st->min_rho = acc.rmin;
         st->step = step + 1;
         if (acc.flags && st->first_bad < 0) st->first_bad = step;
@@ -194,20 +218,6 @@ __device__ void finish_launch(const Partial &mine, double *partials, StepState *
         st->counter = 0u;
         __threadfence();
     }
-}
-
-// Blocks are dispatched round-robin over the 8 XCDs of an MI355X, each with
-// its own L2.  Remap so that consecutive logical tiles (which share halos)
-// run on the same XCD.
-__device__ __forceinline__ int xcd_remap(int b, int nb)
-{
-    constexpr int kXcd = 8;
-    const int per = (nb + kXcd - 1) / kXcd;
-    const int xcd = b % kXcd, slot = b / kXcd;
-    // blocks with b < nb map to distinct logical ids in [0, nb) when nb is a
-    // multiple of kXcd; otherwise fall back to identity for the tail
-    if (nb % kXcd != 0) return b;
-    return xcd * per + slot;
 }
 
 }  // namespace tplbm

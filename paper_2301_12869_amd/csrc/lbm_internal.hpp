@@ -16,14 +16,14 @@ struct LatticeLaunch {
     Phys phys;
     int nx, ny, nz;
     bool fp32, tau1, walls;
-    int tile;             // tile shape selector (0: default)
+    int resident;         // blocks of the persistent grid (two per compute unit)
     double *partials;     // 5 doubles per block
     StepState *st;
     int64_t step;         // level the launch starts from
     hipStream_t stream;
 };
 
-int d2q9_num_blocks(int nx, int ny, int tile);
+int d2q9_num_blocks(int nx, int ny, int resident);
 hipError_t d2q9_launch_step(const LatticeLaunch &L);
 hipError_t d2q9_launch_readout(const LatticeLaunch &L, int field, double *scratch, double *out);
 

@@ -27,7 +27,7 @@ struct tplbm_ctx {
     int cur = 0;
     int64_t step = 0;
     int nblocks = 0;
-    int tile = 0;
+    int resident = 0;
     size_t N = 0;
     int Q = 9;
     Phys phys;
@@ -128,7 +128,7 @@ struct Layout {
     int nblocks;
 };
 
-Layout layout_of(const tplbm_params &p, int tile)
+Layout layout_of(const tplbm_params &p)
 {
     Layout L;
     const size_t N = (size_t)p.nx * p.ny;
@@ -137,17 +137,22 @@ Layout layout_of(const tplbm_params &p, int tile)
     // readout scratch reuses the idle population buffer: it needs 4N doubles
     if (L.f_bytes < align256(4 * N * 8)) L.f_bytes = align256(4 * N * 8);
     L.T_bytes = align256(N * 8);
-    L.nblocks = d2q9_num_blocks(p.nx, p.ny, tile);
+    // partials for the largest grid the persistent launch can use
+    L.nblocks = d2q9_num_blocks(p.nx, p.ny, 1 << 20);
     L.part_bytes = align256((size_t)L.nblocks * 5 * 8);
     L.st_bytes = align256(sizeof(StepState));
     L.total = 2 * L.f_bytes + 2 * L.T_bytes + L.part_bytes + L.st_bytes;
     return L;
 }
 
-int tile_choice()
+// Compute units of the current device (the persistent grid is sized from it).
+int resident_blocks()
 {
-    const char *e = std::getenv("TPLBM_D2Q9_TILE");
-    return e ? std::atoi(e) : 0;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        return 256;
+    return cus;
 }
 
 LatticeLaunch launch_of(tplbm_ctx *c)
@@ -164,7 +169,7 @@ LatticeLaunch launch_of(tplbm_ctx *c)
     L.fp32 = c->p.precision == TPLBM_FP32_DEV;
     L.tau1 = tau_one(c->p);
     L.walls = c->p.walls != 0;
-    L.tile = c->tile;
+    L.resident = c->resident;
     L.partials = c->partials;
     L.st = c->st;
     L.step = c->step;
@@ -186,7 +191,7 @@ int tplbm_workspace_bytes(const tplbm_params *p, size_t *bytes)
     int rc = validate(p);
     if (rc) return rc;
     if (!bytes) return fail(nullptr, TPLBM_EINVAL, "bytes is NULL");
-    *bytes = layout_of(*p, tile_choice()).total;
+    *bytes = layout_of(*p).total;
     return TPLBM_OK;
 }
 
@@ -198,15 +203,14 @@ int tplbm_create(const tplbm_params *p, void *dev_workspace, size_t bytes, void 
     if (!out) return fail(nullptr, TPLBM_EINVAL, "out is NULL");
     if (!dev_workspace) return fail(nullptr, TPLBM_EINVAL, "workspace is NULL");
     if (((uintptr_t)dev_workspace & 255) != 0) return fail(nullptr, TPLBM_EINVAL, "workspace must be 256-byte aligned");
-    const int tile = tile_choice();
-    const Layout L = layout_of(*p, tile);
+    const Layout L = layout_of(*p);
     if (bytes < L.total) return fail(nullptr, TPLBM_ESHAPE, "workspace has %zu bytes, need %zu", bytes, L.total);
     tplbm_ctx *c = new tplbm_ctx();
     c->p = *p;
     c->stream = (hipStream_t)hip_stream;
     c->ws = (char *)dev_workspace;
     c->ws_bytes = bytes;
-    c->tile = tile;
+    c->resident = resident_blocks();
     c->N = (size_t)p->nx * p->ny;
     c->nblocks = L.nblocks;
     char *q = c->ws;
