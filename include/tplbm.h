@@ -182,6 +182,89 @@ int tplbm_eos_coexistence(double a, double b, double R, double T, double *out3);
  * out2 = {vapour spinodal, liquid spinodal}.  EINVAL at or above T_c. */
 int tplbm_eos_spinodal(double a, double b, double R, double T, double *out2);
 
+/* ======================================================================
+ * Batched column sweep (one persistent launch runs many independent 1-D
+ * columns to steady state).  A column is the paper's minimal 1-D system
+ * (Sec. IV): wet-node walls at both ends, liquid/vapour, gravity along the
+ * column (Eqs. Gravity_1 / Gravity_2 per column), the temperature of its two
+ * end nodes held fixed.  Columns use D1Q3, which at tau = 1 is the exact
+ * x-uniform reduction of the D2Q9 update (every relaxation time is 1 here;
+ * the paper uses tau = 1 throughout, Sec. IV.B).
+ * ====================================================================== */
+
+#define TPLBM_COL_CONVERGED 0   /* max |u| < tol at a check level */
+#define TPLBM_COL_DIVERGED 1    /* an unphysical-state flag was seen */
+#define TPLBM_COL_MAX_STEPS 2   /* step budget reached first */
+
+typedef struct tplbm_column {
+    int32_t height;        /* nodes including both wall nodes, 3 .. 2048 */
+    int32_t gravity_form;  /* 1 or 2 */
+    double g;              /* gravity magnitude, > 0 pointing to node 0 */
+} tplbm_column;
+
+typedef struct tplbm_batch_params {
+    double a, b, R, G, sigma;  /* as in tplbm_params */
+    double cv, kappa;
+    int32_t eos;               /* TPLBM_EOS_* */
+    int32_t pad;
+} tplbm_batch_params;
+
+typedef struct tplbm_col_result {
+    int64_t steps;     /* level at which the column stopped */
+    int32_t status;    /* TPLBM_COL_* */
+    int32_t pad;
+    double mass;       /* sum of rho at that level */
+    double max_u;      /* max |u| at that level */
+} tplbm_col_result;
+
+typedef struct tplbm_batch_tuning {
+    int32_t shape;         /* kernel shape index (threads x nodes per thread) */
+    int32_t threads;       /* threads per column */
+    int32_t nodes_per_thread;
+    int32_t check_every;   /* steps between steady-state checks */
+    int32_t grid;          /* resident workgroups of the persistent launch */
+    int32_t pad;
+    double node_steps_per_s; /* throughput measured for the choice */
+} tplbm_batch_tuning;
+
+typedef struct tplbm_batch tplbm_batch;
+
+/* Device workspace bytes for ncols columns (pure). */
+int tplbm_batch_workspace_bytes(const tplbm_batch_params *p, int32_t ncols,
+                                const tplbm_column *cols, size_t *bytes);
+
+/* Bind a workspace and stream; columns are copied.  Errors: EINVAL, ESHAPE
+ * (a height outside 3..2048), EHIP. */
+int tplbm_batch_create(const tplbm_batch_params *p, int32_t ncols, const tplbm_column *cols,
+                       void *dev_workspace, size_t bytes, void *hip_stream, tplbm_batch **out);
+
+/* Initial densities and temperatures, concatenated column after column
+ * (column k occupies sum_{j<k} height_j .. + height_k).  Populations start at
+ * rest (f_i = w_i rho0).  The end nodes' temperatures are the Dirichlet data.
+ * Synchronous. */
+int tplbm_batch_set_state(tplbm_batch *b, const double *rho_concat, const double *T_concat);
+
+/* Run every column from its initial state until max |u^n| < tol at a level n
+ * that is a multiple of the check interval, until a flag is raised, or until
+ * n = max_steps; one persistent launch.  out[k] receives column k's result
+ * (caller array of ncols).  The final levels are kept for tplbm_batch_read.
+ * Never aborts the batch for one bad column.  Synchronous. */
+int tplbm_batch_run(tplbm_batch *b, double tol, int64_t max_steps, tplbm_col_result *out);
+
+/* Final densities (TPLBM_RHO) or temperatures (TPLBM_T), concatenated. */
+int tplbm_batch_read(tplbm_batch *b, int field, double *host_out);
+
+/* Pick the kernel shape and the check interval by timing short trial sweeps
+ * of the batch (at most about budget_ms of GPU time); the choice is kept for
+ * later runs and returned in *out (may be NULL).  Inputs are not modified. */
+int tplbm_batch_autotune(tplbm_batch *b, double budget_ms, tplbm_batch_tuning *out);
+
+/* Set the shape and check interval explicitly (shape -1 keeps the current). */
+int tplbm_batch_set_tuning(tplbm_batch *b, int32_t shape, int32_t check_every);
+
+void tplbm_batch_destroy(tplbm_batch *b);
+const char *tplbm_batch_last_error(const tplbm_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

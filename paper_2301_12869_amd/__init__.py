@@ -77,6 +77,46 @@ SIGNATURES = {
 }
 
 
+class Column(ctypes.Structure):
+    _fields_ = [("height", ctypes.c_int32), ("gravity_form", ctypes.c_int32), ("g", ctypes.c_double)]
+
+
+class BatchParams(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_double), ("b", ctypes.c_double), ("R", ctypes.c_double),
+                ("G", ctypes.c_double), ("sigma", ctypes.c_double), ("cv", ctypes.c_double),
+                ("kappa", ctypes.c_double), ("eos", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class ColResult(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("status", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("mass", ctypes.c_double), ("max_u", ctypes.c_double)]
+
+
+class BatchTuning(ctypes.Structure):
+    _fields_ = [("shape", ctypes.c_int32), ("threads", ctypes.c_int32),
+                ("nodes_per_thread", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("grid", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("node_steps_per_s", ctypes.c_double)]
+
+
+_BP = ctypes.POINTER(BatchParams)
+_CP = ctypes.POINTER(Column)
+SIGNATURES.update({
+    "tplbm_batch_workspace_bytes": ([_BP, ctypes.c_int32, _CP, _SZ], ctypes.c_int),
+    "tplbm_batch_create": ([_BP, ctypes.c_int32, _CP, _VP, ctypes.c_size_t, _VP,
+                            ctypes.POINTER(_VP)], ctypes.c_int),
+    "tplbm_batch_set_state": ([_VP, _DP, _DP], ctypes.c_int),
+    "tplbm_batch_run": ([_VP, ctypes.c_double, ctypes.c_int64, ctypes.POINTER(ColResult)],
+                        ctypes.c_int),
+    "tplbm_batch_read": ([_VP, ctypes.c_int, _DP], ctypes.c_int),
+    "tplbm_batch_autotune": ([_VP, ctypes.c_double, ctypes.POINTER(BatchTuning)], ctypes.c_int),
+    "tplbm_batch_set_tuning": ([_VP, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+    "tplbm_batch_destroy": ([_VP], None),
+    "tplbm_batch_last_error": ([_VP], ctypes.c_char_p),
+})
+COL_STATUS = {0: "converged", 1: "diverged", 2: "max_steps"}
+
+
 def load_library():
     """Load libtplbm.so (built by paper_2301_12869_amd.build)."""
     global _lib
@@ -209,6 +249,92 @@ class Lattice:
     def close(self):
         if getattr(self, "_h", None):
             load_library().tplbm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _bcheck(rc: int, h=None):
+    if rc != OK:
+        raise TplbmError(rc, load_library().tplbm_batch_last_error(h).decode())
+
+
+class Batch:
+    """Many independent 1-D columns swept to steady state by one persistent
+    launch.  columns: sequence of (height, gravity_form, g)."""
+
+    def __init__(self, columns, eos="cs", device=None, stream=None, **over):
+        import torch
+
+        lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the batched sweep needs an MI355X")
+        d = dict(PAPER)
+        d.update(over)
+        p = BatchParams()
+        p.a, p.b, p.R, p.G, p.sigma = d["a"], d["b"], d["R"], d["G"], d["sigma"]
+        p.cv, p.kappa = d["cv"], d["kappa"]
+        p.eos = {"cs": 0, "ideal": 1}[eos]
+        self.params = p
+        self.ncols = len(columns)
+        self.cols = (Column * self.ncols)()
+        for k, (h, form, g) in enumerate(columns):
+            self.cols[k].height, self.cols[k].gravity_form, self.cols[k].g = int(h), int(form), float(g)
+        self.heights = np.array([c[0] for c in columns], dtype=np.int64)
+        self.offsets = np.concatenate([[0], np.cumsum(self.heights)])
+        nb = ctypes.c_size_t()
+        _bcheck(lib.tplbm_batch_workspace_bytes(ctypes.byref(p), self.ncols, self.cols,
+                                                ctypes.byref(nb)))
+        self.device = torch.device(device or "cuda")
+        self.workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        h = _VP()
+        _bcheck(lib.tplbm_batch_create(ctypes.byref(p), self.ncols, self.cols,
+                                       self.workspace.data_ptr(), int(nb.value),
+                                       self.stream.cuda_stream, ctypes.byref(h)))
+        self._h = h
+
+    def set_state(self, rho_concat, T_concat):
+        r = np.ascontiguousarray(rho_concat, dtype=np.float64)
+        t = np.ascontiguousarray(T_concat, dtype=np.float64)
+        if r.size != self.offsets[-1] or t.size != self.offsets[-1]:
+            raise ValueError("concatenated arrays must hold sum(heights) values")
+        _bcheck(load_library().tplbm_batch_set_state(self._h, _dp(r), _dp(t)), self._h)
+
+    def run(self, tol: float, max_steps: int) -> dict:
+        res = (ColResult * self.ncols)()
+        _bcheck(load_library().tplbm_batch_run(self._h, float(tol), int(max_steps), res), self._h)
+        return dict(steps=np.array([r.steps for r in res]),
+                    status=np.array([r.status for r in res]),
+                    mass=np.array([r.mass for r in res]),
+                    max_u=np.array([r.max_u for r in res]))
+
+    def read(self, field: str) -> np.ndarray:
+        out = np.empty(int(self.offsets[-1]))
+        _bcheck(load_library().tplbm_batch_read(self._h, FIELDS[field], _dp(out)), self._h)
+        return out
+
+    def column(self, arr, k):
+        return arr[self.offsets[k]:self.offsets[k + 1]]
+
+    def autotune(self, budget_ms: float = 2000.0) -> dict:
+        t = BatchTuning()
+        _bcheck(load_library().tplbm_batch_autotune(self._h, float(budget_ms), ctypes.byref(t)),
+                self._h)
+        return dict(shape=t.shape, threads=t.threads, nodes_per_thread=t.nodes_per_thread,
+                    check_every=t.check_every, grid=t.grid, node_steps_per_s=t.node_steps_per_s)
+
+    def set_tuning(self, shape: int = -1, check_every: int = 0):
+        _bcheck(load_library().tplbm_batch_set_tuning(self._h, int(shape), int(check_every)),
+                self._h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().tplbm_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

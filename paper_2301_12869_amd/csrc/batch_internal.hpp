@@ -1,0 +1,47 @@
+// Internal interface between the batch host code and the column kernel.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm_common.hpp"
+
+namespace tplbm {
+
+struct ColumnDesc {
+    int32_t height;   // nodes, both wall nodes included
+    int32_t form;     // gravity form 1 or 2
+    int64_t offset;   // first node in the concatenated arrays
+    double g;         // gravity magnitude, positive downward
+};
+
+struct ColumnResult {
+    int64_t steps;    // level at which the run stopped
+    int32_t status;   // 0 converged, 1 diverged, 2 step budget reached
+    int32_t pad;
+    double mass;      // sum of rho at that level
+    double max_u;     // max |u| at that level
+};
+
+struct BatchArgs {
+    const ColumnDesc *cols;
+    int ncols;
+    const int *order;       // processing order (indices into cols)
+    const double *rho0, *T0;
+    double *rho_out, *T_out;
+    ColumnResult *results;
+    unsigned *queue;        // next position in `order`; zero before a launch
+    double tol;
+    int check_every;
+    int64_t max_steps;
+};
+
+struct BatchShape {
+    int threads, nodes_per_thread;
+};
+
+extern const BatchShape kBatchShapes[];
+extern const int kNumBatchShapes;
+hipError_t d1q3_batch_launch(int shape, const BatchArgs &a, const Phys &c, int grid, hipStream_t s);
+hipError_t d1q3_batch_occupancy(int shape, int *blocks_per_cu);
+
+}  // namespace tplbm
