@@ -1,0 +1,431 @@
+// D3Q19 thermal pseudopotential update for gfx950 (every relaxation time 1,
+// where the MRT collision is the BGK one): a 3-D extension of the paper's
+// D2Q9 method, walls on the z layers, periodic in x and y.
+//
+// Velocities: rest, 6 axis neighbours (w = 1/18), 12 edge neighbours
+// (w = 1/36).  Shan-Chen weights w(1) = 1/6, w(2) = 1/12 (sum w c_a c_b =
+// delta_ab, as for the paper's D2Q9 weights).  Forcing at tau = 1: half of
+// Guo's term plus the isotropic sigma term w_i (|c_i|^2 - 1)(3/4) sigma X',
+// the D2Q9 sigma term of Li's scheme written without the 2-D moment basis.
+//
+// One step is four passes over the lattice, intermediate fields in FP64:
+//   A: pull-stream with Zou-He wall reconstruction, rho, j, psi -> M
+//   B: Shan-Chen force (zero at walls), gravity, u = (j + F/2)/rho -> U
+//   C: first Heun stage of the energy equation, k1 = K(T^n) -> K1
+//   D: T^{n+1} = T^n + (k1 + K(T^n + k1))/2, collision f* = f_eq + F'
+//      (rest population closing the mass), store f* and T^{n+1}, partial
+//      sums of the next level's mass; the last block finishes <rho>.
+#include <hip/hip_runtime.h>
+
+#include "lbm_common.hpp"
+#include "lbm_internal.hpp"
+
+namespace tplbm {
+
+namespace {
+
+// velocity set: 0 rest; 1..6 = +x -x +y -y +z -z; 7..18 edges (the table
+// the host uses to lay out initial states, kD3Q19* in lbm_internal.hpp)
+struct V3 {
+    int x, y, z;
+};
+__host__ __device__ constexpr V3 vel(int i) { return V3{kD3Q19x[i], kD3Q19y[i], kD3Q19z[i]}; }
+__host__ __device__ constexpr double wgt(int i) { return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
+// opposite velocity
+__host__ __device__ constexpr int opp(int i)
+{
+    constexpr int o[19] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+    return o[i];
+}
+
+template <class S>
+struct Pop;
+template <>
+struct Pop<double> {
+    __device__ static __forceinline__ double ld(const double *p, size_t i, double) { return p[i]; }
+    __device__ static __forceinline__ double st(double *p, size_t i, double v, double)
+    {
+        p[i] = v;
+        return v;
+    }
+};
+template <>
+struct Pop<float> {
+    __device__ static __forceinline__ double ld(const float *p, size_t i, double wr) { return wr + (double)p[i]; }
+    __device__ static __forceinline__ double st(float *p, size_t i, double v, double wr)
+    {
+        const float d = (float)(v - wr);
+        p[i] = d;
+        return wr + (double)d;
+    }
+};
+
+struct Grid3 {
+    int nx, ny, nz;
+    __device__ __forceinline__ size_t idx(int x, int y, int z) const
+    {
+        return ((size_t)z * ny + y) * nx + x;
+    }
+    __device__ __forceinline__ int wx(int x) const { return x < 0 ? x + nx : (x >= nx ? x - nx : x); }
+    __device__ __forceinline__ int wy(int y) const { return y < 0 ? y + ny : (y >= ny ? y - ny : y); }
+    __device__ __forceinline__ int wz(int z) const { return z < 0 ? z + nz : (z >= nz ? z - nz : z); }
+};
+
+// ---- pass A: pull, Zou-He, moments, psi ----------------------------------
+template <class S, bool WALLS>
+__global__ __launch_bounds__(256) void d3q19_pass_a(const S *__restrict__ fin, const double *__restrict__ Tin,
+                                                    double *__restrict__ M, Phys c, Grid3 G)
+{
+    const size_t N = (size_t)G.nx * G.ny * G.nz;
+    const double rr = c.rho_ref;
+    for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N; n += (size_t)gridDim.x * blockDim.x) {
+        const int x = (int)(n % G.nx);
+        const int y = (int)((n / G.nx) % G.ny);
+        const int z = (int)(n / ((size_t)G.nx * G.ny));
+        double f[19];
+#pragma unroll
+        for (int i = 0; i < 19; ++i) {
+            const V3 v = vel(i);
+            int zs = z - v.z;
+            bool known = true;
+            if (WALLS) {
+                known = zs >= 0 && zs < G.nz;
+                zs = known ? zs : z;
+            } else {
+                zs = G.wz(zs);
+            }
+            f[i] = Pop<S>::ld(fin, (size_t)i * N + G.idx(G.wx(x - v.x), G.wy(y - v.y), zs), wgt(i) * rr);
+            (void)known;
+        }
+        if (WALLS && (z == 0 || z == G.nz - 1)) {
+            // zero-velocity wet-node reconstruction of the populations that
+            // come from beyond the wall, with transverse momentum corrections
+            const int s = z == 0 ? 1 : -1;
+            double Nx = 0.0, Ny = 0.0;
+#pragma unroll
+            for (int i = 0; i < 19; ++i) {
+                const V3 v = vel(i);
+                if (v.z == 0) {
+                    Nx += 0.5 * v.x * f[i];
+                    Ny += 0.5 * v.y * f[i];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 19; ++i) {
+                const V3 v = vel(i);
+                if (v.z == s) f[i] = f[opp(i)] - (double)v.x * Nx - (double)v.y * Ny;
+            }
+        }
+        double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+        for (int i = 0; i < 19; ++i) {
+            const V3 v = vel(i);
+            rho += f[i];
+            jx += v.x * f[i];
+            jy += v.y * f[i];
+            jz += v.z * f[i];
+        }
+        double Z;
+        const double psi = psi_and_Z(c, rho, Tin[n], Z);
+        M[n] = rho;
+        M[N + n] = jx;
+        M[2 * N + n] = jy;
+        M[3 * N + n] = jz;
+        M[4 * N + n] = psi;
+    }
+}
+
+// Shan-Chen sum s = sum_i w(|c_i|^2) psi(x + c_i) c_i, w(1) = 1/6, w(2) = 1/12
+__device__ __forceinline__ void sc_sum(const double *__restrict__ psi, const Grid3 &G, int x, int y, int z,
+                                       double &sx, double &sy, double &sz)
+{
+    sx = sy = sz = 0.0;
+#pragma unroll
+    for (int i = 1; i < 19; ++i) {
+        const V3 v = vel(i);
+        const double w = i < 7 ? 1.0 / 6.0 : 1.0 / 12.0;
+        const double p = psi[G.idx(G.wx(x + v.x), G.wy(y + v.y), G.wz(z + v.z))];
+        sx += w * v.x * p;
+        sy += w * v.y * p;
+        sz += w * v.z * p;
+    }
+}
+
+// ---- pass B: force and velocity --------------------------------------------
+template <bool WALLS>
+__global__ __launch_bounds__(256) void d3q19_pass_b(const double *__restrict__ M, double *__restrict__ U,
+                                                    Phys c, Grid3 G, const StepState *__restrict__ st,
+                                                    int slot)
+{
+    const size_t N = (size_t)G.nx * G.ny * G.nz;
+    const double mean = st->mean[slot];
+    for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N; n += (size_t)gridDim.x * blockDim.x) {
+        const int x = (int)(n % G.nx);
+        const int y = (int)((n / G.nx) % G.ny);
+        const int z = (int)(n / ((size_t)G.nx * G.ny));
+        const double rho = M[n];
+        double Fx = 0.0, Fy = 0.0, Fz = 0.0;
+        if (!(WALLS && (z == 0 || z == G.nz - 1))) {
+            double sx, sy, sz;
+            sc_sum(M + 4 * N, G, x, y, z, sx, sy, sz);
+            const double mg = -c.G * M[4 * N + n];
+            Fx = mg * sx;
+            Fy = mg * sy;
+            Fz = mg * sz + ((c.form == 2) ? -(rho - mean) * c.g : -rho * c.g);
+        }
+        const double inv = rcp_pos(rho);
+        U[n] = (M[N + n] + 0.5 * Fx) * inv;
+        U[N + n] = (M[2 * N + n] + 0.5 * Fy) * inv;
+        U[2 * N + n] = (M[3 * N + n] + 0.5 * Fz) * inv;
+    }
+}
+
+// isotropic differences on the D3Q19 stencil: grad = 3 sum w c phi,
+// lap = 6 sum w (phi_i - phi_0), div u = 3 sum w c.u_i
+__device__ __forceinline__ void grad_lap(const double *__restrict__ a, const double *__restrict__ b, const Grid3 &G,
+                                         int x, int y, int z, double c0, double &gx, double &gy, double &gz,
+                                         double &lap)
+{
+    gx = gy = gz = lap = 0.0;
+#pragma unroll
+    for (int i = 1; i < 19; ++i) {
+        const V3 v = vel(i);
+        const size_t m = G.idx(G.wx(x + v.x), G.wy(y + v.y), G.wz(z + v.z));
+        const double p = b ? a[m] + b[m] : a[m];
+        const double w = wgt(i);
+        gx += w * v.x * p;
+        gy += w * v.y * p;
+        gz += w * v.z * p;
+        lap += w * (p - c0);
+    }
+    gx *= 3.0;
+    gy *= 3.0;
+    gz *= 3.0;
+    lap *= 6.0;
+}
+
+__device__ __forceinline__ double div3(const double *__restrict__ U, size_t N, const Grid3 &G, int x, int y, int z)
+{
+    double d = 0.0;
+#pragma unroll
+    for (int i = 1; i < 19; ++i) {
+        const V3 v = vel(i);
+        const size_t m = G.idx(G.wx(x + v.x), G.wy(y + v.y), G.wz(z + v.z));
+        d += wgt(i) * (v.x * U[m] + v.y * U[N + m] + v.z * U[2 * N + m]);
+    }
+    return 3.0 * d;
+}
+
+// ---- pass C: first Heun stage ------------------------------------------------
+template <bool WALLS>
+__global__ __launch_bounds__(256) void d3q19_pass_c(const double *__restrict__ Tin, const double *__restrict__ M,
+                                                    const double *__restrict__ U, double *__restrict__ K1,
+                                                    Phys c, Grid3 G)
+{
+    const size_t N = (size_t)G.nx * G.ny * G.nz;
+    for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N; n += (size_t)gridDim.x * blockDim.x) {
+        const int x = (int)(n % G.nx);
+        const int y = (int)((n / G.nx) % G.ny);
+        const int z = (int)(n / ((size_t)G.nx * G.ny));
+        if (WALLS && (z == 0 || z == G.nz - 1)) {
+            K1[n] = 0.0;
+            continue;
+        }
+        const double rho = M[n], T0 = Tin[n];
+        double gx, gy, gz, lap;
+        grad_lap(Tin, nullptr, G, x, y, z, T0, gx, gy, gz, lap);
+        const double divu = div3(U, N, G, x, y, z);
+        const double Z = c.eos == 0 ? cs_Z(c.b_quarter * rho) : 0.0;
+        K1[n] = -(U[n] * gx + U[N + n] * gy + U[2 * N + n] * gz) + c.kappa_over_cv * rcp_pos(rho) * lap -
+                T0 * c.R_over_cv * Z * divu;
+    }
+}
+
+// ---- pass D: second Heun stage, collision, stores, partials ------------------
+template <class S, bool WALLS>
+__global__ __launch_bounds__(256) void d3q19_pass_d(const double *__restrict__ Tin, double *__restrict__ Tout,
+                                                    const double *__restrict__ M, const double *__restrict__ U,
+                                                    const double *__restrict__ K1, S *__restrict__ fout, Phys c,
+                                                    Grid3 G, double *__restrict__ partials,
+                                                    StepState *__restrict__ st, int64_t step)
+{
+    __shared__ double s_red[16];
+    __shared__ unsigned s_ured[4];
+    const size_t N = (size_t)G.nx * G.ny * G.nz;
+    const double rr = c.rho_ref;
+    const double mean = st->mean[step & 1];
+    Partial part = {0.0, 0.0, 0.0, 1e300, 0u};
+    for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N; n += (size_t)gridDim.x * blockDim.x) {
+        const int x = (int)(n % G.nx);
+        const int y = (int)((n / G.nx) % G.ny);
+        const int z = (int)(n / ((size_t)G.nx * G.ny));
+        const bool wall = WALLS && (z == 0 || z == G.nz - 1);
+        const double rho = M[n], ux = U[n], uy = U[N + n], uz = U[2 * N + n], T0 = Tin[n];
+        double Tn = T0;
+        if (!wall) {
+            const double k1 = K1[n];
+            double gx, gy, gz, lap;
+            grad_lap(Tin, K1, G, x, y, z, T0 + k1, gx, gy, gz, lap);
+            const double divu = div3(U, N, G, x, y, z);
+            const double Z = c.eos == 0 ? cs_Z(c.b_quarter * rho) : 0.0;
+            const double k2 = -(ux * gx + uy * gy + uz * gz) + c.kappa_over_cv * rcp_pos(rho) * lap -
+                              (T0 + k1) * c.R_over_cv * Z * divu;
+            Tn = T0 + 0.5 * (k1 + k2);
+        }
+        Tout[n] = Tn;
+        double Fx = 0.0, Fy = 0.0, Fz = 0.0, X = 0.0;
+        const double psi0 = M[4 * N + n];
+        if (!wall) {
+            double sx, sy, sz;
+            sc_sum(M + 4 * N, G, x, y, z, sx, sy, sz);
+            const double mg = -c.G * psi0;
+            Fx = mg * sx;
+            Fy = mg * sy;
+            Fz = mg * sz + ((c.form == 2) ? -(rho - mean) * c.g : -rho * c.g);
+            X = c.sigma * c.G2 * (sx * sx + sy * sy + sz * sz);  // sigma |F_int|^2 / psi^2
+        }
+        const double uu = ux * ux + uy * uy + uz * uz;
+        const double uF = ux * Fx + uy * Fy + uz * Fz;
+        double fs[19];
+        double rest = 0.0;
+#pragma unroll
+        for (int i = 1; i < 19; ++i) {
+            const V3 v = vel(i);
+            const double w = wgt(i);
+            const double cu = v.x * ux + v.y * uy + v.z * uz;
+            const double cF = v.x * Fx + v.y * Fy + v.z * Fz;
+            const double c2 = (double)(v.x * v.x + v.y * v.y + v.z * v.z);
+            fs[i] = w * (rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu) + 1.5 * (cF - uF) + 4.5 * cu * cF +
+                         (c2 - 1.0) * 0.75 * X);
+            rest += fs[i];
+        }
+        fs[0] = rho - rest;
+        double nm = 0.0, down = 0.0, up = 0.0;
+#pragma unroll
+        for (int i = 0; i < 19; ++i) {
+            const double v = Pop<S>::st(fout, (size_t)i * N + n, fs[i], wgt(i) * rr);
+            nm += v;
+            const int cz = vel(i).z;
+            if (cz < 0) down += v;
+            if (cz > 0) up += v;
+        }
+        if (WALLS) {
+            if (z == 0) nm -= down;
+            if (z == 1) nm += down;
+            if (z == G.nz - 2) nm += up;
+            if (z == G.nz - 1) nm -= up;
+        }
+        part.mass_n += rho;
+        part.mass_next += nm;
+        part.umax = fmax(part.umax, uu);
+        part.rmin = fmin(part.rmin, rho);
+        unsigned fl = 0u;
+        if (!(rho > 0.0)) fl |= kFlagRho;
+        if (c.eos == 0 && c.b_quarter * rho >= 1.0) fl |= kFlagEta;
+        if (psi0 != psi0) fl |= kFlagPsi;
+        if (rho != rho || uu != uu || Tn != Tn || nm != nm) fl |= kFlagNaN;
+        part.flags |= fl;
+    }
+    part = block_reduce<256>(part, s_red, s_ured);
+    finish_launch<256>(part, partials, st, step, (int)((step + 1) & 1), 1.0 / (double)N, s_red, s_ured);
+}
+
+// ---- readout: from M and U of the current level -------------------------------
+template <bool WALLS>
+__global__ void d3q19_readout(const double *__restrict__ M, const double *__restrict__ U,
+                              const double *__restrict__ Tin, Phys c, Grid3 G, int field,
+                              double *__restrict__ out)
+{
+    const size_t N = (size_t)G.nx * G.ny * G.nz;
+    for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N; n += (size_t)gridDim.x * blockDim.x) {
+        const int x = (int)(n % G.nx);
+        const int y = (int)((n / G.nx) % G.ny);
+        const int z = (int)(n / ((size_t)G.nx * G.ny));
+        const double r = M[n];
+        double v = 0.0;
+        if (field == 0) v = r;
+        else if (field == 1) v = U[n];
+        else if (field == 2) v = U[N + n];
+        else if (field == 3) v = U[2 * N + n];
+        else if (field == 4) v = Tin[n];
+        else {
+            const double pe = p_eos(c, r, Tin[n]);
+            v = pe;
+            if (field == 6 && !(WALLS && (z == 0 || z == G.nz - 1))) {
+                const double *psi = M + 4 * N;
+                const double p0 = psi[n];
+                const double pxp = psi[G.idx(G.wx(x + 1), y, z)], pxm = psi[G.idx(G.wx(x - 1), y, z)];
+                const double pyp = psi[G.idx(x, G.wy(y + 1), z)], pym = psi[G.idx(x, G.wy(y - 1), z)];
+                const double pzp = psi[G.idx(x, y, G.wz(z + 1))], pzm = psi[G.idx(x, y, G.wz(z - 1))];
+                const double dx = 0.5 * (pxp - pxm), dy = 0.5 * (pyp - pym), dz = 0.5 * (pzp - pzm);
+                const double lap = (pxp + pxm) + (pyp + pym) + (pzp + pzm) - 6.0 * p0;
+                const double dzz = (pzp + pzm) - 2.0 * p0;
+                v = pe + c.sigma * c.G2 * (1.0 / 6.0) * (dx * dx + dy * dy + dz * dz) +
+                    c.G * (1.0 / 12.0) * p0 * lap + c.G * (1.0 / 6.0) * p0 * dzz;
+            }
+        }
+        out[n] = v;
+    }
+}
+
+int grid_1d(size_t N, int per_cu_blocks, int cus)
+{
+    const size_t want = (N + 255) / 256;
+    const size_t cap = (size_t)cus * per_cu_blocks;
+    return (int)(want < cap ? want : cap);
+}
+
+template <class S, bool WALLS>
+hipError_t step_t(const LatticeLaunch &L, double *M, double *U, double *K1)
+{
+    Grid3 G{L.nx, L.ny, L.nz};
+    const size_t N = (size_t)L.nx * L.ny * L.nz;
+    const int gA = grid_1d(N, 8, L.resident);
+    hipLaunchKernelGGL((d3q19_pass_a<S, WALLS>), dim3(gA), dim3(256), 0, L.stream, (const S *)L.fin, L.Tin, M,
+                       L.phys, G);
+    hipLaunchKernelGGL((d3q19_pass_b<WALLS>), dim3(gA), dim3(256), 0, L.stream, M, U, L.phys, G, L.st,
+                       (int)(L.step & 1));
+    hipLaunchKernelGGL((d3q19_pass_c<WALLS>), dim3(gA), dim3(256), 0, L.stream, L.Tin, M, U, K1, L.phys, G);
+    const int gD = d3q19_num_blocks(N, L.resident);
+    hipLaunchKernelGGL((d3q19_pass_d<S, WALLS>), dim3(gD), dim3(256), 0, L.stream, L.Tin, L.Tout, M, U, K1,
+                       (S *)L.fout, L.phys, G, L.partials, L.st, L.step);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int d3q19_num_blocks(size_t N, int cus) { return grid_1d(N, 8, cus); }
+
+hipError_t d3q19_launch_step(const LatticeLaunch &L, double *M, double *U, double *K1)
+{
+    if (L.fp32) return L.walls ? step_t<float, true>(L, M, U, K1) : step_t<float, false>(L, M, U, K1);
+    return L.walls ? step_t<double, true>(L, M, U, K1) : step_t<double, false>(L, M, U, K1);
+}
+
+hipError_t d3q19_launch_readout(const LatticeLaunch &L, int field, double *M, double *U, double *out)
+{
+    Grid3 G{L.nx, L.ny, L.nz};
+    const size_t N = (size_t)L.nx * L.ny * L.nz;
+    const int g = grid_1d(N, 8, L.resident);
+    if (L.fp32) {
+        if (L.walls)
+            hipLaunchKernelGGL((d3q19_pass_a<float, true>), dim3(g), dim3(256), 0, L.stream, (const float *)L.fin, L.Tin, M, L.phys, G);
+        else
+            hipLaunchKernelGGL((d3q19_pass_a<float, false>), dim3(g), dim3(256), 0, L.stream, (const float *)L.fin, L.Tin, M, L.phys, G);
+    } else {
+        if (L.walls)
+            hipLaunchKernelGGL((d3q19_pass_a<double, true>), dim3(g), dim3(256), 0, L.stream, (const double *)L.fin, L.Tin, M, L.phys, G);
+        else
+            hipLaunchKernelGGL((d3q19_pass_a<double, false>), dim3(g), dim3(256), 0, L.stream, (const double *)L.fin, L.Tin, M, L.phys, G);
+    }
+    if (L.walls) {
+        hipLaunchKernelGGL((d3q19_pass_b<true>), dim3(g), dim3(256), 0, L.stream, M, U, L.phys, G, L.st, (int)(L.step & 1));
+        hipLaunchKernelGGL((d3q19_readout<true>), dim3(g), dim3(256), 0, L.stream, M, U, L.Tin, L.phys, G, field, out);
+    } else {
+        hipLaunchKernelGGL((d3q19_pass_b<false>), dim3(g), dim3(256), 0, L.stream, M, U, L.phys, G, L.st, (int)(L.step & 1));
+        hipLaunchKernelGGL((d3q19_readout<false>), dim3(g), dim3(256), 0, L.stream, M, U, L.Tin, L.phys, G, field, out);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace tplbm

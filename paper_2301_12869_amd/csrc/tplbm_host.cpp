@@ -24,6 +24,7 @@ struct tplbm_ctx {
     double *T[2] = {nullptr, nullptr};
     double *partials = nullptr;
     StepState *st = nullptr;
+    double *M = nullptr, *U = nullptr, *K1 = nullptr;  // D3Q19 pass buffers
     int cur = 0;
     int64_t step = 0;
     int nblocks = 0;
@@ -74,9 +75,14 @@ int validate(const tplbm_params *p)
     if (!p) return fail(nullptr, TPLBM_EINVAL, "params is NULL");
     if (p->lattice != TPLBM_D2Q9 && p->lattice != TPLBM_D3Q19)
         return fail(nullptr, TPLBM_EINVAL, "lattice must be TPLBM_D2Q9 or TPLBM_D3Q19 (columns use tplbm_batch_*)");
-    if (p->lattice == TPLBM_D3Q19) return fail(nullptr, TPLBM_EUNSUPPORTED, "D3Q19 lattices are not built into this library");
-    if (p->nx < 1 || p->ny < 3) return fail(nullptr, TPLBM_ESHAPE, "need nx >= 1 and ny >= 3");
-    if ((int64_t)p->nx * p->ny > (int64_t)1 << 31) return fail(nullptr, TPLBM_ESHAPE, "lattice too large");
+    if (p->lattice == TPLBM_D3Q19) {
+        if (p->nx < 1 || p->ny < 1 || p->nz < 3) return fail(nullptr, TPLBM_ESHAPE, "need nx, ny >= 1 and nz >= 3");
+        if ((int64_t)p->nx * p->ny * p->nz > (int64_t)1 << 31) return fail(nullptr, TPLBM_ESHAPE, "lattice too large");
+        if (!tau_one(*p)) return fail(nullptr, TPLBM_EUNSUPPORTED, "D3Q19 supports only every tau = 1");
+    } else {
+        if (p->nx < 1 || p->ny < 3) return fail(nullptr, TPLBM_ESHAPE, "need nx >= 1 and ny >= 3");
+        if ((int64_t)p->nx * p->ny > (int64_t)1 << 31) return fail(nullptr, TPLBM_ESHAPE, "lattice too large");
+    }
     if (p->precision != TPLBM_FP64 && p->precision != TPLBM_FP32_DEV)
         return fail(nullptr, TPLBM_EINVAL, "precision must be TPLBM_FP64 or TPLBM_FP32_DEV");
     if (p->eos != TPLBM_EOS_CARNAHAN_STARLING && p->eos != TPLBM_EOS_IDEAL_LATTICE)
@@ -124,24 +130,37 @@ Phys make_phys(const tplbm_params &p)
 }
 
 struct Layout {
-    size_t f_bytes, T_bytes, part_bytes, st_bytes, total;
+    size_t f_bytes, T_bytes, part_bytes, st_bytes, pass_bytes, total;
     int nblocks;
 };
+
+size_t nodes_of(const tplbm_params &p)
+{
+    return (size_t)p.nx * p.ny * (p.lattice == TPLBM_D3Q19 ? (size_t)p.nz : 1);
+}
+int q_of(const tplbm_params &p) { return p.lattice == TPLBM_D3Q19 ? 19 : 9; }
 
 Layout layout_of(const tplbm_params &p)
 {
     Layout L;
-    const size_t N = (size_t)p.nx * p.ny;
+    const size_t N = nodes_of(p);
     const size_t elem = p.precision == TPLBM_FP32_DEV ? 4 : 8;
-    L.f_bytes = align256(9 * N * elem);
-    // readout scratch reuses the idle population buffer: it needs 4N doubles
-    if (L.f_bytes < align256(4 * N * 8)) L.f_bytes = align256(4 * N * 8);
+    L.f_bytes = align256(q_of(p) * N * elem);
     L.T_bytes = align256(N * 8);
-    // partials for the largest grid the persistent launch can use
-    L.nblocks = d2q9_num_blocks(p.nx, p.ny, 1 << 20);
+    if (p.lattice == TPLBM_D3Q19) {
+        // pass buffers: M (rho, j, psi), U (u), K1
+        L.pass_bytes = align256(5 * N * 8) + align256(3 * N * 8) + align256(N * 8);
+        L.nblocks = d3q19_num_blocks(N, 1 << 20);
+    } else {
+        // readout scratch reuses the idle population buffer: it needs 4N doubles
+        if (L.f_bytes < align256(4 * N * 8)) L.f_bytes = align256(4 * N * 8);
+        L.pass_bytes = 0;
+        // partials for the largest grid the persistent launch can use
+        L.nblocks = d2q9_num_blocks(p.nx, p.ny, 1 << 20);
+    }
     L.part_bytes = align256((size_t)L.nblocks * 5 * 8);
     L.st_bytes = align256(sizeof(StepState));
-    L.total = 2 * L.f_bytes + 2 * L.T_bytes + L.part_bytes + L.st_bytes;
+    L.total = 2 * L.f_bytes + 2 * L.T_bytes + L.part_bytes + L.st_bytes + L.pass_bytes;
     return L;
 }
 
@@ -165,7 +184,7 @@ LatticeLaunch launch_of(tplbm_ctx *c)
     L.phys = c->phys;
     L.nx = c->p.nx;
     L.ny = c->p.ny;
-    L.nz = 1;
+    L.nz = c->p.lattice == TPLBM_D3Q19 ? c->p.nz : 1;
     L.fp32 = c->p.precision == TPLBM_FP32_DEV;
     L.tau1 = tau_one(c->p);
     L.walls = c->p.walls != 0;
@@ -211,7 +230,8 @@ int tplbm_create(const tplbm_params *p, void *dev_workspace, size_t bytes, void 
     c->ws = (char *)dev_workspace;
     c->ws_bytes = bytes;
     c->resident = resident_blocks();
-    c->N = (size_t)p->nx * p->ny;
+    c->N = nodes_of(*p);
+    c->Q = q_of(*p);
     c->nblocks = L.nblocks;
     char *q = c->ws;
     c->f[0] = q; q += L.f_bytes;
@@ -219,7 +239,12 @@ int tplbm_create(const tplbm_params *p, void *dev_workspace, size_t bytes, void 
     c->T[0] = (double *)q; q += L.T_bytes;
     c->T[1] = (double *)q; q += L.T_bytes;
     c->partials = (double *)q; q += L.part_bytes;
-    c->st = (StepState *)q;
+    c->st = (StepState *)q; q += L.st_bytes;
+    if (p->lattice == TPLBM_D3Q19) {
+        c->M = (double *)q; q += align256(5 * c->N * 8);
+        c->U = (double *)q; q += align256(3 * c->N * 8);
+        c->K1 = (double *)q;
+    }
     c->phys = make_phys(*p);
     StepState s;
     std::memset(&s, 0, sizeof s);
@@ -238,36 +263,53 @@ int tplbm_set_state(tplbm_ctx *c, const double *rho0, const double *T0)
 {
     if (!c) return fail(nullptr, TPLBM_EINVAL, "ctx is NULL");
     if (!rho0 || !T0) return fail(c, TPLBM_EINVAL, "rho0 and T0 must be non-NULL");
-    const int nx = c->p.nx, ny = c->p.ny;
+    const bool d3 = c->p.lattice == TPLBM_D3Q19;
+    const int nx = c->p.nx, ny = c->p.ny, nz = d3 ? c->p.nz : 1, Q = c->Q;
     const size_t N = c->N;
     const bool walls = c->p.walls != 0, fp32 = c->p.precision == TPLBM_FP32_DEV;
     const double rr = c->phys.rho_ref;
+    double w[19];
+    int cx[19], cy[19], cz[19];
+    for (int i = 0; i < Q; ++i) {
+        if (d3) {
+            cx[i] = kD3Q19x[i]; cy[i] = kD3Q19y[i]; cz[i] = kD3Q19z[i];
+            w[i] = i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+        } else {
+            cx[i] = kCx[i]; cy[i] = kCy[i]; cz[i] = 0;
+            w[i] = kW[i];
+        }
+    }
     // The buffer holds post-collision populations that the first step pulls
     // from: f*_i(x) = w_i rho0(x + c_i) makes the pulled level-0 state the
     // rest state f_i = w_i rho0(x).  Sources beyond a wall are never pulled.
+    // The wall-normal axis is y in 2-D and z in 3-D.
     std::vector<double> fd;
     std::vector<float> ff;
-    if (fp32) ff.resize(9 * N); else fd.resize(9 * N);
-    for (int y = 0; y < ny; ++y)
-        for (int x = 0; x < nx; ++x)
-            for (int i = 0; i < 9; ++i) {
-                int xs = (x + kCx[i] + nx) % nx;
-                int ys = y + kCy[i];
-                if (walls) {
-                    if (ys < 0 || ys >= ny) ys = y;
-                } else {
-                    ys = (ys + ny) % ny;
+    if (fp32) ff.resize((size_t)Q * N); else fd.resize((size_t)Q * N);
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const size_t n = ((size_t)z * ny + y) * nx + x;
+                for (int i = 0; i < Q; ++i) {
+                    int xs = ((x + cx[i]) % nx + nx) % nx;
+                    int ys = y + cy[i], zs = z + cz[i];
+                    if (d3) {
+                        ys = ((ys % ny) + ny) % ny;
+                        if (walls) { if (zs < 0 || zs >= nz) zs = z; } else zs = ((zs % nz) + nz) % nz;
+                    } else {
+                        if (walls) { if (ys < 0 || ys >= ny) ys = y; } else ys = ((ys % ny) + ny) % ny;
+                    }
+                    const double v = w[i] * rho0[((size_t)zs * ny + ys) * nx + xs];
+                    const size_t k = (size_t)i * N + n;
+                    if (fp32) ff[k] = (float)(v - w[i] * rr); else fd[k] = v;
                 }
-                const double v = kW[i] * rho0[(size_t)ys * nx + xs];
-                const size_t k = (size_t)i * N + (size_t)y * nx + x;
-                if (fp32) ff[k] = (float)(v - kW[i] * rr); else fd[k] = v;
             }
     // <rho> of level 0 from the values the first step will see, index order
     double tot = 0.0;
     for (size_t n = 0; n < N; ++n) {
         if (fp32) {
             double r = 0.0;
-            for (int i = 0; i < 9; ++i) r += kW[i] * rr + (double)(float)(kW[i] * rho0[n] - kW[i] * rr);
+            for (int i = 0; i < Q; ++i) r += w[i] * rr + (double)(float)(w[i] * rho0[n] - w[i] * rr);
             tot += r;
         } else {
             tot += rho0[n];
@@ -276,9 +318,9 @@ int tplbm_set_state(tplbm_ctx *c, const double *rho0, const double *T0)
     c->cur = 0;
     c->step = 0;
     if (fp32)
-        HIP_OK(c, hipMemcpyAsync(c->f[0], ff.data(), 9 * N * 4, hipMemcpyHostToDevice, c->stream));
+        HIP_OK(c, hipMemcpyAsync(c->f[0], ff.data(), (size_t)Q * N * 4, hipMemcpyHostToDevice, c->stream));
     else
-        HIP_OK(c, hipMemcpyAsync(c->f[0], fd.data(), 9 * N * 8, hipMemcpyHostToDevice, c->stream));
+        HIP_OK(c, hipMemcpyAsync(c->f[0], fd.data(), (size_t)Q * N * 8, hipMemcpyHostToDevice, c->stream));
     HIP_OK(c, hipMemcpyAsync(c->T[0], T0, N * 8, hipMemcpyHostToDevice, c->stream));
     StepState s;
     std::memset(&s, 0, sizeof s);
@@ -298,7 +340,10 @@ int tplbm_step_async(tplbm_ctx *c, int64_t nsteps)
     if (!c->have_state) return fail(c, TPLBM_EINVAL, "call tplbm_set_state or tplbm_load_state first");
     for (int64_t s = 0; s < nsteps; ++s) {
         LatticeLaunch L = launch_of(c);
-        HIP_OK(c, d2q9_launch_step(L));
+        if (c->p.lattice == TPLBM_D3Q19)
+            HIP_OK(c, d3q19_launch_step(L, c->M, c->U, c->K1));
+        else
+            HIP_OK(c, d2q9_launch_step(L));
         c->cur = 1 - c->cur;
         c->step += 1;
     }
@@ -325,7 +370,10 @@ int tplbm_read_device(tplbm_ctx *c, int field, double *dev_out)
     if (field < TPLBM_RHO || field > TPLBM_P_NN) return fail(c, TPLBM_EINVAL, "unknown field %d", field);
     if (!c->have_state) return fail(c, TPLBM_EINVAL, "no state");
     LatticeLaunch L = launch_of(c);
-    HIP_OK(c, d2q9_launch_readout(L, field, (double *)c->f[1 - c->cur], dev_out));
+    if (c->p.lattice == TPLBM_D3Q19)
+        HIP_OK(c, d3q19_launch_readout(L, field, c->M, c->U, dev_out));
+    else
+        HIP_OK(c, d2q9_launch_readout(L, field, (double *)c->f[1 - c->cur], dev_out));
     return TPLBM_OK;
 }
 
@@ -340,7 +388,10 @@ int tplbm_read(tplbm_ctx *c, int field, double *host_out)
     double *scratch = (double *)c->f[1 - c->cur];
     double *dst = c->T[1 - c->cur];  // idle temperature buffer, N doubles
     LatticeLaunch L = launch_of(c);
-    HIP_OK(c, d2q9_launch_readout(L, field, scratch, dst));
+    if (c->p.lattice == TPLBM_D3Q19)
+        HIP_OK(c, d3q19_launch_readout(L, field, c->M, c->U, dst));
+    else
+        HIP_OK(c, d2q9_launch_readout(L, field, scratch, dst));
     HIP_OK(c, hipMemcpyAsync(host_out, dst, c->N * 8, hipMemcpyDeviceToHost, c->stream));
     HIP_OK(c, hipStreamSynchronize(c->stream));
     return TPLBM_OK;
@@ -367,7 +418,7 @@ int tplbm_state_bytes(const tplbm_ctx *c, size_t *bytes)
 {
     if (!c || !bytes) return fail(nullptr, TPLBM_EINVAL, "NULL argument");
     const size_t elem = c->p.precision == TPLBM_FP32_DEV ? 4 : 8;
-    *bytes = 64 + 9 * c->N * elem + c->N * 8 + sizeof(StepState);
+    *bytes = 64 + (size_t)c->Q * c->N * elem + c->N * 8 + sizeof(StepState);
     return TPLBM_OK;
 }
 
@@ -393,15 +444,16 @@ int tplbm_save_state(tplbm_ctx *c, void *host_blob)
     std::memcpy(h.magic, "TPLBMST1", 8);
     h.step = c->step;
     h.N = (int64_t)c->N;
-    h.Q = 9;
+    h.Q = c->Q;
     h.elem = (int32_t)elem;
     h.nx = c->p.nx;
     h.ny = c->p.ny;
     char *b = (char *)host_blob;
     std::memcpy(b, &h, sizeof h);
-    HIP_OK(c, hipMemcpyAsync(b + 64, c->f[c->cur], 9 * c->N * elem, hipMemcpyDeviceToHost, c->stream));
-    HIP_OK(c, hipMemcpyAsync(b + 64 + 9 * c->N * elem, c->T[c->cur], c->N * 8, hipMemcpyDeviceToHost, c->stream));
-    HIP_OK(c, hipMemcpyAsync(b + 64 + 9 * c->N * elem + c->N * 8, c->st, sizeof(StepState),
+    const size_t fb = (size_t)c->Q * c->N * elem;
+    HIP_OK(c, hipMemcpyAsync(b + 64, c->f[c->cur], fb, hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(c, hipMemcpyAsync(b + 64 + fb, c->T[c->cur], c->N * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(c, hipMemcpyAsync(b + 64 + fb + c->N * 8, c->st, sizeof(StepState),
                              hipMemcpyDeviceToHost, c->stream));
     HIP_OK(c, hipStreamSynchronize(c->stream));
     return TPLBM_OK;
@@ -414,15 +466,16 @@ int tplbm_load_state(tplbm_ctx *c, const void *host_blob)
     BlobHeader h;
     std::memcpy(&h, host_blob, sizeof h);
     if (std::memcmp(h.magic, "TPLBMST1", 8) != 0 || h.N != (int64_t)c->N || h.elem != (int32_t)elem ||
-        h.nx != c->p.nx || h.ny != c->p.ny)
+        h.nx != c->p.nx || h.ny != c->p.ny || h.Q != c->Q)
         return fail(c, TPLBM_ESHAPE, "checkpoint does not match this lattice");
     const char *b = (const char *)host_blob;
     c->cur = 0;
     c->step = h.step;
-    HIP_OK(c, hipMemcpyAsync(c->f[0], b + 64, 9 * c->N * elem, hipMemcpyHostToDevice, c->stream));
-    HIP_OK(c, hipMemcpyAsync(c->T[0], b + 64 + 9 * c->N * elem, c->N * 8, hipMemcpyHostToDevice, c->stream));
+    const size_t fb = (size_t)c->Q * c->N * elem;
+    HIP_OK(c, hipMemcpyAsync(c->f[0], b + 64, fb, hipMemcpyHostToDevice, c->stream));
+    HIP_OK(c, hipMemcpyAsync(c->T[0], b + 64 + fb, c->N * 8, hipMemcpyHostToDevice, c->stream));
     StepState s;
-    std::memcpy(&s, b + 64 + 9 * c->N * elem + c->N * 8, sizeof s);
+    std::memcpy(&s, b + 64 + fb + c->N * 8, sizeof s);
     s.counter = 0;
     HIP_OK(c, hipMemcpyAsync(c->st, &s, sizeof s, hipMemcpyHostToDevice, c->stream));
     HIP_OK(c, hipStreamSynchronize(c->stream));
