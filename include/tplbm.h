@@ -265,6 +265,102 @@ int tplbm_batch_set_tuning(tplbm_batch *b, int32_t shape, int32_t check_every);
 void tplbm_batch_destroy(tplbm_batch *b);
 const char *tplbm_batch_last_error(const tplbm_batch *b);
 
+/* ------------------------------------------------------------------------
+ * Learned warm start for the column sweep.
+ *
+ * A 1-D convolutional network maps a column's parameters to its steady
+ * density and temperature profiles; its prediction seeds tplbm_batch_* runs,
+ * which remain the judge of the steady state.  The paper starts its runs
+ * from liquid below vapour (Sec. V, example of phase formation) and notes
+ * that a run may instead start from the theoretical profile (Sec. IV B);
+ * the network is a learned stand-in for that profile, trained on steady
+ * profiles that the column sweep itself produced.
+ *
+ * Network: six width-5 convolutions 8 -> 64 -> 64 -> 64 -> 64 -> 64 -> 2
+ * along the column, zero padding at the two ends of each column (columns in
+ * a batch never see each other), ReLU after the first five.  Input channels
+ * at node y of a column of height H: (y + 1/2)/H - 1/2, T/T_c - 0.8,
+ * log10 g + 5, gravity_form - 3/2, <rho>/rho_c - 1.3, H/2048 - 1/2, 0, 0.
+ * Output channels: rho/rho_c - <rho>/rho_c and T/T_c - T_wall/T_c.  Loss:
+ * mean over nodes and both channels of the squared error.
+ *
+ * Arithmetic: FP32 master parameters and Adam moments (beta1 0.9, beta2
+ * 0.999, eps 1e-8); every product runs on the BF16 matrix cores (inputs,
+ * weights and back-propagated gradients rounded to BF16, nearest-even) with
+ * FP32 accumulation; biases, losses and reductions in FP32.
+ *
+ * Parameter vector (FP32): for each layer l in order, W_l with shape
+ * (C_out, 5, C_in) row-major (tap t reads node y + t - 2), then b_l (C_out).
+ * ---------------------------------------------------------------------- */
+
+typedef struct tplbm_net_column {
+    int32_t height;        /* nodes including both wall nodes, 3 .. 2048 */
+    int32_t gravity_form;  /* 1 or 2 */
+    double t_reduced;      /* T / T_c of the isothermal column (also its wall value) */
+    double g;              /* gravity magnitude, > 0 */
+    double mean_reduced;   /* <rho> / rho_c, the column's mean density */
+} tplbm_net_column;
+
+typedef struct tplbm_net_config {
+    double rho_c, T_c;       /* critical density and temperature of the EOS */
+    int32_t max_cols;        /* columns per call (minibatch or prediction) */
+    int32_t dataset_cols;    /* training columns held on the device (0: none) */
+    int64_t max_nodes;       /* sum of heights per call, at most about 2^25 */
+    int64_t dataset_nodes;   /* sum of heights of the training columns */
+} tplbm_net_config;
+
+typedef struct tplbm_net tplbm_net;
+
+/* Number of parameters (85 442). */
+int tplbm_net_num_params(int64_t *n);
+
+/* Device workspace bytes for a configuration (pure). */
+int tplbm_net_workspace_bytes(const tplbm_net_config *c, size_t *bytes);
+
+/* Bind a caller-owned device workspace (256-byte aligned, kept alive until
+ * destroy) and a HIP stream.  Errors: EINVAL, ESHAPE. */
+int tplbm_net_create(const tplbm_net_config *c, void *dev_workspace, size_t bytes, void *hip_stream,
+                     tplbm_net **out);
+
+/* Load the FP32 parameter vector from host memory (the layout above) and
+ * reset the Adam moments and step count.  Errors: EINVAL (non-finite). */
+int tplbm_net_set_params(tplbm_net *n, const float *theta);
+int tplbm_net_get_params(tplbm_net *n, float *theta);
+
+/* Copy a training set to the device: ncols column descriptions and their
+ * steady profiles rho and T (host, concatenated column after column).
+ * Errors: EINVAL, ESHAPE (more than the workspace holds). */
+int tplbm_net_set_dataset(tplbm_net *n, int32_t ncols, const tplbm_net_column *cols, const double *rho,
+                          const double *T);
+
+/* Loss of the dataset columns idx[0..nbatch) and its gradient with respect
+ * to the parameters (host, may be NULL).  Parameters are not changed.
+ * Synchronous. */
+int tplbm_net_loss_grad(tplbm_net *n, int32_t nbatch, const int32_t *idx, double *loss, float *grad);
+
+/* One Adam step with learning rate lr on the minibatch idx[0..nbatch);
+ * *loss (may be NULL) receives the loss before the step. */
+int tplbm_net_train_step(tplbm_net *n, int32_t nbatch, const int32_t *idx, float lr, double *loss);
+
+/* Raw network outputs for caller columns: out[2 (offset_k + y) + c] for
+ * channel c at node y of column k (offset_k = sum of earlier heights);
+ * host array of 2 * sum(height) floats.  Synchronous. */
+int tplbm_net_forward(tplbm_net *n, int32_t ncols, const tplbm_net_column *cols, float *out);
+
+/* Warm-start profiles (host, concatenated, FP64): rho = rho_c (out_0 +
+ * <rho>/rho_c) shifted by one constant per column so that its mean is
+ * exactly <rho>; T = T_c (T/T_c + out_1) inside and T_c t_reduced at the two
+ * wall nodes (the Dirichlet data).  Pass them to tplbm_batch_set_state. */
+int tplbm_net_predict(tplbm_net *n, int32_t ncols, const tplbm_net_column *cols, double *rho, double *T);
+
+/* One v_mfma_f32_32x32x8_bf16 on host operands: a and b hold 64 lanes x 4
+ * bf16 values each (lane-major), d receives 64 lanes x 16 FP32 results.  For
+ * checking the matrix-core lane layout the kernels assume. */
+int tplbm_net_mfma_check(tplbm_net *n, const uint16_t *a, const uint16_t *b, float *d);
+
+void tplbm_net_destroy(tplbm_net *n);
+const char *tplbm_net_last_error(const tplbm_net *n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -157,3 +157,13 @@ def init_params(seed: int) -> np.ndarray:
         k += n
         parts.append(np.zeros(int(np.prod(bsh))))
     return np.concatenate(parts)
+
+
+def adam_step(theta, grad, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam step (Kingma and Ba, 2015) with bias-corrected moments; t is
+    the 1-based step number.  Returns the new (theta, m, v)."""
+    m = b1 * m + (1.0 - b1) * grad
+    v = b2 * v + (1.0 - b2) * grad * grad
+    mh = m / (1.0 - b1 ** t)
+    vh = v / (1.0 - b2 ** t)
+    return theta - lr * mh / (np.sqrt(vh) + eps), m, v

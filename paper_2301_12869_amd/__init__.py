@@ -342,3 +342,169 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ---- learned warm start ------------------------------------------------------
+
+class NetColumn(ctypes.Structure):
+    _fields_ = [("height", ctypes.c_int32), ("gravity_form", ctypes.c_int32),
+                ("t_reduced", ctypes.c_double), ("g", ctypes.c_double),
+                ("mean_reduced", ctypes.c_double)]
+
+
+class NetConfig(ctypes.Structure):
+    _fields_ = [("rho_c", ctypes.c_double), ("T_c", ctypes.c_double),
+                ("max_cols", ctypes.c_int32), ("dataset_cols", ctypes.c_int32),
+                ("max_nodes", ctypes.c_int64), ("dataset_nodes", ctypes.c_int64)]
+
+
+_NCP = ctypes.POINTER(NetColumn)
+_FP = ctypes.POINTER(ctypes.c_float)
+_IP = ctypes.POINTER(ctypes.c_int32)
+_U16P = ctypes.POINTER(ctypes.c_uint16)
+SIGNATURES.update({
+    "tplbm_net_num_params": ([ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "tplbm_net_workspace_bytes": ([ctypes.POINTER(NetConfig), _SZ], ctypes.c_int),
+    "tplbm_net_create": ([ctypes.POINTER(NetConfig), _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)],
+                         ctypes.c_int),
+    "tplbm_net_set_params": ([_VP, _FP], ctypes.c_int),
+    "tplbm_net_get_params": ([_VP, _FP], ctypes.c_int),
+    "tplbm_net_set_dataset": ([_VP, ctypes.c_int32, _NCP, _DP, _DP], ctypes.c_int),
+    "tplbm_net_loss_grad": ([_VP, ctypes.c_int32, _IP, _DP, _FP], ctypes.c_int),
+    "tplbm_net_train_step": ([_VP, ctypes.c_int32, _IP, ctypes.c_float, _DP], ctypes.c_int),
+    "tplbm_net_forward": ([_VP, ctypes.c_int32, _NCP, _FP], ctypes.c_int),
+    "tplbm_net_predict": ([_VP, ctypes.c_int32, _NCP, _DP, _DP], ctypes.c_int),
+    "tplbm_net_mfma_check": ([_VP, _U16P, _U16P, _FP], ctypes.c_int),
+    "tplbm_net_destroy": ([_VP], None),
+    "tplbm_net_last_error": ([_VP], ctypes.c_char_p),
+})
+
+
+def _ncheck(rc: int, h=None):
+    if rc != OK:
+        raise TplbmError(rc, load_library().tplbm_net_last_error(h).decode())
+
+
+def _fp(a):
+    return a.ctypes.data_as(_FP)
+
+
+def net_columns(columns):
+    """ctypes array of network column descriptions from (height, form,
+    t_reduced, g, mean_reduced) tuples."""
+    arr = (NetColumn * len(columns))()
+    for k, (h, form, t, g, m) in enumerate(columns):
+        arr[k].height, arr[k].gravity_form = int(h), int(form)
+        arr[k].t_reduced, arr[k].g, arr[k].mean_reduced = float(t), float(g), float(m)
+    return arr
+
+
+def net_num_params() -> int:
+    n = ctypes.c_int64()
+    _ncheck(load_library().tplbm_net_num_params(ctypes.byref(n)))
+    return int(n.value)
+
+
+class Net:
+    """The warm-start network on one GPU: parameters, Adam state, an optional
+    device-resident training set and the buffers of one call of up to
+    max_cols columns / max_nodes nodes."""
+
+    def __init__(self, rho_c, T_c, max_cols, max_nodes, dataset_cols=0, dataset_nodes=0,
+                 device=None, stream=None):
+        import torch
+
+        lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the network kernels need an MI355X")
+        c = NetConfig()
+        c.rho_c, c.T_c = float(rho_c), float(T_c)
+        c.max_cols, c.dataset_cols = int(max_cols), int(dataset_cols)
+        c.max_nodes, c.dataset_nodes = int(max_nodes), int(dataset_nodes)
+        self.config = c
+        self.n_params = net_num_params()
+        nb = ctypes.c_size_t()
+        _ncheck(lib.tplbm_net_workspace_bytes(ctypes.byref(c), ctypes.byref(nb)))
+        self.device = torch.device(device or "cuda")
+        self.workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        h = _VP()
+        _ncheck(lib.tplbm_net_create(ctypes.byref(c), self.workspace.data_ptr(), int(nb.value),
+                                     self.stream.cuda_stream, ctypes.byref(h)))
+        self._h = h
+        self.data_heights = None
+
+    def set_params(self, theta):
+        t = np.ascontiguousarray(theta, dtype=np.float32)
+        if t.size != self.n_params:
+            raise ValueError(f"need {self.n_params} parameters")
+        _ncheck(load_library().tplbm_net_set_params(self._h, _fp(t)), self._h)
+
+    def get_params(self) -> np.ndarray:
+        t = np.empty(self.n_params, dtype=np.float32)
+        _ncheck(load_library().tplbm_net_get_params(self._h, _fp(t)), self._h)
+        return t
+
+    def set_dataset(self, columns, rho_concat, T_concat):
+        cols = net_columns(columns)
+        r = np.ascontiguousarray(rho_concat, dtype=np.float64)
+        t = np.ascontiguousarray(T_concat, dtype=np.float64)
+        n = sum(int(c[0]) for c in columns)
+        if r.size != n or t.size != n:
+            raise ValueError("concatenated profiles must hold sum(heights) values")
+        _ncheck(load_library().tplbm_net_set_dataset(self._h, len(columns), cols, _dp(r), _dp(t)),
+                self._h)
+        self.data_heights = np.array([int(c[0]) for c in columns])
+
+    def loss_grad(self, idx):
+        i = np.ascontiguousarray(idx, dtype=np.int32)
+        loss = ctypes.c_double()
+        g = np.empty(self.n_params, dtype=np.float32)
+        _ncheck(load_library().tplbm_net_loss_grad(self._h, i.size, i.ctypes.data_as(_IP),
+                                                   ctypes.byref(loss), _fp(g)), self._h)
+        return float(loss.value), g
+
+    def train_step(self, idx, lr: float, want_loss: bool = True):
+        i = np.ascontiguousarray(idx, dtype=np.int32)
+        loss = ctypes.c_double()
+        _ncheck(load_library().tplbm_net_train_step(self._h, i.size, i.ctypes.data_as(_IP),
+                                                    float(lr),
+                                                    ctypes.byref(loss) if want_loss else None),
+                self._h)
+        return float(loss.value) if want_loss else None
+
+    def forward(self, columns) -> np.ndarray:
+        cols = net_columns(columns)
+        n = sum(int(c[0]) for c in columns)
+        out = np.empty(2 * n, dtype=np.float32)
+        _ncheck(load_library().tplbm_net_forward(self._h, len(columns), cols, _fp(out)), self._h)
+        return out.reshape(n, 2)
+
+    def predict(self, columns):
+        cols = net_columns(columns)
+        n = sum(int(c[0]) for c in columns)
+        rho, T = np.empty(n), np.empty(n)
+        _ncheck(load_library().tplbm_net_predict(self._h, len(columns), cols, _dp(rho), _dp(T)),
+                self._h)
+        return rho, T
+
+    def mfma_check(self, a, b) -> np.ndarray:
+        a = np.ascontiguousarray(a, dtype=np.uint16)
+        b = np.ascontiguousarray(b, dtype=np.uint16)
+        if a.size != 256 or b.size != 256:
+            raise ValueError("a and b hold 64 lanes x 4 bf16 values")
+        d = np.empty(1024, dtype=np.float32)
+        _ncheck(load_library().tplbm_net_mfma_check(self._h, a.ctypes.data_as(_U16P),
+                                                    b.ctypes.data_as(_U16P), _fp(d)), self._h)
+        return d.reshape(64, 16)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().tplbm_net_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

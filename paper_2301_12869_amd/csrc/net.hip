@@ -1,0 +1,501 @@
+// Warm-start network kernels for gfx950: 1-D convolutions as implicit GEMMs
+// on the BF16 matrix cores (v_mfma_f32_32x32x8_bf16, FP32 accumulation).
+//
+// A batch of columns is laid out position-major, channels fastest, with two
+// all-zero guard positions between columns (and at both ends): a width-5
+// convolution then never mixes columns, and its zero padding is exact
+// without per-tap masks.  Outputs and gradients at guard positions are
+// forced to zero, so every kernel writes every position it owns.
+//
+// Kernels:
+//   conv_mfma   out[p][o] = sum_{t,i} W[o][t][i] in[p + t - 2][i]  (+ bias
+//               and ReLU, or a mask by the layer input) -- forward layers
+//               and, with flipped transposed weights, the input gradient
+//   dw_mfma     partial dW[o][t][i] = sum_p dZ[p][o] X[p + t - 2][i] over a
+//               slice of positions (operands staged transposed in LDS),
+//               reduced in a fixed order afterwards (deterministic)
+//   prep / emit / loss / adam / weight conversion in FP32 or FP64.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "net_internal.hpp"
+
+namespace tplbm {
+
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest, ties to even
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// Accumulator element r of a lane holds D[row][col] of the 32 x 32 tile with
+// col = lane % 32 and row = 8 (r / 4) + 4 (lane / 32) + r % 4.
+__device__ __forceinline__ int acc_row(int r, int lane) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
+
+// MODE 0: hidden forward layer: out_bf16 = bf16(relu(acc + bias))
+// MODE 1: output layer:         out_f32[p][o] = acc + bias for o < NOUT
+// MODE 2: input gradient:       g = acc * (mask[p][o] > 0); out_f32 = g, out_bf16 = bf16(g)
+// A wave owns 32 positions and all 32 NTILES output channels.
+template <int CIN, int NTILES, int MODE, int NOUT>
+__global__ __launch_bounds__(256) void conv_mfma(const uint16_t *__restrict__ in, const uint16_t *__restrict__ W,
+                                                 const float *__restrict__ bias, int P,
+                                                 const uint8_t *__restrict__ guard,
+                                                 const uint16_t *__restrict__ mask, float *__restrict__ out_f32,
+                                                 uint16_t *__restrict__ out_bf16)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int p0 = (blockIdx.x * 4 + wave) * 32;
+    if (p0 >= P) return;
+    const int i = lane & 31, kq = lane >> 5;
+    f32x16 acc[NTILES];
+#pragma unroll
+    for (int nt = 0; nt < NTILES; ++nt)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[nt][r] = 0.0f;
+#pragma unroll
+    for (int t = 0; t < 5; ++t) {
+        int q = p0 + i + t - 2;
+        q = q < 0 ? 0 : (q >= P ? P - 1 : q);  // both ends are guard positions (zero)
+#pragma unroll
+        for (int c0 = 0; c0 < CIN; c0 += 8) {
+            const bf16x4 a = *reinterpret_cast<const bf16x4 *>(in + (size_t)q * CIN + c0 + 4 * kq);
+#pragma unroll
+            for (int nt = 0; nt < NTILES; ++nt) {
+                const int o = 32 * nt + i;
+                const bf16x4 b = *reinterpret_cast<const bf16x4 *>(W + ((size_t)o * 5 + t) * CIN + c0 + 4 * kq);
+                acc[nt] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc[nt], 0, 0, 0);
+            }
+        }
+    }
+    constexpr int COUT = 32 * NTILES;
+#pragma unroll
+    for (int nt = 0; nt < NTILES; ++nt) {
+        const int o = 32 * nt + i;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int p = p0 + acc_row(r, lane);
+            if (p >= P) continue;
+            const bool g = guard[p] != 0;
+            float v = acc[nt][r];
+            if (MODE == 0) {
+                v = g ? 0.0f : fmaxf(v + bias[o], 0.0f);
+                out_bf16[(size_t)p * COUT + o] = f2bf(v);
+            } else if (MODE == 1) {
+                if (o < NOUT) out_f32[(size_t)p * NOUT + o] = g ? 0.0f : v + bias[o];
+            } else {
+                v = (g || !(bf2f(mask[(size_t)p * COUT + o]) > 0.0f)) ? 0.0f : v;
+                out_f32[(size_t)p * COUT + o] = v;
+                out_bf16[(size_t)p * COUT + o] = f2bf(v);
+            }
+        }
+    }
+}
+
+// Partial weight gradient over positions [blockIdx.x * span, ...):
+// dW[o][t][i] = sum_p dZ[p][o] X[p + t - 2][i], a GEMM with M = COUT (o),
+// N = 5 CIN (t, i) and K = positions.  dZ has ZS channels per position
+// (rows o >= ZS are zero).  Each 64-position chunk of dZ and of X (with a
+// 2-position halo on each side) is staged transposed in LDS, so a lane's
+// four consecutive positions are adjacent.
+template <int CIN, int COUT, int ZS>
+__global__ __launch_bounds__(256) void dw_mfma(const uint16_t *__restrict__ dZ, const uint16_t *__restrict__ X,
+                                               int P, int span, float *__restrict__ partial)
+{
+    constexpr int CH = 64;
+    constexpr int MT = COUT / 32;
+    constexpr int NN = 5 * CIN;
+    constexpr int NT = (NN + 31) / 32;
+    constexpr int TILES = MT * NT;
+    constexpr int TPW = (TILES + 3) / 4;
+    __shared__ uint16_t sZ[COUT][CH + 4];
+    __shared__ uint16_t sX[CIN][CH + 8];  // positions p0 - 2 .. p0 + CH + 1
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = lane & 31, kq = lane >> 5;
+    f32x16 acc[TPW];
+#pragma unroll
+    for (int k = 0; k < TPW; ++k)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[k][r] = 0.0f;
+
+    const int pbeg = blockIdx.x * span, pend = min(P, pbeg + span);
+    for (int p0 = pbeg; p0 < pend; p0 += CH) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < COUT * CH; e += 256) {
+            const int o = e % COUT, pp = e / COUT;
+            const int p = p0 + pp;
+            sZ[o][pp] = (o < ZS && p < pend) ? dZ[(size_t)p * ZS + o] : (uint16_t)0;
+        }
+        for (int e = threadIdx.x; e < CIN * (CH + 4); e += 256) {
+            const int c = e % CIN, pp = e / CIN;
+            int p = p0 - 2 + pp;
+            p = p < 0 ? 0 : (p >= P ? P - 1 : p);
+            sX[c][pp] = X[(size_t)p * CIN + c];
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int k8 = 0; k8 < CH; k8 += 8) {
+            const int pk = k8 + 4 * kq;
+#pragma unroll
+            for (int k = 0; k < TPW; ++k) {
+                const int tile = wave + 4 * k;
+                if (tile >= TILES) break;
+                const int mt = tile % MT, nt = tile / MT;
+                const int o = 32 * mt + i;
+                bf16x4 a;
+                a[0] = (short)sZ[o][pk];
+                a[1] = (short)sZ[o][pk + 1];
+                a[2] = (short)sZ[o][pk + 2];
+                a[3] = (short)sZ[o][pk + 3];
+                const int n = 32 * nt + i;
+                bf16x4 b;
+                if (n < NN) {
+                    const int t = n / CIN, c = n % CIN;
+                    // X[p + t - 2] for p = p0 + pk + j  ->  sX index pk + j + t
+                    b[0] = (short)sX[c][pk + t];
+                    b[1] = (short)sX[c][pk + t + 1];
+                    b[2] = (short)sX[c][pk + t + 2];
+                    b[3] = (short)sX[c][pk + t + 3];
+                } else {
+                    b[0] = b[1] = b[2] = b[3] = 0;
+                }
+                acc[k] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc[k], 0, 0, 0);
+            }
+        }
+    }
+    float *dst = partial + (size_t)blockIdx.x * COUT * NN;
+#pragma unroll
+    for (int k = 0; k < TPW; ++k) {
+        const int tile = wave + 4 * k;
+        if (tile >= TILES) break;
+        const int mt = tile % MT, nt = tile / MT;
+        const int n = 32 * nt + i;
+        if (n >= NN) continue;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int o = 32 * mt + acc_row(r, lane);
+            dst[(size_t)o * NN + n] = acc[k][r];
+        }
+    }
+}
+
+// dst[e] = sum_b src[b][e] over b in increasing order (deterministic)
+__global__ void reduce_partials(const float *__restrict__ src, int nb, int stride, int n, float *__restrict__ dst)
+{
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        float s = 0.0f;
+        for (int b = 0; b < nb; ++b) s += src[(size_t)b * stride + e];
+        dst[e] = s;
+    }
+}
+
+// bias-gradient partials: per-channel sums of dZ over position slices
+__global__ void db_partial(const float *__restrict__ dZ, int ZS, int P, int span, float *__restrict__ partial)
+{
+    const int o = threadIdx.x;
+    if (o >= ZS) return;
+    float s = 0.0f;
+    const int pbeg = blockIdx.x * span, pend = min(P, pbeg + span);
+    for (int p = pbeg; p < pend; ++p) s += dZ[(size_t)p * ZS + o];
+    partial[(size_t)blockIdx.x * ZS + o] = s;
+}
+
+// squared-error partials and the output-layer gradient dZ (8 channels per
+// position, the last six zero)
+__global__ __launch_bounds__(256) void loss_grad(const float *__restrict__ out, const float *__restrict__ tgt,
+                                                 const uint8_t *__restrict__ guard, int P, float scale,
+                                                 float *__restrict__ dZf, uint16_t *__restrict__ dZb,
+                                                 float *__restrict__ partial)
+{
+    __shared__ float red[256];
+    float s = 0.0f;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
+        float g0 = 0.0f, g1 = 0.0f;
+        if (!guard[p]) {
+            const float r0 = out[2 * (size_t)p] - tgt[2 * (size_t)p];
+            const float r1 = out[2 * (size_t)p + 1] - tgt[2 * (size_t)p + 1];
+            s += r0 * r0 + r1 * r1;
+            g0 = 2.0f * r0 * scale;
+            g1 = 2.0f * r1 * scale;
+        }
+        dZf[8 * (size_t)p] = g0;
+        dZf[8 * (size_t)p + 1] = g1;
+        dZb[8 * (size_t)p] = f2bf(g0);
+        dZb[8 * (size_t)p + 1] = f2bf(g1);
+#pragma unroll
+        for (int c = 2; c < 8; ++c) {
+            dZf[8 * (size_t)p + c] = 0.0f;
+            dZb[8 * (size_t)p + c] = 0;
+        }
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// Adam on the FP32 master parameters (c1, c2: bias corrections)
+__global__ void adam(float *__restrict__ theta, const float *__restrict__ grad, float *__restrict__ m,
+                     float *__restrict__ v, int n, float lr, float b1, float b2, float eps, float c1, float c2)
+{
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        const float g = grad[e];
+        const float mm = b1 * m[e] + (1.0f - b1) * g;
+        const float vv = b2 * v[e] + (1.0f - b2) * g * g;
+        m[e] = mm;
+        v[e] = vv;
+        theta[e] -= lr * (mm * c1) / (sqrtf(vv * c2) + eps);
+    }
+}
+
+// BF16 copies of one layer's weights: forward Wb[o][t][i] with rows padded
+// to cout_pad, and input-gradient weights Wg[i][t][o] = W[o][4 - t][i] with
+// o padded to cin_g.
+__global__ void prep_weights(const float *__restrict__ Wf, int cout, int cin, int cout_pad, int cin_g,
+                             uint16_t *__restrict__ Wb, uint16_t *__restrict__ Wg)
+{
+    const int nf = cout_pad * 5 * cin;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nf; e += gridDim.x * blockDim.x) {
+        const int o = e / (5 * cin), rem = e % (5 * cin);
+        Wb[e] = o < cout ? f2bf(Wf[(size_t)o * 5 * cin + rem]) : (uint16_t)0;
+    }
+    if (!Wg) return;
+    const int ng = cin * 5 * cin_g;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < ng; e += gridDim.x * blockDim.x) {
+        const int i = e / (5 * cin_g), rem = e % (5 * cin_g);
+        const int t = rem / cin_g, o = rem % cin_g;
+        Wg[e] = o < cout ? f2bf(Wf[((size_t)o * 5 + (4 - t)) * cin + i]) : (uint16_t)0;
+    }
+}
+
+// Input features (8 channels, bf16) of one column per block, its trailing
+// guard positions (block 0 also the two leading ones) and, with a dataset,
+// the targets (rho/rho_c - <rho>/rho_c, T/T_c - T_wall/T_c).
+__global__ __launch_bounds__(256) void prep(const NetCol *__restrict__ cols, const NetEntry *__restrict__ ent,
+                                            const double *__restrict__ rho, const double *__restrict__ T,
+                                            double rho_c, double T_c, uint16_t *__restrict__ x,
+                                            uint8_t *__restrict__ guard, float *__restrict__ tgt)
+{
+    const NetEntry e = ent[blockIdx.x];
+    const NetCol c = cols[e.src];
+    const int H = c.height;
+    const uint32_t k1 = f2bf((float)(c.t_reduced - 0.8));
+    const uint32_t k2 = f2bf((float)(log10(c.g) + 5.0));
+    const uint32_t k3 = f2bf((float)((double)c.form - 1.5));
+    const uint32_t k4 = f2bf((float)(c.mean_reduced - 1.3));
+    const uint32_t k5 = f2bf((float)((double)H / 2048.0 - 0.5));
+    for (int y = threadIdx.x; y < H; y += blockDim.x) {
+        const int64_t p = e.pos + y;
+        const uint32_t k0 = f2bf((float)(((double)y + 0.5) / (double)H - 0.5));
+        *reinterpret_cast<uint4 *>(x + 8 * p) = make_uint4(k0 | (k1 << 16), k2 | (k3 << 16), k4 | (k5 << 16), 0u);
+        guard[p] = 0;
+        if (tgt) {
+            tgt[2 * p] = (float)(rho[c.offset + y] / rho_c - c.mean_reduced);
+            tgt[2 * p + 1] = (float)(T[c.offset + y] / T_c - c.t_reduced);
+        }
+    }
+    // trailing guards pos + H, pos + H + 1; block 0 also the leading pos - 2, pos - 1
+    const int j = threadIdx.x;
+    if (j < 2 || (j < 4 && blockIdx.x == 0)) {
+        const int64_t p = j < 2 ? e.pos + H + j : e.pos - 4 + j;
+        *reinterpret_cast<uint4 *>(x + 8 * p) = make_uint4(0u, 0u, 0u, 0u);
+        guard[p] = 1;
+        if (tgt) tgt[2 * p] = tgt[2 * p + 1] = 0.0f;
+    }
+}
+
+// Warm-start profiles of one column per block: rho = rho_c (out_0 + <rho>/rho_c)
+// shifted so that its mean is <rho>, T = T_c (T_wall/T_c + out_1) with the two
+// wall nodes at T_wall.  FP64.
+__global__ __launch_bounds__(256) void emit(const NetCol *__restrict__ cols, const NetEntry *__restrict__ ent,
+                                            const float *__restrict__ out, double rho_c, double T_c,
+                                            double *__restrict__ rho_out, double *__restrict__ T_out)
+{
+    __shared__ double red[256];
+    const NetEntry e = ent[blockIdx.x];
+    const NetCol c = cols[e.src];
+    const int H = c.height;
+    double s = 0.0;
+    for (int y = threadIdx.x; y < H; y += blockDim.x)
+        s += rho_c * ((double)out[2 * (e.pos + y)] + c.mean_reduced);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    const double shift = rho_c * c.mean_reduced - red[0] / (double)H;
+    const double Tw = T_c * c.t_reduced;
+    for (int y = threadIdx.x; y < H; y += blockDim.x) {
+        const int64_t p = e.pos + y;
+        rho_out[e.out + y] = rho_c * ((double)out[2 * p] + c.mean_reduced) + shift;
+        T_out[e.out + y] = (y == 0 || y == H - 1) ? Tw : T_c * (c.t_reduced + (double)out[2 * p + 1]);
+    }
+}
+
+// raw network outputs of each column, concatenated without guards
+__global__ void raw_out(const NetCol *__restrict__ cols, const NetEntry *__restrict__ ent,
+                        const float *__restrict__ out, float *__restrict__ dst)
+{
+    const NetEntry e = ent[blockIdx.x];
+    const int H = cols[e.src].height;
+    for (int y = threadIdx.x; y < 2 * H; y += blockDim.x) dst[2 * e.out + y] = out[2 * e.pos + y];
+}
+
+// one MFMA on caller-provided operands (lane layout check)
+__global__ void mfma_probe(const uint16_t *__restrict__ a, const uint16_t *__restrict__ b, float *__restrict__ d)
+{
+    const int lane = threadIdx.x;
+    bf16x4 av, bv;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        av[k] = (short)a[lane * 4 + k];
+        bv[k] = (short)b[lane * 4 + k];
+    }
+    f32x16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bv, acc, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) d[lane * 16 + r] = acc[r];
+}
+
+unsigned conv_blocks(int64_t P) { return (unsigned)((P + 127) / 128); }
+
+// slice length (a multiple of 64 positions) and slice count for nblocks
+void slices(int64_t P, int nblocks, int *span, int *nb)
+{
+    int64_t s = (P + nblocks - 1) / nblocks;
+    s = (s + 63) / 64 * 64;
+    *span = (int)s;
+    *nb = (int)((P + s - 1) / s);
+}
+
+}  // namespace
+
+hipError_t net_prep(const NetCol *cols, const NetEntry *entries, int n, const double *rho, const double *T,
+                    double rho_c, double T_c, uint16_t *x, uint8_t *guard, float *tgt, hipStream_t s)
+{
+    hipLaunchKernelGGL(prep, dim3(n), dim3(256), 0, s, cols, entries, rho, T, rho_c, T_c, x, guard, tgt);
+    return hipGetLastError();
+}
+
+hipError_t net_emit(const NetCol *cols, const NetEntry *entries, int n, const float *out, double rho_c,
+                    double T_c, double *rho_out, double *T_out, hipStream_t s)
+{
+    hipLaunchKernelGGL(emit, dim3(n), dim3(256), 0, s, cols, entries, out, rho_c, T_c, rho_out, T_out);
+    return hipGetLastError();
+}
+
+hipError_t net_raw_out(const NetCol *cols, const NetEntry *entries, int n, const float *out, float *dst,
+                       hipStream_t s)
+{
+    hipLaunchKernelGGL(raw_out, dim3(n), dim3(256), 0, s, cols, entries, out, dst);
+    return hipGetLastError();
+}
+
+hipError_t net_conv_forward(int layer, const uint16_t *in, const uint16_t *W, const float *bias, int64_t P,
+                            const uint8_t *guard, uint16_t *out_bf16, float *out_f32, hipStream_t s)
+{
+    const dim3 g(conv_blocks(P)), b(256);
+    const int p = (int)P;
+    if (layer == 0)
+        hipLaunchKernelGGL((conv_mfma<8, 2, 0, 64>), g, b, 0, s, in, W, bias, p, guard, nullptr, nullptr, out_bf16);
+    else if (layer < 5)
+        hipLaunchKernelGGL((conv_mfma<64, 2, 0, 64>), g, b, 0, s, in, W, bias, p, guard, nullptr, nullptr, out_bf16);
+    else
+        hipLaunchKernelGGL((conv_mfma<64, 1, 1, 2>), g, b, 0, s, in, W, bias, p, guard, nullptr, out_f32, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t net_conv_input_grad(int layer, const uint16_t *dZ, const uint16_t *Wg, int64_t P, const uint8_t *guard,
+                               const uint16_t *act_in, float *dprev_f32, uint16_t *dprev_bf16, hipStream_t s)
+{
+    const dim3 g(conv_blocks(P)), b(256);
+    const int p = (int)P;
+    if (layer == 5)
+        hipLaunchKernelGGL((conv_mfma<8, 2, 2, 64>), g, b, 0, s, dZ, Wg, nullptr, p, guard, act_in, dprev_f32,
+                           dprev_bf16);
+    else
+        hipLaunchKernelGGL((conv_mfma<64, 2, 2, 64>), g, b, 0, s, dZ, Wg, nullptr, p, guard, act_in, dprev_f32,
+                           dprev_bf16);
+    return hipGetLastError();
+}
+
+hipError_t net_weight_grad(int layer, const uint16_t *dZ, const uint16_t *X, int64_t P, int nblocks,
+                           float *partial, float *dW, hipStream_t s)
+{
+    int span, nb;
+    slices(P, nblocks, &span, &nb);
+    const int p = (int)P;
+    int stride;
+    if (layer == 0) {
+        stride = 64 * 5 * 8;
+        hipLaunchKernelGGL((dw_mfma<8, 64, 64>), dim3(nb), dim3(256), 0, s, dZ, X, p, span, partial);
+    } else if (layer < 5) {
+        stride = 64 * 5 * 64;
+        hipLaunchKernelGGL((dw_mfma<64, 64, 64>), dim3(nb), dim3(256), 0, s, dZ, X, p, span, partial);
+    } else {
+        stride = 32 * 5 * 64;  // rows 2..31 are zero padding
+        hipLaunchKernelGGL((dw_mfma<64, 32, 8>), dim3(nb), dim3(256), 0, s, dZ, X, p, span, partial);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int n = kNetCout[layer] * 5 * kNetCin[layer];
+    hipLaunchKernelGGL(reduce_partials, dim3((n + 255) / 256), dim3(256), 0, s, partial, nb, stride, n, dW);
+    return hipGetLastError();
+}
+
+hipError_t net_bias_grad(int layer, const float *dZ, int64_t P, int nblocks, float *partial, float *db,
+                         hipStream_t s)
+{
+    int span, nb;
+    slices(P, nblocks, &span, &nb);
+    const int zs = layer == 5 ? 8 : 64;
+    hipLaunchKernelGGL(db_partial, dim3(nb), dim3(64), 0, s, dZ, zs, (int)P, span, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(64), 0, s, partial, nb, zs, kNetCout[layer], db);
+    return hipGetLastError();
+}
+
+hipError_t net_loss(const float *out, const float *tgt, const uint8_t *guard, int64_t P, float scale, float *dZf,
+                    uint16_t *dZb, float *partial, int nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(loss_grad, dim3(nblocks), dim3(256), 0, s, out, tgt, guard, (int)P, scale, dZf, dZb,
+                       partial);
+    return hipGetLastError();
+}
+
+hipError_t net_adam(float *theta, const float *grad, float *m, float *v, int n, float lr, float b1, float b2,
+                    float eps, float c1, float c2, hipStream_t s)
+{
+    hipLaunchKernelGGL(adam, dim3((n + 255) / 256), dim3(256), 0, s, theta, grad, m, v, n, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t net_prep_weights(const float *Wf, int layer, uint16_t *Wb, uint16_t *Wg, hipStream_t s)
+{
+    hipLaunchKernelGGL(prep_weights, dim3(80), dim3(256), 0, s, Wf, kNetCout[layer], kNetCin[layer],
+                       kNetCoutPad[layer], kNetGradCin[layer], Wb, Wg);
+    return hipGetLastError();
+}
+
+hipError_t net_mfma_probe(const uint16_t *a, const uint16_t *b, float *d, hipStream_t s)
+{
+    hipLaunchKernelGGL(mfma_probe, dim3(1), dim3(64), 0, s, a, b, d);
+    return hipGetLastError();
+}
+
+}  // namespace tplbm

@@ -70,3 +70,26 @@ def test_invalid_parameters_are_rejected_on_the_host(lib):
         rc = lib.tplbm_workspace_bytes(ctypes.byref(p), ctypes.byref(nb))
         assert rc in (T.EINVAL, T.ESHAPE), (over, rc)
         assert lib.tplbm_last_error(None)
+
+
+def test_network_parameter_count_and_workspace_on_the_host(lib):
+    """The network's parameter vector has the layout of the reference network
+    (same count), and the workspace query checks its configuration."""
+    import ctypes
+
+    from oracle import net_ref
+
+    assert T.net_num_params() == net_ref.n_params() == 85442
+    c = T.NetConfig(rho_c=0.13, T_c=0.047, max_cols=16, dataset_cols=100, max_nodes=4096,
+                    dataset_nodes=100000)
+    nb = ctypes.c_size_t()
+    assert lib.tplbm_net_workspace_bytes(ctypes.byref(c), ctypes.byref(nb)) == T.OK
+    # at least the activations (5 x 64 bf16 per position) and the training set
+    assert nb.value > 5 * 128 * 4096 + 16 * 100000
+    for field, bad in (("rho_c", 0.0), ("max_cols", 0), ("max_nodes", 2), ("max_nodes", 1 << 26),
+                       ("dataset_cols", -1)):
+        c2 = T.NetConfig.from_buffer_copy(c)
+        setattr(c2, field, bad)
+        rc = lib.tplbm_net_workspace_bytes(ctypes.byref(c2), ctypes.byref(nb))
+        assert rc in (T.EINVAL, T.ESHAPE), (field, rc)
+        assert lib.tplbm_net_last_error(None)

@@ -55,3 +55,14 @@ def test_bf16_rounding():
     r = N.bf16(v)
     assert r[0] == 1.0 and r[1] == 1.0 and r[2] == 1.0 + 2 ** -6
     assert abs(r[3] - np.pi) < 2 ** -7 * 4 and abs(r[4] + 2.5e-3) < 2.5e-3 * 2 ** -8
+
+
+def test_adam_with_a_constant_gradient_moves_by_lr_every_step():
+    """With a constant gradient the bias-corrected moments equal g and g^2 at
+    every step, so each step moves a parameter by lr g / (|g| + eps)."""
+    g = np.array([3.0, -0.25, 1e-3, 0.0])
+    theta, m, v = np.zeros(4), np.zeros(4), np.zeros(4)
+    lr = 1e-2
+    for t in range(1, 6):
+        theta, m, v = N.adam_step(theta, g, m, v, t, lr)
+        np.testing.assert_allclose(theta, -t * lr * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0)
