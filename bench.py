@@ -205,6 +205,63 @@ def run_plain(T, cols, rho, Tt, check_every):
     return dict(seconds=time.perf_counter() - t0, converged=conv, node_steps=node_steps)
 
 
+WS_EVAL_COLS, WS_EVAL_SEED, WS_EVAL_STEPS = 1024, 2002, 2_000_000
+NET_FLOPS_PER_POSITION = 2 * 5 * (8 * 64 + 4 * 64 * 64 + 64 * 2) * 2 + 2 * 5 * (4 * 64 * 64 + 64 * 2)
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def run_warmstart(T, torch):
+    """Held-out columns (1024, drawn as the sweep) from the plain start and
+    from the trained network's profiles, each run to max |u| < 1e-9 or the
+    step budget; plus the network's training throughput on the matrix cores."""
+    from paper_2301_12869_amd import warmstart as WS
+
+    if not os.path.exists(WS.PARAMS_PATH):
+        return {"skipped": f"no trained parameters at {os.path.relpath(WS.PARAMS_PATH, ROOT)}"}
+    cols = WS.Columns(WS_EVAL_COLS, WS_EVAL_SEED)
+    net = T.Net(cols.rho_c, cols.T_c, max_cols=WS_EVAL_COLS, max_nodes=int(cols.height.sum()))
+    net.set_params(np.load(WS.PARAMS_PATH))
+    res = WS.evaluate(net, cols, BATCH_TOL, WS_EVAL_STEPS,
+                      log=lambda m: print("# " + m, file=sys.stderr, flush=True))
+    summary = WS.summarize(cols, res)
+    summary["predict_seconds"] = round(res["predict_seconds"], 4)
+    net.close()
+
+    # training throughput: minibatches of 32 columns of 1024 nodes (smooth
+    # synthetic targets), Adam steps timed with HIP events on the net's stream
+    H, nc = 1024, 32
+    tcols = [(H, 1 + k % 2, 0.7 + 0.2 * k / nc, 10 ** (-6 + 2 * k / nc), 0.5 + 2 * k / nc) for k in range(nc)]
+    s = (np.arange(H) + 0.5) / H
+    rho = np.concatenate([cols.rho_c * (c[4] + 0.5 * np.tanh((0.5 - s) * 30)) for c in tcols])
+    Tt = np.concatenate([np.full(H, cols.T_c * c[2]) for c in tcols])
+    net = T.Net(cols.rho_c, cols.T_c, max_cols=nc, max_nodes=nc * H, dataset_cols=nc,
+                dataset_nodes=nc * H)
+    net.set_params(WS.init_params(3))
+    net.set_dataset(tcols, rho, Tt)
+    idx = np.arange(nc)
+    for _ in range(5):
+        net.train_step(idx, 1e-4, want_loss=False)
+    n_steps = 50
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(net.stream)
+    for _ in range(n_steps):
+        net.train_step(idx, 1e-4, want_loss=False)
+    ev1.record(net.stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / n_steps
+    net.close()
+    tflops = NET_FLOPS_PER_POSITION * nc * H / (ms * 1e-3) / 1e12
+    summary["train_step"] = {
+        "positions": nc * H, "ms": round(ms, 4),
+        "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": MFMA_BF16_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(tflops / MFMA_BF16_PEAK_TFLOPS, 4),
+                     "flops_per_position": NET_FLOPS_PER_POSITION}}
+    print(f"# net train step: {ms:.3f} ms for {nc * H} positions, {tflops:.1f} TFLOP/s", file=sys.stderr,
+          flush=True)
+    return summary
+
+
 def cpu_baseline(rho0, T0, T_c, budget_s=20.0):
     """The FP64 oracle (single thread, plain loops) on a bounded sample: the
     same lattice and inputs, as many whole steps as fit in about budget_s."""
@@ -231,7 +288,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--variants", default="all", help="all | headline | fp32dev | d3q19")
+    ap.add_argument("--variants", default="all", help="all | headline | fp32dev | d3q19 | warmstart")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -265,7 +322,7 @@ def main():
     variants = [(0, 2, 1e-5)]
     if args.variants == "fp32dev":
         variants = [(1, 2, 1e-5)]
-    if args.variants == "d3q19":
+    if args.variants in ("d3q19", "warmstart"):
         variants = [(0, 2, 1e-5)]
     if args.variants == "all":
         variants += [(0, 1, 1e-5), (0, 1, 1e-4), (0, 2, 1e-4), (1, 2, 1e-5), (1, 1, 1e-5),
@@ -353,6 +410,8 @@ def main():
                 "steady_states_per_hour": round(pl["converged"] / (pl["seconds"] / 3600.0), 1),
                 "node_steps_per_s": round(pl["node_steps"] / pl["seconds"], 1)},
         }
+    if args.variants in ("all", "warmstart"):
+        line["warm_start"] = run_warmstart(T, torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(rho0, T0, T_c)
     print(json.dumps(line), flush=True)
