@@ -205,7 +205,7 @@ def run_plain(T, cols, rho, Tt, check_every):
     return dict(seconds=time.perf_counter() - t0, converged=conv, node_steps=node_steps)
 
 
-WS_EVAL_COLS, WS_EVAL_SEED, WS_EVAL_STEPS = 1024, 2002, 2_000_000
+WS_EVAL_COLS, WS_EVAL_SEED, WS_EVAL_STEPS = 1024, 2002, 4_000_000
 NET_FLOPS_PER_POSITION = 2 * 5 * (8 * 64 + 4 * 64 * 64 + 64 * 2) * 2 + 2 * 5 * (4 * 64 * 64 + 64 * 2)
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 
@@ -262,6 +262,24 @@ def run_warmstart(T, torch):
     return summary
 
 
+def copy_bandwidth(torch) -> float:
+    """Bytes read + written per second by a plain 1 GiB device-to-device copy
+    (torch's copy kernel), the practical streaming rate of this HBM."""
+    src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / 5
+    del src, dst
+    return round(2 * (1 << 30) / (ms * 1e-3) / 1e9, 1)
+
+
 def cpu_baseline(rho0, T0, T_c, budget_s=20.0):
     """The FP64 oracle (single thread, plain loops) on a bounded sample: the
     same lattice and inputs, as many whole steps as fit in about budget_s."""
@@ -288,7 +306,9 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--variants", default="all", help="all | headline | fp32dev | d3q19 | warmstart")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the plain per-column comparison of the batched sweep")
+    ap.add_argument("--variants", default="all", help="all | headline | fp32dev | d3q19 | batched | warmstart")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -322,7 +342,7 @@ def main():
     variants = [(0, 2, 1e-5)]
     if args.variants == "fp32dev":
         variants = [(1, 2, 1e-5)]
-    if args.variants in ("d3q19", "warmstart"):
+    if args.variants in ("d3q19", "batched", "warmstart"):
         variants = [(0, 2, 1e-5)]
     if args.variants == "all":
         variants += [(0, 1, 1e-5), (0, 1, 1e-4), (0, 2, 1e-4), (1, 2, 1e-5), (1, 1, 1e-5),
@@ -378,7 +398,7 @@ def main():
     }
     if args.variants in ("all", "d3q19"):
         line["d3q19_256cubed"] = run_d3q19(T, torch, min(args.steps, 200), 10)
-    if args.variants == "all":
+    if args.variants in ("all", "batched"):
         cols, rho, Tt = batch_inputs(T)
         bt = run_batched(T, torch, cols, rho, Tt)
         print(f"# batched sweep: {bt['converged']} converged, {bt['diverged']} diverged, "
@@ -389,6 +409,8 @@ def main():
         # cases, so the comparison errs in its favour
         conv_idx = np.nonzero(bt["status"] == 0)[0]
         pick = [int(k) for k in conv_idx[np.argsort(bt["steps"][conv_idx])][:PLAIN_COLUMNS]]
+        if args.no_plain:
+            pick = []
         pl = run_plain(T, [cols[k] for k in pick], [rho[k] for k in pick], [Tt[k] for k in pick],
                        bt["tuning"]["check_every"])
         print(f"# plain per-column: {pl['converged']} of {len(pick)} converged in "
@@ -407,11 +429,13 @@ def main():
             "plain_per_column": {
                 "columns": pick, "converged": pl["converged"],
                 "seconds": round(pl["seconds"], 2),
-                "steady_states_per_hour": round(pl["converged"] / (pl["seconds"] / 3600.0), 1),
-                "node_steps_per_s": round(pl["node_steps"] / pl["seconds"], 1)},
+                "steady_states_per_hour": (round(pl["converged"] / (pl["seconds"] / 3600.0), 1)
+                                           if pick else None),
+                "node_steps_per_s": round(pl["node_steps"] / pl["seconds"], 1) if pick else None},
         }
     if args.variants in ("all", "warmstart"):
         line["warm_start"] = run_warmstart(T, torch)
+    line["hbm_copy_GBs"] = copy_bandwidth(torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(rho0, T0, T_c)
     print(json.dumps(line), flush=True)

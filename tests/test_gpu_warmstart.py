@@ -1,0 +1,76 @@
+"""What the trained network gains over the plain start (GPU).
+
+Held-out columns of the sweep's distribution (not seen in training) are run
+by the batched solver to max |u| < 1e-9 from the plain liquid-below-vapour
+start and from the network's profiles; the solver decides convergence in
+both cases.  The warm start must reach more steady states within the same
+step budget, lose fewer columns to the method's instability, and reach the
+same steady states: same interface count, and density profiles that differ
+only through the wall mass exchange of the transient (the Zou-He walls do
+not conserve mass while the column moves, so two different transients end
+with slightly different masses)."""
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+N_COLS, SEED, STEPS = 1024, 2002, 4_000_000
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def result():
+    import torch
+
+    import paper_2301_12869_amd as T
+    from paper_2301_12869_amd import warmstart as WS
+
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible MI355X")
+    assert os.path.exists(WS.PARAMS_PATH), "trained parameters are missing"
+    cols = WS.Columns(N_COLS, SEED)
+    net = T.Net(cols.rho_c, cols.T_c, max_cols=N_COLS, max_nodes=int(cols.height.sum()))
+    net.set_params(np.load(WS.PARAMS_PATH))
+    _log(f"held-out columns: {N_COLS} (seed {SEED}), budget {STEPS} steps")
+    res = WS.evaluate(net, cols, 1e-9, STEPS, log=_log)
+    net.close()
+    return cols, res, WS.summarize(cols, res)
+
+
+def test_warm_start_reaches_more_steady_states(result):
+    cols, res, s = result
+    _log(f"summary: { {k: s[k] for k in ('cold', 'warm', 'warm_rho')} }")
+    for name in ("warm", "warm_rho"):
+        assert s[name]["converged"] > s["cold"]["converged"], name
+        assert s[name]["diverged"] < s["cold"]["diverged"], name
+
+
+def test_warm_start_reaches_the_same_steady_states(result):
+    cols, res, s = result
+    for name in ("warm", "warm_rho"):
+        cmp = s[name + "_vs_cold"]
+        _log(f"{name} vs cold: {cmp}")
+        assert cmp["both_converged"] > 0
+        # the same morphology for nearly every column both runs converge
+        assert cmp["same_morphology"] >= 0.9 * cmp["both_converged"]
+        # each converged profile is a steady state of the method: its mass
+        # differs from the cold run's by the walls' transient exchange only
+        c, w = res["cold"], res[name]
+        both = np.nonzero((c["status"] == 0) & (w["status"] == 0))[0]
+        for k in both:
+            a = c["rho"][cols.offsets[k]:cols.offsets[k + 1]]
+            b = w["rho"][cols.offsets[k]:cols.offsets[k + 1]]
+            assert abs(b.sum() - a.sum()) / a.sum() < 1e-2
+        assert cmp["final_rho_max_rel_diff_median"] < 1e-2
+
+
+def test_prediction_keeps_the_column_mass(result):
+    cols, res, s = result
+    m = np.add.reduceat(res["rho_pred"], cols.offsets[:-1])
+    m0 = np.add.reduceat(cols.rho0, cols.offsets[:-1])
+    assert np.abs(m - m0).max() / m0.min() < 1e-12
