@@ -210,7 +210,7 @@ NET_FLOPS_PER_POSITION = 2 * 5 * (8 * 64 + 4 * 64 * 64 + 64 * 2) * 2 + 2 * 5 * (
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 
 
-def run_warmstart(T, torch):
+def run_warmstart(T, torch, evaluate=True):
     """Held-out columns (1024, drawn as the sweep) from the plain start and
     from the trained network's profiles, each run to max |u| < 1e-9 or the
     step budget; plus the network's training throughput on the matrix cores."""
@@ -218,24 +218,26 @@ def run_warmstart(T, torch):
 
     if not os.path.exists(WS.PARAMS_PATH):
         return {"skipped": f"no trained parameters at {os.path.relpath(WS.PARAMS_PATH, ROOT)}"}
-    cols = WS.Columns(WS_EVAL_COLS, WS_EVAL_SEED)
-    net = T.Net(cols.rho_c, cols.T_c, max_cols=WS_EVAL_COLS, max_nodes=int(cols.height.sum()))
-    net.set_params(np.load(WS.PARAMS_PATH))
-    res = WS.evaluate(net, cols, BATCH_TOL, WS_EVAL_STEPS,
-                      log=lambda m: print("# " + m, file=sys.stderr, flush=True))
-    summary = WS.summarize(cols, res)
-    summary["predict_seconds"] = round(res["predict_seconds"], 4)
-    net.close()
+    rho_c, T_c, _ = T.eos_critical()
+    summary = {}
+    if evaluate:
+        cols = WS.Columns(WS_EVAL_COLS, WS_EVAL_SEED)
+        net = T.Net(cols.rho_c, cols.T_c, max_cols=WS_EVAL_COLS, max_nodes=int(cols.height.sum()))
+        net.set_params(np.load(WS.PARAMS_PATH))
+        res = WS.evaluate(net, cols, BATCH_TOL, WS_EVAL_STEPS,
+                          log=lambda m: print("# " + m, file=sys.stderr, flush=True))
+        summary = WS.summarize(cols, res)
+        summary["predict_seconds"] = round(res["predict_seconds"], 4)
+        net.close()
 
     # training throughput: minibatches of 32 columns of 1024 nodes (smooth
     # synthetic targets), Adam steps timed with HIP events on the net's stream
     H, nc = 1024, 32
     tcols = [(H, 1 + k % 2, 0.7 + 0.2 * k / nc, 10 ** (-6 + 2 * k / nc), 0.5 + 2 * k / nc) for k in range(nc)]
     s = (np.arange(H) + 0.5) / H
-    rho = np.concatenate([cols.rho_c * (c[4] + 0.5 * np.tanh((0.5 - s) * 30)) for c in tcols])
-    Tt = np.concatenate([np.full(H, cols.T_c * c[2]) for c in tcols])
-    net = T.Net(cols.rho_c, cols.T_c, max_cols=nc, max_nodes=nc * H, dataset_cols=nc,
-                dataset_nodes=nc * H)
+    rho = np.concatenate([rho_c * (c[4] + 0.5 * np.tanh((0.5 - s) * 30)) for c in tcols])
+    Tt = np.concatenate([np.full(H, T_c * c[2]) for c in tcols])
+    net = T.Net(rho_c, T_c, max_cols=nc, max_nodes=nc * H, dataset_cols=nc, dataset_nodes=nc * H)
     net.set_params(WS.init_params(3))
     net.set_dataset(tcols, rho, Tt)
     idx = np.arange(nc)
@@ -308,7 +310,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the plain per-column comparison of the batched sweep")
-    ap.add_argument("--variants", default="all", help="all | headline | fp32dev | d3q19 | batched | warmstart")
+    ap.add_argument("--variants", default="all", help="all | headline | fp32dev | d3q19 | batched | warmstart | net")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -342,7 +344,7 @@ def main():
     variants = [(0, 2, 1e-5)]
     if args.variants == "fp32dev":
         variants = [(1, 2, 1e-5)]
-    if args.variants in ("d3q19", "batched", "warmstart"):
+    if args.variants in ("d3q19", "batched", "warmstart", "net"):
         variants = [(0, 2, 1e-5)]
     if args.variants == "all":
         variants += [(0, 1, 1e-5), (0, 1, 1e-4), (0, 2, 1e-4), (1, 2, 1e-5), (1, 1, 1e-5),
@@ -433,8 +435,8 @@ def main():
                                            if pick else None),
                 "node_steps_per_s": round(pl["node_steps"] / pl["seconds"], 1) if pick else None},
         }
-    if args.variants in ("all", "warmstart"):
-        line["warm_start"] = run_warmstart(T, torch)
+    if args.variants in ("all", "warmstart", "net"):
+        line["warm_start"] = run_warmstart(T, torch, evaluate=args.variants != "net")
     line["hbm_copy_GBs"] = copy_bandwidth(torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(rho0, T0, T_c)

@@ -10,11 +10,15 @@
 //
 // One step is four passes over the lattice, intermediate fields in FP64:
 //   A: pull-stream with Zou-He wall reconstruction, rho, j, psi -> M
-//   B: Shan-Chen force (zero at walls), gravity, u = (j + F/2)/rho -> U
-//   C: first Heun stage of the energy equation, k1 = K(T^n) -> K1
+//   B: Shan-Chen force (zero at walls), gravity, u = (j + F/2)/rho, and
+//      sigma |F_int|^2 / psi^2                               -> U (u, F, X)
+//   C: div u and the first Heun stage of the energy equation, k1 = K(T^n)
+//                                                             -> K1 (k1, div u)
 //   D: T^{n+1} = T^n + (k1 + K(T^n + k1))/2, collision f* = f_eq + F'
 //      (rest population closing the mass), store f* and T^{n+1}, partial
 //      sums of the next level's mass; the last block finishes <rho>.
+// Every stencil is evaluated once per node and step; the passes hand the
+// results on instead of recomputing them.
 #include <hip/hip_runtime.h>
 
 #include "lbm_common.hpp"
@@ -60,91 +64,154 @@ struct Pop<float> {
     }
 };
 
+// Lattice shape and the row a block works on.  A block owns whole x-rows
+// (fixed y, z); the nine rows at y + dy, z + dz (dy, dz in {-1, 0, 1}) have
+// their first node's index computed once per row, so a neighbour index is a
+// row offset plus a wrapped x: 32-bit, no division per node.  On z-walls the
+// rows beyond the lattice are clamped to the wall row (only pulls use them,
+// and those populations are reconstructed).
 struct Grid3 {
     int nx, ny, nz;
-    __device__ __forceinline__ size_t idx(int x, int y, int z) const
-    {
-        return ((size_t)z * ny + y) * nx + x;
-    }
-    __device__ __forceinline__ int wx(int x) const { return x < 0 ? x + nx : (x >= nx ? x - nx : x); }
-    __device__ __forceinline__ int wy(int y) const { return y < 0 ? y + ny : (y >= ny ? y - ny : y); }
-    __device__ __forceinline__ int wz(int z) const { return z < 0 ? z + nz : (z >= nz ? z - nz : z); }
+    unsigned N;
 };
+
+struct Rows {
+    unsigned b[3][3];  // [dz + 1][dy + 1]
+    __device__ __forceinline__ unsigned at(int dx_wrapped_x, int dy, int dz) const
+    {
+        return b[dz + 1][dy + 1] + (unsigned)dx_wrapped_x;
+    }
+};
+
+template <bool WALLS>
+__device__ __forceinline__ Rows row_bases(const Grid3 &G, int y, int z)
+{
+    Rows r;
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz) {
+        int zz = z + dz;
+        if (WALLS) zz = zz < 0 ? 0 : (zz >= G.nz ? G.nz - 1 : zz);
+        else zz = zz < 0 ? zz + G.nz : (zz >= G.nz ? zz - G.nz : zz);
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy) {
+            int yy = y + dy;
+            yy = yy < 0 ? yy + G.ny : (yy >= G.ny ? yy - G.ny : yy);
+            r.b[dz + 1][dy + 1] = ((unsigned)zz * (unsigned)G.ny + (unsigned)yy) * (unsigned)G.nx;
+        }
+    }
+    return r;
+}
+
+__device__ __forceinline__ int wrap_x(int x, int nx) { return x < 0 ? x + nx : (x >= nx ? x - nx : x); }
+
+// Rows of this block.  Blocks are dispatched round-robin over the 8 XCDs;
+// with a grid that is a multiple of 8, XCD k takes the k-th contiguous
+// eighth of the rows (z-slabs), so the neighbouring rows a stencil reads
+// were mostly brought into that XCD's L2 by its own blocks.
+struct RowIter {
+    int first, end, step;
+};
+__device__ __forceinline__ RowIter row_iter(int rows)
+{
+    RowIter it;
+    const int nb = gridDim.x;
+    if ((nb & 7) == 0 && rows >= nb) {
+        const int per = nb >> 3, chunk = (rows + 7) >> 3;
+        const int r0 = (blockIdx.x & 7) * chunk;
+        it.first = r0 + (blockIdx.x >> 3);
+        it.end = min(rows, r0 + chunk);
+        it.step = per;
+    } else {
+        it.first = blockIdx.x;
+        it.end = rows;
+        it.step = nb;
+    }
+    return it;
+}
+
+// x-neighbours x - 1, x, x + 1 (periodic)
+struct Xs {
+    int v[3];
+};
+__device__ __forceinline__ Xs xs_of(int x, int nx)
+{
+    Xs q;
+    q.v[0] = wrap_x(x - 1, nx);
+    q.v[1] = x;
+    q.v[2] = wrap_x(x + 1, nx);
+    return q;
+}
 
 // ---- pass A: pull, Zou-He, moments, psi ----------------------------------
 template <class S, bool WALLS>
 __global__ __launch_bounds__(256) void d3q19_pass_a(const S *__restrict__ fin, const double *__restrict__ Tin,
                                                     double *__restrict__ M, Phys c, Grid3 G)
 {
-    const size_t N = (size_t)G.nx * G.ny * G.nz;
+    const unsigned N = G.N;
     const double rr = c.rho_ref;
-    for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N; n += (size_t)gridDim.x * blockDim.x) {
-        const int x = (int)(n % G.nx);
-        const int y = (int)((n / G.nx) % G.ny);
-        const int z = (int)(n / ((size_t)G.nx * G.ny));
-        double f[19];
-#pragma unroll
-        for (int i = 0; i < 19; ++i) {
-            const V3 v = vel(i);
-            int zs = z - v.z;
-            bool known = true;
-            if (WALLS) {
-                known = zs >= 0 && zs < G.nz;
-                zs = known ? zs : z;
-            } else {
-                zs = G.wz(zs);
-            }
-            f[i] = Pop<S>::ld(fin, (size_t)i * N + G.idx(G.wx(x - v.x), G.wy(y - v.y), zs), wgt(i) * rr);
-            (void)known;
-        }
-        if (WALLS && (z == 0 || z == G.nz - 1)) {
-            // zero-velocity wet-node reconstruction of the populations that
-            // come from beyond the wall, with transverse momentum corrections
-            const int s = z == 0 ? 1 : -1;
-            double Nx = 0.0, Ny = 0.0;
+    const int rows = G.ny * G.nz;
+    const RowIter it = row_iter(rows);
+    for (int row = it.first; row < it.end; row += it.step) {
+        const int y = row % G.ny, z = row / G.ny;
+        const Rows R = row_bases<WALLS>(G, y, z);
+        for (int x = threadIdx.x; x < G.nx; x += blockDim.x) {
+            const unsigned n = R.at(x, 0, 0);
+            const Xs X = xs_of(x, G.nx);
+            double f[19];
 #pragma unroll
             for (int i = 0; i < 19; ++i) {
                 const V3 v = vel(i);
-                if (v.z == 0) {
-                    Nx += 0.5 * v.x * f[i];
-                    Ny += 0.5 * v.y * f[i];
+                f[i] = Pop<S>::ld(fin, (size_t)i * N + R.at(X.v[1 - v.x], -v.y, -v.z), wgt(i) * rr);
+            }
+            if (WALLS && (z == 0 || z == G.nz - 1)) {
+                // zero-velocity wet-node reconstruction of the populations that
+                // come from beyond the wall, with transverse momentum corrections
+                const int s = z == 0 ? 1 : -1;
+                double Nx = 0.0, Ny = 0.0;
+#pragma unroll
+                for (int i = 0; i < 19; ++i) {
+                    const V3 v = vel(i);
+                    if (v.z == 0) {
+                        Nx += 0.5 * v.x * f[i];
+                        Ny += 0.5 * v.y * f[i];
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < 19; ++i) {
+                    const V3 v = vel(i);
+                    if (v.z == s) f[i] = f[opp(i)] - (double)v.x * Nx - (double)v.y * Ny;
                 }
             }
+            double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
             for (int i = 0; i < 19; ++i) {
                 const V3 v = vel(i);
-                if (v.z == s) f[i] = f[opp(i)] - (double)v.x * Nx - (double)v.y * Ny;
+                rho += f[i];
+                jx += v.x * f[i];
+                jy += v.y * f[i];
+                jz += v.z * f[i];
             }
+            double Z;
+            const double psi = psi_and_Z(c, rho, Tin[n], Z);
+            M[n] = rho;
+            M[N + n] = jx;
+            M[2 * (size_t)N + n] = jy;
+            M[3 * (size_t)N + n] = jz;
+            M[4 * (size_t)N + n] = psi;
         }
-        double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
-#pragma unroll
-        for (int i = 0; i < 19; ++i) {
-            const V3 v = vel(i);
-            rho += f[i];
-            jx += v.x * f[i];
-            jy += v.y * f[i];
-            jz += v.z * f[i];
-        }
-        double Z;
-        const double psi = psi_and_Z(c, rho, Tin[n], Z);
-        M[n] = rho;
-        M[N + n] = jx;
-        M[2 * N + n] = jy;
-        M[3 * N + n] = jz;
-        M[4 * N + n] = psi;
     }
 }
 
 // Shan-Chen sum s = sum_i w(|c_i|^2) psi(x + c_i) c_i, w(1) = 1/6, w(2) = 1/12
-__device__ __forceinline__ void sc_sum(const double *__restrict__ psi, const Grid3 &G, int x, int y, int z,
-                                       double &sx, double &sy, double &sz)
+__device__ __forceinline__ void sc_sum(const double *__restrict__ psi, const Rows &R, const Xs &X, double &sx,
+                                       double &sy, double &sz)
 {
     sx = sy = sz = 0.0;
 #pragma unroll
     for (int i = 1; i < 19; ++i) {
         const V3 v = vel(i);
         const double w = i < 7 ? 1.0 / 6.0 : 1.0 / 12.0;
-        const double p = psi[G.idx(G.wx(x + v.x), G.wy(y + v.y), G.wz(z + v.z))];
+        const double p = psi[R.at(X.v[1 + v.x], v.y, v.z)];
         sx += w * v.x * p;
         sy += w * v.y * p;
         sz += w * v.z * p;
@@ -157,40 +224,49 @@ __global__ __launch_bounds__(256) void d3q19_pass_b(const double *__restrict__ M
                                                     Phys c, Grid3 G, const StepState *__restrict__ st,
                                                     int slot)
 {
-    const size_t N = (size_t)G.nx * G.ny * G.nz;
+    const unsigned N = G.N;
     const double mean = st->mean[slot];
-    for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N; n += (size_t)gridDim.x * blockDim.x) {
-        const int x = (int)(n % G.nx);
-        const int y = (int)((n / G.nx) % G.ny);
-        const int z = (int)(n / ((size_t)G.nx * G.ny));
-        const double rho = M[n];
-        double Fx = 0.0, Fy = 0.0, Fz = 0.0;
-        if (!(WALLS && (z == 0 || z == G.nz - 1))) {
-            double sx, sy, sz;
-            sc_sum(M + 4 * N, G, x, y, z, sx, sy, sz);
-            const double mg = -c.G * M[4 * N + n];
-            Fx = mg * sx;
-            Fy = mg * sy;
-            Fz = mg * sz + ((c.form == 2) ? -(rho - mean) * c.g : -rho * c.g);
+    const int rows = G.ny * G.nz;
+    const RowIter it = row_iter(rows);
+    for (int row = it.first; row < it.end; row += it.step) {
+        const int y = row % G.ny, z = row / G.ny;
+        const Rows R = row_bases<WALLS>(G, y, z);
+        const bool wall = WALLS && (z == 0 || z == G.nz - 1);
+        for (int x = threadIdx.x; x < G.nx; x += blockDim.x) {
+            const unsigned n = R.at(x, 0, 0);
+            const double rho = M[n];
+            double Fx = 0.0, Fy = 0.0, Fz = 0.0, Xs2 = 0.0;
+            if (!wall) {
+                double sx, sy, sz;
+                sc_sum(M + 4 * (size_t)N, R, xs_of(x, G.nx), sx, sy, sz);
+                const double mg = -c.G * M[4 * (size_t)N + n];
+                Fx = mg * sx;
+                Fy = mg * sy;
+                Fz = mg * sz + ((c.form == 2) ? -(rho - mean) * c.g : -rho * c.g);
+                Xs2 = c.sigma * c.G2 * (sx * sx + sy * sy + sz * sz);  // sigma |F_int|^2 / psi^2
+            }
+            const double inv = rcp_pos(rho);
+            U[n] = (M[N + n] + 0.5 * Fx) * inv;
+            U[N + n] = (M[2 * (size_t)N + n] + 0.5 * Fy) * inv;
+            U[2 * (size_t)N + n] = (M[3 * (size_t)N + n] + 0.5 * Fz) * inv;
+            U[3 * (size_t)N + n] = Fx;
+            U[4 * (size_t)N + n] = Fy;
+            U[5 * (size_t)N + n] = Fz;
+            U[6 * (size_t)N + n] = Xs2;
         }
-        const double inv = rcp_pos(rho);
-        U[n] = (M[N + n] + 0.5 * Fx) * inv;
-        U[N + n] = (M[2 * N + n] + 0.5 * Fy) * inv;
-        U[2 * N + n] = (M[3 * N + n] + 0.5 * Fz) * inv;
     }
 }
 
 // isotropic differences on the D3Q19 stencil: grad = 3 sum w c phi,
-// lap = 6 sum w (phi_i - phi_0), div u = 3 sum w c.u_i
-__device__ __forceinline__ void grad_lap(const double *__restrict__ a, const double *__restrict__ b, const Grid3 &G,
-                                         int x, int y, int z, double c0, double &gx, double &gy, double &gz,
-                                         double &lap)
+// lap = 6 sum w (phi_i - phi_0), div u = 3 sum w c.u_i; phi = a (+ b)
+__device__ __forceinline__ void grad_lap(const double *__restrict__ a, const double *__restrict__ b, const Rows &R,
+                                         const Xs &X, double c0, double &gx, double &gy, double &gz, double &lap)
 {
     gx = gy = gz = lap = 0.0;
 #pragma unroll
     for (int i = 1; i < 19; ++i) {
         const V3 v = vel(i);
-        const size_t m = G.idx(G.wx(x + v.x), G.wy(y + v.y), G.wz(z + v.z));
+        const unsigned m = R.at(X.v[1 + v.x], v.y, v.z);
         const double p = b ? a[m] + b[m] : a[m];
         const double w = wgt(i);
         gx += w * v.x * p;
@@ -204,40 +280,48 @@ __device__ __forceinline__ void grad_lap(const double *__restrict__ a, const dou
     lap *= 6.0;
 }
 
-__device__ __forceinline__ double div3(const double *__restrict__ U, size_t N, const Grid3 &G, int x, int y, int z)
+__device__ __forceinline__ double div3(const double *__restrict__ U, unsigned N, const Rows &R, const Xs &X)
 {
     double d = 0.0;
 #pragma unroll
     for (int i = 1; i < 19; ++i) {
         const V3 v = vel(i);
-        const size_t m = G.idx(G.wx(x + v.x), G.wy(y + v.y), G.wz(z + v.z));
-        d += wgt(i) * (v.x * U[m] + v.y * U[N + m] + v.z * U[2 * N + m]);
+        const unsigned m = R.at(X.v[1 + v.x], v.y, v.z);
+        d += wgt(i) * (v.x * U[m] + v.y * U[N + m] + v.z * U[2 * (size_t)N + m]);
     }
     return 3.0 * d;
 }
 
 // ---- pass C: first Heun stage ------------------------------------------------
 template <bool WALLS>
-__global__ __launch_bounds__(256) void d3q19_pass_c(const double *__restrict__ Tin, const double *__restrict__ M,
+__global__ __launch_bounds__(256, 3) void d3q19_pass_c(const double *__restrict__ Tin, const double *__restrict__ M,
                                                     const double *__restrict__ U, double *__restrict__ K1,
                                                     Phys c, Grid3 G)
 {
-    const size_t N = (size_t)G.nx * G.ny * G.nz;
-    for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N; n += (size_t)gridDim.x * blockDim.x) {
-        const int x = (int)(n % G.nx);
-        const int y = (int)((n / G.nx) % G.ny);
-        const int z = (int)(n / ((size_t)G.nx * G.ny));
-        if (WALLS && (z == 0 || z == G.nz - 1)) {
-            K1[n] = 0.0;
-            continue;
+    const unsigned N = G.N;
+    const int rows = G.ny * G.nz;
+    const RowIter it = row_iter(rows);
+    for (int row = it.first; row < it.end; row += it.step) {
+        const int y = row % G.ny, z = row / G.ny;
+        const Rows R = row_bases<WALLS>(G, y, z);
+        const bool wall = WALLS && (z == 0 || z == G.nz - 1);
+        for (int x = threadIdx.x; x < G.nx; x += blockDim.x) {
+            const unsigned n = R.at(x, 0, 0);
+            if (wall) {
+                K1[n] = 0.0;
+                K1[N + n] = 0.0;
+                continue;
+            }
+            const Xs X = xs_of(x, G.nx);
+            const double rho = M[n], T0 = Tin[n];
+            double gx, gy, gz, lap;
+            grad_lap(Tin, nullptr, R, X, T0, gx, gy, gz, lap);
+            const double divu = div3(U, N, R, X);
+            const double Z = c.eos == 0 ? cs_Z(c.b_quarter * rho) : 0.0;
+            K1[n] = -(U[n] * gx + U[N + n] * gy + U[2 * (size_t)N + n] * gz) +
+                    c.kappa_over_cv * rcp_pos(rho) * lap - T0 * c.R_over_cv * Z * divu;
+            K1[N + n] = divu;
         }
-        const double rho = M[n], T0 = Tin[n];
-        double gx, gy, gz, lap;
-        grad_lap(Tin, nullptr, G, x, y, z, T0, gx, gy, gz, lap);
-        const double divu = div3(U, N, G, x, y, z);
-        const double Z = c.eos == 0 ? cs_Z(c.b_quarter * rho) : 0.0;
-        K1[n] = -(U[n] * gx + U[N + n] * gy + U[2 * N + n] * gz) + c.kappa_over_cv * rcp_pos(rho) * lap -
-                T0 * c.R_over_cv * Z * divu;
     }
 }
 
@@ -251,80 +335,76 @@ __global__ __launch_bounds__(256) void d3q19_pass_d(const double *__restrict__ T
 {
     __shared__ double s_red[16];
     __shared__ unsigned s_ured[4];
-    const size_t N = (size_t)G.nx * G.ny * G.nz;
+    const unsigned N = G.N;
     const double rr = c.rho_ref;
-    const double mean = st->mean[step & 1];
     Partial part = {0.0, 0.0, 0.0, 1e300, 0u};
-    for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N; n += (size_t)gridDim.x * blockDim.x) {
-        const int x = (int)(n % G.nx);
-        const int y = (int)((n / G.nx) % G.ny);
-        const int z = (int)(n / ((size_t)G.nx * G.ny));
+    const int rows = G.ny * G.nz;
+    const RowIter it = row_iter(rows);
+    for (int row = it.first; row < it.end; row += it.step) {
+        const int y = row % G.ny, z = row / G.ny;
+        const Rows R = row_bases<WALLS>(G, y, z);
         const bool wall = WALLS && (z == 0 || z == G.nz - 1);
-        const double rho = M[n], ux = U[n], uy = U[N + n], uz = U[2 * N + n], T0 = Tin[n];
-        double Tn = T0;
-        if (!wall) {
-            const double k1 = K1[n];
-            double gx, gy, gz, lap;
-            grad_lap(Tin, K1, G, x, y, z, T0 + k1, gx, gy, gz, lap);
-            const double divu = div3(U, N, G, x, y, z);
-            const double Z = c.eos == 0 ? cs_Z(c.b_quarter * rho) : 0.0;
-            const double k2 = -(ux * gx + uy * gy + uz * gz) + c.kappa_over_cv * rcp_pos(rho) * lap -
-                              (T0 + k1) * c.R_over_cv * Z * divu;
-            Tn = T0 + 0.5 * (k1 + k2);
-        }
-        Tout[n] = Tn;
-        double Fx = 0.0, Fy = 0.0, Fz = 0.0, X = 0.0;
-        const double psi0 = M[4 * N + n];
-        if (!wall) {
-            double sx, sy, sz;
-            sc_sum(M + 4 * N, G, x, y, z, sx, sy, sz);
-            const double mg = -c.G * psi0;
-            Fx = mg * sx;
-            Fy = mg * sy;
-            Fz = mg * sz + ((c.form == 2) ? -(rho - mean) * c.g : -rho * c.g);
-            X = c.sigma * c.G2 * (sx * sx + sy * sy + sz * sz);  // sigma |F_int|^2 / psi^2
-        }
-        const double uu = ux * ux + uy * uy + uz * uz;
-        const double uF = ux * Fx + uy * Fy + uz * Fz;
-        double fs[19];
-        double rest = 0.0;
+        for (int x = threadIdx.x; x < G.nx; x += blockDim.x) {
+            const unsigned n = R.at(x, 0, 0);
+            const Xs X = xs_of(x, G.nx);
+            const double rho = M[n], ux = U[n], uy = U[N + n], uz = U[2 * (size_t)N + n], T0 = Tin[n];
+            double Tn = T0;
+            if (!wall) {
+                const double k1 = K1[n];
+                double gx, gy, gz, lap;
+                grad_lap(Tin, K1, R, X, T0 + k1, gx, gy, gz, lap);
+                const double divu = K1[N + n];
+                const double Z = c.eos == 0 ? cs_Z(c.b_quarter * rho) : 0.0;
+                const double k2 = -(ux * gx + uy * gy + uz * gz) + c.kappa_over_cv * rcp_pos(rho) * lap -
+                                  (T0 + k1) * c.R_over_cv * Z * divu;
+                Tn = T0 + 0.5 * (k1 + k2);
+            }
+            Tout[n] = Tn;
+            const double psi0 = M[4 * (size_t)N + n];
+            const double Fx = U[3 * (size_t)N + n], Fy = U[4 * (size_t)N + n], Fz = U[5 * (size_t)N + n];
+            const double Xs2 = U[6 * (size_t)N + n];
+            const double uu = ux * ux + uy * uy + uz * uz;
+            const double uF = ux * Fx + uy * Fy + uz * Fz;
+            double fs[19];
+            double rest = 0.0;
 #pragma unroll
-        for (int i = 1; i < 19; ++i) {
-            const V3 v = vel(i);
-            const double w = wgt(i);
-            const double cu = v.x * ux + v.y * uy + v.z * uz;
-            const double cF = v.x * Fx + v.y * Fy + v.z * Fz;
-            const double c2 = (double)(v.x * v.x + v.y * v.y + v.z * v.z);
-            fs[i] = w * (rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu) + 1.5 * (cF - uF) + 4.5 * cu * cF +
-                         (c2 - 1.0) * 0.75 * X);
-            rest += fs[i];
-        }
-        fs[0] = rho - rest;
-        double nm = 0.0, down = 0.0, up = 0.0;
+            for (int i = 1; i < 19; ++i) {
+                const V3 v = vel(i);
+                const double w = wgt(i);
+                const double cu = v.x * ux + v.y * uy + v.z * uz;
+                const double cF = v.x * Fx + v.y * Fy + v.z * Fz;
+                const double c2 = (double)(v.x * v.x + v.y * v.y + v.z * v.z);
+                fs[i] = w * (rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu) + 1.5 * (cF - uF) + 4.5 * cu * cF +
+                             (c2 - 1.0) * 0.75 * Xs2);
+                rest += fs[i];
+            }
+            fs[0] = rho - rest;
+            double nm = 0.0, down = 0.0, up = 0.0;
 #pragma unroll
-        for (int i = 0; i < 19; ++i) {
-            const double v = Pop<S>::st(fout, (size_t)i * N + n, fs[i], wgt(i) * rr);
-            nm += v;
-            const int cz = vel(i).z;
-            if (cz < 0) down += v;
-            if (cz > 0) up += v;
+            for (int i = 0; i < 19; ++i) {
+                const double v = Pop<S>::st(fout, (size_t)i * N + n, fs[i], wgt(i) * rr);
+                nm += v;
+                const int cz = vel(i).z;
+                if (cz < 0) down += v;
+                if (cz > 0) up += v;
+            }
+            if (WALLS) {
+                if (z == 0) nm -= down;
+                if (z == 1) nm += down;
+                if (z == G.nz - 2) nm += up;
+                if (z == G.nz - 1) nm -= up;
+            }
+            part.mass_n += rho;
+            part.mass_next += nm;
+            part.umax = fmax(part.umax, uu);
+            part.rmin = fmin(part.rmin, rho);
+            unsigned fl = 0u;
+            if (!(rho > 0.0)) fl |= kFlagRho;
+            if (c.eos == 0 && c.b_quarter * rho >= 1.0) fl |= kFlagEta;
+            if (psi0 != psi0) fl |= kFlagPsi;
+            if (rho != rho || uu != uu || Tn != Tn || nm != nm) fl |= kFlagNaN;
+            part.flags |= fl;
         }
-        if (WALLS) {
-            if (z == 0) nm -= down;
-            if (z == 1) nm += down;
-            if (z == G.nz - 2) nm += up;
-            if (z == G.nz - 1) nm -= up;
-        }
-        part.mass_n += rho;
-        part.mass_next += nm;
-        part.umax = fmax(part.umax, uu);
-        part.rmin = fmin(part.rmin, rho);
-        unsigned fl = 0u;
-        if (!(rho > 0.0)) fl |= kFlagRho;
-        if (c.eos == 0 && c.b_quarter * rho >= 1.0) fl |= kFlagEta;
-        if (psi0 != psi0) fl |= kFlagPsi;
-        if (rho != rho || uu != uu || Tn != Tn || nm != nm) fl |= kFlagNaN;
-        part.flags |= fl;
     }
     part = block_reduce<256>(part, s_red, s_ured);
     finish_launch<256>(part, partials, st, step, (int)((step + 1) & 1), 1.0 / (double)N, s_red, s_ured);
@@ -336,57 +416,62 @@ __global__ void d3q19_readout(const double *__restrict__ M, const double *__rest
                               const double *__restrict__ Tin, Phys c, Grid3 G, int field,
                               double *__restrict__ out)
 {
-    const size_t N = (size_t)G.nx * G.ny * G.nz;
-    for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N; n += (size_t)gridDim.x * blockDim.x) {
-        const int x = (int)(n % G.nx);
-        const int y = (int)((n / G.nx) % G.ny);
-        const int z = (int)(n / ((size_t)G.nx * G.ny));
-        const double r = M[n];
-        double v = 0.0;
-        if (field == 0) v = r;
-        else if (field == 1) v = U[n];
-        else if (field == 2) v = U[N + n];
-        else if (field == 3) v = U[2 * N + n];
-        else if (field == 4) v = Tin[n];
-        else {
-            const double pe = p_eos(c, r, Tin[n]);
-            v = pe;
-            if (field == 6 && !(WALLS && (z == 0 || z == G.nz - 1))) {
-                const double *psi = M + 4 * N;
-                const double p0 = psi[n];
-                const double pxp = psi[G.idx(G.wx(x + 1), y, z)], pxm = psi[G.idx(G.wx(x - 1), y, z)];
-                const double pyp = psi[G.idx(x, G.wy(y + 1), z)], pym = psi[G.idx(x, G.wy(y - 1), z)];
-                const double pzp = psi[G.idx(x, y, G.wz(z + 1))], pzm = psi[G.idx(x, y, G.wz(z - 1))];
-                const double dx = 0.5 * (pxp - pxm), dy = 0.5 * (pyp - pym), dz = 0.5 * (pzp - pzm);
-                const double lap = (pxp + pxm) + (pyp + pym) + (pzp + pzm) - 6.0 * p0;
-                const double dzz = (pzp + pzm) - 2.0 * p0;
-                v = pe + c.sigma * c.G2 * (1.0 / 6.0) * (dx * dx + dy * dy + dz * dz) +
-                    c.G * (1.0 / 12.0) * p0 * lap + c.G * (1.0 / 6.0) * p0 * dzz;
+    const unsigned N = G.N;
+    const int rows = G.ny * G.nz;
+    const RowIter it = row_iter(rows);
+    for (int row = it.first; row < it.end; row += it.step) {
+        const int y = row % G.ny, z = row / G.ny;
+        const Rows R = row_bases<WALLS>(G, y, z);
+        for (int x = threadIdx.x; x < G.nx; x += blockDim.x) {
+            const unsigned n = R.at(x, 0, 0);
+            const double r = M[n];
+            double v = 0.0;
+            if (field == 0) v = r;
+            else if (field == 1) v = U[n];
+            else if (field == 2) v = U[N + n];
+            else if (field == 3) v = U[2 * (size_t)N + n];
+            else if (field == 4) v = Tin[n];
+            else {
+                const double pe = p_eos(c, r, Tin[n]);
+                v = pe;
+                if (field == 6 && !(WALLS && (z == 0 || z == G.nz - 1))) {
+                    const double *psi = M + 4 * (size_t)N;
+                    const Xs X = xs_of(x, G.nx);
+                    const double p0 = psi[n];
+                    const double pxp = psi[R.at(X.v[2], 0, 0)], pxm = psi[R.at(X.v[0], 0, 0)];
+                    const double pyp = psi[R.at(x, 1, 0)], pym = psi[R.at(x, -1, 0)];
+                    const double pzp = psi[R.at(x, 0, 1)], pzm = psi[R.at(x, 0, -1)];
+                    const double dx = 0.5 * (pxp - pxm), dy = 0.5 * (pyp - pym), dz = 0.5 * (pzp - pzm);
+                    const double lap = (pxp + pxm) + (pyp + pym) + (pzp + pzm) - 6.0 * p0;
+                    const double dzz = (pzp + pzm) - 2.0 * p0;
+                    v = pe + c.sigma * c.G2 * (1.0 / 6.0) * (dx * dx + dy * dy + dz * dz) +
+                        c.G * (1.0 / 12.0) * p0 * lap + c.G * (1.0 / 6.0) * p0 * dzz;
+                }
             }
+            out[n] = v;
         }
-        out[n] = v;
     }
 }
 
-int grid_1d(size_t N, int per_cu_blocks, int cus)
+// one block per x-row (fixed y, z), at most 8 resident blocks per compute unit
+int grid_rows(int ny, int nz, int cus)
 {
-    const size_t want = (N + 255) / 256;
-    const size_t cap = (size_t)cus * per_cu_blocks;
-    return (int)(want < cap ? want : cap);
+    const long rows = (long)ny * nz;
+    const long cap = (long)cus * 8;
+    return (int)(rows < cap ? rows : cap);
 }
 
 template <class S, bool WALLS>
 hipError_t step_t(const LatticeLaunch &L, double *M, double *U, double *K1)
 {
-    Grid3 G{L.nx, L.ny, L.nz};
-    const size_t N = (size_t)L.nx * L.ny * L.nz;
-    const int gA = grid_1d(N, 8, L.resident);
+    const Grid3 G{L.nx, L.ny, L.nz, (unsigned)((size_t)L.nx * L.ny * L.nz)};
+    const int gA = grid_rows(L.ny, L.nz, L.resident);
     hipLaunchKernelGGL((d3q19_pass_a<S, WALLS>), dim3(gA), dim3(256), 0, L.stream, (const S *)L.fin, L.Tin, M,
                        L.phys, G);
     hipLaunchKernelGGL((d3q19_pass_b<WALLS>), dim3(gA), dim3(256), 0, L.stream, M, U, L.phys, G, L.st,
                        (int)(L.step & 1));
     hipLaunchKernelGGL((d3q19_pass_c<WALLS>), dim3(gA), dim3(256), 0, L.stream, L.Tin, M, U, K1, L.phys, G);
-    const int gD = d3q19_num_blocks(N, L.resident);
+    const int gD = d3q19_num_blocks(L.ny, L.nz, L.resident);
     hipLaunchKernelGGL((d3q19_pass_d<S, WALLS>), dim3(gD), dim3(256), 0, L.stream, L.Tin, L.Tout, M, U, K1,
                        (S *)L.fout, L.phys, G, L.partials, L.st, L.step);
     return hipGetLastError();
@@ -394,7 +479,7 @@ hipError_t step_t(const LatticeLaunch &L, double *M, double *U, double *K1)
 
 }  // namespace
 
-int d3q19_num_blocks(size_t N, int cus) { return grid_1d(N, 8, cus); }
+int d3q19_num_blocks(int ny, int nz, int cus) { return grid_rows(ny, nz, cus); }
 
 hipError_t d3q19_launch_step(const LatticeLaunch &L, double *M, double *U, double *K1)
 {
@@ -404,9 +489,8 @@ hipError_t d3q19_launch_step(const LatticeLaunch &L, double *M, double *U, doubl
 
 hipError_t d3q19_launch_readout(const LatticeLaunch &L, int field, double *M, double *U, double *out)
 {
-    Grid3 G{L.nx, L.ny, L.nz};
-    const size_t N = (size_t)L.nx * L.ny * L.nz;
-    const int g = grid_1d(N, 8, L.resident);
+    const Grid3 G{L.nx, L.ny, L.nz, (unsigned)((size_t)L.nx * L.ny * L.nz)};
+    const int g = grid_rows(L.ny, L.nz, L.resident);
     if (L.fp32) {
         if (L.walls)
             hipLaunchKernelGGL((d3q19_pass_a<float, true>), dim3(g), dim3(256), 0, L.stream, (const float *)L.fin, L.Tin, M, L.phys, G);

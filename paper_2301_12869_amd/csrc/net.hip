@@ -187,14 +187,28 @@ __global__ __launch_bounds__(256) void dw_mfma(const uint16_t *__restrict__ dZ, 
     }
 }
 
-// dst[e] = sum_b src[b][e] over b in increasing order (deterministic)
+// Sum of count values a[0], a[step], a[2 step], ... added in increasing
+// order (deterministic); eight loads are issued before their additions.
+__device__ __forceinline__ float ordered_sum(const float *__restrict__ a, int count, size_t step)
+{
+    float s = 0.0f;
+    int k = 0;
+    for (; k + 8 <= count; k += 8) {
+        float v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = a[(size_t)(k + j) * step];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s += v[j];
+    }
+    for (; k < count; ++k) s += a[(size_t)k * step];
+    return s;
+}
+
+// dst[e] = sum_b src[b][e] over b in increasing order
 __global__ void reduce_partials(const float *__restrict__ src, int nb, int stride, int n, float *__restrict__ dst)
 {
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
-        float s = 0.0f;
-        for (int b = 0; b < nb; ++b) s += src[(size_t)b * stride + e];
-        dst[e] = s;
-    }
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x)
+        dst[e] = ordered_sum(src + e, nb, (size_t)stride);
 }
 
 // bias-gradient partials: per-channel sums of dZ over position slices
@@ -202,10 +216,8 @@ __global__ void db_partial(const float *__restrict__ dZ, int ZS, int P, int span
 {
     const int o = threadIdx.x;
     if (o >= ZS) return;
-    float s = 0.0f;
     const int pbeg = blockIdx.x * span, pend = min(P, pbeg + span);
-    for (int p = pbeg; p < pend; ++p) s += dZ[(size_t)p * ZS + o];
-    partial[(size_t)blockIdx.x * ZS + o] = s;
+    partial[(size_t)blockIdx.x * ZS + o] = ordered_sum(dZ + (size_t)pbeg * ZS + o, pend - pbeg, (size_t)ZS);
 }
 
 // squared-error partials and the output-layer gradient dZ (8 channels per

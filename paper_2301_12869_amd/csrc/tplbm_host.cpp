@@ -77,7 +77,9 @@ int validate(const tplbm_params *p)
         return fail(nullptr, TPLBM_EINVAL, "lattice must be TPLBM_D2Q9 or TPLBM_D3Q19 (columns use tplbm_batch_*)");
     if (p->lattice == TPLBM_D3Q19) {
         if (p->nx < 1 || p->ny < 1 || p->nz < 3) return fail(nullptr, TPLBM_ESHAPE, "need nx, ny >= 1 and nz >= 3");
-        if ((int64_t)p->nx * p->ny * p->nz > (int64_t)1 << 31) return fail(nullptr, TPLBM_ESHAPE, "lattice too large");
+        // population indices are 32-bit: 19 N < 2^32
+        if ((int64_t)p->nx * p->ny * p->nz * 19 >= (int64_t)1 << 32)
+            return fail(nullptr, TPLBM_ESHAPE, "lattice too large (at most 2^32 / 19 nodes)");
         if (!tau_one(*p)) return fail(nullptr, TPLBM_EUNSUPPORTED, "D3Q19 supports only every tau = 1");
     } else {
         if (p->nx < 1 || p->ny < 3) return fail(nullptr, TPLBM_ESHAPE, "need nx >= 1 and ny >= 3");
@@ -148,9 +150,9 @@ Layout layout_of(const tplbm_params &p)
     L.f_bytes = align256(q_of(p) * N * elem);
     L.T_bytes = align256(N * 8);
     if (p.lattice == TPLBM_D3Q19) {
-        // pass buffers: M (rho, j, psi), U (u), K1
-        L.pass_bytes = align256(5 * N * 8) + align256(3 * N * 8) + align256(N * 8);
-        L.nblocks = d3q19_num_blocks(N, 1 << 20);
+        // pass buffers: M (rho, j, psi), U (u, F, sigma |F_int|^2 / psi^2), K1 (k1, div u)
+        L.pass_bytes = align256(5 * N * 8) + align256(7 * N * 8) + align256(2 * N * 8);
+        L.nblocks = d3q19_num_blocks(p.ny, p.nz, 1 << 20);
     } else {
         // readout scratch reuses the idle population buffer: it needs 4N doubles
         if (L.f_bytes < align256(4 * N * 8)) L.f_bytes = align256(4 * N * 8);
@@ -242,7 +244,7 @@ int tplbm_create(const tplbm_params *p, void *dev_workspace, size_t bytes, void 
     c->st = (StepState *)q; q += L.st_bytes;
     if (p->lattice == TPLBM_D3Q19) {
         c->M = (double *)q; q += align256(5 * c->N * 8);
-        c->U = (double *)q; q += align256(3 * c->N * 8);
+        c->U = (double *)q; q += align256(7 * c->N * 8);
         c->K1 = (double *)q;
     }
     c->phys = make_phys(*p);
