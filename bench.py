@@ -210,6 +210,35 @@ NET_FLOPS_PER_POSITION = 2 * 5 * (8 * 64 + 4 * 64 * 64 + 64 * 2) * 2 + 2 * 5 * (
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 
 
+def train_throughput(T, torch, WS, rho_c, T_c, nc, H=1024, n_steps=50):
+    tcols = [(H, 1 + k % 2, 0.7 + 0.2 * k / nc, 10 ** (-6 + 2 * k / nc), 0.5 + 2 * k / nc) for k in range(nc)]
+    s = (np.arange(H) + 0.5) / H
+    rho = np.concatenate([rho_c * (c[4] + 0.5 * np.tanh((0.5 - s) * 30)) for c in tcols])
+    Tt = np.concatenate([np.full(H, T_c * c[2]) for c in tcols])
+    net = T.Net(rho_c, T_c, max_cols=nc, max_nodes=nc * H, dataset_cols=nc, dataset_nodes=nc * H)
+    net.set_params(WS.init_params(3))
+    net.set_dataset(tcols, rho, Tt)
+    idx = np.arange(nc)
+    for _ in range(5):
+        net.train_step(idx, 1e-4, want_loss=False)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(net.stream)
+    for _ in range(n_steps):
+        net.train_step(idx, 1e-4, want_loss=False)
+    ev1.record(net.stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / n_steps
+    net.close()
+    tflops = NET_FLOPS_PER_POSITION * nc * H / (ms * 1e-3) / 1e12
+    print(f"# net train step ({nc} columns): {ms:.3f} ms for {nc * H} positions, {tflops:.1f} TFLOP/s",
+          file=sys.stderr, flush=True)
+    return {"positions": nc * H, "ms": round(ms, 4),
+            "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": MFMA_BF16_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(tflops / MFMA_BF16_PEAK_TFLOPS, 4),
+                         "flops_per_position": NET_FLOPS_PER_POSITION}}
+
+
 def run_warmstart(T, torch, evaluate=True):
     """Held-out columns (1024, drawn as the sweep) from the plain start and
     from the trained network's profiles, each run to max |u| < 1e-9 or the
@@ -230,37 +259,11 @@ def run_warmstart(T, torch, evaluate=True):
         summary["predict_seconds"] = round(res["predict_seconds"], 4)
         net.close()
 
-    # training throughput: minibatches of 32 columns of 1024 nodes (smooth
-    # synthetic targets), Adam steps timed with HIP events on the net's stream
-    H, nc = 1024, 32
-    tcols = [(H, 1 + k % 2, 0.7 + 0.2 * k / nc, 10 ** (-6 + 2 * k / nc), 0.5 + 2 * k / nc) for k in range(nc)]
-    s = (np.arange(H) + 0.5) / H
-    rho = np.concatenate([rho_c * (c[4] + 0.5 * np.tanh((0.5 - s) * 30)) for c in tcols])
-    Tt = np.concatenate([np.full(H, T_c * c[2]) for c in tcols])
-    net = T.Net(rho_c, T_c, max_cols=nc, max_nodes=nc * H, dataset_cols=nc, dataset_nodes=nc * H)
-    net.set_params(WS.init_params(3))
-    net.set_dataset(tcols, rho, Tt)
-    idx = np.arange(nc)
-    for _ in range(5):
-        net.train_step(idx, 1e-4, want_loss=False)
-    n_steps = 50
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(net.stream)
-    for _ in range(n_steps):
-        net.train_step(idx, 1e-4, want_loss=False)
-    ev1.record(net.stream)
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / n_steps
-    net.close()
-    tflops = NET_FLOPS_PER_POSITION * nc * H / (ms * 1e-3) / 1e12
-    summary["train_step"] = {
-        "positions": nc * H, "ms": round(ms, 4),
-        "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": MFMA_BF16_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(tflops / MFMA_BF16_PEAK_TFLOPS, 4),
-                     "flops_per_position": NET_FLOPS_PER_POSITION}}
-    print(f"# net train step: {ms:.3f} ms for {nc * H} positions, {tflops:.1f} TFLOP/s", file=sys.stderr,
-          flush=True)
+    # training throughput: Adam steps on minibatches of nc columns of 1024
+    # nodes (smooth synthetic targets), timed with HIP events on the net's
+    # stream; 32 columns is the training minibatch, 256 fills the GPU
+    for key, nc in (("train_step", 32), ("train_step_256_columns", 256)):
+        summary[key] = train_throughput(T, torch, WS, rho_c, T_c, nc)
     return summary
 
 

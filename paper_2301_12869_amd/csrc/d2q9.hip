@@ -201,7 +201,7 @@ __device__ __forceinline__ void pull_loads(const S *__restrict__ fin, const doub
     T = Tin[q.row + gx];
 }
 
-template <class S, bool TAU1, bool WALLS, int TX, int TY, int NT, int MIN_WAVES_PER_EU>
+template <class S, bool TAU1, bool WALLS, int TX, int TY, int NT, int MIN_WAVES_PER_EU, int PF0>
 __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step(const S *__restrict__ fin,
                                                          S *__restrict__ fout,
                                                          const double *__restrict__ Tin,
@@ -246,12 +246,13 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step(const S *__res
     const int t_end = min(ntiles, t_begin + tiles_per_xcd);
 
     Prefetch<S, NSLOT> pre;
-    auto issue = [&](int t) {
+    // issue the pulls of region slots [k0, k1) of tile t
+    auto issue = [&](int t, int k0, int k1) {
         const int x0 = (t % tiles_x) * TX, y0 = (t / tiles_x) * TY;
 #pragma unroll
         for (int k = 0; k < NSLOT; ++k) {
             const int r = tid + k * kThreads;
-            if (r < R3N) {
+            if (k >= k0 && k < k1 && r < R3N) {
                 const NodeGeom q = region_node<WALLS, W3, TY>(r, x0, y0, nx, ny, small_x);
                 pull_loads<S>(fin, Tin, N, q, pre.f[k], pre.T[k]);
             }
@@ -259,10 +260,14 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step(const S *__res
     };
 
     Partial part = {0.0, 0.0, 0.0, 1e300, 0u};
+    // The first slot of a tile's pulls is issued during the previous tile's
+    // last phase (it is consumed first), the others at the start of the tile:
+    // every pull is issued before any is consumed, and a third of them is
+    // already in flight while the previous tile computes.
+    if (t_begin + slot < t_end) issue(t_begin + slot, 0, PF0);
     for (int t = t_begin + slot; t < t_end; t += per_xcd_blocks) {
         const int x0 = (t % tiles_x) * TX, y0 = (t / tiles_x) * TY;
-        // every pull of the tile is issued before any is consumed
-        issue(t);
+        issue(t, PF0, NSLOT);
 
         // ---- phase 1: density, momentum, psi on tile + 3 (from registers) ----
 #pragma unroll
@@ -353,6 +358,8 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step(const S *__res
             s_k1[r] = energy_rhs(c, tt, s_T[c2], s_ux[c2], s_uy[c2], divu, rcp_pos(s_rho[c2]), s_Z[c2]);
         }
         __syncthreads();
+
+        if (t + per_xcd_blocks < t_end) issue(t + per_xcd_blocks, 0, PF0);
 
         // ---- phase 4: second Heun stage, collision, stores, partials ----
         for (int r = tid; r < TY * TX; r += kThreads) {
@@ -662,7 +669,11 @@ hipError_t launch_t(const LatticeLaunch &L)
     const int tiles_x = (L.nx + kTX - 1) / kTX, tiles_y = (L.ny + kTY - 1) / kTY;
     const int ntiles = tiles_x * tiles_y;
     const int nb = d2q9_num_blocks(L.nx, L.ny, L.resident);
-    hipLaunchKernelGGL((d2q9_step<S, TAU1, WALLS, kTX, kTY, kNT, 4>), dim3(nb), dim3(kNT), 0, L.stream,
+    // FP32 storage leaves room in registers to issue the first third of the
+    // next tile's pulls before the last phase; in FP64 those registers would
+    // spill, so every pull of a tile is issued at its start
+    constexpr int PF0 = sizeof(S) == 4 ? 1 : 0;
+    hipLaunchKernelGGL((d2q9_step<S, TAU1, WALLS, kTX, kTY, kNT, 4, PF0>), dim3(nb), dim3(kNT), 0, L.stream,
                        (const S *)L.fin, (S *)L.fout, L.Tin, L.Tout, L.phys, L.nx, L.ny, tiles_x,
                        ntiles, L.partials, L.st, L.step);
     return hipGetLastError();

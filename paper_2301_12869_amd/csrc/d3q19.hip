@@ -202,8 +202,75 @@ __global__ __launch_bounds__(256) void d3q19_pass_a(const S *__restrict__ fin, c
     }
 }
 
+// ---- tiles for the stencil passes -------------------------------------------
+// Passes B, C and D evaluate 18-neighbour stencils.  A block takes a tile of
+// 64 x 4 x 4 nodes, stages the stencil fields of the tile plus a one-node
+// halo (66 x 6 x 6) in LDS once, and evaluates every stencil from there.
+// Tiles are walked persistently; XCD k takes the k-th contiguous eighth of
+// them (z-slabs), as for the rows of pass A.
+constexpr int kTX = 64, kTY = 4, kTZ = 4;
+constexpr int kRX = kTX + 2, kRY = kTY + 2, kRZ = kTZ + 2;
+constexpr int kRegion = kRX * kRY * kRZ;
+constexpr int kTileNodes = kTX * kTY * kTZ;
+constexpr int kStencilThreads = 256;
+
+struct TileIter {
+    int first, end, step;
+};
+__device__ __forceinline__ TileIter tile_iter(int ntiles)
+{
+    TileIter it;
+    const int nb = gridDim.x;
+    if ((nb & 7) == 0 && ntiles >= nb) {
+        const int chunk = (ntiles + 7) >> 3;
+        const int t0 = (blockIdx.x & 7) * chunk;
+        it.first = t0 + (blockIdx.x >> 3);
+        it.end = min(ntiles, t0 + chunk);
+        it.step = nb >> 3;
+    } else {
+        it.first = blockIdx.x;
+        it.end = ntiles;
+        it.step = nb;
+    }
+    return it;
+}
+
+struct Tile3 {
+    int x0, y0, z0;
+};
+__device__ __forceinline__ Tile3 tile_origin(const Grid3 &G, int t)
+{
+    const int tx = (G.nx + kTX - 1) / kTX, ty = (G.ny + kTY - 1) / kTY;
+    Tile3 o;
+    o.x0 = (t % tx) * kTX;
+    o.y0 = ((t / tx) % ty) * kTY;
+    o.z0 = (t / (tx * ty)) * kTZ;
+    return o;
+}
+
+__device__ __forceinline__ int periodic(int v, int n) { return v < 0 ? n - 1 : (v >= n ? v % n : v); }
+
+// global index of region node r (periodic x, y; z periodic or clamped at
+// walls -- clamped values are never used by a stencil)
+template <bool WALLS>
+__device__ __forceinline__ unsigned region_index(const Grid3 &G, const Tile3 &o, int r)
+{
+    const int rx = r % kRX, ry = (r / kRX) % kRY, rz = r / (kRX * kRY);
+    const int x = periodic(o.x0 + rx - 1, G.nx), y = periodic(o.y0 + ry - 1, G.ny);
+    int z = o.z0 + rz - 1;
+    if (WALLS) z = z < 0 ? 0 : (z >= G.nz ? G.nz - 1 : z);
+    else z = periodic(z, G.nz);
+    return ((unsigned)z * (unsigned)G.ny + (unsigned)y) * (unsigned)G.nx + (unsigned)x;
+}
+
+// region index of the neighbour (dx, dy, dz) of tile node (tx, ty, tz)
+__device__ __forceinline__ int rnb(int tx, int ty, int tz, int dx, int dy, int dz)
+{
+    return ((tz + 1 + dz) * kRY + (ty + 1 + dy)) * kRX + (tx + 1 + dx);
+}
+
 // Shan-Chen sum s = sum_i w(|c_i|^2) psi(x + c_i) c_i, w(1) = 1/6, w(2) = 1/12
-__device__ __forceinline__ void sc_sum(const double *__restrict__ psi, const Rows &R, const Xs &X, double &sx,
+__device__ __forceinline__ void sc_sum(const double *__restrict__ sp, int tx, int ty, int tz, double &sx,
                                        double &sy, double &sz)
 {
     sx = sy = sz = 0.0;
@@ -211,7 +278,7 @@ __device__ __forceinline__ void sc_sum(const double *__restrict__ psi, const Row
     for (int i = 1; i < 19; ++i) {
         const V3 v = vel(i);
         const double w = i < 7 ? 1.0 / 6.0 : 1.0 / 12.0;
-        const double p = psi[R.at(X.v[1 + v.x], v.y, v.z)];
+        const double p = sp[rnb(tx, ty, tz, v.x, v.y, v.z)];
         sx += w * v.x * p;
         sy += w * v.y * p;
         sz += w * v.z * p;
@@ -220,26 +287,32 @@ __device__ __forceinline__ void sc_sum(const double *__restrict__ psi, const Row
 
 // ---- pass B: force and velocity --------------------------------------------
 template <bool WALLS>
-__global__ __launch_bounds__(256) void d3q19_pass_b(const double *__restrict__ M, double *__restrict__ U,
-                                                    Phys c, Grid3 G, const StepState *__restrict__ st,
-                                                    int slot)
+__global__ __launch_bounds__(kStencilThreads) void d3q19_pass_b(const double *__restrict__ M, double *__restrict__ U,
+                                                                Phys c, Grid3 G, const StepState *__restrict__ st,
+                                                                int slot)
 {
+    __shared__ double s_psi[kRegion];
     const unsigned N = G.N;
     const double mean = st->mean[slot];
-    const int rows = G.ny * G.nz;
-    const RowIter it = row_iter(rows);
-    for (int row = it.first; row < it.end; row += it.step) {
-        const int y = row % G.ny, z = row / G.ny;
-        const Rows R = row_bases<WALLS>(G, y, z);
-        const bool wall = WALLS && (z == 0 || z == G.nz - 1);
-        for (int x = threadIdx.x; x < G.nx; x += blockDim.x) {
-            const unsigned n = R.at(x, 0, 0);
+    const int ntiles = ((G.nx + kTX - 1) / kTX) * ((G.ny + kTY - 1) / kTY) * ((G.nz + kTZ - 1) / kTZ);
+    const TileIter it = tile_iter(ntiles);
+    for (int t = it.first; t < it.end; t += it.step) {
+        const Tile3 o = tile_origin(G, t);
+        __syncthreads();
+        for (int r = threadIdx.x; r < kRegion; r += kStencilThreads)
+            s_psi[r] = M[4 * (size_t)N + region_index<WALLS>(G, o, r)];
+        __syncthreads();
+        for (int k = threadIdx.x; k < kTileNodes; k += kStencilThreads) {
+            const int tx = k % kTX, ty = (k / kTX) % kTY, tz = k / (kTX * kTY);
+            const int x = o.x0 + tx, y = o.y0 + ty, z = o.z0 + tz;
+            if (x >= G.nx || y >= G.ny || z >= G.nz) continue;
+            const unsigned n = ((unsigned)z * (unsigned)G.ny + (unsigned)y) * (unsigned)G.nx + (unsigned)x;
             const double rho = M[n];
             double Fx = 0.0, Fy = 0.0, Fz = 0.0, Xs2 = 0.0;
-            if (!wall) {
+            if (!(WALLS && (z == 0 || z == G.nz - 1))) {
                 double sx, sy, sz;
-                sc_sum(M + 4 * (size_t)N, R, xs_of(x, G.nx), sx, sy, sz);
-                const double mg = -c.G * M[4 * (size_t)N + n];
+                sc_sum(s_psi, tx, ty, tz, sx, sy, sz);
+                const double mg = -c.G * s_psi[rnb(tx, ty, tz, 0, 0, 0)];
                 Fx = mg * sx;
                 Fy = mg * sy;
                 Fz = mg * sz + ((c.form == 2) ? -(rho - mean) * c.g : -rho * c.g);
@@ -257,17 +330,16 @@ __global__ __launch_bounds__(256) void d3q19_pass_b(const double *__restrict__ M
     }
 }
 
-// isotropic differences on the D3Q19 stencil: grad = 3 sum w c phi,
-// lap = 6 sum w (phi_i - phi_0), div u = 3 sum w c.u_i; phi = a (+ b)
-__device__ __forceinline__ void grad_lap(const double *__restrict__ a, const double *__restrict__ b, const Rows &R,
-                                         const Xs &X, double c0, double &gx, double &gy, double &gz, double &lap)
+// isotropic differences on the D3Q19 stencil from a region field:
+// grad = 3 sum w c phi, lap = 6 sum w (phi_i - phi_0)
+__device__ __forceinline__ void grad_lap(const double *__restrict__ a, int tx, int ty, int tz, double c0, double &gx,
+                                         double &gy, double &gz, double &lap)
 {
     gx = gy = gz = lap = 0.0;
 #pragma unroll
     for (int i = 1; i < 19; ++i) {
         const V3 v = vel(i);
-        const unsigned m = R.at(X.v[1 + v.x], v.y, v.z);
-        const double p = b ? a[m] + b[m] : a[m];
+        const double p = a[rnb(tx, ty, tz, v.x, v.y, v.z)];
         const double w = wgt(i);
         gx += w * v.x * p;
         gy += w * v.y * p;
@@ -280,46 +352,60 @@ __device__ __forceinline__ void grad_lap(const double *__restrict__ a, const dou
     lap *= 6.0;
 }
 
-__device__ __forceinline__ double div3(const double *__restrict__ U, unsigned N, const Rows &R, const Xs &X)
+// div u = 3 sum w c.u_i from the region fields of u
+__device__ __forceinline__ double div3(const double *__restrict__ ux, const double *__restrict__ uy,
+                                       const double *__restrict__ uz, int tx, int ty, int tz)
 {
     double d = 0.0;
 #pragma unroll
     for (int i = 1; i < 19; ++i) {
         const V3 v = vel(i);
-        const unsigned m = R.at(X.v[1 + v.x], v.y, v.z);
-        d += wgt(i) * (v.x * U[m] + v.y * U[N + m] + v.z * U[2 * (size_t)N + m]);
+        const int m = rnb(tx, ty, tz, v.x, v.y, v.z);
+        d += wgt(i) * (v.x * ux[m] + v.y * uy[m] + v.z * uz[m]);
     }
     return 3.0 * d;
 }
 
-// ---- pass C: first Heun stage ------------------------------------------------
+// ---- pass C: div u and the first Heun stage ------------------------------------
 template <bool WALLS>
-__global__ __launch_bounds__(256, 3) void d3q19_pass_c(const double *__restrict__ Tin, const double *__restrict__ M,
-                                                    const double *__restrict__ U, double *__restrict__ K1,
-                                                    Phys c, Grid3 G)
+__global__ __launch_bounds__(kStencilThreads) void d3q19_pass_c(const double *__restrict__ Tin,
+                                                                const double *__restrict__ M,
+                                                                const double *__restrict__ U,
+                                                                double *__restrict__ K1, Phys c, Grid3 G)
 {
+    __shared__ double s_T[kRegion], s_ux[kRegion], s_uy[kRegion], s_uz[kRegion];
     const unsigned N = G.N;
-    const int rows = G.ny * G.nz;
-    const RowIter it = row_iter(rows);
-    for (int row = it.first; row < it.end; row += it.step) {
-        const int y = row % G.ny, z = row / G.ny;
-        const Rows R = row_bases<WALLS>(G, y, z);
-        const bool wall = WALLS && (z == 0 || z == G.nz - 1);
-        for (int x = threadIdx.x; x < G.nx; x += blockDim.x) {
-            const unsigned n = R.at(x, 0, 0);
-            if (wall) {
+    const int ntiles = ((G.nx + kTX - 1) / kTX) * ((G.ny + kTY - 1) / kTY) * ((G.nz + kTZ - 1) / kTZ);
+    const TileIter it = tile_iter(ntiles);
+    for (int t = it.first; t < it.end; t += it.step) {
+        const Tile3 o = tile_origin(G, t);
+        __syncthreads();
+        for (int r = threadIdx.x; r < kRegion; r += kStencilThreads) {
+            const unsigned m = region_index<WALLS>(G, o, r);
+            s_T[r] = Tin[m];
+            s_ux[r] = U[m];
+            s_uy[r] = U[N + m];
+            s_uz[r] = U[2 * (size_t)N + m];
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < kTileNodes; k += kStencilThreads) {
+            const int tx = k % kTX, ty = (k / kTX) % kTY, tz = k / (kTX * kTY);
+            const int x = o.x0 + tx, y = o.y0 + ty, z = o.z0 + tz;
+            if (x >= G.nx || y >= G.ny || z >= G.nz) continue;
+            const unsigned n = ((unsigned)z * (unsigned)G.ny + (unsigned)y) * (unsigned)G.nx + (unsigned)x;
+            if (WALLS && (z == 0 || z == G.nz - 1)) {
                 K1[n] = 0.0;
                 K1[N + n] = 0.0;
                 continue;
             }
-            const Xs X = xs_of(x, G.nx);
-            const double rho = M[n], T0 = Tin[n];
+            const int c0 = rnb(tx, ty, tz, 0, 0, 0);
+            const double rho = M[n], T0 = s_T[c0];
             double gx, gy, gz, lap;
-            grad_lap(Tin, nullptr, R, X, T0, gx, gy, gz, lap);
-            const double divu = div3(U, N, R, X);
+            grad_lap(s_T, tx, ty, tz, T0, gx, gy, gz, lap);
+            const double divu = div3(s_ux, s_uy, s_uz, tx, ty, tz);
             const double Z = c.eos == 0 ? cs_Z(c.b_quarter * rho) : 0.0;
-            K1[n] = -(U[n] * gx + U[N + n] * gy + U[2 * (size_t)N + n] * gz) +
-                    c.kappa_over_cv * rcp_pos(rho) * lap - T0 * c.R_over_cv * Z * divu;
+            K1[n] = -(s_ux[c0] * gx + s_uy[c0] * gy + s_uz[c0] * gz) + c.kappa_over_cv * rcp_pos(rho) * lap -
+                    T0 * c.R_over_cv * Z * divu;
             K1[N + n] = divu;
         }
     }
@@ -327,32 +413,43 @@ __global__ __launch_bounds__(256, 3) void d3q19_pass_c(const double *__restrict_
 
 // ---- pass D: second Heun stage, collision, stores, partials ------------------
 template <class S, bool WALLS>
-__global__ __launch_bounds__(256) void d3q19_pass_d(const double *__restrict__ Tin, double *__restrict__ Tout,
-                                                    const double *__restrict__ M, const double *__restrict__ U,
-                                                    const double *__restrict__ K1, S *__restrict__ fout, Phys c,
-                                                    Grid3 G, double *__restrict__ partials,
-                                                    StepState *__restrict__ st, int64_t step)
+__global__ __launch_bounds__(kStencilThreads) void d3q19_pass_d(const double *__restrict__ Tin,
+                                                                double *__restrict__ Tout,
+                                                                const double *__restrict__ M,
+                                                                const double *__restrict__ U,
+                                                                const double *__restrict__ K1,
+                                                                S *__restrict__ fout, Phys c, Grid3 G,
+                                                                double *__restrict__ partials,
+                                                                StepState *__restrict__ st, int64_t step)
 {
+    __shared__ double s_Tt[kRegion];  // T~ = T^n + k1
     __shared__ double s_red[16];
     __shared__ unsigned s_ured[4];
     const unsigned N = G.N;
     const double rr = c.rho_ref;
     Partial part = {0.0, 0.0, 0.0, 1e300, 0u};
-    const int rows = G.ny * G.nz;
-    const RowIter it = row_iter(rows);
-    for (int row = it.first; row < it.end; row += it.step) {
-        const int y = row % G.ny, z = row / G.ny;
-        const Rows R = row_bases<WALLS>(G, y, z);
-        const bool wall = WALLS && (z == 0 || z == G.nz - 1);
-        for (int x = threadIdx.x; x < G.nx; x += blockDim.x) {
-            const unsigned n = R.at(x, 0, 0);
-            const Xs X = xs_of(x, G.nx);
+    const int ntiles = ((G.nx + kTX - 1) / kTX) * ((G.ny + kTY - 1) / kTY) * ((G.nz + kTZ - 1) / kTZ);
+    const TileIter it = tile_iter(ntiles);
+    for (int t = it.first; t < it.end; t += it.step) {
+        const Tile3 o = tile_origin(G, t);
+        __syncthreads();
+        for (int r = threadIdx.x; r < kRegion; r += kStencilThreads) {
+            const unsigned m = region_index<WALLS>(G, o, r);
+            s_Tt[r] = Tin[m] + K1[m];
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < kTileNodes; k += kStencilThreads) {
+            const int tx = k % kTX, ty = (k / kTX) % kTY, tz = k / (kTX * kTY);
+            const int x = o.x0 + tx, y = o.y0 + ty, z = o.z0 + tz;
+            if (x >= G.nx || y >= G.ny || z >= G.nz) continue;
+            const unsigned n = ((unsigned)z * (unsigned)G.ny + (unsigned)y) * (unsigned)G.nx + (unsigned)x;
+            const bool wall = WALLS && (z == 0 || z == G.nz - 1);
             const double rho = M[n], ux = U[n], uy = U[N + n], uz = U[2 * (size_t)N + n], T0 = Tin[n];
             double Tn = T0;
             if (!wall) {
                 const double k1 = K1[n];
                 double gx, gy, gz, lap;
-                grad_lap(Tin, K1, R, X, T0 + k1, gx, gy, gz, lap);
+                grad_lap(s_Tt, tx, ty, tz, T0 + k1, gx, gy, gz, lap);
                 const double divu = K1[N + n];
                 const double Z = c.eos == 0 ? cs_Z(c.b_quarter * rho) : 0.0;
                 const double k2 = -(ux * gx + uy * gy + uz * gz) + c.kappa_over_cv * rcp_pos(rho) * lap -
@@ -406,8 +503,8 @@ __global__ __launch_bounds__(256) void d3q19_pass_d(const double *__restrict__ T
             part.flags |= fl;
         }
     }
-    part = block_reduce<256>(part, s_red, s_ured);
-    finish_launch<256>(part, partials, st, step, (int)((step + 1) & 1), 1.0 / (double)N, s_red, s_ured);
+    part = block_reduce<kStencilThreads>(part, s_red, s_ured);
+    finish_launch<kStencilThreads>(part, partials, st, step, (int)((step + 1) & 1), 1.0 / (double)N, s_red, s_ured);
 }
 
 // ---- readout: from M and U of the current level -------------------------------
@@ -461,6 +558,14 @@ int grid_rows(int ny, int nz, int cus)
     return (int)(rows < cap ? rows : cap);
 }
 
+// one block per tile, at most 4 resident blocks per compute unit (LDS)
+int grid_tiles(int nx, int ny, int nz, int cus)
+{
+    const long t = (long)((nx + kTX - 1) / kTX) * ((ny + kTY - 1) / kTY) * ((nz + kTZ - 1) / kTZ);
+    const long cap = (long)cus * 4;
+    return (int)(t < cap ? t : cap);
+}
+
 template <class S, bool WALLS>
 hipError_t step_t(const LatticeLaunch &L, double *M, double *U, double *K1)
 {
@@ -468,18 +573,20 @@ hipError_t step_t(const LatticeLaunch &L, double *M, double *U, double *K1)
     const int gA = grid_rows(L.ny, L.nz, L.resident);
     hipLaunchKernelGGL((d3q19_pass_a<S, WALLS>), dim3(gA), dim3(256), 0, L.stream, (const S *)L.fin, L.Tin, M,
                        L.phys, G);
-    hipLaunchKernelGGL((d3q19_pass_b<WALLS>), dim3(gA), dim3(256), 0, L.stream, M, U, L.phys, G, L.st,
+    const int gT = grid_tiles(L.nx, L.ny, L.nz, L.resident);
+    hipLaunchKernelGGL((d3q19_pass_b<WALLS>), dim3(gT), dim3(kStencilThreads), 0, L.stream, M, U, L.phys, G, L.st,
                        (int)(L.step & 1));
-    hipLaunchKernelGGL((d3q19_pass_c<WALLS>), dim3(gA), dim3(256), 0, L.stream, L.Tin, M, U, K1, L.phys, G);
-    const int gD = d3q19_num_blocks(L.ny, L.nz, L.resident);
-    hipLaunchKernelGGL((d3q19_pass_d<S, WALLS>), dim3(gD), dim3(256), 0, L.stream, L.Tin, L.Tout, M, U, K1,
+    hipLaunchKernelGGL((d3q19_pass_c<WALLS>), dim3(gT), dim3(kStencilThreads), 0, L.stream, L.Tin, M, U, K1,
+                       L.phys, G);
+    hipLaunchKernelGGL((d3q19_pass_d<S, WALLS>), dim3(gT), dim3(kStencilThreads), 0, L.stream, L.Tin, L.Tout, M,
+                       U, K1,
                        (S *)L.fout, L.phys, G, L.partials, L.st, L.step);
     return hipGetLastError();
 }
 
 }  // namespace
 
-int d3q19_num_blocks(int ny, int nz, int cus) { return grid_rows(ny, nz, cus); }
+int d3q19_num_blocks(int nx, int ny, int nz, int cus) { return grid_tiles(nx, ny, nz, cus); }
 
 hipError_t d3q19_launch_step(const LatticeLaunch &L, double *M, double *U, double *K1)
 {
@@ -502,11 +609,12 @@ hipError_t d3q19_launch_readout(const LatticeLaunch &L, int field, double *M, do
         else
             hipLaunchKernelGGL((d3q19_pass_a<double, false>), dim3(g), dim3(256), 0, L.stream, (const double *)L.fin, L.Tin, M, L.phys, G);
     }
+    const int gT = grid_tiles(L.nx, L.ny, L.nz, L.resident);
     if (L.walls) {
-        hipLaunchKernelGGL((d3q19_pass_b<true>), dim3(g), dim3(256), 0, L.stream, M, U, L.phys, G, L.st, (int)(L.step & 1));
+        hipLaunchKernelGGL((d3q19_pass_b<true>), dim3(gT), dim3(kStencilThreads), 0, L.stream, M, U, L.phys, G, L.st, (int)(L.step & 1));
         hipLaunchKernelGGL((d3q19_readout<true>), dim3(g), dim3(256), 0, L.stream, M, U, L.Tin, L.phys, G, field, out);
     } else {
-        hipLaunchKernelGGL((d3q19_pass_b<false>), dim3(g), dim3(256), 0, L.stream, M, U, L.phys, G, L.st, (int)(L.step & 1));
+        hipLaunchKernelGGL((d3q19_pass_b<false>), dim3(gT), dim3(kStencilThreads), 0, L.stream, M, U, L.phys, G, L.st, (int)(L.step & 1));
         hipLaunchKernelGGL((d3q19_readout<false>), dim3(g), dim3(256), 0, L.stream, M, U, L.Tin, L.phys, G, field, out);
     }
     return hipGetLastError();

@@ -29,7 +29,7 @@ constexpr int kD3Q19y[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, 
 constexpr int kD3Q19z[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
 
 int d2q9_num_blocks(int nx, int ny, int resident);
-int d3q19_num_blocks(int ny, int nz, int cus);
+int d3q19_num_blocks(int nx, int ny, int nz, int cus);
 hipError_t d3q19_launch_step(const LatticeLaunch &L, double *M, double *U, double *K1);
 hipError_t d3q19_launch_readout(const LatticeLaunch &L, int field, double *M, double *U, double *out);
 hipError_t d2q9_launch_step(const LatticeLaunch &L);

@@ -43,23 +43,27 @@ __device__ __forceinline__ int acc_row(int r, int lane) { return 8 * (r >> 2) + 
 // MODE 0: hidden forward layer: out_bf16 = bf16(relu(acc + bias))
 // MODE 1: output layer:         out_f32[p][o] = acc + bias for o < NOUT
 // MODE 2: input gradient:       g = acc * (mask[p][o] > 0); out_f32 = g, out_bf16 = bf16(g)
-// A wave owns 32 positions and all 32 NTILES output channels.
+// A block covers 128 positions and all 32 NTILES output channels; each of
+// its 4 NTILES waves owns 32 positions and one 32-channel tile (the waves of
+// a position group read the same activations, which L1 serves).
 template <int CIN, int NTILES, int MODE, int NOUT>
-__global__ __launch_bounds__(256) void conv_mfma(const uint16_t *__restrict__ in, const uint16_t *__restrict__ W,
-                                                 const float *__restrict__ bias, int P,
-                                                 const uint8_t *__restrict__ guard,
-                                                 const uint16_t *__restrict__ mask, float *__restrict__ out_f32,
-                                                 uint16_t *__restrict__ out_bf16)
+__global__ __launch_bounds__(256 * NTILES) void conv_mfma(const uint16_t *__restrict__ in,
+                                                          const uint16_t *__restrict__ W,
+                                                          const float *__restrict__ bias, int P,
+                                                          const uint8_t *__restrict__ guard,
+                                                          const uint16_t *__restrict__ mask,
+                                                          float *__restrict__ out_f32,
+                                                          uint16_t *__restrict__ out_bf16)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int p0 = (blockIdx.x * 4 + wave) * 32;
+    const int nt = wave % NTILES;
+    const int p0 = (blockIdx.x * 4 + wave / NTILES) * 32;
     if (p0 >= P) return;
     const int i = lane & 31, kq = lane >> 5;
-    f32x16 acc[NTILES];
+    const int o = 32 * nt + i;
+    f32x16 acc;
 #pragma unroll
-    for (int nt = 0; nt < NTILES; ++nt)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc[nt][r] = 0.0f;
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
 #pragma unroll
     for (int t = 0; t < 5; ++t) {
         int q = p0 + i + t - 2;
@@ -67,34 +71,26 @@ __global__ __launch_bounds__(256) void conv_mfma(const uint16_t *__restrict__ in
 #pragma unroll
         for (int c0 = 0; c0 < CIN; c0 += 8) {
             const bf16x4 a = *reinterpret_cast<const bf16x4 *>(in + (size_t)q * CIN + c0 + 4 * kq);
-#pragma unroll
-            for (int nt = 0; nt < NTILES; ++nt) {
-                const int o = 32 * nt + i;
-                const bf16x4 b = *reinterpret_cast<const bf16x4 *>(W + ((size_t)o * 5 + t) * CIN + c0 + 4 * kq);
-                acc[nt] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc[nt], 0, 0, 0);
-            }
+            const bf16x4 b = *reinterpret_cast<const bf16x4 *>(W + ((size_t)o * 5 + t) * CIN + c0 + 4 * kq);
+            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
         }
     }
     constexpr int COUT = 32 * NTILES;
 #pragma unroll
-    for (int nt = 0; nt < NTILES; ++nt) {
-        const int o = 32 * nt + i;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int p = p0 + acc_row(r, lane);
-            if (p >= P) continue;
-            const bool g = guard[p] != 0;
-            float v = acc[nt][r];
-            if (MODE == 0) {
-                v = g ? 0.0f : fmaxf(v + bias[o], 0.0f);
-                out_bf16[(size_t)p * COUT + o] = f2bf(v);
-            } else if (MODE == 1) {
-                if (o < NOUT) out_f32[(size_t)p * NOUT + o] = g ? 0.0f : v + bias[o];
-            } else {
-                v = (g || !(bf2f(mask[(size_t)p * COUT + o]) > 0.0f)) ? 0.0f : v;
-                out_f32[(size_t)p * COUT + o] = v;
-                out_bf16[(size_t)p * COUT + o] = f2bf(v);
-            }
+    for (int r = 0; r < 16; ++r) {
+        const int p = p0 + acc_row(r, lane);
+        if (p >= P) continue;
+        const bool g = guard[p] != 0;
+        float v = acc[r];
+        if (MODE == 0) {
+            v = g ? 0.0f : fmaxf(v + bias[o], 0.0f);
+            out_bf16[(size_t)p * COUT + o] = f2bf(v);
+        } else if (MODE == 1) {
+            if (o < NOUT) out_f32[(size_t)p * NOUT + o] = g ? 0.0f : v + bias[o];
+        } else {
+            v = (g || !(bf2f(mask[(size_t)p * COUT + o]) > 0.0f)) ? 0.0f : v;
+            out_f32[(size_t)p * COUT + o] = v;
+            out_bf16[(size_t)p * COUT + o] = f2bf(v);
         }
     }
 }
@@ -420,21 +416,21 @@ hipError_t net_raw_out(const NetCol *cols, const NetEntry *entries, int n, const
 hipError_t net_conv_forward(int layer, const uint16_t *in, const uint16_t *W, const float *bias, int64_t P,
                             const uint8_t *guard, uint16_t *out_bf16, float *out_f32, hipStream_t s)
 {
-    const dim3 g(conv_blocks(P)), b(256);
+    const dim3 g(conv_blocks(P)), b2(512), b1(256);
     const int p = (int)P;
     if (layer == 0)
-        hipLaunchKernelGGL((conv_mfma<8, 2, 0, 64>), g, b, 0, s, in, W, bias, p, guard, nullptr, nullptr, out_bf16);
+        hipLaunchKernelGGL((conv_mfma<8, 2, 0, 64>), g, b2, 0, s, in, W, bias, p, guard, nullptr, nullptr, out_bf16);
     else if (layer < 5)
-        hipLaunchKernelGGL((conv_mfma<64, 2, 0, 64>), g, b, 0, s, in, W, bias, p, guard, nullptr, nullptr, out_bf16);
+        hipLaunchKernelGGL((conv_mfma<64, 2, 0, 64>), g, b2, 0, s, in, W, bias, p, guard, nullptr, nullptr, out_bf16);
     else
-        hipLaunchKernelGGL((conv_mfma<64, 1, 1, 2>), g, b, 0, s, in, W, bias, p, guard, nullptr, out_f32, nullptr);
+        hipLaunchKernelGGL((conv_mfma<64, 1, 1, 2>), g, b1, 0, s, in, W, bias, p, guard, nullptr, out_f32, nullptr);
     return hipGetLastError();
 }
 
 hipError_t net_conv_input_grad(int layer, const uint16_t *dZ, const uint16_t *Wg, int64_t P, const uint8_t *guard,
                                const uint16_t *act_in, float *dprev_f32, uint16_t *dprev_bf16, hipStream_t s)
 {
-    const dim3 g(conv_blocks(P)), b(256);
+    const dim3 g(conv_blocks(P)), b(512);
     const int p = (int)P;
     if (layer == 5)
         hipLaunchKernelGGL((conv_mfma<8, 2, 2, 64>), g, b, 0, s, dZ, Wg, nullptr, p, guard, act_in, dprev_f32,

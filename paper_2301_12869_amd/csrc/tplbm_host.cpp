@@ -152,7 +152,7 @@ Layout layout_of(const tplbm_params &p)
     if (p.lattice == TPLBM_D3Q19) {
         // pass buffers: M (rho, j, psi), U (u, F, sigma |F_int|^2 / psi^2), K1 (k1, div u)
         L.pass_bytes = align256(5 * N * 8) + align256(7 * N * 8) + align256(2 * N * 8);
-        L.nblocks = d3q19_num_blocks(p.ny, p.nz, 1 << 20);
+        L.nblocks = d3q19_num_blocks(p.nx, p.ny, p.nz, 1 << 20);
     } else {
         // readout scratch reuses the idle population buffer: it needs 4N doubles
         if (L.f_bytes < align256(4 * N * 8)) L.f_bytes = align256(4 * N * 8);
