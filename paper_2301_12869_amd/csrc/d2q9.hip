@@ -183,25 +183,23 @@ __device__ __forceinline__ NodeGeom region_node(int r, int x0, int y0, int nx, i
     return q;
 }
 
-// Issue the pull loads of one region node (all in-bounds).
+// Issue the pull loads [i0, i1) of one region node (all in-bounds); loads
+// 0..8 are the populations, load 9 the temperature.
 template <class S>
 __device__ __forceinline__ void pull_loads(const S *__restrict__ fin, const double *__restrict__ Tin,
-                                           size_t N, const NodeGeom &q, S (&f)[9], double &T)
+                                           size_t N, const NodeGeom &q, S (&f)[9], double &T, int i0 = 0,
+                                           int i1 = 10)
 {
     const unsigned gx = (unsigned)q.gx;
-    f[0] = fin[0 * N + q.row + gx];
-    f[1] = fin[1 * N + q.row + q.xm];
-    f[2] = fin[2 * N + q.rowm + gx];
-    f[3] = fin[3 * N + q.row + q.xp];
-    f[4] = fin[4 * N + q.rowp + gx];
-    f[5] = fin[5 * N + q.rowm + q.xm];
-    f[6] = fin[6 * N + q.rowm + q.xp];
-    f[7] = fin[7 * N + q.rowp + q.xp];
-    f[8] = fin[8 * N + q.rowp + q.xm];
-    T = Tin[q.row + gx];
+    const unsigned idx[9] = {q.row + gx, q.row + q.xm, q.rowm + gx, q.row + q.xp, q.rowp + gx,
+                             q.rowm + q.xm, q.rowm + q.xp, q.rowp + q.xp, q.rowp + q.xm};
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        if (i >= i0 && i < i1) f[i] = fin[(size_t)i * N + idx[i]];
+    if (9 >= i0 && 9 < i1) T = Tin[q.row + gx];
 }
 
-template <class S, bool TAU1, bool WALLS, int TX, int TY, int NT, int MIN_WAVES_PER_EU, int PF0>
+template <class S, bool TAU1, bool WALLS, int TX, int TY, int NT, int MIN_WAVES_PER_EU, int PFP>
 __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step(const S *__restrict__ fin,
                                                          S *__restrict__ fout,
                                                          const double *__restrict__ Tin,
@@ -246,28 +244,31 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step(const S *__res
     const int t_end = min(ntiles, t_begin + tiles_per_xcd);
 
     Prefetch<S, NSLOT> pre;
-    // issue the pulls of region slots [k0, k1) of tile t
-    auto issue = [&](int t, int k0, int k1) {
+    // issue loads [i0, i1) of the first region slot of tile t (early), or the
+    // remaining loads of the tile
+    auto issue = [&](int t, bool early) {
         const int x0 = (t % tiles_x) * TX, y0 = (t / tiles_x) * TY;
 #pragma unroll
         for (int k = 0; k < NSLOT; ++k) {
             const int r = tid + k * kThreads;
-            if (k >= k0 && k < k1 && r < R3N) {
+            const int i0 = early ? 0 : (k == 0 ? PFP : 0);
+            const int i1 = early ? (k == 0 ? PFP : 0) : 10;
+            if (i0 < i1 && r < R3N) {
                 const NodeGeom q = region_node<WALLS, W3, TY>(r, x0, y0, nx, ny, small_x);
-                pull_loads<S>(fin, Tin, N, q, pre.f[k], pre.T[k]);
+                pull_loads<S>(fin, Tin, N, q, pre.f[k], pre.T[k], i0, i1);
             }
         }
     };
 
     Partial part = {0.0, 0.0, 0.0, 1e300, 0u};
-    // The first slot of a tile's pulls is issued during the previous tile's
-    // last phase (it is consumed first), the others at the start of the tile:
-    // every pull is issued before any is consumed, and a third of them is
-    // already in flight while the previous tile computes.
-    if (t_begin + slot < t_end) issue(t_begin + slot, 0, PF0);
+    // The first PFP loads of a tile's first region slot are issued during the
+    // previous tile's last phase (that slot is consumed first), the rest at
+    // the start of the tile: every pull is issued before any is consumed, and
+    // part of them is in flight while the previous tile computes.
+    if (t_begin + slot < t_end) issue(t_begin + slot, true);
     for (int t = t_begin + slot; t < t_end; t += per_xcd_blocks) {
         const int x0 = (t % tiles_x) * TX, y0 = (t / tiles_x) * TY;
-        issue(t, PF0, NSLOT);
+        issue(t, false);
 
         // ---- phase 1: density, momentum, psi on tile + 3 (from registers) ----
 #pragma unroll
@@ -359,7 +360,7 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step(const S *__res
         }
         __syncthreads();
 
-        if (t + per_xcd_blocks < t_end) issue(t + per_xcd_blocks, 0, PF0);
+        if (t + per_xcd_blocks < t_end) issue(t + per_xcd_blocks, true);
 
         // ---- phase 4: second Heun stage, collision, stores, partials ----
         for (int r = tid; r < TY * TX; r += kThreads) {
@@ -669,11 +670,13 @@ hipError_t launch_t(const LatticeLaunch &L)
     const int tiles_x = (L.nx + kTX - 1) / kTX, tiles_y = (L.ny + kTY - 1) / kTY;
     const int ntiles = tiles_x * tiles_y;
     const int nb = d2q9_num_blocks(L.nx, L.ny, L.resident);
-    // FP32 storage leaves room in registers to issue the first third of the
-    // next tile's pulls before the last phase; in FP64 those registers would
-    // spill, so every pull of a tile is issued at its start
-    constexpr int PF0 = sizeof(S) == 4 ? 1 : 0;
-    hipLaunchKernelGGL((d2q9_step<S, TAU1, WALLS, kTX, kTY, kNT, 4, PF0>), dim3(nb), dim3(kNT), 0, L.stream,
+    // How many loads of the next tile's first region slot are issued before
+    // the last phase of the current tile: with FP32 storage all of them
+    // (populations and temperature) fit in registers; with FP64 storage the
+    // first three populations do, more would spill.  The general-relaxation
+    // collision needs those registers itself.
+    constexpr int PFP = TAU1 ? (sizeof(S) == 4 ? 10 : 3) : 0;
+    hipLaunchKernelGGL((d2q9_step<S, TAU1, WALLS, kTX, kTY, kNT, 4, PFP>), dim3(nb), dim3(kNT), 0, L.stream,
                        (const S *)L.fin, (S *)L.fout, L.Tin, L.Tout, L.phys, L.nx, L.ny, tiles_x,
                        ntiles, L.partials, L.st, L.step);
     return hipGetLastError();
