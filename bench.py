@@ -85,6 +85,7 @@ def run_variant(T, torch, rho0, T0, precision, form, g, steps, warmup):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     d = lat.diagnostics()
+    rho_end = lat.read("rho") if not d["flags"] else None
     lat.close()
     # F = rho g with g = 1e-4 over 2048 rows drives the vapour beyond its
     # spinodal within about 1300 steps: the method itself fails there (the
@@ -92,7 +93,7 @@ def run_variant(T, torch, rho0, T0, precision, form, g, steps, warmup):
     status = "ok" if not d["flags"] else f"unphysical from level {d['first_bad_step']}"
     ms_events = ev0.elapsed_time(ev1)
     return dict(wall_s=wall, ms_per_step=1e3 * wall / steps, status=status,
-                kernel_ms=ms_events / steps, mass=d["mass"], max_u=d["max_u"])
+                kernel_ms=ms_events / steps, mass=d["mass"], max_u=d["max_u"], rho=rho_end)
 
 
 D3_N = 256
@@ -123,16 +124,28 @@ def run_d3q19(T, torch, steps, warmup):
         ev1.record(lat.stream)
         torch.cuda.synchronize()
         d = lat.diagnostics()
+        rho32 = lat.read("rho")
         lat.close()
+        # the same steps with FP64 populations: the error of the FP32 storage
+        p64 = T.make_params(T.D3Q19, nx=n, ny=n, nz=n, walls=True, precision=T.FP64,
+                            gravity_form=form, g=1e-5)
+        lat = T.Lattice(p64)
+        lat.set_state(rho0, T0)
+        lat.step(warmup + steps)
+        rho64 = lat.read("rho")
+        lat.close()
+        err = float(np.abs(rho32 - rho64).max() / np.abs(rho64).max())
         ms = ev0.elapsed_time(ev1) / steps
         mlups = n ** 3 / (ms * 1e-3) / 1e6
         gbs = D3_BYTES_PER_NODE[1] * n ** 3 / (ms * 1e-3) / 1e9
         out[f"fp32dev_form{form}_g1e-05"] = {
             "mlups": round(mlups, 1), "GBs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
             "ms_per_step": round(ms, 4), "bytes_per_node_step": D3_BYTES_PER_NODE[1],
+            "rho_rel_err_vs_fp64": err, "steps_compared": warmup + steps,
             "status": "ok" if not d["flags"] else f"unphysical from level {d['first_bad_step']}"}
         print(f"# d3q19 256^3 fp32dev form{form}: {ms*1e3:.0f} us/step, {mlups:.0f} MLUPS, "
-              f"{gbs:.0f} GB/s ({100*gbs/HBM_PEAK_GBS:.1f}% of HBM)", file=sys.stderr, flush=True)
+              f"{gbs:.0f} GB/s ({100*gbs/HBM_PEAK_GBS:.1f}% of HBM), rho error vs FP64 {err:.2e}",
+              file=sys.stderr, flush=True)
     return out
 
 
@@ -361,6 +374,11 @@ def main():
         r["achieved_GBs"] = bpn * NX * NY / (r["kernel_ms"] * 1e-3) / 1e9
         r["frac_hbm"] = r["achieved_GBs"] / HBM_PEAK_GBS
         results[key] = r
+        twin = results.get(key.replace("fp32dev", "fp64"))
+        if prec == 1 and twin is not None and twin["rho"] is not None and r["rho"] is not None:
+            # same inputs and step count with FP64 populations (which match the
+            # FP64 oracle to 1e-12): the error of the FP32 deviation storage
+            r["rho_rel_err_vs_fp64"] = float(np.abs(r["rho"] - twin["rho"]).max() / np.abs(twin["rho"]).max())
         print(f"# {key}: {r['kernel_ms']*1e3:.1f} us/step, {r['mlups']:.0f} MLUPS, "
               f"{r['achieved_GBs']:.0f} GB/s ({100*r['frac_hbm']:.1f}% of HBM) [{r['status']}]",
               file=sys.stderr, flush=True)
@@ -398,7 +416,9 @@ def main():
                          "status": v["status"],
                          "frac_hbm": round(v["frac_hbm"], 4),
                          "bytes_per_node_step": BYTES_PER_NODE[0 if k.startswith("fp64") else 1],
-                         "traffic": measured_traffic(k)}
+                         "traffic": measured_traffic(k),
+                         **({"rho_rel_err_vs_fp64": v["rho_rel_err_vs_fp64"]}
+                            if "rho_rel_err_vs_fp64" in v else {})}
                      for k, v in results.items()},
     }
     if args.variants in ("all", "d3q19"):

@@ -93,3 +93,27 @@ def test_network_parameter_count_and_workspace_on_the_host(lib):
         rc = lib.tplbm_net_workspace_bytes(ctypes.byref(c2), ctypes.byref(nb))
         assert rc in (T.EINVAL, T.ESHAPE), (field, rc)
         assert lib.tplbm_net_last_error(None)
+
+
+def test_degenerate_lattices_and_columns_are_rejected_on_the_host(lib):
+    """Empty, too small, too large and unsupported configurations return an
+    error code before any device work (no GPU needed)."""
+    import ctypes
+
+    nb = ctypes.c_size_t()
+    for kw, codes in ((dict(lattice=T.D3Q19, nx=4, ny=4, nz=2), (T.ESHAPE,)),
+                      (dict(lattice=T.D3Q19, nx=4, ny=4, nz=8, tau=(1, 1, 1, 1, 1, 0.8)), (T.EUNSUPPORTED,)),
+                      (dict(lattice=T.D3Q19, nx=1024, ny=1024, nz=256), (T.ESHAPE,)),
+                      (dict(lattice=T.D2Q9, nx=0, ny=8), (T.ESHAPE,)),
+                      (dict(lattice=T.D2Q9, nx=65536, ny=65536), (T.ESHAPE,))):
+        p = T.make_params(**kw)
+        assert lib.tplbm_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)) in codes, kw
+    bp = T.BatchParams(a=0.5, b=4.0, R=1.0, G=-1.0, sigma=1.385, cv=5.0, kappa=0.02, eos=0, pad=0)
+    cols = (T.Column * 1)()
+    assert lib.tplbm_batch_workspace_bytes(ctypes.byref(bp), 0, cols, ctypes.byref(nb)) == T.EINVAL
+    for h, form, g, code in ((2, 1, 1e-5, T.ESHAPE), (2049, 1, 1e-5, T.ESHAPE), (100, 3, 1e-5, T.EINVAL)):
+        cols[0].height, cols[0].gravity_form, cols[0].g = h, form, g
+        assert lib.tplbm_batch_workspace_bytes(ctypes.byref(bp), 1, cols, ctypes.byref(nb)) == code
+        assert lib.tplbm_batch_last_error(None)
+    cols[0].height, cols[0].gravity_form = 2048, 2
+    assert lib.tplbm_batch_workspace_bytes(ctypes.byref(bp), 1, cols, ctypes.byref(nb)) == T.OK
