@@ -6,7 +6,12 @@ product's HIP kernels never use it.
 The network maps a column's parameters to its steady profiles.  Input at
 position y of a column of height H (channels, in this order):
     s - 1/2 with s = (y + 1/2)/H,  T/T_c - 0.8,  log10(g) + 5,  form - 3/2,
-    <rho>/rho_c - 1.3,  H/2048 - 1/2,  0,  0        (8 channels, two zero)
+    <rho>/rho_c - 1.3,  H/2048 - 1/2,  clip(d/32, -4, 4)/4,  clip(d/4, -4, 4)/4
+with d = y + 1/2 - h the distance (in nodes) to the lever-rule interface
+height h = H (<rho> - rho_v)/(rho_l - rho_v) of the column (rho_v, rho_l:
+Maxwell coexistence densities at T; the caller computes h).  The last two
+channels locate the interface to a fraction of a node even in BF16, which
+the coarse position channel cannot do for tall columns (8-bit mantissa).
 Six 1-D convolutions of width 5 with zero padding at both ends of the column
 (the column never sees its neighbours in a batch), ReLU after the first five:
     8 -> 64 -> 64 -> 64 -> 64 -> 64 -> 2.
@@ -38,10 +43,13 @@ def bf16(x: np.ndarray) -> np.ndarray:
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
-def features(height: int, t_reduced: float, g: float, form: int, mean_reduced: float) -> np.ndarray:
+def features(height: int, t_reduced: float, g: float, form: int, mean_reduced: float,
+             lever_height: float) -> np.ndarray:
     """Input channels (8, H) of one column."""
     H = int(height)
-    s = (np.arange(H) + 0.5) / H
+    y = np.arange(H) + 0.5
+    s = y / H
+    d = y - lever_height
     x = np.zeros((8, H))
     x[0] = s - 0.5
     x[1] = t_reduced - 0.8
@@ -49,6 +57,8 @@ def features(height: int, t_reduced: float, g: float, form: int, mean_reduced: f
     x[3] = form - 1.5
     x[4] = mean_reduced - 1.3
     x[5] = H / 2048.0 - 0.5
+    x[6] = np.clip(d / 32.0, -4.0, 4.0) / 4.0
+    x[7] = np.clip(d / 4.0, -4.0, 4.0) / 4.0
     return x
 
 

@@ -9,7 +9,7 @@ from oracle import net_ref as N
 
 
 def _batch(seed):
-    cols = [(9, 0.8, 3e-5, 1, 1.2), (14, 0.9, 1e-6, 2, 0.7), (6, 0.72, 1e-4, 1, 2.1)]
+    cols = [(9, 0.8, 3e-5, 1, 1.2, 4.2), (14, 0.9, 1e-6, 2, 0.7, 3.0), (6, 0.72, 1e-4, 1, 2.1, 5.5)]
     xs = [N.features(*c) for c in cols]
     rng = W.uniform_pm1(seed, sum(2 * c[0] for c in cols))
     tg, k = [], 0
@@ -66,3 +66,13 @@ def test_adam_with_a_constant_gradient_moves_by_lr_every_step():
     for t in range(1, 6):
         theta, m, v = N.adam_step(theta, g, m, v, t, lr)
         np.testing.assert_allclose(theta, -t * lr * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0)
+
+
+def test_interface_channels():
+    """The two interface channels are zero at the lever-rule height, odd
+    about it, and saturate at +-1 at 128 and 16 nodes away."""
+    x = N.features(300, 0.8, 1e-5, 1, 1.3, 100.0)
+    y = np.arange(300) + 0.5
+    assert np.all(np.sign(x[6]) == np.sign(y - 100.0)) and np.all(np.sign(x[7]) == np.sign(y - 100.0))
+    assert abs(x[6][99]) < 1 / 128 and abs(x[7][100]) == 0.5 / 16
+    assert x[6][0] == -99.5 / 128 and x[6][-1] == 1.0 and x[7][0] == -1.0 and x[7][-1] == 1.0
