@@ -224,7 +224,7 @@ MFMA_BF16_PEAK_TFLOPS = 2500.0
 
 
 def train_throughput(T, torch, WS, rho_c, T_c, nc, H=1024, n_steps=50):
-    tcols = [(H, 1 + k % 2, 0.7 + 0.2 * k / nc, 10 ** (-6 + 2 * k / nc), 0.5 + 2 * k / nc) for k in range(nc)]
+    tcols = [(H, 1 + k % 2, 0.7 + 0.2 * k / nc, 10 ** (-6 + 2 * k / nc), 0.5 + 2 * k / nc, H / 2) for k in range(nc)]
     s = (np.arange(H) + 0.5) / H
     rho = np.concatenate([rho_c * (c[4] + 0.5 * np.tanh((0.5 - s) * 30)) for c in tcols])
     Tt = np.concatenate([np.full(H, T_c * c[2]) for c in tcols])
@@ -280,6 +280,66 @@ def run_warmstart(T, torch, evaluate=True):
     return summary
 
 
+def long_runs(T, torch, rho0, T0):
+    """The step counts the workloads are specified with, once: D2Q9 1024x2048
+    for 10^5 steps and D3Q19 256^3 for 5*10^4 steps, FP32-deviation and FP64
+    populations from the same inputs; reports the end state and the FP32
+    error against FP64.  Not timed."""
+    out = {}
+
+    def run(p, r0, t0, steps, label):
+        lat = T.Lattice(p)
+        lat.set_state(r0, t0)
+        done = 0
+        while done < steps:
+            k = min(10000, steps - done)
+            lat.step_async(k)
+            done += k
+            d = lat.diagnostics()
+            print(f"# long {label}: {done} steps, flags {d['flags']}", file=sys.stderr, flush=True)
+            if d["flags"]:
+                break  # the method failed (first_bad_step says where); stop here
+        rho = lat.read("rho")
+        lat.close()
+        return d, rho
+
+    def rel_err(a, b, d1, d2):
+        if d1["flags"] or d2["flags"]:
+            return None
+        return float(np.abs(a - b).max() / np.abs(b).max())
+
+    for form in (2, 1):
+        res = {}
+        for prec in (0, 1):
+            p = T.make_params(T.D2Q9, nx=NX, ny=NY, walls=True, precision=prec, gravity_form=form, g=1e-5,
+                              rho_ref=float(rho0.mean()))
+            res[prec] = run(p, rho0, T0, 100000, f"d2q9 form{form} {'fp64' if prec == 0 else 'fp32dev'}")
+        (d64, r64), (d32, r32) = res[0], res[1]
+        out[f"d2q9_1024x2048_form{form}_g1e-05_100000_steps"] = {
+            "fp64": {"flags": d64["flags"], "first_bad_step": d64["first_bad_step"], "max_u": d64["max_u"],
+                     "mass_rel_change": float(d64["mass"] / rho0.sum() - 1.0)},
+            "fp32dev": {"flags": d32["flags"], "first_bad_step": d32["first_bad_step"], "max_u": d32["max_u"],
+                        "rho_rel_err_vs_fp64": rel_err(r32, r64, d32, d64)}}
+    rho_c, T_c, _ = T.eos_critical()
+    rv, rl, _ = T.eos_coexistence(0.8 * T_c)
+    n = D3_N
+    r3 = W.layered_density((n, n, n), 64, rl, rv, 1e-3, seed=4)
+    t3 = W.wall_temperature_field((n, n, n), 0.8 * T_c, 0.9 * T_c, 0.8 * T_c)
+    for form in (2, 1):
+        res = {}
+        for prec in (1, 0):
+            p = T.make_params(T.D3Q19, nx=n, ny=n, nz=n, walls=True, precision=prec, gravity_form=form,
+                              g=1e-5, rho_ref=float(r3.mean()))
+            res[prec] = run(p, r3, t3, 50000, f"d3q19 form{form} {'fp64' if prec == 0 else 'fp32dev'}")
+        (d64, r64), (d32, r32) = res[0], res[1]
+        out[f"d3q19_256cubed_form{form}_g1e-05_50000_steps"] = {
+            "fp64": {"flags": d64["flags"], "first_bad_step": d64["first_bad_step"], "max_u": d64["max_u"],
+                     "mass_rel_change": float(d64["mass"] / r3.sum() - 1.0)},
+            "fp32dev": {"flags": d32["flags"], "first_bad_step": d32["first_bad_step"], "max_u": d32["max_u"],
+                        "rho_rel_err_vs_fp64": rel_err(r32, r64, d32, d64)}}
+    return out
+
+
 def copy_bandwidth(torch) -> float:
     """Bytes read + written per second by a plain 1 GiB device-to-device copy
     (torch's copy kernel), the practical streaming rate of this HBM."""
@@ -324,6 +384,8 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--long", action="store_true",
+                    help="only the long untimed runs (10^5 D2Q9 and 5*10^4 D3Q19 steps), as a JSON line")
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the plain per-column comparison of the batched sweep")
     ap.add_argument("--variants", default="all", help="all | headline | fp32dev | d3q19 | batched | warmstart | net")
@@ -356,6 +418,9 @@ def main():
     rho_c, T_c, _ = T.eos_critical()
     rho0, T0 = make_inputs(T)
     print(f"# inputs ready: {NX}x{NY}, mean rho {rho0.mean():.6f}", file=sys.stderr, flush=True)
+    if args.long:
+        print(json.dumps({"long_runs": long_runs(T, torch, rho0, T0)}), flush=True)
+        return
 
     variants = [(0, 2, 1e-5)]
     if args.variants == "fp32dev":

@@ -280,7 +280,8 @@ const char *tplbm_batch_last_error(const tplbm_batch *b);
  * along the column, zero padding at the two ends of each column (columns in
  * a batch never see each other), ReLU after the first five.  Input channels
  * at node y of a column of height H: (y + 1/2)/H - 1/2, T/T_c - 0.8,
- * log10 g + 5, gravity_form - 3/2, <rho>/rho_c - 1.3, H/2048 - 1/2, 0, 0.
+ * log10 g + 5, gravity_form - 3/2, <rho>/rho_c - 1.3, H/2048 - 1/2, and
+ * clip(d/32, -4, 4)/4, clip(d/4, -4, 4)/4 with d = y + 1/2 - lever_height.
  * Output channels: rho/rho_c - <rho>/rho_c and T/T_c - T_wall/T_c.  Loss:
  * mean over nodes and both channels of the squared error.
  *
@@ -299,6 +300,9 @@ typedef struct tplbm_net_column {
     double t_reduced;      /* T / T_c of the isothermal column (also its wall value) */
     double g;              /* gravity magnitude, > 0 */
     double mean_reduced;   /* <rho> / rho_c, the column's mean density */
+    double lever_height;   /* H (<rho> - rho_v)/(rho_l - rho_v) in nodes, with the
+                              Maxwell coexistence densities at T (tplbm_eos_coexistence):
+                              where a flat interface would sit without gravity */
 } tplbm_net_column;
 
 typedef struct tplbm_net_config {

@@ -349,7 +349,7 @@ class Batch:
 class NetColumn(ctypes.Structure):
     _fields_ = [("height", ctypes.c_int32), ("gravity_form", ctypes.c_int32),
                 ("t_reduced", ctypes.c_double), ("g", ctypes.c_double),
-                ("mean_reduced", ctypes.c_double)]
+                ("mean_reduced", ctypes.c_double), ("lever_height", ctypes.c_double)]
 
 
 class NetConfig(ctypes.Structure):
@@ -391,11 +391,12 @@ def _fp(a):
 
 def net_columns(columns):
     """ctypes array of network column descriptions from (height, form,
-    t_reduced, g, mean_reduced) tuples."""
+    t_reduced, g, mean_reduced, lever_height) tuples."""
     arr = (NetColumn * len(columns))()
-    for k, (h, form, t, g, m) in enumerate(columns):
+    for k, (h, form, t, g, m, hl) in enumerate(columns):
         arr[k].height, arr[k].gravity_form = int(h), int(form)
         arr[k].t_reduced, arr[k].g, arr[k].mean_reduced = float(t), float(g), float(m)
+        arr[k].lever_height = float(hl)
     return arr
 
 

@@ -41,7 +41,7 @@ __device__ __forceinline__ double rcp_pos(double x)
 // root (Goldschmidt-style); zero maps to zero, negative or NaN to NaN.
 __device__ __forceinline__ double sqrt_pos(double a)
 {
-    if (a == 0.0) return 0.0;
+    if (!(a > 0.0)) return a == 0.0 ? 0.0 : __builtin_nan("");
     const double y = __builtin_amdgcn_rsq(a);
     double g = a * y, h = 0.5 * y;
     const double r = fma(-g, h, 0.5);

@@ -287,7 +287,9 @@ __global__ void prep_weights(const float *__restrict__ Wf, int cout, int cin, in
     }
 }
 
-// Input features (8 channels, bf16) of one column per block, its trailing
+// Input features (8 channels, bf16: position, T/T_c, log10 g, form, <rho>,
+// height, and the distance to the lever-rule interface at two widths) of one
+// column per block, its trailing
 // guard positions (block 0 also the two leading ones) and, with a dataset,
 // the targets (rho/rho_c - <rho>/rho_c, T/T_c - T_wall/T_c).
 __global__ __launch_bounds__(256) void prep(const NetCol *__restrict__ cols, const NetEntry *__restrict__ ent,
@@ -305,8 +307,12 @@ __global__ __launch_bounds__(256) void prep(const NetCol *__restrict__ cols, con
     const uint32_t k5 = f2bf((float)((double)H / 2048.0 - 0.5));
     for (int y = threadIdx.x; y < H; y += blockDim.x) {
         const int64_t p = e.pos + y;
-        const uint32_t k0 = f2bf((float)(((double)y + 0.5) / (double)H - 0.5));
-        *reinterpret_cast<uint4 *>(x + 8 * p) = make_uint4(k0 | (k1 << 16), k2 | (k3 << 16), k4 | (k5 << 16), 0u);
+        const double yc = (double)y + 0.5, d = yc - c.lever_height;
+        const uint32_t k0 = f2bf((float)(yc / (double)H - 0.5));
+        const uint32_t k6 = f2bf((float)(fmin(fmax(d / 32.0, -4.0), 4.0) / 4.0));
+        const uint32_t k7 = f2bf((float)(fmin(fmax(d / 4.0, -4.0), 4.0) / 4.0));
+        *reinterpret_cast<uint4 *>(x + 8 * p) =
+            make_uint4(k0 | (k1 << 16), k2 | (k3 << 16), k4 | (k5 << 16), k6 | (k7 << 16));
         guard[p] = 0;
         if (tgt) {
             tgt[2 * p] = (float)(rho[c.offset + y] / rho_c - c.mean_reduced);

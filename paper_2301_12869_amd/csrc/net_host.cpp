@@ -138,8 +138,9 @@ int check_column(tplbm_net *n, const tplbm_net_column &c, int k)
         return nfail(n, TPLBM_ESHAPE, "column %d: height %d outside 3..%d", k, c.height, kMaxHeight);
     if (c.gravity_form != 1 && c.gravity_form != 2)
         return nfail(n, TPLBM_EINVAL, "column %d: gravity_form must be 1 or 2", k);
-    if (!(c.g > 0) || !std::isfinite(c.g) || !std::isfinite(c.t_reduced) || !std::isfinite(c.mean_reduced))
-        return nfail(n, TPLBM_EINVAL, "column %d: need finite t_reduced, mean_reduced and g > 0", k);
+    if (!(c.g > 0) || !std::isfinite(c.g) || !std::isfinite(c.t_reduced) || !std::isfinite(c.mean_reduced) ||
+        !std::isfinite(c.lever_height))
+        return nfail(n, TPLBM_EINVAL, "column %d: need finite t_reduced, mean_reduced, lever_height and g > 0", k);
     return TPLBM_OK;
 }
 
@@ -151,6 +152,7 @@ NetCol to_dev(const tplbm_net_column &c, int64_t offset)
     d.t_reduced = c.t_reduced;
     d.g = c.g;
     d.mean_reduced = c.mean_reduced;
+    d.lever_height = c.lever_height;
     d.offset = offset;
     return d;
 }

@@ -19,6 +19,7 @@ struct NetCol {
     double t_reduced;   // T / T_c
     double g;           // gravity magnitude
     double mean_reduced;  // <rho> / rho_c
+    double lever_height;  // lever-rule interface height (nodes)
     int64_t offset;     // first node in the dataset arrays (training columns)
 };
 

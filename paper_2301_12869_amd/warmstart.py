@@ -48,11 +48,12 @@ class Columns:
         self.form = d["form"].astype(np.int64)
         self.g = d["g"]
         self.t_reduced = d["t_reduced"]
-        rho, T = [], []
+        rho, T, rvl = [], [], []
         for k in range(n):
             H = int(self.height[k])
             Tk = self.t_reduced[k] * self.T_c
             rv, rl, _ = eos_coexistence(Tk)
+            rvl.append((rv, rl))
             rho.append(W.column_initial_density(H, rv + d["fill"][k] * (rl - rv), rl, rv, NOISE,
                                                 int(d["seed"][k])))
             T.append(np.full(H, Tk))
@@ -60,7 +61,11 @@ class Columns:
         self.T0 = np.concatenate(T)
         self.offsets = np.concatenate([[0], np.cumsum(self.height)])
         # the exact mean of each start: the mass the steady state must carry
-        self.mean_reduced = np.add.reduceat(self.rho0, self.offsets[:-1]) / self.height / self.rho_c
+        mean = np.add.reduceat(self.rho0, self.offsets[:-1]) / self.height
+        self.mean_reduced = mean / self.rho_c
+        # where a flat interface would sit without gravity (lever rule)
+        rvl = np.array(rvl)
+        self.lever_height = self.height * (mean - rvl[:, 0]) / (rvl[:, 1] - rvl[:, 0])
 
     def solver_columns(self, idx=None):
         idx = range(self.n) if idx is None else idx
@@ -69,7 +74,7 @@ class Columns:
     def net_columns(self, idx=None):
         idx = range(self.n) if idx is None else idx
         return [(int(self.height[k]), int(self.form[k]), float(self.t_reduced[k]), float(self.g[k]),
-                 float(self.mean_reduced[k])) for k in idx]
+                 float(self.mean_reduced[k]), float(self.lever_height[k])) for k in idx]
 
     def take(self, arr, idx):
         return np.concatenate([arr[self.offsets[k]:self.offsets[k + 1]] for k in idx])

@@ -205,6 +205,28 @@ def test_unphysical_state_is_reported(T, orc, crit):
     lat.close()
 
 
+def test_undefined_pseudopotential_is_flagged_like_the_oracle(T, orc, crit):
+    """A node hot enough that p_EOS > rho/3 (the radicand of psi negative,
+    here T = 0.5 at rho = 0.02) is reported as an undefined pseudopotential
+    at level 0, as the oracle reports it."""
+    _log("case undefined psi")
+    _, T_c, _ = crit
+    nx, ny = 8, 16
+    rho0 = np.full((ny, nx), 0.02)
+    T0 = np.full((ny, nx), 0.8 * T_c)
+    T0[7, 4] = 0.5
+    P = orc.make_params("D2Q9", nx=nx, ny=ny, walls=True, g=1e-5)
+    f = orc.init_rest(P, rho0.ravel())
+    d_orc = orc.step(P, f, T0.ravel().copy(), 1)
+    assert d_orc["flags"] & 8
+    lat = T.Lattice(T.make_params(T.D2Q9, nx=nx, ny=ny, g=1e-5))
+    lat.set_state(rho0, T0)
+    lat.step_async(1)
+    d = lat.diagnostics()
+    lat.close()
+    assert d["flags"] & 8 and d["first_bad_step"] == 0, d  # 8: psi undefined
+
+
 def test_full_size_1024x2048_against_the_oracle(T, orc, crit):
     """The benchmark workload at its real size and launch configuration
     (1024 x 2048, heated bottom wall, both gravity forms): a few steps, every

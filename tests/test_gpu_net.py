@@ -47,16 +47,16 @@ def _theta(seed):
     return th.astype(np.float32)
 
 
-# (height, form, t_reduced, g, mean_reduced): a 3-node column, ragged
-# heights across the 32-position wave tiles and 128-position blocks, and
-# the tallest column the sweep holds
-COLS = [(37, 1, 0.8, 3e-5, 1.2), (3, 2, 0.9, 1e-6, 0.7), (130, 2, 0.72, 1e-4, 2.1),
-        (301, 1, 0.65, 7e-6, 1.6), (64, 2, 0.95, 2e-5, 1.0), (2048, 1, 0.85, 4e-6, 1.33)]
+# (height, form, t_reduced, g, mean_reduced, lever_height): a 3-node column,
+# ragged heights across the 32-position wave tiles and 128-position blocks,
+# and the tallest column the sweep holds
+COLS = [(37, 1, 0.8, 3e-5, 1.2, 15.3), (3, 2, 0.9, 1e-6, 0.7, 1.0), (130, 2, 0.72, 1e-4, 2.1, 77.7),
+        (301, 1, 0.65, 7e-6, 1.6, 120.25), (64, 2, 0.95, 2e-5, 1.0, 40.0), (2048, 1, 0.85, 4e-6, 1.33, 1003.6)]
 
 
 def _features(c):
-    h, form, t, g, m = c
-    return N.features(h, t, g, form, m)
+    h, form, t, g, m, hl = c
+    return N.features(h, t, g, form, m, hl)
 
 
 def _rel(a, b):
@@ -119,7 +119,7 @@ def _dataset(consts, cols, seed):
     k = 0
     rng = W.uniform_pm1(seed, sum(2 * c[0] for c in cols))
     for c in cols:
-        h, form, t, g, m = c
+        h, form, t, g, m, hl = c
         tgt = 0.3 * rng[k:k + 2 * h].reshape(2, h)
         k += 2 * h
         tg.append(tgt)
@@ -159,7 +159,7 @@ def test_gradient_matches_the_bf16_reference(T, consts):
 
 
 def test_adam_step_matches_the_reference_and_training_lowers_the_loss(T, consts):
-    cols = [(96, 1, 0.8, 1e-5, 1.3), (200, 2, 0.7, 5e-5, 1.1), (57, 1, 0.9, 2e-6, 1.5)]
+    cols = [(96, 1, 0.8, 1e-5, 1.3, 40.0), (200, 2, 0.7, 5e-5, 1.1, 60.5), (57, 1, 0.9, 2e-6, 1.5, 30.0)]
     theta = _theta(9)
     tg, rho, TT = _dataset(consts, cols, 10)
     n = sum(c[0] for c in cols)
@@ -176,7 +176,7 @@ def test_adam_step_matches_the_reference_and_training_lowers_the_loss(T, consts)
     # a smooth target the network can fit: loss falls by 10x within 300 steps
     rho_c, T_c = consts
     rho_s, T_s = [], []
-    for (h, form, t, gg, m) in cols:
+    for (h, form, t, gg, m, hl) in cols:
         s = (np.arange(h) + 0.5) / h
         rho_s.append(rho_c * (m + 0.5 * np.tanh((0.4 - s) * 20)))
         T_s.append(np.full(h, T_c * t))
@@ -198,7 +198,7 @@ def test_predict_keeps_the_mean_density_and_the_wall_temperatures(T, consts):
     raw = net.forward(COLS)
     rho, TT = net.predict(COLS)
     k = 0
-    for (h, form, t, g, m) in COLS:
+    for (h, form, t, g, m, hl) in COLS:
         r, tt, o = rho[k:k + h], TT[k:k + h], raw[k:k + h].astype(np.float64)
         k += h
         assert r.mean() == pytest.approx(m * rho_c, rel=1e-13)
@@ -213,14 +213,14 @@ def test_predict_keeps_the_mean_density_and_the_wall_temperatures(T, consts):
 def test_bad_arguments_are_rejected(T, consts):
     net = _net(T, consts, max_cols=2, max_nodes=100)
     with pytest.raises(T.TplbmError):
-        net.forward([(10, 1, 0.8, 1e-5, 1.3)])  # parameters not set yet
+        net.forward([(10, 1, 0.8, 1e-5, 1.3, 5.0)])  # parameters not set yet
     net.set_params(_theta(1))
     with pytest.raises(T.TplbmError):
-        net.forward([(60, 1, 0.8, 1e-5, 1.3), (60, 1, 0.8, 1e-5, 1.3)])  # 120 nodes > 100
+        net.forward([(60, 1, 0.8, 1e-5, 1.3, 5.0), (60, 1, 0.8, 1e-5, 1.3, 5.0)])  # 120 nodes > 100
     with pytest.raises(T.TplbmError):
-        net.forward([(10, 3, 0.8, 1e-5, 1.3)])  # gravity form
+        net.forward([(10, 3, 0.8, 1e-5, 1.3, 5.0)])  # gravity form
     with pytest.raises(T.TplbmError):
-        net.forward([(10, 1, 0.8, -1e-5, 1.3)])  # g <= 0
+        net.forward([(10, 1, 0.8, -1e-5, 1.3, 5.0)])  # g <= 0
     with pytest.raises(T.TplbmError):
         net.train_step([0], 1e-3)  # no dataset
     bad = _theta(1)

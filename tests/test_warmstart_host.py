@@ -32,3 +32,16 @@ def test_column_draw_and_parameters():
     assert th.dtype == np.float32 and th.size == 85442
     # biases start at zero, weights inside the He-uniform bound of layer 0
     assert np.all(th[2560:2624] == 0) and np.abs(th[:2560]).max() <= np.sqrt(6 / 40)
+
+
+def test_lever_rule_height():
+    """The lever-rule height puts the mean density's mass into a flat
+    liquid-below-vapour profile: H <rho> = h rho_l + (H - h) rho_v."""
+    from paper_2301_12869_amd import eos_coexistence
+
+    c = WS.Columns(16, 9)
+    for k in range(16):
+        H, h = c.height[k], c.lever_height[k]
+        rv, rl, _ = eos_coexistence(c.t_reduced[k] * c.T_c)
+        assert 0.0 <= h <= H
+        assert abs(h * rl + (H - h) * rv - H * c.mean_reduced[k] * c.rho_c) < 1e-12 * H
