@@ -394,7 +394,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the lattice update "
-              "is not sharded across GPUs in this build", file=sys.stderr)
+              "is not sharded across GPUs", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -270,7 +270,7 @@ const char *tplbm_batch_last_error(const tplbm_batch *b);
  *
  * A 1-D convolutional network maps a column's parameters to its steady
  * density and temperature profiles; its prediction seeds tplbm_batch_* runs,
- * which remain the judge of the steady state.  The paper starts its runs
+ * which decide the steady state.  The paper starts its runs
  * from liquid below vapour (Sec. V, example of phase formation) and notes
  * that a run may instead start from the theoretical profile (Sec. IV B);
  * the network is a learned stand-in for that profile, trained on steady

@@ -9,7 +9,7 @@ The pipeline, all on the GPU through the library's C ABI:
      BF16 matrix-core forward/backward, Adam on FP32 master weights);
   3. seed held-out columns with the network's profiles (mean density
      renormalised, wall temperatures kept) and let the batched solver run
-     them to steady state; the solver stays the judge of the steady state.
+     them to steady state; the solver decides what the steady state is.
 
 Run as ``python -m paper_2301_12869_amd.warmstart --out DIR`` to generate
 data, train and evaluate; the parameters are written to DIR/warmstart_params.npy.

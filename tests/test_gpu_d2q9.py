@@ -42,7 +42,7 @@ def _rel(a, b):
 
 def _rel_p(a, b, rho):
     """Pressures are differences of terms of size a rho^2 (about 60 times p
-    itself near coexistence), so their rounding is judged on that scale."""
+    itself near coexistence), so their rounding is compared on that scale."""
     return np.abs(a - b).max() / (0.5 * np.abs(rho).max() ** 2)
 
 
