@@ -43,54 +43,71 @@ __device__ __forceinline__ int acc_row(int r, int lane) { return 8 * (r >> 2) + 
 // MODE 0: hidden forward layer: out_bf16 = bf16(relu(acc + bias))
 // MODE 1: output layer:         out_f32[p][o] = acc + bias for o < NOUT
 // MODE 2: input gradient:       g = acc * (mask[p][o] > 0); out_f32 = g, out_bf16 = bf16(g)
-// A block covers 128 positions and all 32 NTILES output channels; each of
-// its 4 NTILES waves owns 32 positions and one 32-channel tile (the waves of
-// a position group read the same activations, which L1 serves).
+// Persistent blocks of 4 waves: the layer's BF16 weights are staged in LDS
+// once per block (rows padded by 4 elements against bank conflicts), then
+// the block walks 128-position tiles; each wave owns 32 positions and all
+// 32 NTILES output channels, so one activation fragment feeds NTILES MFMAs.
 template <int CIN, int NTILES, int MODE, int NOUT>
-__global__ __launch_bounds__(256 * NTILES) void conv_mfma(const uint16_t *__restrict__ in,
-                                                          const uint16_t *__restrict__ W,
-                                                          const float *__restrict__ bias, int P,
-                                                          const uint8_t *__restrict__ guard,
-                                                          const uint16_t *__restrict__ mask,
-                                                          float *__restrict__ out_f32,
-                                                          uint16_t *__restrict__ out_bf16)
+__global__ __launch_bounds__(256) void conv_mfma(const uint16_t *__restrict__ in, const uint16_t *__restrict__ W,
+                                                 const float *__restrict__ bias, int P,
+                                                 const uint8_t *__restrict__ guard,
+                                                 const uint16_t *__restrict__ mask, float *__restrict__ out_f32,
+                                                 uint16_t *__restrict__ out_bf16)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int nt = wave % NTILES;
-    const int p0 = (blockIdx.x * 4 + wave / NTILES) * 32;
-    if (p0 >= P) return;
-    const int i = lane & 31, kq = lane >> 5;
-    const int o = 32 * nt + i;
-    f32x16 acc;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-#pragma unroll
-    for (int t = 0; t < 5; ++t) {
-        int q = p0 + i + t - 2;
-        q = q < 0 ? 0 : (q >= P ? P - 1 : q);  // both ends are guard positions (zero)
-#pragma unroll
-        for (int c0 = 0; c0 < CIN; c0 += 8) {
-            const bf16x4 a = *reinterpret_cast<const bf16x4 *>(in + (size_t)q * CIN + c0 + 4 * kq);
-            const bf16x4 b = *reinterpret_cast<const bf16x4 *>(W + ((size_t)o * 5 + t) * CIN + c0 + 4 * kq);
-            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
-        }
-    }
     constexpr int COUT = 32 * NTILES;
+    constexpr int ROW = 5 * CIN;       // weights of one output channel
+    constexpr int RS = ROW + 4;        // padded LDS row
+    __shared__ uint16_t sW[COUT * RS];
+    for (int e = threadIdx.x; e < COUT * ROW / 4; e += 256) {
+        const int o = (4 * e) / ROW, k = (4 * e) % ROW;
+        *reinterpret_cast<uint2 *>(&sW[o * RS + k]) = *reinterpret_cast<const uint2 *>(W + 4 * (size_t)e);
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = lane & 31, kq = lane >> 5;
+    for (int tile = blockIdx.x; tile * 128 < P; tile += gridDim.x) {
+        const int p0 = tile * 128 + wave * 32;
+        if (p0 >= P) continue;
+        f32x16 acc[NTILES];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int p = p0 + acc_row(r, lane);
-        if (p >= P) continue;
-        const bool g = guard[p] != 0;
-        float v = acc[r];
-        if (MODE == 0) {
-            v = g ? 0.0f : fmaxf(v + bias[o], 0.0f);
-            out_bf16[(size_t)p * COUT + o] = f2bf(v);
-        } else if (MODE == 1) {
-            if (o < NOUT) out_f32[(size_t)p * NOUT + o] = g ? 0.0f : v + bias[o];
-        } else {
-            v = (g || !(bf2f(mask[(size_t)p * COUT + o]) > 0.0f)) ? 0.0f : v;
-            out_f32[(size_t)p * COUT + o] = v;
-            out_bf16[(size_t)p * COUT + o] = f2bf(v);
+        for (int nt = 0; nt < NTILES; ++nt)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[nt][r] = 0.0f;
+#pragma unroll
+        for (int t = 0; t < 5; ++t) {
+            int q = p0 + i + t - 2;
+            q = q < 0 ? 0 : (q >= P ? P - 1 : q);  // both ends are guard positions (zero)
+#pragma unroll
+            for (int c0 = 0; c0 < CIN; c0 += 8) {
+                const bf16x4 a = *reinterpret_cast<const bf16x4 *>(in + (size_t)q * CIN + c0 + 4 * kq);
+#pragma unroll
+                for (int nt = 0; nt < NTILES; ++nt) {
+                    const bf16x4 b = *reinterpret_cast<const bf16x4 *>(&sW[(32 * nt + i) * RS + t * CIN + c0 + 4 * kq]);
+                    acc[nt] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc[nt], 0, 0, 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int nt = 0; nt < NTILES; ++nt) {
+            const int o = 32 * nt + i;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int p = p0 + acc_row(r, lane);
+                if (p >= P) continue;
+                const bool g = guard[p] != 0;
+                float v = acc[nt][r];
+                if (MODE == 0) {
+                    v = g ? 0.0f : fmaxf(v + bias[o], 0.0f);
+                    out_bf16[(size_t)p * COUT + o] = f2bf(v);
+                } else if (MODE == 1) {
+                    if (o < NOUT) out_f32[(size_t)p * NOUT + o] = g ? 0.0f : v + bias[o];
+                } else {
+                    v = (g || !(bf2f(mask[(size_t)p * COUT + o]) > 0.0f)) ? 0.0f : v;
+                    out_f32[(size_t)p * COUT + o] = v;
+                    out_bf16[(size_t)p * COUT + o] = f2bf(v);
+                }
+            }
         }
     }
 }
@@ -207,13 +224,24 @@ __global__ void reduce_partials(const float *__restrict__ src, int nb, int strid
         dst[e] = ordered_sum(src + e, nb, (size_t)stride);
 }
 
-// bias-gradient partials: per-channel sums of dZ over position slices
-__global__ void db_partial(const float *__restrict__ dZ, int ZS, int P, int span, float *__restrict__ partial)
+// bias-gradient partials: per-channel sums of dZ over position slices.  The
+// 256 threads form 256 / ZS groups; group k sums positions k, k + groups, ...
+// of the slice, then the group sums are added in group order (deterministic).
+__global__ __launch_bounds__(256) void db_partial(const float *__restrict__ dZ, int ZS, int P, int span,
+                                                  float *__restrict__ partial)
 {
-    const int o = threadIdx.x;
-    if (o >= ZS) return;
+    __shared__ float red[256];
+    const int groups = 256 / ZS;
+    const int o = threadIdx.x % ZS, k = threadIdx.x / ZS;
     const int pbeg = blockIdx.x * span, pend = min(P, pbeg + span);
-    partial[(size_t)blockIdx.x * ZS + o] = ordered_sum(dZ + (size_t)pbeg * ZS + o, pend - pbeg, (size_t)ZS);
+    const int cnt = pend - pbeg - k > 0 ? (pend - pbeg - k + groups - 1) / groups : 0;
+    red[threadIdx.x] = ordered_sum(dZ + (size_t)(pbeg + k) * ZS + o, cnt, (size_t)groups * ZS);
+    __syncthreads();
+    if (threadIdx.x < ZS) {
+        float t = 0.0f;
+        for (int g = 0; g < groups; ++g) t += red[g * ZS + o];
+        partial[(size_t)blockIdx.x * ZS + o] = t;
+    }
 }
 
 // squared-error partials and the output-layer gradient dZ (8 channels per
@@ -385,7 +413,12 @@ __global__ void mfma_probe(const uint16_t *__restrict__ a, const uint16_t *__res
     for (int r = 0; r < 16; ++r) d[lane * 16 + r] = acc[r];
 }
 
-unsigned conv_blocks(int64_t P) { return (unsigned)((P + 127) / 128); }
+// persistent convolution grid: one block per 128-position tile, at most 1024
+unsigned conv_blocks(int64_t P)
+{
+    const int64_t t = (P + 127) / 128;
+    return (unsigned)(t < 1024 ? t : 1024);
+}
 
 // slice length (a multiple of 64 positions) and slice count for nblocks
 void slices(int64_t P, int nblocks, int *span, int *nb)
@@ -422,21 +455,21 @@ hipError_t net_raw_out(const NetCol *cols, const NetEntry *entries, int n, const
 hipError_t net_conv_forward(int layer, const uint16_t *in, const uint16_t *W, const float *bias, int64_t P,
                             const uint8_t *guard, uint16_t *out_bf16, float *out_f32, hipStream_t s)
 {
-    const dim3 g(conv_blocks(P)), b2(512), b1(256);
+    const dim3 g(conv_blocks(P)), b(256);
     const int p = (int)P;
     if (layer == 0)
-        hipLaunchKernelGGL((conv_mfma<8, 2, 0, 64>), g, b2, 0, s, in, W, bias, p, guard, nullptr, nullptr, out_bf16);
+        hipLaunchKernelGGL((conv_mfma<8, 2, 0, 64>), g, b, 0, s, in, W, bias, p, guard, nullptr, nullptr, out_bf16);
     else if (layer < 5)
-        hipLaunchKernelGGL((conv_mfma<64, 2, 0, 64>), g, b2, 0, s, in, W, bias, p, guard, nullptr, nullptr, out_bf16);
+        hipLaunchKernelGGL((conv_mfma<64, 2, 0, 64>), g, b, 0, s, in, W, bias, p, guard, nullptr, nullptr, out_bf16);
     else
-        hipLaunchKernelGGL((conv_mfma<64, 1, 1, 2>), g, b1, 0, s, in, W, bias, p, guard, nullptr, out_f32, nullptr);
+        hipLaunchKernelGGL((conv_mfma<64, 1, 1, 2>), g, b, 0, s, in, W, bias, p, guard, nullptr, out_f32, nullptr);
     return hipGetLastError();
 }
 
 hipError_t net_conv_input_grad(int layer, const uint16_t *dZ, const uint16_t *Wg, int64_t P, const uint8_t *guard,
                                const uint16_t *act_in, float *dprev_f32, uint16_t *dprev_bf16, hipStream_t s)
 {
-    const dim3 g(conv_blocks(P)), b(512);
+    const dim3 g(conv_blocks(P)), b(256);
     const int p = (int)P;
     if (layer == 5)
         hipLaunchKernelGGL((conv_mfma<8, 2, 2, 64>), g, b, 0, s, dZ, Wg, nullptr, p, guard, act_in, dprev_f32,
@@ -477,7 +510,7 @@ hipError_t net_bias_grad(int layer, const float *dZ, int64_t P, int nblocks, flo
     int span, nb;
     slices(P, nblocks, &span, &nb);
     const int zs = layer == 5 ? 8 : 64;
-    hipLaunchKernelGGL(db_partial, dim3(nb), dim3(64), 0, s, dZ, zs, (int)P, span, partial);
+    hipLaunchKernelGGL(db_partial, dim3(nb), dim3(256), 0, s, dZ, zs, (int)P, span, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(64), 0, s, partial, nb, zs, kNetCout[layer], db);
