@@ -97,13 +97,23 @@ __global__ __launch_bounds__(NT) void d1q3_batch(BatchArgs a, Phys c)
         int64_t n = 0;
         double mass = 0.0, umax = 0.0;
         unsigned fl_seen = 0u;  // flags of every level below the budget so far
+        // waves whose first node lies beyond the column own no node: they
+        // skip the arithmetic but take part in every barrier (their halo
+        // values are never read: the neighbour that would read them is at or
+        // beyond the top wall)
+        const bool wave_active = wid * 64 * npt < H;
         for (;; ++n) {
+            const bool check = n >= a.max_steps || n % a.check_every == 0;
             // ---- phase A: density, momentum, psi; column mass ----
             double rho[NPT], jy[NPT], psi[NPT], Z[NPT];
             double msum = 0.0;
             unsigned fl = 0u;
 #pragma unroll
             for (int k = 0; k < NPT; ++k) {
+                if (!wave_active) {
+                    rho[k] = jy[k] = psi[k] = Z[k] = 0.0;
+                    continue;
+                }
                 const int y = y0 + k;
                 const bool own = k < npt && y < H;
                 rho[k] = f0[k] + fp[k] + fm[k];
@@ -120,21 +130,31 @@ __global__ __launch_bounds__(NT) void d1q3_batch(BatchArgs a, Phys c)
             }
             hpsi.first[tid] = psi[0];
             hpsi.last[tid] = last_of<NPT>(psi, npt);
-            msum = wave_sum(msum);
-            if (lane == 0) red_mass[wid] = msum;
-            __syncthreads();
+            // the column mass: every step for gravity form 2 (its mean enters
+            // the force), otherwise only at the check levels (it is reported)
             double tot = 0.0;
+            if (form2 || check) {
+                msum = wave_active ? wave_sum(msum) : 0.0;
+                if (lane == 0) red_mass[wid] = msum;
+            }
+            __syncthreads();
+            if (form2 || check) {
 #pragma unroll
-            for (int w = 0; w < NW; ++w) tot += red_mass[w];
+                for (int w = 0; w < NW; ++w) tot += red_mass[w];
+            }
             const double mean = tot / (double)H;
             const double psiL = tid > 0 ? hpsi.last[tid - 1] : 0.0;
             const double psiR = tid < NT - 1 ? hpsi.first[tid + 1] : 0.0;
 
             // ---- phase B: force, velocity ----
-            double u[NPT], F[NPT], X[NPT];
+            double u[NPT], F[NPT], X[NPT], irho[NPT];
             double u2max = 0.0;
 #pragma unroll
             for (int k = 0; k < NPT; ++k) {
+                if (!wave_active) {
+                    u[k] = F[k] = X[k] = irho[k] = 0.0;
+                    continue;
+                }
                 const int y = y0 + k;
                 const bool own = k < npt && y < H;
                 const bool wall = y == 0 || y == H - 1;
@@ -148,15 +168,16 @@ __global__ __launch_bounds__(NT) void d1q3_batch(BatchArgs a, Phys c)
                 }
                 F[k] = Fi + Fg;
                 X[k] = c.sigma * c.G2 * sv * sv;  // sigma |F_int|^2 / psi^2
-                u[k] = own ? (jy[k] + 0.5 * F[k]) * rcp_pos(rho[k]) : 0.0;
+                irho[k] = own ? rcp_pos(rho[k]) : 0.0;
+                u[k] = own ? (jy[k] + 0.5 * F[k]) * irho[k] : 0.0;
                 if (own) u2max = fmax(u2max, u[k] * u[k]);
             }
             // decisions at the check levels, in the oracle's order: a flag at
             // any level below the budget, then the budget, then the steady test
             if (n < a.max_steps) fl_seen |= fl;
-            if (n >= a.max_steps || n % a.check_every == 0) {
-                const double m2w = wave_max(u2max);
-                const unsigned flw = wave_or(fl_seen);
+            if (check) {
+                const double m2w = wave_active ? wave_max(u2max) : 0.0;
+                const unsigned flw = wave_active ? wave_or(fl_seen) : 0u;
                 if (lane == 0) {
                     red_u[wid] = m2w;
                     red_fl[wid] = flw;
@@ -188,9 +209,13 @@ __global__ __launch_bounds__(NT) void d1q3_batch(BatchArgs a, Phys c)
             const double TR = tid < NT - 1 ? hT.first[tid + 1] : 0.0;
 
             // ---- phase C: first Heun stage ----
-            double k1[NPT], divu[NPT], irho[NPT];
+            double k1[NPT], divu[NPT];
 #pragma unroll
             for (int k = 0; k < NPT; ++k) {
+                if (!wave_active) {
+                    k1[k] = divu[k] = 0.0;
+                    continue;
+                }
                 const int y = y0 + k;
                 const bool own = k < npt && y < H;
                 const bool wall = y == 0 || y == H - 1;
@@ -199,7 +224,6 @@ __global__ __launch_bounds__(NT) void d1q3_batch(BatchArgs a, Phys c)
                 const double Tm = k > 0 ? T[k - 1] : TL;
                 const double Tp = (k + 1 < npt) ? T[(k + 1) % NPT] : TR;
                 divu[k] = 0.5 * (up - um);
-                irho[k] = own ? rcp_pos(rho[k]) : 0.0;
                 k1[k] = (own && !wall) ? energy_rhs_1d(c, Tm, T[k], Tp, u[k], divu[k], irho[k], Z[k]) : 0.0;
             }
             hk.first[tid] = k1[0];
@@ -212,10 +236,14 @@ __global__ __launch_bounds__(NT) void d1q3_batch(BatchArgs a, Phys c)
             double fs0[NPT], fsp[NPT], fsm[NPT], Tn[NPT];
 #pragma unroll
             for (int k = 0; k < NPT; ++k) {
+                Tn[k] = T[k];
+                if (!wave_active) {
+                    fs0[k] = fsp[k] = fsm[k] = 0.0;
+                    continue;
+                }
                 const int y = y0 + k;
                 const bool own = k < npt && y < H;
                 const bool wall = y == 0 || y == H - 1;
-                Tn[k] = T[k];
                 if (own && !wall) {
                     const double Tm = (k > 0 ? T[k - 1] : TL) + (k > 0 ? k1[k - 1] : kL);
                     const double Tp = ((k + 1 < npt) ? T[(k + 1) % NPT] : TR) +
