@@ -203,8 +203,9 @@ static double branch_root(const orc_params *P, double T, double p_target, double
 {
     /* p is increasing on [lo, hi] */
     for (int it = 0; it < 300; ++it) {
-        double mid = 0.5 * (lo + hi);
+        double mid = 0.5 * (lo + hi), lo0 = lo, hi0 = hi;
         if (orc_eos_p(P, mid, T) < p_target) lo = mid; else hi = mid;
+        if (lo == lo0 && hi == hi0) break; /* the bracket can shrink no further */
     }
     return 0.5 * (lo + hi);
 }
@@ -230,7 +231,9 @@ int orc_coexistence(const orc_params *P, double T, double *out3)
         double area = ps * (1.0 / rv - 1.0 / rl)
                       - (cs_int_p_over_rho2(P, rl, T) - cs_int_p_over_rho2(P, rv, T));
         /* area grows with ps; zero area is the coexistence pressure */
+        double lo0 = lo, hi0 = hi;
         if (area > 0) hi = ps; else lo = ps;
+        if (lo == lo0 && hi == hi0) break;
     }
     double ps = 0.5 * (lo + hi);
     out3[0] = branch_root(P, T, ps, 1e-14, sp[0]);
