@@ -53,6 +53,7 @@ extern "C" {
 #define TPLBM_EHIP 4            /* a HIP runtime call failed */
 #define TPLBM_EUNPHYSICAL 5     /* NaN, rho <= 0, eta >= 1 or negative psi radicand seen */
 #define TPLBM_ENOTCONVERGED 6   /* a host solve did not converge */
+#define TPLBM_ENOSOLUTION 7     /* per-column theory status: the configuration cannot exist */
 
 /* ---- enumerations ---- */
 #define TPLBM_D1Q3 1
@@ -181,6 +182,85 @@ int tplbm_eos_coexistence(double a, double b, double R, double T, double *out3);
 /* Spinodal densities at T (local extrema of p_EOS, Sec. V):
  * out2 = {vapour spinodal, liquid spinodal}.  EINVAL at or above T_c. */
 int tplbm_eos_spinodal(double a, double b, double R, double T, double *out2);
+
+/* ======================================================================
+ * Sharp-interface theory of a column (Sec. IV A; its numerical procedure in
+ * the appendix; configurations of Sec. VI).  Host only, FP64.
+ *
+ * At rest the column obeys dp/dy = F_g,y(rho) (Eq. Momentum_Balance_TS) and
+ * its temperature is linear between the walls (Eq. Temp_Profile).  An
+ * interface at height h joins the Maxwell coexistence states of T(h)
+ * (Eq. MaxwellRule); elsewhere the pressure advances by explicit Euler steps
+ * and the density is the inverse EOS (Eq. Inverse_EOS) on the phase's stable
+ * or metastable branch (Eqs. Numerical_Vapor_Region,
+ * Numerical_Liquid_Region).  A branch driven past its spinodal, or a vapour
+ * driven to zero pressure, means the configuration cannot exist.  The
+ * interface height is searched until the mean density is the given one.
+ *
+ * Geometry as in a batch column: nodes y = 0 .. height-1, walls on the first
+ * and last node, T(y) = T_bot + (T_top - T_bot) y / (height - 1), g > 0
+ * pointing to node 0, F = -rho g (form 1) or -(rho - mean_rho) g (form 2).
+ * Discretisation: each node interval is split into `substeps` Euler steps
+ * (the interval holding an interface is split there first, each part into
+ * `substeps`); a V-L-V configuration is integrated as V-L until p - p_sat(T)
+ * changes sign inside the liquid, where a second interface (linearly
+ * interpolated inside that Euler step) starts a vapour at the coexistence
+ * state.  The mean density is the integral of the sharp profile over the node
+ * cells [-1/2, height - 1/2] divided by height (trapezoids over the Euler
+ * steps, plus half a cell at each wall holding the wall value): it equals the
+ * node mean of a smooth profile and is continuous in h.  Search: h is tried
+ * on every node from 0 up; the first pair of neighbouring placements that
+ * both exist and bracket mean_rho is bisected to a width of 1e-12.
+ * A node exactly on an interface takes the lower phase's value.
+ * ====================================================================== */
+
+#define TPLBM_THEORY_LV 0       /* liquid below vapour */
+#define TPLBM_THEORY_VL 1       /* vapour below liquid */
+#define TPLBM_THEORY_VLV 2      /* vapour, liquid, vapour */
+
+/* reasons a configuration cannot exist (tplbm_theory_result.reasons: the OR
+ * over every interface placement the search tried) */
+#define TPLBM_THEORY_NO_LIQUID 1u               /* a liquid passed its spinodal (boiling, cavitation) */
+#define TPLBM_THEORY_NO_VAPOUR 2u               /* a vapour passed its spinodal (condensation) */
+#define TPLBM_THEORY_ZERO_PRESSURE 4u           /* a vapour's pressure fell to zero */
+#define TPLBM_THEORY_SUPERCRITICAL_INTERFACE 8u /* interface tried where T >= T_c */
+#define TPLBM_THEORY_NO_SECOND_INTERFACE 16u    /* V-L-V: the liquid never met p_sat */
+#define TPLBM_THEORY_NO_MATCH 32u               /* no two neighbouring placements bracket mean_rho */
+#define TPLBM_THEORY_BROKEN_BRACKET 64u         /* a placement inside the bracket cannot exist */
+#define TPLBM_THEORY_SOLVE_FAILED 128u          /* a spinodal or coexistence solve failed (T near T_c) */
+
+typedef struct tplbm_theory_column {
+    int32_t height;        /* nodes including both wall nodes, 3 .. 2^24 */
+    int32_t gravity_form;  /* 1 or 2 */
+    int32_t config;        /* TPLBM_THEORY_LV, _VL or _VLV */
+    int32_t substeps;      /* Euler steps per node interval, 1 .. 4096 */
+    double T_bot, T_top;   /* absolute wall temperatures (nodes 0 and height-1), > 0 */
+    double g;              /* signed; > 0 points to node 0 */
+    double mean_rho;       /* mean density, 0 < mean_rho < 4/b */
+} tplbm_theory_column;
+
+typedef struct tplbm_theory_result {
+    int32_t status;        /* TPLBM_OK or TPLBM_ENOSOLUTION */
+    int32_t n_interfaces;  /* 1 (L-V, V-L) or 2 (V-L-V); 0 without a solution */
+    uint32_t reasons;      /* TPLBM_THEORY_* bits when status is TPLBM_ENOSOLUTION */
+    uint32_t pad;
+    double interface[2];   /* interface heights (node units from node 0); NaN if absent */
+    double mean_rho;       /* mean density of the returned profile */
+} tplbm_theory_result;
+
+/* Solve ncols independent columns with the EOS constants a, b, R on up to
+ * nthreads host threads (<= 0: one per hardware thread).  rho (and p, which
+ * may be NULL) receive the node densities and pressures, column after column
+ * (column k at sum_{j<k} height_j); a column without a solution is filled
+ * with NaN.  out[k] receives each column's status.  Returns TPLBM_OK once
+ * every column has been tried, whatever their statuses; EINVAL or ESHAPE (and
+ * nothing written) for a bad column, EOS constant or NULL pointer.
+ * Thread-safe; host memory only. */
+int tplbm_theory_solve(double a, double b, double R, int32_t ncols, const tplbm_theory_column *cols,
+                       double *rho, double *p, tplbm_theory_result *out, int32_t nthreads);
+
+/* Message of the calling thread's last failed tplbm_theory_solve.  Never NULL. */
+const char *tplbm_theory_last_error(void);
 
 /* ======================================================================
  * Batched column sweep (one persistent launch runs many independent 1-D

@@ -16,9 +16,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtplbm.so")
 
-OK, EINVAL, ESHAPE, EUNSUPPORTED, EHIP, EUNPHYSICAL, ENOTCONVERGED = range(7)
+OK, EINVAL, ESHAPE, EUNSUPPORTED, EHIP, EUNPHYSICAL, ENOTCONVERGED, ENOSOLUTION = range(8)
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ESHAPE", 3: "EUNSUPPORTED", 4: "EHIP",
-                5: "EUNPHYSICAL", 6: "ENOTCONVERGED"}
+                5: "EUNPHYSICAL", 6: "ENOTCONVERGED", 7: "ENOSOLUTION"}
 D1Q3, D2Q9, D3Q19 = 1, 2, 3
 FP64, FP32_DEV = 0, 1
 FIELDS = {"rho": 0, "ux": 1, "uy": 2, "uz": 3, "T": 4, "p_eos": 5, "p_nn": 6}
@@ -164,6 +164,67 @@ def eos_spinodal(T, a=0.5, b=4.0, R=1.0):
     out = np.zeros(2)
     _check(load_library().tplbm_eos_spinodal(a, b, R, float(T), _dp(out)))
     return tuple(float(v) for v in out)
+
+
+# ---------------------------------------------------------------------------
+# sharp-interface theory of a column (host, FP64)
+# ---------------------------------------------------------------------------
+THEORY_CONFIGS = {"L-V": 0, "V-L": 1, "V-L-V": 2}
+THEORY_REASONS = {1: "liquid spinodal", 2: "vapour spinodal", 4: "zero pressure",
+                  8: "interface above T_c", 16: "no second interface", 32: "no placement matches the mean",
+                  64: "broken bracket", 128: "EOS solve failed"}
+
+
+class TheoryColumn(ctypes.Structure):
+    _fields_ = [("height", ctypes.c_int32), ("gravity_form", ctypes.c_int32),
+                ("config", ctypes.c_int32), ("substeps", ctypes.c_int32),
+                ("T_bot", ctypes.c_double), ("T_top", ctypes.c_double),
+                ("g", ctypes.c_double), ("mean_rho", ctypes.c_double)]
+
+
+class TheoryResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("n_interfaces", ctypes.c_int32),
+                ("reasons", ctypes.c_uint32), ("pad", ctypes.c_uint32),
+                ("interface", ctypes.c_double * 2), ("mean_rho", ctypes.c_double)]
+
+
+SIGNATURES.update({
+    "tplbm_theory_solve": ([ctypes.c_double] * 3 + [ctypes.c_int32, ctypes.POINTER(TheoryColumn), _DP, _DP,
+                                                   ctypes.POINTER(TheoryResult), ctypes.c_int32], ctypes.c_int),
+    "tplbm_theory_last_error": ([], ctypes.c_char_p),
+})
+
+
+def theory_solve(columns, substeps=8, nthreads=0, a=0.5, b=4.0, R=1.0):
+    """Sharp-interface equilibria of columns given as tuples
+    (height, T_bot, T_top, g, gravity_form, mean_rho, config) with config one
+    of "L-V", "V-L", "V-L-V".  Returns one dict per column: rho, p (node
+    arrays) and interfaces for a configuration that exists, else None for
+    rho/p and the list of reasons."""
+    n = len(columns)
+    cols = (TheoryColumn * max(n, 1))()
+    heights = []
+    for k, (h, tb, tt, g, form, mean, cfg) in enumerate(columns):
+        cols[k] = TheoryColumn(int(h), int(form), THEORY_CONFIGS[cfg], int(substeps),
+                               float(tb), float(tt), float(g), float(mean))
+        heights.append(int(h))
+    total = sum(heights)
+    rho, p = np.empty(max(total, 1)), np.empty(max(total, 1))
+    res = (TheoryResult * max(n, 1))()
+    rc = load_library().tplbm_theory_solve(a, b, R, n, cols, _dp(rho), _dp(p), res, int(nthreads))
+    if rc != OK:
+        raise TplbmError(rc, load_library().tplbm_theory_last_error().decode())
+    out, off = [], 0
+    for k, h in enumerate(heights):
+        r = res[k]
+        if r.status == OK:
+            out.append(dict(rho=rho[off:off + h].copy(), p=p[off:off + h].copy(),
+                            interfaces=list(r.interface[:r.n_interfaces]), mean=r.mean_rho, reasons=[]))
+        else:
+            out.append(dict(rho=None, p=None, interfaces=[], mean=None,
+                            reasons=[v for bit, v in THEORY_REASONS.items() if r.reasons & bit]))
+        off += h
+    return out
 
 
 def make_params(lattice=D2Q9, nx=1, ny=1, nz=1, walls=True, precision=FP64, eos="cs",

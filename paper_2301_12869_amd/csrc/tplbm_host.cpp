@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/tplbm.h"
+#include "eos_host.hpp"
 #include "lbm_internal.hpp"
 
 using namespace tplbm;
@@ -491,103 +492,14 @@ const char *tplbm_last_error(const tplbm_ctx *c) { return c ? c->err.c_str() : g
 
 }  // extern "C"
 
-// ---------------------------------------------------------------------------
-// FP64 equation-of-state utilities.  Carnahan-Starling (Eq. EOS):
-//   p = rho R T Z(eta) - a rho^2,  eta = b rho / 4,
-//   Z = (1 + eta + eta^2 - eta^3)/(1 - eta)^3.
-// With h(eta) = eta Z(eta): dp/drho = R T h'(eta) - 2 a rho and
-// d2p/drho2 = (b/4) R T h''(eta) - 2 a, where
-//   h'  = (1 + 4 eta + 4 eta^2 - 4 eta^3 + eta^4)/(1 - eta)^4,
-//   h'' = (8 + 20 eta - 4 eta^2)/(1 - eta)^5.
-// Coexistence (Eq. MaxwellRule) is solved as equal pressure and equal
-// chemical potential mu = p/rho + R T [ln eta + (4 eta - 3 eta^2)/(1-eta)^2]
-// - a rho (the equal-area rule written as mu_v = mu_l).
-// ---------------------------------------------------------------------------
-namespace {
-struct CS {
-    double a, b, R;
-    double Z(double e) const { return (1 + e + e * e - e * e * e) / ((1 - e) * (1 - e) * (1 - e)); }
-    double h1(double e) const
-    {
-        const double s = 1 - e;
-        return (1 + 4 * e + 4 * e * e - 4 * e * e * e + e * e * e * e) / (s * s * s * s);
-    }
-    double h2(double e) const
-    {
-        const double s = 1 - e;
-        return (8 + 20 * e - 4 * e * e) / (s * s * s * s * s);
-    }
-    double h3(double e) const  // derivative of h2
-    {
-        const double s = 1 - e;
-        return ((20 - 8 * e) * s + 5 * (8 + 20 * e - 4 * e * e)) / (s * s * s * s * s * s);
-    }
-    double p(double r, double T) const { return r * R * T * Z(b * r / 4) - a * r * r; }
-    double dp(double r, double T) const { return R * T * h1(b * r / 4) - 2 * a * r; }
-    double d2p(double r, double T) const { return b / 4 * R * T * h2(b * r / 4) - 2 * a; }
-    double mu(double r, double T) const
-    {
-        const double e = b * r / 4;
-        return p(r, T) / r + R * T * (std::log(e) + (4 * e - 3 * e * e) / ((1 - e) * (1 - e))) - a * r;
-    }
-    double rho_max() const { return 4.0 / b; }
-};
-
-// root of a monotone function on [lo, hi] by safeguarded Newton
-template <class F, class D>
-double newton_bracket(F f, D df, double lo, double hi, double target, int &ok)
-{
-    double flo = f(lo) - target, fhi = f(hi) - target;
-    ok = (flo <= 0) != (fhi <= 0) || flo == 0 || fhi == 0;
-    if (!ok) return 0.5 * (lo + hi);
-    const bool inc = fhi > flo;
-    double x = 0.5 * (lo + hi);
-    for (int it = 0; it < 200; ++it) {
-        const double fx = f(x) - target;
-        if (fx == 0) return x;
-        if ((fx > 0) == inc) hi = x; else lo = x;
-        const double d = df(x);
-        double xn = (d != 0) ? x - fx / d : 0.5 * (lo + hi);
-        if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
-        if (std::fabs(xn - x) <= 1e-16 * std::fabs(x) || hi - lo <= 1e-17 * std::fabs(x)) return xn;
-        x = xn;
-    }
-    return x;
-}
-
-int cs_spinodal(const CS &m, double T, double &sv, double &sl)
-{
-    int ok;
-    const double top = m.rho_max() * (1 - 1e-12);
-    // inflection of p(rho): d2p/drho2 = 0, increasing in rho
-    const double ri = newton_bracket([&](double r) { return m.d2p(r, T); },
-                                     [&](double r) { return m.b * m.b / 16 * m.R * T * m.h3(m.b * r / 4); },
-                                     1e-12, top, 0.0, ok);
-    if (!ok || m.dp(ri, T) >= 0) return TPLBM_EINVAL;
-    sv = newton_bracket([&](double r) { return m.dp(r, T); }, [&](double r) { return m.d2p(r, T); },
-                        1e-14, ri, 0.0, ok);
-    if (!ok) return TPLBM_ENOTCONVERGED;
-    sl = newton_bracket([&](double r) { return m.dp(r, T); }, [&](double r) { return m.d2p(r, T); },
-                        ri, top, 0.0, ok);
-    if (!ok) return TPLBM_ENOTCONVERGED;
-    return TPLBM_OK;
-}
-}  // namespace
+// FP64 equation-of-state utilities (eos_host.hpp).
+using namespace tplbm::eos;
 
 extern "C" int tplbm_eos_critical(double a, double b, double R, double *out3)
 {
     if (!out3 || !(a > 0 && b > 0 && R > 0)) return fail(nullptr, TPLBM_EINVAL, "bad EOS constants");
-    CS m{a, b, R};
-    // at the critical point rho d2p/drho2 = dp/drho, i.e. eta h''(eta) = h'(eta)
-    int ok;
-    const double eta = newton_bracket([&](double e) { return e * m.h2(e) - m.h1(e); },
-                                      [&](double e) { return e * m.h3(e); }, 1e-3, 0.5, 0.0, ok);
-    if (!ok) return fail(nullptr, TPLBM_ENOTCONVERGED, "critical point not bracketed");
-    const double rc = 4 * eta / b;
-    const double Tc = 8 * a / (b * R * m.h2(eta));
-    out3[0] = rc;
-    out3[1] = Tc;
-    out3[2] = m.p(rc, Tc);
+    if (cs_critical(CS{a, b, R}, out3[0], out3[1], out3[2]))
+        return fail(nullptr, TPLBM_ENOTCONVERGED, "critical point not bracketed");
     return TPLBM_OK;
 }
 
@@ -606,32 +518,10 @@ extern "C" int tplbm_eos_spinodal(double a, double b, double R, double T, double
 extern "C" int tplbm_eos_coexistence(double a, double b, double R, double T, double *out3)
 {
     if (!out3 || !(a > 0 && b > 0 && R > 0 && T > 0)) return fail(nullptr, TPLBM_EINVAL, "bad arguments");
-    CS m{a, b, R};
-    double sv, sl;
-    int rc = cs_spinodal(m, T, sv, sl);
-    if (rc) return fail(nullptr, rc, "no coexistence at T = %g (at or above T_c?)", T);
-    const double top = m.rho_max() * (1 - 1e-13);
-    double plo = std::max(m.p(sl, T), 0.0), phi = m.p(sv, T);
-    auto branches = [&](double ps, double &rv, double &rl) {
-        int ok1, ok2;
-        rv = newton_bracket([&](double r) { return m.p(r, T); }, [&](double r) { return m.dp(r, T); },
-                            1e-15, sv, ps, ok1);
-        rl = newton_bracket([&](double r) { return m.p(r, T); }, [&](double r) { return m.dp(r, T); },
-                            sl, top, ps, ok2);
-        return ok1 && ok2;
-    };
-    // mu_l - mu_v decreases as the trial pressure rises between the spinodal
-    // pressures; bisection on the pressure with Newton roots on each branch
-    double rv = 0, rl = 0;
-    for (int it = 0; it < 400; ++it) {
-        const double ps = 0.5 * (plo + phi);
-        if (!branches(ps, rv, rl)) return fail(nullptr, TPLBM_ENOTCONVERGED, "branch root failed");
-        const double dmu = m.mu(rl, T) - m.mu(rv, T);
-        if (dmu > 0) plo = ps; else phi = ps;
-        if (phi - plo <= 1e-17 * phi) break;
-    }
-    const double ps = 0.5 * (plo + phi);
-    if (!branches(ps, rv, rl)) return fail(nullptr, TPLBM_ENOTCONVERGED, "branch root failed");
+    double rv, rl, ps;
+    int rc = cs_coexistence(CS{a, b, R}, T, rv, rl, ps);
+    if (rc == TPLBM_EINVAL) return fail(nullptr, rc, "no coexistence at T = %g (at or above T_c?)", T);
+    if (rc) return fail(nullptr, rc, "branch root failed");
     out3[0] = rv;
     out3[1] = rl;
     out3[2] = ps;

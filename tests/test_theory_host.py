@@ -1,0 +1,131 @@
+"""The library's sharp-interface column theory (tplbm_theory_solve, host code)
+against the theory reference in oracle/, on the same columns.
+
+Both sides take the same Euler steps from the same Maxwell states, so they
+differ only by the rounding of their independent EOS solves (relative
+~1e-15 per solve, accumulated over a few thousand steps) and by the
+bisection of the interface height, which both stop at a width of 1e-12.
+Hence the bounds: interface heights within 1e-9 nodes, node densities and
+pressures within 1e-9 relative.  Where a configuration cannot exist, both
+must say so and name the same causes.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2301_12869_amd as T
+from oracle import theory_ref as TR
+
+RHO_C, T_C, P_C = O.critical()
+MEAN = 1.3344 * RHO_C
+
+# (height, T_bot/T_c, T_top/T_c, g, form, mean_rho, config): the minimal
+# column, ragged heights, both gravity signs and forms, heating from above,
+# a column whose bottom is supercritical (a liquid there cannot exist,
+# a vapour can), and a V-L-V case
+CASES = [
+    (3, 0.8, 0.8, 1e-5, 1, MEAN, "L-V"),
+    (41, 0.85, 0.65, 2e-5, 1, MEAN, "L-V"),
+    (41, 0.85, 0.65, 2e-5, 2, MEAN, "L-V"),
+    (37, 0.7, 0.8, -3e-5, 1, MEAN, "V-L"),
+    (53, 0.78, 0.72, -2e-5, 2, 1.1 * RHO_C, "L-V"),
+    (45, 1.05, 0.6, 3e-5, 1, MEAN, "L-V"),
+    (45, 1.05, 0.6, 3e-5, 1, MEAN, "V-L"),
+    (61, 0.9, 0.6, 4e-5, 1, MEAN, "V-L-V"),
+    (41, 0.75, 0.75, 0.0, 2, 0.8 * RHO_C, "V-L"),
+]
+
+
+def _oracle(case, m):
+    H, tb, tt, g, form, mean, cfg = case
+    col = TR.Column(O.make_params("D1Q3", ny=H), H, tb * T_C, tt * T_C, g, form, mean, m)
+    try:
+        return col.solve(cfg), None
+    except TR.NoSolution as e:
+        return None, str(e)
+
+
+def _product(cases, m, nthreads=0):
+    cols = [(H, tb * T_C, tt * T_C, g, form, mean, cfg) for (H, tb, tt, g, form, mean, cfg) in cases]
+    return T.theory_solve(cols, substeps=m, nthreads=nthreads)
+
+
+@pytest.fixture(scope="module")
+def product_results():
+    return _product(CASES, 3)
+
+
+@pytest.mark.parametrize("k", range(len(CASES)))
+def test_theory_matches_the_reference(product_results, k):
+    case = CASES[k]
+    want, why = _oracle(case, 3)
+    got = product_results[k]
+    if want is None:
+        assert got["rho"] is None, why
+        for r in got["reasons"]:
+            if r in ("liquid spinodal", "vapour spinodal", "zero pressure"):
+                assert r in why
+        return
+    assert got["rho"] is not None, got["reasons"]
+    assert len(got["interfaces"]) == len(want["interfaces"])
+    for a, b in zip(got["interfaces"], want["interfaces"]):
+        assert a == pytest.approx(b, abs=1e-9)
+    np.testing.assert_allclose(got["rho"], want["rho"], rtol=1e-9)
+    np.testing.assert_allclose(got["p"], want["p"], rtol=1e-9, atol=1e-9 * np.abs(want["p"]).max())
+    assert got["mean"] == pytest.approx(case[5], rel=1e-9)
+
+
+def test_configurations_that_cannot_exist_report_their_causes():
+    # form 2 at strong negative gravity: the vapour reaches zero pressure;
+    # form 1 well past the boiling limit: the liquid reaches its spinodal
+    cases = [(101, 0.8, 0.7, -6e-5, 2, MEAN, "L-V"), (101, 0.75 + 0.17, 0.75 - 0.17, 1.5e-5, 1, MEAN, "L-V")]
+    got = _product(cases, 2)
+    assert got[0]["rho"] is None and "zero pressure" in got[0]["reasons"]
+    assert got[1]["rho"] is None and "liquid spinodal" in got[1]["reasons"]
+    for g, c in zip(got, cases):
+        _, why = _oracle(c, 2)
+        assert why is not None
+        assert "no placement matches the mean" in g["reasons"]
+
+
+def test_threads_do_not_change_the_results():
+    cases = CASES * 3
+    a = _product(cases, 2, nthreads=1)
+    b = _product(cases, 2, nthreads=7)
+    for x, y in zip(a, b):
+        assert x["interfaces"] == y["interfaces"]
+        if x["rho"] is not None:
+            assert np.array_equal(x["rho"], y["rho"]) and np.array_equal(x["p"], y["p"])
+
+
+def test_v_l_is_l_v_upside_down():
+    a, b = _product([(71, 0.85, 0.7, 3e-5, 2, MEAN, "L-V"), (71, 0.7, 0.85, -3e-5, 2, MEAN, "V-L")], 4)
+    assert b["interfaces"][0] == pytest.approx(70 - a["interfaces"][0], abs=1e-9)
+    np.testing.assert_allclose(b["rho"], a["rho"][::-1], rtol=1e-12)
+
+
+def test_lever_rule_at_zero_gravity():
+    Tm = 0.8 * T_C
+    rv, rl, ps = T.eos_coexistence(Tm)
+    mean = 0.4 * rv + 0.6 * rl
+    (r,) = _product([(129, 0.8, 0.8, 0.0, 1, mean, "L-V")], 1)
+    assert r["interfaces"][0] == pytest.approx(129 * (mean - rv) / (rl - rv) - 0.5, abs=1e-9)
+    np.testing.assert_allclose(r["p"], ps, rtol=1e-13)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(height=2), dict(gravity_form=3), dict(config=3), dict(substeps=0), dict(T_bot=-1.0),
+    dict(g=math.inf), dict(mean_rho=1.5),
+])
+def test_bad_columns_are_rejected(bad):
+    good = dict(height=11, gravity_form=1, config=0, substeps=2, T_bot=0.07, T_top=0.07, g=0.0, mean_rho=0.1)
+    good.update(bad)
+    col = (T.TheoryColumn * 1)(T.TheoryColumn(**good))
+    rho, p = np.empty(64), np.empty(64)
+    res = (T.TheoryResult * 1)()
+    lib = T.load_library()
+    rc = lib.tplbm_theory_solve(0.5, 4.0, 1.0, 1, col, T._dp(rho), T._dp(p), res, 1)
+    assert rc in (T.EINVAL, T.ESHAPE)
+    assert lib.tplbm_theory_last_error().decode()
