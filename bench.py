@@ -253,9 +253,10 @@ def train_throughput(T, torch, WS, rho_c, T_c, nc, H=1024, n_steps=50):
 
 
 def run_warmstart(T, torch, evaluate=True):
-    """Held-out columns (1024, drawn as the sweep) from the plain start and
-    from the trained network's profiles, each run to max |u| < 1e-9 or the
-    step budget; plus the network's training throughput on the matrix cores."""
+    """Held-out columns (1024, drawn as the sweep) from the plain start, from
+    the trained network's profiles and from the sharp-interface theory, each
+    run to max |u| < 1e-9 or the step budget; plus the network's training
+    throughput on the matrix cores."""
     from paper_2301_12869_amd import warmstart as WS
 
     if not os.path.exists(WS.PARAMS_PATH):

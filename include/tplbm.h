@@ -279,7 +279,7 @@ const char *tplbm_theory_last_error(void);
 typedef struct tplbm_column {
     int32_t height;        /* nodes including both wall nodes, 3 .. 2048 */
     int32_t gravity_form;  /* 1 or 2 */
-    double g;              /* gravity magnitude, > 0 pointing to node 0 */
+    double g;              /* signed gravity: > 0 points to node 0, < 0 away from it */
 } tplbm_column;
 
 typedef struct tplbm_batch_params {

@@ -121,6 +121,12 @@ def load_library():
     """Load libtplbm.so (built by paper_2301_12869_amd.build)."""
     global _lib
     if _lib is None:
+        # torch ships its own HIP runtime under the same soname as the one the
+        # library links; loading torch first makes the process hold one
+        # runtime (torch's), which the library then binds to.  Loaded the
+        # other way round, the two runtimes meet and HIP finds no device.
+        import torch  # noqa: F401
+
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_2301_12869_amd.build` (no CPU fallback exists)")

@@ -23,7 +23,7 @@ import time
 
 import numpy as np
 
-from . import Batch, Net, eos_coexistence, eos_critical
+from . import Batch, Net, eos_coexistence, eos_critical, theory_solve
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 PARAMS_PATH = os.path.join(_HERE, "warmstart_params.npy")
@@ -155,17 +155,48 @@ def train(net: Net, n_data: int, heights, epochs: int, batch_nodes: int, lr0: fl
     return hist
 
 
-def evaluate(net: Net, cols: Columns, tol: float, max_steps: int, check_every: int = 100, log=print):
-    """Cold (plain start), warm (network density and temperature) and
-    warm_rho (network density, the column's uniform temperature) starts of
-    the same columns, each run to max |u| < tol or max_steps; returns
-    per-column results and the final profiles."""
+def theory_start(cols: Columns, substeps: int = 1):
+    """Sharp-interface L-V equilibria of the columns (tplbm_theory_solve on
+    host threads) as a start: node densities shifted to the column's exact
+    mass, the column's uniform temperature.  Columns without an L-V solution
+    keep the plain start.  Returns (rho, T, mask of the columns without one)."""
+    tc = [(int(cols.height[k]), cols.t_reduced[k] * cols.T_c, cols.t_reduced[k] * cols.T_c,
+           float(cols.g[k]), int(cols.form[k]), float(cols.mean_reduced[k] * cols.rho_c), "L-V")
+          for k in range(cols.n)]
+    sol = theory_solve(tc, substeps=substeps)
+    rho = cols.rho0.copy()
+    missing = np.zeros(cols.n, dtype=bool)
+    for k, s in enumerate(sol):
+        a, b = cols.offsets[k], cols.offsets[k + 1]
+        if s["rho"] is None:
+            missing[k] = True
+            continue
+        r = s["rho"]
+        rho[a:b] = r + (cols.rho0[a:b].mean() - r.mean())
+    return rho, cols.T0.copy(), missing
+
+
+def evaluate(net: Net, cols: Columns, tol: float, max_steps: int, check_every: int = 100, log=print,
+             theory: bool = True):
+    """Cold (plain start), warm (network density and temperature), warm_rho
+    (network density, the column's uniform temperature) and theory
+    (sharp-interface equilibrium) starts of the same columns, each run to
+    max |u| < tol or max_steps; returns per-column results and the final
+    profiles."""
     out = {}
     sc = cols.solver_columns()
     t0 = time.perf_counter()
     rho_w, T_w = net.predict(cols.net_columns())
     t_pred = time.perf_counter() - t0
-    starts = (("cold", (cols.rho0, cols.T0)), ("warm", (rho_w, T_w)), ("warm_rho", (rho_w, cols.T0)))
+    starts = [("cold", (cols.rho0, cols.T0)), ("warm", (rho_w, T_w)), ("warm_rho", (rho_w, cols.T0))]
+    if theory:
+        t0 = time.perf_counter()
+        rho_t, T_t, missing = theory_start(cols)
+        out["theory_seconds"] = time.perf_counter() - t0
+        out["theory_without_solution"] = missing
+        log(f"theory start: {cols.n - missing.sum()} L-V solutions, {missing.sum()} without, "
+            f"{out['theory_seconds']:.1f} s")
+        starts.append(("theory", (rho_t, T_t)))
     for name, (r, t) in starts:
         b = Batch(sc)
         b.set_state(r, t)
@@ -249,10 +280,13 @@ def summarize(cols: Columns, res: dict) -> dict:
     c = res["cold"]
     m0 = np.add.reduceat(cols.rho0, cols.offsets[:-1])  # mass of the plain start (= the seeded mass)
     out = {}
-    for name in ("cold", "warm", "warm_rho"):
+    names = [n for n in ("cold", "warm", "warm_rho", "theory") if n in res]
+    setup = dict(cold=0.0, warm=res["predict_seconds"], warm_rho=res["predict_seconds"],
+                 theory=res.get("theory_seconds", 0.0))
+    for name in names:
         r = res[name]
         conv = r["status"] == 0
-        secs = r["seconds"] + (res["predict_seconds"] if name != "cold" else 0.0)
+        secs = r["seconds"] + setup[name]
         out[name] = dict(converged=int(conv.sum()), diverged=int((r["status"] == 1).sum()),
                          budget=int((r["status"] == 2).sum()), seconds=secs,
                          steady_states_per_hour=float(conv.sum() / secs * 3600.0),
@@ -267,7 +301,7 @@ def summarize(cols: Columns, res: dict) -> dict:
     if pe:
         out["prediction_rel_l2_median"] = float(np.median(pe))
         out["prediction_rel_l2_q90"] = float(np.quantile(pe, 0.9))
-    for name in ("warm", "warm_rho"):
+    for name in names[1:]:
         w = res[name]
         both = (c["status"] == 0) & (w["status"] == 0)
         cmp = dict(both_converged=int(both.sum()))
@@ -289,7 +323,16 @@ def summarize(cols: Columns, res: dict) -> dict:
         out[name + "_vs_cold"] = cmp
     # mass the walls add or remove during the transient (the seeded mass is
     # the column's <rho> H for every start)
-    for name in ("cold", "warm", "warm_rho"):
+    if "theory" in res:
+        # columns with no L-V equilibrium in theory: what the solver did
+        # with them from the plain start
+        miss = res["theory_without_solution"]
+        out["theory"]["without_solution"] = int(miss.sum())
+        out["theory"]["without_solution_cold_status"] = {
+            v: int((c["status"][miss] == k).sum()) for k, v in ((0, "converged"), (1, "diverged"), (2, "budget"))}
+        out["theory"]["with_solution_cold_status"] = {
+            v: int((c["status"][~miss] == k).sum()) for k, v in ((0, "converged"), (1, "diverged"), (2, "budget"))}
+    for name in names:
         r = res[name]
         conv = r["status"] == 0
         if conv.any():

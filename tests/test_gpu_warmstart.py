@@ -38,7 +38,7 @@ def result():
     net = T.Net(cols.rho_c, cols.T_c, max_cols=N_COLS, max_nodes=int(cols.height.sum()))
     net.set_params(np.load(WS.PARAMS_PATH))
     _log(f"held-out columns: {N_COLS} (seed {SEED}), budget {STEPS} steps")
-    res = WS.evaluate(net, cols, 1e-9, STEPS, log=_log)
+    res = WS.evaluate(net, cols, 1e-9, STEPS, log=_log, theory=False)
     net.close()
     return cols, res, WS.summarize(cols, res)
 
