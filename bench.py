@@ -281,6 +281,27 @@ def run_warmstart(T, torch, evaluate=True):
     return summary
 
 
+def run_diagram():
+    """The (g, Delta T) configuration diagrams of both gravity forms: 25 x 11
+    grid points x 3 configurations, the theory on host threads and the
+    lattice as one batched launch of 1 650 columns of 101 nodes (10^6-step
+    budget); reports the agreement counts and the two times."""
+    from paper_2301_12869_amd import diagram as D
+
+    gs = np.linspace(-3e-4, 3e-4, 25)
+    dts = np.linspace(-0.5, 0.5, 11)
+    recs, info = D.sweep((1, 2), gs, dts, 1_000_000,
+                         log=lambda m: print("# diagram " + m, file=sys.stderr, flush=True))
+    agree = D.agreement(recs)
+    total = sum(v["agree"] for v in agree.values())
+    return {"workload": "forms 1, 2; g in [-3e-4, 3e-4] (25 points); dT/Tc in [-0.5, 0.5] (11); "
+                        "L-V, V-L, V-L-V; 101 nodes, <rho> = 1.3344 rho_c, T_med = 0.75 T_c",
+            "points": len(recs), "agree": total, "agree_frac": round(total / len(recs), 4),
+            "per_configuration": agree, "theory_seconds": round(info["theory_seconds"], 2),
+            "lattice_seconds": round(info["lattice_seconds"], 2),
+            "lattice_node_steps_per_s": round(info["node_steps"] / info["lattice_seconds"], 1)}
+
+
 def long_runs(T, torch, rho0, T0):
     """The step counts the workloads are specified with, once: D2Q9 1024x2048
     for 10^5 steps and D3Q19 256^3 for 5*10^4 steps, FP32-deviation and FP64
@@ -389,7 +410,8 @@ def main():
                     help="only the long untimed runs (10^5 D2Q9 and 5*10^4 D3Q19 steps), as a JSON line")
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the plain per-column comparison of the batched sweep")
-    ap.add_argument("--variants", default="all", help="all | headline | fp32dev | d3q19 | batched | warmstart | net")
+    ap.add_argument("--variants", default="all",
+                    help="all | headline | fp32dev | d3q19 | batched | warmstart | net | diagram")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -426,7 +448,7 @@ def main():
     variants = [(0, 2, 1e-5)]
     if args.variants == "fp32dev":
         variants = [(1, 2, 1e-5)]
-    if args.variants in ("d3q19", "batched", "warmstart", "net"):
+    if args.variants in ("d3q19", "batched", "warmstart", "net", "diagram"):
         variants = [(0, 2, 1e-5)]
     if args.variants == "all":
         variants += [(0, 1, 1e-5), (0, 1, 1e-4), (0, 2, 1e-4), (1, 2, 1e-5), (1, 1, 1e-5),
@@ -526,6 +548,8 @@ def main():
         }
     if args.variants in ("all", "warmstart", "net"):
         line["warm_start"] = run_warmstart(T, torch, evaluate=args.variants != "net")
+    if args.variants in ("all", "diagram"):
+        line["configuration_diagram"] = run_diagram()
     line["hbm_copy_GBs"] = copy_bandwidth(torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(rho0, T0, T_c)
