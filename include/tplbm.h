@@ -327,9 +327,23 @@ int tplbm_batch_set_state(tplbm_batch *b, const double *rho_concat, const double
 /* Run every column from its initial state until max |u^n| < tol at a level n
  * that is a multiple of the check interval, until a flag is raised, or until
  * n = max_steps; one persistent launch.  out[k] receives column k's result
- * (caller array of ncols).  The final levels are kept for tplbm_batch_read.
- * Never aborts the batch for one bad column.  Synchronous. */
+ * (caller array of ncols; levels count from this run's start).  The final
+ * levels are kept for tplbm_batch_read and tplbm_batch_resume.  Never aborts
+ * the batch for one bad column.  Synchronous. */
 int tplbm_batch_run(tplbm_batch *b, double tol, int64_t max_steps, tplbm_col_result *out);
+
+/* Arm the next tplbm_batch_run to continue every column from the level the
+ * last run ended at (its populations and temperatures, bit for bit, as if the
+ * run had gone on) instead of from tplbm_batch_set_state's state, with the
+ * wall temperatures replaced by T_bot[k] (node 0) and T_top[k] (last node)
+ * for column k -- a change of the boundary conditions in the middle of a run,
+ * as in the phase-change protocol of Sec. V A.  T_bot or T_top may be NULL to
+ * keep those walls.  One-shot: a later run starts from set_state's state
+ * again unless resume is called again.  Errors: EINVAL if no run has ended
+ * since the last set_state or autotune (whose trial launches overwrite the
+ * end state), or a wall temperature is not finite and > 0; EHIP.
+ * Synchronous. */
+int tplbm_batch_resume(tplbm_batch *b, const double *T_bot, const double *T_top);
 
 /* Final densities (TPLBM_RHO) or temperatures (TPLBM_T), concatenated. */
 int tplbm_batch_read(tplbm_batch *b, int field, double *host_out);

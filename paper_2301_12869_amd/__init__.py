@@ -111,6 +111,7 @@ SIGNATURES.update({
     "tplbm_batch_read": ([_VP, ctypes.c_int, _DP], ctypes.c_int),
     "tplbm_batch_autotune": ([_VP, ctypes.c_double, ctypes.POINTER(BatchTuning)], ctypes.c_int),
     "tplbm_batch_set_tuning": ([_VP, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+    "tplbm_batch_resume": ([_VP, _DP, _DP], ctypes.c_int),
     "tplbm_batch_destroy": ([_VP], None),
     "tplbm_batch_last_error": ([_VP], ctypes.c_char_p),
 })
@@ -384,6 +385,20 @@ class Batch:
         out = np.empty(int(self.offsets[-1]))
         _bcheck(load_library().tplbm_batch_read(self._h, FIELDS[field], _dp(out)), self._h)
         return out
+
+    def resume(self, T_bot=None, T_top=None):
+        """Make the next run continue from where the last one ended, with new
+        wall temperatures (per-column sequences; None keeps those walls)."""
+        def arr(v):
+            if v is None:
+                return None
+            a = np.ascontiguousarray(v, dtype=np.float64)
+            if a.size != self.ncols:
+                raise ValueError("one wall temperature per column")
+            return a
+        tb, tt = arr(T_bot), arr(T_top)
+        _bcheck(load_library().tplbm_batch_resume(self._h, _dp(tb) if tb is not None else None,
+                                                  _dp(tt) if tt is not None else None), self._h)
 
     def column(self, arr, k):
         return arr[self.offsets[k]:self.offsets[k + 1]]

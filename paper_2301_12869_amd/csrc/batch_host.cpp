@@ -29,6 +29,9 @@ struct tplbm_batch {
     int *d_order = nullptr;
     int *d_sample = nullptr;  // autotuner trial order
     double *rho0 = nullptr, *T0 = nullptr, *rho_out = nullptr, *T_out = nullptr;
+    double *f_end = nullptr;    // end-level populations of the last launch (3 planes)
+    bool have_end = false;      // f_end/T_out hold the end of a tplbm_batch_run
+    bool resume = false;        // the next run continues from f_end/T_out
     ColumnResult *results = nullptr;
     unsigned *queue = nullptr;
     int shape = 0, check_every = 100;
@@ -97,7 +100,7 @@ BLayout blayout(int ncols, int64_t total)
     L.field = al(sizeof(double) * (size_t)total);
     L.results = al(sizeof(ColumnResult) * ncols);
     L.queue = 256;
-    L.total = L.cols + 2 * L.order + 4 * L.field + L.results + L.queue;
+    L.total = L.cols + 2 * L.order + 7 * L.field + L.results + L.queue;
     return L;
 }
 
@@ -129,7 +132,7 @@ int grid_for(tplbm_batch *b, int shape)
 }
 
 int run_once(tplbm_batch *b, const ColumnDesc *cols, const int *order, int ncols, int shape,
-             int check_every, double tol, int64_t max_steps, float *ms)
+             int check_every, double tol, int64_t max_steps, float *ms, bool resume = false)
 {
     BHIP(b, hipMemsetAsync(b->queue, 0, sizeof(unsigned), b->stream));
     BatchArgs a;
@@ -137,9 +140,12 @@ int run_once(tplbm_batch *b, const ColumnDesc *cols, const int *order, int ncols
     a.ncols = ncols;
     a.order = order;
     a.rho0 = b->rho0;
-    a.T0 = b->T0;
+    a.T0 = resume ? b->T_out : b->T0;
     a.rho_out = b->rho_out;
     a.T_out = b->T_out;
+    a.f_in = resume ? b->f_end : nullptr;
+    a.f_out = b->f_end;
+    a.nodes = b->total;
     a.results = b->results;
     a.queue = b->queue;
     a.tol = tol;
@@ -215,6 +221,7 @@ int tplbm_batch_create(const tplbm_batch_params *p, int32_t ncols, const tplbm_c
     b->T0 = (double *)q; q += L.field;
     b->rho_out = (double *)q; q += L.field;
     b->T_out = (double *)q; q += L.field;
+    b->f_end = (double *)q; q += 3 * L.field;
     b->results = (ColumnResult *)q; q += L.results;
     b->queue = (unsigned *)q;
     b->phys = make_bphys(*p);
@@ -243,6 +250,33 @@ int tplbm_batch_set_state(tplbm_batch *b, const double *rho, const double *T)
     BHIP(b, hipMemcpyAsync(b->T0, T, sizeof(double) * b->total, hipMemcpyHostToDevice, b->stream));
     BHIP(b, hipStreamSynchronize(b->stream));
     b->have_state = true;
+    b->have_end = false;
+    b->resume = false;
+    return TPLBM_OK;
+}
+
+int tplbm_batch_resume(tplbm_batch *b, const double *T_bot, const double *T_top)
+{
+    if (!b) return bfail(nullptr, TPLBM_EINVAL, "batch is NULL");
+    if (!b->have_end) return bfail(b, TPLBM_EINVAL, "no run has ended since the last set_state or autotune");
+    for (int k = 0; k < b->ncols; ++k) {
+        if ((T_bot && !(T_bot[k] > 0 && std::isfinite(T_bot[k]))) ||
+            (T_top && !(T_top[k] > 0 && std::isfinite(T_top[k]))))
+            return bfail(b, TPLBM_EINVAL, "column %d: wall temperatures must be finite and > 0", k);
+    }
+    if (T_bot || T_top) {
+        std::vector<double> T(b->total);
+        BHIP(b, hipMemcpyAsync(T.data(), b->T_out, sizeof(double) * b->total, hipMemcpyDeviceToHost, b->stream));
+        BHIP(b, hipStreamSynchronize(b->stream));
+        for (int k = 0; k < b->ncols; ++k) {
+            const ColumnDesc &d = b->cols[k];
+            if (T_bot) T[d.offset] = T_bot[k];
+            if (T_top) T[d.offset + d.height - 1] = T_top[k];
+        }
+        BHIP(b, hipMemcpyAsync(b->T_out, T.data(), sizeof(double) * b->total, hipMemcpyHostToDevice, b->stream));
+        BHIP(b, hipStreamSynchronize(b->stream));
+    }
+    b->resume = true;
     return TPLBM_OK;
 }
 
@@ -251,8 +285,12 @@ int tplbm_batch_run(tplbm_batch *b, double tol, int64_t max_steps, tplbm_col_res
     if (!b) return bfail(nullptr, TPLBM_EINVAL, "batch is NULL");
     if (!b->have_state) return bfail(b, TPLBM_EINVAL, "call tplbm_batch_set_state first");
     if (!(tol >= 0) || max_steps < 0) return bfail(b, TPLBM_EINVAL, "need tol >= 0 and max_steps >= 0");
-    int rc = run_once(b, b->d_cols, b->d_order, b->ncols, b->shape, b->check_every, tol, max_steps, nullptr);
+    const bool resume = b->resume;
+    b->resume = false;
+    int rc = run_once(b, b->d_cols, b->d_order, b->ncols, b->shape, b->check_every, tol, max_steps, nullptr,
+                      resume);
     if (rc) return rc;
+    b->have_end = true;
     if (out) {
         std::vector<ColumnResult> r(b->ncols);
         BHIP(b, hipMemcpyAsync(r.data(), b->results, sizeof(ColumnResult) * b->ncols, hipMemcpyDeviceToHost, b->stream));
@@ -303,6 +341,9 @@ int tplbm_batch_autotune(tplbm_batch *b, double budget_ms, tplbm_batch_tuning *o
 {
     if (!b) return bfail(nullptr, TPLBM_EINVAL, "batch is NULL");
     if (!b->have_state) return bfail(b, TPLBM_EINVAL, "call tplbm_batch_set_state first");
+    // the trial launches overwrite the sampled columns' end state
+    b->have_end = false;
+    b->resume = false;
     int hmax = 0;
     for (auto &c : b->cols) hmax = std::max(hmax, (int)c.height);
     // trial sample: a stride through the production order, about two

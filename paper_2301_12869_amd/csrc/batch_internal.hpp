@@ -28,6 +28,14 @@ struct BatchArgs {
     const int *order;       // processing order (indices into cols)
     const double *rho0, *T0;
     double *rho_out, *T_out;
+    // populations of a previous run's end level (f0, f+, f- planes of
+    // `nodes` values each) to continue from instead of rest populations of
+    // rho0; NULL starts at rest.  The end level's populations go to f_out.
+    // f_in may equal f_out, and T0 may equal T_out: a column's nodes are read
+    // only by the block that runs it, before that block writes them.
+    const double *f_in;
+    double *f_out;
+    int64_t nodes;
     ColumnResult *results;
     unsigned *queue;        // next position in `order`; zero before a launch
     double tol;

@@ -80,17 +80,25 @@ __global__ __launch_bounds__(NT) void d1q3_batch(BatchArgs a, Phys c)
         const double g = d.g;
         const bool form2 = d.form == 2;
 
-        // ---- load: rest populations f = w rho0, temperature ----
+        // ---- load: rest populations f = w rho0 (or a previous run's end
+        // populations), temperature ----
         double f0[NPT], fp[NPT], fm[NPT], T[NPT];
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
             const int y = y0 + k;
             const bool own = k < npt && y < H;
-            const double r0 = own ? a.rho0[d.offset + y] : 0.0;
-            T[k] = own ? a.T0[d.offset + y] : 0.0;
-            f0[k] = 2.0 * r0 / 3.0;
-            fp[k] = r0 / 6.0;
-            fm[k] = r0 / 6.0;
+            const int64_t i = d.offset + y;
+            T[k] = own ? a.T0[i] : 0.0;
+            if (a.f_in) {
+                f0[k] = own ? a.f_in[i] : 0.0;
+                fp[k] = own ? a.f_in[a.nodes + i] : 0.0;
+                fm[k] = own ? a.f_in[2 * a.nodes + i] : 0.0;
+            } else {
+                const double r0 = own ? a.rho0[i] : 0.0;
+                f0[k] = 2.0 * r0 / 3.0;
+                fp[k] = r0 / 6.0;
+                fm[k] = r0 / 6.0;
+            }
         }
 
         int status = 2;
@@ -279,13 +287,18 @@ __global__ __launch_bounds__(NT) void d1q3_batch(BatchArgs a, Phys c)
             }
         }
 
-        // ---- outputs of the final level: rho, T; per-column result ----
+        // ---- outputs of the final level: rho, T, populations; per-column
+        // result ----
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
             const int y = y0 + k;
             if (k < npt && y < H) {
-                a.rho_out[d.offset + y] = f0[k] + fp[k] + fm[k];
-                a.T_out[d.offset + y] = T[k];
+                const int64_t i = d.offset + y;
+                a.rho_out[i] = f0[k] + fp[k] + fm[k];
+                a.T_out[i] = T[k];
+                a.f_out[i] = f0[k];
+                a.f_out[a.nodes + i] = fp[k];
+                a.f_out[2 * a.nodes + i] = fm[k];
             }
         }
         if (tid == 0) {

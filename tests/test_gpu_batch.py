@@ -162,3 +162,71 @@ def test_full_draw_4096_columns_sampled_against_the_oracle(T, orc, crit):
         assert np.abs(b.column(grho, k) - orho).max() / orho.max() < TOL
         assert np.abs(b.column(gT, k) - oT).max() / oT.max() < TOL
     b.close()
+
+
+def _walled_columns(orc, crit):
+    """Six columns with a temperature difference between the walls (linear
+    start), both forms, liquid below vapour plus noise."""
+    _, T_c, _ = crit
+    P = orc.make_params("D1Q3", ny=3)
+    spec = [(20, 1, 2e-5), (37, 2, 5e-6), (64, 1, 1e-5), (90, 2, 3e-5), (128, 1, 1e-6), (200, 2, 8e-6)]
+    rv, rl, _ = orc.coexistence(P, 0.8 * T_c)
+    rho, Tc = [], []
+    for k, (H, form, g) in enumerate(spec):
+        rho.append(W.column_initial_density(H, 0.5 * (rv + rl), rl, rv, 1e-3, 500 + k))
+        Tc.append(T_c * (0.82 - 0.04 * np.arange(H) / (H - 1)))
+    return spec, np.concatenate(rho), np.concatenate(Tc)
+
+
+def test_resume_continues_the_run_bit_for_bit(T, orc, crit):
+    cols, rho, Tc = _walled_columns(orc, crit)
+    b = T.Batch(cols)
+    b.set_tuning(shape=0, check_every=100)
+    b.set_state(rho, Tc)
+    b.run(0.0, 3000)
+    b.resume()
+    r2 = b.run(0.0, 2000)
+    split = b.read("rho"), b.read("T")
+    b.set_state(rho, Tc)
+    r1 = b.run(0.0, 5000)
+    whole = b.read("rho"), b.read("T")
+    assert np.all(r1["status"] == 2) and np.all(r2["steps"] == 2000)
+    assert np.array_equal(split[0], whole[0]) and np.array_equal(split[1], whole[1])
+    assert np.array_equal(r1["mass"], r2["mass"])
+    with pytest.raises(ValueError):
+        b.resume([1.0] * 5)  # one value per column
+    b.set_state(rho, Tc)
+    with pytest.raises(T.TplbmError):
+        b.resume()  # nothing has run since set_state
+    b.close()
+
+
+def test_resume_with_new_wall_temperatures_matches_the_oracle(T, orc, crit):
+    """The phase-change protocol's boundary change: 3000 steps, then the
+    bottom wall 3% hotter and the top wall 3% colder for 2000 more steps,
+    against the oracle doing the same to its temperature array."""
+    cols, rho, Tc = _walled_columns(orc, crit)
+    b = T.Batch(cols)
+    b.set_tuning(shape=0, check_every=100)
+    b.set_state(rho, Tc)
+    b.run(0.0, 3000)
+    tb = np.array([b.column(Tc, k)[0] * 1.03 for k in range(len(cols))])
+    tt = np.array([b.column(Tc, k)[-1] * 0.97 for k in range(len(cols))])
+    b.resume(tb, tt)
+    res = b.run(0.0, 2000)
+    grho, gT = b.read("rho"), b.read("T")
+    for k, (H, form, g) in enumerate(cols):
+        P = orc.make_params("D1Q3", ny=H, g=g, gravity_form=form)
+        f = orc.init_rest(P, b.column(rho, k).copy())
+        TT = b.column(Tc, k).copy()
+        orc.step(P, f, TT, 3000)
+        TT[0], TT[-1] = tb[k], tt[k]
+        orc.step(P, f, TT, 2000)
+        m = orc.macro(P, f, TT)
+        er = np.abs(b.column(grho, k) - m["rho"]).max() / m["rho"].max()
+        eT = np.abs(b.column(gT, k) - TT).max() / TT.max()
+        _log(f"column {k} {(H, form, g)}: status {res['status'][k]}, rho err {er:.2e}, T err {eT:.2e}")
+        assert res["status"][k] == 2
+        assert er < TOL and eT < TOL
+        assert b.column(gT, k)[0] == tb[k] and b.column(gT, k)[-1] == tt[k]
+    b.close()
