@@ -63,6 +63,16 @@ extern "C" {
 #define TPLBM_FP64 0            /* populations stored in FP64 */
 #define TPLBM_FP32_DEV 1        /* populations stored in FP32 as f_i - w_i rho_ref */
 
+/* state between steps (tplbm_params.state).  With every relaxation time 1
+ * the post-collision populations are a closed function of the node's density,
+ * force-corrected velocity and force (Eq. LiFS with Eq. OperatorMRT at
+ * Lambda = I), so a D2Q9 FP64 lattice can carry rho and j instead of the nine
+ * populations: AUTO does that where it applies (the same arithmetic as the
+ * population state, equal to rounding) and stores populations everywhere
+ * else; POPULATIONS always stores populations. */
+#define TPLBM_STATE_AUTO 0
+#define TPLBM_STATE_POPULATIONS 1
+
 #define TPLBM_EOS_CARNAHAN_STARLING 0
 #define TPLBM_EOS_IDEAL_LATTICE 1 /* p = rho/3, psi = 0: for tests of the closed forms */
 
@@ -100,6 +110,8 @@ typedef struct tplbm_params {
     double cv, kappa;       /* Eq. Energy_Equation */
     double g;               /* gravity magnitude along -(wall-normal axis) */
     double rho_ref;         /* FP32_DEV reference density; ignored for FP64 */
+    int32_t state;          /* TPLBM_STATE_*: what a lattice stores between steps */
+    int32_t pad;            /* zero */
 } tplbm_params;
 
 /* Diagnostics of the time level `step` (the level the last step started from). */

@@ -21,6 +21,7 @@ STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ESHAPE", 3: "EUNSUPPORTED", 4: "EHIP",
                 5: "EUNPHYSICAL", 6: "ENOTCONVERGED", 7: "ENOSOLUTION"}
 D1Q3, D2Q9, D3Q19 = 1, 2, 3
 FP64, FP32_DEV = 0, 1
+STATE_AUTO, STATE_POPULATIONS = 0, 1
 FIELDS = {"rho": 0, "ux": 1, "uy": 2, "uz": 3, "T": 4, "p_eos": 5, "p_nn": 6}
 FLAG_NAMES = {1: "nan", 2: "rho<=0", 4: "eta>=1", 8: "psi undefined"}
 
@@ -41,7 +42,7 @@ class Params(ctypes.Structure):
         ("a", ctypes.c_double), ("b", ctypes.c_double), ("R", ctypes.c_double),
         ("G", ctypes.c_double), ("sigma", ctypes.c_double), ("tau", ctypes.c_double * 6),
         ("cv", ctypes.c_double), ("kappa", ctypes.c_double), ("g", ctypes.c_double),
-        ("rho_ref", ctypes.c_double),
+        ("rho_ref", ctypes.c_double), ("state", ctypes.c_int32), ("pad", ctypes.c_int32),
     ]
 
 
@@ -235,7 +236,7 @@ def theory_solve(columns, substeps=8, nthreads=0, a=0.5, b=4.0, R=1.0):
 
 
 def make_params(lattice=D2Q9, nx=1, ny=1, nz=1, walls=True, precision=FP64, eos="cs",
-                gravity_form=1, g=0.0, rho_ref=0.0, **over) -> Params:
+                gravity_form=1, g=0.0, rho_ref=0.0, state=STATE_AUTO, **over) -> Params:
     d = dict(PAPER)
     d.update(over)
     p = Params()
@@ -249,6 +250,7 @@ def make_params(lattice=D2Q9, nx=1, ny=1, nz=1, walls=True, precision=FP64, eos=
     for k in range(6):
         p.tau[k] = float(d["tau"][k])
     p.cv, p.kappa, p.g, p.rho_ref = d["cv"], d["kappa"], float(g), float(rho_ref)
+    p.state, p.pad = int(state), 0
     return p
 
 

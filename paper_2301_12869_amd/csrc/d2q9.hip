@@ -124,6 +124,97 @@ __device__ __forceinline__ int wrapi(int v, int n)
     return v < 0 ? v + n : v;
 }
 
+// Zou-He reconstruction (zero wall velocity) of the populations a wall node
+// does not receive, then density and momentum of the pulled set.  Both the
+// population and the moment kernel take their level's (rho, j) from here.
+__device__ __forceinline__ void pulled_moments(double f[9], bool bot, bool top, double &rho, double &jx,
+                                               double &jy)
+{
+    if (bot) {  // unknowns 2, 5, 6
+        const double d = f[1] - f[3];
+        f[2] = f[4];
+        f[5] = f[7] - 0.5 * d;
+        f[6] = f[8] + 0.5 * d;
+    }
+    if (top) {  // unknowns 4, 7, 8
+        const double d = f[1] - f[3];
+        f[4] = f[2];
+        f[7] = f[5] + 0.5 * d;
+        f[8] = f[6] - 0.5 * d;
+    }
+    rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+    jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+    jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+}
+
+// Shan-Chen force on the psi stencil (LDS, centre index c3, row stride ld)
+// plus gravity, and X = |F_int|^2 / psi^2 = G^2 |sum w psi c|^2 for the sigma
+// term.  Zero at wall nodes.
+__device__ __forceinline__ void node_force(const Phys &c, const double *s_psi, int c3, int ld, double rho,
+                                           double mean, bool wall, double &Fx, double &Fy, double &X)
+{
+    Fx = Fy = X = 0.0;
+    if (wall) return;
+    Stencil p;
+    p.load(s_psi, c3, ld);
+    const double sx = (p.e - p.w) * (1.0 / 3.0) + ((p.ne + p.se) - (p.nw + p.sw)) * (1.0 / 12.0);
+    const double sy = (p.n - p.s) * (1.0 / 3.0) + ((p.ne + p.nw) - (p.se + p.sw)) * (1.0 / 12.0);
+    const double mg = -c.G * s_psi[c3];
+    const double fg = (c.form == 2) ? -(rho - mean) * c.g : -rho * c.g;
+    Fx = mg * sx;
+    Fy = mg * sy + fg;
+    X = c.G2 * (sx * sx + sy * sy);
+}
+
+// Every relaxation rate 1: f* = f_eq(rho, u) + F', F' = M^-1 (S/2) =
+// w_i [3/2 (c - u).F + 9/2 (c.u)(c.F)] + sigma X (-8, 1, ..., 1)/36.  The
+// rest population is closed by mass conservation, f*_0 = rho - sum_{i>0}
+// f*_i (exact in exact arithmetic), so the collision adds no systematic
+// rounding drift to the mass.  Opposite velocities share the even part of
+// f_eq + F' and differ in the sign of the odd part: per pair (i, i')
+// f*_i = E + O, f*_i' = E - O with
+// E = w rho (1 - 3/2 u^2 + 9/2 (c.u)^2) + w (9/2 (c.u)(c.F) - 3/2 u.F) + sigma X/36
+// O = w (3 rho c.u + 3/2 c.F)
+__device__ __forceinline__ void collide_tau1(const Phys &c, double rho, double ux, double uy, double Fx,
+                                             double Fy, double X, double fs[9])
+{
+    const double uu = ux * ux + uy * uy;
+    const double uF = ux * Fx + uy * Fy;
+    const double sx36 = c.sigma * X * (1.0 / 36.0);
+    const double r1 = kW1 * rho, r5 = kW5 * rho;
+    const double b1 = r1 * (1.0 - 1.5 * uu) - kW1 * 1.5 * uF + sx36;
+    const double b5 = r5 * (1.0 - 1.5 * uu) - kW5 * 1.5 * uF + sx36;
+    auto pair = [&](double cu, double cF, double wr, double wi, double base, double &fp, double &fm) {
+        const double E = base + 4.5 * cu * (wr * cu + wi * cF);
+        const double O = 3.0 * wr * cu + 1.5 * wi * cF;
+        fp = E + O;
+        fm = E - O;
+    };
+    pair(ux, Fx, r1, kW1, b1, fs[1], fs[3]);
+    pair(uy, Fy, r1, kW1, b1, fs[2], fs[4]);
+    pair(ux + uy, Fx + Fy, r5, kW5, b5, fs[5], fs[7]);
+    pair(uy - ux, Fy - Fx, r5, kW5, b5, fs[6], fs[8]);
+    const double rest = ((fs[1] + fs[2]) + (fs[3] + fs[4])) + ((fs[5] + fs[6]) + (fs[7] + fs[8]));
+    fs[0] = rho - rest;
+}
+
+// Next level's mass contribution of a node's post-collision set: a
+// population moving into a wall layer is counted twice by that wall's
+// reconstruction; one leaving through a wall is not counted.
+template <bool WALLS>
+__device__ __forceinline__ double next_mass(const double v[9], int gy, int ny)
+{
+    double nm = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7])) + v[8];
+    if (WALLS) {
+        const double down = (v[4] + v[7]) + v[8], up = (v[2] + v[5]) + v[6];
+        if (gy == 0) nm -= down;
+        if (gy == 1) nm += down;
+        if (gy == ny - 2) nm += up;
+        if (gy == ny - 1) nm -= up;
+    }
+    return nm;
+}
+
 // Register-resident pulled populations of the region nodes one thread owns
 // in phase 1 (raw stored values; converted when consumed).  All of them are
 // loaded before the first is used, so a tile costs one memory round trip.
@@ -279,21 +370,8 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step(const S *__res
                 double f[9];
 #pragma unroll
                 for (int i = 0; i < 9; ++i) f[i] = PopIO<S>::load(pre.f[k], i, wref[i]);
-                if (WALLS && q.bot) {  // Zou-He, zero wall velocity: unknowns 2, 5, 6
-                    const double d = f[1] - f[3];
-                    f[2] = f[4];
-                    f[5] = f[7] - 0.5 * d;
-                    f[6] = f[8] + 0.5 * d;
-                }
-                if (WALLS && q.top) {  // unknowns 4, 7, 8
-                    const double d = f[1] - f[3];
-                    f[4] = f[2];
-                    f[7] = f[5] + 0.5 * d;
-                    f[8] = f[6] - 0.5 * d;
-                }
-                double rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
-                double jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
-                double jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+                double rho, jx, jy;
+                pulled_moments(f, WALLS && q.bot, WALLS && q.top, rho, jx, jy);
                 double Z = 0.0, psi = 0.0, T = pre.T[k];
                 if (q.valid) {
                     psi = psi_and_Z(c, rho, T, Z);
@@ -325,19 +403,8 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step(const S *__res
             }
             if (!valid) continue;
             const double rho = s_rho[r];
-            double Fx = 0.0, Fy = 0.0;
-            if (!wall) {
-                Stencil p;
-                const int c3 = (ry + 1) * W3 + (rx + 1);
-                p.load(s_psi, c3, W3);
-                // sum_i w(|c_i|^2) psi(x + c_i) c_i with w(1) = 1/3, w(2) = 1/12
-                const double sx = (p.e - p.w) * (1.0 / 3.0) + ((p.ne + p.se) - (p.nw + p.sw)) * (1.0 / 12.0);
-                const double sy = (p.n - p.s) * (1.0 / 3.0) + ((p.ne + p.nw) - (p.se + p.sw)) * (1.0 / 12.0);
-                const double mg = -c.G * s_psi[c3];
-                const double fg = (c.form == 2) ? -(rho - mean) * c.g : -rho * c.g;
-                Fx = mg * sx;
-                Fy = mg * sy + fg;
-            }
+            double Fx, Fy, X;
+            node_force(c, s_psi, (ry + 1) * W3 + (rx + 1), W3, rho, mean, wall, Fx, Fy, X);
             const double inv = rcp_pos(rho);
             s_ux[r] = (s_ux[r] + 0.5 * Fx) * inv;
             s_uy[r] = (s_uy[r] + 0.5 * Fy) * inv;
@@ -390,51 +457,13 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step(const S *__res
             Tout[g] = Tn;
 
             // forces (again, from the LDS psi) for the collision
-            double Fx = 0.0, Fy = 0.0, X = 0.0;
+            double Fx, Fy, X;
             const double psi0 = s_psi[c3];
-            if (!wall) {
-                Stencil p;
-                p.load(s_psi, c3, W3);
-                const double sx = (p.e - p.w) * (1.0 / 3.0) + ((p.ne + p.se) - (p.nw + p.sw)) * (1.0 / 12.0);
-                const double sy = (p.n - p.s) * (1.0 / 3.0) + ((p.ne + p.nw) - (p.se + p.sw)) * (1.0 / 12.0);
-                const double mg = -c.G * psi0;
-                const double fg = (c.form == 2) ? -(rho - mean) * c.g : -rho * c.g;
-                Fx = mg * sx;
-                Fy = mg * sy + fg;
-                // |F_int|^2 / psi^2 = G^2 |sum w psi c|^2
-                X = c.G2 * (sx * sx + sy * sy);
-            }
+            node_force(c, s_psi, c3, W3, rho, mean, wall, Fx, Fy, X);
 
             double fs[9];
             if (TAU1) {
-                // every rate 1: f* = f_eq(rho, u) + F', F' = M^-1 (S/2) =
-                // w_i [3/2 (c - u).F + 9/2 (c.u)(c.F)] + sigma X (-8, 1, ..., 1)/36.
-                // The rest population is closed by mass conservation,
-                // f*_0 = rho - sum_{i>0} f*_i (exact in exact arithmetic), so
-                // the collision adds no systematic rounding drift to the mass.
-                // Opposite velocities share the even part of f_eq + F' and
-                // differ in the sign of the odd part: per pair (i, i')
-                // f*_i = E + O, f*_i' = E - O with
-                // E = w rho (1 - 3/2 u^2 + 9/2 (c.u)^2) + w (9/2 (c.u)(c.F) - 3/2 u.F) + sigma X/36
-                // O = w (3 rho c.u + 3/2 c.F)
-                const double uu = ux * ux + uy * uy;
-                const double uF = ux * Fx + uy * Fy;
-                const double sx36 = c.sigma * X * (1.0 / 36.0);
-                const double r1 = kW1 * rho, r5 = kW5 * rho;
-                const double b1 = r1 * (1.0 - 1.5 * uu) - kW1 * 1.5 * uF + sx36;
-                const double b5 = r5 * (1.0 - 1.5 * uu) - kW5 * 1.5 * uF + sx36;
-                auto pair = [&](double cu, double cF, double wr, double wi, double base, double &fp, double &fm) {
-                    const double E = base + 4.5 * cu * (wr * cu + wi * cF);
-                    const double O = 3.0 * wr * cu + 1.5 * wi * cF;
-                    fp = E + O;
-                    fm = E - O;
-                };
-                pair(ux, Fx, r1, kW1, b1, fs[1], fs[3]);
-                pair(uy, Fy, r1, kW1, b1, fs[2], fs[4]);
-                pair(ux + uy, Fx + Fy, r5, kW5, b5, fs[5], fs[7]);
-                pair(uy - ux, Fy - Fx, r5, kW5, b5, fs[6], fs[8]);
-                double rest = ((fs[1] + fs[2]) + (fs[3] + fs[4])) + ((fs[5] + fs[6]) + (fs[7] + fs[8]));
-                fs[0] = rho - rest;
+                collide_tau1(c, rho, ux, uy, Fx, Fy, X, fs);
             } else {
                 // general relaxation times: moments m = M f of the pulled
                 // populations, relaxation toward m_eq, source (I - Lambda/2) S
@@ -514,20 +543,11 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step(const S *__res
                 fs[8] = d0 + 2.0 * d1 + d2 + d3 + d4 - d5 - d6 - d8;
             }
 
-            // stores, and the next level's mass: a population moving into a
-            // wall layer is counted twice by that wall's reconstruction; one
-            // leaving through a wall is not counted
+            // stores, and the next level's mass
             double v[9];
 #pragma unroll
             for (int i = 0; i < 9; ++i) v[i] = PopIO<S>::store(fout, (size_t)i * N + g, fs[i], wref[i]);
-            double nm = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7])) + v[8];
-            if (WALLS) {
-                const double down = (v[4] + v[7]) + v[8], up = (v[2] + v[5]) + v[6];
-                if (gy == 0) nm -= down;
-                if (gy == 1) nm += down;
-                if (gy == ny - 2) nm += up;
-                if (gy == ny - 1) nm -= up;
-            }
+            const double nm = next_mass<WALLS>(v, gy, ny);
             part.mass_n += rho;
             part.mass_next += nm;
             part.umax = fmax(part.umax, ux * ux + uy * uy);
@@ -544,6 +564,294 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step(const S *__res
     part = block_reduce<kThreads>(part, s_red, s_ured);
     finish_launch<kThreads>(part, partials, st, step, (int)((step + 1) & 1),
                             1.0 / (double)N, s_red, s_ured);
+}
+
+// ---------------------------------------------------------------------------
+// Moment-state update (every relaxation time 1, FP64).  With all rates 1 the
+// post-collision populations are a closed function of the node's density,
+// force-corrected velocity and force (collide_tau1), so the state between
+// launches can be the level's density and momentum instead of the nine
+// populations: the planes rho, j_x, j_y of M (and T^n).  One launch, per
+// TX x TY tile:
+//   phase 1, tile + 3: load rho, j, T; psi                       -> LDS
+//   phases 2, 3: as in the population kernel (force, velocity; k1)
+//   phase 4a, tile: T^{n+1}, stored; statistics of level n
+//   phase 4b, tile + 1: post-collision set f*(y) of every node (registers)
+//            and the next level's mass contribution of the tile nodes
+//   phase 4c: three rounds of three directions through LDS planes: each
+//            tile node x pulls f*_i(x - c_i)
+//   phase 4d, tile: Zou-He and the moments of the pulled set -> M^{n+1}.
+// Phases 4b-4d evaluate the same source expressions, in the same order, as
+// the population kernel's collision, store, pull and moment sums (shared
+// functions), so the two states agree to rounding: the compiler may fuse
+// multiply-adds in different places in the two kernels, and the blocks sum
+// the next level's mass over another tiling.
+// ---------------------------------------------------------------------------
+template <bool WALLS, int TX, int TY, int NT, int MIN_WAVES_PER_EU>
+__global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step_mom(const double *__restrict__ Min,
+                                                             double *__restrict__ Mout,
+                                                             const double *__restrict__ Tin,
+                                                             double *__restrict__ Tout, Phys c,
+                                                             int nx, int ny, int tiles_x, int ntiles,
+                                                             double *__restrict__ partials,
+                                                             StepState *__restrict__ st, int64_t step)
+{
+    constexpr int W3 = TX + 6, H3 = TY + 6;
+    constexpr int W2 = TX + 4, H2 = TY + 4;
+    constexpr int W1 = TX + 2, H1 = TY + 2;
+    constexpr int R3N = H3 * W3, R2N = H2 * W2, R1N = H1 * W1, RTN = TX * TY;
+    constexpr int NS3 = (R3N + NT - 1) / NT, NS1 = (R1N + NT - 1) / NT, NST = (RTN + NT - 1) / NT;
+    static_assert(R1N <= R2N && RTN <= R2N, "exchange planes must fit the tile + 2 arrays");
+    __shared__ double s_psi[R3N];
+    __shared__ double s_rho[R2N];
+    __shared__ double s_T[R2N];
+    __shared__ double s_ux[R2N];
+    __shared__ double s_uy[R2N];
+    __shared__ double s_Z[R2N];
+    __shared__ double s_k1[R1N];
+    __shared__ double s_red[4 * NT / 64];
+    __shared__ unsigned s_ured[NT / 64];
+    double *const plane[3] = {s_k1, s_T, s_Z};  // free once T^{n+1} is stored
+    constexpr int kCx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    constexpr int kCy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+
+    const int tid = threadIdx.x;
+    const size_t N = (size_t)nx * ny;
+    const double mean = st->mean[step & 1];
+
+    const int nb = gridDim.x;
+    const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+    const int per_xcd_blocks = nb >> 3;
+    const int tiles_per_xcd = (ntiles + 7) >> 3;
+    const int t_begin = xcd * tiles_per_xcd;
+    const int t_end = min(ntiles, t_begin + tiles_per_xcd);
+
+    // global column / row of a region coordinate (periodic wrap; rows beyond
+    // a wall are reported invalid)
+    auto col_of = [&](int x) { return (x >= 0 && x < nx) ? x : wrapi(x, nx); };
+    auto row_of = [&](int y, bool &valid) {
+        if (WALLS) {
+            valid = (y >= 0 && y < ny);
+            return valid ? y : 0;
+        }
+        valid = true;
+        return (y >= 0 && y < ny) ? y : wrapi(y, ny);
+    };
+
+    Partial part = {0.0, 0.0, 0.0, 1e300, 0u};
+    for (int t = t_begin + slot; t < t_end; t += per_xcd_blocks) {
+        const int x0 = (t % tiles_x) * TX, y0 = (t / tiles_x) * TY;
+
+        // ---- phase 1: rho, j, T, psi on tile + 3 ----
+        double lr[NS3], ljx[NS3], ljy[NS3], lT[NS3];
+#pragma unroll
+        for (int k = 0; k < NS3; ++k) {
+            const int r = tid + k * NT;
+            lr[k] = ljx[k] = ljy[k] = lT[k] = 0.0;
+            if (r < R3N) {
+                const int ry = r / W3, rx = r - ry * W3;
+                bool valid;
+                const int gy = row_of(y0 + ry - 3, valid);
+                if (valid) {
+                    const size_t g = (size_t)gy * nx + col_of(x0 + rx - 3);
+                    lr[k] = Min[g];
+                    ljx[k] = Min[N + g];
+                    ljy[k] = Min[2 * N + g];
+                    lT[k] = Tin[g];
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NS3; ++k) {
+            const int r = tid + k * NT;
+            if (r < R3N) {
+                const int ry = r / W3, rx = r - ry * W3;
+                bool valid;
+                row_of(y0 + ry - 3, valid);
+                double Z = 0.0, psi = 0.0;
+                if (valid) psi = psi_and_Z(c, lr[k], lT[k], Z);
+                s_psi[r] = psi;
+                if (rx >= 1 && rx < W3 - 1 && ry >= 1 && ry < H3 - 1) {
+                    const int qi = (ry - 1) * W2 + (rx - 1);
+                    s_rho[qi] = lr[k];
+                    s_T[qi] = lT[k];
+                    s_ux[qi] = ljx[k];
+                    s_uy[qi] = ljy[k];
+                    s_Z[qi] = Z;
+                }
+            }
+        }
+        __syncthreads();
+
+        // ---- phase 2: force and force-corrected velocity on tile + 2 ----
+        for (int r = tid; r < R2N; r += NT) {
+            const int ry = r / W2, rx = r - ry * W2;
+            const int gy = y0 + ry - 2;
+            bool valid = true, wall = false;
+            if (WALLS) {
+                valid = (gy >= 0 && gy < ny);
+                wall = (gy == 0 || gy == ny - 1);
+            }
+            if (!valid) continue;
+            const double rho = s_rho[r];
+            double Fx, Fy, X;
+            node_force(c, s_psi, (ry + 1) * W3 + (rx + 1), W3, rho, mean, wall, Fx, Fy, X);
+            const double inv = rcp_pos(rho);
+            s_ux[r] = (s_ux[r] + 0.5 * Fx) * inv;
+            s_uy[r] = (s_uy[r] + 0.5 * Fy) * inv;
+        }
+        __syncthreads();
+
+        // ---- phase 3: first Heun stage on tile + 1 ----
+        for (int r = tid; r < R1N; r += NT) {
+            const int ry = r / W1, rx = r - ry * W1;
+            const int gy = y0 + ry - 1;
+            const int c2 = (ry + 1) * W2 + (rx + 1);
+            if (WALLS && (gy <= 0 || gy >= ny - 1)) {
+                s_k1[r] = 0.0;  // Dirichlet walls (and nodes beyond them): T~ = T
+                continue;
+            }
+            const double divu = divergence(s_ux, s_uy, c2, W2);
+            Stencil tt;
+            tt.load(s_T, c2, W2);
+            s_k1[r] = energy_rhs(c, tt, s_T[c2], s_ux[c2], s_uy[c2], divu, rcp_pos(s_rho[c2]), s_Z[c2]);
+        }
+        __syncthreads();
+
+        // ---- phase 4a: second Heun stage and T^{n+1}; level-n statistics ----
+        for (int r = tid; r < RTN; r += NT) {
+            const int ry = r / TX, rx = r - ry * TX;
+            const int gx = x0 + rx, gy = y0 + ry;
+            if (gx >= nx || gy >= ny) continue;
+            const int c2 = (ry + 2) * W2 + (rx + 2);
+            const int c1 = (ry + 1) * W1 + (rx + 1);
+            const int c3 = (ry + 3) * W3 + (rx + 3);
+            const bool wall = WALLS && (gy == 0 || gy == ny - 1);
+            const double rho = s_rho[c2], ux = s_ux[c2], uy = s_uy[c2], T = s_T[c2];
+            double Tn = T;
+            if (!wall) {
+                const double divu = divergence(s_ux, s_uy, c2, W2);
+                Stencil tt, kk;  // T~ = T^n + k1 at the node and its neighbours
+                tt.load(s_T, c2, W2);
+                kk.load(s_k1, c1, W1);
+                tt.e += kk.e; tt.w += kk.w; tt.n += kk.n; tt.s += kk.s;
+                tt.ne += kk.ne; tt.nw += kk.nw; tt.sw += kk.sw; tt.se += kk.se;
+                const double k1 = s_k1[c1];
+                const double k2 = energy_rhs(c, tt, T + k1, ux, uy, divu, rcp_pos(rho), s_Z[c2]);
+                Tn = T + 0.5 * (k1 + k2);
+            }
+            Tout[(size_t)gy * nx + gx] = Tn;
+            part.mass_n += rho;
+            part.umax = fmax(part.umax, ux * ux + uy * uy);
+            part.rmin = fmin(part.rmin, rho);
+            unsigned fl = 0u;
+            if (!(rho > 0.0)) fl |= kFlagRho;
+            if (c.eos == 0 && c.b_quarter * rho >= 1.0) fl |= kFlagEta;
+            if (s_psi[c3] != s_psi[c3]) fl |= kFlagPsi;
+            if (rho != rho || ux != ux || uy != uy || Tn != Tn) fl |= kFlagNaN;
+            part.flags |= fl;
+        }
+
+        // ---- phase 4b: post-collision sets of tile + 1 (registers) ----
+        double fsr[NS1][9];
+        double nm_own[NS1];
+#pragma unroll
+        for (int k = 0; k < NS1; ++k) {
+            const int r = tid + k * NT;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) fsr[k][i] = 0.0;
+            nm_own[k] = 0.0;
+            if (r < R1N) {
+                const int ry = r / W1, rx = r - ry * W1;
+                const int gy = y0 + ry - 1;
+                bool valid = true, wall = false;
+                if (WALLS) {
+                    valid = (gy >= 0 && gy < ny);
+                    wall = (gy == 0 || gy == ny - 1);
+                }
+                if (valid) {
+                    const int c2 = (ry + 1) * W2 + (rx + 1);
+                    const int c3 = (ry + 2) * W3 + (rx + 2);
+                    const double rho = s_rho[c2];
+                    double Fx, Fy, X;
+                    node_force(c, s_psi, c3, W3, rho, mean, wall, Fx, Fy, X);
+                    collide_tau1(c, rho, s_ux[c2], s_uy[c2], Fx, Fy, X, fsr[k]);
+                    // the next level's mass of the tile nodes (periodic y
+                    // wraps rows: only nodes of the tile itself count)
+                    const int ty = ry - 1, tx = rx - 1;
+                    if (ty >= 0 && ty < TY && tx >= 0 && tx < TX && x0 + tx < nx && y0 + ty < ny)
+                        nm_own[k] = next_mass<WALLS>(fsr[k], y0 + ty, ny);
+                }
+            }
+        }
+        __syncthreads();  // every read of s_rho, s_ux, s_uy, s_T, s_Z, s_k1 is done
+
+        // the tile nodes' mass contributions, accumulated below in the tile
+        // loop's node order (s_rho is free now)
+#pragma unroll
+        for (int k = 0; k < NS1; ++k) {
+            const int r = tid + k * NT;
+            if (r < R1N) {
+                const int ry = r / W1, rx = r - ry * W1;
+                const int ty = ry - 1, tx = rx - 1;
+                if (ty >= 0 && ty < TY && tx >= 0 && tx < TX) s_rho[ty * TX + tx] = nm_own[k];
+            }
+        }
+
+        // ---- phase 4c: pull through three rounds of three planes ----
+        double fp[NST][9];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+#pragma unroll
+            for (int k = 0; k < NS1; ++k) {
+                const int r = tid + k * NT;
+                if (r < R1N) {
+                    plane[0][r] = fsr[k][3 * q];
+                    plane[1][r] = fsr[k][3 * q + 1];
+                    plane[2][r] = fsr[k][3 * q + 2];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < NST; ++k) {
+                const int r = tid + k * NT;
+                if (r < RTN) {
+                    const int ry = r / TX, rx = r - ry * TX;
+                    const int d1 = (ry + 1) * W1 + (rx + 1);
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        const int i = 3 * q + j;
+                        fp[k][i] = plane[j][d1 - kCy[i] * W1 - kCx[i]];
+                    }
+                }
+            }
+            __syncthreads();
+        }
+
+        // ---- phase 4d: moments of the pulled sets, stores, next mass ----
+#pragma unroll
+        for (int k = 0; k < NST; ++k) {
+            const int r = tid + k * NT;
+            if (r < RTN) {
+                const int ry = r / TX, rx = r - ry * TX;
+                const int gx = x0 + rx, gy = y0 + ry;
+                if (gx < nx && gy < ny) {
+                    double rho, jx, jy;
+                    pulled_moments(fp[k], WALLS && gy == 0, WALLS && gy == ny - 1, rho, jx, jy);
+                    const size_t g = (size_t)gy * nx + gx;
+                    Mout[g] = rho;
+                    Mout[N + g] = jx;
+                    Mout[2 * N + g] = jy;
+                    const double nm = s_rho[r];
+                    part.mass_next += nm;
+                    if (nm != nm) part.flags |= kFlagNaN;
+                }
+            }
+        }
+        __syncthreads();  // LDS is rewritten by the next tile's phase 1
+    }
+    part = block_reduce<NT>(part, s_red, s_ured);
+    finish_launch<NT>(part, partials, st, step, (int)((step + 1) & 1), 1.0 / (double)N, s_red, s_ured);
 }
 
 // ---------------------------------------------------------------------------
@@ -599,6 +907,22 @@ __global__ void d2q9_readout_a(const S *__restrict__ fin, const double *__restri
         scr[N + g] = psi_and_Z(c, rho, Tin[g], Z);
         scr[2 * N + g] = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
         scr[3 * N + g] = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+    }
+}
+
+// Readout kernel A for the moment state: the level's rho and j are stored.
+__global__ void d2q9_readout_a_mom(const double *__restrict__ M, const double *__restrict__ Tin, Phys c,
+                                   int nx, int ny, double *__restrict__ scr /* 4N */)
+{
+    const size_t N = (size_t)nx * ny;
+    for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < N;
+         g += (size_t)gridDim.x * blockDim.x) {
+        const double rho = M[g];
+        double Z;
+        scr[g] = rho;
+        scr[N + g] = psi_and_Z(c, rho, Tin[g], Z);
+        scr[2 * N + g] = M[N + g];
+        scr[3 * N + g] = M[2 * N + g];
     }
 }
 
@@ -663,6 +987,9 @@ __global__ void d2q9_readout_b(const double *__restrict__ scr, const double *__r
 // Tile of 64 x 32 nodes per block of 1024 threads (16 wavefronts): the LDS
 // staging of a tile (about 137 KB) allows one block per compute unit.
 constexpr int kTX = 64, kTY = 32, kNT = 1024;
+// The moment kernel's tile is 29 rows high so that its tile + 1 ring
+// (66 x 31 = 2046 nodes) takes two slots of 1024 threads (about 126 KB of LDS).
+constexpr int kTYm = 29;
 
 template <class S, bool TAU1, bool WALLS>
 hipError_t launch_t(const LatticeLaunch &L)
@@ -682,13 +1009,26 @@ hipError_t launch_t(const LatticeLaunch &L)
     return hipGetLastError();
 }
 
+template <bool WALLS>
+hipError_t launch_mom(const LatticeLaunch &L)
+{
+    const int tiles_x = (L.nx + kTX - 1) / kTX, tiles_y = (L.ny + kTYm - 1) / kTYm;
+    const int ntiles = tiles_x * tiles_y;
+    const int nb = d2q9_num_blocks(L.nx, L.ny, L.resident, true);
+    hipLaunchKernelGGL((d2q9_step_mom<WALLS, kTX, kTYm, kNT, 4>), dim3(nb), dim3(kNT), 0, L.stream,
+                       (const double *)L.fin, (double *)L.fout, L.Tin, L.Tout, L.phys, L.nx, L.ny, tiles_x,
+                       ntiles, L.partials, L.st, L.step);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 // Persistent grid: one block per compute unit (at most one per tile), a
 // multiple of 8 so that every XCD gets the same number of blocks.
-int d2q9_num_blocks(int nx, int ny, int cus)
+int d2q9_num_blocks(int nx, int ny, int cus, bool moments)
 {
-    const int ntiles = ((nx + kTX - 1) / kTX) * ((ny + kTY - 1) / kTY);
+    const int ty = moments ? kTYm : kTY;
+    const int ntiles = ((nx + kTX - 1) / kTX) * ((ny + ty - 1) / ty);
     int nb = ntiles < cus ? ntiles : cus;
     nb = ((nb + 7) / 8) * 8;
     return nb;
@@ -696,6 +1036,7 @@ int d2q9_num_blocks(int nx, int ny, int cus)
 
 hipError_t d2q9_launch_step(const LatticeLaunch &L)
 {
+    if (L.moments) return L.walls ? launch_mom<true>(L) : launch_mom<false>(L);
     if (L.fp32) {
         if (L.tau1) return L.walls ? launch_t<float, true, true>(L) : launch_t<float, true, false>(L);
         return L.walls ? launch_t<float, false, true>(L) : launch_t<float, false, false>(L);
@@ -709,7 +1050,10 @@ hipError_t d2q9_launch_readout(const LatticeLaunch &L, int field, double *scratc
     const size_t N = (size_t)L.nx * L.ny;
     const int threads = 256;
     const int blocks = (int)((N + threads - 1) / threads < 65535 ? (N + threads - 1) / threads : 65535);
-    if (L.fp32) {
+    if (L.moments) {
+        hipLaunchKernelGGL(d2q9_readout_a_mom, dim3(blocks), dim3(threads), 0, L.stream, (const double *)L.fin,
+                           L.Tin, L.phys, L.nx, L.ny, scratch);
+    } else if (L.fp32) {
         if (L.walls)
             hipLaunchKernelGGL((d2q9_readout_a<float, true>), dim3(blocks), dim3(threads), 0, L.stream,
                                (const float *)L.fin, L.Tin, L.phys, L.nx, L.ny, scratch);

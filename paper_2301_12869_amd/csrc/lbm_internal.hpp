@@ -16,6 +16,7 @@ struct LatticeLaunch {
     Phys phys;
     int nx, ny, nz;
     bool fp32, tau1, walls;
+    bool moments;         // D2Q9 state is (rho, j_x, j_y) planes instead of populations
     int resident;         // blocks of the persistent grid (two per compute unit)
     double *partials;     // 5 doubles per block
     StepState *st;
@@ -28,7 +29,7 @@ constexpr int kD3Q19x[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0
 constexpr int kD3Q19y[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
 constexpr int kD3Q19z[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
 
-int d2q9_num_blocks(int nx, int ny, int resident);
+int d2q9_num_blocks(int nx, int ny, int resident, bool moments = false);
 int d3q19_num_blocks(int nx, int ny, int nz, int cus);
 hipError_t d3q19_launch_step(const LatticeLaunch &L, double *M, double *U, double *K1);
 hipError_t d3q19_launch_readout(const LatticeLaunch &L, int field, double *M, double *U, double *out);

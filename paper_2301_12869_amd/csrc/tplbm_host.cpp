@@ -32,6 +32,8 @@ struct tplbm_ctx {
     int resident = 0;
     size_t N = 0;
     int Q = 9;
+    bool mom = false;  // D2Q9 state carried as (rho, j_x, j_y) planes
+    int planes = 9;    // state planes per node between steps (Q, or 3 with mom)
     Phys phys;
     bool have_state = false;
     std::string err;
@@ -71,6 +73,14 @@ bool tau_one(const tplbm_params &p)
     return true;
 }
 
+// The moment state applies where the post-collision set is a closed function
+// of (rho, u, F): D2Q9, every rate 1; FP64 so that it carries exactly what
+// the population state would.
+bool uses_moments(const tplbm_params &p)
+{
+    return p.lattice == TPLBM_D2Q9 && p.precision == TPLBM_FP64 && tau_one(p) && p.state == TPLBM_STATE_AUTO;
+}
+
 int validate(const tplbm_params *p)
 {
     if (!p) return fail(nullptr, TPLBM_EINVAL, "params is NULL");
@@ -102,6 +112,8 @@ int validate(const tplbm_params *p)
     }
     if (!(p->cv > 0) || !(p->kappa >= 0)) return fail(nullptr, TPLBM_EINVAL, "need c_v > 0, kappa >= 0");
     if (!std::isfinite(p->g) || !std::isfinite(p->sigma)) return fail(nullptr, TPLBM_EINVAL, "g and sigma must be finite");
+    if (p->state != TPLBM_STATE_AUTO && p->state != TPLBM_STATE_POPULATIONS)
+        return fail(nullptr, TPLBM_EINVAL, "state must be TPLBM_STATE_AUTO or TPLBM_STATE_POPULATIONS");
     if (p->precision == TPLBM_FP32_DEV && !std::isfinite(p->rho_ref))
         return fail(nullptr, TPLBM_EINVAL, "rho_ref must be finite");
     return TPLBM_OK;
@@ -155,11 +167,13 @@ Layout layout_of(const tplbm_params &p)
         L.pass_bytes = align256(5 * N * 8) + align256(7 * N * 8) + align256(2 * N * 8);
         L.nblocks = d3q19_num_blocks(p.nx, p.ny, p.nz, 1 << 20);
     } else {
-        // readout scratch reuses the idle population buffer: it needs 4N doubles
+        // the moment state holds 3 planes; the readout scratch reuses the
+        // idle state buffer and needs 4N doubles
+        if (uses_moments(p)) L.f_bytes = align256(3 * N * 8);
         if (L.f_bytes < align256(4 * N * 8)) L.f_bytes = align256(4 * N * 8);
         L.pass_bytes = 0;
         // partials for the largest grid the persistent launch can use
-        L.nblocks = d2q9_num_blocks(p.nx, p.ny, 1 << 20);
+        L.nblocks = d2q9_num_blocks(p.nx, p.ny, 1 << 20, uses_moments(p));
     }
     L.part_bytes = align256((size_t)L.nblocks * 5 * 8);
     L.st_bytes = align256(sizeof(StepState));
@@ -191,6 +205,7 @@ LatticeLaunch launch_of(tplbm_ctx *c)
     L.fp32 = c->p.precision == TPLBM_FP32_DEV;
     L.tau1 = tau_one(c->p);
     L.walls = c->p.walls != 0;
+    L.moments = c->mom;
     L.resident = c->resident;
     L.partials = c->partials;
     L.st = c->st;
@@ -235,6 +250,8 @@ int tplbm_create(const tplbm_params *p, void *dev_workspace, size_t bytes, void 
     c->resident = resident_blocks();
     c->N = nodes_of(*p);
     c->Q = q_of(*p);
+    c->mom = uses_moments(*p);
+    c->planes = c->mom ? 3 : c->Q;
     c->nblocks = L.nblocks;
     char *q = c->ws;
     c->f[0] = q; q += L.f_bytes;
@@ -288,8 +305,26 @@ int tplbm_set_state(tplbm_ctx *c, const double *rho0, const double *T0)
     // The wall-normal axis is y in 2-D and z in 3-D.
     std::vector<double> fd;
     std::vector<float> ff;
-    if (fp32) ff.resize((size_t)Q * N); else fd.resize((size_t)Q * N);
-    for (int z = 0; z < nz; ++z)
+    if (c->mom) {
+        // The pulled level-0 set is f_i = w_i rho0(x) at every node (the
+        // wall reconstruction returns the same values): store its density
+        // and momentum, summed as the kernels sum a pulled set.
+        fd.resize(3 * N);
+        for (size_t n = 0; n < N; ++n) {
+            // the kernels add loaded values: no product may fuse into a sum here
+#pragma clang fp contract(off)
+            double f[9];
+            for (int i = 0; i < 9; ++i) f[i] = w[i] * rho0[n];
+            fd[n] = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+            fd[N + n] = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+            fd[2 * N + n] = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+        }
+    } else if (fp32) {
+        ff.resize((size_t)Q * N);
+    } else {
+        fd.resize((size_t)Q * N);
+    }
+    for (int z = 0; z < nz && !c->mom; ++z)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
                 const size_t n = ((size_t)z * ny + y) * nx + x;
@@ -323,7 +358,7 @@ int tplbm_set_state(tplbm_ctx *c, const double *rho0, const double *T0)
     if (fp32)
         HIP_OK(c, hipMemcpyAsync(c->f[0], ff.data(), (size_t)Q * N * 4, hipMemcpyHostToDevice, c->stream));
     else
-        HIP_OK(c, hipMemcpyAsync(c->f[0], fd.data(), (size_t)Q * N * 8, hipMemcpyHostToDevice, c->stream));
+        HIP_OK(c, hipMemcpyAsync(c->f[0], fd.data(), fd.size() * 8, hipMemcpyHostToDevice, c->stream));
     HIP_OK(c, hipMemcpyAsync(c->T[0], T0, N * 8, hipMemcpyHostToDevice, c->stream));
     StepState s;
     std::memset(&s, 0, sizeof s);
@@ -421,7 +456,7 @@ int tplbm_state_bytes(const tplbm_ctx *c, size_t *bytes)
 {
     if (!c || !bytes) return fail(nullptr, TPLBM_EINVAL, "NULL argument");
     const size_t elem = c->p.precision == TPLBM_FP32_DEV ? 4 : 8;
-    *bytes = 64 + (size_t)c->Q * c->N * elem + c->N * 8 + sizeof(StepState);
+    *bytes = 64 + (size_t)c->planes * c->N * elem + c->N * 8 + sizeof(StepState);
     return TPLBM_OK;
 }
 
@@ -447,13 +482,13 @@ int tplbm_save_state(tplbm_ctx *c, void *host_blob)
     std::memcpy(h.magic, "TPLBMST1", 8);
     h.step = c->step;
     h.N = (int64_t)c->N;
-    h.Q = c->Q;
+    h.Q = c->planes;
     h.elem = (int32_t)elem;
     h.nx = c->p.nx;
     h.ny = c->p.ny;
     char *b = (char *)host_blob;
     std::memcpy(b, &h, sizeof h);
-    const size_t fb = (size_t)c->Q * c->N * elem;
+    const size_t fb = (size_t)c->planes * c->N * elem;
     HIP_OK(c, hipMemcpyAsync(b + 64, c->f[c->cur], fb, hipMemcpyDeviceToHost, c->stream));
     HIP_OK(c, hipMemcpyAsync(b + 64 + fb, c->T[c->cur], c->N * 8, hipMemcpyDeviceToHost, c->stream));
     HIP_OK(c, hipMemcpyAsync(b + 64 + fb + c->N * 8, c->st, sizeof(StepState),
@@ -469,12 +504,12 @@ int tplbm_load_state(tplbm_ctx *c, const void *host_blob)
     BlobHeader h;
     std::memcpy(&h, host_blob, sizeof h);
     if (std::memcmp(h.magic, "TPLBMST1", 8) != 0 || h.N != (int64_t)c->N || h.elem != (int32_t)elem ||
-        h.nx != c->p.nx || h.ny != c->p.ny || h.Q != c->Q)
+        h.nx != c->p.nx || h.ny != c->p.ny || h.Q != c->planes)
         return fail(c, TPLBM_ESHAPE, "checkpoint does not match this lattice");
     const char *b = (const char *)host_blob;
     c->cur = 0;
     c->step = h.step;
-    const size_t fb = (size_t)c->Q * c->N * elem;
+    const size_t fb = (size_t)c->planes * c->N * elem;
     HIP_OK(c, hipMemcpyAsync(c->f[0], b + 64, fb, hipMemcpyHostToDevice, c->stream));
     HIP_OK(c, hipMemcpyAsync(c->T[0], b + 64 + fb, c->N * 8, hipMemcpyHostToDevice, c->stream));
     StepState s;

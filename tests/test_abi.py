@@ -60,9 +60,13 @@ def test_invalid_parameters_are_rejected_on_the_host(lib):
     nb = ctypes.c_size_t()
     good = T.make_params(T.D2Q9, nx=4, ny=8)
     assert lib.tplbm_workspace_bytes(ctypes.byref(good), ctypes.byref(nb)) == T.OK
+    # FP64 with every rate 1 keeps (rho, j) planes (readout scratch 4 planes)
+    assert nb.value > 2 * 4 * 32 * 8 + 2 * 32 * 8
+    pop = T.make_params(T.D2Q9, nx=4, ny=8, state=T.STATE_POPULATIONS)
+    assert lib.tplbm_workspace_bytes(ctypes.byref(pop), ctypes.byref(nb)) == T.OK
     assert nb.value > 2 * 9 * 32 * 8
     cases = [dict(ny=2), dict(tau=(1, 1, 1, 1, 1, 0.5)), dict(G=1.0), dict(gravity_form=3),
-             dict(precision=7), dict(lattice=5)]
+             dict(precision=7), dict(lattice=5), dict(state=2)]
     for over in cases:
         kw = dict(lattice=T.D2Q9, nx=4, ny=8)
         kw.update(over)

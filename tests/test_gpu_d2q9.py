@@ -151,6 +151,44 @@ def test_tiles_edges_and_relaxation_times(T, orc, crit, walls, form, taus, shape
     _check_fields(got, want, FP64_TOL, FP64_TOL * 1e-1)
 
 
+@pytest.mark.parametrize("walls,form,shape", [
+    (True, 1, (70, 61)),    # ragged in both tilings
+    (False, 1, (65, 33)),   # periodic
+    (True, 1, (1, 40)),     # one column
+    (True, 1, (5, 3)),      # minimum height
+    (True, 2, (100, 37)),
+    (True, 2, (130, 90)),   # several tiles each way
+])
+def test_moment_state_matches_the_population_state(T, orc, crit, walls, form, shape):
+    """FP64 with every rate 1 carries (rho, j) between steps by default; the
+    population state (TPLBM_STATE_POPULATIONS) on the same inputs runs the
+    same source expressions, so the fields agree to rounding (measured
+    3e-16 after 500 steps: the compiler fuses multiply-adds in other places
+    in the two kernels, and form 2's mean is summed over another tiling).
+    Bound: 1e-13 of each field's scale, far inside the 1e-12 oracle bar."""
+    _log(f"case moments walls={walls} form={form} shape={shape}")
+    _, T_c, _ = crit
+    nx, ny = shape
+    P = orc.make_params("D2Q9", nx=nx, ny=ny)
+    rv, rl, _ = orc.coexistence(P, 0.8 * T_c)
+    rho0 = W.layered_density((ny, nx), max(1, ny // 3), rl, rv, 2e-2, seed=nx * 77 + ny)
+    T0 = (0.8 + 0.02 * W.uniform_pm1(9, nx * ny)).reshape(ny, nx) * T_c
+    if walls:
+        T0[0] = 0.86 * T_c
+        T0[-1] = 0.77 * T_c
+    kw = dict(nx=nx, ny=ny, walls=walls, g=1e-4, gravity_form=form)
+    pop = _run_gpu(T, dict(kw, state=T.STATE_POPULATIONS), rho0, T0, 500)
+    mom = _run_gpu(T, kw, rho0, T0, 500)
+    for k in ("rho", "ux", "uy", "T", "p_nn"):
+        _log(f"  {k}: max |moments - populations| {np.abs(mom[k] - pop[k]).max():.3e}")
+    for k in ("rho", "T", "p_nn"):
+        assert np.abs(mom[k] - pop[k]).max() <= 1e-13 * np.abs(pop[k]).max(), k
+    for k in ("ux", "uy"):  # velocities: on the lattice sound-speed scale
+        assert np.abs(mom[k] - pop[k]).max() <= 1e-14, k
+    assert mom["diag"]["mass"] == pytest.approx(pop["diag"]["mass"], rel=1e-14)
+    assert mom["diag"]["flags"] == pop["diag"]["flags"] == 0
+
+
 def test_ideal_gas_and_strong_gravity(T, orc):
     _log("case ideal gas")
     nx, ny = 9, 30
