@@ -574,12 +574,13 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step(const S *__res
 // populations: the planes rho, j_x, j_y of M (and T^n).  One launch, per
 // TX x TY tile:
 //   phase 1, tile + 3: load rho, j, T; psi                       -> LDS
-//   phases 2, 3: as in the population kernel (force, velocity; k1)
+//   phases 2, 3: as in the population kernel (force, velocity; k1), and
+//            T~ = T^n + k1 and div u kept in LDS for the second stage
 //   phase 4a, tile: T^{n+1}, stored; statistics of level n
 //   phase 4b, tile + 1: post-collision set f*(y) of every node (registers)
 //            and the next level's mass contribution of the tile nodes
-//   phase 4c: three rounds of three directions through LDS planes: each
-//            tile node x pulls f*_i(x - c_i)
+//   phase 4c: two rounds of five and four directions through LDS planes:
+//            each tile node x pulls f*_i(x - c_i)
 //   phase 4d, tile: Zou-He and the moments of the pulled set -> M^{n+1}.
 // Phases 4b-4d evaluate the same source expressions, in the same order, as
 // the population kernel's collision, store, pull and moment sums (shared
@@ -608,10 +609,13 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step_mom(const doub
     __shared__ double s_ux[R2N];
     __shared__ double s_uy[R2N];
     __shared__ double s_Z[R2N];
-    __shared__ double s_k1[R1N];
+    __shared__ double s_k1[R1N];   // first Heun stage K(T^n)
+    __shared__ double s_Tt[R1N];   // T~ = T^n + k1
+    __shared__ double s_div[R1N];  // div u, for both Heun stages
     __shared__ double s_red[4 * NT / 64];
     __shared__ unsigned s_ured[NT / 64];
-    double *const plane[3] = {s_k1, s_T, s_Z};  // free once T^{n+1} is stored
+    constexpr int NP = 5;          // exchange planes, free once T^{n+1} is stored
+    double *const plane[NP] = {s_k1, s_Tt, s_div, s_T, s_Z};
     constexpr int kCx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
     constexpr int kCy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 
@@ -702,19 +706,25 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step_mom(const doub
         }
         __syncthreads();
 
-        // ---- phase 3: first Heun stage on tile + 1 ----
+        // ---- phase 3: first Heun stage on tile + 1; T~ and div u kept ----
         for (int r = tid; r < R1N; r += NT) {
             const int ry = r / W1, rx = r - ry * W1;
             const int gy = y0 + ry - 1;
             const int c2 = (ry + 1) * W2 + (rx + 1);
             if (WALLS && (gy <= 0 || gy >= ny - 1)) {
-                s_k1[r] = 0.0;  // Dirichlet walls (and nodes beyond them): T~ = T
+                // Dirichlet walls (and nodes beyond them): T~ = T
+                s_k1[r] = 0.0;
+                s_Tt[r] = s_T[c2] + 0.0;
+                s_div[r] = 0.0;
                 continue;
             }
             const double divu = divergence(s_ux, s_uy, c2, W2);
             Stencil tt;
             tt.load(s_T, c2, W2);
-            s_k1[r] = energy_rhs(c, tt, s_T[c2], s_ux[c2], s_uy[c2], divu, rcp_pos(s_rho[c2]), s_Z[c2]);
+            const double k1 = energy_rhs(c, tt, s_T[c2], s_ux[c2], s_uy[c2], divu, rcp_pos(s_rho[c2]), s_Z[c2]);
+            s_k1[r] = k1;
+            s_Tt[r] = s_T[c2] + k1;
+            s_div[r] = divu;
         }
         __syncthreads();
 
@@ -730,14 +740,10 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step_mom(const doub
             const double rho = s_rho[c2], ux = s_ux[c2], uy = s_uy[c2], T = s_T[c2];
             double Tn = T;
             if (!wall) {
-                const double divu = divergence(s_ux, s_uy, c2, W2);
-                Stencil tt, kk;  // T~ = T^n + k1 at the node and its neighbours
-                tt.load(s_T, c2, W2);
-                kk.load(s_k1, c1, W1);
-                tt.e += kk.e; tt.w += kk.w; tt.n += kk.n; tt.s += kk.s;
-                tt.ne += kk.ne; tt.nw += kk.nw; tt.sw += kk.sw; tt.se += kk.se;
+                Stencil tt;  // T~ = T^n + k1 at the node and its neighbours
+                tt.load(s_Tt, c1, W1);
                 const double k1 = s_k1[c1];
-                const double k2 = energy_rhs(c, tt, T + k1, ux, uy, divu, rcp_pos(rho), s_Z[c2]);
+                const double k2 = energy_rhs(c, tt, s_Tt[c1], ux, uy, s_div[c1], rcp_pos(rho), s_Z[c2]);
                 Tn = T + 0.5 * (k1 + k2);
             }
             Tout[(size_t)gy * nx + gx] = Tn;
@@ -798,17 +804,17 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step_mom(const doub
             }
         }
 
-        // ---- phase 4c: pull through three rounds of three planes ----
+        // ---- phase 4c: pull through two rounds of up to five planes ----
         double fp[NST][9];
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
+        for (int i0 = 0; i0 < 9; i0 += NP) {
 #pragma unroll
             for (int k = 0; k < NS1; ++k) {
                 const int r = tid + k * NT;
                 if (r < R1N) {
-                    plane[0][r] = fsr[k][3 * q];
-                    plane[1][r] = fsr[k][3 * q + 1];
-                    plane[2][r] = fsr[k][3 * q + 2];
+#pragma unroll
+                    for (int j = 0; j < NP; ++j)
+                        if (i0 + j < 9) plane[j][r] = fsr[k][i0 + j];
                 }
             }
             __syncthreads();
@@ -819,9 +825,9 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step_mom(const doub
                     const int ry = r / TX, rx = r - ry * TX;
                     const int d1 = (ry + 1) * W1 + (rx + 1);
 #pragma unroll
-                    for (int j = 0; j < 3; ++j) {
-                        const int i = 3 * q + j;
-                        fp[k][i] = plane[j][d1 - kCy[i] * W1 - kCx[i]];
+                    for (int j = 0; j < NP; ++j) {
+                        const int i = i0 + j;
+                        if (i < 9) fp[k][i] = plane[j][d1 - kCy[i] * W1 - kCx[i]];
                     }
                 }
             }
@@ -988,7 +994,7 @@ __global__ void d2q9_readout_b(const double *__restrict__ scr, const double *__r
 // staging of a tile (about 137 KB) allows one block per compute unit.
 constexpr int kTX = 64, kTY = 32, kNT = 1024;
 // The moment kernel's tile is 29 rows high so that its tile + 1 ring
-// (66 x 31 = 2046 nodes) takes two slots of 1024 threads (about 126 KB of LDS).
+// (66 x 31 = 2046 nodes) takes two slots of 1024 threads (about 159 KB of LDS).
 constexpr int kTYm = 29;
 
 template <class S, bool TAU1, bool WALLS>
