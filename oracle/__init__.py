@@ -43,6 +43,7 @@ class Params(ctypes.Structure):
         ("a", ctypes.c_double), ("b", ctypes.c_double), ("R", ctypes.c_double),
         ("G", ctypes.c_double), ("sigma", ctypes.c_double), ("tau", ctypes.c_double * 6),
         ("cv", ctypes.c_double), ("kappa", ctypes.c_double), ("g", ctypes.c_double),
+        ("rho_v", ctypes.c_double),
     ]
 
 
@@ -98,7 +99,7 @@ PAPER_PARAMS = dict(a=0.5, b=4.0, R=1.0, G=-1.0, sigma=1.385, tau=(1.0,) * 6,
 
 
 def make_params(lattice="D2Q9", nx=1, ny=1, nz=1, walls=True, eos="cs", gravity_form=1,
-                g=0.0, **over) -> Params:
+                g=0.0, rho_v=0.0, **over) -> Params:
     d = dict(PAPER_PARAMS)
     d.update(over)
     p = Params()
@@ -111,6 +112,7 @@ def make_params(lattice="D2Q9", nx=1, ny=1, nz=1, walls=True, eos="cs", gravity_
     for k in range(6):
         p.tau[k] = float(d["tau"][k])
     p.cv, p.kappa, p.g = d["cv"], d["kappa"], float(g)
+    p.rho_v = float(rho_v)
     return p
 
 

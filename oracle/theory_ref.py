@@ -23,7 +23,8 @@ local saturation pressure, where a second interface starts a vapour phase.
 
 Geometry (the lattice's): H nodes y = 0 .. H-1, the walls on nodes 0 and H-1,
 T(y) = T_bot + (T_top - T_bot) y / (H - 1), y up, g > 0 pointing down,
-F = -rho g (form 1) or -(rho - <rho>) g (form 2).
+F = -rho g (form 1), -(rho - <rho>) g (form 2) or -(rho - rho_v) g with a
+given rho_v (form 3, Eq. Gravity_3).
 
 Readings where the paper leaves the details open:
   * Euler steps: each node interval is split into `m` equal steps; the
@@ -102,19 +103,24 @@ def inverse_eos(P, p, T, branch, Tc, guess=None):
 class Column:
     """One column's theoretical equilibrium (see the module docstring)."""
 
-    def __init__(self, P, H, T_bot, T_top, g, form, mean, m=8):
-        if H < 3 or form not in (1, 2) or m < 1:
+    def __init__(self, P, H, T_bot, T_top, g, form, mean, m=8, rho_v=0.0):
+        if H < 3 or form not in (1, 2, 3) or m < 1:
             raise ValueError("bad column")
         self.P, self.H, self.T_bot, self.T_top = P, int(H), float(T_bot), float(T_top)
         self.g, self.form, self.mean, self.m = float(g), int(form), float(mean), int(m)
+        self.rho_v = float(rho_v)
         self.Tc = O.critical(P.a, P.b, P.R)[1]
 
     def T(self, y):
         return self.T_bot + (self.T_top - self.T_bot) * y / (self.H - 1)
 
     def F(self, rho):
-        """F_g,y of Eqs. Gravity_1 / Gravity_2 with y up."""
-        return -(rho - self.mean) * self.g if self.form == 2 else -rho * self.g
+        """F_g,y of Eqs. Gravity_1 / Gravity_2 / Gravity_3 with y up."""
+        if self.form == 2:
+            return -(rho - self.mean) * self.g
+        if self.form == 3:
+            return -(rho - self.rho_v) * self.g
+        return -rho * self.g
 
     def psat(self, y):
         return O.coexistence(self.P, self.T(y))[2]
@@ -238,9 +244,9 @@ class Column:
         return dict(config=config, rho=rho, p=p, T=T, mean=mean, interfaces=interfaces)
 
 
-def existing_configs(P, H, T_bot, T_top, g, form, mean, m=8):
+def existing_configs(P, H, T_bot, T_top, g, form, mean, m=8, rho_v=0.0):
     """Which of L-V, V-L and V-L-V exist for the column (Sec. VI)."""
-    c = Column(P, H, T_bot, T_top, g, form, mean, m)
+    c = Column(P, H, T_bot, T_top, g, form, mean, m, rho_v)
     out = {}
     for cfg in CONFIGS:
         try:

@@ -44,13 +44,23 @@ typedef struct {
     int32_t nx, ny, nz;   /* D1Q3 uses ny only; D2Q9 nx, ny; D3Q19 all */
     int32_t walls;        /* 1: wet-node walls at both ends of the wall-normal axis; 0: periodic */
     int32_t eos;          /* 0: Carnahan-Starling; 1: ideal lattice gas p = rho/3 (psi = 0) */
-    int32_t gravity_form; /* 1: F = rho g; 2: F = (rho - <rho>) g */
+    int32_t gravity_form; /* 1: F = rho g; 2: F = (rho - <rho>) g; 3: F = (rho - rho_v) g */
     int32_t pad0;
     double a, b, R, G, sigma;
     double tau[6];        /* tau_rho, tau_e, tau_varsigma, tau_j, tau_q, tau_nu */
     double cv, kappa;
     double g;             /* gravity magnitude; g > 0 points down the wall-normal axis */
+    double rho_v;         /* form 3: the vapour density of Eq. Gravity_3 */
 } orc_params;
+
+/* gravity along the wall-normal axis (Eqs. Gravity_1, Gravity_2, Gravity_3):
+ * F = -(rho - s) g with s = 0, <rho> or rho_v */
+static double gravity(const orc_params *P, double rho, double mean)
+{
+    if (P->gravity_form == 2) return -(rho - mean) * P->g;
+    if (P->gravity_form == 3) return -(rho - P->rho_v) * P->g;
+    return -rho * P->g;
+}
 
 /* status / flags */
 #define ORC_OK 0
@@ -394,7 +404,7 @@ static double d2q9_macro(const orc_params *P, const double *f, const double *T, 
             }
             w->Fix[n] = -P->G * w->psi[n] * sx;
             w->Fiy[n] = -P->G * w->psi[n] * sy;
-            double fg = (P->gravity_form == 2) ? -(w->rho[n] - mean) * P->g : -w->rho[n] * P->g;
+            double fg = gravity(P, w->rho[n], mean);
             w->Fx[n] = w->Fix[n];
             w->Fy[n] = w->Fiy[n] + fg;
         }
@@ -592,7 +602,7 @@ static void d1q3_step_once(const orc_params *P, double *f, double *T, d1_work *w
         if (wall) { w->Fi[y] = 0; w->F[y] = 0; continue; }
         double s = 0.5 * (w->psi[wrap(y + 1, ny)] - w->psi[wrap(y - 1, ny)]);
         w->Fi[y] = -P->G * w->psi[y] * s;
-        double fg = (P->gravity_form == 2) ? -(w->rho[y] - mean) * P->g : -w->rho[y] * P->g;
+        double fg = gravity(P, w->rho[y], mean);
         w->F[y] = w->Fi[y] + fg;
     }
     double mass = 0, umax = 0, rmin = INFINITY;
@@ -692,7 +702,7 @@ static int validate(const orc_params *P)
     for (int k = 0; k < 6; ++k)
         if (!(P->tau[k] > 0.5)) return ORC_EINVAL;
     if (P->lattice != 2 && !tau_all_one(P)) return ORC_EUNSUPPORTED;
-    if (P->gravity_form != 1 && P->gravity_form != 2) return ORC_EINVAL;
+    if (P->gravity_form < 1 || P->gravity_form > 3) return ORC_EINVAL;
     if (P->G == 0) return ORC_EINVAL;
     return ORC_OK;
 }
@@ -997,7 +1007,7 @@ static double d3q19_macro(const orc_params *P, const double *f, const double *T,
                 double fix = -P->G * w->psi[n] * sx;
                 double fiy = -P->G * w->psi[n] * sy;
                 double fiz = -P->G * w->psi[n] * sz;
-                double fg = (P->gravity_form == 2) ? -(w->rho[n] - mean) * P->g : -w->rho[n] * P->g;
+                double fg = gravity(P, w->rho[n], mean);
                 w->Fx[n] = fix;
                 w->Fy[n] = fiy;
                 w->Fz[n] = fiz + fg;

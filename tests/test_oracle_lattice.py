@@ -201,16 +201,18 @@ def test_wall_mass_bookkeeping_identity(orc, crit):
         assert abs((f.sum() - M0) - expect) < 2e-15 * M0
 
 
-@pytest.mark.parametrize("lat", ["D1Q3", "D2Q9"])
-def test_ideal_gas_column_reaches_the_barometric_closed_form(orc, lat):
-    """Special case psi = 0 (ideal lattice gas p = rho/3) with F = rho g:
-    the steady column satisfies rho(1) = rho(0)/(1 + 3g/2),
-    rho(y+1) = rho(y)(1 - 3g/2)/(1 + 3g/2) in the interior and
-    rho(N-1) = rho(N-2)(1 - 3g/2), from u = 0 in the streaming of the
+@pytest.mark.parametrize("lat,form", [("D1Q3", 1), ("D2Q9", 1), ("D1Q3", 3), ("D2Q9", 3)])
+def test_ideal_gas_column_reaches_the_barometric_closed_form(orc, lat, form):
+    """Special case psi = 0 (ideal lattice gas p = rho/3) with
+    F = -(rho - s) g, s = 0 (Eq. Gravity_1) or s = rho_v (Eq. Gravity_3):
+    with a = 3g/2 the steady column satisfies rho(1) = (rho(0) + a s)/(1 + a),
+    rho(y+1) = (rho(y)(1 - a) + 2 a s)/(1 + a) in the interior and
+    rho(N-1) = rho(N-2)(1 - a) + a s, from u = 0 in the streaming of the
     force-corrected equilibrium with a force-free Zou-He wall node."""
     ny, g = 24, 2e-3
+    s = 0.0 if form == 1 else 0.7
     nx = 1 if lat == "D1Q3" else 2
-    P = orc.make_params(lat, nx=nx, ny=ny, eos="ideal", g=g, gravity_form=1)
+    P = orc.make_params(lat, nx=nx, ny=ny, eos="ideal", g=g, gravity_form=form, rho_v=s)
     shape = (ny,) if lat == "D1Q3" else (ny, nx)
     f = orc.init_rest(P, np.ones(shape).ravel())
     T = np.ones(int(np.prod(shape)))
@@ -218,9 +220,11 @@ def test_ideal_gas_column_reaches_the_barometric_closed_form(orc, lat):
     assert st == "converged"
     r = orc.macro(P, f, T)["rho"].reshape(ny, -1)[:, 0]
     a = 1.5 * g
-    assert r[1] / r[0] == pytest.approx(1 / (1 + a), rel=1e-12)
-    assert np.allclose(r[2:-1] / r[1:-2], (1 - a) / (1 + a), rtol=1e-12, atol=0)
-    assert r[-1] / r[-2] == pytest.approx(1 - a, rel=1e-12)
+    assert r[1] == pytest.approx((r[0] + a * s) / (1 + a), rel=1e-12)
+    assert np.allclose(r[2:-1], (r[1:-2] * (1 - a) + 2 * a * s) / (1 + a), rtol=1e-12, atol=0)
+    assert r[-1] == pytest.approx(r[-2] * (1 - a) + a * s, rel=1e-12)
+    if form == 3:  # the profile differs from form 1's: the s terms are not negligible
+        assert abs(r[-1] / r[-2] - (1 - a)) > 1e-4
 
 
 def _psi_force_1d(orc, P, rho, T):
