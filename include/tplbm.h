@@ -10,7 +10,7 @@
  * second-order equilibrium (Eq. EquilibriumDistribution), the Shan-Chen
  * nearest-neighbour force (Eq. ShanChenForce) on the Yuan-Schaefer
  * pseudopotential (Eq. InteractionPotential) of the Carnahan-Starling EOS
- * (Eq. EOS), the two gravity forms of Sec. II (Eqs. Gravity_1, Gravity_2),
+ * (Eq. EOS), the gravity forms of Sec. II (Eqs. Gravity_1, Gravity_2, Gravity_3),
  * Zou-He no-slip wet-node walls with zero interaction force at the wall, and
  * the energy equation (Eq. Energy_Equation) with isotropic second-order
  * differences and a two-stage Runge-Kutta step.
@@ -102,7 +102,8 @@ typedef struct tplbm_params {
     int32_t walls;          /* 1: wet-node walls on the wall-normal axis; 0: periodic */
     int32_t precision;      /* TPLBM_FP64 or TPLBM_FP32_DEV */
     int32_t eos;            /* TPLBM_EOS_* */
-    int32_t gravity_form;   /* 1: F_g = rho g (Eq. Gravity_1); 2: (rho - <rho>) g (Eq. Gravity_2) */
+    int32_t gravity_form;   /* 1: F_g = rho g (Eq. Gravity_1); 2: (rho - <rho>) g (Eq. Gravity_2);
+                               3: (rho - rho_v) g (Eq. Gravity_3) */
     double a, b, R;         /* Carnahan-Starling constants (Eq. EOS) */
     double G;               /* Eq. InteractionPotential, c = 1; must be < 0 for C-S */
     double sigma;           /* Eq. LiFS */
@@ -112,6 +113,7 @@ typedef struct tplbm_params {
     double rho_ref;         /* FP32_DEV reference density; ignored for FP64 */
     int32_t state;          /* TPLBM_STATE_*: what a lattice stores between steps */
     int32_t pad;            /* zero */
+    double rho_v;           /* gravity form 3: the vapour density subtracted (finite) */
 } tplbm_params;
 
 /* Diagnostics of the time level `step` (the level the last step started from). */
@@ -211,7 +213,8 @@ int tplbm_eos_spinodal(double a, double b, double R, double T, double *out2);
  *
  * Geometry as in a batch column: nodes y = 0 .. height-1, walls on the first
  * and last node, T(y) = T_bot + (T_top - T_bot) y / (height - 1), g > 0
- * pointing to node 0, F = -rho g (form 1) or -(rho - mean_rho) g (form 2).
+ * pointing to node 0, F = -rho g (form 1), -(rho - mean_rho) g (form 2) or
+ * -(rho - rho_v) g (form 3).
  * Discretisation: each node interval is split into `substeps` Euler steps
  * (the interval holding an interface is split there first, each part into
  * `substeps`); a V-L-V configuration is integrated as V-L until p - p_sat(T)
@@ -243,12 +246,13 @@ int tplbm_eos_spinodal(double a, double b, double R, double T, double *out2);
 
 typedef struct tplbm_theory_column {
     int32_t height;        /* nodes including both wall nodes, 3 .. 2^24 */
-    int32_t gravity_form;  /* 1 or 2 */
+    int32_t gravity_form;  /* 1, 2 or 3 */
     int32_t config;        /* TPLBM_THEORY_LV, _VL or _VLV */
     int32_t substeps;      /* Euler steps per node interval, 1 .. 4096 */
     double T_bot, T_top;   /* absolute wall temperatures (nodes 0 and height-1), > 0 */
     double g;              /* signed; > 0 points to node 0 */
     double mean_rho;       /* mean density, 0 < mean_rho < 4/b */
+    double rho_v;          /* form 3: the vapour density subtracted (finite) */
 } tplbm_theory_column;
 
 typedef struct tplbm_theory_result {
@@ -290,8 +294,9 @@ const char *tplbm_theory_last_error(void);
 
 typedef struct tplbm_column {
     int32_t height;        /* nodes including both wall nodes, 3 .. 2048 */
-    int32_t gravity_form;  /* 1 or 2 */
+    int32_t gravity_form;  /* 1, 2 or 3 (Eqs. Gravity_1, Gravity_2, Gravity_3) */
     double g;              /* signed gravity: > 0 points to node 0, < 0 away from it */
+    double rho_v;          /* form 3: the vapour density subtracted (finite; ignored otherwise) */
 } tplbm_column;
 
 typedef struct tplbm_batch_params {

@@ -43,6 +43,7 @@ class Params(ctypes.Structure):
         ("G", ctypes.c_double), ("sigma", ctypes.c_double), ("tau", ctypes.c_double * 6),
         ("cv", ctypes.c_double), ("kappa", ctypes.c_double), ("g", ctypes.c_double),
         ("rho_ref", ctypes.c_double), ("state", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("rho_v", ctypes.c_double),
     ]
 
 
@@ -79,7 +80,8 @@ SIGNATURES = {
 
 
 class Column(ctypes.Structure):
-    _fields_ = [("height", ctypes.c_int32), ("gravity_form", ctypes.c_int32), ("g", ctypes.c_double)]
+    _fields_ = [("height", ctypes.c_int32), ("gravity_form", ctypes.c_int32), ("g", ctypes.c_double),
+                ("rho_v", ctypes.c_double)]
 
 
 class BatchParams(ctypes.Structure):
@@ -187,7 +189,7 @@ class TheoryColumn(ctypes.Structure):
     _fields_ = [("height", ctypes.c_int32), ("gravity_form", ctypes.c_int32),
                 ("config", ctypes.c_int32), ("substeps", ctypes.c_int32),
                 ("T_bot", ctypes.c_double), ("T_top", ctypes.c_double),
-                ("g", ctypes.c_double), ("mean_rho", ctypes.c_double)]
+                ("g", ctypes.c_double), ("mean_rho", ctypes.c_double), ("rho_v", ctypes.c_double)]
 
 
 class TheoryResult(ctypes.Structure):
@@ -205,16 +207,18 @@ SIGNATURES.update({
 
 def theory_solve(columns, substeps=8, nthreads=0, a=0.5, b=4.0, R=1.0):
     """Sharp-interface equilibria of columns given as tuples
-    (height, T_bot, T_top, g, gravity_form, mean_rho, config) with config one
-    of "L-V", "V-L", "V-L-V".  Returns one dict per column: rho, p (node
+    (height, T_bot, T_top, g, gravity_form, mean_rho, config[, rho_v]) with
+    config one of "L-V", "V-L", "V-L-V" (rho_v: gravity form 3).  Returns one dict per column: rho, p (node
     arrays) and interfaces for a configuration that exists, else None for
     rho/p and the list of reasons."""
     n = len(columns)
     cols = (TheoryColumn * max(n, 1))()
     heights = []
-    for k, (h, tb, tt, g, form, mean, cfg) in enumerate(columns):
+    for k, col in enumerate(columns):
+        h, tb, tt, g, form, mean, cfg = col[:7]
+        rv = float(col[7]) if len(col) > 7 else 0.0
         cols[k] = TheoryColumn(int(h), int(form), THEORY_CONFIGS[cfg], int(substeps),
-                               float(tb), float(tt), float(g), float(mean))
+                               float(tb), float(tt), float(g), float(mean), rv)
         heights.append(int(h))
     total = sum(heights)
     rho, p = np.empty(max(total, 1)), np.empty(max(total, 1))
@@ -236,7 +240,7 @@ def theory_solve(columns, substeps=8, nthreads=0, a=0.5, b=4.0, R=1.0):
 
 
 def make_params(lattice=D2Q9, nx=1, ny=1, nz=1, walls=True, precision=FP64, eos="cs",
-                gravity_form=1, g=0.0, rho_ref=0.0, state=STATE_AUTO, **over) -> Params:
+                gravity_form=1, g=0.0, rho_ref=0.0, state=STATE_AUTO, rho_v=0.0, **over) -> Params:
     d = dict(PAPER)
     d.update(over)
     p = Params()
@@ -251,6 +255,7 @@ def make_params(lattice=D2Q9, nx=1, ny=1, nz=1, walls=True, precision=FP64, eos=
         p.tau[k] = float(d["tau"][k])
     p.cv, p.kappa, p.g, p.rho_ref = d["cv"], d["kappa"], float(g), float(rho_ref)
     p.state, p.pad = int(state), 0
+    p.rho_v = float(rho_v)
     return p
 
 
@@ -335,7 +340,8 @@ def _bcheck(rc: int, h=None):
 
 class Batch:
     """Many independent 1-D columns swept to steady state by one persistent
-    launch.  columns: sequence of (height, gravity_form, g)."""
+    launch.  columns: sequence of (height, gravity_form, g) or
+    (height, gravity_form, g, rho_v) (rho_v: gravity form 3)."""
 
     def __init__(self, columns, eos="cs", device=None, stream=None, **over):
         import torch
@@ -352,8 +358,10 @@ class Batch:
         self.params = p
         self.ncols = len(columns)
         self.cols = (Column * self.ncols)()
-        for k, (h, form, g) in enumerate(columns):
+        for k, col in enumerate(columns):
+            h, form, g = col[:3]
             self.cols[k].height, self.cols[k].gravity_form, self.cols[k].g = int(h), int(form), float(g)
+            self.cols[k].rho_v = float(col[3]) if len(col) > 3 else 0.0
         self.heights = np.array([c[0] for c in columns], dtype=np.int64)
         self.offsets = np.concatenate([[0], np.cumsum(self.heights)])
         nb = ctypes.c_size_t()

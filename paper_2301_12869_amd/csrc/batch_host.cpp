@@ -79,9 +79,10 @@ int validate(const tplbm_batch_params *p, int32_t ncols, const tplbm_column *col
     for (int k = 0; k < ncols; ++k) {
         if (cols[k].height < 3 || cols[k].height > kMaxHeight)
             return bfail(nullptr, TPLBM_ESHAPE, "column %d: height %d outside 3..%d", k, cols[k].height, kMaxHeight);
-        if (cols[k].gravity_form != 1 && cols[k].gravity_form != 2)
-            return bfail(nullptr, TPLBM_EINVAL, "column %d: gravity_form must be 1 or 2", k);
+        if (cols[k].gravity_form < 1 || cols[k].gravity_form > 3)
+            return bfail(nullptr, TPLBM_EINVAL, "column %d: gravity_form must be 1, 2 or 3", k);
         if (!std::isfinite(cols[k].g)) return bfail(nullptr, TPLBM_EINVAL, "column %d: g not finite", k);
+        if (!std::isfinite(cols[k].rho_v)) return bfail(nullptr, TPLBM_EINVAL, "column %d: rho_v not finite", k);
         t += cols[k].height;
     }
     *total = t;
@@ -205,6 +206,7 @@ int tplbm_batch_create(const tplbm_batch_params *p, int32_t ncols, const tplbm_c
         b->cols[k].form = cols[k].gravity_form;
         b->cols[k].offset = off;
         b->cols[k].g = cols[k].g;
+        b->cols[k].rho_v = cols[k].rho_v;
         off += cols[k].height;
     }
     // longest columns first: their time to steady state grows fastest with

@@ -9,9 +9,10 @@ namespace tplbm {
 
 struct ColumnDesc {
     int32_t height;   // nodes, both wall nodes included
-    int32_t form;     // gravity form 1 or 2
+    int32_t form;     // gravity form 1, 2 or 3
     int64_t offset;   // first node in the concatenated arrays
     double g;         // gravity magnitude, positive downward
+    double rho_v;     // form 3: the subtracted vapour density
 };
 
 struct ColumnResult {

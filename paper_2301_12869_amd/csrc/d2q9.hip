@@ -160,7 +160,7 @@ __device__ __forceinline__ void node_force(const Phys &c, const double *s_psi, i
     const double sx = (p.e - p.w) * (1.0 / 3.0) + ((p.ne + p.se) - (p.nw + p.sw)) * (1.0 / 12.0);
     const double sy = (p.n - p.s) * (1.0 / 3.0) + ((p.ne + p.nw) - (p.se + p.sw)) * (1.0 / 12.0);
     const double mg = -c.G * s_psi[c3];
-    const double fg = (c.form == 2) ? -(rho - mean) * c.g : -rho * c.g;
+    const double fg = gravity_force(c.form, rho, mean, c.rho_v, c.g);
     Fx = mg * sx;
     Fy = mg * sy + fg;
     X = c.G2 * (sx * sx + sy * sy);
@@ -978,7 +978,7 @@ __global__ void d2q9_readout_b(const double *__restrict__ scr, const double *__r
                 const double pSW = psi[(size_t)ym * nx + xm], pSE = psi[(size_t)ym * nx + xp];
                 const double sx = (pE - pW) * (1.0 / 3.0) + ((pNE + pSE) - (pNW + pSW)) * (1.0 / 12.0);
                 const double sy = (pN - pS) * (1.0 / 3.0) + ((pNE + pNW) - (pSE + pSW)) * (1.0 / 12.0);
-                const double fg = (c.form == 2) ? -(r - mean) * c.g : -r * c.g;
+                const double fg = gravity_force(c.form, r, mean, c.rho_v, c.g);
                 Fx = -c.G * p0 * sx;
                 Fy = -c.G * p0 * sy + fg;
             }

@@ -19,12 +19,21 @@ struct Phys {
     double kappa_over_cv;     // kappa / c_v
     double R_over_cv;         // R / c_v: (T/(rho c_v)) (dp/dT)_rho = T (R/c_v) Z(eta)
     double g;                 // gravity magnitude (down the wall-normal axis)
+    double rho_v;             // gravity form 3: the subtracted vapour density
     double rho_ref;           // FP32-deviation reference density
     double lam[9];            // relaxation rates in moment order (Eq. RelaxationMatrix)
     double sig_e, sig_s;      // sigma / tau_e and sigma / tau_varsigma: the sigma part of (I - Lambda/2) S
     int eos;                  // 0 Carnahan-Starling, 1 ideal lattice gas
-    int form;                 // 1: rho g, 2: (rho - <rho>) g
+    int form;                 // 1: rho g, 2: (rho - <rho>) g, 3: (rho - rho_v) g
 };
+
+// Gravity along the wall-normal axis, g > 0 pointing to its first layer
+// (Eqs. Gravity_1, Gravity_2, Gravity_3): -(rho - s) g with s = 0, <rho> or
+// rho_v.
+__device__ __forceinline__ double gravity_force(int form, double rho, double mean, double rho_v, double g)
+{
+    return form == 2 ? -(rho - mean) * g : (form == 3 ? -(rho - rho_v) * g : -rho * g);
+}
 
 // Reciprocal of a positive normal double: hardware estimate refined by two
 // Newton steps (within about one ulp; no special-case handling, so callers

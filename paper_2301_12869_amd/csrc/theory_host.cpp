@@ -119,8 +119,13 @@ public:
 private:
     double T(double y) const { return c_.T_bot + (c_.T_top - c_.T_bot) * y / (H_ - 1); }
 
-    // F_g,y of Eqs. Gravity_1 / Gravity_2 with y up and g > 0 pointing down
-    double F(double rho) const { return c_.gravity_form == 2 ? -(rho - c_.mean_rho) * c_.g : -rho * c_.g; }
+    // F_g,y of Eqs. Gravity_1 / Gravity_2 / Gravity_3 with y up and g > 0 pointing down
+    double F(double rho) const
+    {
+        if (c_.gravity_form == 2) return -(rho - c_.mean_rho) * c_.g;
+        if (c_.gravity_form == 3) return -(rho - c_.rho_v) * c_.g;
+        return -rho * c_.g;
+    }
 
     const Spinodal &spinodal(double T)
     {
@@ -325,7 +330,8 @@ extern "C" int tplbm_theory_solve(double a, double b, double R, int32_t ncols, c
     for (int32_t i = 0; i < ncols; ++i) {
         const tplbm_theory_column &c = cols[i];
         if (c.height < 3 || c.height > (1 << 24)) return tfail(TPLBM_ESHAPE, "column %d: height %d outside 3 .. 2^24", i, c.height);
-        if (c.gravity_form != 1 && c.gravity_form != 2) return tfail(TPLBM_EINVAL, "column %d: gravity form must be 1 or 2", i);
+        if (c.gravity_form < 1 || c.gravity_form > 3) return tfail(TPLBM_EINVAL, "column %d: gravity form must be 1, 2 or 3", i);
+        if (!std::isfinite(c.rho_v)) return tfail(TPLBM_EINVAL, "column %d: rho_v must be finite", i);
         if (c.config < TPLBM_THEORY_LV || c.config > TPLBM_THEORY_VLV) return tfail(TPLBM_EINVAL, "column %d: unknown configuration", i);
         if (c.substeps < 1 || c.substeps > 4096) return tfail(TPLBM_EINVAL, "column %d: substeps outside 1 .. 4096", i);
         if (!(c.T_bot > 0 && c.T_top > 0) || !std::isfinite(c.T_bot) || !std::isfinite(c.T_top))

@@ -100,8 +100,9 @@ int validate(const tplbm_params *p)
         return fail(nullptr, TPLBM_EINVAL, "precision must be TPLBM_FP64 or TPLBM_FP32_DEV");
     if (p->eos != TPLBM_EOS_CARNAHAN_STARLING && p->eos != TPLBM_EOS_IDEAL_LATTICE)
         return fail(nullptr, TPLBM_EINVAL, "unknown eos");
-    if (p->gravity_form != 1 && p->gravity_form != 2)
-        return fail(nullptr, TPLBM_EINVAL, "gravity_form must be 1 or 2");
+    if (p->gravity_form < 1 || p->gravity_form > 3)
+        return fail(nullptr, TPLBM_EINVAL, "gravity_form must be 1, 2 or 3");
+    if (!std::isfinite(p->rho_v)) return fail(nullptr, TPLBM_EINVAL, "rho_v must be finite");
     for (int k = 0; k < 6; ++k)
         if (!(p->tau[k] > 0.5)) return fail(nullptr, TPLBM_EINVAL, "tau[%d] must exceed 1/2", k);
     if (p->eos == TPLBM_EOS_CARNAHAN_STARLING) {
@@ -133,6 +134,7 @@ Phys make_phys(const tplbm_params &p)
     c.kappa_over_cv = p.kappa / p.cv;
     c.R_over_cv = p.R / p.cv;
     c.g = p.g;
+    c.rho_v = p.rho_v;
     c.rho_ref = p.precision == TPLBM_FP32_DEV ? p.rho_ref : 0.0;
     const double t[9] = {p.tau[0], p.tau[1], p.tau[2], p.tau[3], p.tau[4],
                          p.tau[3], p.tau[4], p.tau[5], p.tau[5]};

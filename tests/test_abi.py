@@ -65,8 +65,8 @@ def test_invalid_parameters_are_rejected_on_the_host(lib):
     pop = T.make_params(T.D2Q9, nx=4, ny=8, state=T.STATE_POPULATIONS)
     assert lib.tplbm_workspace_bytes(ctypes.byref(pop), ctypes.byref(nb)) == T.OK
     assert nb.value > 2 * 9 * 32 * 8
-    cases = [dict(ny=2), dict(tau=(1, 1, 1, 1, 1, 0.5)), dict(G=1.0), dict(gravity_form=3),
-             dict(precision=7), dict(lattice=5), dict(state=2)]
+    cases = [dict(ny=2), dict(tau=(1, 1, 1, 1, 1, 0.5)), dict(G=1.0), dict(gravity_form=4),
+             dict(gravity_form=3, rho_v=float("inf")), dict(precision=7), dict(lattice=5), dict(state=2)]
     for over in cases:
         kw = dict(lattice=T.D2Q9, nx=4, ny=8)
         kw.update(over)
@@ -115,9 +115,10 @@ def test_degenerate_lattices_and_columns_are_rejected_on_the_host(lib):
     bp = T.BatchParams(a=0.5, b=4.0, R=1.0, G=-1.0, sigma=1.385, cv=5.0, kappa=0.02, eos=0, pad=0)
     cols = (T.Column * 1)()
     assert lib.tplbm_batch_workspace_bytes(ctypes.byref(bp), 0, cols, ctypes.byref(nb)) == T.EINVAL
-    for h, form, g, code in ((2, 1, 1e-5, T.ESHAPE), (2049, 1, 1e-5, T.ESHAPE), (100, 3, 1e-5, T.EINVAL)):
-        cols[0].height, cols[0].gravity_form, cols[0].g = h, form, g
+    for h, form, g, rv, code in ((2, 1, 1e-5, 0.0, T.ESHAPE), (2049, 1, 1e-5, 0.0, T.ESHAPE),
+                                 (100, 4, 1e-5, 0.0, T.EINVAL), (100, 3, 1e-5, float("nan"), T.EINVAL)):
+        cols[0].height, cols[0].gravity_form, cols[0].g, cols[0].rho_v = h, form, g, rv
         assert lib.tplbm_batch_workspace_bytes(ctypes.byref(bp), 1, cols, ctypes.byref(nb)) == code
         assert lib.tplbm_batch_last_error(None)
-    cols[0].height, cols[0].gravity_form = 2048, 2
+    cols[0].height, cols[0].gravity_form, cols[0].rho_v = 2048, 3, 0.02
     assert lib.tplbm_batch_workspace_bytes(ctypes.byref(bp), 1, cols, ctypes.byref(nb)) == T.OK

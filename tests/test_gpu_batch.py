@@ -230,3 +230,27 @@ def test_resume_with_new_wall_temperatures_matches_the_oracle(T, orc, crit):
         assert er < TOL and eT < TOL
         assert b.column(gT, k)[0] == tb[k] and b.column(gT, k)[-1] == tt[k]
     b.close()
+
+
+def test_gravity_form_3_columns_match_the_oracle(T, orc, crit):
+    """F = (rho - rho_v) g (Eq. Gravity_3) with a per-column rho_v, against
+    the oracle column after 3000 steps."""
+    cols, rho, Tc = _walled_columns(orc, crit)
+    cols3 = [(H, 3, g, 0.02 + 0.002 * k) for k, (H, form, g) in enumerate(cols)]
+    b = T.Batch(cols3)
+    b.set_tuning(shape=0, check_every=100)
+    b.set_state(rho, Tc)
+    res = b.run(0.0, 3000)
+    grho, gT = b.read("rho"), b.read("T")
+    for k, (H, form, g, rv) in enumerate(cols3):
+        P = orc.make_params("D1Q3", ny=H, g=g, gravity_form=3, rho_v=rv)
+        f = orc.init_rest(P, b.column(rho, k).copy())
+        TT = b.column(Tc, k).copy()
+        orc.step(P, f, TT, 3000)
+        m = orc.macro(P, f, TT)
+        er = np.abs(b.column(grho, k) - m["rho"]).max() / m["rho"].max()
+        eT = np.abs(b.column(gT, k) - TT).max() / TT.max()
+        _log(f"column {k} {(H, 3, g, rv)}: status {res['status'][k]}, rho err {er:.2e}, T err {eT:.2e}")
+        assert res["status"][k] == 2
+        assert er < TOL and eT < TOL
+    b.close()

@@ -22,7 +22,7 @@ RHO_C, T_C, P_C = O.critical()
 MEAN = 1.3344 * RHO_C
 
 # (height, T_bot/T_c, T_top/T_c, g, form, mean_rho, config): the minimal
-# column, ragged heights, both gravity signs and forms, heating from above,
+# column, ragged heights, both gravity signs and all three forms, heating from above,
 # a column whose bottom is supercritical (a liquid there cannot exist,
 # a vapour can), and a V-L-V case
 CASES = [
@@ -35,12 +35,15 @@ CASES = [
     (45, 1.05, 0.6, 3e-5, 1, MEAN, "V-L"),
     (61, 0.9, 0.6, 4e-5, 1, MEAN, "V-L-V"),
     (41, 0.75, 0.75, 0.0, 2, 0.8 * RHO_C, "V-L"),
+    (43, 0.84, 0.68, 3e-5, 3, MEAN, "L-V"),  # gravity form 3 (rho_v below)
 ]
+RHO_V3 = 0.12 * RHO_C  # the subtracted density of the form-3 case
 
 
 def _oracle(case, m):
     H, tb, tt, g, form, mean, cfg = case
-    col = TR.Column(O.make_params("D1Q3", ny=H), H, tb * T_C, tt * T_C, g, form, mean, m)
+    col = TR.Column(O.make_params("D1Q3", ny=H), H, tb * T_C, tt * T_C, g, form, mean, m,
+                    RHO_V3 if form == 3 else 0.0)
     try:
         return col.solve(cfg), None
     except TR.NoSolution as e:
@@ -48,7 +51,8 @@ def _oracle(case, m):
 
 
 def _product(cases, m, nthreads=0):
-    cols = [(H, tb * T_C, tt * T_C, g, form, mean, cfg) for (H, tb, tt, g, form, mean, cfg) in cases]
+    cols = [(H, tb * T_C, tt * T_C, g, form, mean, cfg, RHO_V3 if form == 3 else 0.0)
+            for (H, tb, tt, g, form, mean, cfg) in cases]
     return T.theory_solve(cols, substeps=m, nthreads=nthreads)
 
 
@@ -116,11 +120,12 @@ def test_lever_rule_at_zero_gravity():
 
 
 @pytest.mark.parametrize("bad", [
-    dict(height=2), dict(gravity_form=3), dict(config=3), dict(substeps=0), dict(T_bot=-1.0),
-    dict(g=math.inf), dict(mean_rho=1.5),
+    dict(height=2), dict(gravity_form=4), dict(config=3), dict(substeps=0), dict(T_bot=-1.0),
+    dict(g=math.inf), dict(mean_rho=1.5), dict(gravity_form=3, rho_v=math.nan),
 ])
 def test_bad_columns_are_rejected(bad):
-    good = dict(height=11, gravity_form=1, config=0, substeps=2, T_bot=0.07, T_top=0.07, g=0.0, mean_rho=0.1)
+    good = dict(height=11, gravity_form=1, config=0, substeps=2, T_bot=0.07, T_top=0.07, g=0.0, mean_rho=0.1,
+                rho_v=0.0)
     good.update(bad)
     col = (T.TheoryColumn * 1)(T.TheoryColumn(**good))
     rho, p = np.empty(64), np.empty(64)
