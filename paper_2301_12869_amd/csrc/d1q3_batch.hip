@@ -172,7 +172,7 @@ __global__ __launch_bounds__(NT) void d1q3_batch(BatchArgs a, Phys c)
                 if (own && !wall) {
                     sv = 0.5 * (pp - pm);
                     Fi = -c.G * psi[k] * sv;
-                    Fg = gravity_force(d.form, rho[k], mean, d.rho_v, g);
+                    Fg = gravity_force(rho[k], gravity_sub(d.form, mean, d.rho_v), g);
                 }
                 F[k] = Fi + Fg;
                 X[k] = c.sigma * c.G2 * sv * sv;  // sigma |F_int|^2 / psi^2

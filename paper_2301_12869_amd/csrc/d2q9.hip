@@ -148,10 +148,11 @@ __device__ __forceinline__ void pulled_moments(double f[9], bool bot, bool top, 
 }
 
 // Shan-Chen force on the psi stencil (LDS, centre index c3, row stride ld)
-// plus gravity, and X = |F_int|^2 / psi^2 = G^2 |sum w psi c|^2 for the sigma
+// plus gravity (sub: the density the gravity form subtracts), and
+// X = |F_int|^2 / psi^2 = G^2 |sum w psi c|^2 for the sigma
 // term.  Zero at wall nodes.
 __device__ __forceinline__ void node_force(const Phys &c, const double *s_psi, int c3, int ld, double rho,
-                                           double mean, bool wall, double &Fx, double &Fy, double &X)
+                                           double sub, bool wall, double &Fx, double &Fy, double &X)
 {
     Fx = Fy = X = 0.0;
     if (wall) return;
@@ -160,7 +161,7 @@ __device__ __forceinline__ void node_force(const Phys &c, const double *s_psi, i
     const double sx = (p.e - p.w) * (1.0 / 3.0) + ((p.ne + p.se) - (p.nw + p.sw)) * (1.0 / 12.0);
     const double sy = (p.n - p.s) * (1.0 / 3.0) + ((p.ne + p.nw) - (p.se + p.sw)) * (1.0 / 12.0);
     const double mg = -c.G * s_psi[c3];
-    const double fg = gravity_force(c.form, rho, mean, c.rho_v, c.g);
+    const double fg = gravity_force(rho, sub, c.g);
     Fx = mg * sx;
     Fy = mg * sy + fg;
     X = c.G2 * (sx * sx + sy * sy);
@@ -320,6 +321,7 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step(const S *__res
     const size_t N = (size_t)nx * ny;
     const double rr = c.rho_ref;
     const double mean = st->mean[step & 1];
+    const double sub = gravity_sub(c.form, mean, c.rho_v);
     const bool small_x = nx < W3;
     const double wref[9] = {kW0 * rr, kW1 * rr, kW1 * rr, kW1 * rr, kW1 * rr,
                             kW5 * rr, kW5 * rr, kW5 * rr, kW5 * rr};
@@ -404,7 +406,7 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step(const S *__res
             if (!valid) continue;
             const double rho = s_rho[r];
             double Fx, Fy, X;
-            node_force(c, s_psi, (ry + 1) * W3 + (rx + 1), W3, rho, mean, wall, Fx, Fy, X);
+            node_force(c, s_psi, (ry + 1) * W3 + (rx + 1), W3, rho, sub, wall, Fx, Fy, X);
             const double inv = rcp_pos(rho);
             s_ux[r] = (s_ux[r] + 0.5 * Fx) * inv;
             s_uy[r] = (s_uy[r] + 0.5 * Fy) * inv;
@@ -459,7 +461,7 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step(const S *__res
             // forces (again, from the LDS psi) for the collision
             double Fx, Fy, X;
             const double psi0 = s_psi[c3];
-            node_force(c, s_psi, c3, W3, rho, mean, wall, Fx, Fy, X);
+            node_force(c, s_psi, c3, W3, rho, sub, wall, Fx, Fy, X);
 
             double fs[9];
             if (TAU1) {
@@ -622,6 +624,7 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step_mom(const doub
     const int tid = threadIdx.x;
     const size_t N = (size_t)nx * ny;
     const double mean = st->mean[step & 1];
+    const double sub = gravity_sub(c.form, mean, c.rho_v);
 
     const int nb = gridDim.x;
     const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
@@ -699,7 +702,7 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step_mom(const doub
             if (!valid) continue;
             const double rho = s_rho[r];
             double Fx, Fy, X;
-            node_force(c, s_psi, (ry + 1) * W3 + (rx + 1), W3, rho, mean, wall, Fx, Fy, X);
+            node_force(c, s_psi, (ry + 1) * W3 + (rx + 1), W3, rho, sub, wall, Fx, Fy, X);
             const double inv = rcp_pos(rho);
             s_ux[r] = (s_ux[r] + 0.5 * Fx) * inv;
             s_uy[r] = (s_uy[r] + 0.5 * Fy) * inv;
@@ -780,7 +783,7 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step_mom(const doub
                     const int c3 = (ry + 2) * W3 + (rx + 2);
                     const double rho = s_rho[c2];
                     double Fx, Fy, X;
-                    node_force(c, s_psi, c3, W3, rho, mean, wall, Fx, Fy, X);
+                    node_force(c, s_psi, c3, W3, rho, sub, wall, Fx, Fy, X);
                     collide_tau1(c, rho, s_ux[c2], s_uy[c2], Fx, Fy, X, fsr[k]);
                     // the next level's mass of the tile nodes (periodic y
                     // wraps rows: only nodes of the tile itself count)
@@ -978,7 +981,7 @@ __global__ void d2q9_readout_b(const double *__restrict__ scr, const double *__r
                 const double pSW = psi[(size_t)ym * nx + xm], pSE = psi[(size_t)ym * nx + xp];
                 const double sx = (pE - pW) * (1.0 / 3.0) + ((pNE + pSE) - (pNW + pSW)) * (1.0 / 12.0);
                 const double sy = (pN - pS) * (1.0 / 3.0) + ((pNE + pNW) - (pSE + pSW)) * (1.0 / 12.0);
-                const double fg = gravity_force(c.form, r, mean, c.rho_v, c.g);
+                const double fg = gravity_force(r, gravity_sub(c.form, mean, c.rho_v), c.g);
                 Fx = -c.G * p0 * sx;
                 Fy = -c.G * p0 * sy + fg;
             }

@@ -315,7 +315,7 @@ __global__ __launch_bounds__(kStencilThreads) void d3q19_pass_b(const double *__
                 const double mg = -c.G * s_psi[rnb(tx, ty, tz, 0, 0, 0)];
                 Fx = mg * sx;
                 Fy = mg * sy;
-                Fz = mg * sz + gravity_force(c.form, rho, mean, c.rho_v, c.g);
+                Fz = mg * sz + gravity_force(rho, gravity_sub(c.form, mean, c.rho_v), c.g);
                 Xs2 = c.sigma * c.G2 * (sx * sx + sy * sy + sz * sz);  // sigma |F_int|^2 / psi^2
             }
             const double inv = rcp_pos(rho);

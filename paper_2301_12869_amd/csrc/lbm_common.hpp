@@ -28,12 +28,14 @@ struct Phys {
 };
 
 // Gravity along the wall-normal axis, g > 0 pointing to its first layer
-// (Eqs. Gravity_1, Gravity_2, Gravity_3): -(rho - s) g with s = 0, <rho> or
-// rho_v.
-__device__ __forceinline__ double gravity_force(int form, double rho, double mean, double rho_v, double g)
+// (Eqs. Gravity_1, Gravity_2, Gravity_3): F_g = -(rho - s) g, where the
+// subtracted density s is 0, <rho> or rho_v (-(rho - 0) g is -rho g exactly).
+// s is uniform over a launch, so the kernels form it once.
+__device__ __forceinline__ double gravity_sub(int form, double mean, double rho_v)
 {
-    return form == 2 ? -(rho - mean) * g : (form == 3 ? -(rho - rho_v) * g : -rho * g);
+    return form == 2 ? mean : (form == 3 ? rho_v : 0.0);
 }
+__device__ __forceinline__ double gravity_force(double rho, double sub, double g) { return -(rho - sub) * g; }
 
 // Reciprocal of a positive normal double: hardware estimate refined by two
 // Newton steps (within about one ulp; no special-case handling, so callers
