@@ -208,11 +208,11 @@ __global__ __launch_bounds__(256) void d3q19_pass_a(const S *__restrict__ fin, c
 // halo (66 x 6 x 6) in LDS once, and evaluates every stencil from there.
 // Tiles are walked persistently; XCD k takes the k-th contiguous eighth of
 // them (z-slabs), as for the rows of pass A.
-constexpr int kTX = 64, kTY = 4, kTZ = 4;
+constexpr int kTX = 64, kTY = 8, kTZ = 4;
 constexpr int kRX = kTX + 2, kRY = kTY + 2, kRZ = kTZ + 2;
 constexpr int kRegion = kRX * kRY * kRZ;
 constexpr int kTileNodes = kTX * kTY * kTZ;
-constexpr int kStencilThreads = 256;
+constexpr int kStencilThreads = 512;
 
 struct TileIter {
     int first, end, step;
@@ -423,8 +423,8 @@ __global__ __launch_bounds__(kStencilThreads) void d3q19_pass_d(const double *__
                                                                 StepState *__restrict__ st, int64_t step)
 {
     __shared__ double s_Tt[kRegion];  // T~ = T^n + k1
-    __shared__ double s_red[16];
-    __shared__ unsigned s_ured[4];
+    __shared__ double s_red[4 * kStencilThreads / 64];
+    __shared__ unsigned s_ured[kStencilThreads / 64];
     const unsigned N = G.N;
     const double rr = c.rho_ref;
     Partial part = {0.0, 0.0, 0.0, 1e300, 0u};
