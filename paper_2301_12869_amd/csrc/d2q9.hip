@@ -313,7 +313,8 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step(const S *__res
     __shared__ double s_ux[H2 * W2];
     __shared__ double s_uy[H2 * W2];
     __shared__ double s_Z[H2 * W2];
-    __shared__ double s_k1[H1 * W1];  // first Heun stage K(T^n); T~ = T^n + k1
+    __shared__ double s_k1[H1 * W1];   // first Heun stage K(T^n); T~ = T^n + k1
+    __shared__ double s_div[H1 * W1];  // div u, for both Heun stages
     __shared__ double s_red[4 * kThreads / 64];
     __shared__ unsigned s_ured[kThreads / 64];
 
@@ -420,12 +421,14 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step(const S *__res
             const int c2 = (ry + 1) * W2 + (rx + 1);
             if (WALLS && (gy <= 0 || gy >= ny - 1)) {
                 s_k1[r] = 0.0;  // Dirichlet walls (and nodes beyond them): T~ = T
+                s_div[r] = 0.0;
                 continue;
             }
             const double divu = divergence(s_ux, s_uy, c2, W2);
             Stencil tt;
             tt.load(s_T, c2, W2);
             s_k1[r] = energy_rhs(c, tt, s_T[c2], s_ux[c2], s_uy[c2], divu, rcp_pos(s_rho[c2]), s_Z[c2]);
+            s_div[r] = divu;
         }
         __syncthreads();
 
@@ -446,7 +449,7 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step(const S *__res
             // temperature
             double Tn = T;
             if (!wall) {
-                const double divu = divergence(s_ux, s_uy, c2, W2);
+                const double divu = s_div[c1];
                 Stencil tt, kk;  // T~ = T^n + k1 at the node and its neighbours
                 tt.load(s_T, c2, W2);
                 kk.load(s_k1, c1, W1);
