@@ -764,14 +764,17 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step_mom(const doub
             part.flags |= fl;
         }
 
-        // ---- phase 4b: post-collision sets of tile + 1 (registers) ----
-        double fsr[NS1][9];
+        __syncthreads();  // every read of s_k1, s_Tt, s_div, s_T, s_Z is done: they become exchange planes
+
+        // ---- phase 4b: post-collision sets of tile + 1; populations 0..4 go
+        // straight to the exchange planes, 5..8 stay in registers ----
+        double fsr[NS1][9 - NP];
         double nm_own[NS1];
 #pragma unroll
         for (int k = 0; k < NS1; ++k) {
             const int r = tid + k * NT;
 #pragma unroll
-            for (int i = 0; i < 9; ++i) fsr[k][i] = 0.0;
+            for (int i = 0; i < 9 - NP; ++i) fsr[k][i] = 0.0;
             nm_own[k] = 0.0;
             if (r < R1N) {
                 const int ry = r / W1, rx = r - ry * W1;
@@ -781,22 +784,29 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step_mom(const doub
                     valid = (gy >= 0 && gy < ny);
                     wall = (gy == 0 || gy == ny - 1);
                 }
+                double fs[9];
+#pragma unroll
+                for (int i = 0; i < 9; ++i) fs[i] = 0.0;  // nodes beyond a wall send nothing
                 if (valid) {
                     const int c2 = (ry + 1) * W2 + (rx + 1);
                     const int c3 = (ry + 2) * W3 + (rx + 2);
                     const double rho = s_rho[c2];
                     double Fx, Fy, X;
                     node_force(c, s_psi, c3, W3, rho, sub, wall, Fx, Fy, X);
-                    collide_tau1(c, rho, s_ux[c2], s_uy[c2], Fx, Fy, X, fsr[k]);
+                    collide_tau1(c, rho, s_ux[c2], s_uy[c2], Fx, Fy, X, fs);
                     // the next level's mass of the tile nodes (periodic y
                     // wraps rows: only nodes of the tile itself count)
                     const int ty = ry - 1, tx = rx - 1;
                     if (ty >= 0 && ty < TY && tx >= 0 && tx < TX && x0 + tx < nx && y0 + ty < ny)
-                        nm_own[k] = next_mass<WALLS>(fsr[k], y0 + ty, ny);
+                        nm_own[k] = next_mass<WALLS>(fs, y0 + ty, ny);
                 }
+#pragma unroll
+                for (int j = 0; j < NP; ++j) plane[j][r] = fs[j];
+#pragma unroll
+                for (int i = 0; i < 9 - NP; ++i) fsr[k][i] = fs[NP + i];
             }
         }
-        __syncthreads();  // every read of s_rho, s_ux, s_uy, s_T, s_Z, s_k1 is done
+        __syncthreads();  // every read of s_rho, s_ux, s_uy is done; planes hold populations 0..4
 
         // the tile nodes' mass contributions, accumulated below in the tile
         // loop's node order (s_rho is free now)
@@ -810,20 +820,22 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step_mom(const doub
             }
         }
 
-        // ---- phase 4c: pull through two rounds of up to five planes ----
+        // ---- phase 4c: pull, in two rounds of up to five planes ----
         double fp[NST][9];
 #pragma unroll
         for (int i0 = 0; i0 < 9; i0 += NP) {
+            if (i0 > 0) {
 #pragma unroll
-            for (int k = 0; k < NS1; ++k) {
-                const int r = tid + k * NT;
-                if (r < R1N) {
+                for (int k = 0; k < NS1; ++k) {
+                    const int r = tid + k * NT;
+                    if (r < R1N) {
 #pragma unroll
-                    for (int j = 0; j < NP; ++j)
-                        if (i0 + j < 9) plane[j][r] = fsr[k][i0 + j];
+                        for (int j = 0; j < NP; ++j)
+                            if (i0 + j < 9) plane[j][r] = fsr[k][i0 + j - NP];
+                    }
                 }
+                __syncthreads();
             }
-            __syncthreads();
 #pragma unroll
             for (int k = 0; k < NST; ++k) {
                 const int r = tid + k * NT;
@@ -999,9 +1011,11 @@ __global__ void d2q9_readout_b(const double *__restrict__ scr, const double *__r
 // Tile of 64 x 32 nodes per block of 1024 threads (16 wavefronts): the LDS
 // staging of a tile (about 137 KB) allows one block per compute unit.
 constexpr int kTX = 64, kTY = 32, kNT = 1024;
-// The moment kernel's tile is 29 rows high so that its tile + 1 ring
-// (66 x 31 = 2046 nodes) takes two slots of 1024 threads (about 159 KB of LDS).
-constexpr int kTYm = 29;
+// The moment kernel's tile is 26 rows high: its tile + 2 region (68 x 30 =
+// 2040 nodes) and tile + 1 region (66 x 28) take two slots of 1024 threads
+// each (about 144 KB of LDS), and 1024 x 2048 splits into 1264 tiles, at most
+// five per block of a 256-block grid.
+constexpr int kTYm = 26;
 
 template <class S, bool TAU1, bool WALLS>
 hipError_t launch_t(const LatticeLaunch &L)
