@@ -278,11 +278,21 @@ def test_full_size_1024x2048_against_the_oracle(T, orc, crit):
     rv, rl, _ = orc.coexistence(P, 0.8 * T_c)
     rho0 = W.layered_density((ny, nx), 64, rl, rv, 1e-3, seed=2)
     T0 = W.wall_temperature_field((ny, nx), 0.8 * T_c, 0.9 * T_c, 0.8 * T_c)
-    for form, g, prec in ((1, 1e-4, 0), (2, 1e-5, 1)):
-        _log(f"case full size form={form} precision={prec}")
+    # (form, g, precision, state): the benchmark's headline case (form 2,
+    # FP64, moment state) first, then form 1, the FP64 population state and
+    # the FP32-deviation storage
+    cases = ((2, 1e-5, 0, T.STATE_AUTO), (1, 1e-4, 0, T.STATE_AUTO), (2, 1e-5, 0, T.STATE_POPULATIONS),
+             (2, 1e-5, 1, T.STATE_AUTO))
+    wants = {}
+    for form, g, prec, state in cases:
+        _log(f"case full size form={form} precision={prec} state={state}")
         kw = dict(nx=nx, ny=ny, walls=True, g=g, gravity_form=form)
-        want = _run_oracle(orc, kw, rho0, T0, 3)
-        got = _run_gpu(T, kw, rho0, T0, 3, precision=prec, rho_ref=float(rho0.mean()))
-        tol = FP64_TOL if prec == 0 else FP32_RHO_TOL
-        assert _rel(got["rho"], want["rho"]) < tol
-        assert _rel(got["T"], want["T"]) < tol
+        if (form, g) not in wants:
+            wants[(form, g)] = _run_oracle(orc, kw, rho0, T0, 3)
+        want = wants[(form, g)]
+        got = _run_gpu(T, dict(kw, state=state), rho0, T0, 3, precision=prec, rho_ref=float(rho0.mean()))
+        if prec == 0:
+            _check_fields(got, want, FP64_TOL, FP64_TOL * 1e-1)
+        else:
+            assert _rel(got["rho"], want["rho"]) < FP32_RHO_TOL
+            assert _rel(got["T"], want["T"]) < FP32_RHO_TOL
