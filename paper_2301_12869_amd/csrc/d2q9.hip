@@ -582,10 +582,13 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step(const S *__res
 //   phases 2, 3: as in the population kernel (force, velocity; k1), and
 //            T~ = T^n + k1 and div u kept in LDS for the second stage
 //   phase 4a, tile: T^{n+1}, stored; statistics of level n
-//   phase 4b, tile + 1: post-collision set f*(y) of every node (registers)
-//            and the next level's mass contribution of the tile nodes
-//   phase 4c: two rounds of five and four directions through LDS planes:
-//            each tile node x pulls f*_i(x - c_i)
+//   phase 4b, tile + 1 (after a barrier, so that the energy update's LDS
+//            fields are free): post-collision set f*(y) of every node,
+//            directions 0..4 written straight to five LDS planes, 5..8 kept
+//            in registers; the next level's mass contribution of the tile
+//            nodes
+//   phase 4c: each tile node x pulls f*_i(x - c_i) from the planes, then
+//            directions 5..8 go through the same planes
 //   phase 4d, tile: Zou-He and the moments of the pulled set -> M^{n+1}.
 // Phases 4b-4d evaluate the same source expressions, in the same order, as
 // the population kernel's collision, store, pull and moment sums (shared
