@@ -19,6 +19,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -42,10 +43,15 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "d2q9_1024x2048_traffic.json")
 
 
 def source_hash() -> str:
+    """Hash of the kernel sources' code: comments and whitespace are dropped,
+    so only a change to the code itself invalidates the counter record."""
     h = hashlib.sha256()
     for s in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, s), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, s)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
