@@ -35,6 +35,20 @@ struct V3 {
 };
 __host__ __device__ constexpr V3 vel(int i) { return V3{kD3Q19x[i], kD3Q19y[i], kD3Q19z[i]}; }
 __host__ __device__ constexpr double wgt(int i) { return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
+// c . (a, b, c) over the nonzero components of c only, in x, y, z order.  In
+// the unrolled loops c is a compile-time constant, so a zero component costs
+// neither a load nor a multiply-add; the result equals the full sum (the
+// skipped terms are signed zeros).
+__device__ __forceinline__ double cdot(const V3 v, double a, double b, double c)
+{
+    double s = 0.0;
+    bool any = false;
+    if (v.x) { s = v.x * a; any = true; }
+    if (v.y) { s = any ? s + v.y * b : v.y * b; any = true; }
+    if (v.z) { s = any ? s + v.z * c : v.z * c; any = true; }
+    return s;
+}
+
 // opposite velocity
 __host__ __device__ constexpr int opp(int i)
 {
@@ -172,14 +186,19 @@ __global__ __launch_bounds__(256) void d3q19_pass_a(const S *__restrict__ fin, c
                 for (int i = 0; i < 19; ++i) {
                     const V3 v = vel(i);
                     if (v.z == 0) {
-                        Nx += 0.5 * v.x * f[i];
-                        Ny += 0.5 * v.y * f[i];
+                        if (v.x) Nx += 0.5 * v.x * f[i];
+                        if (v.y) Ny += 0.5 * v.y * f[i];
                     }
                 }
 #pragma unroll
                 for (int i = 0; i < 19; ++i) {
                     const V3 v = vel(i);
-                    if (v.z == s) f[i] = f[opp(i)] - (double)v.x * Nx - (double)v.y * Ny;
+                    if (v.z == s) {
+                        double r = f[opp(i)];
+                        if (v.x) r -= (double)v.x * Nx;
+                        if (v.y) r -= (double)v.y * Ny;
+                        f[i] = r;
+                    }
                 }
             }
             double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
@@ -187,9 +206,9 @@ __global__ __launch_bounds__(256) void d3q19_pass_a(const S *__restrict__ fin, c
             for (int i = 0; i < 19; ++i) {
                 const V3 v = vel(i);
                 rho += f[i];
-                jx += v.x * f[i];
-                jy += v.y * f[i];
-                jz += v.z * f[i];
+                if (v.x) jx += v.x * f[i];
+                if (v.y) jy += v.y * f[i];
+                if (v.z) jz += v.z * f[i];
             }
             double Z;
             const double psi = psi_and_Z(c, rho, Tin[n], Z);
@@ -213,6 +232,9 @@ constexpr int kRX = kTX + 2, kRY = kTY + 2, kRZ = kTZ + 2;
 constexpr int kRegion = kRX * kRY * kRZ;
 constexpr int kTileNodes = kTX * kTY * kTZ;
 constexpr int kStencilThreads = 512;
+// Pass C stages four fields of the region (about 127 KB of LDS), so one block
+// fits a compute unit; it takes 1024 threads to keep 4 waves per SIMD busy.
+constexpr int kPassCThreads = 1024;
 
 struct TileIter {
     int first, end, step;
@@ -279,9 +301,9 @@ __device__ __forceinline__ void sc_sum(const double *__restrict__ sp, int tx, in
         const V3 v = vel(i);
         const double w = i < 7 ? 1.0 / 6.0 : 1.0 / 12.0;
         const double p = sp[rnb(tx, ty, tz, v.x, v.y, v.z)];
-        sx += w * v.x * p;
-        sy += w * v.y * p;
-        sz += w * v.z * p;
+        if (v.x) sx += w * v.x * p;
+        if (v.y) sy += w * v.y * p;
+        if (v.z) sz += w * v.z * p;
     }
 }
 
@@ -341,9 +363,9 @@ __device__ __forceinline__ void grad_lap(const double *__restrict__ a, int tx, i
         const V3 v = vel(i);
         const double p = a[rnb(tx, ty, tz, v.x, v.y, v.z)];
         const double w = wgt(i);
-        gx += w * v.x * p;
-        gy += w * v.y * p;
-        gz += w * v.z * p;
+        if (v.x) gx += w * v.x * p;
+        if (v.y) gy += w * v.y * p;
+        if (v.z) gz += w * v.z * p;
         lap += w * (p - c0);
     }
     gx *= 3.0;
@@ -361,14 +383,14 @@ __device__ __forceinline__ double div3(const double *__restrict__ ux, const doub
     for (int i = 1; i < 19; ++i) {
         const V3 v = vel(i);
         const int m = rnb(tx, ty, tz, v.x, v.y, v.z);
-        d += wgt(i) * (v.x * ux[m] + v.y * uy[m] + v.z * uz[m]);
+        d += wgt(i) * cdot(v, v.x ? ux[m] : 0.0, v.y ? uy[m] : 0.0, v.z ? uz[m] : 0.0);
     }
     return 3.0 * d;
 }
 
 // ---- pass C: div u and the first Heun stage ------------------------------------
 template <bool WALLS>
-__global__ __launch_bounds__(kStencilThreads) void d3q19_pass_c(const double *__restrict__ Tin,
+__global__ __launch_bounds__(kPassCThreads) void d3q19_pass_c(const double *__restrict__ Tin,
                                                                 const double *__restrict__ M,
                                                                 const double *__restrict__ U,
                                                                 double *__restrict__ K1, Phys c, Grid3 G)
@@ -380,7 +402,7 @@ __global__ __launch_bounds__(kStencilThreads) void d3q19_pass_c(const double *__
     for (int t = it.first; t < it.end; t += it.step) {
         const Tile3 o = tile_origin(G, t);
         __syncthreads();
-        for (int r = threadIdx.x; r < kRegion; r += kStencilThreads) {
+        for (int r = threadIdx.x; r < kRegion; r += kPassCThreads) {
             const unsigned m = region_index<WALLS>(G, o, r);
             s_T[r] = Tin[m];
             s_ux[r] = U[m];
@@ -388,7 +410,7 @@ __global__ __launch_bounds__(kStencilThreads) void d3q19_pass_c(const double *__
             s_uz[r] = U[2 * (size_t)N + m];
         }
         __syncthreads();
-        for (int k = threadIdx.x; k < kTileNodes; k += kStencilThreads) {
+        for (int k = threadIdx.x; k < kTileNodes; k += kPassCThreads) {
             const int tx = k % kTX, ty = (k / kTX) % kTY, tz = k / (kTX * kTY);
             const int x = o.x0 + tx, y = o.y0 + ty, z = o.z0 + tz;
             if (x >= G.nx || y >= G.ny || z >= G.nz) continue;
@@ -468,8 +490,8 @@ __global__ __launch_bounds__(kStencilThreads) void d3q19_pass_d(const double *__
             for (int i = 1; i < 19; ++i) {
                 const V3 v = vel(i);
                 const double w = wgt(i);
-                const double cu = v.x * ux + v.y * uy + v.z * uz;
-                const double cF = v.x * Fx + v.y * Fy + v.z * Fz;
+                const double cu = cdot(v, ux, uy, uz);
+                const double cF = cdot(v, Fx, Fy, Fz);
                 const double c2 = (double)(v.x * v.x + v.y * v.y + v.z * v.z);
                 fs[i] = w * (rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu) + 1.5 * (cF - uF) + 4.5 * cu * cF +
                              (c2 - 1.0) * 0.75 * Xs2);
@@ -576,7 +598,7 @@ hipError_t step_t(const LatticeLaunch &L, double *M, double *U, double *K1)
     const int gT = grid_tiles(L.nx, L.ny, L.nz, L.resident);
     hipLaunchKernelGGL((d3q19_pass_b<WALLS>), dim3(gT), dim3(kStencilThreads), 0, L.stream, M, U, L.phys, G, L.st,
                        (int)(L.step & 1));
-    hipLaunchKernelGGL((d3q19_pass_c<WALLS>), dim3(gT), dim3(kStencilThreads), 0, L.stream, L.Tin, M, U, K1,
+    hipLaunchKernelGGL((d3q19_pass_c<WALLS>), dim3(gT), dim3(kPassCThreads), 0, L.stream, L.Tin, M, U, K1,
                        L.phys, G);
     hipLaunchKernelGGL((d3q19_pass_d<S, WALLS>), dim3(gT), dim3(kStencilThreads), 0, L.stream, L.Tin, L.Tout, M,
                        U, K1,
