@@ -223,18 +223,28 @@ __global__ __launch_bounds__(256) void d3q19_pass_a(const S *__restrict__ fin, c
 
 // ---- tiles for the stencil passes -------------------------------------------
 // Passes B, C and D evaluate 18-neighbour stencils.  A block takes a tile of
-// 64 x 4 x 4 nodes, stages the stencil fields of the tile plus a one-node
-// halo (66 x 6 x 6) in LDS once, and evaluates every stencil from there.
-// Tiles are walked persistently; XCD k takes the k-th contiguous eighth of
-// them (z-slabs), as for the rows of pass A.
-constexpr int kTX = 64, kTY = 8, kTZ = 4;
-constexpr int kRX = kTX + 2, kRY = kTY + 2, kRZ = kTZ + 2;
-constexpr int kRegion = kRX * kRY * kRZ;
-constexpr int kTileNodes = kTX * kTY * kTZ;
+// TX x TY x TZ nodes, stages the stencil fields of the tile plus a one-node
+// halo ((TX + 2) x (TY + 2) x (TZ + 2), the region) in LDS once, and
+// evaluates every stencil from there.  Tiles are walked persistently; XCD k
+// takes the k-th contiguous eighth of them (z-slabs), as for the rows of
+// pass A.
+template <int TX_, int TY_, int TZ_>
+struct TileShape {
+    static constexpr int TX = TX_, TY = TY_, TZ = TZ_;
+    static constexpr int RX = TX + 2, RY = TY + 2, RZ = TZ + 2;
+    static constexpr int Region = RX * RY * RZ, Nodes = TX * TY * TZ;
+    __host__ __device__ static int count(int nx, int ny, int nz)
+    {
+        return ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY) * ((nz + TZ - 1) / TZ);
+    }
+};
+// Passes B and D stage one field each (the region of a 64 x 8 x 4 tile:
+// 66 x 10 x 6 nodes, 31.7 KB).  Pass C stages four; with a 32 x 8 x 4 tile
+// (34 x 10 x 6 nodes, 65 KB) two of its 512-thread blocks share a compute
+// unit.
+using TileBD = TileShape<64, 8, 4>;
+using TileC = TileShape<32, 8, 4>;
 constexpr int kStencilThreads = 512;
-// Pass C stages four fields of the region (about 127 KB of LDS), so one block
-// fits a compute unit; it takes 1024 threads to keep 4 waves per SIMD busy.
-constexpr int kPassCThreads = 1024;
 
 struct TileIter {
     int first, end, step;
@@ -260,13 +270,14 @@ __device__ __forceinline__ TileIter tile_iter(int ntiles)
 struct Tile3 {
     int x0, y0, z0;
 };
+template <class Sh>
 __device__ __forceinline__ Tile3 tile_origin(const Grid3 &G, int t)
 {
-    const int tx = (G.nx + kTX - 1) / kTX, ty = (G.ny + kTY - 1) / kTY;
+    const int tx = (G.nx + Sh::TX - 1) / Sh::TX, ty = (G.ny + Sh::TY - 1) / Sh::TY;
     Tile3 o;
-    o.x0 = (t % tx) * kTX;
-    o.y0 = ((t / tx) % ty) * kTY;
-    o.z0 = (t / (tx * ty)) * kTZ;
+    o.x0 = (t % tx) * Sh::TX;
+    o.y0 = ((t / tx) % ty) * Sh::TY;
+    o.z0 = (t / (tx * ty)) * Sh::TZ;
     return o;
 }
 
@@ -274,10 +285,10 @@ __device__ __forceinline__ int periodic(int v, int n) { return v < 0 ? n - 1 : (
 
 // global index of region node r (periodic x, y; z periodic or clamped at
 // walls -- clamped values are never used by a stencil)
-template <bool WALLS>
+template <bool WALLS, class Sh>
 __device__ __forceinline__ unsigned region_index(const Grid3 &G, const Tile3 &o, int r)
 {
-    const int rx = r % kRX, ry = (r / kRX) % kRY, rz = r / (kRX * kRY);
+    const int rx = r % Sh::RX, ry = (r / Sh::RX) % Sh::RY, rz = r / (Sh::RX * Sh::RY);
     const int x = periodic(o.x0 + rx - 1, G.nx), y = periodic(o.y0 + ry - 1, G.ny);
     int z = o.z0 + rz - 1;
     if (WALLS) z = z < 0 ? 0 : (z >= G.nz ? G.nz - 1 : z);
@@ -286,12 +297,14 @@ __device__ __forceinline__ unsigned region_index(const Grid3 &G, const Tile3 &o,
 }
 
 // region index of the neighbour (dx, dy, dz) of tile node (tx, ty, tz)
+template <class Sh>
 __device__ __forceinline__ int rnb(int tx, int ty, int tz, int dx, int dy, int dz)
 {
-    return ((tz + 1 + dz) * kRY + (ty + 1 + dy)) * kRX + (tx + 1 + dx);
+    return ((tz + 1 + dz) * Sh::RY + (ty + 1 + dy)) * Sh::RX + (tx + 1 + dx);
 }
 
 // Shan-Chen sum s = sum_i w(|c_i|^2) psi(x + c_i) c_i, w(1) = 1/6, w(2) = 1/12
+template <class Sh>
 __device__ __forceinline__ void sc_sum(const double *__restrict__ sp, int tx, int ty, int tz, double &sx,
                                        double &sy, double &sz)
 {
@@ -300,7 +313,7 @@ __device__ __forceinline__ void sc_sum(const double *__restrict__ sp, int tx, in
     for (int i = 1; i < 19; ++i) {
         const V3 v = vel(i);
         const double w = i < 7 ? 1.0 / 6.0 : 1.0 / 12.0;
-        const double p = sp[rnb(tx, ty, tz, v.x, v.y, v.z)];
+        const double p = sp[rnb<Sh>(tx, ty, tz, v.x, v.y, v.z)];
         if (v.x) sx += w * v.x * p;
         if (v.y) sy += w * v.y * p;
         if (v.z) sz += w * v.z * p;
@@ -313,19 +326,20 @@ __global__ __launch_bounds__(kStencilThreads) void d3q19_pass_b(const double *__
                                                                 Phys c, Grid3 G, const StepState *__restrict__ st,
                                                                 int slot)
 {
-    __shared__ double s_psi[kRegion];
+    using Sh = TileBD;
+    __shared__ double s_psi[Sh::Region];
     const unsigned N = G.N;
     const double mean = st->mean[slot];
-    const int ntiles = ((G.nx + kTX - 1) / kTX) * ((G.ny + kTY - 1) / kTY) * ((G.nz + kTZ - 1) / kTZ);
+    const int ntiles = Sh::count(G.nx, G.ny, G.nz);
     const TileIter it = tile_iter(ntiles);
     for (int t = it.first; t < it.end; t += it.step) {
-        const Tile3 o = tile_origin(G, t);
+        const Tile3 o = tile_origin<Sh>(G, t);
         __syncthreads();
-        for (int r = threadIdx.x; r < kRegion; r += kStencilThreads)
-            s_psi[r] = M[4 * (size_t)N + region_index<WALLS>(G, o, r)];
+        for (int r = threadIdx.x; r < Sh::Region; r += kStencilThreads)
+            s_psi[r] = M[4 * (size_t)N + region_index<WALLS, Sh>(G, o, r)];
         __syncthreads();
-        for (int k = threadIdx.x; k < kTileNodes; k += kStencilThreads) {
-            const int tx = k % kTX, ty = (k / kTX) % kTY, tz = k / (kTX * kTY);
+        for (int k = threadIdx.x; k < Sh::Nodes; k += kStencilThreads) {
+            const int tx = k % Sh::TX, ty = (k / Sh::TX) % Sh::TY, tz = k / (Sh::TX * Sh::TY);
             const int x = o.x0 + tx, y = o.y0 + ty, z = o.z0 + tz;
             if (x >= G.nx || y >= G.ny || z >= G.nz) continue;
             const unsigned n = ((unsigned)z * (unsigned)G.ny + (unsigned)y) * (unsigned)G.nx + (unsigned)x;
@@ -333,8 +347,8 @@ __global__ __launch_bounds__(kStencilThreads) void d3q19_pass_b(const double *__
             double Fx = 0.0, Fy = 0.0, Fz = 0.0, Xs2 = 0.0;
             if (!(WALLS && (z == 0 || z == G.nz - 1))) {
                 double sx, sy, sz;
-                sc_sum(s_psi, tx, ty, tz, sx, sy, sz);
-                const double mg = -c.G * s_psi[rnb(tx, ty, tz, 0, 0, 0)];
+                sc_sum<Sh>(s_psi, tx, ty, tz, sx, sy, sz);
+                const double mg = -c.G * s_psi[rnb<Sh>(tx, ty, tz, 0, 0, 0)];
                 Fx = mg * sx;
                 Fy = mg * sy;
                 Fz = mg * sz + gravity_force(rho, gravity_sub(c.form, mean, c.rho_v), c.g);
@@ -354,6 +368,7 @@ __global__ __launch_bounds__(kStencilThreads) void d3q19_pass_b(const double *__
 
 // isotropic differences on the D3Q19 stencil from a region field:
 // grad = 3 sum w c phi, lap = 6 sum w (phi_i - phi_0)
+template <class Sh>
 __device__ __forceinline__ void grad_lap(const double *__restrict__ a, int tx, int ty, int tz, double c0, double &gx,
                                          double &gy, double &gz, double &lap)
 {
@@ -361,7 +376,7 @@ __device__ __forceinline__ void grad_lap(const double *__restrict__ a, int tx, i
 #pragma unroll
     for (int i = 1; i < 19; ++i) {
         const V3 v = vel(i);
-        const double p = a[rnb(tx, ty, tz, v.x, v.y, v.z)];
+        const double p = a[rnb<Sh>(tx, ty, tz, v.x, v.y, v.z)];
         const double w = wgt(i);
         if (v.x) gx += w * v.x * p;
         if (v.y) gy += w * v.y * p;
@@ -375,6 +390,7 @@ __device__ __forceinline__ void grad_lap(const double *__restrict__ a, int tx, i
 }
 
 // div u = 3 sum w c.u_i from the region fields of u
+template <class Sh>
 __device__ __forceinline__ double div3(const double *__restrict__ ux, const double *__restrict__ uy,
                                        const double *__restrict__ uz, int tx, int ty, int tz)
 {
@@ -382,7 +398,7 @@ __device__ __forceinline__ double div3(const double *__restrict__ ux, const doub
 #pragma unroll
     for (int i = 1; i < 19; ++i) {
         const V3 v = vel(i);
-        const int m = rnb(tx, ty, tz, v.x, v.y, v.z);
+        const int m = rnb<Sh>(tx, ty, tz, v.x, v.y, v.z);
         d += wgt(i) * cdot(v, v.x ? ux[m] : 0.0, v.y ? uy[m] : 0.0, v.z ? uz[m] : 0.0);
     }
     return 3.0 * d;
@@ -390,28 +406,29 @@ __device__ __forceinline__ double div3(const double *__restrict__ ux, const doub
 
 // ---- pass C: div u and the first Heun stage ------------------------------------
 template <bool WALLS>
-__global__ __launch_bounds__(kPassCThreads) void d3q19_pass_c(const double *__restrict__ Tin,
+__global__ __launch_bounds__(kStencilThreads) void d3q19_pass_c(const double *__restrict__ Tin,
                                                                 const double *__restrict__ M,
                                                                 const double *__restrict__ U,
                                                                 double *__restrict__ K1, Phys c, Grid3 G)
 {
-    __shared__ double s_T[kRegion], s_ux[kRegion], s_uy[kRegion], s_uz[kRegion];
+    using Sh = TileC;
+    __shared__ double s_T[Sh::Region], s_ux[Sh::Region], s_uy[Sh::Region], s_uz[Sh::Region];
     const unsigned N = G.N;
-    const int ntiles = ((G.nx + kTX - 1) / kTX) * ((G.ny + kTY - 1) / kTY) * ((G.nz + kTZ - 1) / kTZ);
+    const int ntiles = Sh::count(G.nx, G.ny, G.nz);
     const TileIter it = tile_iter(ntiles);
     for (int t = it.first; t < it.end; t += it.step) {
-        const Tile3 o = tile_origin(G, t);
+        const Tile3 o = tile_origin<Sh>(G, t);
         __syncthreads();
-        for (int r = threadIdx.x; r < kRegion; r += kPassCThreads) {
-            const unsigned m = region_index<WALLS>(G, o, r);
+        for (int r = threadIdx.x; r < Sh::Region; r += kStencilThreads) {
+            const unsigned m = region_index<WALLS, Sh>(G, o, r);
             s_T[r] = Tin[m];
             s_ux[r] = U[m];
             s_uy[r] = U[N + m];
             s_uz[r] = U[2 * (size_t)N + m];
         }
         __syncthreads();
-        for (int k = threadIdx.x; k < kTileNodes; k += kPassCThreads) {
-            const int tx = k % kTX, ty = (k / kTX) % kTY, tz = k / (kTX * kTY);
+        for (int k = threadIdx.x; k < Sh::Nodes; k += kStencilThreads) {
+            const int tx = k % Sh::TX, ty = (k / Sh::TX) % Sh::TY, tz = k / (Sh::TX * Sh::TY);
             const int x = o.x0 + tx, y = o.y0 + ty, z = o.z0 + tz;
             if (x >= G.nx || y >= G.ny || z >= G.nz) continue;
             const unsigned n = ((unsigned)z * (unsigned)G.ny + (unsigned)y) * (unsigned)G.nx + (unsigned)x;
@@ -420,11 +437,11 @@ __global__ __launch_bounds__(kPassCThreads) void d3q19_pass_c(const double *__re
                 K1[N + n] = 0.0;
                 continue;
             }
-            const int c0 = rnb(tx, ty, tz, 0, 0, 0);
+            const int c0 = rnb<Sh>(tx, ty, tz, 0, 0, 0);
             const double rho = M[n], T0 = s_T[c0];
             double gx, gy, gz, lap;
-            grad_lap(s_T, tx, ty, tz, T0, gx, gy, gz, lap);
-            const double divu = div3(s_ux, s_uy, s_uz, tx, ty, tz);
+            grad_lap<Sh>(s_T, tx, ty, tz, T0, gx, gy, gz, lap);
+            const double divu = div3<Sh>(s_ux, s_uy, s_uz, tx, ty, tz);
             const double Z = c.eos == 0 ? cs_Z(c.b_quarter * rho) : 0.0;
             K1[n] = -(s_ux[c0] * gx + s_uy[c0] * gy + s_uz[c0] * gz) + c.kappa_over_cv * rcp_pos(rho) * lap -
                     T0 * c.R_over_cv * Z * divu;
@@ -444,24 +461,25 @@ __global__ __launch_bounds__(kStencilThreads) void d3q19_pass_d(const double *__
                                                                 double *__restrict__ partials,
                                                                 StepState *__restrict__ st, int64_t step)
 {
-    __shared__ double s_Tt[kRegion];  // T~ = T^n + k1
+    using Sh = TileBD;
+    __shared__ double s_Tt[Sh::Region];  // T~ = T^n + k1
     __shared__ double s_red[4 * kStencilThreads / 64];
     __shared__ unsigned s_ured[kStencilThreads / 64];
     const unsigned N = G.N;
     const double rr = c.rho_ref;
     Partial part = {0.0, 0.0, 0.0, 1e300, 0u};
-    const int ntiles = ((G.nx + kTX - 1) / kTX) * ((G.ny + kTY - 1) / kTY) * ((G.nz + kTZ - 1) / kTZ);
+    const int ntiles = Sh::count(G.nx, G.ny, G.nz);
     const TileIter it = tile_iter(ntiles);
     for (int t = it.first; t < it.end; t += it.step) {
-        const Tile3 o = tile_origin(G, t);
+        const Tile3 o = tile_origin<Sh>(G, t);
         __syncthreads();
-        for (int r = threadIdx.x; r < kRegion; r += kStencilThreads) {
-            const unsigned m = region_index<WALLS>(G, o, r);
+        for (int r = threadIdx.x; r < Sh::Region; r += kStencilThreads) {
+            const unsigned m = region_index<WALLS, Sh>(G, o, r);
             s_Tt[r] = Tin[m] + K1[m];
         }
         __syncthreads();
-        for (int k = threadIdx.x; k < kTileNodes; k += kStencilThreads) {
-            const int tx = k % kTX, ty = (k / kTX) % kTY, tz = k / (kTX * kTY);
+        for (int k = threadIdx.x; k < Sh::Nodes; k += kStencilThreads) {
+            const int tx = k % Sh::TX, ty = (k / Sh::TX) % Sh::TY, tz = k / (Sh::TX * Sh::TY);
             const int x = o.x0 + tx, y = o.y0 + ty, z = o.z0 + tz;
             if (x >= G.nx || y >= G.ny || z >= G.nz) continue;
             const unsigned n = ((unsigned)z * (unsigned)G.ny + (unsigned)y) * (unsigned)G.nx + (unsigned)x;
@@ -471,7 +489,7 @@ __global__ __launch_bounds__(kStencilThreads) void d3q19_pass_d(const double *__
             if (!wall) {
                 const double k1 = K1[n];
                 double gx, gy, gz, lap;
-                grad_lap(s_Tt, tx, ty, tz, T0 + k1, gx, gy, gz, lap);
+                grad_lap<Sh>(s_Tt, tx, ty, tz, T0 + k1, gx, gy, gz, lap);
                 const double divu = K1[N + n];
                 const double Z = c.eos == 0 ? cs_Z(c.b_quarter * rho) : 0.0;
                 const double k2 = -(ux * gx + uy * gy + uz * gz) + c.kappa_over_cv * rcp_pos(rho) * lap -
@@ -581,9 +599,10 @@ int grid_rows(int ny, int nz, int cus)
 }
 
 // one block per tile, at most 4 resident blocks per compute unit (LDS)
+template <class Sh>
 int grid_tiles(int nx, int ny, int nz, int cus)
 {
-    const long t = (long)((nx + kTX - 1) / kTX) * ((ny + kTY - 1) / kTY) * ((nz + kTZ - 1) / kTZ);
+    const long t = Sh::count(nx, ny, nz);
     const long cap = (long)cus * 4;
     return (int)(t < cap ? t : cap);
 }
@@ -595,10 +614,11 @@ hipError_t step_t(const LatticeLaunch &L, double *M, double *U, double *K1)
     const int gA = grid_rows(L.ny, L.nz, L.resident);
     hipLaunchKernelGGL((d3q19_pass_a<S, WALLS>), dim3(gA), dim3(256), 0, L.stream, (const S *)L.fin, L.Tin, M,
                        L.phys, G);
-    const int gT = grid_tiles(L.nx, L.ny, L.nz, L.resident);
+    const int gT = grid_tiles<TileBD>(L.nx, L.ny, L.nz, L.resident);
+    const int gC = grid_tiles<TileC>(L.nx, L.ny, L.nz, L.resident);
     hipLaunchKernelGGL((d3q19_pass_b<WALLS>), dim3(gT), dim3(kStencilThreads), 0, L.stream, M, U, L.phys, G, L.st,
                        (int)(L.step & 1));
-    hipLaunchKernelGGL((d3q19_pass_c<WALLS>), dim3(gT), dim3(kPassCThreads), 0, L.stream, L.Tin, M, U, K1,
+    hipLaunchKernelGGL((d3q19_pass_c<WALLS>), dim3(gC), dim3(kStencilThreads), 0, L.stream, L.Tin, M, U, K1,
                        L.phys, G);
     hipLaunchKernelGGL((d3q19_pass_d<S, WALLS>), dim3(gT), dim3(kStencilThreads), 0, L.stream, L.Tin, L.Tout, M,
                        U, K1,
@@ -608,7 +628,8 @@ hipError_t step_t(const LatticeLaunch &L, double *M, double *U, double *K1)
 
 }  // namespace
 
-int d3q19_num_blocks(int nx, int ny, int nz, int cus) { return grid_tiles(nx, ny, nz, cus); }
+// the grid of pass D, which writes the per-block partials
+int d3q19_num_blocks(int nx, int ny, int nz, int cus) { return grid_tiles<TileBD>(nx, ny, nz, cus); }
 
 hipError_t d3q19_launch_step(const LatticeLaunch &L, double *M, double *U, double *K1)
 {
@@ -631,7 +652,7 @@ hipError_t d3q19_launch_readout(const LatticeLaunch &L, int field, double *M, do
         else
             hipLaunchKernelGGL((d3q19_pass_a<double, false>), dim3(g), dim3(256), 0, L.stream, (const double *)L.fin, L.Tin, M, L.phys, G);
     }
-    const int gT = grid_tiles(L.nx, L.ny, L.nz, L.resident);
+    const int gT = grid_tiles<TileBD>(L.nx, L.ny, L.nz, L.resident);
     if (L.walls) {
         hipLaunchKernelGGL((d3q19_pass_b<true>), dim3(gT), dim3(kStencilThreads), 0, L.stream, M, U, L.phys, G, L.st, (int)(L.step & 1));
         hipLaunchKernelGGL((d3q19_readout<true>), dim3(g), dim3(256), 0, L.stream, M, U, L.Tin, L.phys, G, field, out);
