@@ -156,6 +156,65 @@ __device__ __forceinline__ Xs xs_of(int x, int nx)
     return q;
 }
 
+// Zero-velocity wet-node reconstruction of the populations of a wall node
+// (z = 0 or nz - 1) that come from beyond the wall, with transverse momentum
+// corrections, then the density and momentum of the pulled set, for the
+// moment-state pass.  Pass A spells out the same statements in its body
+// (called from there, the array is not kept in registers).
+template <bool WALLS>
+__device__ __forceinline__ void pulled_moments3(double (&f)[19], int z, int nz, double &rho, double &jx,
+                                                double &jy, double &jz)
+{
+    if (WALLS && (z == 0 || z == nz - 1)) {
+        const int s = z == 0 ? 1 : -1;
+        double Nx = 0.0, Ny = 0.0;
+#pragma unroll
+        for (int i = 0; i < 19; ++i) {
+            const V3 v = vel(i);
+            if (v.z == 0) {
+                if (v.x) Nx += 0.5 * v.x * f[i];
+                if (v.y) Ny += 0.5 * v.y * f[i];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 19; ++i) {
+            const V3 v = vel(i);
+            if (v.z == s) {
+                double r = f[opp(i)];
+                if (v.x) r -= (double)v.x * Nx;
+                if (v.y) r -= (double)v.y * Ny;
+                f[i] = r;
+            }
+        }
+    }
+    rho = jx = jy = jz = 0.0;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+        const V3 v = vel(i);
+        rho += f[i];
+        if (v.x) jx += v.x * f[i];
+        if (v.y) jy += v.y * f[i];
+        if (v.z) jz += v.z * f[i];
+    }
+}
+
+// Post-collision population i at every relaxation time 1 of a node with
+// density rho, force-corrected velocity u, force F and sigma |F_int|^2 /
+// psi^2 = Xs2 (uu = u.u, uF = u.F): f_eq + half of Guo's term + the
+// isotropic sigma term.  Pass D closes the rest population instead, f*_0 =
+// rho - sum_{i>0} f*_i, which equals the i = 0 value in exact arithmetic.
+__device__ __forceinline__ double post_tau1(int i, double rho, double ux, double uy, double uz, double Fx, double Fy,
+                                            double Fz, double Xs2, double uu, double uF)
+{
+    const V3 v = vel(i);
+    const double w = wgt(i);
+    const double cu = cdot(v, ux, uy, uz);
+    const double cF = cdot(v, Fx, Fy, Fz);
+    const double c2 = (double)(v.x * v.x + v.y * v.y + v.z * v.z);
+    return w * (rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu) + 1.5 * (cF - uF) + 4.5 * cu * cF +
+                (c2 - 1.0) * 0.75 * Xs2);
+}
+
 // ---- pass A: pull, Zou-He, moments, psi ----------------------------------
 template <class S, bool WALLS>
 __global__ __launch_bounds__(256) void d3q19_pass_a(const S *__restrict__ fin, const double *__restrict__ Tin,
@@ -245,6 +304,10 @@ struct TileShape {
 using TileBD = TileShape<64, 8, 4>;
 using TileC = TileShape<32, 8, 4>;
 constexpr int kStencilThreads = 512;
+// The moment-state pass stages nine fields of a 32 x 8 x 4 tile's region
+// (34 x 10 x 6 nodes, 147 KB): one block per compute unit, 1024 threads.
+using TileM = TileShape<32, 8, 4>;
+constexpr int kMomThreads = 1024;
 
 struct TileIter {
     int first, end, step;
@@ -506,13 +569,7 @@ __global__ __launch_bounds__(kStencilThreads) void d3q19_pass_d(const double *__
             double rest = 0.0;
 #pragma unroll
             for (int i = 1; i < 19; ++i) {
-                const V3 v = vel(i);
-                const double w = wgt(i);
-                const double cu = cdot(v, ux, uy, uz);
-                const double cF = cdot(v, Fx, Fy, Fz);
-                const double c2 = (double)(v.x * v.x + v.y * v.y + v.z * v.z);
-                fs[i] = w * (rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu) + 1.5 * (cF - uF) + 4.5 * cu * cF +
-                             (c2 - 1.0) * 0.75 * Xs2);
+                fs[i] = post_tau1(i, rho, ux, uy, uz, Fx, Fy, Fz, Xs2, uu, uF);
                 rest += fs[i];
             }
             fs[0] = rho - rest;
@@ -545,6 +602,130 @@ __global__ __launch_bounds__(kStencilThreads) void d3q19_pass_d(const double *__
     }
     part = block_reduce<kStencilThreads>(part, s_red, s_ured);
     finish_launch<kStencilThreads>(part, partials, st, step, (int)((step + 1) & 1), 1.0 / (double)N, s_red, s_ured);
+}
+
+// ---- moment-state pass (every tau = 1, FP64) ----------------------------------
+// With every relaxation time 1 the post-collision set of a node is a closed
+// function of its (rho, u, F, X) (post_tau1), so the state between steps can
+// be the level's M = (rho, j, psi) and T instead of the 19 populations.  This
+// pass replaces pass D and the next step's pass A: it stages rho, u, F, X and
+// T~ = T^n + k1 on the region of a tile; every tile node
+//   * takes the second Heun stage (T^{n+1}, stored),
+//   * closes its own rest population, f*_0 = rho - sum_{i>0} f*_i, as pass D
+//     does,
+//   * pulls f_i(x) = f*_i(x - c_i), evaluating post_tau1 at the neighbour x - c_i,
+//   * reconstructs the wall populations, sums rho' and j', and evaluates
+//     psi(rho', T^{n+1}): M^{n+1}.
+// It evaluates the same expressions as passes D and A, so the two states agree
+// to rounding (the compiler may fuse multiply-adds differently in the two).
+template <bool WALLS>
+__global__ __launch_bounds__(kMomThreads) void d3q19_pass_m(const double *__restrict__ Tin,
+                                                            double *__restrict__ Tout,
+                                                            const double *__restrict__ Min,
+                                                            const double *__restrict__ U,
+                                                            const double *__restrict__ K1,
+                                                            double *__restrict__ Mout, Phys c, Grid3 G,
+                                                            double *__restrict__ partials,
+                                                            StepState *__restrict__ st, int64_t step)
+{
+    using Sh = TileM;
+    __shared__ double s_rho[Sh::Region], s_ux[Sh::Region], s_uy[Sh::Region], s_uz[Sh::Region];
+    __shared__ double s_Fx[Sh::Region], s_Fy[Sh::Region], s_Fz[Sh::Region], s_X[Sh::Region];
+    __shared__ double s_Tt[Sh::Region];  // T~ = T^n + k1
+    __shared__ double s_red[4 * kMomThreads / 64];
+    __shared__ unsigned s_ured[kMomThreads / 64];
+    const unsigned N = G.N;
+    Partial part = {0.0, 0.0, 0.0, 1e300, 0u};
+    const int ntiles = Sh::count(G.nx, G.ny, G.nz);
+    const TileIter it = tile_iter(ntiles);
+    for (int t = it.first; t < it.end; t += it.step) {
+        const Tile3 o = tile_origin<Sh>(G, t);
+        __syncthreads();
+        for (int r = threadIdx.x; r < Sh::Region; r += kMomThreads) {
+            const unsigned m = region_index<WALLS, Sh>(G, o, r);
+            s_rho[r] = Min[m];
+            s_ux[r] = U[m];
+            s_uy[r] = U[N + m];
+            s_uz[r] = U[2 * (size_t)N + m];
+            s_Fx[r] = U[3 * (size_t)N + m];
+            s_Fy[r] = U[4 * (size_t)N + m];
+            s_Fz[r] = U[5 * (size_t)N + m];
+            s_X[r] = U[6 * (size_t)N + m];
+            s_Tt[r] = Tin[m] + K1[m];
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < Sh::Nodes; k += kMomThreads) {
+            const int tx = k % Sh::TX, ty = (k / Sh::TX) % Sh::TY, tz = k / (Sh::TX * Sh::TY);
+            const int x = o.x0 + tx, y = o.y0 + ty, z = o.z0 + tz;
+            if (x >= G.nx || y >= G.ny || z >= G.nz) continue;
+            const unsigned n = ((unsigned)z * (unsigned)G.ny + (unsigned)y) * (unsigned)G.nx + (unsigned)x;
+            const bool wall = WALLS && (z == 0 || z == G.nz - 1);
+            const int c0 = rnb<Sh>(tx, ty, tz, 0, 0, 0);
+            const double rho = s_rho[c0], ux = s_ux[c0], uy = s_uy[c0], uz = s_uz[c0], T0 = Tin[n];
+            double Tn = T0;
+            if (!wall) {
+                const double k1 = K1[n];
+                double gx, gy, gz, lap;
+                grad_lap<Sh>(s_Tt, tx, ty, tz, T0 + k1, gx, gy, gz, lap);
+                const double divu = K1[N + n];
+                const double Z = c.eos == 0 ? cs_Z(c.b_quarter * rho) : 0.0;
+                const double k2 = -(ux * gx + uy * gy + uz * gz) + c.kappa_over_cv * rcp_pos(rho) * lap -
+                                  (T0 + k1) * c.R_over_cv * Z * divu;
+                Tn = T0 + 0.5 * (k1 + k2);
+            }
+            Tout[n] = Tn;
+            const double uu = ux * ux + uy * uy + uz * uz;
+            double f[19];
+            {
+                const double Fx = s_Fx[c0], Fy = s_Fy[c0], Fz = s_Fz[c0];
+                const double uF = ux * Fx + uy * Fy + uz * Fz;
+                double rest = 0.0;
+#pragma unroll
+                for (int i = 1; i < 19; ++i) rest += post_tau1(i, rho, ux, uy, uz, Fx, Fy, Fz, s_X[c0], uu, uF);
+                f[0] = rho - rest;
+            }
+#pragma unroll
+            for (int i = 1; i < 19; ++i) {
+                const V3 v = vel(i);
+                const int q = rnb<Sh>(tx, ty, tz, -v.x, -v.y, -v.z);
+                const double qx = s_ux[q], qy = s_uy[q], qz = s_uz[q];
+                const double Fx = s_Fx[q], Fy = s_Fy[q], Fz = s_Fz[q];
+                f[i] = post_tau1(i, s_rho[q], qx, qy, qz, Fx, Fy, Fz, s_X[q], qx * qx + qy * qy + qz * qz,
+                                 qx * Fx + qy * Fy + qz * Fz);
+            }
+            double rn, jx, jy, jz;
+            pulled_moments3<WALLS>(f, z, G.nz, rn, jx, jy, jz);
+            double Z;
+            const double psin = psi_and_Z(c, rn, Tn, Z);
+            Mout[n] = rn;
+            Mout[N + n] = jx;
+            Mout[2 * (size_t)N + n] = jy;
+            Mout[3 * (size_t)N + n] = jz;
+            Mout[4 * (size_t)N + n] = psin;
+            const double psi0 = Min[4 * (size_t)N + n];
+            part.mass_n += rho;
+            part.mass_next += rn;
+            part.umax = fmax(part.umax, uu);
+            part.rmin = fmin(part.rmin, rho);
+            unsigned fl = 0u;
+            if (!(rho > 0.0)) fl |= kFlagRho;
+            if (c.eos == 0 && c.b_quarter * rho >= 1.0) fl |= kFlagEta;
+            if (psi0 != psi0) fl |= kFlagPsi;
+            if (rho != rho || uu != uu || Tn != Tn || rn != rn) fl |= kFlagNaN;
+            part.flags |= fl;
+        }
+    }
+    part = block_reduce<kMomThreads>(part, s_red, s_ured);
+    finish_launch<kMomThreads>(part, partials, st, step, (int)((step + 1) & 1), 1.0 / (double)N, s_red, s_ured);
+}
+
+// psi of level 0 for the moment state (rho and j come from the host)
+__global__ void d3q19_psi_init(double *__restrict__ M, const double *__restrict__ Tin, Phys c, unsigned N)
+{
+    for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (size_t)gridDim.x * blockDim.x) {
+        double Z;
+        M[4 * (size_t)N + n] = psi_and_Z(c, M[n], Tin[n], Z);
+    }
 }
 
 // ---- readout: from M and U of the current level -------------------------------
@@ -626,22 +807,57 @@ hipError_t step_t(const LatticeLaunch &L, double *M, double *U, double *K1)
     return hipGetLastError();
 }
 
+// Moment state: M^n is the state buffer fin, M^{n+1} goes to fout.
+template <bool WALLS>
+hipError_t step_mom_t(const LatticeLaunch &L, double *U, double *K1)
+{
+    const Grid3 G{L.nx, L.ny, L.nz, (unsigned)((size_t)L.nx * L.ny * L.nz)};
+    const double *Min = (const double *)L.fin;
+    const int gT = grid_tiles<TileBD>(L.nx, L.ny, L.nz, L.resident);
+    const int gC = grid_tiles<TileC>(L.nx, L.ny, L.nz, L.resident);
+    const int gM = grid_tiles<TileM>(L.nx, L.ny, L.nz, L.resident);
+    hipLaunchKernelGGL((d3q19_pass_b<WALLS>), dim3(gT), dim3(kStencilThreads), 0, L.stream, Min, U, L.phys, G, L.st,
+                       (int)(L.step & 1));
+    hipLaunchKernelGGL((d3q19_pass_c<WALLS>), dim3(gC), dim3(kStencilThreads), 0, L.stream, L.Tin, Min, U, K1,
+                       L.phys, G);
+    hipLaunchKernelGGL((d3q19_pass_m<WALLS>), dim3(gM), dim3(kMomThreads), 0, L.stream, L.Tin, L.Tout, Min, U, K1,
+                       (double *)L.fout, L.phys, G, L.partials, L.st, L.step);
+    return hipGetLastError();
+}
+
 }  // namespace
 
-// the grid of pass D, which writes the per-block partials
-int d3q19_num_blocks(int nx, int ny, int nz, int cus) { return grid_tiles<TileBD>(nx, ny, nz, cus); }
+// the larger of the grids that write per-block partials (pass D, or the
+// moment-state pass)
+int d3q19_num_blocks(int nx, int ny, int nz, int cus)
+{
+    const int d = grid_tiles<TileBD>(nx, ny, nz, cus), m = grid_tiles<TileM>(nx, ny, nz, cus);
+    return d > m ? d : m;
+}
 
 hipError_t d3q19_launch_step(const LatticeLaunch &L, double *M, double *U, double *K1)
 {
+    if (L.moments) return L.walls ? step_mom_t<true>(L, U, K1) : step_mom_t<false>(L, U, K1);
     if (L.fp32) return L.walls ? step_t<float, true>(L, M, U, K1) : step_t<float, false>(L, M, U, K1);
     return L.walls ? step_t<double, true>(L, M, U, K1) : step_t<double, false>(L, M, U, K1);
+}
+
+hipError_t d3q19_launch_psi_init(const LatticeLaunch &L, double *M)
+{
+    const unsigned N = (unsigned)((size_t)L.nx * L.ny * L.nz);
+    const int threads = 256;
+    const int blocks = (int)((N + threads - 1) / threads < 65535 ? (N + threads - 1) / threads : 65535);
+    hipLaunchKernelGGL(d3q19_psi_init, dim3(blocks), dim3(threads), 0, L.stream, M, L.Tin, L.phys, N);
+    return hipGetLastError();
 }
 
 hipError_t d3q19_launch_readout(const LatticeLaunch &L, int field, double *M, double *U, double *out)
 {
     const Grid3 G{L.nx, L.ny, L.nz, (unsigned)((size_t)L.nx * L.ny * L.nz)};
     const int g = grid_rows(L.ny, L.nz, L.resident);
-    if (L.fp32) {
+    if (L.moments) {
+        M = (double *)L.fin;  // the state is M itself
+    } else if (L.fp32) {
         if (L.walls)
             hipLaunchKernelGGL((d3q19_pass_a<float, true>), dim3(g), dim3(256), 0, L.stream, (const float *)L.fin, L.Tin, M, L.phys, G);
         else

@@ -16,7 +16,7 @@ struct LatticeLaunch {
     Phys phys;
     int nx, ny, nz;
     bool fp32, tau1, walls;
-    bool moments;         // D2Q9 state is (rho, j_x, j_y) planes instead of populations
+    bool moments;         // the state is moments (D2Q9: rho, j_x, j_y; D3Q19: rho, j, psi), not populations
     int resident;         // blocks of the persistent grid (two per compute unit)
     double *partials;     // 5 doubles per block
     StepState *st;
@@ -33,6 +33,8 @@ int d2q9_num_blocks(int nx, int ny, int resident, bool moments = false);
 int d3q19_num_blocks(int nx, int ny, int nz, int cus);
 hipError_t d3q19_launch_step(const LatticeLaunch &L, double *M, double *U, double *K1);
 hipError_t d3q19_launch_readout(const LatticeLaunch &L, int field, double *M, double *U, double *out);
+// psi plane of a level-0 moment state M (rho and j set) from rho and L.Tin
+hipError_t d3q19_launch_psi_init(const LatticeLaunch &L, double *M);
 hipError_t d2q9_launch_step(const LatticeLaunch &L);
 hipError_t d2q9_launch_readout(const LatticeLaunch &L, int field, double *scratch, double *out);
 

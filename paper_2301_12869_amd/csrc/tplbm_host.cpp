@@ -32,8 +32,8 @@ struct tplbm_ctx {
     int resident = 0;
     size_t N = 0;
     int Q = 9;
-    bool mom = false;  // D2Q9 state carried as (rho, j_x, j_y) planes
-    int planes = 9;    // state planes per node between steps (Q, or 3 with mom)
+    bool mom = false;  // state carried as moments: D2Q9 (rho, j_x, j_y), D3Q19 (rho, j, psi)
+    int planes = 9;    // state planes per node between steps (Q, or 3 / 5 with mom)
     Phys phys;
     bool have_state = false;
     std::string err;
@@ -74,11 +74,12 @@ bool tau_one(const tplbm_params &p)
 }
 
 // The moment state applies where the post-collision set is a closed function
-// of (rho, u, F): D2Q9, every rate 1; FP64 so that it carries exactly what
-// the population state would.
+// of (rho, u, F): every rate 1 (D2Q9 with all rates 1, D3Q19 always); FP64 so
+// that it carries exactly what the population state would.
 bool uses_moments(const tplbm_params &p)
 {
-    return p.lattice == TPLBM_D2Q9 && p.precision == TPLBM_FP64 && tau_one(p) && p.state == TPLBM_STATE_AUTO;
+    return (p.lattice == TPLBM_D2Q9 || p.lattice == TPLBM_D3Q19) && p.precision == TPLBM_FP64 && tau_one(p) &&
+           p.state == TPLBM_STATE_AUTO;
 }
 
 int validate(const tplbm_params *p)
@@ -165,8 +166,11 @@ Layout layout_of(const tplbm_params &p)
     L.f_bytes = align256(q_of(p) * N * elem);
     L.T_bytes = align256(N * 8);
     if (p.lattice == TPLBM_D3Q19) {
-        // pass buffers: M (rho, j, psi), U (u, F, sigma |F_int|^2 / psi^2), K1 (k1, div u)
-        L.pass_bytes = align256(5 * N * 8) + align256(7 * N * 8) + align256(2 * N * 8);
+        // pass buffers: M (rho, j, psi), U (u, F, sigma |F_int|^2 / psi^2), K1 (k1, div u);
+        // the moment state is M itself (5 planes) and needs no separate M
+        const bool mom = uses_moments(p);
+        if (mom) L.f_bytes = align256(5 * N * 8);
+        L.pass_bytes = (mom ? 0 : align256(5 * N * 8)) + align256(7 * N * 8) + align256(2 * N * 8);
         L.nblocks = d3q19_num_blocks(p.nx, p.ny, p.nz, 1 << 20);
     } else {
         // the moment state holds 3 planes; the readout scratch reuses the
@@ -253,7 +257,7 @@ int tplbm_create(const tplbm_params *p, void *dev_workspace, size_t bytes, void 
     c->N = nodes_of(*p);
     c->Q = q_of(*p);
     c->mom = uses_moments(*p);
-    c->planes = c->mom ? 3 : c->Q;
+    c->planes = c->mom ? (p->lattice == TPLBM_D3Q19 ? 5 : 3) : c->Q;
     c->nblocks = L.nblocks;
     char *q = c->ws;
     c->f[0] = q; q += L.f_bytes;
@@ -263,7 +267,7 @@ int tplbm_create(const tplbm_params *p, void *dev_workspace, size_t bytes, void 
     c->partials = (double *)q; q += L.part_bytes;
     c->st = (StepState *)q; q += L.st_bytes;
     if (p->lattice == TPLBM_D3Q19) {
-        c->M = (double *)q; q += align256(5 * c->N * 8);
+        if (!c->mom) { c->M = (double *)q; q += align256(5 * c->N * 8); }
         c->U = (double *)q; q += align256(7 * c->N * 8);
         c->K1 = (double *)q;
     }
@@ -307,7 +311,27 @@ int tplbm_set_state(tplbm_ctx *c, const double *rho0, const double *T0)
     // The wall-normal axis is y in 2-D and z in 3-D.
     std::vector<double> fd;
     std::vector<float> ff;
-    if (c->mom) {
+    if (c->mom && d3) {
+        // As below for D3Q19: rho and j of the pulled rest set, summed in the
+        // kernels' order (velocity components of zero add nothing); the psi
+        // plane is filled on the device once T^0 is there.
+        fd.assign(5 * N, 0.0);
+        for (size_t n = 0; n < N; ++n) {
+#pragma clang fp contract(off)
+            double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+            for (int i = 0; i < 19; ++i) {
+                const double f = w[i] * rho0[n];
+                r += f;
+                if (cx[i]) jx += cx[i] * f;
+                if (cy[i]) jy += cy[i] * f;
+                if (cz[i]) jz += cz[i] * f;
+            }
+            fd[n] = r;
+            fd[N + n] = jx;
+            fd[2 * N + n] = jy;
+            fd[3 * N + n] = jz;
+        }
+    } else if (c->mom) {
         // The pulled level-0 set is f_i = w_i rho0(x) at every node (the
         // wall reconstruction returns the same values): store its density
         // and momentum, summed as the kernels sum a pulled set.
@@ -362,6 +386,10 @@ int tplbm_set_state(tplbm_ctx *c, const double *rho0, const double *T0)
     else
         HIP_OK(c, hipMemcpyAsync(c->f[0], fd.data(), fd.size() * 8, hipMemcpyHostToDevice, c->stream));
     HIP_OK(c, hipMemcpyAsync(c->T[0], T0, N * 8, hipMemcpyHostToDevice, c->stream));
+    if (c->mom && d3) {
+        LatticeLaunch L = launch_of(c);
+        HIP_OK(c, d3q19_launch_psi_init(L, (double *)c->f[0]));
+    }
     StepState s;
     std::memset(&s, 0, sizeof s);
     s.mean[0] = tot / (double)N;

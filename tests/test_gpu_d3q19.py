@@ -46,14 +46,16 @@ def _oracle(orc, shape, walls, form, g, rho0, T0, steps):
     return orc.macro(P, f, TT)
 
 
-def _gpu(T, shape, walls, form, g, rho0, T0, steps, precision=0):
+def _gpu(T, shape, walls, form, g, rho0, T0, steps, precision=0, state=None):
     nx, ny, nz = shape
     p = T.make_params(T.D3Q19, nx=nx, ny=ny, nz=nz, walls=walls, gravity_form=form, g=g,
-                      precision=precision, rho_ref=float(rho0.mean()), rho_v=RHO_V3)
+                      precision=precision, rho_ref=float(rho0.mean()), rho_v=RHO_V3,
+                      state=T.STATE_AUTO if state is None else state)
     lat = T.Lattice(p)
     lat.set_state(rho0, T0)
     lat.step(steps)
     out = {k: lat.read(k) for k in ("rho", "ux", "uy", "uz", "T", "p_nn")}
+    out["diag"] = lat.diagnostics()
     lat.close()
     return out
 
@@ -81,6 +83,45 @@ def test_small_lattices_fp64(T, orc, crit, shape, walls, form):
     for k in ("ux", "uy", "uz"):
         assert np.abs(got[k] - want[k]).max() < 1e-13, k
     assert np.abs(got["p_nn"] - want["p_nn"]).max() / (0.5 * want["rho"].max() ** 2) < 1e-12
+
+
+@pytest.mark.parametrize("shape,walls,form", [((70, 9, 11), True, 2), ((33, 10, 7), False, 1),
+                                              ((40, 12, 9), True, 3)])
+def test_moment_state_matches_population_state(T, orc, crit, shape, walls, form):
+    """FP64 D3Q19 carries (rho, j, psi) and T between steps by default; the
+    nineteen-population state computes the same expressions, so the two agree
+    to rounding (differently fused multiply-adds), on lattices spanning
+    several tiles of both kernels with ragged edges."""
+    _log(f"case d3q19 moment vs population {shape} walls={walls} form={form}")
+    rho0, T0 = _state(orc, crit, shape, 8, shape[2] // 3)
+    pop = _gpu(T, shape, walls, form, 2e-4, rho0, T0, 300, state=T.STATE_POPULATIONS)
+    mom = _gpu(T, shape, walls, form, 2e-4, rho0, T0, 300)
+    for k in ("rho", "T"):
+        assert _rel(mom[k], pop[k]) < 1e-13, (k, _rel(mom[k], pop[k]))
+    for k in ("ux", "uy", "uz"):
+        assert np.abs(mom[k] - pop[k]).max() < 1e-14, k
+    assert mom["diag"]["mass"] == pytest.approx(pop["diag"]["mass"], rel=1e-13)
+    assert mom["diag"]["flags"] == pop["diag"]["flags"] == 0
+
+
+def test_moment_state_checkpoint_is_bitwise(T, orc, crit):
+    shape = (34, 9, 10)
+    rho0, T0 = _state(orc, crit, shape, 9, 3)
+    p = T.make_params(T.D3Q19, nx=34, ny=9, nz=10, walls=True, gravity_form=2, g=2e-4)
+    a = T.Lattice(p)
+    a.set_state(rho0, T0)
+    a.step(40)
+    blob = a.save_state()
+    a.step(25)
+    want = {k: a.read(k) for k in ("rho", "uz", "T")}
+    a.close()
+    b = T.Lattice(p)
+    b.load_state(blob)
+    b.step(25)
+    got = {k: b.read(k) for k in ("rho", "uz", "T")}
+    b.close()
+    for k in want:
+        assert np.array_equal(got[k], want[k]), k
 
 
 def test_small_lattice_fp32_deviation(T, orc, crit):
