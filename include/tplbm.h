@@ -66,10 +66,12 @@ extern "C" {
 /* state between steps (tplbm_params.state).  With every relaxation time 1
  * the post-collision populations are a closed function of the node's density,
  * force-corrected velocity and force (Eq. LiFS with Eq. OperatorMRT at
- * Lambda = I), so a D2Q9 FP64 lattice can carry rho and j instead of the nine
- * populations: AUTO does that where it applies (the same arithmetic as the
- * population state, equal to rounding) and stores populations everywhere
- * else; POPULATIONS always stores populations. */
+ * Lambda = I), so an FP64 lattice can carry its moments instead of the
+ * populations: rho and j (D2Q9, 3 planes instead of 9) or rho, j and psi
+ * (D3Q19, 5 planes instead of 19), plus T.  AUTO does that where it applies
+ * (FP64, every tau = 1; the same arithmetic as the population state, equal to
+ * rounding) and stores populations everywhere else; POPULATIONS always stores
+ * populations. */
 #define TPLBM_STATE_AUTO 0
 #define TPLBM_STATE_POPULATIONS 1
 
@@ -168,8 +170,8 @@ int tplbm_read_device(tplbm_ctx *ctx, int field, double *dev_out);
 /* Diagnostics of the last completed step.  Synchronous. */
 int tplbm_diagnostics(tplbm_ctx *ctx, tplbm_diag *out);
 
-/* Exact checkpoint of the state (populations, temperature, <rho>, step
- * count) to a host blob of tplbm_state_bytes() bytes and back.
+/* Exact checkpoint of the state (populations or moments, temperature,
+ * <rho>, step count) to a host blob of tplbm_state_bytes() bytes and back.
  * Synchronous.  Restoring and stepping reproduces an uninterrupted run bit
  * for bit. */
 int tplbm_state_bytes(const tplbm_ctx *ctx, size_t *bytes);
