@@ -19,6 +19,12 @@
 //      sums of the next level's mass; the last block finishes <rho>.
 // Every stencil is evaluated once per node and step; the passes hand the
 // results on instead of recomputing them.
+//
+// FP64 lattices carry M and T between steps instead of the populations (the
+// moment state): a step is then B, C and M, where M fuses D with the next
+// step's A -- the second Heun stage, the post-collision populations of each
+// node's neighbours evaluated from their (rho, u, F, X), the pull, Zou-He and
+// psi -> M^{n+1}.
 #include <hip/hip_runtime.h>
 
 #include "lbm_common.hpp"
