@@ -56,39 +56,50 @@ class Diag(ctypes.Structure):
 _lib = None
 
 
+def _bind(L):
+    """Declare the argument and result types of the exported functions."""
+    dp = ctypes.POINTER(ctypes.c_double)
+    pp = ctypes.POINTER(Params)
+    for name, args in {
+        "orc_eos_p": [pp, ctypes.c_double, ctypes.c_double],
+        "orc_eos_dpdT": [pp, ctypes.c_double, ctypes.c_double],
+        "orc_eos_dpdrho": [pp, ctypes.c_double, ctypes.c_double],
+        "orc_eos_d2pdrho2": [pp, ctypes.c_double, ctypes.c_double],
+    }.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_double
+    L.orc_critical.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
+    L.orc_spinodal.argtypes = [pp, ctypes.c_double, dp]
+    L.orc_coexistence.argtypes = [pp, ctypes.c_double, dp]
+    L.orc_init_rest.argtypes = [pp, dp, dp]
+    L.orc_step.argtypes = [pp, dp, dp, ctypes.c_int64, ctypes.POINTER(Diag)]
+    L.orc_run_to_steady.argtypes = [pp, dp, dp, ctypes.c_double, ctypes.c_int64,
+                                    ctypes.c_int64, dp]
+    L.orc_macro.argtypes = [pp, dp, dp, dp, dp, dp, dp, dp, dp]
+    L.orc_collide.argtypes = [pp, dp, dp, dp]
+    L.orc_d2q9_minv.argtypes = [dp]
+    L.orc_d3q19_velocities.argtypes = [ctypes.POINTER(ctypes.c_int), dp]
+    for fn in ("orc_critical", "orc_spinodal", "orc_coexistence", "orc_init_rest",
+               "orc_step", "orc_run_to_steady", "orc_macro", "orc_collide"):
+        getattr(L, fn).restype = ctypes.c_int
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB):
             build()
-        L = ctypes.CDLL(_LIB)
-        dp = ctypes.POINTER(ctypes.c_double)
-        pp = ctypes.POINTER(Params)
-        for name, args in {
-            "orc_eos_p": [pp, ctypes.c_double, ctypes.c_double],
-            "orc_eos_dpdT": [pp, ctypes.c_double, ctypes.c_double],
-            "orc_eos_dpdrho": [pp, ctypes.c_double, ctypes.c_double],
-            "orc_eos_d2pdrho2": [pp, ctypes.c_double, ctypes.c_double],
-        }.items():
-            fn = getattr(L, name)
-            fn.argtypes = args
-            fn.restype = ctypes.c_double
-        L.orc_critical.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
-        L.orc_spinodal.argtypes = [pp, ctypes.c_double, dp]
-        L.orc_coexistence.argtypes = [pp, ctypes.c_double, dp]
-        L.orc_init_rest.argtypes = [pp, dp, dp]
-        L.orc_step.argtypes = [pp, dp, dp, ctypes.c_int64, ctypes.POINTER(Diag)]
-        L.orc_run_to_steady.argtypes = [pp, dp, dp, ctypes.c_double, ctypes.c_int64,
-                                        ctypes.c_int64, dp]
-        L.orc_macro.argtypes = [pp, dp, dp, dp, dp, dp, dp, dp, dp]
-        L.orc_collide.argtypes = [pp, dp, dp, dp]
-        L.orc_d2q9_minv.argtypes = [dp]
-        L.orc_d3q19_velocities.argtypes = [ctypes.POINTER(ctypes.c_int), dp]
-        for fn in ("orc_critical", "orc_spinodal", "orc_coexistence", "orc_init_rest",
-                   "orc_step", "orc_run_to_steady", "orc_macro", "orc_collide"):
-            getattr(L, fn).restype = ctypes.c_int
-        _lib = L
+        _lib = _bind(ctypes.CDLL(_LIB))
     return _lib
+
+
+def load_build(path: str):
+    """Load another build of the oracle source (the tests plant mistakes in a
+    copy of it to check that the pins catch them).  Returns the bound library;
+    assign it to ``oracle._lib`` to route every call here through it."""
+    return _bind(ctypes.CDLL(os.path.abspath(path)))
 
 
 # ---------------------------------------------------------------------------
