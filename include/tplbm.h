@@ -172,11 +172,15 @@ int tplbm_diagnostics(tplbm_ctx *ctx, tplbm_diag *out);
 
 /* Exact checkpoint of the state (populations or moments, temperature,
  * <rho>, step count) to a host blob of tplbm_state_bytes() bytes and back.
- * Synchronous.  Restoring and stepping reproduces an uninterrupted run bit
- * for bit. */
+ * The blob starts with a 64-byte header naming the lattice, its sizes, the
+ * stored precision, the walls and the number of state planes.  load_state
+ * takes the blob's length in `bytes` and rejects (ESHAPE, nothing read past
+ * the header) a blob whose length or header does not match this lattice;
+ * EINVAL for a blob this library did not write.  Synchronous.  Restoring and
+ * stepping reproduces an uninterrupted run bit for bit. */
 int tplbm_state_bytes(const tplbm_ctx *ctx, size_t *bytes);
 int tplbm_save_state(tplbm_ctx *ctx, void *host_blob);
-int tplbm_load_state(tplbm_ctx *ctx, const void *host_blob);
+int tplbm_load_state(tplbm_ctx *ctx, const void *host_blob, size_t bytes);
 
 /* Release the host handle (the workspace stays the caller's). NULL is a no-op. */
 void tplbm_destroy(tplbm_ctx *ctx);
@@ -377,6 +381,7 @@ int tplbm_batch_set_tuning(tplbm_batch *b, int32_t shape, int32_t check_every);
 
 void tplbm_batch_destroy(tplbm_batch *b);
 const char *tplbm_batch_last_error(const tplbm_batch *b);
+
 
 /* ------------------------------------------------------------------------
  * Learned warm start for the column sweep.

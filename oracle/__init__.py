@@ -30,7 +30,7 @@ def build(force: bool = True) -> str:
         tmp = _LIB + ".tmp"
         subprocess.check_call(
             ["gcc", "-O2", "-std=c99", "-Wall", "-fPIC", "-shared", "-ffp-contract=off",
-             "-fno-fast-math", "-o", tmp, _SRC, "-lm"])
+             "-fno-fast-math", "-fopenmp", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -80,6 +80,8 @@ def _bind(L):
     L.orc_collide.argtypes = [pp, dp, dp, dp]
     L.orc_d2q9_minv.argtypes = [dp]
     L.orc_d3q19_velocities.argtypes = [ctypes.POINTER(ctypes.c_int), dp]
+    L.orc_set_threads.argtypes = [ctypes.c_int]
+    L.orc_set_threads.restype = ctypes.c_int
     for fn in ("orc_critical", "orc_spinodal", "orc_coexistence", "orc_init_rest",
                "orc_step", "orc_run_to_steady", "orc_macro", "orc_collide"):
         getattr(L, fn).restype = ctypes.c_int
@@ -100,6 +102,13 @@ def load_build(path: str):
     copy of it to check that the pins catch them).  Returns the bound library;
     assign it to ``oracle._lib`` to route every call here through it."""
     return _bind(ctypes.CDLL(os.path.abspath(path)))
+
+
+def set_threads(n: int) -> int:
+    """Run the D2Q9 and D3Q19 node loops on n threads (1: the plain serial
+    definition, the default).  Results are bit for bit the same for any n.
+    Returns the previous setting."""
+    return int(lib().orc_set_threads(int(n)))
 
 
 # ---------------------------------------------------------------------------

@@ -33,11 +33,27 @@
  *   - The steady test uses max |u^n| over all nodes.
  * Parity unpinned: the transient between the pinned limits (nucleation
  * times, metastable life times) is checked only against the GPU path.
+ *
+ * Threads: orc_set_threads(n) lets the D2Q9 and D3Q19 node loops run on n
+ * OpenMP threads (default 1, the plain definition).  Every node's arithmetic
+ * is the same on any thread, each output is written by one iteration, the
+ * flags are OR-ed (order-free), and the sums (mass, <rho>) stay serial in
+ * index order, so the results are bit for bit those of one thread.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+static int orc_threads = 1;
+
+/* number of threads for the node loops (>= 1); returns the previous value */
+int orc_set_threads(int n)
+{
+    int prev = orc_threads;
+    orc_threads = n < 1 ? 1 : n;
+    return prev;
+}
 
 typedef struct {
     int32_t lattice;      /* 1: D1Q3 column, 2: D2Q9, 3: D3Q19 */
@@ -371,21 +387,26 @@ static double d2q9_macro(const orc_params *P, const double *f, const double *T, 
                          int *flags)
 {
     int nx = P->nx, ny = P->ny, N = nx * ny;
+    int fl = 0;
     /* density (Eq. Density) */
+#pragma omp parallel for num_threads(orc_threads) reduction(| : fl)
     for (int n = 0; n < N; ++n) {
         double s = 0;
         for (int i = 0; i < 9; ++i) s += f[i * N + n];
         w->rho[n] = s;
-        if (!(s == s)) *flags |= ORC_FLAG_NAN;
-        if (s <= 0) *flags |= ORC_FLAG_RHO;
+        if (!(s == s)) fl |= ORC_FLAG_NAN;
+        if (s <= 0) fl |= ORC_FLAG_RHO;
     }
     /* mean density over all nodes, in index order */
     double tot = 0;
     for (int n = 0; n < N; ++n) tot += w->rho[n];
     double mean = tot / N;
     /* pseudopotential */
-    for (int n = 0; n < N; ++n) w->psi[n] = psi_of(P, w->rho[n], T[n], flags);
+#pragma omp parallel for num_threads(orc_threads) reduction(| : fl)
+    for (int n = 0; n < N; ++n) w->psi[n] = psi_of(P, w->rho[n], T[n], &fl);
+    *flags |= fl;
     /* forces: Shan-Chen (Eq. ShanChenForce) plus gravity (Eqs. Gravity_1/2) */
+#pragma omp parallel for num_threads(orc_threads)
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             int n = y * nx + x;
@@ -409,6 +430,7 @@ static double d2q9_macro(const orc_params *P, const double *f, const double *T, 
             w->Fy[n] = w->Fiy[n] + fg;
         }
     /* force-corrected velocity (Eq. Momentum) */
+#pragma omp parallel for num_threads(orc_threads)
     for (int n = 0; n < N; ++n) {
         double jx = 0, jy = 0;
         for (int i = 0; i < 9; ++i) {
@@ -460,6 +482,7 @@ static void d2q9_step_once(const orc_params *P, double *f, double *T, d2_work *w
     dg->mass = mass; dg->mean_rho = mean; dg->max_u = umax; dg->min_rho = rmin;
 
     /* temperature: Heun with rho, u frozen; Dirichlet at the walls */
+#pragma omp parallel for num_threads(orc_threads)
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             int n = y * nx + x;
@@ -468,6 +491,7 @@ static void d2q9_step_once(const orc_params *P, double *f, double *T, d2_work *w
             w->k1[n] = d2q9_energy_rhs(P, T, w, x, y);
             w->Tt[n] = T[n] + w->k1[n];
         }
+#pragma omp parallel for num_threads(orc_threads)
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             int n = y * nx + x;
@@ -484,6 +508,7 @@ static void d2q9_step_once(const orc_params *P, double *f, double *T, d2_work *w
         nrm[k] = 0;
         for (int i = 0; i < 9; ++i) nrm[k] += M2[k][i] * M2[k][i];
     }
+#pragma omp parallel for num_threads(orc_threads)
     for (int n = 0; n < N; ++n) {
         double fl[9], fe[9], m[9], me[9], S[9], ms[9];
         for (int i = 0; i < 9; ++i) fl[i] = f[i * N + n];
@@ -508,7 +533,9 @@ static void d2q9_step_once(const orc_params *P, double *f, double *T, d2_work *w
         }
     }
 
-    /* streaming (Eq. LBE): periodic in x; in y periodic or cut at the walls */
+    /* streaming (Eq. LBE): periodic in x; in y periodic or cut at the walls
+     * (every destination is written by one source) */
+#pragma omp parallel for num_threads(orc_threads)
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x)
             for (int i = 0; i < 9; ++i) {
@@ -974,17 +1001,22 @@ static double d3q19_macro(const orc_params *P, const double *f, const double *T,
 {
     int nx = P->nx, ny = P->ny, nz = P->nz;
     size_t N = (size_t)nx * ny * nz;
+    int fl = 0;
+#pragma omp parallel for num_threads(orc_threads) reduction(| : fl)
     for (size_t n = 0; n < N; ++n) {
         double s = 0;
         for (int i = 0; i < 19; ++i) s += f[i * N + n];
         w->rho[n] = s;
-        if (!(s == s)) *flags |= ORC_FLAG_NAN;
-        if (s <= 0) *flags |= ORC_FLAG_RHO;
+        if (!(s == s)) fl |= ORC_FLAG_NAN;
+        if (s <= 0) fl |= ORC_FLAG_RHO;
     }
     double tot = 0;
     for (size_t n = 0; n < N; ++n) tot += w->rho[n];
     double mean = tot / (double)N;
-    for (size_t n = 0; n < N; ++n) w->psi[n] = psi_of(P, w->rho[n], T[n], flags);
+#pragma omp parallel for num_threads(orc_threads) reduction(| : fl)
+    for (size_t n = 0; n < N; ++n) w->psi[n] = psi_of(P, w->rho[n], T[n], &fl);
+    *flags |= fl;
+#pragma omp parallel for num_threads(orc_threads)
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
@@ -1013,6 +1045,7 @@ static double d3q19_macro(const orc_params *P, const double *f, const double *T,
                 w->Fz[n] = fiz + fg;
                 w->Fi2[n] = fix * fix + fiy * fiy + fiz * fiz;
             }
+#pragma omp parallel for num_threads(orc_threads)
     for (size_t n = 0; n < N; ++n) {
         double jx = 0, jy = 0, jz = 0;
         for (int i = 0; i < 19; ++i) {
@@ -1061,6 +1094,7 @@ static void d3q19_step_once(const orc_params *P, double *f, double *T, d3_work *
         if (w->rho[n] < rmin) rmin = w->rho[n];
     }
     dg->mass = mass; dg->mean_rho = mean; dg->max_u = umax; dg->min_rho = rmin;
+#pragma omp parallel for num_threads(orc_threads)
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
@@ -1070,6 +1104,7 @@ static void d3q19_step_once(const orc_params *P, double *f, double *T, d3_work *
                 w->k1[n] = d3q19_energy_rhs(P, T, w, x, y, z);
                 w->Tt[n] = T[n] + w->k1[n];
             }
+#pragma omp parallel for num_threads(orc_threads)
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
@@ -1080,6 +1115,7 @@ static void d3q19_step_once(const orc_params *P, double *f, double *T, d3_work *
                 w->Tn[n] = T[n] + 0.5 * (w->k1[n] + k2);
             }
     /* collision at tau = 1: f* = f_eq + F' */
+#pragma omp parallel for num_threads(orc_threads)
     for (size_t n = 0; n < N; ++n) {
         double r = w->rho[n], ux = w->ux[n], uy = w->uy[n], uz = w->uz[n];
         double Fx = w->Fx[n], Fy = w->Fy[n], Fz = w->Fz[n];
@@ -1097,7 +1133,9 @@ static void d3q19_step_once(const orc_params *P, double *f, double *T, d3_work *
             w->fs[i * N + n] = feq + guo + sig;
         }
     }
-    /* stream: periodic in x and y; z periodic or cut at the walls */
+    /* stream: periodic in x and y; z periodic or cut at the walls (every
+     * destination is written by one source) */
+#pragma omp parallel for num_threads(orc_threads)
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x)

@@ -70,7 +70,7 @@ SIGNATURES = {
     "tplbm_diagnostics": ([_VP, ctypes.POINTER(Diag)], ctypes.c_int),
     "tplbm_state_bytes": ([_VP, _SZ], ctypes.c_int),
     "tplbm_save_state": ([_VP, _VP], ctypes.c_int),
-    "tplbm_load_state": ([_VP, _VP], ctypes.c_int),
+    "tplbm_load_state": ([_VP, _VP, ctypes.c_size_t], ctypes.c_int),
     "tplbm_destroy": ([_VP], None),
     "tplbm_last_error": ([_VP], ctypes.c_char_p),
     "tplbm_eos_critical": ([ctypes.c_double] * 3 + [_DP], ctypes.c_int),
@@ -300,8 +300,14 @@ class Lattice:
         return out
 
     def read_device(self, field: str, out):
-        """Enqueue a readout into a float64 device tensor of n elements."""
-        assert out.dtype.itemsize == 8 and out.numel() == self.n and out.is_contiguous()
+        """Enqueue a readout into a contiguous float64 tensor of n elements on
+        this lattice's device."""
+        import torch
+
+        if not isinstance(out, torch.Tensor) or out.device != self.device:
+            raise ValueError(f"out must be a tensor on {self.device}")
+        if out.dtype != torch.float64 or out.numel() != self.n or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous float64 tensor of {self.n} elements")
         _check(load_library().tplbm_read_device(self._h, FIELDS[field], out.data_ptr()), self._h)
 
     def diagnostics(self) -> dict:
@@ -319,7 +325,7 @@ class Lattice:
 
     def load_state(self, blob: bytes):
         buf = ctypes.create_string_buffer(blob, len(blob))
-        _check(load_library().tplbm_load_state(self._h, buf), self._h)
+        _check(load_library().tplbm_load_state(self._h, buf, len(blob)), self._h)
 
     def close(self):
         if getattr(self, "_h", None):

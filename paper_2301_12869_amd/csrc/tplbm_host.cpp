@@ -495,9 +495,10 @@ struct BlobHeader {
     char magic[8];
     int64_t step;
     int64_t N;
-    int32_t Q, elem;
+    int32_t Q, elem;  // state planes per node and bytes per value
     int32_t nx, ny;
-    char pad[24];
+    int32_t lattice, nz, precision, walls;
+    char pad[8];
 };
 static_assert(sizeof(BlobHeader) == 64, "blob header");
 }  // namespace
@@ -509,13 +510,17 @@ int tplbm_save_state(tplbm_ctx *c, void *host_blob)
     const size_t elem = c->p.precision == TPLBM_FP32_DEV ? 4 : 8;
     BlobHeader h;
     std::memset(&h, 0, sizeof h);
-    std::memcpy(h.magic, "TPLBMST1", 8);
+    std::memcpy(h.magic, "TPLBMST2", 8);
     h.step = c->step;
     h.N = (int64_t)c->N;
     h.Q = c->planes;
     h.elem = (int32_t)elem;
     h.nx = c->p.nx;
     h.ny = c->p.ny;
+    h.lattice = c->p.lattice;
+    h.nz = c->p.lattice == TPLBM_D3Q19 ? c->p.nz : 1;
+    h.precision = c->p.precision;
+    h.walls = c->p.walls != 0;
     char *b = (char *)host_blob;
     std::memcpy(b, &h, sizeof h);
     const size_t fb = (size_t)c->planes * c->N * elem;
@@ -527,14 +532,21 @@ int tplbm_save_state(tplbm_ctx *c, void *host_blob)
     return TPLBM_OK;
 }
 
-int tplbm_load_state(tplbm_ctx *c, const void *host_blob)
+int tplbm_load_state(tplbm_ctx *c, const void *host_blob, size_t bytes)
 {
     if (!c || !host_blob) return fail(c, TPLBM_EINVAL, "NULL argument");
     const size_t elem = c->p.precision == TPLBM_FP32_DEV ? 4 : 8;
+    size_t want = 0;
+    tplbm_state_bytes(c, &want);
+    if (bytes != want)
+        return fail(c, TPLBM_ESHAPE, "checkpoint has %zu bytes, this lattice's has %zu", bytes, want);
     BlobHeader h;
     std::memcpy(&h, host_blob, sizeof h);
-    if (std::memcmp(h.magic, "TPLBMST1", 8) != 0 || h.N != (int64_t)c->N || h.elem != (int32_t)elem ||
-        h.nx != c->p.nx || h.ny != c->p.ny || h.Q != c->planes)
+    if (std::memcmp(h.magic, "TPLBMST2", 8) != 0)
+        return fail(c, TPLBM_EINVAL, "not a checkpoint of this library (bad magic)");
+    if (h.N != (int64_t)c->N || h.elem != (int32_t)elem || h.nx != c->p.nx || h.ny != c->p.ny ||
+        h.Q != c->planes || h.lattice != c->p.lattice || h.nz != (c->p.lattice == TPLBM_D3Q19 ? c->p.nz : 1) ||
+        h.precision != c->p.precision || h.walls != (c->p.walls != 0))
         return fail(c, TPLBM_ESHAPE, "checkpoint does not match this lattice");
     const char *b = (const char *)host_blob;
     c->cur = 0;

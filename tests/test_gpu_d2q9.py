@@ -205,6 +205,8 @@ def test_ideal_gas_and_strong_gravity(T, orc):
 
 
 def test_checkpoint_restart_is_bitwise(T, orc, crit):
+    import torch
+
     _log("case checkpoint")
     kw, rho0, T0 = _c1_inputs(orc, crit, 2)
     p = T.make_params(T.D2Q9, **kw)
@@ -217,11 +219,24 @@ def test_checkpoint_restart_is_bitwise(T, orc, crit):
     b.step(300)
     blob = b.save_state()
     c = T.Lattice(p)
+    # a truncated blob, a foreign blob and another lattice's blob are refused
+    with pytest.raises(T.TplbmError, match="ESHAPE"):
+        c.load_state(blob[:-8])
+    with pytest.raises(T.TplbmError, match="EINVAL"):
+        c.load_state(b"XXXXXXXX" + blob[8:])
+    other = T.Lattice(T.make_params(T.D2Q9, **dict(kw, walls=False)))
+    with pytest.raises(T.TplbmError, match="ESHAPE"):
+        other.load_state(blob)
+    other.close()
     c.load_state(blob)
     c.step(400)
     for k in ref:
         assert np.array_equal(c.read(k), ref[k]), k
     assert c.diagnostics()["step"] == 700
+    with pytest.raises(ValueError):
+        c.read_device("rho", torch.empty(c.n, dtype=torch.float32, device=c.device))
+    with pytest.raises(ValueError):
+        c.read_device("rho", torch.empty(c.n, dtype=torch.float64))
     for x in (a, b, c):
         x.close()
 

@@ -36,7 +36,7 @@ def _build_variant(tmp, name, edits):
         fh.write(src)
     so = os.path.join(tmp, f"lib{name}.so")
     subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
-                           "-fno-fast-math", "-o", so, path, "-lm"])
+                           "-fno-fast-math", "-fopenmp", "-o", so, path, "-lm"])
     return so
 
 
