@@ -382,6 +382,35 @@ int tplbm_batch_set_tuning(tplbm_batch *b, int32_t shape, int32_t check_every);
 void tplbm_batch_destroy(tplbm_batch *b);
 const char *tplbm_batch_last_error(const tplbm_batch *b);
 
+/* Allocation-free variant of tplbm_batch_create + tplbm_batch_set_state +
+ * tplbm_batch_run, for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * It allocates nothing and takes no workspace: it runs the same column
+ * kernel as tplbm_batch_run.
+ *   cols[ncols]      host column descriptions (read during the call)
+ *   dev_rho0, dev_T0 device arrays: initial densities and temperatures,
+ *                    concatenated as in tplbm_batch_set_state (populations
+ *                    start at rest, f_i = w_i rho0; the end nodes'
+ *                    temperatures are the Dirichlet data)
+ *   dev_rho_out, dev_T_out  device arrays of the same length: the densities
+ *                    and temperatures of each column's end level (they may
+ *                    alias dev_rho0 and dev_T0)
+ *   dev_results      device array of ncols records, as tplbm_batch_run's out
+ *   tol, max_steps   as in tplbm_batch_run; check_every >= 1 is the
+ *                    steady-state check interval
+ * Columns run in index order on the 256 x 8 kernel shape (no autotuning; a
+ * caller that sorts its columns by decreasing height balances the launch).
+ * The column descriptions, their node offsets, the processing order and the
+ * work-queue counter live in a fixed device array of about 480 KiB per GPU
+ * that the library holds until the process ends; ncols is at most 8192
+ * (ESHAPE beyond).  Every call on a GPU shares that array, so calls that
+ * overlap on one GPU (another stream or another host thread) race: the
+ * caller serialises them.  The stream must belong to the current device.
+ * Synchronous.  Errors (tplbm_batch_last_error(NULL)): EINVAL, ESHAPE, EHIP. */
+int tplbm_batch_run_noalloc(const tplbm_batch_params *p, int32_t ncols, const tplbm_column *cols,
+                            const double *dev_rho0, const double *dev_T0, double *dev_rho_out,
+                            double *dev_T_out, tplbm_col_result *dev_results, double tol,
+                            int64_t max_steps, int32_t check_every, void *hip_stream);
 
 /* ------------------------------------------------------------------------
  * Learned warm start for the column sweep.

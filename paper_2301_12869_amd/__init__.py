@@ -117,6 +117,8 @@ SIGNATURES.update({
     "tplbm_batch_resume": ([_VP, _DP, _DP], ctypes.c_int),
     "tplbm_batch_destroy": ([_VP], None),
     "tplbm_batch_last_error": ([_VP], ctypes.c_char_p),
+    "tplbm_batch_run_noalloc": ([_BP, ctypes.c_int32, _CP, _VP, _VP, _VP, _VP, _VP, ctypes.c_double,
+                                 ctypes.c_int64, ctypes.c_int32, _VP], ctypes.c_int),
 })
 COL_STATUS = {0: "converged", 1: "diverged", 2: "max_steps"}
 
@@ -440,6 +442,56 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def batch_params(eos="cs", **over) -> BatchParams:
+    d = dict(PAPER)
+    d.update(over)
+    p = BatchParams()
+    p.a, p.b, p.R, p.G, p.sigma = d["a"], d["b"], d["R"], d["G"], d["sigma"]
+    p.cv, p.kappa = d["cv"], d["kappa"]
+    p.eos = {"cs": 0, "ideal": 1}[eos]
+    return p
+
+
+def batch_run_noalloc(columns, rho0, T0, rho_out, T_out, results, tol: float, max_steps: int,
+                      check_every: int, params: BatchParams = None, stream=None):
+    """tplbm_batch_run_noalloc on caller tensors: rho0, T0, rho_out, T_out
+    are contiguous float64 device tensors of sum(heights) values; results a
+    contiguous device tensor of 32 * ncols bytes (one tplbm_col_result per
+    column, readable with ``col_results``).  columns as for Batch."""
+    import torch
+
+    n = len(columns)
+    cols = (Column * n)()
+    for k, col in enumerate(columns):
+        h, form, g = col[:3]
+        cols[k].height, cols[k].gravity_form, cols[k].g = int(h), int(form), float(g)
+        cols[k].rho_v = float(col[3]) if len(col) > 3 else 0.0
+    total = int(sum(int(c[0]) for c in columns))
+    dev = rho0.device
+    for t in (rho0, T0, rho_out, T_out):
+        if t.device != dev or t.dtype != torch.float64 or t.numel() != total or not t.is_contiguous():
+            raise ValueError(f"density and temperature tensors must be contiguous float64 on {dev} "
+                             f"with {total} values")
+    if results.device != dev or results.numel() * results.element_size() != 32 * n \
+            or not results.is_contiguous():
+        raise ValueError(f"results must be a contiguous tensor of {32 * n} bytes on {dev}")
+    p = params or batch_params()
+    s = stream or torch.cuda.current_stream(dev)
+    _bcheck(load_library().tplbm_batch_run_noalloc(
+        ctypes.byref(p), n, cols, rho0.data_ptr(), T0.data_ptr(), rho_out.data_ptr(),
+        T_out.data_ptr(), results.data_ptr(), float(tol), int(max_steps), int(check_every),
+        s.cuda_stream))
+
+
+def col_results(results) -> dict:
+    """Decode a device or host buffer of tplbm_col_result records."""
+    raw = results.cpu().numpy().view(np.uint8).tobytes() if hasattr(results, "cpu") else bytes(results)
+    rec = np.frombuffer(raw, dtype=np.dtype([("steps", "<i8"), ("status", "<i4"), ("pad", "<i4"),
+                                             ("mass", "<f8"), ("max_u", "<f8")]))
+    return dict(steps=rec["steps"].copy(), status=rec["status"].copy(), mass=rec["mass"].copy(),
+                max_u=rec["max_u"].copy())
 
 
 # ---- learned warm start ------------------------------------------------------

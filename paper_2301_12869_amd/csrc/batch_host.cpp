@@ -67,7 +67,10 @@ constexpr int kMaxHeight = 2048;
 
 size_t al(size_t v) { return (v + 255) & ~(size_t)255; }
 
-int validate(const tplbm_batch_params *p, int32_t ncols, const tplbm_column *cols, int64_t *total)
+}  // namespace
+
+int tplbm::batch_validate(const tplbm_batch_params *p, int32_t ncols, const tplbm_column *cols,
+                          int64_t *total)
 {
     if (!p || !cols || ncols <= 0) return bfail(nullptr, TPLBM_EINVAL, "need params, ncols > 0 and columns");
     if (p->eos != TPLBM_EOS_CARNAHAN_STARLING && p->eos != TPLBM_EOS_IDEAL_LATTICE)
@@ -89,23 +92,18 @@ int validate(const tplbm_batch_params *p, int32_t ncols, const tplbm_column *col
     return TPLBM_OK;
 }
 
-struct BLayout {
-    size_t cols, order, field, results, queue, total;
-};
-
-BLayout blayout(int ncols, int64_t total)
+int tplbm::batch_fail(int code, const char *fmt, ...)
 {
-    BLayout L;
-    L.cols = al(sizeof(ColumnDesc) * ncols);
-    L.order = al(sizeof(int) * ncols);
-    L.field = al(sizeof(double) * (size_t)total);
-    L.results = al(sizeof(ColumnResult) * ncols);
-    L.queue = 256;
-    L.total = L.cols + 2 * L.order + 7 * L.field + L.results + L.queue;
-    return L;
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_berr = buf;
+    return code;
 }
 
-Phys make_bphys(const tplbm_batch_params &p)
+Phys tplbm::batch_phys(const tplbm_batch_params &p)
 {
     Phys c;
     std::memset(&c, 0, sizeof c);
@@ -122,6 +120,35 @@ Phys make_bphys(const tplbm_batch_params &p)
     c.eos = p.eos;
     c.form = 1;
     return c;
+}
+
+int tplbm::batch_grid(int shape, int ncols)
+{
+    int per = 1, dev = 0, cus = 256;
+    if (d1q3_batch_occupancy(shape, &per) != hipSuccess || per < 1) per = 1;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
+    }
+    return (int)std::min<long>((long)cus * per, ncols);
+}
+
+namespace {
+
+struct BLayout {
+    size_t cols, order, field, results, queue, total;
+};
+
+BLayout blayout(int ncols, int64_t total)
+{
+    BLayout L;
+    L.cols = al(sizeof(ColumnDesc) * ncols);
+    L.order = al(sizeof(int) * ncols);
+    L.field = al(sizeof(double) * (size_t)total);
+    L.results = al(sizeof(ColumnResult) * ncols);
+    L.queue = 256;
+    L.total = L.cols + 2 * L.order + 7 * L.field + L.results + L.queue;
+    return L;
 }
 
 int grid_for(tplbm_batch *b, int shape)
@@ -177,7 +204,7 @@ int tplbm_batch_workspace_bytes(const tplbm_batch_params *p, int32_t ncols, cons
                                 size_t *bytes)
 {
     int64_t total;
-    int rc = validate(p, ncols, cols, &total);
+    int rc = batch_validate(p, ncols, cols, &total);
     if (rc) return rc;
     if (!bytes) return bfail(nullptr, TPLBM_EINVAL, "bytes is NULL");
     *bytes = blayout(ncols, total).total;
@@ -188,7 +215,7 @@ int tplbm_batch_create(const tplbm_batch_params *p, int32_t ncols, const tplbm_c
                        void *dev_workspace, size_t bytes, void *hip_stream, tplbm_batch **out)
 {
     int64_t total;
-    int rc = validate(p, ncols, cols, &total);
+    int rc = batch_validate(p, ncols, cols, &total);
     if (rc) return rc;
     if (!out || !dev_workspace) return bfail(nullptr, TPLBM_EINVAL, "NULL argument");
     if (((uintptr_t)dev_workspace & 255) != 0) return bfail(nullptr, TPLBM_EINVAL, "workspace must be 256-byte aligned");
@@ -226,7 +253,7 @@ int tplbm_batch_create(const tplbm_batch_params *p, int32_t ncols, const tplbm_c
     b->f_end = (double *)q; q += 3 * L.field;
     b->results = (ColumnResult *)q; q += L.results;
     b->queue = (unsigned *)q;
-    b->phys = make_bphys(*p);
+    b->phys = batch_phys(*p);
     int dev = 0;
     if (hipGetDevice(&dev) == hipSuccess) {
         int cus = 0;

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/tplbm.h"
 #include "lbm_common.hpp"
 
 namespace tplbm {
@@ -33,7 +34,8 @@ struct BatchArgs {
     // `nodes` values each) to continue from instead of rest populations of
     // rho0; NULL starts at rest.  The end level's populations go to f_out.
     // f_in may equal f_out, and T0 may equal T_out: a column's nodes are read
-    // only by the block that runs it, before that block writes them.
+    // only by the block that runs it, before that block writes them.  f_out
+    // NULL: the end populations are not kept.
     const double *f_in;
     double *f_out;
     int64_t nodes;
@@ -52,5 +54,15 @@ extern const BatchShape kBatchShapes[];
 extern const int kNumBatchShapes;
 hipError_t d1q3_batch_launch(int shape, const BatchArgs &a, const Phys &c, int grid, hipStream_t s);
 hipError_t d1q3_batch_occupancy(int shape, int *blocks_per_cu);
+
+// Host helpers shared by the batch entry points (batch_host.cpp).
+// Validate batch parameters and columns; *total receives the node count.
+// On failure the message goes to the calling thread's context-free error.
+int batch_validate(const tplbm_batch_params *p, int32_t ncols, const tplbm_column *cols, int64_t *total);
+// Record a context-free failure (tplbm_batch_last_error(NULL)) and return code.
+int batch_fail(int code, const char *fmt, ...);
+Phys batch_phys(const tplbm_batch_params &p);
+// Persistent grid of a shape: resident workgroups on the current device, at most ncols.
+int batch_grid(int shape, int ncols);
 
 }  // namespace tplbm

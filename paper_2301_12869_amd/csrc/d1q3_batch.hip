@@ -296,9 +296,11 @@ __global__ __launch_bounds__(NT) void d1q3_batch(BatchArgs a, Phys c)
                 const int64_t i = d.offset + y;
                 a.rho_out[i] = f0[k] + fp[k] + fm[k];
                 a.T_out[i] = T[k];
-                a.f_out[i] = f0[k];
-                a.f_out[a.nodes + i] = fp[k];
-                a.f_out[2 * a.nodes + i] = fm[k];
+                if (a.f_out) {
+                    a.f_out[i] = f0[k];
+                    a.f_out[a.nodes + i] = fp[k];
+                    a.f_out[2 * a.nodes + i] = fm[k];
+                }
             }
         }
         if (tid == 0) {
