@@ -391,6 +391,29 @@ def long_runs(T, torch, rho0, T0):
     return out
 
 
+def fp32dev_accuracy(T, rho0, T0, steps=100_000):
+    """Error of the FP32-deviation storage at the workload's configured length:
+    the headline lattice (F = (rho - <rho>) g, g = 1e-5) run for `steps` steps
+    with FP64 storage (which matches the FP64 oracle to 1e-12) and with FP32
+    deviations (per-row references re-centred every 256 steps), same inputs.
+    Not timed."""
+    out = {}
+    for prec in (0, 1):
+        p = T.make_params(T.D2Q9, nx=NX, ny=NY, walls=True, precision=prec, gravity_form=2, g=1e-5)
+        lat = T.Lattice(p)
+        lat.set_state(rho0, T0)
+        lat.step(steps)
+        out[prec] = (lat.read("rho"), lat.diagnostics())
+        lat.close()
+    (r64, d64), (r32, d32) = out[0], out[1]
+    err = None if (d64["flags"] or d32["flags"]) else float(np.abs(r32 - r64).max() / np.abs(r64).max())
+    print(f"# fp32dev accuracy: rho rel err vs FP64 after {steps} steps {err}", file=sys.stderr, flush=True)
+    return {"workload": f"D2Q9 {NX}x{NY}, (rho-<rho>)g, g=1e-5", "steps": steps,
+            "reference": "FP64 storage (matches the FP64 oracle within 1e-12)",
+            "fp32_references": "one per row, re-centred every 256 steps",
+            "rho_rel_err_vs_fp64": err, "bar": 1e-5}
+
+
 def copy_bandwidth(torch) -> float:
     """Bytes read + written per second by a plain 1 GiB device-to-device copy
     (torch's copy kernel), the practical streaming rate of this HBM."""
@@ -405,28 +428,77 @@ def copy_bandwidth(torch) -> float:
     ev1.record()
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / 5
+    torch_gbs = round(2 * (1 << 30) / (ms * 1e-3) / 1e9, 1)
+    # the library's own streaming copy (16-byte vector loads and stores)
+    import paper_2301_12869_amd as T
+
+    s = torch.cuda.current_stream()
+    lib = T.load_library()
+    lib.tplbm_stream_copy(src.data_ptr(), dst.data_ptr(), 1 << 30, s.cuda_stream)
+    torch.cuda.synchronize()
+    ev0.record(s)
+    for _ in range(5):
+        lib.tplbm_stream_copy(src.data_ptr(), dst.data_ptr(), 1 << 30, s.cuda_stream)
+    ev1.record(s)
+    torch.cuda.synchronize()
+    ok = bool(torch.equal(src, dst))
+    ms = ev0.elapsed_time(ev1) / 5
     del src, dst
-    return round(2 * (1 << 30) / (ms * 1e-3) / 1e9, 1)
+    return {"torch_copy_GBs": torch_gbs,
+            "hip_stream_copy_GBs": round(2 * (1 << 30) / (ms * 1e-3) / 1e9, 1) if ok else None,
+            "bytes_per_copy": 2 * (1 << 30)}
 
 
-def cpu_baseline(rho0, T0, T_c, budget_s=20.0):
-    """The FP64 oracle (single thread, plain loops) on a bounded sample: the
-    same lattice and inputs, as many whole steps as fit in about budget_s."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(rho0, T0, T_c, budget_s=12.0):
+    """The FP64 oracle on a bounded sample of the same lattice and inputs (as
+    many whole steps as fit in about budget_s, after one warm-up step), timed
+    twice on this host: single-threaded (the plain definition) and with its
+    node loops on every thread this process may use (results bit for bit the
+    same).  `value` is the all-threads rate."""
     import oracle
 
-    P = oracle.make_params("D2Q9", nx=NX, ny=NY, walls=True, g=1e-5, gravity_form=2)
-    f = oracle.init_rest(P, rho0.ravel())
-    TT = T0.ravel().copy()
-    t0 = time.perf_counter()
-    oracle.step(P, f, TT, 1)
-    one = time.perf_counter() - t0
-    n = max(1, int(budget_s / max(one, 1e-3)) - 1)
-    t0 = time.perf_counter()
-    oracle.step(P, f, TT, n)
-    dt = time.perf_counter() - t0
-    return dict(value=round(NX * NY * n / dt / 1e6, 3), unit="MLUPS", cores=1, kind="oracle",
-                sample=f"{n} steps of the {NX}x{NY} D2Q9 FP64 workload (gravity form 2) after one "
-                       f"warm-up step, single-threaded plain C, {dt:.1f} s")
+    nproc = os.cpu_count() or 1
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = nproc
+    omp = os.environ.get("OMP_NUM_THREADS")
+    threads = max(1, min(usable, int(omp))) if omp and omp.isdigit() else usable
+
+    def timed(nthreads):
+        oracle.set_threads(nthreads)
+        P = oracle.make_params("D2Q9", nx=NX, ny=NY, walls=True, g=1e-5, gravity_form=2)
+        f = oracle.init_rest(P, rho0.ravel())
+        TT = T0.ravel().copy()
+        t0 = time.perf_counter()
+        oracle.step(P, f, TT, 1)
+        one = time.perf_counter() - t0
+        n = max(1, int(budget_s / max(one, 1e-3)) - 1)
+        t0 = time.perf_counter()
+        oracle.step(P, f, TT, n)
+        dt = time.perf_counter() - t0
+        return NX * NY * n / dt / 1e6, n, dt
+
+    v1, n1, dt1 = timed(1)
+    vt, nt, dtt = timed(threads)
+    oracle.set_threads(1)
+    return dict(value=round(vt, 3), unit="MLUPS", cores=threads, kind="oracle",
+                sample=f"{nt} steps of the {NX}x{NY} D2Q9 FP64 workload (gravity form 2) after one "
+                       f"warm-up step, plain C with OpenMP node loops on {threads} threads, {dtt:.1f} s",
+                single_thread={"value": round(v1, 3), "unit": "MLUPS", "cores": 1,
+                               "sample": f"{n1} steps, {dt1:.1f} s"},
+                nproc=nproc, usable_cpus=usable, cpu_model=_cpu_model())
 
 
 def main():
@@ -495,9 +567,11 @@ def main():
         results[key] = r
         twin = results.get(key.replace("fp32dev", "fp64"))
         if prec == 1 and twin is not None and twin["rho"] is not None and r["rho"] is not None:
-            # same inputs and step count with FP64 populations (which match the
+            # same inputs and step count with FP64 storage (which matches the
             # FP64 oracle to 1e-12): the error of the FP32 deviation storage
+            # over the timed window (the configured length: fp32dev_accuracy)
             r["rho_rel_err_vs_fp64"] = float(np.abs(r["rho"] - twin["rho"]).max() / np.abs(twin["rho"]).max())
+            r["steps_compared"] = args.warmup + args.steps
         print(f"# {key}: {r['kernel_ms']*1e3:.1f} us/step, {r['mlups']:.0f} MLUPS, "
               f"{r['achieved_GBs']:.0f} GB/s ({100*r['frac_hbm']:.1f}% of HBM) [{r['status']}]",
               file=sys.stderr, flush=True)
@@ -537,7 +611,8 @@ def main():
                          "frac_hbm": round(v["frac_hbm"], 4),
                          "bytes_per_node_step": BYTES_PER_NODE[k.split("_")[0]],
                          "traffic": measured_traffic(k),
-                         **({"rho_rel_err_vs_fp64": v["rho_rel_err_vs_fp64"]}
+                         **({"rho_rel_err_vs_fp64": v["rho_rel_err_vs_fp64"],
+                             "steps_compared": v["steps_compared"]}
                             if "rho_rel_err_vs_fp64" in v else {})}
                      for k, v in results.items()},
     }
@@ -582,7 +657,9 @@ def main():
         line["warm_start"] = run_warmstart(T, torch, evaluate=args.variants != "net")
     if args.variants in ("all", "diagram"):
         line["configuration_diagram"] = run_diagram()
-    line["hbm_copy_GBs"] = copy_bandwidth(torch)
+    if args.variants in ("all", "fp32dev"):
+        line["fp32dev_accuracy"] = fp32dev_accuracy(T, rho0, T0)
+    line["hbm_copy"] = copy_bandwidth(torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(rho0, T0, T_c)
     print(json.dumps(line), flush=True)

@@ -61,7 +61,7 @@ extern "C" {
 #define TPLBM_D3Q19 3
 
 #define TPLBM_FP64 0            /* populations stored in FP64 */
-#define TPLBM_FP32_DEV 1        /* populations stored in FP32 as f_i - w_i rho_ref */
+#define TPLBM_FP32_DEV 1        /* populations stored in FP32 as f_i - w_i rho_ref(layer) */
 
 /* state between steps (tplbm_params.state).  With every relaxation time 1
  * the post-collision populations are a closed function of the node's density,
@@ -112,11 +112,21 @@ typedef struct tplbm_params {
     double tau[6];          /* tau_rho, tau_e, tau_varsigma, tau_j, tau_q, tau_nu (> 1/2) */
     double cv, kappa;       /* Eq. Energy_Equation */
     double g;               /* gravity magnitude along -(wall-normal axis) */
-    double rho_ref;         /* FP32_DEV reference density; ignored for FP64 */
+    double rho_ref;         /* FP32_DEV with ref_interval < 0: the one reference density */
     int32_t state;          /* TPLBM_STATE_*: what a lattice stores between steps */
-    int32_t pad;            /* zero */
+    int32_t ref_interval;   /* FP32_DEV reference densities (ignored for FP64):
+                               > 0: one per wall-normal layer (row in 2-D, plane in 3-D),
+                                    the layer's mean of the initial density, re-centred
+                                    on the layer's current mean density every
+                                    ref_interval steps (the stored deviations are
+                                    re-encoded; the populations change by at most one
+                                    FP32 rounding of the new deviation);
+                               0:   the same with TPLBM_REF_INTERVAL_DEFAULT steps;
+                               < 0: rho_ref for every layer, never re-centred */
     double rho_v;           /* gravity form 3: the vapour density subtracted (finite) */
 } tplbm_params;
+
+#define TPLBM_REF_INTERVAL_DEFAULT 256
 
 /* Diagnostics of the time level `step` (the level the last step started from). */
 typedef struct tplbm_diag {
@@ -188,6 +198,13 @@ void tplbm_destroy(tplbm_ctx *ctx);
 /* Message of the last failure on ctx, or of the last failed call made with
  * no context when ctx is NULL.  Never NULL. */
 const char *tplbm_last_error(const tplbm_ctx *ctx);
+
+/* Copy `bytes` bytes between two 16-byte aligned device buffers with 16-byte
+ * vector loads and stores (asynchronous on hip_stream).  A measurement
+ * utility: the HBM streaming rate a bandwidth-bound kernel can reach on this
+ * GPU, which the benchmark reports beside the lattice kernels' rates.
+ * Errors: EINVAL (NULL or misaligned pointer), EHIP. */
+int tplbm_stream_copy(const void *dev_src, void *dev_dst, size_t bytes, void *hip_stream);
 
 /* ---- host FP64 equation-of-state utilities (Eq. EOS, Eq. MaxwellRule) ---- */
 

@@ -42,7 +42,7 @@ class Params(ctypes.Structure):
         ("a", ctypes.c_double), ("b", ctypes.c_double), ("R", ctypes.c_double),
         ("G", ctypes.c_double), ("sigma", ctypes.c_double), ("tau", ctypes.c_double * 6),
         ("cv", ctypes.c_double), ("kappa", ctypes.c_double), ("g", ctypes.c_double),
-        ("rho_ref", ctypes.c_double), ("state", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("rho_ref", ctypes.c_double), ("state", ctypes.c_int32), ("ref_interval", ctypes.c_int32),
         ("rho_v", ctypes.c_double),
     ]
 
@@ -73,6 +73,7 @@ SIGNATURES = {
     "tplbm_load_state": ([_VP, _VP, ctypes.c_size_t], ctypes.c_int),
     "tplbm_destroy": ([_VP], None),
     "tplbm_last_error": ([_VP], ctypes.c_char_p),
+    "tplbm_stream_copy": ([_VP, _VP, ctypes.c_size_t, _VP], ctypes.c_int),
     "tplbm_eos_critical": ([ctypes.c_double] * 3 + [_DP], ctypes.c_int),
     "tplbm_eos_coexistence": ([ctypes.c_double] * 4 + [_DP], ctypes.c_int),
     "tplbm_eos_spinodal": ([ctypes.c_double] * 4 + [_DP], ctypes.c_int),
@@ -242,7 +243,12 @@ def theory_solve(columns, substeps=8, nthreads=0, a=0.5, b=4.0, R=1.0):
 
 
 def make_params(lattice=D2Q9, nx=1, ny=1, nz=1, walls=True, precision=FP64, eos="cs",
-                gravity_form=1, g=0.0, rho_ref=0.0, state=STATE_AUTO, rho_v=0.0, **over) -> Params:
+                gravity_form=1, g=0.0, rho_ref=0.0, state=STATE_AUTO, rho_v=0.0, ref_interval=0,
+                **over) -> Params:
+    """Lattice parameters (paper values unless overridden).  FP32_DEV storage
+    keeps one reference density per wall-normal layer, re-centred every
+    ref_interval steps (0: the library's default interval; < 0: rho_ref for
+    every layer, never re-centred)."""
     d = dict(PAPER)
     d.update(over)
     p = Params()
@@ -256,7 +262,7 @@ def make_params(lattice=D2Q9, nx=1, ny=1, nz=1, walls=True, precision=FP64, eos=
     for k in range(6):
         p.tau[k] = float(d["tau"][k])
     p.cv, p.kappa, p.g, p.rho_ref = d["cv"], d["kappa"], float(g), float(rho_ref)
-    p.state, p.pad = int(state), 0
+    p.state, p.ref_interval = int(state), int(ref_interval)
     p.rho_v = float(rho_v)
     return p
 

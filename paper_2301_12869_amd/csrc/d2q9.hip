@@ -51,7 +51,8 @@ struct PopIO<double> {
 };
 template <>
 struct PopIO<float> {
-    // FP32 deviation storage: the stored value is f_i - w_i rho_ref
+    // FP32 deviation storage: the stored value is f_i - w_i rho_ref(layer),
+    // with the reference density of the layer (row) the value is stored in
     __device__ static __forceinline__ double load(const float *p, size_t i, double wref)
     {
         return wref + (double)p[i];
@@ -275,6 +276,31 @@ __device__ __forceinline__ NodeGeom region_node(int r, int x0, int y0, int nx, i
     return q;
 }
 
+// Reference terms w_i rho_ref(layer of the stored value) of a node's pulled
+// set: directions 0, 1, 3 come from its own row, 2, 5, 6 from the row below,
+// 4, 7, 8 from the row above.  `lr` holds the references of consecutive rows
+// and `k` is the index of the node's own row in it.  FP64 storage has no
+// reference.
+template <class S>
+__device__ __forceinline__ void pull_refs(const double *lr, int k, double (&w)[9])
+{
+    if (sizeof(S) == 8) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) w[i] = 0.0;
+        return;
+    }
+    const double r0 = lr[k], rm = lr[k - 1], rp = lr[k + 1];
+    w[0] = kW0 * r0;
+    w[1] = kW1 * r0;
+    w[3] = kW1 * r0;
+    w[2] = kW1 * rm;
+    w[5] = kW5 * rm;
+    w[6] = kW5 * rm;
+    w[4] = kW1 * rp;
+    w[7] = kW5 * rp;
+    w[8] = kW5 * rp;
+}
+
 // Issue the pull loads [i0, i1) of one region node (all in-bounds); loads
 // 0..8 are the populations, load 9 the temperature.
 template <class S>
@@ -299,7 +325,8 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step(const S *__res
                                                          int nx, int ny, int tiles_x, int ntiles,
                                                          double *__restrict__ partials,
                                                          StepState *__restrict__ st,
-                                                         int64_t step)
+                                                         int64_t step,
+                                                         const double *__restrict__ rref)
 {
     constexpr int kThreads = NT;
     constexpr int W3 = TX + 6, H3 = TY + 6;
@@ -317,15 +344,22 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step(const S *__res
     __shared__ double s_div[H1 * W1];  // div u, for both Heun stages
     __shared__ double s_red[4 * kThreads / 64];
     __shared__ unsigned s_ured[kThreads / 64];
+    // FP32 deviations: row references of a tile's region rows and the rows
+    // its pulls reach, y0 - 4 .. y0 + TY + 3 (rows beyond a wall are clamped:
+    // the populations pulled from there are reconstructed, never used);
+    // double-buffered so that the next tile's rows load during this tile
+    constexpr int NR = TY + 8;
+    __shared__ double s_rref[2][NR];
 
     const int tid = threadIdx.x;
     const size_t N = (size_t)nx * ny;
-    const double rr = c.rho_ref;
     const double mean = st->mean[step & 1];
     const double sub = gravity_sub(c.form, mean, c.rho_v);
     const bool small_x = nx < W3;
-    const double wref[9] = {kW0 * rr, kW1 * rr, kW1 * rr, kW1 * rr, kW1 * rr,
-                            kW5 * rr, kW5 * rr, kW5 * rr, kW5 * rr};
+    auto ref_row = [&](int y) {
+        if (WALLS) return y < 0 ? 0 : (y >= ny ? ny - 1 : y);
+        return wrapi(y, ny);
+    };
 
     // Tiles of this block: blocks are dispatched round-robin over the 8 XCDs;
     // each XCD gets a contiguous range of tiles so that halos are shared in
@@ -360,9 +394,16 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step(const S *__res
     // the start of the tile: every pull is issued before any is consumed, and
     // part of them is in flight while the previous tile computes.
     if (t_begin + slot < t_end) issue(t_begin + slot, true);
-    for (int t = t_begin + slot; t < t_end; t += per_xcd_blocks) {
+    if (sizeof(S) == 4) {
+        if (tid < NR && t_begin + slot < t_end)
+            s_rref[0][tid] = rref[ref_row(((t_begin + slot) / tiles_x) * TY - 4 + tid)];
+        __syncthreads();
+    }
+    int rb = 0;  // buffer of s_rref holding this tile's rows
+    for (int t = t_begin + slot; t < t_end; t += per_xcd_blocks, rb ^= 1) {
         const int x0 = (t % tiles_x) * TX, y0 = (t / tiles_x) * TY;
         issue(t, false);
+        const double *lref = s_rref[rb];
 
         // ---- phase 1: density, momentum, psi on tile + 3 (from registers) ----
 #pragma unroll
@@ -370,7 +411,8 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step(const S *__res
             const int r = tid + k * kThreads;
             if (r < R3N) {
                 const NodeGeom q = region_node<WALLS, W3, TY>(r, x0, y0, nx, ny, small_x);
-                double f[9];
+                double wref[9], f[9];
+                pull_refs<S>(lref, r / W3 + 1, wref);  // region row ry is y0 + ry - 3
 #pragma unroll
                 for (int i = 0; i < 9; ++i) f[i] = PopIO<S>::load(pre.f[k], i, wref[i]);
                 double rho, jx, jy;
@@ -432,7 +474,13 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step(const S *__res
         }
         __syncthreads();
 
-        if (t + per_xcd_blocks < t_end) issue(t + per_xcd_blocks, true);
+        if (t + per_xcd_blocks < t_end) {
+            issue(t + per_xcd_blocks, true);
+            // the next tile's row references go to the other buffer (read
+            // after this tile's closing barrier)
+            if (sizeof(S) == 4 && tid < NR)
+                s_rref[rb ^ 1][tid] = rref[ref_row(((t + per_xcd_blocks) / tiles_x) * TY - 4 + tid)];
+        }
 
         // ---- phase 4: second Heun stage, collision, stores, partials ----
         for (int r = tid; r < TY * TX; r += kThreads) {
@@ -476,7 +524,8 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step(const S *__res
                 S raw[9];
                 double Tdummy;
                 pull_loads<S>(fin, Tin, N, q, raw, Tdummy);
-                double f[9];
+                double wref[9], f[9];
+                pull_refs<S>(lref, ry + 4, wref);
 #pragma unroll
                 for (int i = 0; i < 9; ++i) f[i] = PopIO<S>::load(raw, i, wref[i]);
                 if (WALLS && q.bot) {
@@ -548,10 +597,13 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step(const S *__res
                 fs[8] = d0 + 2.0 * d1 + d2 + d3 + d4 - d5 - d6 - d8;
             }
 
-            // stores, and the next level's mass
+            // stores (FP32: relative to this row's reference), and the next level's mass
+            const double ry_ref = sizeof(S) == 4 ? lref[ry + 4] : 0.0;
+            const double wst[9] = {kW0 * ry_ref, kW1 * ry_ref, kW1 * ry_ref, kW1 * ry_ref, kW1 * ry_ref,
+                                   kW5 * ry_ref, kW5 * ry_ref, kW5 * ry_ref, kW5 * ry_ref};
             double v[9];
 #pragma unroll
-            for (int i = 0; i < 9; ++i) v[i] = PopIO<S>::store(fout, (size_t)i * N + g, fs[i], wref[i]);
+            for (int i = 0; i < 9; ++i) v[i] = PopIO<S>::store(fout, (size_t)i * N + g, fs[i], wst[i]);
             const double nm = next_mass<WALLS>(v, gy, ny);
             part.mass_n += rho;
             part.mass_next += nm;
@@ -888,10 +940,10 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step_mom(const doub
 // ---------------------------------------------------------------------------
 template <class S, bool WALLS>
 __global__ void d2q9_readout_a(const S *__restrict__ fin, const double *__restrict__ Tin, Phys c,
-                               int nx, int ny, double *__restrict__ scr /* 4N */)
+                               int nx, int ny, double *__restrict__ scr /* 4N */,
+                               const double *__restrict__ rref)
 {
     const size_t N = (size_t)nx * ny;
-    const double rr = c.rho_ref;
     for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < N;
          g += (size_t)gridDim.x * blockDim.x) {
         const int gy = (int)(g / nx), gx = (int)(g - (size_t)gy * nx);
@@ -906,19 +958,23 @@ __global__ void d2q9_readout_a(const S *__restrict__ fin, const double *__restri
         const size_t row = (size_t)gy * nx;
         const size_t rowm = (size_t)(bot ? gy : ym) * nx;
         const size_t rowp = (size_t)(top ? gy : yp) * nx;
+        // FP32: references of the rows the values are stored in
+        const double r0 = sizeof(S) == 4 ? rref[gy] : 0.0;
+        const double rm = sizeof(S) == 4 ? rref[bot ? gy : ym] : 0.0;
+        const double rp = sizeof(S) == 4 ? rref[top ? gy : yp] : 0.0;
         double f[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-        f[0] = PopIO<S>::load(fin, 0 * N + row + gx, kW0 * rr);
-        f[1] = PopIO<S>::load(fin, 1 * N + row + xm, kW1 * rr);
-        f[3] = PopIO<S>::load(fin, 3 * N + row + xp, kW1 * rr);
+        f[0] = PopIO<S>::load(fin, 0 * N + row + gx, kW0 * r0);
+        f[1] = PopIO<S>::load(fin, 1 * N + row + xm, kW1 * r0);
+        f[3] = PopIO<S>::load(fin, 3 * N + row + xp, kW1 * r0);
         if (!bot) {
-            f[2] = PopIO<S>::load(fin, 2 * N + rowm + gx, kW1 * rr);
-            f[5] = PopIO<S>::load(fin, 5 * N + rowm + xm, kW5 * rr);
-            f[6] = PopIO<S>::load(fin, 6 * N + rowm + xp, kW5 * rr);
+            f[2] = PopIO<S>::load(fin, 2 * N + rowm + gx, kW1 * rm);
+            f[5] = PopIO<S>::load(fin, 5 * N + rowm + xm, kW5 * rm);
+            f[6] = PopIO<S>::load(fin, 6 * N + rowm + xp, kW5 * rm);
         }
         if (!top) {
-            f[4] = PopIO<S>::load(fin, 4 * N + rowp + gx, kW1 * rr);
-            f[7] = PopIO<S>::load(fin, 7 * N + rowp + xp, kW5 * rr);
-            f[8] = PopIO<S>::load(fin, 8 * N + rowp + xm, kW5 * rr);
+            f[4] = PopIO<S>::load(fin, 4 * N + rowp + gx, kW1 * rp);
+            f[7] = PopIO<S>::load(fin, 7 * N + rowp + xp, kW5 * rp);
+            f[8] = PopIO<S>::load(fin, 8 * N + rowp + xm, kW5 * rp);
         }
         if (bot) {
             const double d = f[1] - f[3];
@@ -1034,7 +1090,7 @@ hipError_t launch_t(const LatticeLaunch &L)
     constexpr int PFP = TAU1 ? (sizeof(S) == 4 ? 10 : 3) : 0;
     hipLaunchKernelGGL((d2q9_step<S, TAU1, WALLS, kTX, kTY, kNT, 4, PFP>), dim3(nb), dim3(kNT), 0, L.stream,
                        (const S *)L.fin, (S *)L.fout, L.Tin, L.Tout, L.phys, L.nx, L.ny, tiles_x,
-                       ntiles, L.partials, L.st, L.step);
+                       ntiles, L.partials, L.st, L.step, L.rref);
     return hipGetLastError();
 }
 
@@ -1085,17 +1141,17 @@ hipError_t d2q9_launch_readout(const LatticeLaunch &L, int field, double *scratc
     } else if (L.fp32) {
         if (L.walls)
             hipLaunchKernelGGL((d2q9_readout_a<float, true>), dim3(blocks), dim3(threads), 0, L.stream,
-                               (const float *)L.fin, L.Tin, L.phys, L.nx, L.ny, scratch);
+                               (const float *)L.fin, L.Tin, L.phys, L.nx, L.ny, scratch, L.rref);
         else
             hipLaunchKernelGGL((d2q9_readout_a<float, false>), dim3(blocks), dim3(threads), 0, L.stream,
-                               (const float *)L.fin, L.Tin, L.phys, L.nx, L.ny, scratch);
+                               (const float *)L.fin, L.Tin, L.phys, L.nx, L.ny, scratch, L.rref);
     } else {
         if (L.walls)
             hipLaunchKernelGGL((d2q9_readout_a<double, true>), dim3(blocks), dim3(threads), 0, L.stream,
-                               (const double *)L.fin, L.Tin, L.phys, L.nx, L.ny, scratch);
+                               (const double *)L.fin, L.Tin, L.phys, L.nx, L.ny, scratch, L.rref);
         else
             hipLaunchKernelGGL((d2q9_readout_a<double, false>), dim3(blocks), dim3(threads), 0, L.stream,
-                               (const double *)L.fin, L.Tin, L.phys, L.nx, L.ny, scratch);
+                               (const double *)L.fin, L.Tin, L.phys, L.nx, L.ny, scratch, L.rref);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -224,15 +224,32 @@ __device__ __forceinline__ double post_tau1(int i, double rho, double ux, double
 // ---- pass A: pull, Zou-He, moments, psi ----------------------------------
 template <class S, bool WALLS>
 __global__ __launch_bounds__(256) void d3q19_pass_a(const S *__restrict__ fin, const double *__restrict__ Tin,
-                                                    double *__restrict__ M, Phys c, Grid3 G)
+                                                    double *__restrict__ M, Phys c, Grid3 G,
+                                                    const double *__restrict__ rref)
 {
     const unsigned N = G.N;
-    const double rr = c.rho_ref;
     const int rows = G.ny * G.nz;
     const RowIter it = row_iter(rows);
     for (int row = it.first; row < it.end; row += it.step) {
         const int y = row % G.ny, z = row / G.ny;
         const Rows R = row_bases<WALLS>(G, y, z);
+        // FP32: reference densities of the planes the pulled values are
+        // stored in (z - c_z; beyond a wall the plane itself, whose values
+        // are then reconstructed)
+        double rz[3] = {0.0, 0.0, 0.0};
+        if (sizeof(S) == 4) {
+            int zm = z - 1, zp = z + 1;
+            if (WALLS) {
+                zm = zm < 0 ? 0 : zm;
+                zp = zp >= G.nz ? G.nz - 1 : zp;
+            } else {
+                zm = zm < 0 ? zm + G.nz : zm;
+                zp = zp >= G.nz ? zp - G.nz : zp;
+            }
+            rz[0] = rref[zm];
+            rz[1] = rref[z];
+            rz[2] = rref[zp];
+        }
         for (int x = threadIdx.x; x < G.nx; x += blockDim.x) {
             const unsigned n = R.at(x, 0, 0);
             const Xs X = xs_of(x, G.nx);
@@ -240,7 +257,7 @@ __global__ __launch_bounds__(256) void d3q19_pass_a(const S *__restrict__ fin, c
 #pragma unroll
             for (int i = 0; i < 19; ++i) {
                 const V3 v = vel(i);
-                f[i] = Pop<S>::ld(fin, (size_t)i * N + R.at(X.v[1 - v.x], -v.y, -v.z), wgt(i) * rr);
+                f[i] = Pop<S>::ld(fin, (size_t)i * N + R.at(X.v[1 - v.x], -v.y, -v.z), wgt(i) * rz[1 - v.z]);
             }
             if (WALLS && (z == 0 || z == G.nz - 1)) {
                 // zero-velocity wet-node reconstruction of the populations that
@@ -528,14 +545,14 @@ __global__ __launch_bounds__(kStencilThreads) void d3q19_pass_d(const double *__
                                                                 const double *__restrict__ K1,
                                                                 S *__restrict__ fout, Phys c, Grid3 G,
                                                                 double *__restrict__ partials,
-                                                                StepState *__restrict__ st, int64_t step)
+                                                                StepState *__restrict__ st, int64_t step,
+                                                                const double *__restrict__ rref)
 {
     using Sh = TileBD;
     __shared__ double s_Tt[Sh::Region];  // T~ = T^n + k1
     __shared__ double s_red[4 * kStencilThreads / 64];
     __shared__ unsigned s_ured[kStencilThreads / 64];
     const unsigned N = G.N;
-    const double rr = c.rho_ref;
     Partial part = {0.0, 0.0, 0.0, 1e300, 0u};
     const int ntiles = Sh::count(G.nx, G.ny, G.nz);
     const TileIter it = tile_iter(ntiles);
@@ -580,6 +597,7 @@ __global__ __launch_bounds__(kStencilThreads) void d3q19_pass_d(const double *__
             }
             fs[0] = rho - rest;
             double nm = 0.0, down = 0.0, up = 0.0;
+            const double rr = sizeof(S) == 4 ? rref[z] : 0.0;  // this plane's reference (FP32)
 #pragma unroll
             for (int i = 0; i < 19; ++i) {
                 const double v = Pop<S>::st(fout, (size_t)i * N + n, fs[i], wgt(i) * rr);
@@ -800,7 +818,7 @@ hipError_t step_t(const LatticeLaunch &L, double *M, double *U, double *K1)
     const Grid3 G{L.nx, L.ny, L.nz, (unsigned)((size_t)L.nx * L.ny * L.nz)};
     const int gA = grid_rows(L.ny, L.nz, L.resident);
     hipLaunchKernelGGL((d3q19_pass_a<S, WALLS>), dim3(gA), dim3(256), 0, L.stream, (const S *)L.fin, L.Tin, M,
-                       L.phys, G);
+                       L.phys, G, L.rref);
     const int gT = grid_tiles<TileBD>(L.nx, L.ny, L.nz, L.resident);
     const int gC = grid_tiles<TileC>(L.nx, L.ny, L.nz, L.resident);
     hipLaunchKernelGGL((d3q19_pass_b<WALLS>), dim3(gT), dim3(kStencilThreads), 0, L.stream, M, U, L.phys, G, L.st,
@@ -809,7 +827,7 @@ hipError_t step_t(const LatticeLaunch &L, double *M, double *U, double *K1)
                        L.phys, G);
     hipLaunchKernelGGL((d3q19_pass_d<S, WALLS>), dim3(gT), dim3(kStencilThreads), 0, L.stream, L.Tin, L.Tout, M,
                        U, K1,
-                       (S *)L.fout, L.phys, G, L.partials, L.st, L.step);
+                       (S *)L.fout, L.phys, G, L.partials, L.st, L.step, L.rref);
     return hipGetLastError();
 }
 
@@ -865,14 +883,14 @@ hipError_t d3q19_launch_readout(const LatticeLaunch &L, int field, double *M, do
         M = (double *)L.fin;  // the state is M itself
     } else if (L.fp32) {
         if (L.walls)
-            hipLaunchKernelGGL((d3q19_pass_a<float, true>), dim3(g), dim3(256), 0, L.stream, (const float *)L.fin, L.Tin, M, L.phys, G);
+            hipLaunchKernelGGL((d3q19_pass_a<float, true>), dim3(g), dim3(256), 0, L.stream, (const float *)L.fin, L.Tin, M, L.phys, G, L.rref);
         else
-            hipLaunchKernelGGL((d3q19_pass_a<float, false>), dim3(g), dim3(256), 0, L.stream, (const float *)L.fin, L.Tin, M, L.phys, G);
+            hipLaunchKernelGGL((d3q19_pass_a<float, false>), dim3(g), dim3(256), 0, L.stream, (const float *)L.fin, L.Tin, M, L.phys, G, L.rref);
     } else {
         if (L.walls)
-            hipLaunchKernelGGL((d3q19_pass_a<double, true>), dim3(g), dim3(256), 0, L.stream, (const double *)L.fin, L.Tin, M, L.phys, G);
+            hipLaunchKernelGGL((d3q19_pass_a<double, true>), dim3(g), dim3(256), 0, L.stream, (const double *)L.fin, L.Tin, M, L.phys, G, L.rref);
         else
-            hipLaunchKernelGGL((d3q19_pass_a<double, false>), dim3(g), dim3(256), 0, L.stream, (const double *)L.fin, L.Tin, M, L.phys, G);
+            hipLaunchKernelGGL((d3q19_pass_a<double, false>), dim3(g), dim3(256), 0, L.stream, (const double *)L.fin, L.Tin, M, L.phys, G, L.rref);
     }
     const int gT = grid_tiles<TileBD>(L.nx, L.ny, L.nz, L.resident);
     if (L.walls) {

@@ -20,7 +20,6 @@ struct Phys {
     double R_over_cv;         // R / c_v: (T/(rho c_v)) (dp/dT)_rho = T (R/c_v) Z(eta)
     double g;                 // gravity magnitude (down the wall-normal axis)
     double rho_v;             // gravity form 3: the subtracted vapour density
-    double rho_ref;           // FP32-deviation reference density
     double lam[9];            // relaxation rates in moment order (Eq. RelaxationMatrix)
     double sig_e, sig_s;      // sigma / tau_e and sigma / tau_varsigma: the sigma part of (I - Lambda/2) S
     int eos;                  // 0 Carnahan-Starling, 1 ideal lattice gas

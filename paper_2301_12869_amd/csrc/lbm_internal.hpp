@@ -22,7 +22,22 @@ struct LatticeLaunch {
     StepState *st;
     int64_t step;         // level the launch starts from
     hipStream_t stream;
+    const double *rref;   // FP32 deviations: reference density per wall-normal layer
 };
+
+// Velocity set of a lattice for the per-layer reference kernels: weights and
+// the wall-normal velocity component of each population.
+struct LayerSet {
+    int Q;
+    double w[19];
+    int cn[19];
+};
+
+// Re-centre the FP32 deviations of every wall-normal layer (lnodes nodes
+// each, nlayers of them) on the layer's current mean density, then write the
+// level's <rho> and mass into st (parity slot `slot`).  lmass: nlayers doubles.
+hipError_t recentre_layers_launch(float *f, double *rref, double *lmass, size_t N, int lnodes, int nlayers,
+                                  const LayerSet &q, bool walls, StepState *st, int slot, hipStream_t s);
 
 // D3Q19 velocity set of this library: rest, +x -x +y -y +z -z, 12 edges
 constexpr int kD3Q19x[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};

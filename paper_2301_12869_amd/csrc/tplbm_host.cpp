@@ -26,6 +26,10 @@ struct tplbm_ctx {
     double *partials = nullptr;
     StepState *st = nullptr;
     double *M = nullptr, *U = nullptr, *K1 = nullptr;  // D3Q19 pass buffers
+    double *rref = nullptr;   // FP32 deviations: reference density per wall-normal layer
+    double *lmass = nullptr;  // per-layer next-level mass of a re-centring
+    int nlayers = 0;          // wall-normal layers (ny in 2-D, nz in 3-D)
+    int ref_interval = 0;     // steps between re-centrings (0: never)
     int cur = 0;
     int64_t step = 0;
     int nblocks = 0;
@@ -116,7 +120,7 @@ int validate(const tplbm_params *p)
     if (!std::isfinite(p->g) || !std::isfinite(p->sigma)) return fail(nullptr, TPLBM_EINVAL, "g and sigma must be finite");
     if (p->state != TPLBM_STATE_AUTO && p->state != TPLBM_STATE_POPULATIONS)
         return fail(nullptr, TPLBM_EINVAL, "state must be TPLBM_STATE_AUTO or TPLBM_STATE_POPULATIONS");
-    if (p->precision == TPLBM_FP32_DEV && !std::isfinite(p->rho_ref))
+    if (p->precision == TPLBM_FP32_DEV && p->ref_interval < 0 && !std::isfinite(p->rho_ref))
         return fail(nullptr, TPLBM_EINVAL, "rho_ref must be finite");
     return TPLBM_OK;
 }
@@ -136,7 +140,6 @@ Phys make_phys(const tplbm_params &p)
     c.R_over_cv = p.R / p.cv;
     c.g = p.g;
     c.rho_v = p.rho_v;
-    c.rho_ref = p.precision == TPLBM_FP32_DEV ? p.rho_ref : 0.0;
     const double t[9] = {p.tau[0], p.tau[1], p.tau[2], p.tau[3], p.tau[4],
                          p.tau[3], p.tau[4], p.tau[5], p.tau[5]};
     for (int k = 0; k < 9; ++k) c.lam[k] = 1.0 / t[k];
@@ -148,9 +151,11 @@ Phys make_phys(const tplbm_params &p)
 }
 
 struct Layout {
-    size_t f_bytes, T_bytes, part_bytes, st_bytes, pass_bytes, total;
+    size_t f_bytes, T_bytes, part_bytes, st_bytes, pass_bytes, ref_bytes, total;
     int nblocks;
 };
+
+int layers_of(const tplbm_params &p) { return p.lattice == TPLBM_D3Q19 ? p.nz : p.ny; }
 
 size_t nodes_of(const tplbm_params &p)
 {
@@ -183,7 +188,9 @@ Layout layout_of(const tplbm_params &p)
     }
     L.part_bytes = align256((size_t)L.nblocks * 5 * 8);
     L.st_bytes = align256(sizeof(StepState));
-    L.total = 2 * L.f_bytes + 2 * L.T_bytes + L.part_bytes + L.st_bytes + L.pass_bytes;
+    // FP32 deviations: layer references and the re-centring's layer shares
+    L.ref_bytes = p.precision == TPLBM_FP32_DEV ? 2 * align256((size_t)layers_of(p) * 8) : 0;
+    L.total = 2 * L.f_bytes + 2 * L.T_bytes + L.part_bytes + L.st_bytes + L.pass_bytes + L.ref_bytes;
     return L;
 }
 
@@ -217,7 +224,32 @@ LatticeLaunch launch_of(tplbm_ctx *c)
     L.st = c->st;
     L.step = c->step;
     L.stream = c->stream;
+    L.rref = c->rref;
     return L;
+}
+
+// The per-layer reference kernels' view of the velocity set.
+LayerSet layer_set(const tplbm_params &p)
+{
+    LayerSet q;
+    std::memset(&q, 0, sizeof q);
+    if (p.lattice == TPLBM_D3Q19) {
+        q.Q = 19;
+        for (int i = 0; i < 19; ++i) {
+            q.w[i] = i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+            q.cn[i] = kD3Q19z[i];
+        }
+    } else {
+        const double w[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+                             1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+        const int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+        q.Q = 9;
+        for (int i = 0; i < 9; ++i) {
+            q.w[i] = w[i];
+            q.cn[i] = cy[i];
+        }
+    }
+    return q;
 }
 
 // D2Q9 velocity set in the paper's order (Eq. VelocitySet) and weights.
@@ -269,7 +301,14 @@ int tplbm_create(const tplbm_params *p, void *dev_workspace, size_t bytes, void 
     if (p->lattice == TPLBM_D3Q19) {
         if (!c->mom) { c->M = (double *)q; q += align256(5 * c->N * 8); }
         c->U = (double *)q; q += align256(7 * c->N * 8);
-        c->K1 = (double *)q;
+        c->K1 = (double *)q; q += align256(2 * c->N * 8);
+    }
+    c->nlayers = layers_of(*p);
+    if (p->precision == TPLBM_FP32_DEV) {
+        c->rref = (double *)q; q += align256((size_t)c->nlayers * 8);
+        c->lmass = (double *)q;
+        c->ref_interval = p->ref_interval > 0 ? p->ref_interval
+                          : (p->ref_interval == 0 ? TPLBM_REF_INTERVAL_DEFAULT : 0);
     }
     c->phys = make_phys(*p);
     StepState s;
@@ -293,7 +332,21 @@ int tplbm_set_state(tplbm_ctx *c, const double *rho0, const double *T0)
     const int nx = c->p.nx, ny = c->p.ny, nz = d3 ? c->p.nz : 1, Q = c->Q;
     const size_t N = c->N;
     const bool walls = c->p.walls != 0, fp32 = c->p.precision == TPLBM_FP32_DEV;
-    const double rr = c->phys.rho_ref;
+    // FP32 deviations: one reference density per wall-normal layer, the
+    // layer's mean initial density (summed in index order), or the single
+    // rho_ref when the references are not re-centred
+    const int nl = c->nlayers;
+    const size_t lnodes = N / (size_t)nl;
+    std::vector<double> rref;
+    if (fp32) {
+        rref.assign(nl, c->p.rho_ref);
+        if (c->p.ref_interval >= 0)
+            for (int l = 0; l < nl; ++l) {
+                double s = 0.0;
+                for (size_t k = 0; k < lnodes; ++k) s += rho0[(size_t)l * lnodes + k];
+                rref[l] = s / (double)lnodes;
+            }
+    }
     double w[19];
     int cx[19], cy[19], cz[19];
     for (int i = 0; i < Q; ++i) {
@@ -365,15 +418,22 @@ int tplbm_set_state(tplbm_ctx *c, const double *rho0, const double *T0)
                     }
                     const double v = w[i] * rho0[((size_t)zs * ny + ys) * nx + xs];
                     const size_t k = (size_t)i * N + n;
-                    if (fp32) ff[k] = (float)(v - w[i] * rr); else fd[k] = v;
+                    if (fp32) ff[k] = (float)(v - w[i] * rref[d3 ? z : y]); else fd[k] = v;
                 }
             }
-    // <rho> of level 0 from the values the first step will see, index order
+    // <rho> of level 0 from the values the first step will see, index order:
+    // with FP32 deviations, population i of node n was stored in the layer
+    // of n - c_i (a node's own layer where that lies beyond a wall)
     double tot = 0.0;
     for (size_t n = 0; n < N; ++n) {
         if (fp32) {
+            const int l = (int)(n / lnodes);
             double r = 0.0;
-            for (int i = 0; i < Q; ++i) r += w[i] * rr + (double)(float)(w[i] * rho0[n] - w[i] * rr);
+            for (int i = 0; i < Q; ++i) {
+                int ls = l - (d3 ? cz[i] : cy[i]);
+                if (ls < 0 || ls >= nl) ls = walls ? l : (ls + nl) % nl;
+                r += w[i] * rref[ls] + (double)(float)(w[i] * rho0[n] - w[i] * rref[ls]);
+            }
             tot += r;
         } else {
             tot += rho0[n];
@@ -386,6 +446,7 @@ int tplbm_set_state(tplbm_ctx *c, const double *rho0, const double *T0)
     else
         HIP_OK(c, hipMemcpyAsync(c->f[0], fd.data(), fd.size() * 8, hipMemcpyHostToDevice, c->stream));
     HIP_OK(c, hipMemcpyAsync(c->T[0], T0, N * 8, hipMemcpyHostToDevice, c->stream));
+    if (fp32) HIP_OK(c, hipMemcpyAsync(c->rref, rref.data(), (size_t)nl * 8, hipMemcpyHostToDevice, c->stream));
     if (c->mom && d3) {
         LatticeLaunch L = launch_of(c);
         HIP_OK(c, d3q19_launch_psi_init(L, (double *)c->f[0]));
@@ -406,7 +467,12 @@ int tplbm_step_async(tplbm_ctx *c, int64_t nsteps)
     if (!c) return fail(nullptr, TPLBM_EINVAL, "ctx is NULL");
     if (nsteps < 0) return fail(c, TPLBM_EINVAL, "nsteps must be >= 0");
     if (!c->have_state) return fail(c, TPLBM_EINVAL, "call tplbm_set_state or tplbm_load_state first");
+    const LayerSet lset = layer_set(c->p);
     for (int64_t s = 0; s < nsteps; ++s) {
+        if (c->ref_interval > 0 && c->step > 0 && c->step % c->ref_interval == 0)
+            HIP_OK(c, recentre_layers_launch((float *)c->f[c->cur], c->rref, c->lmass, c->N, (int)(c->N / c->nlayers),
+                                             c->nlayers, lset, c->p.walls != 0, c->st, (int)(c->step & 1),
+                                             c->stream));
         LatticeLaunch L = launch_of(c);
         if (c->p.lattice == TPLBM_D3Q19)
             HIP_OK(c, d3q19_launch_step(L, c->M, c->U, c->K1));
@@ -486,7 +552,7 @@ int tplbm_state_bytes(const tplbm_ctx *c, size_t *bytes)
 {
     if (!c || !bytes) return fail(nullptr, TPLBM_EINVAL, "NULL argument");
     const size_t elem = c->p.precision == TPLBM_FP32_DEV ? 4 : 8;
-    *bytes = 64 + (size_t)c->planes * c->N * elem + c->N * 8 + sizeof(StepState);
+    *bytes = 64 + (size_t)c->planes * c->N * elem + c->N * 8 + sizeof(StepState) + (c->rref ? (size_t)c->nlayers * 8 : 0);
     return TPLBM_OK;
 }
 
@@ -528,6 +594,9 @@ int tplbm_save_state(tplbm_ctx *c, void *host_blob)
     HIP_OK(c, hipMemcpyAsync(b + 64 + fb, c->T[c->cur], c->N * 8, hipMemcpyDeviceToHost, c->stream));
     HIP_OK(c, hipMemcpyAsync(b + 64 + fb + c->N * 8, c->st, sizeof(StepState),
                              hipMemcpyDeviceToHost, c->stream));
+    if (c->rref)
+        HIP_OK(c, hipMemcpyAsync(b + 64 + fb + c->N * 8 + sizeof(StepState), c->rref, (size_t)c->nlayers * 8,
+                                 hipMemcpyDeviceToHost, c->stream));
     HIP_OK(c, hipStreamSynchronize(c->stream));
     return TPLBM_OK;
 }
@@ -558,6 +627,9 @@ int tplbm_load_state(tplbm_ctx *c, const void *host_blob, size_t bytes)
     std::memcpy(&s, b + 64 + fb + c->N * 8, sizeof s);
     s.counter = 0;
     HIP_OK(c, hipMemcpyAsync(c->st, &s, sizeof s, hipMemcpyHostToDevice, c->stream));
+    if (c->rref)
+        HIP_OK(c, hipMemcpyAsync(c->rref, b + 64 + fb + c->N * 8 + sizeof(StepState), (size_t)c->nlayers * 8,
+                                 hipMemcpyHostToDevice, c->stream));
     HIP_OK(c, hipStreamSynchronize(c->stream));
     c->have_state = true;
     return TPLBM_OK;

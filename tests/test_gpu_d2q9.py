@@ -66,8 +66,8 @@ def _run_oracle(orc, kw, rho0, T0, steps):
     return m
 
 
-def _run_gpu(T, kw, rho0, T0, steps, precision=0, rho_ref=0.0):
-    p = T.make_params(T.D2Q9, precision=precision, rho_ref=rho_ref, **kw)
+def _run_gpu(T, kw, rho0, T0, steps, precision=0, rho_ref=0.0, ref_interval=0):
+    p = T.make_params(T.D2Q9, precision=precision, rho_ref=rho_ref, ref_interval=ref_interval, **kw)
     lat = T.Lattice(p)
     lat.set_state(rho0, T0)
     lat.step(steps)
@@ -111,18 +111,50 @@ def test_c1_fp64_20000_steps(T, orc, crit, form):
     assert got["diag"]["mass"] == pytest.approx(want["rho"].sum(), rel=1e-13)
 
 
+@pytest.mark.parametrize("ref_interval", [-1, 0, 50])
 @pytest.mark.parametrize("form", [1, 2])
-def test_c1_fp32_deviation_storage(T, orc, crit, form):
-    """Same workload with populations stored as FP32 f_i - w_i rho_ref
-    (rho_ref = initial mean density): density within 1e-5 of the FP64 oracle."""
-    _log(f"case c1 fp32dev form={form}")
+def test_c1_fp32_deviation_storage(T, orc, crit, form, ref_interval):
+    """Same workload with populations stored as FP32 deviations f_i - w_i
+    rho_ref: one reference for the lattice (the initial mean density,
+    ref_interval -1), or one per row re-centred every 256 (default) or 50
+    steps.  Density within 1e-5 of the FP64 oracle."""
+    _log(f"case c1 fp32dev form={form} ref_interval={ref_interval}")
     kw, rho0, T0 = _c1_inputs(orc, crit, form)
     want = _c1_oracle(form)
-    got = _run_gpu(T, kw, rho0, T0, 20000, precision=1, rho_ref=float(rho0.mean()))
+    got = _run_gpu(T, kw, rho0, T0, 20000, precision=1, rho_ref=float(rho0.mean()),
+                   ref_interval=ref_interval)
     err = _rel(got["rho"], want["rho"])
     _log(f"  fp32dev rho rel err {err:.3e}  T rel err {_rel(got['T'], want['T']):.3e}")
     assert err < FP32_RHO_TOL
     assert _rel(got["T"], want["T"]) < FP32_RHO_TOL
+    # the level's mean density after the last re-centring is the oracle's
+    assert got["diag"]["mean_rho"] == pytest.approx(want["rho"].mean(), rel=1e-6)
+
+
+def test_fp32_checkpoint_across_re_centrings_is_bitwise(T, orc, crit):
+    """FP32 deviations with per-row references re-centred every 100 steps:
+    the references travel with the checkpoint, so stopping at 250, saving,
+    loading into a new lattice and running on to 700 reproduces a straight
+    700-step run bit for bit."""
+    _log("case fp32 checkpoint with re-centring")
+    kw, rho0, T0 = _c1_inputs(orc, crit, 2)
+    p = T.make_params(T.D2Q9, precision=T.FP32_DEV, ref_interval=100, **kw)
+    a = T.Lattice(p)
+    a.set_state(rho0, T0)
+    a.step(700)
+    ref = {k: a.read(k) for k in ("rho", "uy", "T")}
+    b = T.Lattice(p)
+    b.set_state(rho0, T0)
+    b.step(250)
+    blob = b.save_state()
+    c = T.Lattice(p)
+    c.load_state(blob)
+    c.step(450)
+    for k in ref:
+        assert np.array_equal(c.read(k), ref[k]), k
+    assert c.diagnostics()["mean_rho"] == a.diagnostics()["mean_rho"]
+    for x in (a, b, c):
+        x.close()
 
 
 @pytest.mark.parametrize("walls,form,taus,shape", [

@@ -46,11 +46,11 @@ def _oracle(orc, shape, walls, form, g, rho0, T0, steps):
     return orc.macro(P, f, TT)
 
 
-def _gpu(T, shape, walls, form, g, rho0, T0, steps, precision=0, state=None):
+def _gpu(T, shape, walls, form, g, rho0, T0, steps, precision=0, state=None, ref_interval=0):
     nx, ny, nz = shape
     p = T.make_params(T.D3Q19, nx=nx, ny=ny, nz=nz, walls=walls, gravity_form=form, g=g,
                       precision=precision, rho_ref=float(rho0.mean()), rho_v=RHO_V3,
-                      state=T.STATE_AUTO if state is None else state)
+                      state=T.STATE_AUTO if state is None else state, ref_interval=ref_interval)
     lat = T.Lattice(p)
     lat.set_state(rho0, T0)
     lat.step(steps)
@@ -124,13 +124,16 @@ def test_moment_state_checkpoint_is_bitwise(T, orc, crit):
         assert np.array_equal(got[k], want[k]), k
 
 
-def test_small_lattice_fp32_deviation(T, orc, crit):
+@pytest.mark.parametrize("ref_interval", [-1, 0, 40])
+def test_small_lattice_fp32_deviation(T, orc, crit, ref_interval):
+    """FP32 deviations from one reference (-1) or per-plane references
+    re-centred every 256 (default) or 40 steps, against the FP64 oracle."""
     shape = (6, 6, 24)
     rho0, T0 = _state(orc, crit, shape, 6, 8)
     want = _oracle(orc, shape, True, 2, 1e-4, rho0, T0, 500)
-    got = _gpu(T, shape, True, 2, 1e-4, rho0, T0, 500, precision=1)
+    got = _gpu(T, shape, True, 2, 1e-4, rho0, T0, 500, precision=1, ref_interval=ref_interval)
     err = _rel(got["rho"], want["rho"])
-    _log(f"  fp32dev rho rel err {err:.3e}")
+    _log(f"  fp32dev ref_interval={ref_interval} rho rel err {err:.3e}")
     assert err < 1e-5
     assert _rel(got["T"], want["T"]) < 1e-5
 
