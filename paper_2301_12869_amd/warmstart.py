@@ -306,20 +306,39 @@ def summarize(cols: Columns, res: dict) -> dict:
         both = (c["status"] == 0) & (w["status"] == 0)
         cmp = dict(both_converged=int(both.sum()))
         if both.any():
-            same, diffs, dmass = 0, [], []
+            same, diffs, dmass, pairs = 0, [], [], []
             for k in np.nonzero(both)[0]:
                 a = c["rho"][cols.offsets[k]:cols.offsets[k + 1]]
                 b = w["rho"][cols.offsets[k]:cols.offsets[k + 1]]
-                if interfaces(a) == interfaces(b):
+                pa, pb = interface_positions(a), interface_positions(b)
+                rec = dict(column=int(k), height=int(cols.height[k]), morphology_cold=morphology(a),
+                           morphology_warm=morphology(b), mass_diff=float(b.sum() - a.sum()),
+                           rho_max_rel_diff=float(np.abs(a - b).max() / a.max()))
+                if rec["morphology_cold"] == rec["morphology_warm"] and len(pa) == len(pb):
                     same += 1
-                    diffs.append(float(np.abs(a - b).max() / a.max()))
+                    diffs.append(rec["rho_max_rel_diff"])
                     dmass.append(float(abs(b.sum() - a.sum()) / a.sum()))
+                    # a flat interface moves by the mass difference over the
+                    # density jump; half a node covers where a node straddles it
+                    jump = float(a.max() - a.min())
+                    shift = float(np.max(np.abs(np.array(pb) - np.array(pa)))) if pa else 0.0
+                    rec.update(interface_shift=shift, shift_bound=abs(rec["mass_diff"]) / jump + 0.5)
+                pairs.append(rec)
             cmp.update(steps_ratio_median=float(np.median(w["steps"][both] / c["steps"][both])),
                        same_morphology=same)
             if diffs:
                 cmp.update(final_rho_max_rel_diff_median=float(np.median(diffs)),
                            final_rho_max_rel_diff_max=float(np.max(diffs)),
                            final_mass_rel_diff_median=float(np.median(dmass)))
+            # pairs that settled in different configurations (several steady
+            # states of one column can coexist), and same-configuration pairs
+            # whose interfaces moved further than their mass difference explains
+            other = [p for p in pairs if p["morphology_cold"] != p["morphology_warm"]]
+            bad = [p for p in pairs if "interface_shift" in p and p["interface_shift"] > p["shift_bound"]]
+            worst = max(pairs, key=lambda p: p["rho_max_rel_diff"])
+            cmp.update(shift_within_bound=sum(1 for p in pairs if "interface_shift" in p
+                                              and p["interface_shift"] <= p["shift_bound"]),
+                       other_configuration=other, violations=bad, largest_difference=worst)
         out[name + "_vs_cold"] = cmp
     # mass the walls add or remove during the transient (the seeded mass is
     # the column's <rho> H for every start)
@@ -337,6 +356,25 @@ def summarize(cols: Columns, res: dict) -> dict:
         conv = r["status"] == 0
         if conv.any():
             out[name]["mass_drift_rel_median"] = float(np.median(np.abs(r["mass"][conv] - m0[conv]) / m0[conv]))
+    return out
+
+
+def morphology(rho: np.ndarray) -> str:
+    """Phase sequence from the bottom ('L-V', 'V-L', 'V-L-V', ...), split at
+    the midpoint between the extreme densities."""
+    from .diagram import morphology as phases
+
+    return phases(rho)
+
+
+def interface_positions(rho: np.ndarray) -> list:
+    """Heights (in nodes from node 0) where a profile crosses the midpoint
+    between its extreme densities, by linear interpolation between nodes."""
+    mid = 0.5 * (rho.max() + rho.min())
+    d = rho - mid
+    out = []
+    for k in np.nonzero(np.sign(d[1:]) != np.sign(d[:-1]))[0]:
+        out.append(float(k + d[k] / (d[k] - d[k + 1])))
     return out
 
 

@@ -52,18 +52,45 @@ def test_warm_start_reaches_more_steady_states(result):
 
 
 def test_warm_start_reaches_the_same_steady_states(result):
+    """For every column that converges from both starts: the same phase
+    sequence, and each interface within |Delta mass| / (rho_l - rho_v) + 0.5
+    nodes of the cold start's -- the shift a different final mass alone
+    explains (the Zou-He walls exchange mass during the transient, C19, so
+    two different transients end with slightly different masses; the steady
+    state of a column is set by its mass).  The densities then differ only
+    near the interfaces.
+
+    One column may hold several steady states (L-V, V-L and V-L-V can
+    coexist, Sec. VI).  A pair that settled in different configurations is
+    accepted only where the sharp-interface theory (Sec. IV A) rules out the
+    cold start's configuration and allows the warm start's: the lattice held
+    the plain start in a configuration the theory says cannot exist (the
+    condensation region of F = (rho - <rho>) g, Sec. V B), and the warm start
+    found the theory's equilibrium instead.  Held-out column 773 (form 2,
+    g = 5.85e-5, T/T_c = 0.924, 144 nodes, mean 0.708 rho_c) is such a
+    column: the theory has no L-V equilibrium there (the vapour reaches its
+    spinodal) and a V-L one with the interface at node 106."""
+    import paper_2301_12869_amd as T
+
     cols, res, s = result
     for name in ("warm", "warm_rho"):
         cmp = s[name + "_vs_cold"]
-        _log(f"{name} vs cold: {cmp}")
+        _log(f"{name} vs cold: { {k: v for k, v in cmp.items() if k not in ('violations', 'other_configuration')} }")
+        for v in cmp["violations"]:
+            _log(f"  interface moved beyond its mass difference: {v}")
         assert cmp["both_converged"] > 0
-        # the same morphology for nearly every column both runs converge
-        assert cmp["same_morphology"] >= 0.9 * cmp["both_converged"]
-        # both are steady states of the method to the same tolerance; their
-        # masses differ only by what the walls exchanged during the two
-        # transients (up to a few % in a column whose liquid layer evaporates)
+        assert not cmp["violations"]
+        for p in cmp["other_configuration"]:
+            k = p["column"]
+            H, form, g = int(cols.height[k]), int(cols.form[k]), float(cols.g[k])
+            Tk = float(cols.t_reduced[k]) * cols.T_c
+            mean = float(cols.mean_reduced[k]) * cols.rho_c
+            th = {cfg: T.theory_solve([(H, Tk, Tk, g, form, mean, cfg)], substeps=2)[0]["rho"] is not None
+                  for cfg in (p["morphology_cold"], p["morphology_warm"])}
+            _log(f"  other configuration: {p}; theory allows {th}")
+            assert not th[p["morphology_cold"]] and th[p["morphology_warm"]], p
+        assert cmp["same_morphology"] + len(cmp["other_configuration"]) == cmp["both_converged"]
         assert cmp["final_mass_rel_diff_median"] < 1e-3
-        assert cmp["final_rho_max_rel_diff_median"] < 1e-2
 
 
 def test_prediction_keeps_the_column_mass(result):
