@@ -203,13 +203,13 @@ def batch_inputs(T, n=BATCH_COLS, seed=BATCH_SEED):
     return cols, rho, Tt
 
 
-def run_batched(T, torch, cols, rho, Tt):
+def run_batched(T, torch, cols, rho, Tt, max_steps=BATCH_MAX_STEPS):
     b = T.Batch(cols)
     b.set_state(np.concatenate(rho), np.concatenate(Tt))
     tune = b.autotune(budget_ms=3000)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    res = b.run(BATCH_TOL, BATCH_MAX_STEPS)
+    res = b.run(BATCH_TOL, max_steps)
     dt = time.perf_counter() - t0
     b.close()
     H = np.array([c[0] for c in cols])
@@ -245,6 +245,108 @@ def run_plain(T, cols, rho, Tt, check_every):
         node_steps += H * n
         lat.close()
     return dict(seconds=time.perf_counter() - t0, converged=conv, node_steps=node_steps)
+
+
+GOLDEN_COLUMNS = os.path.join(ROOT, "tests", "golden", "c3_columns_seed3_to_steady.npz")
+
+
+def like_for_like(T, torch, plain_budget_s=60.0):
+    """Steady states per hour of the plain per-column method, the batched
+    sweep from the plain start and the batched sweep from the learned warm
+    start, on one column set: the sweep's draw (seed 3) shortest first, as the
+    oracle ran it for the goldens (every column it tried until 64 converged:
+    the same starts, tolerance, check interval and step budget).  Accuracy:
+    each method's converged profiles against the oracle's.  The plain method
+    (one fused-kernel launch per step on an nx = 1 lattice, the host reading
+    max |u| between chunks) takes the set in its fixed order until its time
+    budget is spent; its rate is over the columns it finished."""
+    from paper_2301_12869_amd import warmstart as WS
+
+    g = np.load(GOLDEN_COLUMNS, allow_pickle=False)
+    H = g["height"].astype(int)
+    cols = [(int(h), int(f), float(gg)) for h, f, gg in zip(H, g["form"], g["g"])]
+    off = np.concatenate([[0], np.cumsum(H)])
+    rho0 = g["rho0"]
+    T0 = np.concatenate([np.full(h, t) for h, t in zip(H, g["T"])])
+    tol, K, max_steps = float(g["tol"]), int(g["check_every"]), int(g["max_steps"])
+    gold_conv = g["status"] == 0
+
+    def accuracy(rho, conv):
+        both = np.nonzero(conv & gold_conv)[0]
+        if not len(both):
+            return None
+        return float(max(np.abs(rho[off[k]:off[k + 1]] - g["rho"][off[k]:off[k + 1]]).max()
+                         / g["rho"][off[k]:off[k + 1]].max() for k in both))
+
+    out = {"columns": len(cols), "oracle_converged": int(gold_conv.sum()),
+           "heights": [int(H.min()), int(H.max())], "tol": tol, "check_every": K, "max_steps": max_steps}
+
+    def batch(start_rho, start_T, label, setup_s=0.0):
+        b = T.Batch(cols)
+        b.set_state(start_rho, start_T)
+        b.set_tuning(shape=0, check_every=K)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = b.run(tol, max_steps)
+        dt = time.perf_counter() - t0 + setup_s
+        rho = b.read("rho")
+        b.close()
+        conv = res["status"] == 0
+        rec = {"converged": int(conv.sum()), "diverged": int((res["status"] == 1).sum()),
+               "seconds": round(dt, 3), "steady_states_per_hour": round(conv.sum() / dt * 3600.0, 1),
+               "same_status_as_oracle": int((res["status"] == g["status"]).sum()),
+               "rho_max_rel_err_vs_oracle": accuracy(rho, conv)}
+        print(f"# like-for-like {label}: {rec}", file=sys.stderr, flush=True)
+        return rec
+
+    out["batched_cold"] = batch(rho0, T0, "batched cold")
+    rho_c, T_c, _ = T.eos_critical()
+    net_cols = []
+    for k, (h, f, gg) in enumerate(cols):
+        rv, rl, _ = T.eos_coexistence(float(g["T"][k]))
+        mean = float(rho0[off[k]:off[k + 1]].mean())
+        net_cols.append((h, f, float(g["T"][k]) / T_c, gg, mean / rho_c, h * (mean - rv) / (rl - rv)))
+    net = T.Net(rho_c, T_c, max_cols=len(cols), max_nodes=int(H.sum()))
+    net.set_params(np.load(WS.PARAMS_PATH))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rho_w, T_w = net.predict(net_cols)
+    t_pred = time.perf_counter() - t0
+    net.close()
+    out["batched_warm_rho"] = batch(rho_w, T0, "batched warm (network rho, column T)", t_pred)
+    out["batched_warm"] = batch(rho_w, T_w, "batched warm (network rho and T)", t_pred)
+    # the plain per-column method over the same set, in order, within the budget
+    t0 = time.perf_counter()
+    conv, done, errs = 0, 0, []
+    for k, (h, f, gg) in enumerate(cols):
+        if time.perf_counter() - t0 > plain_budget_s:
+            break
+        lat = T.Lattice(T.make_params(T.D2Q9, nx=1, ny=h, walls=True, gravity_form=f, g=gg))
+        lat.set_state(rho0[off[k]:off[k + 1]], T0[off[k]:off[k + 1]])
+        n = 0
+        while n < max_steps:
+            lat.step_async(K)
+            n += K
+            d = lat.diagnostics()
+            if d["flags"]:
+                break
+            if d["max_u"] < tol:
+                conv += 1
+                if gold_conv[k]:
+                    r = lat.read("rho")
+                    errs.append(float(np.abs(r - g["rho"][off[k]:off[k + 1]]).max()
+                                      / g["rho"][off[k]:off[k + 1]].max()))
+                break
+        lat.close()
+        done += 1
+    dt = time.perf_counter() - t0
+    out["plain_per_column"] = {"columns_finished": done, "converged": conv, "seconds": round(dt, 2),
+                               "steady_states_per_hour": round(conv / dt * 3600.0, 1),
+                               "rho_max_rel_err_vs_oracle": max(errs) if errs else None,
+                               "note": "max|u| read one level before each check level (the library's "
+                                       "diagnostics report the last step's velocity)"}
+    print(f"# like-for-like plain per column: {out['plain_per_column']}", file=sys.stderr, flush=True)
+    return out
 
 
 WS_EVAL_COLS, WS_EVAL_SEED, WS_EVAL_STEPS = 1024, 2002, 4_000_000
@@ -511,6 +613,10 @@ def main():
                     help="only the long untimed runs (10^5 D2Q9 and 5*10^4 D3Q19 steps), as a JSON line")
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the plain per-column comparison of the batched sweep")
+    ap.add_argument("--batch-max-steps", type=int, default=BATCH_MAX_STEPS,
+                    help="step budget of the 4096-column sweep (profiling runs use a shorter one)")
+    ap.add_argument("--no-like-for-like", action="store_true",
+                    help="skip the like-for-like steady-states/hour comparison")
     ap.add_argument("--variants", default="all",
                     help="all | headline | fp64pop | fp32dev | d3q19 | batched | warmstart | net | diagram")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -620,7 +726,7 @@ def main():
         line["d3q19_256cubed"] = run_d3q19(T, torch, min(args.steps, 200), 10)
     if args.variants in ("all", "batched"):
         cols, rho, Tt = batch_inputs(T)
-        bt = run_batched(T, torch, cols, rho, Tt)
+        bt = run_batched(T, torch, cols, rho, Tt, args.batch_max_steps)
         print(f"# batched sweep: {bt['converged']} converged, {bt['diverged']} diverged, "
               f"{bt['max_steps']} at the budget in {bt['seconds']:.1f} s, tuning {bt['tuning']}",
               file=sys.stderr, flush=True)
@@ -638,7 +744,7 @@ def main():
         line["batched_sweep"] = {
             "metric": "steady-states/hour",
             "workload": f"{BATCH_COLS} columns, heights 128..2048, g 1e-6..1e-4, T/Tc 0.6..0.95, "
-                        f"both forms, run to max|u| < {BATCH_TOL:g} or {BATCH_MAX_STEPS} steps",
+                        f"both forms, run to max|u| < {BATCH_TOL:g} or {args.batch_max_steps} steps",
             "value": round(bt["converged"] / (bt["seconds"] / 3600.0), 1),
             "converged": bt["converged"], "diverged": bt["diverged"],
             "at_step_budget": bt["max_steps"], "seconds": round(bt["seconds"], 2),
@@ -653,6 +759,8 @@ def main():
                                            if pick else None),
                 "node_steps_per_s": round(pl["node_steps"] / pl["seconds"], 1) if pick else None},
         }
+    if args.variants in ("all", "batched") and not args.no_like_for_like and os.path.exists(GOLDEN_COLUMNS):
+        line["like_for_like"] = like_for_like(T, torch)
     if args.variants in ("all", "warmstart", "net"):
         line["warm_start"] = run_warmstart(T, torch, evaluate=args.variants != "net")
     if args.variants in ("all", "diagram"):
