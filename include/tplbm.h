@@ -495,6 +495,15 @@ int tplbm_net_create(const tplbm_net_config *c, void *dev_workspace, size_t byte
 int tplbm_net_set_params(tplbm_net *n, const float *theta);
 int tplbm_net_get_params(tplbm_net *n, float *theta);
 
+/* Initialise the parameters (and reset Adam) with He-uniform weights, bound
+ * sqrt(6 / (5 C_in)), and zero biases.  Weight k, counted over the layers in
+ * the parameter layout's order, is 2 u_k - 1 times the bound, where u_k takes
+ * the top 53 bits of the SplitMix64 finaliser of
+ * seed + (k + 1) * 0x9E3779B97F4A7C15 (mod 2^64), rounded to FP32.  The
+ * network is an addition to the paper's method: its initialisation follows
+ * no passage of the paper. */
+int tplbm_net_init(tplbm_net *n, uint64_t seed);
+
 /* Copy a training set to the device: ncols column descriptions and their
  * steady profiles rho and T (host, concatenated column after column).
  * Errors: EINVAL, ESHAPE (more than the workspace holds). */
@@ -520,6 +529,12 @@ int tplbm_net_forward(tplbm_net *n, int32_t ncols, const tplbm_net_column *cols,
  * exactly <rho>; T = T_c (T/T_c + out_1) inside and T_c t_reduced at the two
  * wall nodes (the Dirichlet data).  Pass them to tplbm_batch_set_state. */
 int tplbm_net_predict(tplbm_net *n, int32_t ncols, const tplbm_net_column *cols, double *rho, double *T);
+
+/* The same profiles into device arrays (caller-owned, sum(height) doubles
+ * each), enqueued on the network's stream without waiting: a warm start can
+ * then seed tplbm_batch_run_noalloc without a round trip through the host. */
+int tplbm_net_predict_device(tplbm_net *n, int32_t ncols, const tplbm_net_column *cols, double *dev_rho,
+                             double *dev_T);
 
 /* One v_mfma_f32_32x32x8_bf16 on host operands: a and b hold 64 lanes x 4
  * bf16 values each (lane-major), d receives 64 lanes x 16 FP32 results.  For

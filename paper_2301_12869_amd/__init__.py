@@ -148,6 +148,17 @@ def load_library():
     return _lib
 
 
+def _device(device=None):
+    """torch device with its index (a bare "cuda" becomes the current device),
+    so that it compares equal to the device of a tensor allocated on it."""
+    import torch
+
+    d = torch.device(device or "cuda")
+    if d.type == "cuda" and d.index is None:
+        d = torch.device("cuda", torch.cuda.current_device())
+    return d
+
+
 def _check(rc: int, ctx=None):
     if rc != OK:
         msg = load_library().tplbm_last_error(ctx).decode()
@@ -279,7 +290,7 @@ class Lattice:
         self.params = params
         nbytes = ctypes.c_size_t()
         _check(lib.tplbm_workspace_bytes(ctypes.byref(params), ctypes.byref(nbytes)))
-        self.device = torch.device(device or "cuda")
+        self.device = _device(device)
         self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
         self.stream = stream or torch.cuda.current_stream(self.device)
         h = _VP()
@@ -381,7 +392,7 @@ class Batch:
         nb = ctypes.c_size_t()
         _bcheck(lib.tplbm_batch_workspace_bytes(ctypes.byref(p), self.ncols, self.cols,
                                                 ctypes.byref(nb)))
-        self.device = torch.device(device or "cuda")
+        self.device = _device(device)
         self.workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
         self.stream = stream or torch.cuda.current_stream(self.device)
         h = _VP()
@@ -530,6 +541,8 @@ SIGNATURES.update({
     "tplbm_net_train_step": ([_VP, ctypes.c_int32, _IP, ctypes.c_float, _DP], ctypes.c_int),
     "tplbm_net_forward": ([_VP, ctypes.c_int32, _NCP, _FP], ctypes.c_int),
     "tplbm_net_predict": ([_VP, ctypes.c_int32, _NCP, _DP, _DP], ctypes.c_int),
+    "tplbm_net_predict_device": ([_VP, ctypes.c_int32, _NCP, _VP, _VP], ctypes.c_int),
+    "tplbm_net_init": ([_VP, ctypes.c_uint64], ctypes.c_int),
     "tplbm_net_mfma_check": ([_VP, _U16P, _U16P, _FP], ctypes.c_int),
     "tplbm_net_destroy": ([_VP], None),
     "tplbm_net_last_error": ([_VP], ctypes.c_char_p),
@@ -582,7 +595,7 @@ class Net:
         self.n_params = net_num_params()
         nb = ctypes.c_size_t()
         _ncheck(lib.tplbm_net_workspace_bytes(ctypes.byref(c), ctypes.byref(nb)))
-        self.device = torch.device(device or "cuda")
+        self.device = _device(device)
         self.workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
         self.stream = stream or torch.cuda.current_stream(self.device)
         h = _VP()
@@ -596,6 +609,10 @@ class Net:
         if t.size != self.n_params:
             raise ValueError(f"need {self.n_params} parameters")
         _ncheck(load_library().tplbm_net_set_params(self._h, _fp(t)), self._h)
+
+    def init(self, seed: int):
+        """He-uniform initialisation from the seeded SplitMix64 stream (C side)."""
+        _ncheck(load_library().tplbm_net_init(self._h, int(seed) % (1 << 64)), self._h)
 
     def get_params(self) -> np.ndarray:
         t = np.empty(self.n_params, dtype=np.float32)
@@ -644,6 +661,20 @@ class Net:
         _ncheck(load_library().tplbm_net_predict(self._h, len(columns), cols, _dp(rho), _dp(T)),
                 self._h)
         return rho, T
+
+    def predict_device(self, columns, rho_out, T_out):
+        """Profiles into float64 device tensors of sum(heights) values each,
+        enqueued on the network's stream."""
+        import torch
+
+        cols = net_columns(columns)
+        n = sum(int(c[0]) for c in columns)
+        for t in (rho_out, T_out):
+            if not isinstance(t, torch.Tensor) or t.device != self.device or t.dtype != torch.float64 \
+                    or t.numel() != n or not t.is_contiguous():
+                raise ValueError(f"outputs must be contiguous float64 tensors of {n} values on {self.device}")
+        _ncheck(load_library().tplbm_net_predict_device(self._h, len(columns), cols, rho_out.data_ptr(),
+                                                        T_out.data_ptr()), self._h)
 
     def mfma_check(self, a, b) -> np.ndarray:
         a = np.ascontiguousarray(a, dtype=np.uint16)

@@ -379,6 +379,30 @@ int tplbm_net_set_params(tplbm_net *n, const float *theta)
     return TPLBM_OK;
 }
 
+int tplbm_net_init(tplbm_net *n, uint64_t seed)
+{
+    if (!n) return nfail(nullptr, TPLBM_EINVAL, "net is NULL");
+    // He-uniform weights, bound sqrt(6 / fan_in) with fan_in = 5 C_in, zero
+    // biases.  Draw k (counted over the weights of every layer in order) is
+    // the SplitMix64 finaliser of seed + (k + 1) * 0x9E3779B97F4A7C15 (Steele,
+    // Lea and Flood, OOPSLA 2014), mapped to [-1, 1) from its top 53 bits.
+    std::vector<float> theta(n->np, 0.0f);
+    uint64_t k = 0;
+    for (int l = 0; l < kNetLayers; ++l) {
+        const double bound = std::sqrt(6.0 / (double)(kNetTaps * kNetCin[l]));
+        const int64_t nw = (int64_t)kNetCout[l] * kNetTaps * kNetCin[l], off = w_offset(l);
+        for (int64_t e = 0; e < nw; ++e, ++k) {
+            uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
+            z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+            z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+            z ^= z >> 31;
+            const double u = 2.0 * ((double)(z >> 11) * 0x1.0p-53) - 1.0;
+            theta[off + e] = (float)(bound * u);
+        }
+    }
+    return tplbm_net_set_params(n, theta.data());
+}
+
 int tplbm_net_get_params(tplbm_net *n, float *theta)
 {
     if (!n || !theta) return nfail(n, TPLBM_EINVAL, "NULL argument");
@@ -481,6 +505,22 @@ int tplbm_net_predict(tplbm_net *n, int32_t ncols, const tplbm_net_column *cols,
     NHIP(n, hipMemcpyAsync(rho, n->pred_rho, sizeof(double) * nodes, hipMemcpyDeviceToHost, n->stream));
     NHIP(n, hipMemcpyAsync(T, n->pred_T, sizeof(double) * nodes, hipMemcpyDeviceToHost, n->stream));
     NHIP(n, hipStreamSynchronize(n->stream));
+    return TPLBM_OK;
+}
+
+int tplbm_net_predict_device(tplbm_net *n, int32_t ncols, const tplbm_net_column *cols, double *dev_rho,
+                             double *dev_T)
+{
+    if (!n || !dev_rho || !dev_T) return nfail(n, TPLBM_EINVAL, "NULL argument");
+    if (!n->have_params) return nfail(n, TPLBM_EINVAL, "call tplbm_net_set_params first");
+    int64_t P, nodes;
+    int rc = direct_batch(n, ncols, cols, &P, &nodes);
+    if (rc) return rc;
+    rc = forward(n, P);
+    if (rc) return rc;
+    NHIP(n, net_emit(n->cols, n->entries, ncols, n->out, n->c.rho_c, n->c.T_c, n->pred_rho, n->pred_T, n->stream));
+    NHIP(n, hipMemcpyAsync(dev_rho, n->pred_rho, sizeof(double) * nodes, hipMemcpyDeviceToDevice, n->stream));
+    NHIP(n, hipMemcpyAsync(dev_T, n->pred_T, sizeof(double) * nodes, hipMemcpyDeviceToDevice, n->stream));
     return TPLBM_OK;
 }
 

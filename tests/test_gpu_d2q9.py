@@ -265,6 +265,10 @@ def test_checkpoint_restart_is_bitwise(T, orc, crit):
     for k in ref:
         assert np.array_equal(c.read(k), ref[k]), k
     assert c.diagnostics()["step"] == 700
+    dev = torch.empty(c.n, dtype=torch.float64, device="cuda")
+    c.read_device("rho", dev)
+    torch.cuda.synchronize()
+    assert np.array_equal(dev.cpu().numpy(), ref["rho"])
     with pytest.raises(ValueError):
         c.read_device("rho", torch.empty(c.n, dtype=torch.float32, device=c.device))
     with pytest.raises(ValueError):

@@ -228,3 +228,37 @@ def test_bad_arguments_are_rejected(T, consts):
     with pytest.raises(T.TplbmError):
         net.set_params(bad)
     net.close()
+
+
+def test_c_initialisation_equals_the_reference_draw(T, consts):
+    """tplbm_net_init(seed) draws the He-uniform weights of the reference's
+    init_params (same SplitMix64 stream, same order, rounded to FP32) and
+    zero biases, bit for bit."""
+    rho_c, T_c = consts
+    net = T.Net(rho_c, T_c, max_cols=4, max_nodes=256)
+    for seed in (0, 12345, 2 ** 63 + 7):
+        net.init(seed)
+        got = net.get_params()
+        want = N.init_params(seed).astype(np.float32)
+        assert np.array_equal(got, want), seed
+    net.close()
+
+
+def test_device_prediction_equals_the_host_prediction(T, consts):
+    """tplbm_net_predict_device writes the same profiles into device arrays."""
+    import torch
+
+    rho_c, T_c = consts
+    net = T.Net(rho_c, T_c, max_cols=len(COLS), max_nodes=sum(c[0] for c in COLS))
+    net.set_params(_theta(11))
+    rho, Tp = net.predict(COLS)
+    n = rho.size
+    dr = torch.empty(n, dtype=torch.float64, device=net.device)
+    dT = torch.empty(n, dtype=torch.float64, device=net.device)
+    net.predict_device(COLS, dr, dT)
+    torch.cuda.synchronize()
+    assert np.array_equal(dr.cpu().numpy(), rho)
+    assert np.array_equal(dT.cpu().numpy(), Tp)
+    with pytest.raises(ValueError):
+        net.predict_device(COLS, dr[:-1], dT)
+    net.close()
