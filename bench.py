@@ -69,6 +69,42 @@ def measured_traffic(variant: str):
     return None if v is None else float(v["hbm_bytes_per_launch"])
 
 
+SQ_FILE = os.path.join(ROOT, "profiles", "d2q9_1024x2048_sq_counters.json")
+# MI355X vector issue: 256 compute units x 4 SIMDs x 16 lanes per clock at 2.4 GHz
+VALU_LANE_OPS_PEAK = 256 * 64 * 2.4e9
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def measured_sq(variant: str):
+    """Per-node SQ counter figures from the committed rocprofv3 record, or None
+    when the kernel source changed since the counters were taken."""
+    try:
+        with open(SQ_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != source_hash():
+        return None
+    return rec.get("variants", {}).get(variant)
+
+
+def valu_roofline(variant: str, kernel_ms: float):
+    """The same launch against the vector units: VALU lane-instructions and
+    FP64 flops per node from the committed SQ counters, over the measured
+    kernel time, against the chip's issue rate (256 CUs x 64 lanes x 2.4 GHz)
+    and its FP64 vector peak."""
+    sq = measured_sq(variant)
+    if sq is None:
+        return None
+    secs = kernel_ms * 1e-3
+    lane = sq["valu_lane_instr_per_node"] * NX * NY / secs
+    fp64 = sq["fp64_flops_per_node"] * NX * NY / secs / 1e12
+    return {"bound": "alu", "achieved": round(lane / 1e12, 3), "peak": round(VALU_LANE_OPS_PEAK / 1e12, 3),
+            "unit": "T VALU lane-instructions/s", "frac": round(lane / VALU_LANE_OPS_PEAK, 4),
+            "fp64_TFLOPs": round(fp64, 2), "fp64_frac": round(fp64 / FP64_VECTOR_PEAK_TFLOPS, 4),
+            "per_node": {k: v for k, v in sq.items() if k not in ("counters", "kernel")}}
+
+
 def make_inputs(T):
     rho_c, T_c, _ = T.eos_critical()
     rv, rl, _ = T.eos_coexistence(0.8 * T_c)
@@ -712,6 +748,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(head["achieved_GBs"], 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(head["frac_hbm"], 4), "traffic": traffic},
+        "roofline_valu": valu_roofline(head_key, head["kernel_ms"]),
         "variants": {k: {"mlups": round(v["mlups"], 1), "GBs": round(v["achieved_GBs"], 1),
                          "status": v["status"],
                          "frac_hbm": round(v["frac_hbm"], 4),
