@@ -1,0 +1,140 @@
+"""Full-size parity against goldens the FP64 oracle wrote
+(tests/golden/make_full_size.py, which calls only oracle/ and the seeded
+input generators).
+
+- 1024 x 2048 D2Q9 after 1000 steps, both gravity forms: a fixed sample of
+  1280 nodes (rows across the walls, the interface and the bulk) for rho, u,
+  T and the normal pressure, and the per-row sums of rho and T of every row.
+- 256^3 D3Q19 after 100 steps, both forms, on the full lattice (so that the
+  form-2 mean density is the lattice's own): 2816 sampled nodes and the
+  per-plane sums of rho and T.
+- Config-3 columns (seed 3), the shortest first, run to max|u| < 1e-9: the
+  statuses and stopping levels of every column the oracle tried, identical,
+  and the end profiles of at least 64 converged columns.
+
+FP64 bar: 1e-12 relative (pressures on the a rho^2 scale, velocities 1e-14
+absolute).  Inputs are rebuilt from the scalars stored with the goldens, so
+both sides start from the same bits.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+TOL = 1e-12
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+
+    import paper_2301_12869_amd as T
+
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible MI355X")
+    T.load_library()
+    return T
+
+
+def _golden(name):
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        pytest.fail(f"{name} is missing: run tests/golden/make_full_size.py")
+    return np.load(path, allow_pickle=False)
+
+
+def _rel(a, b, scale=None):
+    return float(np.abs(a - b).max() / (scale if scale is not None else np.abs(b).max()))
+
+
+@pytest.mark.parametrize("form", [1, 2])
+def test_d2q9_1024x2048_after_1000_steps(T, form):
+    g = _golden("c2_d2q9_1024x2048_1000_steps.npz")
+    nx, ny = 1024, 2048
+    rl, rv, T_c = float(g["rho_l"]), float(g["rho_v"]), float(g["T_c"])
+    rho0 = W.layered_density((ny, nx), 64, rl, rv, 1e-3, seed=2)
+    T0 = W.wall_temperature_field((ny, nx), 0.8 * T_c, 0.9 * T_c, 0.8 * T_c)
+    _log(f"case d2q9 1024x2048 form {form}, {int(g['steps'])} steps against the oracle's golden")
+    lat = T.Lattice(T.make_params(T.D2Q9, nx=nx, ny=ny, walls=True, gravity_form=form, g=1e-5))
+    lat.set_state(rho0, T0)
+    lat.step(int(g["steps"]))
+    out = {k: lat.read(k).reshape(ny, nx) for k in ("rho", "ux", "uy", "T", "p_nn")}
+    lat.close()
+    sel = np.ix_(g["rows"], g["cols"])
+    assert _rel(out["rho"][sel], g[f"form{form}_rho"]) < TOL
+    assert _rel(out["T"][sel], g[f"form{form}_T"]) < TOL
+    assert np.abs(out["ux"][sel] - g[f"form{form}_ux"]).max() < 1e-14
+    assert np.abs(out["uy"][sel] - g[f"form{form}_uy"]).max() < 1e-14
+    assert _rel(out["p_nn"][sel], g[f"form{form}_p_nn"], scale=0.5 * rl * rl) < TOL
+    assert _rel(out["rho"].sum(axis=1), g[f"form{form}_row_rho"]) < TOL
+    assert _rel(out["T"].sum(axis=1), g[f"form{form}_row_T"]) < TOL
+    _log(f"  rho {_rel(out['rho'][sel], g[f'form{form}_rho']):.2e}, rows "
+         f"{_rel(out['rho'].sum(axis=1), g[f'form{form}_row_rho']):.2e}")
+
+
+@pytest.mark.parametrize("form", [1, 2])
+def test_d3q19_256cubed_after_100_steps(T, form):
+    g = _golden("c4_d3q19_256cubed_100_steps.npz")
+    n = 256
+    rl, rv, T_c = float(g["rho_l"]), float(g["rho_v"]), float(g["T_c"])
+    rho0 = W.layered_density((n, n, n), 64, rl, rv, 1e-3, seed=4)
+    T0 = W.wall_temperature_field((n, n, n), 0.8 * T_c, 0.9 * T_c, 0.8 * T_c)
+    _log(f"case d3q19 256^3 form {form}, {int(g['steps'])} steps against the oracle's golden")
+    lat = T.Lattice(T.make_params(T.D3Q19, nx=n, ny=n, nz=n, walls=True, gravity_form=form, g=1e-5))
+    lat.set_state(rho0, T0)
+    lat.step(int(g["steps"]))
+    planes, ys, xs = g["planes"], g["ys"], g["xs"]
+    for k in ("rho", "ux", "uy", "uz", "T", "p_nn"):
+        full = lat.read(k).reshape(n, n, n)
+        got = full[planes][:, ys, xs]
+        want = g[f"form{form}_{k}"]
+        if k in ("rho", "T"):
+            assert _rel(got, want) < TOL, k
+            assert _rel(full.reshape(n, n * n).sum(axis=1), g[f"form{form}_plane_{k}"]) < TOL, k
+        elif k == "p_nn":
+            assert _rel(got, want, scale=0.5 * rl * rl) < TOL
+        else:
+            assert np.abs(got - want).max() < 1e-14, k
+    lat.close()
+
+
+def test_config3_columns_to_steady_state(T):
+    g = _golden("c3_columns_seed3_to_steady.npz")
+    H = g["height"].astype(int)
+    cols = [(int(h), int(f), float(gg)) for h, f, gg in zip(H, g["form"], g["g"])]
+    Tcol = np.concatenate([np.full(h, t) for h, t in zip(H, g["T"])])
+    status, steps = g["status"], g["steps"]
+    conv = status == 0
+    assert conv.sum() >= 64
+    _log(f"case config-3 columns: {len(cols)} columns ({conv.sum()} converged in the oracle), "
+         f"heights {H.min()}..{H.max()}")
+    b = T.Batch(cols)
+    b.set_state(g["rho0"], Tcol)
+    b.set_tuning(shape=0, check_every=int(g["check_every"]))
+    res = b.run(float(g["tol"]), int(g["max_steps"]))
+    rho, Tend = b.read("rho"), b.read("T")
+    off = np.concatenate([[0], np.cumsum(H)])
+    assert np.array_equal(res["status"], status), (res["status"], status)
+    # converged and budget-bound columns stop at a check level, which must be
+    # the oracle's (a diverged column's recorded level marks where each side
+    # noticed the flag, not a check level)
+    keep = status != 1
+    assert np.array_equal(res["steps"][keep], steps[keep])
+    worst = 0.0
+    for k in np.nonzero(conv)[0]:
+        a, bb = rho[off[k]:off[k + 1]], g["rho"][off[k]:off[k + 1]]
+        worst = max(worst, _rel(a, bb))
+        assert _rel(a, bb) < TOL, k
+        assert _rel(Tend[off[k]:off[k + 1]], g["Tend"][off[k]:off[k + 1]]) < TOL, k
+    b.close()
+    _log(f"  statuses and levels identical; worst converged profile {worst:.2e}")
