@@ -1112,6 +1112,7 @@ hipError_t launch_mom(const LatticeLaunch &L)
 // multiple of 8 so that every XCD gets the same number of blocks.
 int d2q9_num_blocks(int nx, int ny, int cus, bool moments)
 {
+    if (moments) return d2q9_march_blocks(nx, ny, cus);
     const int ty = moments ? kTYm : kTY;
     const int ntiles = ((nx + kTX - 1) / kTX) * ((ny + ty - 1) / ty);
     int nb = ntiles < cus ? ntiles : cus;
@@ -1121,7 +1122,7 @@ int d2q9_num_blocks(int nx, int ny, int cus, bool moments)
 
 hipError_t d2q9_launch_step(const LatticeLaunch &L)
 {
-    if (L.moments) return L.walls ? launch_mom<true>(L) : launch_mom<false>(L);
+    if (L.moments) return d2q9_march_launch(L);
     if (L.fp32) {
         if (L.tau1) return L.walls ? launch_t<float, true, true>(L) : launch_t<float, true, false>(L);
         return L.walls ? launch_t<float, false, true>(L) : launch_t<float, false, false>(L);

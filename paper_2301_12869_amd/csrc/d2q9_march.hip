@@ -1,0 +1,497 @@
+// D2Q9 update on the moment state (every relaxation rate 1) by row marching.
+//
+// One wavefront owns a strip of at most 58 columns and a range of rows (a
+// segment).  Its 64 lanes hold the strip's columns plus three halo columns on
+// each side: lane l is column x0 - 3 + l (periodic in x).  The wavefront
+// walks the rows of its segment upwards; the step that loads row a of the
+// level-n state finishes one row of every stage of the update (Sec. III):
+//   row a     (rho, j) and T^n loaded; psi and Z(eta)           Eqs. EOS, InteractionPotential
+//   row a - 1 Shan-Chen force, gravity, u = (j + F/2)/rho        Eqs. ShanChenForce, Gravity_*, Momentum
+//   row a - 2 first Heun stage k1 = K(T^n), T~ = T^n + k1, div u Eq. Energy_Equation
+//   row a - 3 second Heun stage and T^{n+1}; tau = 1 collision with Li's forcing
+//   row a - 4 pull-streaming of the post-collision sets, Zou-He at the walls, (rho, j)^{n+1}
+// A stage reads the rows it needs below and above from registers: every
+// per-row quantity lives in a four-row ring indexed by the row modulo 4, and
+// the march is unrolled four times so that every ring index is a compile-time
+// constant (no copies between rows).  Neighbours across columns come from the
+// adjacent lanes by DPP wavefront shifts.  Nothing goes through LDS and the
+// march takes no barrier; each stencil is evaluated once per node.
+//
+// A row of a stencil field is kept as its value c, the difference of its
+// right and left neighbours d and their sum s.  The isotropic gradient and
+// Laplacian of a node (weights w_i / c_s^2 of the D2Q9 set) follow from the
+// rows below (m), at (0) and above (p):
+//   d/dx = d0/3 + (dp + dm)/12,   d/dy = (cp - cm)/3 + (sp - sm)/12,
+//   lap  = ((s0 + (cp + cm)) - 4 c0) 2/3 + ((sp + sm) - 4 c0)/6,
+// where pairs of equal neighbours are summed before 4 c0 is subtracted, so
+// the Laplacian of a uniform field is exactly zero.
+//
+// Rows below the first and above the last row of a lattice with walls hold
+// zeros (no state there); the wall rows themselves carry no force, keep
+// their temperature and receive the Zou-He reconstruction.  Without walls
+// the rows wrap.  Per-lane diagnostics (mass of level n and of the next
+// level, max |u|^2, min rho, flags) are reduced over the block and the grid
+// as in the tile kernels.
+#include <hip/hip_runtime.h>
+
+#include "lbm_common.hpp"
+#include "lbm_internal.hpp"
+
+namespace tplbm {
+
+namespace {
+
+constexpr int kHalo = 3;
+constexpr int kStrip = 64 - 2 * kHalo;  // interior columns of a wavefront
+constexpr int kNT = 256;                // four independent wavefronts per block
+constexpr int kPF = 2;                  // rows of loads in flight ahead of use
+constexpr double kW1 = 1.0 / 9.0, kW5 = 1.0 / 36.0;
+
+// lane l receives the value of lane l - 1 (the column to its left; lane 0
+// receives zero)
+__device__ __forceinline__ double from_left(double v)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x138, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x138, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+// lane l receives the value of lane l + 1 (the column to its right; lane 63
+// receives zero)
+__device__ __forceinline__ double from_right(double v)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x130, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x130, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ int wrap(int v, int n)
+{
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// Per-row quantities of one lane, four rows each (index: row & 3 relative
+// to the segment's first row).
+struct Rings {
+    double pc[4], pd[4], ps[4];                 // psi
+    double rho[4], jx[4], jy[4], Z[4];
+    double tc[4], td[4], ts[4];                 // T^n
+    double ux[4], uy[4], uxd[4], uys[4], inv[4];
+    double fx[4], fy[4], X[4];                  // force and |F_int|^2/psi^2
+    double ttc[4], ttd[4], tts[4], k1[4], dv[4];  // T~ = T^n + k1, k1, div u
+    double pull[4][9];                          // pulled sets being assembled
+    double lr[4], ljx[4], ljy[4], lT[4];        // loads in flight
+};
+
+struct Strip {
+    const double *Min;
+    double *Mout;
+    const double *Tin;
+    double *Tout;
+    size_t N;
+    int nx, ny, y0, y1, gx;
+    bool walls;  // walls at the first and last rows; periodic rows otherwise
+    bool interior;
+    double sub;
+};
+
+__device__ __forceinline__ void set_row(double v, double &c, double &d, double &s)
+{
+    const double l = from_left(v), r = from_right(v);
+    c = v;
+    d = r - l;
+    s = r + l;
+}
+
+// K(T) at a node from the three rows of the field the stage differentiates
+// (T^n for the first stage, T~ for the second), centre value t0.
+__device__ __forceinline__ double energy_rhs(const Phys &c, double cm, double dm, double sm, double t0,
+                                             double d0, double s0, double cp, double dp, double sp,
+                                             double ux, double uy, double divu, double inv, double Z)
+{
+    const double gx = d0 * (1.0 / 3.0) + (dp + dm) * (1.0 / 12.0);
+    const double gy = (cp - cm) * (1.0 / 3.0) + (sp - sm) * (1.0 / 12.0);
+    const double c4 = 4.0 * t0;
+    const double lap = ((s0 + (cp + cm)) - c4) * (2.0 / 3.0) + ((sp + sm) - c4) * (1.0 / 6.0);
+    const double adv = -(ux * gx + uy * gy);
+    const double cond = c.kappa_over_cv * inv * lap;
+    const double work = -t0 * c.R_over_cv * Z * divu;
+    return adv + cond + work;
+}
+
+// tau = 1 collision: f* = f_eq(rho, u) + F' with Li's forcing, the rest
+// population closed by mass conservation (the same expressions as the tile
+// kernels' collision).
+__device__ __forceinline__ void collide(const Phys &c, double rho, double ux, double uy, double Fx, double Fy,
+                                        double X, double fs[9])
+{
+    const double uu = ux * ux + uy * uy;
+    const double uF = ux * Fx + uy * Fy;
+    const double sx36 = c.sigma * X * (1.0 / 36.0);
+    const double r1 = kW1 * rho, r5 = kW5 * rho;
+    const double b1 = r1 * (1.0 - 1.5 * uu) - kW1 * 1.5 * uF + sx36;
+    const double b5 = r5 * (1.0 - 1.5 * uu) - kW5 * 1.5 * uF + sx36;
+    auto pair = [&](double cu, double cF, double wr, double wi, double base, double &fp, double &fm) {
+        const double E = base + 4.5 * cu * (wr * cu + wi * cF);
+        const double O = 3.0 * wr * cu + 1.5 * wi * cF;
+        fp = E + O;
+        fm = E - O;
+    };
+    pair(ux, Fx, r1, kW1, b1, fs[1], fs[3]);
+    pair(uy, Fy, r1, kW1, b1, fs[2], fs[4]);
+    pair(ux + uy, Fx + Fy, r5, kW5, b5, fs[5], fs[7]);
+    pair(uy - ux, Fy - Fx, r5, kW5, b5, fs[6], fs[8]);
+    const double rest = ((fs[1] + fs[2]) + (fs[3] + fs[4])) + ((fs[5] + fs[6]) + (fs[7] + fs[8]));
+    fs[0] = rho - rest;
+}
+
+// Next level's mass of a post-collision set: a population moving into a
+// wall layer is counted twice by that wall's reconstruction, one leaving
+// through a wall not at all.
+__device__ __forceinline__ double next_mass(const double v[9], int gy, int ny, bool walls)
+{
+    double nm = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7])) + v[8];
+    if (walls) {
+        const double down = (v[4] + v[7]) + v[8], up = (v[2] + v[5]) + v[6];
+        if (gy == 0) nm -= down;
+        if (gy == 1) nm += down;
+        if (gy == ny - 2) nm += up;
+        if (gy == ny - 1) nm -= up;
+    }
+    return nm;
+}
+
+// Issue the loads of row r into ring slot S (zeros beyond a wall and past
+// the last row the segment reads: every path writes the slot, so that no
+// ring value has to outlive its row).
+template <bool EDGE, int S>
+__device__ __forceinline__ void issue_row(Rings &R, const Strip &A, int r)
+{
+    double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+    if (!EDGE) {
+        // interior segment: every row it reads exists; the last steps
+        // re-read its last row instead of rows it does not need
+        const size_t row = (size_t)min(r, A.y1 + kHalo - 1) * A.nx;
+        v0 = (A.Min + row)[A.gx];
+        v1 = (A.Min + A.N + row)[A.gx];
+        v2 = (A.Min + 2 * A.N + row)[A.gx];
+        v3 = (A.Tin + row)[A.gx];
+    } else if (r < A.y1 + kHalo && (!A.walls || (r >= 0 && r < A.ny))) {
+        const int gy = A.walls ? r : wrap(r, A.ny);
+        const size_t row = (size_t)gy * A.nx;
+        v0 = (A.Min + row)[A.gx];
+        v1 = (A.Min + A.N + row)[A.gx];
+        v2 = (A.Min + 2 * A.N + row)[A.gx];
+        v3 = (A.Tin + row)[A.gx];
+    }
+    // one assignment per slot on every path (stores of the two paths that
+    // the optimiser sank into one would defeat the rings' promotion to
+    // registers)
+    R.lr[S] = v0;
+    R.ljx[S] = v1;
+    R.ljy[S] = v2;
+    R.lT[S] = v3;
+}
+
+// Stages of a march step (a compile-time set: the first and last steps of a
+// segment run only the stages whose rows the segment needs).
+constexpr int kLoad = 1, kForce = 2, kHeun1 = 4, kCollide = 8, kHeun2 = 16, kPull = 32;
+constexpr int kAll = 63;
+
+// One step of the march: loads of row a + kPF, then the stages in PH.  J is
+// the ring slot of row a.  Every stage writes its ring slots on every path;
+// only stores and diagnostics depend on run-time conditions.
+template <bool EDGE, int J, int PH>
+__device__ __forceinline__ void march_step(Rings &R, const Strip &A, const Phys &c, Partial &part, int a)
+{
+    constexpr int S0 = J & 3, S1 = (J + 3) & 3, S2 = (J + 2) & 3, S3 = (J + 1) & 3;  // rows a, a-1, a-2, a-3
+    constexpr int S4 = J & 3;                                                       // row a-4
+    if (PH & kLoad) issue_row<EDGE, (J + kPF) & 3>(R, A, a + kPF);
+
+    // ---- row a: psi, Z and the stencil rows of psi and T^n ----
+    if (PH & kLoad) {
+        const double rho = R.lr[S0], T = R.lT[S0];
+        double Z = 0.0, psi = 0.0;
+        if (!EDGE || !A.walls || (a >= 0 && a < A.ny)) psi = psi_and_Z(c, rho, T, Z);
+        R.rho[S0] = rho;
+        R.jx[S0] = R.ljx[S0];
+        R.jy[S0] = R.ljy[S0];
+        R.Z[S0] = Z;
+        set_row(psi, R.pc[S0], R.pd[S0], R.ps[S0]);
+        set_row(T, R.tc[S0], R.td[S0], R.ts[S0]);
+        if (a >= A.y0 && a < A.y1 && A.interior) {
+            unsigned fl = 0u;
+            if (!(rho > 0.0)) fl |= kFlagRho;
+            if (c.eos == 0 && c.b_quarter * rho >= 1.0) fl |= kFlagEta;
+            if (psi != psi) fl |= kFlagPsi;
+            part.flags |= fl;
+        }
+    }
+
+    __builtin_amdgcn_sched_barrier(0);
+    // ---- row a - 1: force and force-corrected velocity ----
+    const int b = a - 1;
+    if (PH & kForce) {
+        const bool valid = !EDGE || !A.walls || (b >= 0 && b < A.ny);
+        const bool wall = EDGE && A.walls && (b == 0 || b == A.ny - 1);
+        double Fx = 0.0, Fy = 0.0, X = 0.0, inv = 0.0, ux = 0.0, uy = 0.0;
+        if (valid && !wall) {
+            const double sx = R.pd[S1] * (1.0 / 3.0) + (R.pd[S0] + R.pd[S2]) * (1.0 / 12.0);
+            const double sy = (R.pc[S0] - R.pc[S2]) * (1.0 / 3.0) + (R.ps[S0] - R.ps[S2]) * (1.0 / 12.0);
+            const double mg = -c.G * R.pc[S1];
+            Fx = mg * sx;
+            Fy = mg * sy + gravity_force(R.rho[S1], A.sub, c.g);
+            X = c.G2 * (sx * sx + sy * sy);
+        }
+        if (valid) {
+            inv = rcp_pos(R.rho[S1]);
+            ux = (R.jx[S1] + 0.5 * Fx) * inv;
+            uy = (R.jy[S1] + 0.5 * Fy) * inv;
+        }
+        R.fx[S1] = Fx;
+        R.fy[S1] = Fy;
+        R.X[S1] = X;
+        R.inv[S1] = inv;
+        R.ux[S1] = ux;
+        R.uy[S1] = uy;
+        const double uxl = from_left(ux), uxr = from_right(ux);
+        const double uyl = from_left(uy), uyr = from_right(uy);
+        R.uxd[S1] = uxr - uxl;
+        R.uys[S1] = uyr + uyl;
+    }
+
+    __builtin_amdgcn_sched_barrier(0);
+    // ---- row a - 2: first Heun stage ----
+    const int r2 = a - 2;
+    if (PH & kHeun1) {
+        double k1 = 0.0, dv = 0.0, Tt = R.tc[S2] + 0.0;
+        if (!EDGE || !A.walls || (r2 > 0 && r2 < A.ny - 1)) {
+            // rows r2 - 1, r2, r2 + 1 sit in slots S3, S2, S1
+            dv = (R.uxd[S2] * (1.0 / 3.0) + (R.uxd[S1] + R.uxd[S3]) * (1.0 / 12.0)) +
+                 ((R.uy[S1] - R.uy[S3]) * (1.0 / 3.0) + (R.uys[S1] - R.uys[S3]) * (1.0 / 12.0));
+            k1 = energy_rhs(c, R.tc[S3], R.td[S3], R.ts[S3], R.tc[S2], R.td[S2], R.ts[S2], R.tc[S1], R.td[S1],
+                            R.ts[S1], R.ux[S2], R.uy[S2], dv, R.inv[S2], R.Z[S2]);
+            Tt = R.tc[S2] + k1;
+        }
+        R.k1[S2] = k1;
+        R.dv[S2] = dv;
+        set_row(Tt, R.ttc[S2], R.ttd[S2], R.tts[S2]);
+    }
+
+    __builtin_amdgcn_sched_barrier(0);
+    // ---- row a - 3: second Heun stage, T^{n+1}, collision ----
+    const int q = a - 3;
+    if (PH & kCollide) {
+        const bool valid = !EDGE || !A.walls || (q >= 0 && q < A.ny);
+        constexpr bool own = (PH & kHeun2) != 0;  // row q is one of the segment's own rows
+        const double rho = R.rho[S3], ux = R.ux[S3], uy = R.uy[S3];
+        if (own) {
+            const bool wall = EDGE && A.walls && (q == 0 || q == A.ny - 1);
+            const double T = R.tc[S3];
+            double Tn = T;
+            if (!wall) {
+                // T~ rows q - 1, q, q + 1 sit in slots S4, S3, S2
+                const double k2 = energy_rhs(c, R.ttc[S4], R.ttd[S4], R.tts[S4], R.ttc[S3], R.ttd[S3], R.tts[S3],
+                                             R.ttc[S2], R.ttd[S2], R.tts[S2], ux, uy, R.dv[S3], R.inv[S3],
+                                             R.Z[S3]);
+                Tn = T + 0.5 * (R.k1[S3] + k2);
+            }
+            if (A.interior) {
+                (A.Tout + (size_t)q * A.nx)[A.gx] = Tn;
+                part.mass_n += rho;
+                part.umax = fmax(part.umax, ux * ux + uy * uy);
+                part.rmin = fmin(part.rmin, rho);
+                if (rho != rho || ux != ux || uy != uy || Tn != Tn) part.flags |= kFlagNaN;
+            }
+        }
+        double fs[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) fs[i] = 0.0;  // rows beyond a wall send nothing
+        if (valid) collide(c, rho, ux, uy, R.fx[S3], R.fy[S3], R.X[S3], fs);
+        if (own && A.interior) {
+            const double nm = next_mass(fs, q, A.ny, EDGE && A.walls);
+            part.mass_next += nm;
+            if (nm != nm) part.flags |= kFlagNaN;
+        }
+        // f_i(x) = f*_i(x - c_i): x-components +1 come from the left lane,
+        // -1 from the right lane; y-components +1 go to row q + 1, -1 to q - 1
+        R.pull[S2][2] = fs[2];
+        R.pull[S2][5] = from_left(fs[5]);
+        R.pull[S2][6] = from_right(fs[6]);
+        R.pull[S3][0] = fs[0];
+        R.pull[S3][1] = from_left(fs[1]);
+        R.pull[S3][3] = from_right(fs[3]);
+        R.pull[S4][4] = fs[4];
+        R.pull[S4][7] = from_right(fs[7]);
+        R.pull[S4][8] = from_left(fs[8]);
+    }
+
+    __builtin_amdgcn_sched_barrier(0);
+    // ---- row a - 4: moments of the pulled set ----
+    const int p = a - 4;
+    if (PH & kPull) {
+        double f[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[i] = R.pull[S4][i];
+        const bool bot = EDGE && A.walls && p == 0, top = EDGE && A.walls && p == A.ny - 1;
+        if (bot) {  // unknowns 2, 5, 6
+            const double d = f[1] - f[3];
+            f[2] = f[4];
+            f[5] = f[7] - 0.5 * d;
+            f[6] = f[8] + 0.5 * d;
+        }
+        if (top) {  // unknowns 4, 7, 8
+            const double d = f[1] - f[3];
+            f[4] = f[2];
+            f[7] = f[5] + 0.5 * d;
+            f[8] = f[6] - 0.5 * d;
+        }
+        const double rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+        const double jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+        const double jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+        if (A.interior) {
+            const size_t row = (size_t)p * A.nx;
+            (A.Mout + row)[A.gx] = rho;
+            (A.Mout + A.N + row)[A.gx] = jx;
+            (A.Mout + 2 * A.N + row)[A.gx] = jy;
+        }
+    }
+    // the scheduler keeps the stages (and the steps) in order: interleaving
+    // them would stretch the rings' live ranges past the register budget
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// The march over one segment.
+template <bool EDGE>
+__device__ __forceinline__ void march(const Strip &A, const Phys &c, Partial &part)
+{
+    // Step a loads row a and finishes rows a - 1 .. a - 4.  The segment
+    // [y0, y1) needs psi on rows y0 - 3 .. y1 + 2, u on y0 - 2 .. y1 + 1,
+    // the first Heun stage and the collision on y0 - 1 .. y1, and the
+    // rest on its own rows: seven entry steps, y1 - y0 - 1 steps with
+    // every stage, and a final collision and pull.
+    Rings R;
+    const int a0 = A.y0 - kHalo;
+    issue_row<EDGE, 0>(R, A, a0);
+    issue_row<EDGE, 1>(R, A, a0 + 1);
+    march_step<EDGE, 0, kLoad>(R, A, c, part, a0);
+    march_step<EDGE, 1, kLoad>(R, A, c, part, a0 + 1);
+    march_step<EDGE, 2, kLoad | kForce>(R, A, c, part, a0 + 2);
+    march_step<EDGE, 3, kLoad | kForce>(R, A, c, part, a0 + 3);
+    march_step<EDGE, 0, kLoad | kForce | kHeun1>(R, A, c, part, a0 + 4);
+    march_step<EDGE, 1, kLoad | kForce | kHeun1 | kCollide>(R, A, c, part, a0 + 5);
+    march_step<EDGE, 2, kAll & ~kPull>(R, A, c, part, a0 + 6);
+    int a = a0 + 7;
+    const int last = A.y1 + 2;  // last step with every stage
+    for (; a + 3 <= last; a += 4) {
+        march_step<EDGE, 3, kAll>(R, A, c, part, a);
+        march_step<EDGE, 0, kAll>(R, A, c, part, a + 1);
+        march_step<EDGE, 1, kAll>(R, A, c, part, a + 2);
+        march_step<EDGE, 2, kAll>(R, A, c, part, a + 3);
+    }
+    constexpr int kLast = kCollide | kPull;
+    switch (last + 1 - a) {
+    case 0:
+        march_step<EDGE, 3, kLast>(R, A, c, part, a);
+        break;
+    case 1:
+        march_step<EDGE, 3, kAll>(R, A, c, part, a);
+        march_step<EDGE, 0, kLast>(R, A, c, part, a + 1);
+        break;
+    case 2:
+        march_step<EDGE, 3, kAll>(R, A, c, part, a);
+        march_step<EDGE, 0, kAll>(R, A, c, part, a + 1);
+        march_step<EDGE, 1, kLast>(R, A, c, part, a + 2);
+        break;
+    default:
+        march_step<EDGE, 3, kAll>(R, A, c, part, a);
+        march_step<EDGE, 0, kAll>(R, A, c, part, a + 1);
+        march_step<EDGE, 1, kAll>(R, A, c, part, a + 2);
+        march_step<EDGE, 2, kLast>(R, A, c, part, a + 3);
+        break;
+    }
+}
+
+__global__ __launch_bounds__(kNT, 2) void d2q9_march_mom(const double *__restrict__ Min, double *__restrict__ Mout,
+                                                         const double *__restrict__ Tin, double *__restrict__ Tout,
+                                                         Phys c, int nx, int ny, int walls, int nstrips, int nseg, int spb,
+                                                         double *__restrict__ partials, StepState *__restrict__ st,
+                                                         int64_t step)
+{
+    __shared__ double s_red[4 * kNT / 64];
+    __shared__ unsigned s_ured[kNT / 64];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // blocks are dealt to the eight XCDs in turn: XCD k takes the k-th band
+    // of segments, so that neighbouring strips and segments share its L2
+    const int band = blockIdx.x & 7;
+    const int i = (int)(blockIdx.x >> 3) * (kNT / 64) + wv;
+    const int sib = i / nstrips, strip = i - sib * nstrips;
+    const int seg = band * spb + sib;
+
+    Partial part = {0.0, 0.0, 0.0, 1e300, 0u};
+    if (sib < spb && seg < nseg) {
+        Strip A;
+        A.Min = Min;
+        A.Mout = Mout;
+        A.Tin = Tin;
+        A.Tout = Tout;
+        A.N = (size_t)nx * ny;
+        A.nx = nx;
+        A.ny = ny;
+        A.walls = walls != 0;
+        A.y0 = (int)((int64_t)seg * ny / nseg);
+        A.y1 = (int)((int64_t)(seg + 1) * ny / nseg);
+        const int x0 = (int)((int64_t)strip * nx / nstrips);
+        const int x1 = (int)((int64_t)(strip + 1) * nx / nstrips);
+        A.gx = wrap(x0 - kHalo + lane, nx);
+        A.interior = lane >= kHalo && lane < kHalo + (x1 - x0);
+        A.sub = gravity_sub(c.form, st->mean[step & 1], c.rho_v);
+
+        // segments whose rows all exist and hold no wall row take the
+        // variant without the checks
+        if (A.y0 >= kHalo && A.y1 <= ny - kHalo)
+            march<false>(A, c, part);
+        else
+            march<true>(A, c, part);
+    }
+    part = block_reduce<kNT>(part, s_red, s_ured);
+    finish_launch<kNT>(part, partials, st, step, (int)((step + 1) & 1), 1.0 / ((double)nx * ny), s_red, s_ured);
+}
+
+struct MarchGrid {
+    int nstrips, nseg, spb, nblocks;
+};
+
+// Strips of at most 58 columns; segments so that the grid holds about two
+// wavefronts per SIMD (eight per compute unit), a multiple of 8 once there
+// are at least 8, dealt to the XCDs in bands of spb segments.
+MarchGrid march_grid(int nx, int ny, int cus)
+{
+    MarchGrid g;
+    g.nstrips = (nx + kStrip - 1) / kStrip;
+    const long target = 8L * cus;
+    long nseg = target / g.nstrips;
+    if (nseg < 1) nseg = 1;
+    if (nseg > ny) nseg = ny;
+    if (nseg >= 8) nseg -= nseg % 8;
+    g.nseg = (int)nseg;
+    g.spb = (g.nseg + 7) / 8;
+    g.nblocks = 8 * ((g.spb * g.nstrips + kNT / 64 - 1) / (kNT / 64));
+    return g;
+}
+
+}  // namespace
+
+int d2q9_march_blocks(int nx, int ny, int cus) { return march_grid(nx, ny, cus).nblocks; }
+
+hipError_t d2q9_march_launch(const LatticeLaunch &L)
+{
+    const MarchGrid g = march_grid(L.nx, L.ny, L.resident);
+    hipLaunchKernelGGL(d2q9_march_mom, dim3(g.nblocks), dim3(kNT), 0, L.stream, (const double *)L.fin,
+                       (double *)L.fout, L.Tin, L.Tout, L.phys, L.nx, L.ny, L.walls ? 1 : 0, g.nstrips, g.nseg,
+                       g.spb, L.partials, L.st, L.step);
+    return hipGetLastError();
+}
+
+}  // namespace tplbm

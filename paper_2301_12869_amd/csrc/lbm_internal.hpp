@@ -51,6 +51,9 @@ hipError_t d3q19_launch_readout(const LatticeLaunch &L, int field, double *M, do
 // psi plane of a level-0 moment state M (rho and j set) from rho and L.Tin
 hipError_t d3q19_launch_psi_init(const LatticeLaunch &L, double *M);
 hipError_t d2q9_launch_step(const LatticeLaunch &L);
+// moment-state D2Q9 update by row marching (d2q9_march.hip)
+int d2q9_march_blocks(int nx, int ny, int cus);
+hipError_t d2q9_march_launch(const LatticeLaunch &L);
 hipError_t d2q9_launch_readout(const LatticeLaunch &L, int field, double *scratch, double *out);
 
 }  // namespace tplbm
