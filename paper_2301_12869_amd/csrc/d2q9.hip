@@ -126,8 +126,7 @@ __device__ __forceinline__ int wrapi(int v, int n)
 }
 
 // Zou-He reconstruction (zero wall velocity) of the populations a wall node
-// does not receive, then density and momentum of the pulled set.  Both the
-// population and the moment kernel take their level's (rho, j) from here.
+// does not receive, then density and momentum of the pulled set.
 __device__ __forceinline__ void pulled_moments(double f[9], bool bot, bool top, double &rho, double &jx,
                                                double &jy)
 {
@@ -624,316 +623,6 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step(const S *__res
 }
 
 // ---------------------------------------------------------------------------
-// Moment-state update (every relaxation time 1, FP64).  With all rates 1 the
-// post-collision populations are a closed function of the node's density,
-// force-corrected velocity and force (collide_tau1), so the state between
-// launches can be the level's density and momentum instead of the nine
-// populations: the planes rho, j_x, j_y of M (and T^n).  One launch, per
-// TX x TY tile:
-//   phase 1, tile + 3: load rho, j, T; psi                       -> LDS
-//   phases 2, 3: as in the population kernel (force, velocity; k1), and
-//            T~ = T^n + k1 and div u kept in LDS for the second stage
-//   phase 4a, tile: T^{n+1}, stored; statistics of level n
-//   phase 4b, tile + 1 (after a barrier, so that the energy update's LDS
-//            fields are free): post-collision set f*(y) of every node,
-//            directions 0..4 written straight to five LDS planes, 5..8 kept
-//            in registers; the next level's mass contribution of the tile
-//            nodes
-//   phase 4c: each tile node x pulls f*_i(x - c_i) from the planes, then
-//            directions 5..8 go through the same planes
-//   phase 4d, tile: Zou-He and the moments of the pulled set -> M^{n+1}.
-// Phases 4b-4d evaluate the same source expressions, in the same order, as
-// the population kernel's collision, store, pull and moment sums (shared
-// functions), so the two states agree to rounding: the compiler may fuse
-// multiply-adds in different places in the two kernels, and the blocks sum
-// the next level's mass over another tiling.
-// ---------------------------------------------------------------------------
-template <bool WALLS, int TX, int TY, int NT, int MIN_WAVES_PER_EU>
-__global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step_mom(const double *__restrict__ Min,
-                                                             double *__restrict__ Mout,
-                                                             const double *__restrict__ Tin,
-                                                             double *__restrict__ Tout, Phys c,
-                                                             int nx, int ny, int tiles_x, int ntiles,
-                                                             double *__restrict__ partials,
-                                                             StepState *__restrict__ st, int64_t step)
-{
-    constexpr int W3 = TX + 6, H3 = TY + 6;
-    constexpr int W2 = TX + 4, H2 = TY + 4;
-    constexpr int W1 = TX + 2, H1 = TY + 2;
-    constexpr int R3N = H3 * W3, R2N = H2 * W2, R1N = H1 * W1, RTN = TX * TY;
-    constexpr int NS3 = (R3N + NT - 1) / NT, NS1 = (R1N + NT - 1) / NT, NST = (RTN + NT - 1) / NT;
-    static_assert(R1N <= R2N && RTN <= R2N, "exchange planes must fit the tile + 2 arrays");
-    __shared__ double s_psi[R3N];
-    __shared__ double s_rho[R2N];
-    __shared__ double s_T[R2N];
-    __shared__ double s_ux[R2N];
-    __shared__ double s_uy[R2N];
-    __shared__ double s_Z[R2N];
-    __shared__ double s_k1[R1N];   // first Heun stage K(T^n)
-    __shared__ double s_Tt[R1N];   // T~ = T^n + k1
-    __shared__ double s_div[R1N];  // div u, for both Heun stages
-    __shared__ double s_red[4 * NT / 64];
-    __shared__ unsigned s_ured[NT / 64];
-    constexpr int NP = 5;          // exchange planes, free once T^{n+1} is stored
-    double *const plane[NP] = {s_k1, s_Tt, s_div, s_T, s_Z};
-    constexpr int kCx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-    constexpr int kCy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-
-    const int tid = threadIdx.x;
-    const size_t N = (size_t)nx * ny;
-    const double mean = st->mean[step & 1];
-    const double sub = gravity_sub(c.form, mean, c.rho_v);
-
-    const int nb = gridDim.x;
-    const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
-    const int per_xcd_blocks = nb >> 3;
-    const int tiles_per_xcd = (ntiles + 7) >> 3;
-    const int t_begin = xcd * tiles_per_xcd;
-    const int t_end = min(ntiles, t_begin + tiles_per_xcd);
-
-    // global column / row of a region coordinate (periodic wrap; rows beyond
-    // a wall are reported invalid)
-    auto col_of = [&](int x) { return (x >= 0 && x < nx) ? x : wrapi(x, nx); };
-    auto row_of = [&](int y, bool &valid) {
-        if (WALLS) {
-            valid = (y >= 0 && y < ny);
-            return valid ? y : 0;
-        }
-        valid = true;
-        return (y >= 0 && y < ny) ? y : wrapi(y, ny);
-    };
-
-    Partial part = {0.0, 0.0, 0.0, 1e300, 0u};
-    for (int t = t_begin + slot; t < t_end; t += per_xcd_blocks) {
-        const int x0 = (t % tiles_x) * TX, y0 = (t / tiles_x) * TY;
-
-        // ---- phase 1: rho, j, T, psi on tile + 3 ----
-        double lr[NS3], ljx[NS3], ljy[NS3], lT[NS3];
-#pragma unroll
-        for (int k = 0; k < NS3; ++k) {
-            const int r = tid + k * NT;
-            lr[k] = ljx[k] = ljy[k] = lT[k] = 0.0;
-            if (r < R3N) {
-                const int ry = r / W3, rx = r - ry * W3;
-                bool valid;
-                const int gy = row_of(y0 + ry - 3, valid);
-                if (valid) {
-                    const size_t g = (size_t)gy * nx + col_of(x0 + rx - 3);
-                    lr[k] = Min[g];
-                    ljx[k] = Min[N + g];
-                    ljy[k] = Min[2 * N + g];
-                    lT[k] = Tin[g];
-                }
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < NS3; ++k) {
-            const int r = tid + k * NT;
-            if (r < R3N) {
-                const int ry = r / W3, rx = r - ry * W3;
-                bool valid;
-                row_of(y0 + ry - 3, valid);
-                double Z = 0.0, psi = 0.0;
-                if (valid) psi = psi_and_Z(c, lr[k], lT[k], Z);
-                s_psi[r] = psi;
-                if (rx >= 1 && rx < W3 - 1 && ry >= 1 && ry < H3 - 1) {
-                    const int qi = (ry - 1) * W2 + (rx - 1);
-                    s_rho[qi] = lr[k];
-                    s_T[qi] = lT[k];
-                    s_ux[qi] = ljx[k];
-                    s_uy[qi] = ljy[k];
-                    s_Z[qi] = Z;
-                }
-            }
-        }
-        __syncthreads();
-
-        // ---- phase 2: force and force-corrected velocity on tile + 2 ----
-        for (int r = tid; r < R2N; r += NT) {
-            const int ry = r / W2, rx = r - ry * W2;
-            const int gy = y0 + ry - 2;
-            bool valid = true, wall = false;
-            if (WALLS) {
-                valid = (gy >= 0 && gy < ny);
-                wall = (gy == 0 || gy == ny - 1);
-            }
-            if (!valid) continue;
-            const double rho = s_rho[r];
-            double Fx, Fy, X;
-            node_force(c, s_psi, (ry + 1) * W3 + (rx + 1), W3, rho, sub, wall, Fx, Fy, X);
-            const double inv = rcp_pos(rho);
-            s_ux[r] = (s_ux[r] + 0.5 * Fx) * inv;
-            s_uy[r] = (s_uy[r] + 0.5 * Fy) * inv;
-        }
-        __syncthreads();
-
-        // ---- phase 3: first Heun stage on tile + 1; T~ and div u kept ----
-        for (int r = tid; r < R1N; r += NT) {
-            const int ry = r / W1, rx = r - ry * W1;
-            const int gy = y0 + ry - 1;
-            const int c2 = (ry + 1) * W2 + (rx + 1);
-            if (WALLS && (gy <= 0 || gy >= ny - 1)) {
-                // Dirichlet walls (and nodes beyond them): T~ = T
-                s_k1[r] = 0.0;
-                s_Tt[r] = s_T[c2] + 0.0;
-                s_div[r] = 0.0;
-                continue;
-            }
-            const double divu = divergence(s_ux, s_uy, c2, W2);
-            Stencil tt;
-            tt.load(s_T, c2, W2);
-            const double k1 = energy_rhs(c, tt, s_T[c2], s_ux[c2], s_uy[c2], divu, rcp_pos(s_rho[c2]), s_Z[c2]);
-            s_k1[r] = k1;
-            s_Tt[r] = s_T[c2] + k1;
-            s_div[r] = divu;
-        }
-        __syncthreads();
-
-        // ---- phase 4a: second Heun stage and T^{n+1}; level-n statistics ----
-        for (int r = tid; r < RTN; r += NT) {
-            const int ry = r / TX, rx = r - ry * TX;
-            const int gx = x0 + rx, gy = y0 + ry;
-            if (gx >= nx || gy >= ny) continue;
-            const int c2 = (ry + 2) * W2 + (rx + 2);
-            const int c1 = (ry + 1) * W1 + (rx + 1);
-            const int c3 = (ry + 3) * W3 + (rx + 3);
-            const bool wall = WALLS && (gy == 0 || gy == ny - 1);
-            const double rho = s_rho[c2], ux = s_ux[c2], uy = s_uy[c2], T = s_T[c2];
-            double Tn = T;
-            if (!wall) {
-                Stencil tt;  // T~ = T^n + k1 at the node and its neighbours
-                tt.load(s_Tt, c1, W1);
-                const double k1 = s_k1[c1];
-                const double k2 = energy_rhs(c, tt, s_Tt[c1], ux, uy, s_div[c1], rcp_pos(rho), s_Z[c2]);
-                Tn = T + 0.5 * (k1 + k2);
-            }
-            Tout[(size_t)gy * nx + gx] = Tn;
-            part.mass_n += rho;
-            part.umax = fmax(part.umax, ux * ux + uy * uy);
-            part.rmin = fmin(part.rmin, rho);
-            unsigned fl = 0u;
-            if (!(rho > 0.0)) fl |= kFlagRho;
-            if (c.eos == 0 && c.b_quarter * rho >= 1.0) fl |= kFlagEta;
-            if (s_psi[c3] != s_psi[c3]) fl |= kFlagPsi;
-            if (rho != rho || ux != ux || uy != uy || Tn != Tn) fl |= kFlagNaN;
-            part.flags |= fl;
-        }
-
-        __syncthreads();  // every read of s_k1, s_Tt, s_div, s_T, s_Z is done: they become exchange planes
-
-        // ---- phase 4b: post-collision sets of tile + 1; populations 0..4 go
-        // straight to the exchange planes, 5..8 stay in registers ----
-        double fsr[NS1][9 - NP];
-        double nm_own[NS1];
-#pragma unroll
-        for (int k = 0; k < NS1; ++k) {
-            const int r = tid + k * NT;
-#pragma unroll
-            for (int i = 0; i < 9 - NP; ++i) fsr[k][i] = 0.0;
-            nm_own[k] = 0.0;
-            if (r < R1N) {
-                const int ry = r / W1, rx = r - ry * W1;
-                const int gy = y0 + ry - 1;
-                bool valid = true, wall = false;
-                if (WALLS) {
-                    valid = (gy >= 0 && gy < ny);
-                    wall = (gy == 0 || gy == ny - 1);
-                }
-                double fs[9];
-#pragma unroll
-                for (int i = 0; i < 9; ++i) fs[i] = 0.0;  // nodes beyond a wall send nothing
-                if (valid) {
-                    const int c2 = (ry + 1) * W2 + (rx + 1);
-                    const int c3 = (ry + 2) * W3 + (rx + 2);
-                    const double rho = s_rho[c2];
-                    double Fx, Fy, X;
-                    node_force(c, s_psi, c3, W3, rho, sub, wall, Fx, Fy, X);
-                    collide_tau1(c, rho, s_ux[c2], s_uy[c2], Fx, Fy, X, fs);
-                    // the next level's mass of the tile nodes (periodic y
-                    // wraps rows: only nodes of the tile itself count)
-                    const int ty = ry - 1, tx = rx - 1;
-                    if (ty >= 0 && ty < TY && tx >= 0 && tx < TX && x0 + tx < nx && y0 + ty < ny)
-                        nm_own[k] = next_mass<WALLS>(fs, y0 + ty, ny);
-                }
-#pragma unroll
-                for (int j = 0; j < NP; ++j) plane[j][r] = fs[j];
-#pragma unroll
-                for (int i = 0; i < 9 - NP; ++i) fsr[k][i] = fs[NP + i];
-            }
-        }
-        __syncthreads();  // every read of s_rho, s_ux, s_uy is done; planes hold populations 0..4
-
-        // the tile nodes' mass contributions, accumulated below in the tile
-        // loop's node order (s_rho is free now)
-#pragma unroll
-        for (int k = 0; k < NS1; ++k) {
-            const int r = tid + k * NT;
-            if (r < R1N) {
-                const int ry = r / W1, rx = r - ry * W1;
-                const int ty = ry - 1, tx = rx - 1;
-                if (ty >= 0 && ty < TY && tx >= 0 && tx < TX) s_rho[ty * TX + tx] = nm_own[k];
-            }
-        }
-
-        // ---- phase 4c: pull, in two rounds of up to five planes ----
-        double fp[NST][9];
-#pragma unroll
-        for (int i0 = 0; i0 < 9; i0 += NP) {
-            if (i0 > 0) {
-#pragma unroll
-                for (int k = 0; k < NS1; ++k) {
-                    const int r = tid + k * NT;
-                    if (r < R1N) {
-#pragma unroll
-                        for (int j = 0; j < NP; ++j)
-                            if (i0 + j < 9) plane[j][r] = fsr[k][i0 + j - NP];
-                    }
-                }
-                __syncthreads();
-            }
-#pragma unroll
-            for (int k = 0; k < NST; ++k) {
-                const int r = tid + k * NT;
-                if (r < RTN) {
-                    const int ry = r / TX, rx = r - ry * TX;
-                    const int d1 = (ry + 1) * W1 + (rx + 1);
-#pragma unroll
-                    for (int j = 0; j < NP; ++j) {
-                        const int i = i0 + j;
-                        if (i < 9) fp[k][i] = plane[j][d1 - kCy[i] * W1 - kCx[i]];
-                    }
-                }
-            }
-            __syncthreads();
-        }
-
-        // ---- phase 4d: moments of the pulled sets, stores, next mass ----
-#pragma unroll
-        for (int k = 0; k < NST; ++k) {
-            const int r = tid + k * NT;
-            if (r < RTN) {
-                const int ry = r / TX, rx = r - ry * TX;
-                const int gx = x0 + rx, gy = y0 + ry;
-                if (gx < nx && gy < ny) {
-                    double rho, jx, jy;
-                    pulled_moments(fp[k], WALLS && gy == 0, WALLS && gy == ny - 1, rho, jx, jy);
-                    const size_t g = (size_t)gy * nx + gx;
-                    Mout[g] = rho;
-                    Mout[N + g] = jx;
-                    Mout[2 * N + g] = jy;
-                    const double nm = s_rho[r];
-                    part.mass_next += nm;
-                    if (nm != nm) part.flags |= kFlagNaN;
-                }
-            }
-        }
-        __syncthreads();  // LDS is rewritten by the next tile's phase 1
-    }
-    part = block_reduce<NT>(part, s_red, s_ured);
-    finish_launch<NT>(part, partials, st, step, (int)((step + 1) & 1), 1.0 / (double)N, s_red, s_ured);
-}
-
-// ---------------------------------------------------------------------------
 // Readout (off the hot loop): level-n fields from the current buffer.
 // Kernel A: rho, psi, j per node into scratch; kernel B: forces, u, p_EOS and
 // the normal pressure with plain central differences (interior nodes).
@@ -1070,11 +759,6 @@ __global__ void d2q9_readout_b(const double *__restrict__ scr, const double *__r
 // Tile of 64 x 32 nodes per block of 1024 threads (16 wavefronts): the LDS
 // staging of a tile (about 137 KB) allows one block per compute unit.
 constexpr int kTX = 64, kTY = 32, kNT = 1024;
-// The moment kernel's tile is 26 rows high: its tile + 2 region (68 x 30 =
-// 2040 nodes) and tile + 1 region (66 x 28) take two slots of 1024 threads
-// each (about 144 KB of LDS), and 1024 x 2048 splits into 1264 tiles, at most
-// five per block of a 256-block grid.
-constexpr int kTYm = 26;
 
 template <class S, bool TAU1, bool WALLS>
 hipError_t launch_t(const LatticeLaunch &L)
@@ -1094,27 +778,15 @@ hipError_t launch_t(const LatticeLaunch &L)
     return hipGetLastError();
 }
 
-template <bool WALLS>
-hipError_t launch_mom(const LatticeLaunch &L)
-{
-    const int tiles_x = (L.nx + kTX - 1) / kTX, tiles_y = (L.ny + kTYm - 1) / kTYm;
-    const int ntiles = tiles_x * tiles_y;
-    const int nb = d2q9_num_blocks(L.nx, L.ny, L.resident, true);
-    hipLaunchKernelGGL((d2q9_step_mom<WALLS, kTX, kTYm, kNT, 4>), dim3(nb), dim3(kNT), 0, L.stream,
-                       (const double *)L.fin, (double *)L.fout, L.Tin, L.Tout, L.phys, L.nx, L.ny, tiles_x,
-                       ntiles, L.partials, L.st, L.step);
-    return hipGetLastError();
-}
-
 }  // namespace
 
-// Persistent grid: one block per compute unit (at most one per tile), a
-// multiple of 8 so that every XCD gets the same number of blocks.
+// Persistent grid of the population kernels: one block per compute unit (at
+// most one per tile), a multiple of 8 so that every XCD gets the same number
+// of blocks.  The moment state is updated by the row-marching kernel.
 int d2q9_num_blocks(int nx, int ny, int cus, bool moments)
 {
     if (moments) return d2q9_march_blocks(nx, ny, cus);
-    const int ty = moments ? kTYm : kTY;
-    const int ntiles = ((nx + kTX - 1) / kTX) * ((ny + ty - 1) / ty);
+    const int ntiles = ((nx + kTX - 1) / kTX) * ((ny + kTY - 1) / kTY);
     int nb = ntiles < cus ? ntiles : cus;
     nb = ((nb + 7) / 8) * 8;
     return nb;

@@ -77,10 +77,11 @@ struct Rings {
     double rho[4], jx[4], jy[4], Z[4];
     double tc[4], td[4], ts[4];                 // T^n
     double ux[4], uy[4], uxd[4], uys[4], inv[4];
-    double fx[4], fy[4], X[4];                  // force and |F_int|^2/psi^2
     double ttc[4], ttd[4], tts[4], k1[4], dv[4];  // T~ = T^n + k1, k1, div u
     double pull[4][9];                          // pulled sets being assembled
     double lr[4], ljx[4], ljy[4], lT[4];        // loads in flight
+    double mass_n, mass_next, umax, rmin;       // diagnostics of the lane's own nodes
+    unsigned flags;
 };
 
 struct Strip {
@@ -195,14 +196,14 @@ __device__ __forceinline__ void issue_row(Rings &R, const Strip &A, int r)
 
 // Stages of a march step (a compile-time set: the first and last steps of a
 // segment run only the stages whose rows the segment needs).
-constexpr int kLoad = 1, kForce = 2, kHeun1 = 4, kCollide = 8, kHeun2 = 16, kPull = 32;
+constexpr int kLoad = 1, kForce = 2, kCollide = 4, kPull = 8, kHeun1 = 16, kHeun2 = 32;
 constexpr int kAll = 63;
 
 // One step of the march: loads of row a + kPF, then the stages in PH.  J is
 // the ring slot of row a.  Every stage writes its ring slots on every path;
 // only stores and diagnostics depend on run-time conditions.
 template <bool EDGE, int J, int PH>
-__device__ __forceinline__ void march_step(Rings &R, const Strip &A, const Phys &c, Partial &part, int a)
+__device__ __forceinline__ void march_step(Rings &R, const Strip &A, const Phys &c, int a)
 {
     constexpr int S0 = J & 3, S1 = (J + 3) & 3, S2 = (J + 2) & 3, S3 = (J + 1) & 3;  // rows a, a-1, a-2, a-3
     constexpr int S4 = J & 3;                                                       // row a-4
@@ -224,33 +225,30 @@ __device__ __forceinline__ void march_step(Rings &R, const Strip &A, const Phys 
             if (!(rho > 0.0)) fl |= kFlagRho;
             if (c.eos == 0 && c.b_quarter * rho >= 1.0) fl |= kFlagEta;
             if (psi != psi) fl |= kFlagPsi;
-            part.flags |= fl;
+            R.flags |= fl;
         }
     }
 
-    __builtin_amdgcn_sched_barrier(0);
-    // ---- row a - 1: force and force-corrected velocity ----
+    // ---- row a - 1: force, force-corrected velocity and the collision ----
     const int b = a - 1;
     if (PH & kForce) {
         const bool valid = !EDGE || !A.walls || (b >= 0 && b < A.ny);
         const bool wall = EDGE && A.walls && (b == 0 || b == A.ny - 1);
+        const double rho = R.rho[S1];
         double Fx = 0.0, Fy = 0.0, X = 0.0, inv = 0.0, ux = 0.0, uy = 0.0;
         if (valid && !wall) {
             const double sx = R.pd[S1] * (1.0 / 3.0) + (R.pd[S0] + R.pd[S2]) * (1.0 / 12.0);
             const double sy = (R.pc[S0] - R.pc[S2]) * (1.0 / 3.0) + (R.ps[S0] - R.ps[S2]) * (1.0 / 12.0);
             const double mg = -c.G * R.pc[S1];
             Fx = mg * sx;
-            Fy = mg * sy + gravity_force(R.rho[S1], A.sub, c.g);
+            Fy = mg * sy + gravity_force(rho, A.sub, c.g);
             X = c.G2 * (sx * sx + sy * sy);
         }
         if (valid) {
-            inv = rcp_pos(R.rho[S1]);
+            inv = rcp_pos(rho);
             ux = (R.jx[S1] + 0.5 * Fx) * inv;
             uy = (R.jy[S1] + 0.5 * Fy) * inv;
         }
-        R.fx[S1] = Fx;
-        R.fy[S1] = Fy;
-        R.X[S1] = X;
         R.inv[S1] = inv;
         R.ux[S1] = ux;
         R.uy[S1] = uy;
@@ -258,81 +256,45 @@ __device__ __forceinline__ void march_step(Rings &R, const Strip &A, const Phys 
         const double uyl = from_left(uy), uyr = from_right(uy);
         R.uxd[S1] = uxr - uxl;
         R.uys[S1] = uyr + uyl;
-    }
-
-    __builtin_amdgcn_sched_barrier(0);
-    // ---- row a - 2: first Heun stage ----
-    const int r2 = a - 2;
-    if (PH & kHeun1) {
-        double k1 = 0.0, dv = 0.0, Tt = R.tc[S2] + 0.0;
-        if (!EDGE || !A.walls || (r2 > 0 && r2 < A.ny - 1)) {
-            // rows r2 - 1, r2, r2 + 1 sit in slots S3, S2, S1
-            dv = (R.uxd[S2] * (1.0 / 3.0) + (R.uxd[S1] + R.uxd[S3]) * (1.0 / 12.0)) +
-                 ((R.uy[S1] - R.uy[S3]) * (1.0 / 3.0) + (R.uys[S1] - R.uys[S3]) * (1.0 / 12.0));
-            k1 = energy_rhs(c, R.tc[S3], R.td[S3], R.ts[S3], R.tc[S2], R.td[S2], R.ts[S2], R.tc[S1], R.td[S1],
-                            R.ts[S1], R.ux[S2], R.uy[S2], dv, R.inv[S2], R.Z[S2]);
-            Tt = R.tc[S2] + k1;
-        }
-        R.k1[S2] = k1;
-        R.dv[S2] = dv;
-        set_row(Tt, R.ttc[S2], R.ttd[S2], R.tts[S2]);
-    }
-
-    __builtin_amdgcn_sched_barrier(0);
-    // ---- row a - 3: second Heun stage, T^{n+1}, collision ----
-    const int q = a - 3;
-    if (PH & kCollide) {
-        const bool valid = !EDGE || !A.walls || (q >= 0 && q < A.ny);
-        constexpr bool own = (PH & kHeun2) != 0;  // row q is one of the segment's own rows
-        const double rho = R.rho[S3], ux = R.ux[S3], uy = R.uy[S3];
+        const bool own = b >= A.y0 && b < A.y1 && A.interior;
         if (own) {
-            const bool wall = EDGE && A.walls && (q == 0 || q == A.ny - 1);
-            const double T = R.tc[S3];
-            double Tn = T;
-            if (!wall) {
-                // T~ rows q - 1, q, q + 1 sit in slots S4, S3, S2
-                const double k2 = energy_rhs(c, R.ttc[S4], R.ttd[S4], R.tts[S4], R.ttc[S3], R.ttd[S3], R.tts[S3],
-                                             R.ttc[S2], R.ttd[S2], R.tts[S2], ux, uy, R.dv[S3], R.inv[S3],
-                                             R.Z[S3]);
-                Tn = T + 0.5 * (R.k1[S3] + k2);
-            }
-            if (A.interior) {
-                (A.Tout + (size_t)q * A.nx)[A.gx] = Tn;
-                part.mass_n += rho;
-                part.umax = fmax(part.umax, ux * ux + uy * uy);
-                part.rmin = fmin(part.rmin, rho);
-                if (rho != rho || ux != ux || uy != uy || Tn != Tn) part.flags |= kFlagNaN;
-            }
+            R.mass_n += rho;
+            R.umax = fmax(R.umax, ux * ux + uy * uy);
+            R.rmin = fmin(R.rmin, rho);
+            if (rho != rho || ux != ux || uy != uy) R.flags |= kFlagNaN;
         }
-        double fs[9];
+        if (PH & kCollide) {
+            // tau = 1: the post-collision set of row b is a function of its
+            // (rho, u, F, X) alone, so it is formed here
+            double fs[9];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) fs[i] = 0.0;  // rows beyond a wall send nothing
-        if (valid) collide(c, rho, ux, uy, R.fx[S3], R.fy[S3], R.X[S3], fs);
-        if (own && A.interior) {
-            const double nm = next_mass(fs, q, A.ny, EDGE && A.walls);
-            part.mass_next += nm;
-            if (nm != nm) part.flags |= kFlagNaN;
+            for (int i = 0; i < 9; ++i) fs[i] = 0.0;  // rows beyond a wall send nothing
+            if (valid) collide(c, rho, ux, uy, Fx, Fy, X, fs);
+            if (own) {
+                const double nm = next_mass(fs, b, A.ny, EDGE && A.walls);
+                R.mass_next += nm;
+                if (nm != nm) R.flags |= kFlagNaN;
+            }
+            // f_i(x) = f*_i(x - c_i): x-components +1 come from the left lane,
+            // -1 from the right lane; y-components +1 go to row b + 1, -1 to b - 1
+            R.pull[S0][2] = fs[2];
+            R.pull[S0][5] = from_left(fs[5]);
+            R.pull[S0][6] = from_right(fs[6]);
+            R.pull[S1][0] = fs[0];
+            R.pull[S1][1] = from_left(fs[1]);
+            R.pull[S1][3] = from_right(fs[3]);
+            R.pull[S2][4] = fs[4];
+            R.pull[S2][7] = from_right(fs[7]);
+            R.pull[S2][8] = from_left(fs[8]);
         }
-        // f_i(x) = f*_i(x - c_i): x-components +1 come from the left lane,
-        // -1 from the right lane; y-components +1 go to row q + 1, -1 to q - 1
-        R.pull[S2][2] = fs[2];
-        R.pull[S2][5] = from_left(fs[5]);
-        R.pull[S2][6] = from_right(fs[6]);
-        R.pull[S3][0] = fs[0];
-        R.pull[S3][1] = from_left(fs[1]);
-        R.pull[S3][3] = from_right(fs[3]);
-        R.pull[S4][4] = fs[4];
-        R.pull[S4][7] = from_right(fs[7]);
-        R.pull[S4][8] = from_left(fs[8]);
     }
 
-    __builtin_amdgcn_sched_barrier(0);
-    // ---- row a - 4: moments of the pulled set ----
-    const int p = a - 4;
+    // ---- row a - 2: moments of the pulled set ----
     if (PH & kPull) {
+        const int p = a - 2;
         double f[9];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) f[i] = R.pull[S4][i];
+        for (int i = 0; i < 9; ++i) f[i] = R.pull[S2][i];
         const bool bot = EDGE && A.walls && p == 0, top = EDGE && A.walls && p == A.ny - 1;
         if (bot) {  // unknowns 2, 5, 6
             const double d = f[1] - f[3];
@@ -356,60 +318,101 @@ __device__ __forceinline__ void march_step(Rings &R, const Strip &A, const Phys 
             (A.Mout + 2 * A.N + row)[A.gx] = jy;
         }
     }
-    // the scheduler keeps the stages (and the steps) in order: interleaving
-    // them would stretch the rings' live ranges past the register budget
-    __builtin_amdgcn_sched_barrier(0);
+
+    // ---- row a - 2: first Heun stage ----
+    const int r2 = a - 2;
+    if (PH & kHeun1) {
+        double k1 = 0.0, dv = 0.0, Tt = R.tc[S2] + 0.0;
+        if (!EDGE || !A.walls || (r2 > 0 && r2 < A.ny - 1)) {
+            // rows r2 - 1, r2, r2 + 1 sit in slots S3, S2, S1
+            dv = (R.uxd[S2] * (1.0 / 3.0) + (R.uxd[S1] + R.uxd[S3]) * (1.0 / 12.0)) +
+                 ((R.uy[S1] - R.uy[S3]) * (1.0 / 3.0) + (R.uys[S1] - R.uys[S3]) * (1.0 / 12.0));
+            k1 = energy_rhs(c, R.tc[S3], R.td[S3], R.ts[S3], R.tc[S2], R.td[S2], R.ts[S2], R.tc[S1], R.td[S1],
+                            R.ts[S1], R.ux[S2], R.uy[S2], dv, R.inv[S2], R.Z[S2]);
+            Tt = R.tc[S2] + k1;
+        }
+        R.k1[S2] = k1;
+        R.dv[S2] = dv;
+        set_row(Tt, R.ttc[S2], R.ttd[S2], R.tts[S2]);
+    }
+
+    // ---- row a - 3: second Heun stage and T^{n+1} (always a row of the segment) ----
+    if (PH & kHeun2) {
+        const int q = a - 3;
+        const bool wall = EDGE && A.walls && (q == 0 || q == A.ny - 1);
+        const double T = R.tc[S3];
+        double Tn = T;
+        if (!wall) {
+            // T~ rows q - 1, q, q + 1 sit in slots S4, S3, S2
+            const double k2 = energy_rhs(c, R.ttc[S4], R.ttd[S4], R.tts[S4], R.ttc[S3], R.ttd[S3], R.tts[S3],
+                                         R.ttc[S2], R.ttd[S2], R.tts[S2], R.ux[S3], R.uy[S3], R.dv[S3],
+                                         R.inv[S3], R.Z[S3]);
+            Tn = T + 0.5 * (R.k1[S3] + k2);
+        }
+        if (A.interior) {
+            (A.Tout + (size_t)q * A.nx)[A.gx] = Tn;
+            if (Tn != Tn) R.flags |= kFlagNaN;
+        }
+    }
 }
 
 // The march over one segment.
 template <bool EDGE>
 __device__ __forceinline__ void march(const Strip &A, const Phys &c, Partial &part)
 {
-    // Step a loads row a and finishes rows a - 1 .. a - 4.  The segment
-    // [y0, y1) needs psi on rows y0 - 3 .. y1 + 2, u on y0 - 2 .. y1 + 1,
-    // the first Heun stage and the collision on y0 - 1 .. y1, and the
-    // rest on its own rows: seven entry steps, y1 - y0 - 1 steps with
-    // every stage, and a final collision and pull.
+    // Step a loads row a, takes the force, velocity and collision of row
+    // a - 1, the pull and the first Heun stage of row a - 2 and the second
+    // Heun stage of row a - 3.  The segment [y0, y1) needs psi on rows
+    // y0 - 3 .. y1 + 2, u on y0 - 2 .. y1 + 1, the collision on y0 - 1 ..
+    // y1, the first Heun stage on y0 - 1 .. y1 and the rest on its own rows:
+    // six entry steps, y1 - y0 - 1 steps with every stage and a last step.
     Rings R;
+    R.mass_n = R.mass_next = R.umax = 0.0;
+    R.rmin = 1e300;
+    R.flags = 0u;
     const int a0 = A.y0 - kHalo;
     issue_row<EDGE, 0>(R, A, a0);
     issue_row<EDGE, 1>(R, A, a0 + 1);
-    march_step<EDGE, 0, kLoad>(R, A, c, part, a0);
-    march_step<EDGE, 1, kLoad>(R, A, c, part, a0 + 1);
-    march_step<EDGE, 2, kLoad | kForce>(R, A, c, part, a0 + 2);
-    march_step<EDGE, 3, kLoad | kForce>(R, A, c, part, a0 + 3);
-    march_step<EDGE, 0, kLoad | kForce | kHeun1>(R, A, c, part, a0 + 4);
-    march_step<EDGE, 1, kLoad | kForce | kHeun1 | kCollide>(R, A, c, part, a0 + 5);
-    march_step<EDGE, 2, kAll & ~kPull>(R, A, c, part, a0 + 6);
-    int a = a0 + 7;
-    const int last = A.y1 + 2;  // last step with every stage
+    march_step<EDGE, 0, kLoad>(R, A, c, a0);
+    march_step<EDGE, 1, kLoad>(R, A, c, a0 + 1);
+    march_step<EDGE, 2, kLoad | kForce>(R, A, c, a0 + 2);
+    march_step<EDGE, 3, kLoad | kForce | kCollide>(R, A, c, a0 + 3);
+    march_step<EDGE, 0, kLoad | kForce | kCollide | kHeun1>(R, A, c, a0 + 4);
+    march_step<EDGE, 1, kAll & ~kHeun2>(R, A, c, a0 + 5);
+    int a = a0 + 6;
+    const int last = A.y1 + 1;  // last step with every stage
     for (; a + 3 <= last; a += 4) {
-        march_step<EDGE, 3, kAll>(R, A, c, part, a);
-        march_step<EDGE, 0, kAll>(R, A, c, part, a + 1);
-        march_step<EDGE, 1, kAll>(R, A, c, part, a + 2);
-        march_step<EDGE, 2, kAll>(R, A, c, part, a + 3);
+        march_step<EDGE, 2, kAll>(R, A, c, a);
+        march_step<EDGE, 3, kAll>(R, A, c, a + 1);
+        march_step<EDGE, 0, kAll>(R, A, c, a + 2);
+        march_step<EDGE, 1, kAll>(R, A, c, a + 3);
     }
-    constexpr int kLast = kCollide | kPull;
+    constexpr int kLast = kLoad | kForce | kHeun1 | kHeun2;
     switch (last + 1 - a) {
     case 0:
-        march_step<EDGE, 3, kLast>(R, A, c, part, a);
+        march_step<EDGE, 2, kLast>(R, A, c, a);
         break;
     case 1:
-        march_step<EDGE, 3, kAll>(R, A, c, part, a);
-        march_step<EDGE, 0, kLast>(R, A, c, part, a + 1);
+        march_step<EDGE, 2, kAll>(R, A, c, a);
+        march_step<EDGE, 3, kLast>(R, A, c, a + 1);
         break;
     case 2:
-        march_step<EDGE, 3, kAll>(R, A, c, part, a);
-        march_step<EDGE, 0, kAll>(R, A, c, part, a + 1);
-        march_step<EDGE, 1, kLast>(R, A, c, part, a + 2);
+        march_step<EDGE, 2, kAll>(R, A, c, a);
+        march_step<EDGE, 3, kAll>(R, A, c, a + 1);
+        march_step<EDGE, 0, kLast>(R, A, c, a + 2);
         break;
     default:
-        march_step<EDGE, 3, kAll>(R, A, c, part, a);
-        march_step<EDGE, 0, kAll>(R, A, c, part, a + 1);
-        march_step<EDGE, 1, kAll>(R, A, c, part, a + 2);
-        march_step<EDGE, 2, kLast>(R, A, c, part, a + 3);
+        march_step<EDGE, 2, kAll>(R, A, c, a);
+        march_step<EDGE, 3, kAll>(R, A, c, a + 1);
+        march_step<EDGE, 0, kAll>(R, A, c, a + 2);
+        march_step<EDGE, 1, kLast>(R, A, c, a + 3);
         break;
     }
+    part.mass_n += R.mass_n;
+    part.mass_next += R.mass_next;
+    part.umax = fmax(part.umax, R.umax);
+    part.rmin = fmin(part.rmin, R.rmin);
+    part.flags |= R.flags;
 }
 
 __global__ __launch_bounds__(kNT, 2) void d2q9_march_mom(const double *__restrict__ Min, double *__restrict__ Mout,
