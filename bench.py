@@ -38,15 +38,23 @@ NX, NY = 1024, 2048
 # FP64 moment state rho, j_x, j_y, T; FP64 populations 9 + T; FP32 deviations
 # 9 (4 bytes) + T
 BYTES_PER_NODE = {"fp64": 4 * 8 * 2, "fp64pop": 9 * 8 * 2 + 8 * 2, "fp32dev": 9 * 4 * 2 + 8 * 2}
-KERNEL_SOURCES = ["paper_2301_12869_amd/csrc/d2q9.hip", "paper_2301_12869_amd/csrc/lbm_common.hpp"]
+# the sources each variant's kernel is built from: a counter record holds for
+# a variant while the code of these files is unchanged
+_CSRC = "paper_2301_12869_amd/csrc/"
+KERNEL_SOURCES = {
+    "fp64": [_CSRC + "d2q9_march.hip", _CSRC + "lbm_common.hpp"],
+    "fp64pop": [_CSRC + "d2q9.hip", _CSRC + "lbm_common.hpp"],
+    "fp32dev": [_CSRC + "d2q9.hip", _CSRC + "layer_ref.hip", _CSRC + "lbm_common.hpp"],
+}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "d2q9_1024x2048_traffic.json")
 
 
-def source_hash() -> str:
-    """Hash of the kernel sources' code: comments and whitespace are dropped,
-    so only a change to the code itself invalidates the counter record."""
+def source_hash(variant: str) -> str:
+    """Hash of the code of a variant's kernel sources: comments and whitespace
+    are dropped, so only a change to the code itself invalidates its counter
+    record.  ``variant`` is a bench key such as ``fp64_form2_g1e-05``."""
     h = hashlib.sha256()
-    for s in KERNEL_SOURCES:
+    for s in KERNEL_SOURCES[variant.split("_")[0]]:
         with open(os.path.join(ROOT, s)) as fh:
             text = fh.read()
         text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
@@ -55,17 +63,22 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(variant: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary,
-    or None when the kernel source changed since the counters were taken."""
+def _counter_record(path: str, variant: str):
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
-    if rec.get("source_hash") != source_hash():
-        return None
     v = rec.get("variants", {}).get(variant)
+    if v is None or v.get("source_hash") != source_hash(variant):
+        return None
+    return v
+
+
+def measured_traffic(variant: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    or None when the kernel's source changed since the counters were taken."""
+    v = _counter_record(TRAFFIC_FILE, variant)
     return None if v is None else float(v["hbm_bytes_per_launch"])
 
 
@@ -77,15 +90,8 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 def measured_sq(variant: str):
     """Per-node SQ counter figures from the committed rocprofv3 record, or None
-    when the kernel source changed since the counters were taken."""
-    try:
-        with open(SQ_FILE) as fh:
-            rec = json.load(fh)
-    except (OSError, ValueError):
-        return None
-    if rec.get("source_hash") != source_hash():
-        return None
-    return rec.get("variants", {}).get(variant)
+    when the kernel's source changed since the counters were taken."""
+    return _counter_record(SQ_FILE, variant)
 
 
 def valu_roofline(variant: str, kernel_ms: float):
@@ -102,7 +108,7 @@ def valu_roofline(variant: str, kernel_ms: float):
     return {"bound": "alu", "achieved": round(lane / 1e12, 3), "peak": round(VALU_LANE_OPS_PEAK / 1e12, 3),
             "unit": "T VALU lane-instructions/s", "frac": round(lane / VALU_LANE_OPS_PEAK, 4),
             "fp64_TFLOPs": round(fp64, 2), "fp64_frac": round(fp64 / FP64_VECTOR_PEAK_TFLOPS, 4),
-            "per_node": {k: v for k, v in sq.items() if k not in ("counters", "kernel")}}
+            "per_node": {k: v for k, v in sq.items() if k not in ("counters", "kernel", "source_hash")}}
 
 
 def make_inputs(T):

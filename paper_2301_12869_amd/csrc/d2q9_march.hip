@@ -45,6 +45,7 @@ constexpr int kHalo = 3;
 constexpr int kStrip = 64 - 2 * kHalo;  // interior columns of a wavefront
 constexpr int kNT = 256;                // four independent wavefronts per block
 constexpr int kPF = 2;                  // rows of loads in flight ahead of use
+static_assert(kPF >= 2 && kPF <= 3, "a load slot must be free when its row is issued");
 constexpr double kW1 = 1.0 / 9.0, kW5 = 1.0 / 36.0;
 
 // lane l receives the value of lane l - 1 (the column to its left; lane 0
@@ -70,6 +71,43 @@ __device__ __forceinline__ int wrap(int v, int n)
     return v < 0 ? v + n : v;
 }
 
+// Row accesses go through buffer resources whose range is one row of one
+// plane: a lane outside the range (a halo lane's store, every lane of a row
+// the march does not need) reads zero and writes nothing.  This keeps every
+// load and store out of branches, so the compiler's wait counts for the
+// loads in flight stay exact.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr int kRsrcWord3 = 0x00020000;  // raw 32-bit dword access (gfx9 family)
+constexpr unsigned kOut = 0x80000000u;  // a byte offset beyond every row's range
+
+__device__ __forceinline__ double row_load(const double *row, int bytes, unsigned off)
+{
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc((void *)row, (short)0, bytes, kRsrcWord3);
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+
+__device__ __forceinline__ void row_store(double *row, int bytes, unsigned off, double v)
+{
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc((void *)row, (short)0, bytes, kRsrcWord3);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)off, 0, 0);
+}
+
+// sqrt_pos without a branch: the same refined reciprocal square root for a
+// positive argument, zero for zero, NaN for a negative or NaN argument.
+__device__ __forceinline__ double sqrt_pos_sel(double a)
+{
+    const bool pos = a > 0.0;
+    const double x = pos ? a : 1.0;
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    const double d = fma(-g, g, x);
+    const double s = fma(d, h, g);
+    return pos ? s : (a == 0.0 ? 0.0 : __builtin_nan(""));
+}
+
 // Per-row quantities of one lane, four rows each (index: row & 3 relative
 // to the segment's first row).
 struct Rings {
@@ -91,6 +129,7 @@ struct Strip {
     double *Tout;
     size_t N;
     int nx, ny, y0, y1, gx;
+    unsigned ldoff, stoff;  // byte offsets of the lane's column: loads, stores (kOut on halo lanes)
     bool walls;  // walls at the first and last rows; periodic rows otherwise
     bool interior;
     double sub;
@@ -154,12 +193,51 @@ __device__ __forceinline__ double next_mass(const double v[9], int gy, int ny, b
     double nm = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7])) + v[8];
     if (walls) {
         const double down = (v[4] + v[7]) + v[8], up = (v[2] + v[5]) + v[6];
-        if (gy == 0) nm -= down;
-        if (gy == 1) nm += down;
-        if (gy == ny - 2) nm += up;
-        if (gy == ny - 1) nm -= up;
+        nm = gy == 0 ? nm - down : nm;
+        nm = gy == 1 ? nm + down : nm;
+        nm = gy == ny - 2 ? nm + up : nm;
+        nm = gy == ny - 1 ? nm - up : nm;
     }
     return nm;
+}
+
+// Diagnostics of a node of level n (mass, max |u|^2, min rho, NaN flag),
+// added when the lane owns the node: by selects, or (BRANCH) by a branch,
+// which keeps the register demand of the wall segments' steps lower.
+template <bool BRANCH>
+__device__ __forceinline__ void level_diag(Rings &R, bool own, double rho, double ux, double uy)
+{
+    const double uu = ux * ux + uy * uy;
+    const bool nan = rho != rho || ux != ux || uy != uy;
+    if (BRANCH) {
+        if (own) {
+            R.mass_n += rho;
+            R.umax = fmax(R.umax, uu);
+            R.rmin = fmin(R.rmin, rho);
+            if (nan) R.flags |= kFlagNaN;
+        }
+    } else {
+        R.mass_n += own ? rho : 0.0;
+        R.umax = own ? fmax(R.umax, uu) : R.umax;
+        R.rmin = own ? fmin(R.rmin, rho) : R.rmin;
+        R.flags |= (own && nan) ? kFlagNaN : 0u;
+    }
+}
+
+// psi and Z(eta) of a node (Eqs. EOS, InteractionPotential), the EOS fixed
+// at compile time; the same arithmetic as psi_and_Z.  A row of zeros (beyond
+// a wall) gets psi = 0.
+template <int EOS>
+__device__ __forceinline__ double psi_Z(const Phys &c, double rho, double T, double &Z)
+{
+    if constexpr (EOS == 1) {
+        Z = 0.0;
+        return 0.0;
+    } else {
+        Z = cs_Z(c.b_quarter * rho);
+        const double p = rho * (c.R * T * Z - c.a * rho);
+        return sqrt_pos_sel(c.two_over_G * (p - rho * (1.0 / 3.0)));
+    }
 }
 
 // Issue the loads of row r into ring slot S (zeros beyond a wall and past
@@ -168,30 +246,21 @@ __device__ __forceinline__ double next_mass(const double v[9], int gy, int ny, b
 template <bool EDGE, int S>
 __device__ __forceinline__ void issue_row(Rings &R, const Strip &A, int r)
 {
-    double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
-    if (!EDGE) {
-        // interior segment: every row it reads exists; the last steps
-        // re-read its last row instead of rows it does not need
-        const size_t row = (size_t)min(r, A.y1 + kHalo - 1) * A.nx;
-        v0 = (A.Min + row)[A.gx];
-        v1 = (A.Min + A.N + row)[A.gx];
-        v2 = (A.Min + 2 * A.N + row)[A.gx];
-        v3 = (A.Tin + row)[A.gx];
-    } else if (r < A.y1 + kHalo && (!A.walls || (r >= 0 && r < A.ny))) {
-        const int gy = A.walls ? r : wrap(r, A.ny);
-        const size_t row = (size_t)gy * A.nx;
-        v0 = (A.Min + row)[A.gx];
-        v1 = (A.Min + A.N + row)[A.gx];
-        v2 = (A.Min + 2 * A.N + row)[A.gx];
-        v3 = (A.Tin + row)[A.gx];
+    // rows past the last one the segment reads, and rows beyond a wall, are
+    // read as zeros (an empty range); the row index is uniform
+    bool need = r < A.y1 + kHalo;
+    int gy = r;
+    if (EDGE) {
+        if (A.walls) need = need && r >= 0 && r < A.ny;
+        else gy = wrap(r, A.ny);
     }
-    // one assignment per slot on every path (stores of the two paths that
-    // the optimiser sank into one would defeat the rings' promotion to
-    // registers)
-    R.lr[S] = v0;
-    R.ljx[S] = v1;
-    R.ljy[S] = v2;
-    R.lT[S] = v3;
+    gy = need ? gy : 0;
+    const int bytes = need ? A.nx * 8 : 0;
+    const size_t row = (size_t)gy * A.nx;
+    R.lr[S] = row_load(A.Min + row, bytes, A.ldoff);
+    R.ljx[S] = row_load(A.Min + A.N + row, bytes, A.ldoff);
+    R.ljy[S] = row_load(A.Min + 2 * A.N + row, bytes, A.ldoff);
+    R.lT[S] = row_load(A.Tin + row, bytes, A.ldoff);
 }
 
 // Stages of a march step (a compile-time set: the first and last steps of a
@@ -200,43 +269,43 @@ constexpr int kLoad = 1, kForce = 2, kCollide = 4, kPull = 8, kHeun1 = 16, kHeun
 constexpr int kAll = 63;
 
 // One step of the march: loads of row a + kPF, then the stages in PH.  J is
-// the ring slot of row a.  Every stage writes its ring slots on every path;
-// only stores and diagnostics depend on run-time conditions.
-template <bool EDGE, int J, int PH>
+// the ring slot of row a.  A step of an interior segment holds no branch (a
+// lane's own nodes select their diagnostics), so that the compiler can
+// interleave the independent stages of the step; a segment with a wall row
+// branches, uniformly, around the stages that wall rows and the rows of
+// zeros beyond them skip.
+template <bool EDGE, int EOS, int J, int PH>
 __device__ __forceinline__ void march_step(Rings &R, const Strip &A, const Phys &c, int a)
 {
     constexpr int S0 = J & 3, S1 = (J + 3) & 3, S2 = (J + 2) & 3, S3 = (J + 1) & 3;  // rows a, a-1, a-2, a-3
     constexpr int S4 = J & 3;                                                       // row a-4
+    const bool walls = EDGE && A.walls;
     if (PH & kLoad) issue_row<EDGE, (J + kPF) & 3>(R, A, a + kPF);
 
     // ---- row a: psi, Z and the stencil rows of psi and T^n ----
     if (PH & kLoad) {
         const double rho = R.lr[S0], T = R.lT[S0];
-        double Z = 0.0, psi = 0.0;
-        if (!EDGE || !A.walls || (a >= 0 && a < A.ny)) psi = psi_and_Z(c, rho, T, Z);
+        double Z;
+        const double psi = psi_Z<EOS>(c, rho, T, Z);
         R.rho[S0] = rho;
         R.jx[S0] = R.ljx[S0];
         R.jy[S0] = R.ljy[S0];
         R.Z[S0] = Z;
         set_row(psi, R.pc[S0], R.pd[S0], R.ps[S0]);
         set_row(T, R.tc[S0], R.td[S0], R.ts[S0]);
-        if (a >= A.y0 && a < A.y1 && A.interior) {
-            unsigned fl = 0u;
-            if (!(rho > 0.0)) fl |= kFlagRho;
-            if (c.eos == 0 && c.b_quarter * rho >= 1.0) fl |= kFlagEta;
-            if (psi != psi) fl |= kFlagPsi;
-            R.flags |= fl;
-        }
+        const bool own = a >= A.y0 && a < A.y1 && A.interior;
+        unsigned fl = (rho > 0.0 ? 0u : kFlagRho) | (psi != psi ? kFlagPsi : 0u);
+        if (EOS == 0) fl |= c.b_quarter * rho >= 1.0 ? kFlagEta : 0u;
+        R.flags |= own ? fl : 0u;
     }
 
+    if (EDGE) __builtin_amdgcn_sched_barrier(0);  // a wall segment keeps its stages apart
     // ---- row a - 1: force, force-corrected velocity and the collision ----
     const int b = a - 1;
     if (PH & kForce) {
-        const bool valid = !EDGE || !A.walls || (b >= 0 && b < A.ny);
-        const bool wall = EDGE && A.walls && (b == 0 || b == A.ny - 1);
         const double rho = R.rho[S1];
         double Fx = 0.0, Fy = 0.0, X = 0.0, inv = 0.0, ux = 0.0, uy = 0.0;
-        if (valid && !wall) {
+        if (!walls || (b > 0 && b < A.ny - 1)) {  // wall rows carry no force
             const double sx = R.pd[S1] * (1.0 / 3.0) + (R.pd[S0] + R.pd[S2]) * (1.0 / 12.0);
             const double sy = (R.pc[S0] - R.pc[S2]) * (1.0 / 3.0) + (R.ps[S0] - R.ps[S2]) * (1.0 / 12.0);
             const double mg = -c.G * R.pc[S1];
@@ -244,7 +313,7 @@ __device__ __forceinline__ void march_step(Rings &R, const Strip &A, const Phys 
             Fy = mg * sy + gravity_force(rho, A.sub, c.g);
             X = c.G2 * (sx * sx + sy * sy);
         }
-        if (valid) {
+        if (!walls || (b >= 0 && b < A.ny)) {  // rows beyond a wall keep u = 0
             inv = rcp_pos(rho);
             ux = (R.jx[S1] + 0.5 * Fx) * inv;
             uy = (R.jy[S1] + 0.5 * Fy) * inv;
@@ -257,24 +326,16 @@ __device__ __forceinline__ void march_step(Rings &R, const Strip &A, const Phys 
         R.uxd[S1] = uxr - uxl;
         R.uys[S1] = uyr + uyl;
         const bool own = b >= A.y0 && b < A.y1 && A.interior;
-        if (own) {
-            R.mass_n += rho;
-            R.umax = fmax(R.umax, ux * ux + uy * uy);
-            R.rmin = fmin(R.rmin, rho);
-            if (rho != rho || ux != ux || uy != uy) R.flags |= kFlagNaN;
-        }
+        level_diag<EDGE>(R, own, rho, ux, uy);
         if (PH & kCollide) {
             // tau = 1: the post-collision set of row b is a function of its
-            // (rho, u, F, X) alone, so it is formed here
+            // (rho, u, F, X) alone, so it is formed here; a row of zeros
+            // beyond a wall gives a set of zeros (it sends nothing)
             double fs[9];
-#pragma unroll
-            for (int i = 0; i < 9; ++i) fs[i] = 0.0;  // rows beyond a wall send nothing
-            if (valid) collide(c, rho, ux, uy, Fx, Fy, X, fs);
-            if (own) {
-                const double nm = next_mass(fs, b, A.ny, EDGE && A.walls);
-                R.mass_next += nm;
-                if (nm != nm) R.flags |= kFlagNaN;
-            }
+            collide(c, rho, ux, uy, Fx, Fy, X, fs);
+            const double nm = next_mass(fs, b, A.ny, walls);
+            R.mass_next += own ? nm : 0.0;
+            R.flags |= (own && nm != nm) ? kFlagNaN : 0u;
             // f_i(x) = f*_i(x - c_i): x-components +1 come from the left lane,
             // -1 from the right lane; y-components +1 go to row b + 1, -1 to b - 1
             R.pull[S0][2] = fs[2];
@@ -289,20 +350,20 @@ __device__ __forceinline__ void march_step(Rings &R, const Strip &A, const Phys 
         }
     }
 
+    if (EDGE) __builtin_amdgcn_sched_barrier(0);  // a wall segment keeps its stages apart
     // ---- row a - 2: moments of the pulled set ----
     if (PH & kPull) {
         const int p = a - 2;
         double f[9];
 #pragma unroll
         for (int i = 0; i < 9; ++i) f[i] = R.pull[S2][i];
-        const bool bot = EDGE && A.walls && p == 0, top = EDGE && A.walls && p == A.ny - 1;
-        if (bot) {  // unknowns 2, 5, 6
+        if (walls && p == 0) {  // Zou-He, bottom wall: unknowns 2, 5, 6
             const double d = f[1] - f[3];
             f[2] = f[4];
             f[5] = f[7] - 0.5 * d;
             f[6] = f[8] + 0.5 * d;
         }
-        if (top) {  // unknowns 4, 7, 8
+        if (walls && p == A.ny - 1) {  // top wall: unknowns 4, 7, 8
             const double d = f[1] - f[3];
             f[4] = f[2];
             f[7] = f[5] + 0.5 * d;
@@ -311,53 +372,50 @@ __device__ __forceinline__ void march_step(Rings &R, const Strip &A, const Phys 
         const double rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
         const double jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
         const double jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
-        if (A.interior) {
-            const size_t row = (size_t)p * A.nx;
-            (A.Mout + row)[A.gx] = rho;
-            (A.Mout + A.N + row)[A.gx] = jx;
-            (A.Mout + 2 * A.N + row)[A.gx] = jy;
-        }
+        const size_t row = (size_t)p * A.nx;
+        row_store(A.Mout + row, A.nx * 8, A.stoff, rho);
+        row_store(A.Mout + A.N + row, A.nx * 8, A.stoff, jx);
+        row_store(A.Mout + 2 * A.N + row, A.nx * 8, A.stoff, jy);
     }
 
+    if (EDGE) __builtin_amdgcn_sched_barrier(0);  // a wall segment keeps its stages apart
     // ---- row a - 2: first Heun stage ----
     const int r2 = a - 2;
     if (PH & kHeun1) {
-        double k1 = 0.0, dv = 0.0, Tt = R.tc[S2] + 0.0;
-        if (!EDGE || !A.walls || (r2 > 0 && r2 < A.ny - 1)) {
+        double k1 = 0.0, dv = 0.0;
+        if (!walls || (r2 > 0 && r2 < A.ny - 1)) {
             // rows r2 - 1, r2, r2 + 1 sit in slots S3, S2, S1
             dv = (R.uxd[S2] * (1.0 / 3.0) + (R.uxd[S1] + R.uxd[S3]) * (1.0 / 12.0)) +
                  ((R.uy[S1] - R.uy[S3]) * (1.0 / 3.0) + (R.uys[S1] - R.uys[S3]) * (1.0 / 12.0));
             k1 = energy_rhs(c, R.tc[S3], R.td[S3], R.ts[S3], R.tc[S2], R.td[S2], R.ts[S2], R.tc[S1], R.td[S1],
                             R.ts[S1], R.ux[S2], R.uy[S2], dv, R.inv[S2], R.Z[S2]);
-            Tt = R.tc[S2] + k1;
         }
+        const double Tt = R.tc[S2] + k1;
         R.k1[S2] = k1;
         R.dv[S2] = dv;
         set_row(Tt, R.ttc[S2], R.ttd[S2], R.tts[S2]);
     }
 
+    if (EDGE) __builtin_amdgcn_sched_barrier(0);  // a wall segment keeps its stages apart
     // ---- row a - 3: second Heun stage and T^{n+1} (always a row of the segment) ----
     if (PH & kHeun2) {
         const int q = a - 3;
-        const bool wall = EDGE && A.walls && (q == 0 || q == A.ny - 1);
         const double T = R.tc[S3];
         double Tn = T;
-        if (!wall) {
+        if (!walls || (q > 0 && q < A.ny - 1)) {  // wall rows keep their temperature
             // T~ rows q - 1, q, q + 1 sit in slots S4, S3, S2
             const double k2 = energy_rhs(c, R.ttc[S4], R.ttd[S4], R.tts[S4], R.ttc[S3], R.ttd[S3], R.tts[S3],
                                          R.ttc[S2], R.ttd[S2], R.tts[S2], R.ux[S3], R.uy[S3], R.dv[S3],
                                          R.inv[S3], R.Z[S3]);
             Tn = T + 0.5 * (R.k1[S3] + k2);
         }
-        if (A.interior) {
-            (A.Tout + (size_t)q * A.nx)[A.gx] = Tn;
-            if (Tn != Tn) R.flags |= kFlagNaN;
-        }
+        row_store(A.Tout + (size_t)q * A.nx, A.nx * 8, A.stoff, Tn);
+        R.flags |= (A.interior && Tn != Tn) ? kFlagNaN : 0u;
     }
 }
 
 // The march over one segment.
-template <bool EDGE>
+template <bool EDGE, int EOS>
 __device__ __forceinline__ void march(const Strip &A, const Phys &c, Partial &part)
 {
     // Step a loads row a, takes the force, velocity and collision of row
@@ -373,39 +431,40 @@ __device__ __forceinline__ void march(const Strip &A, const Phys &c, Partial &pa
     const int a0 = A.y0 - kHalo;
     issue_row<EDGE, 0>(R, A, a0);
     issue_row<EDGE, 1>(R, A, a0 + 1);
-    march_step<EDGE, 0, kLoad>(R, A, c, a0);
-    march_step<EDGE, 1, kLoad>(R, A, c, a0 + 1);
-    march_step<EDGE, 2, kLoad | kForce>(R, A, c, a0 + 2);
-    march_step<EDGE, 3, kLoad | kForce | kCollide>(R, A, c, a0 + 3);
-    march_step<EDGE, 0, kLoad | kForce | kCollide | kHeun1>(R, A, c, a0 + 4);
-    march_step<EDGE, 1, kAll & ~kHeun2>(R, A, c, a0 + 5);
+    if constexpr (kPF > 2) issue_row<EDGE, 2>(R, A, a0 + 2);
+    march_step<EDGE, EOS, 0, kLoad>(R, A, c, a0);
+    march_step<EDGE, EOS, 1, kLoad>(R, A, c, a0 + 1);
+    march_step<EDGE, EOS, 2, kLoad | kForce>(R, A, c, a0 + 2);
+    march_step<EDGE, EOS, 3, kLoad | kForce | kCollide>(R, A, c, a0 + 3);
+    march_step<EDGE, EOS, 0, kLoad | kForce | kCollide | kHeun1>(R, A, c, a0 + 4);
+    march_step<EDGE, EOS, 1, kAll & ~kHeun2>(R, A, c, a0 + 5);
     int a = a0 + 6;
     const int last = A.y1 + 1;  // last step with every stage
     for (; a + 3 <= last; a += 4) {
-        march_step<EDGE, 2, kAll>(R, A, c, a);
-        march_step<EDGE, 3, kAll>(R, A, c, a + 1);
-        march_step<EDGE, 0, kAll>(R, A, c, a + 2);
-        march_step<EDGE, 1, kAll>(R, A, c, a + 3);
+        march_step<EDGE, EOS, 2, kAll>(R, A, c, a);
+        march_step<EDGE, EOS, 3, kAll>(R, A, c, a + 1);
+        march_step<EDGE, EOS, 0, kAll>(R, A, c, a + 2);
+        march_step<EDGE, EOS, 1, kAll>(R, A, c, a + 3);
     }
     constexpr int kLast = kLoad | kForce | kHeun1 | kHeun2;
     switch (last + 1 - a) {
     case 0:
-        march_step<EDGE, 2, kLast>(R, A, c, a);
+        march_step<EDGE, EOS, 2, kLast>(R, A, c, a);
         break;
     case 1:
-        march_step<EDGE, 2, kAll>(R, A, c, a);
-        march_step<EDGE, 3, kLast>(R, A, c, a + 1);
+        march_step<EDGE, EOS, 2, kAll>(R, A, c, a);
+        march_step<EDGE, EOS, 3, kLast>(R, A, c, a + 1);
         break;
     case 2:
-        march_step<EDGE, 2, kAll>(R, A, c, a);
-        march_step<EDGE, 3, kAll>(R, A, c, a + 1);
-        march_step<EDGE, 0, kLast>(R, A, c, a + 2);
+        march_step<EDGE, EOS, 2, kAll>(R, A, c, a);
+        march_step<EDGE, EOS, 3, kAll>(R, A, c, a + 1);
+        march_step<EDGE, EOS, 0, kLast>(R, A, c, a + 2);
         break;
     default:
-        march_step<EDGE, 2, kAll>(R, A, c, a);
-        march_step<EDGE, 3, kAll>(R, A, c, a + 1);
-        march_step<EDGE, 0, kAll>(R, A, c, a + 2);
-        march_step<EDGE, 1, kLast>(R, A, c, a + 3);
+        march_step<EDGE, EOS, 2, kAll>(R, A, c, a);
+        march_step<EDGE, EOS, 3, kAll>(R, A, c, a + 1);
+        march_step<EDGE, EOS, 0, kAll>(R, A, c, a + 2);
+        march_step<EDGE, EOS, 1, kLast>(R, A, c, a + 3);
         break;
     }
     part.mass_n += R.mass_n;
@@ -415,6 +474,7 @@ __device__ __forceinline__ void march(const Strip &A, const Phys &c, Partial &pa
     part.flags |= R.flags;
 }
 
+template <int EOS>
 __global__ __launch_bounds__(kNT, 2) void d2q9_march_mom(const double *__restrict__ Min, double *__restrict__ Mout,
                                                          const double *__restrict__ Tin, double *__restrict__ Tout,
                                                          Phys c, int nx, int ny, int walls, int nstrips, int nseg, int spb,
@@ -449,14 +509,16 @@ __global__ __launch_bounds__(kNT, 2) void d2q9_march_mom(const double *__restric
         const int x1 = (int)((int64_t)(strip + 1) * nx / nstrips);
         A.gx = wrap(x0 - kHalo + lane, nx);
         A.interior = lane >= kHalo && lane < kHalo + (x1 - x0);
+        A.ldoff = (unsigned)A.gx * 8u;
+        A.stoff = A.interior ? A.ldoff : kOut;
         A.sub = gravity_sub(c.form, st->mean[step & 1], c.rho_v);
 
         // segments whose rows all exist and hold no wall row take the
         // variant without the checks
         if (A.y0 >= kHalo && A.y1 <= ny - kHalo)
-            march<false>(A, c, part);
+            march<false, EOS>(A, c, part);
         else
-            march<true>(A, c, part);
+            march<true, EOS>(A, c, part);
     }
     part = block_reduce<kNT>(part, s_red, s_ured);
     finish_launch<kNT>(part, partials, st, step, (int)((step + 1) & 1), 1.0 / ((double)nx * ny), s_red, s_ured);
@@ -491,7 +553,8 @@ int d2q9_march_blocks(int nx, int ny, int cus) { return march_grid(nx, ny, cus).
 hipError_t d2q9_march_launch(const LatticeLaunch &L)
 {
     const MarchGrid g = march_grid(L.nx, L.ny, L.resident);
-    hipLaunchKernelGGL(d2q9_march_mom, dim3(g.nblocks), dim3(kNT), 0, L.stream, (const double *)L.fin,
+    auto kern = L.phys.eos == 1 ? d2q9_march_mom<1> : d2q9_march_mom<0>;
+    hipLaunchKernelGGL(kern, dim3(g.nblocks), dim3(kNT), 0, L.stream, (const double *)L.fin,
                        (double *)L.fout, L.Tin, L.Tout, L.phys, L.nx, L.ny, L.walls ? 1 : 0, g.nstrips, g.nseg,
                        g.spb, L.partials, L.st, L.step);
     return hipGetLastError();
