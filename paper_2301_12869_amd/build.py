@@ -24,7 +24,7 @@ COMMON = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}",
           "-Wall", "-Wno-unused-function", "-I", CSRC, "-I", os.path.join(ROOT, "include")]
 
 SOURCES = ["d2q9.hip", "d2q9_march.hip", "layer_ref.hip", "stream_copy.hip", "tplbm_host.cpp"]
-EXTRA_SOURCES = ["d1q3_batch.hip", "batch_noalloc.hip", "d3q19.hip", "net.hip", "batch_host.cpp", "net_host.cpp", "theory_host.cpp"]
+EXTRA_SOURCES = ["d1q3_batch.hip", "batch_noalloc.hip", "d3q19.hip", "d3q19_march.hip", "net.hip", "batch_host.cpp", "net_host.cpp", "theory_host.cpp"]
 
 
 def _asm_scanner():

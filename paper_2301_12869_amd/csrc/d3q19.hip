@@ -8,25 +8,26 @@
 // Guo's term plus the isotropic sigma term w_i (|c_i|^2 - 1)(3/4) sigma X',
 // the D2Q9 sigma term of Li's scheme written without the 2-D moment basis.
 //
-// One step is four passes over the lattice, intermediate fields in FP64:
+// This file holds the pass kernels.  The population state (FP32 deviations
+// or FP64 populations) is advanced by the z-marching kernels of
+// d3q19_march.hip; the passes here serve the readout and the moment state:
 //   A: pull-stream with Zou-He wall reconstruction, rho, j, psi -> M
 //   B: Shan-Chen force (zero at walls), gravity, u = (j + F/2)/rho, and
 //      sigma |F_int|^2 / psi^2                               -> U (u, F, X)
 //   C: div u and the first Heun stage of the energy equation, k1 = K(T^n)
 //                                                             -> K1 (k1, div u)
-//   D: T^{n+1} = T^n + (k1 + K(T^n + k1))/2, collision f* = f_eq + F'
-//      (rest population closing the mass), store f* and T^{n+1}, partial
-//      sums of the next level's mass; the last block finishes <rho>.
 // Every stencil is evaluated once per node and step; the passes hand the
 // results on instead of recomputing them.
 //
 // FP64 lattices carry M and T between steps instead of the populations (the
-// moment state): a step is then B, C and M, where M fuses D with the next
-// step's A -- the second Heun stage, the post-collision populations of each
+// moment state): a step is then B, C and M, where M takes the second Heun
+// stage and the collision (T^{n+1} = T^n + (k1 + K(T^n + k1))/2, f* = f_eq +
+// F') fused with the next step's A -- the post-collision populations of each
 // node's neighbours evaluated from their (rho, u, F, X), the pull, Zou-He and
 // psi -> M^{n+1}.
 #include <hip/hip_runtime.h>
 
+#include "d3q19_common.hpp"
 #include "lbm_common.hpp"
 #include "lbm_internal.hpp"
 
@@ -34,55 +35,7 @@ namespace tplbm {
 
 namespace {
 
-// velocity set: 0 rest; 1..6 = +x -x +y -y +z -z; 7..18 edges (the table
-// the host uses to lay out initial states, kD3Q19* in lbm_internal.hpp)
-struct V3 {
-    int x, y, z;
-};
-__host__ __device__ constexpr V3 vel(int i) { return V3{kD3Q19x[i], kD3Q19y[i], kD3Q19z[i]}; }
-__host__ __device__ constexpr double wgt(int i) { return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
-// c . (a, b, c) over the nonzero components of c only, in x, y, z order.  In
-// the unrolled loops c is a compile-time constant, so a zero component costs
-// neither a load nor a multiply-add; the result equals the full sum (the
-// skipped terms are signed zeros).
-__device__ __forceinline__ double cdot(const V3 v, double a, double b, double c)
-{
-    double s = 0.0;
-    bool any = false;
-    if (v.x) { s = v.x * a; any = true; }
-    if (v.y) { s = any ? s + v.y * b : v.y * b; any = true; }
-    if (v.z) { s = any ? s + v.z * c : v.z * c; any = true; }
-    return s;
-}
-
-// opposite velocity
-__host__ __device__ constexpr int opp(int i)
-{
-    constexpr int o[19] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
-    return o[i];
-}
-
-template <class S>
-struct Pop;
-template <>
-struct Pop<double> {
-    __device__ static __forceinline__ double ld(const double *p, size_t i, double) { return p[i]; }
-    __device__ static __forceinline__ double st(double *p, size_t i, double v, double)
-    {
-        p[i] = v;
-        return v;
-    }
-};
-template <>
-struct Pop<float> {
-    __device__ static __forceinline__ double ld(const float *p, size_t i, double wr) { return wr + (double)p[i]; }
-    __device__ static __forceinline__ double st(float *p, size_t i, double v, double wr)
-    {
-        const float d = (float)(v - wr);
-        p[i] = d;
-        return wr + (double)d;
-    }
-};
+using namespace d3;
 
 // Lattice shape and the row a block works on.  A block owns whole x-rows
 // (fixed y, z); the nine rows at y + dy, z + dz (dy, dz in {-1, 0, 1}) have
@@ -90,10 +43,6 @@ struct Pop<float> {
 // row offset plus a wrapped x: 32-bit, no division per node.  On z-walls the
 // rows beyond the lattice are clamped to the wall row (only pulls use them,
 // and those populations are reconstructed).
-struct Grid3 {
-    int nx, ny, nz;
-    unsigned N;
-};
 
 struct Rows {
     unsigned b[3][3];  // [dz + 1][dy + 1]
@@ -160,65 +109,6 @@ __device__ __forceinline__ Xs xs_of(int x, int nx)
     q.v[1] = x;
     q.v[2] = wrap_x(x + 1, nx);
     return q;
-}
-
-// Zero-velocity wet-node reconstruction of the populations of a wall node
-// (z = 0 or nz - 1) that come from beyond the wall, with transverse momentum
-// corrections, then the density and momentum of the pulled set, for the
-// moment-state pass.  Pass A spells out the same statements in its body
-// (called from there, the array is not kept in registers).
-template <bool WALLS>
-__device__ __forceinline__ void pulled_moments3(double (&f)[19], int z, int nz, double &rho, double &jx,
-                                                double &jy, double &jz)
-{
-    if (WALLS && (z == 0 || z == nz - 1)) {
-        const int s = z == 0 ? 1 : -1;
-        double Nx = 0.0, Ny = 0.0;
-#pragma unroll
-        for (int i = 0; i < 19; ++i) {
-            const V3 v = vel(i);
-            if (v.z == 0) {
-                if (v.x) Nx += 0.5 * v.x * f[i];
-                if (v.y) Ny += 0.5 * v.y * f[i];
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < 19; ++i) {
-            const V3 v = vel(i);
-            if (v.z == s) {
-                double r = f[opp(i)];
-                if (v.x) r -= (double)v.x * Nx;
-                if (v.y) r -= (double)v.y * Ny;
-                f[i] = r;
-            }
-        }
-    }
-    rho = jx = jy = jz = 0.0;
-#pragma unroll
-    for (int i = 0; i < 19; ++i) {
-        const V3 v = vel(i);
-        rho += f[i];
-        if (v.x) jx += v.x * f[i];
-        if (v.y) jy += v.y * f[i];
-        if (v.z) jz += v.z * f[i];
-    }
-}
-
-// Post-collision population i at every relaxation time 1 of a node with
-// density rho, force-corrected velocity u, force F and sigma |F_int|^2 /
-// psi^2 = Xs2 (uu = u.u, uF = u.F): f_eq + half of Guo's term + the
-// isotropic sigma term.  Pass D closes the rest population instead, f*_0 =
-// rho - sum_{i>0} f*_i, which equals the i = 0 value in exact arithmetic.
-__device__ __forceinline__ double post_tau1(int i, double rho, double ux, double uy, double uz, double Fx, double Fy,
-                                            double Fz, double Xs2, double uu, double uF)
-{
-    const V3 v = vel(i);
-    const double w = wgt(i);
-    const double cu = cdot(v, ux, uy, uz);
-    const double cF = cdot(v, Fx, Fy, Fz);
-    const double c2 = (double)(v.x * v.x + v.y * v.y + v.z * v.z);
-    return w * (rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu) + 1.5 * (cF - uF) + 4.5 * cu * cF +
-                (c2 - 1.0) * 0.75 * Xs2);
 }
 
 // ---- pass A: pull, Zou-He, moments, psi ----------------------------------
@@ -536,111 +426,21 @@ __global__ __launch_bounds__(kStencilThreads) void d3q19_pass_c(const double *__
     }
 }
 
-// ---- pass D: second Heun stage, collision, stores, partials ------------------
-template <class S, bool WALLS>
-__global__ __launch_bounds__(kStencilThreads) void d3q19_pass_d(const double *__restrict__ Tin,
-                                                                double *__restrict__ Tout,
-                                                                const double *__restrict__ M,
-                                                                const double *__restrict__ U,
-                                                                const double *__restrict__ K1,
-                                                                S *__restrict__ fout, Phys c, Grid3 G,
-                                                                double *__restrict__ partials,
-                                                                StepState *__restrict__ st, int64_t step,
-                                                                const double *__restrict__ rref)
-{
-    using Sh = TileBD;
-    __shared__ double s_Tt[Sh::Region];  // T~ = T^n + k1
-    __shared__ double s_red[4 * kStencilThreads / 64];
-    __shared__ unsigned s_ured[kStencilThreads / 64];
-    const unsigned N = G.N;
-    Partial part = {0.0, 0.0, 0.0, 1e300, 0u};
-    const int ntiles = Sh::count(G.nx, G.ny, G.nz);
-    const TileIter it = tile_iter(ntiles);
-    for (int t = it.first; t < it.end; t += it.step) {
-        const Tile3 o = tile_origin<Sh>(G, t);
-        __syncthreads();
-        for (int r = threadIdx.x; r < Sh::Region; r += kStencilThreads) {
-            const unsigned m = region_index<WALLS, Sh>(G, o, r);
-            s_Tt[r] = Tin[m] + K1[m];
-        }
-        __syncthreads();
-        for (int k = threadIdx.x; k < Sh::Nodes; k += kStencilThreads) {
-            const int tx = k % Sh::TX, ty = (k / Sh::TX) % Sh::TY, tz = k / (Sh::TX * Sh::TY);
-            const int x = o.x0 + tx, y = o.y0 + ty, z = o.z0 + tz;
-            if (x >= G.nx || y >= G.ny || z >= G.nz) continue;
-            const unsigned n = ((unsigned)z * (unsigned)G.ny + (unsigned)y) * (unsigned)G.nx + (unsigned)x;
-            const bool wall = WALLS && (z == 0 || z == G.nz - 1);
-            const double rho = M[n], ux = U[n], uy = U[N + n], uz = U[2 * (size_t)N + n], T0 = Tin[n];
-            double Tn = T0;
-            if (!wall) {
-                const double k1 = K1[n];
-                double gx, gy, gz, lap;
-                grad_lap<Sh>(s_Tt, tx, ty, tz, T0 + k1, gx, gy, gz, lap);
-                const double divu = K1[N + n];
-                const double Z = c.eos == 0 ? cs_Z(c.b_quarter * rho) : 0.0;
-                const double k2 = -(ux * gx + uy * gy + uz * gz) + c.kappa_over_cv * rcp_pos(rho) * lap -
-                                  (T0 + k1) * c.R_over_cv * Z * divu;
-                Tn = T0 + 0.5 * (k1 + k2);
-            }
-            Tout[n] = Tn;
-            const double psi0 = M[4 * (size_t)N + n];
-            const double Fx = U[3 * (size_t)N + n], Fy = U[4 * (size_t)N + n], Fz = U[5 * (size_t)N + n];
-            const double Xs2 = U[6 * (size_t)N + n];
-            const double uu = ux * ux + uy * uy + uz * uz;
-            const double uF = ux * Fx + uy * Fy + uz * Fz;
-            double fs[19];
-            double rest = 0.0;
-#pragma unroll
-            for (int i = 1; i < 19; ++i) {
-                fs[i] = post_tau1(i, rho, ux, uy, uz, Fx, Fy, Fz, Xs2, uu, uF);
-                rest += fs[i];
-            }
-            fs[0] = rho - rest;
-            double nm = 0.0, down = 0.0, up = 0.0;
-            const double rr = sizeof(S) == 4 ? rref[z] : 0.0;  // this plane's reference (FP32)
-#pragma unroll
-            for (int i = 0; i < 19; ++i) {
-                const double v = Pop<S>::st(fout, (size_t)i * N + n, fs[i], wgt(i) * rr);
-                nm += v;
-                const int cz = vel(i).z;
-                if (cz < 0) down += v;
-                if (cz > 0) up += v;
-            }
-            if (WALLS) {
-                if (z == 0) nm -= down;
-                if (z == 1) nm += down;
-                if (z == G.nz - 2) nm += up;
-                if (z == G.nz - 1) nm -= up;
-            }
-            part.mass_n += rho;
-            part.mass_next += nm;
-            part.umax = fmax(part.umax, uu);
-            part.rmin = fmin(part.rmin, rho);
-            unsigned fl = 0u;
-            if (!(rho > 0.0)) fl |= kFlagRho;
-            if (c.eos == 0 && c.b_quarter * rho >= 1.0) fl |= kFlagEta;
-            if (psi0 != psi0) fl |= kFlagPsi;
-            if (rho != rho || uu != uu || Tn != Tn || nm != nm) fl |= kFlagNaN;
-            part.flags |= fl;
-        }
-    }
-    part = block_reduce<kStencilThreads>(part, s_red, s_ured);
-    finish_launch<kStencilThreads>(part, partials, st, step, (int)((step + 1) & 1), 1.0 / (double)N, s_red, s_ured);
-}
-
 // ---- moment-state pass (every tau = 1, FP64) ----------------------------------
 // With every relaxation time 1 the post-collision set of a node is a closed
 // function of its (rho, u, F, X) (post_tau1), so the state between steps can
 // be the level's M = (rho, j, psi) and T instead of the 19 populations.  This
-// pass replaces pass D and the next step's pass A: it stages rho, u, F, X and
+// pass takes the second Heun stage and the collision, fused with the next
+// step's pass A: it stages rho, u, F, X and
 // T~ = T^n + k1 on the region of a tile; every tile node
 //   * takes the second Heun stage (T^{n+1}, stored),
-//   * closes its own rest population, f*_0 = rho - sum_{i>0} f*_i, as pass D
-//     does,
+//   * closes its own rest population, f*_0 = rho - sum_{i>0} f*_i, as the
+//     population state's collision does,
 //   * pulls f_i(x) = f*_i(x - c_i), evaluating post_tau1 at the neighbour x - c_i,
 //   * reconstructs the wall populations, sums rho' and j', and evaluates
 //     psi(rho', T^{n+1}): M^{n+1}.
-// It evaluates the same expressions as passes D and A, so the two states agree
+// It evaluates the same expressions as the population state's collision and
+// pass A, so the two states agree
 // to rounding (the compiler may fuse multiply-adds differently in the two).
 template <bool WALLS>
 __global__ __launch_bounds__(kMomThreads) void d3q19_pass_m(const double *__restrict__ Tin,
@@ -812,25 +612,6 @@ int grid_tiles(int nx, int ny, int nz, int cus)
     return (int)(t < cap ? t : cap);
 }
 
-template <class S, bool WALLS>
-hipError_t step_t(const LatticeLaunch &L, double *M, double *U, double *K1)
-{
-    const Grid3 G{L.nx, L.ny, L.nz, (unsigned)((size_t)L.nx * L.ny * L.nz)};
-    const int gA = grid_rows(L.ny, L.nz, L.resident);
-    hipLaunchKernelGGL((d3q19_pass_a<S, WALLS>), dim3(gA), dim3(256), 0, L.stream, (const S *)L.fin, L.Tin, M,
-                       L.phys, G, L.rref);
-    const int gT = grid_tiles<TileBD>(L.nx, L.ny, L.nz, L.resident);
-    const int gC = grid_tiles<TileC>(L.nx, L.ny, L.nz, L.resident);
-    hipLaunchKernelGGL((d3q19_pass_b<WALLS>), dim3(gT), dim3(kStencilThreads), 0, L.stream, M, U, L.phys, G, L.st,
-                       (int)(L.step & 1));
-    hipLaunchKernelGGL((d3q19_pass_c<WALLS>), dim3(gC), dim3(kStencilThreads), 0, L.stream, L.Tin, M, U, K1,
-                       L.phys, G);
-    hipLaunchKernelGGL((d3q19_pass_d<S, WALLS>), dim3(gT), dim3(kStencilThreads), 0, L.stream, L.Tin, L.Tout, M,
-                       U, K1,
-                       (S *)L.fout, L.phys, G, L.partials, L.st, L.step, L.rref);
-    return hipGetLastError();
-}
-
 // Moment state: M^n is the state buffer fin, M^{n+1} goes to fout.
 template <bool WALLS>
 hipError_t step_mom_t(const LatticeLaunch &L, double *U, double *K1)
@@ -851,19 +632,18 @@ hipError_t step_mom_t(const LatticeLaunch &L, double *U, double *K1)
 
 }  // namespace
 
-// the larger of the grids that write per-block partials (pass D, or the
-// moment-state pass)
+// the larger of the grids that write per-block partials (the moment-state
+// pass, or the z-marching LBM kernel)
 int d3q19_num_blocks(int nx, int ny, int nz, int cus)
 {
-    const int d = grid_tiles<TileBD>(nx, ny, nz, cus), m = grid_tiles<TileM>(nx, ny, nz, cus);
-    return d > m ? d : m;
+    const int m = grid_tiles<TileM>(nx, ny, nz, cus), z = d3q19_march_blocks(nx, ny, nz, cus);
+    return m > z ? m : z;
 }
 
 hipError_t d3q19_launch_step(const LatticeLaunch &L, double *M, double *U, double *K1)
 {
     if (L.moments) return L.walls ? step_mom_t<true>(L, U, K1) : step_mom_t<false>(L, U, K1);
-    if (L.fp32) return L.walls ? step_t<float, true>(L, M, U, K1) : step_t<float, false>(L, M, U, K1);
-    return L.walls ? step_t<double, true>(L, M, U, K1) : step_t<double, false>(L, M, U, K1);
+    return d3q19_march_step(L, U);
 }
 
 hipError_t d3q19_launch_psi_init(const LatticeLaunch &L, double *M)

@@ -1,0 +1,600 @@
+// D3Q19 population-state update (FP32 deviations or FP64 populations, every
+// relaxation time 1) as two z-marching kernels.
+//
+// A block owns a 32 x 16 tile of (x, y) columns and a range of z planes (a
+// segment), and walks the planes upwards keeping one thread per column.  The
+// planes of the fields a stencil needs are staged in LDS, so each field is
+// read from memory once per node; the halo of a tile is the ring of columns
+// around it.
+//
+//   L (halo 1): pull f_i(x) = f*_i(x - c_i) of the previous level with the
+//     wet-node reconstruction on wall planes, rho and j (Eqs. Density,
+//     Momentum), psi (Eqs. EOS, InteractionPotential) -> a ring of four psi
+//     planes in LDS.  One plane behind: the Shan-Chen force (Eq.
+//     ShanChenForce, zero on wall planes) and gravity (Eqs. Gravity_*), u =
+//     (j + F/2)/rho, and the tau = 1 collision (f_eq plus half of Guo's term
+//     plus the isotropic sigma term), stored as the next level's f*; u and
+//     rho go to U for E; the diagnostics of the level (mass with wall
+//     multiplicities for <rho>, max |u|, min rho, flags) are reduced as in
+//     the other lattice kernels.
+//   E (halo 2): the energy equation (Eq. Energy_Equation) advanced by
+//     Heun's method with rho and u of the level frozen: T^n and u planes in
+//     LDS; one plane behind, div u and k1 = K(T^n) on the tile and its halo
+//     ring, T~ = T^n + k1 -> LDS; one more plane behind, k2 = K(T~) and
+//     T^{n+1} = T^n + (k1 + k2)/2 on the tile.  Wall planes keep T.
+//
+// The divergence of u is accumulated plane by plane: the contribution of a
+// plane to the divergence at its own plane and at the planes above and below
+// depends only on that plane's values, so u needs a single plane in LDS.
+//
+// Threads and columns: thread t owns interior column t (x = t % 32, y = t /
+// 32 of the tile).  The ring of columns around the tile at distance 1 (100
+// columns) and, for E, at distance 2 (108 columns) are taken as a second
+// column by threads 0..99 and 100..207.  A block of 512 threads (8 waves, one
+// block per compute unit) leaves each thread up to 256 registers for the
+// loads of the next plane in flight.  Column coordinates wrap in x and y
+// (periodic), so a tile that extends past the lattice edge reads the
+// periodic images; only columns inside the lattice store results.
+#include <hip/hip_runtime.h>
+
+#include "d3q19_common.hpp"
+#include "lbm_common.hpp"
+#include "lbm_internal.hpp"
+
+namespace tplbm {
+
+namespace {
+
+using namespace d3;
+
+constexpr int kTX = 32, kTY = 16;
+constexpr int kThreads = kTX * kTY;  // one thread per interior column: 512
+constexpr int kRing1 = 2 * (kTX + 2) + 2 * kTY;        // columns at distance 1: 100
+constexpr int kRing2 = 2 * (kTX + 4) + 2 * (kTY + 2);  // columns at distance 2: 108
+static_assert(kRing1 + kRing2 <= kThreads, "the halo rings are taken by one thread each");
+
+// Region of a tile with a halo of H columns: (kTX + 2H) x (kTY + 2H).
+template <int H>
+struct Region {
+    static constexpr int RX = kTX + 2 * H, RY = kTY + 2 * H, N = RX * RY;
+};
+
+// Region coordinates of column k of the ring at distance r from the tile,
+// inside a region of halo H >= r: bottom row, top row, left and right sides.
+__device__ __forceinline__ void ring_column(int r, int H, int k, int &rx, int &ry)
+{
+    const int w = kTX + 2 * r, h = kTY + 2 * r, off = H - r;
+    if (k < w) {
+        rx = k;
+        ry = 0;
+    } else if (k < 2 * w) {
+        rx = k - w;
+        ry = h - 1;
+    } else if (k < 2 * w + (h - 2)) {
+        rx = 0;
+        ry = 1 + (k - 2 * w);
+    } else {
+        rx = w - 1;
+        ry = 1 + (k - 2 * w - (h - 2));
+    }
+    rx += off;
+    ry += off;
+}
+
+__device__ __forceinline__ int wrap_mod(int v, int n)
+{
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// Block -> tile and z segment.  Blocks are dealt to the eight XCDs in turn;
+// XCD k takes the k-th contiguous eighth of the (segment-major) block list,
+// so the tiles one XCD runs together are neighbours in x and y of the same
+// segment and share their halo columns in its L2.
+struct MarchG3 {
+    int ntx, nty, nseg, nblocks;
+};
+
+struct Seg3 {
+    int x0, y0, z0, z1;
+};
+
+__device__ __forceinline__ Seg3 block_segment(const MarchG3 &M, int nz)
+{
+    const int nb = M.nblocks;
+    int b = blockIdx.x;
+    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
+    const int tiles = M.ntx * M.nty;
+    const int seg = b / tiles, tl = b - seg * tiles;
+    Seg3 s;
+    s.x0 = (tl % M.ntx) * kTX;
+    s.y0 = (tl / M.ntx) * kTY;
+    s.z0 = (int)((int64_t)seg * nz / M.nseg);
+    s.z1 = (int)((int64_t)(seg + 1) * nz / M.nseg);
+    return s;
+}
+
+// Plane index of z for loads: wrapped (periodic) or clamped to the wall
+// planes (walls).  `beyond` tells a plane outside a walled lattice.
+template <bool WALLS>
+__device__ __forceinline__ int plane_of(int z, int nz, bool &beyond)
+{
+    if (WALLS) {
+        beyond = z < 0 || z >= nz;
+        return z < 0 ? 0 : (z >= nz ? nz - 1 : z);
+    }
+    beyond = false;
+    return wrap_mod(z, nz);
+}
+
+// Column of a tile's region: its node offsets within a plane for dx, dy in
+// {-1, 0, 1} (periodic x, y), and whether it is a lattice node this block
+// owns (interior columns inside the lattice).
+struct Col {
+    unsigned xo[3];   // x + dx, wrapped
+    unsigned yo[3];   // (y + dy, wrapped) * nx
+    unsigned n0;      // yo[1] + xo[1]
+    int r;            // region index
+};
+
+__device__ __forceinline__ Col make_col(const Grid3 &G, int x0, int y0, int rx, int ry, int H, int RX)
+{
+    Col c;
+    const int gx = x0 + rx - H, gy = y0 + ry - H;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        c.xo[d] = (unsigned)wrap_mod(gx + d - 1, G.nx);
+        c.yo[d] = (unsigned)wrap_mod(gy + d - 1, G.ny) * (unsigned)G.nx;
+    }
+    c.n0 = c.yo[1] + c.xo[1];
+    c.r = ry * RX + rx;
+    return c;
+}
+
+// ---- L: pull, psi, force, u, collision -------------------------------------
+
+// Loads of one column at one plane: the nineteen pulled values f*_i(x - c_i)
+// as stored, and T.  Issued one plane ahead of their use.
+template <class S>
+struct PullLoads {
+    S f[19];
+    double T;
+};
+
+template <class S, bool WALLS>
+__device__ __forceinline__ void pull_issue(PullLoads<S> &P, const S *__restrict__ fin,
+                                           const double *__restrict__ Tin, const Grid3 &G, const Col &c, int a)
+{
+    bool beyond;
+    const int za = plane_of<WALLS>(a, G.nz, beyond);
+    if (beyond) {  // uniform: a plane beyond a wall is not read
+#pragma unroll
+        for (int i = 0; i < 19; ++i) P.f[i] = (S)0;
+        P.T = 0.0;
+        return;
+    }
+    const unsigned plane = (unsigned)G.nx * (unsigned)G.ny;
+    unsigned zoff[3];  // zoff[1 - c_z]: the plane a - c_z a population comes from
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        bool bb;
+        zoff[d] = (unsigned)plane_of<WALLS>(za + d - 1, G.nz, bb) * plane;
+    }
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+        const V3 v = vel(i);
+        P.f[i] = Pop<S>::raw(fin, (size_t)i * G.N + (zoff[1 - v.z] + c.yo[1 - v.y] + c.xo[1 - v.x]));
+    }
+    P.T = Tin[zoff[1] + c.n0];
+}
+
+// rho, j (wall reconstruction on wall planes) and psi of a pulled column
+template <class S, bool WALLS>
+__device__ __forceinline__ double pull_finish(const PullLoads<S> &P, const Phys &c, const Grid3 &G, int a,
+                                              const double *__restrict__ rref, double &rho, double &jx, double &jy,
+                                              double &jz)
+{
+    bool beyond;
+    const int za = plane_of<WALLS>(a, G.nz, beyond);
+    if (beyond) {
+        rho = jx = jy = jz = 0.0;
+        return 0.0;
+    }
+    double rz[3] = {0.0, 0.0, 0.0};
+    if (sizeof(S) == 4) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            bool bb;
+            rz[d] = rref[plane_of<WALLS>(za + d - 1, G.nz, bb)];
+        }
+    }
+    double f[19];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) f[i] = Pop<S>::val(P.f[i], wgt(i) * rz[1 - vel(i).z]);
+    pulled_moments3<WALLS>(f, za, G.nz, rho, jx, jy, jz);
+    double Z;
+    return psi_and_Z(c, rho, P.T, Z);
+}
+
+template <class S, bool WALLS>
+__global__ __launch_bounds__(kThreads) void d3q19_march_l(const S *__restrict__ fin, S *__restrict__ fout,
+                                                          const double *__restrict__ Tin, double *__restrict__ U,
+                                                          Phys c, Grid3 G, MarchG3 M, double *__restrict__ partials,
+                                                          StepState *__restrict__ st, int64_t step,
+                                                          const double *__restrict__ rref)
+{
+    using R = Region<1>;
+    __shared__ double s_psi[4][R::N];
+    __shared__ double s_red[4 * kThreads / 64];
+    __shared__ unsigned s_ured[kThreads / 64];
+    const int t = threadIdx.x;
+    const unsigned N = G.N;
+    const Seg3 sg = block_segment(M, G.nz);
+    const int tx = t % kTX, ty = t / kTX;
+    const Col own = make_col(G, sg.x0, sg.y0, tx + 1, ty + 1, 1, R::RX);
+    const bool mine = sg.x0 + tx < G.nx && sg.y0 + ty < G.ny;  // a lattice node of this tile
+    const bool has2 = t < kRing1;
+    int rx2 = 0, ry2 = 0;
+    if (has2) ring_column(1, 1, t, rx2, ry2);
+    const Col two = make_col(G, sg.x0, sg.y0, rx2, ry2, 1, R::RX);
+    const double sub = gravity_sub(c.form, st->mean[step & 1], c.rho_v);
+    const unsigned plane = (unsigned)G.nx * (unsigned)G.ny;
+
+    Partial part = {0.0, 0.0, 0.0, 1e300, 0u};
+    double rho_b = 0.0, jx_b = 0.0, jy_b = 0.0, jz_b = 0.0;  // plane a - 1 of the own column
+    // planes z0 - 1 .. z1 are pulled; the force, velocity and collision of
+    // plane a - 1 follow the pull of plane a
+    PullLoads<S> pre;
+    pull_issue<S, WALLS>(pre, fin, Tin, G, own, sg.z0 - 1);
+    for (int a = sg.z0 - 1; a <= sg.z1; ++a) {
+        // the ring column's loads are issued first and waited for last
+        PullLoads<S> rg;
+        if (has2) pull_issue<S, WALLS>(rg, fin, Tin, G, two, a);
+        double rho, jx, jy, jz;
+        const double psi = pull_finish<S, WALLS>(pre, c, G, a, rref, rho, jx, jy, jz);
+        if (a < sg.z1) pull_issue<S, WALLS>(pre, fin, Tin, G, own, a + 1);
+        s_psi[a & 3][own.r] = psi;
+        if (has2) {
+            double r2, x2, y2, z2;
+            s_psi[a & 3][two.r] = pull_finish<S, WALLS>(rg, c, G, a, rref, r2, x2, y2, z2);
+        }
+        __syncthreads();
+
+        const int b = a - 1;
+        if (b >= sg.z0 && mine) {
+            const unsigned n = (unsigned)b * plane + own.n0;
+            const bool wall = WALLS && (b == 0 || b == G.nz - 1);
+            double Fx = 0.0, Fy = 0.0, Fz = 0.0, Xs2 = 0.0;
+            const double psi0 = s_psi[b & 3][own.r];
+            if (!wall) {
+                double sx = 0.0, sy = 0.0, sz = 0.0;
+#pragma unroll
+                for (int i = 1; i < 19; ++i) {
+                    const V3 v = vel(i);
+                    const double w = i < 7 ? 1.0 / 6.0 : 1.0 / 12.0;
+                    const double p = s_psi[(b + v.z) & 3][own.r + v.y * R::RX + v.x];
+                    if (v.x) sx += w * v.x * p;
+                    if (v.y) sy += w * v.y * p;
+                    if (v.z) sz += w * v.z * p;
+                }
+                const double mg = -c.G * psi0;
+                Fx = mg * sx;
+                Fy = mg * sy;
+                Fz = mg * sz + gravity_force(rho_b, sub, c.g);
+                Xs2 = c.sigma * c.G2 * (sx * sx + sy * sy + sz * sz);  // sigma |F_int|^2 / psi^2
+            }
+            const double inv = rcp_pos(rho_b);
+            const double ux = (jx_b + 0.5 * Fx) * inv, uy = (jy_b + 0.5 * Fy) * inv, uz = (jz_b + 0.5 * Fz) * inv;
+            U[n] = ux;
+            U[N + n] = uy;
+            U[2 * (size_t)N + n] = uz;
+            U[3 * (size_t)N + n] = rho_b;
+            const double uu = ux * ux + uy * uy + uz * uz;
+            const double uF = ux * Fx + uy * Fy + uz * Fz;
+            // post-collision populations stored as they are formed; the rest
+            // population closes the mass
+            const double rr = sizeof(S) == 4 ? rref[b] : 0.0;  // this plane's reference (FP32)
+            double rest = 0.0, nm = 0.0, down = 0.0, up = 0.0;
+#pragma unroll
+            for (int i = 1; i < 19; ++i) {
+                const double fi = post_tau1(i, rho_b, ux, uy, uz, Fx, Fy, Fz, Xs2, uu, uF);
+                rest += fi;
+                const double v = Pop<S>::st(fout, (size_t)i * N + n, fi, wgt(i) * rr);
+                nm += v;
+                const int cz = vel(i).z;
+                if (cz < 0) down += v;
+                if (cz > 0) up += v;
+            }
+            nm += Pop<S>::st(fout, n, rho_b - rest, wgt(0) * rr);
+            if (WALLS) {
+                if (b == 0) nm -= down;
+                if (b == 1) nm += down;
+                if (b == G.nz - 2) nm += up;
+                if (b == G.nz - 1) nm -= up;
+            }
+            part.mass_n += rho_b;
+            part.mass_next += nm;
+            part.umax = fmax(part.umax, uu);
+            part.rmin = fmin(part.rmin, rho_b);
+            unsigned fl = 0u;
+            if (!(rho_b > 0.0)) fl |= kFlagRho;
+            if (c.eos == 0 && c.b_quarter * rho_b >= 1.0) fl |= kFlagEta;
+            if (psi0 != psi0) fl |= kFlagPsi;
+            if (rho_b != rho_b || uu != uu || nm != nm) fl |= kFlagNaN;
+            part.flags |= fl;
+        }
+        rho_b = rho;
+        jx_b = jx;
+        jy_b = jy;
+        jz_b = jz;
+    }
+    part = block_reduce<kThreads>(part, s_red, s_ured);
+    finish_launch<kThreads>(part, partials, st, step, (int)((step + 1) & 1), 1.0 / (double)N, s_red, s_ured);
+}
+
+// ---- E: the energy equation --------------------------------------------------
+
+// Per-plane contributions of u to div u = 3 sum_i w_i c_i . u(x + c_i):
+// cen to the plane itself (in-plane neighbours), side to the planes above and
+// below (their in-plane x, y offsets), zc with + to the plane below and - to
+// the plane above (the z components).
+struct DivPart {
+    double cen, side, zc;
+};
+
+template <int RX>
+__device__ __forceinline__ DivPart div_part(const double *__restrict__ ux, const double *__restrict__ uy,
+                                            const double *__restrict__ uz, int r)
+{
+    constexpr double w1 = 1.0 / 18.0, w2 = 1.0 / 36.0;
+    const double dx = ux[r + 1] - ux[r - 1];
+    const double dxy = (ux[r + 1 + RX] - ux[r - 1 + RX]) + (ux[r + 1 - RX] - ux[r - 1 - RX]);
+    const double dy = uy[r + RX] - uy[r - RX];
+    const double dyx = (uy[r + RX + 1] - uy[r - RX + 1]) + (uy[r + RX - 1] - uy[r - RX - 1]);
+    const double s4 = (uz[r + 1] + uz[r - 1]) + (uz[r + RX] + uz[r - RX]);
+    DivPart p;
+    p.cen = (w1 * dx + w2 * dxy) + (w1 * dy + w2 * dyx);
+    p.side = w2 * (dx + dy);
+    p.zc = w1 * uz[r] + w2 * s4;
+    return p;
+}
+
+// Isotropic gradient and Laplacian of a field from three LDS planes (below,
+// own, above) at region index r: grad = 3 sum w c phi, lap = 6 sum w (phi_i -
+// phi_0), in the order of the velocity set.
+template <int RX>
+__device__ __forceinline__ void grad_lap_planes(const double *__restrict__ pm, const double *__restrict__ p0,
+                                                const double *__restrict__ pp, int r, double &gx, double &gy,
+                                                double &gz, double &lap)
+{
+    const double c0 = p0[r];
+    gx = gy = gz = lap = 0.0;
+#pragma unroll
+    for (int i = 1; i < 19; ++i) {
+        const V3 v = vel(i);
+        const double *pl = v.z < 0 ? pm : (v.z > 0 ? pp : p0);
+        const double p = pl[r + v.y * RX + v.x];
+        const double w = wgt(i);
+        if (v.x) gx += w * v.x * p;
+        if (v.y) gy += w * v.y * p;
+        if (v.z) gz += w * v.z * p;
+        lap += w * (p - c0);
+    }
+    gx *= 3.0;
+    gy *= 3.0;
+    gz *= 3.0;
+    lap *= 6.0;
+}
+
+// Values of one column at one plane, as E loads them.
+struct EVals {
+    double T, ux, uy, uz, rho;
+};
+
+__device__ __forceinline__ EVals load_e(const double *__restrict__ Tin, const double *__restrict__ U, unsigned N,
+                                        unsigned n, bool beyond)
+{
+    EVals v = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (!beyond) {
+        v.T = Tin[n];
+        v.ux = U[n];
+        v.uy = U[N + n];
+        v.uz = U[2 * (size_t)N + n];
+        v.rho = U[3 * (size_t)N + n];
+    }
+    return v;
+}
+
+// div u of a column accumulated over the planes: when the contributions of
+// plane a arrive, div(a - 1) = pend + side(a) + zc(a) is complete and pend
+// becomes cen(a) + side(a - 1) - zc(a - 1), the part of div(a) known so far.
+struct DivAcc {
+    double pend, side, zc;
+    __device__ __forceinline__ double push(const DivPart &p)
+    {
+        const double done = pend + p.side + p.zc;
+        pend = p.cen + side - zc;
+        side = p.side;
+        zc = p.zc;
+        return 3.0 * done;
+    }
+};
+
+// The energy-equation coefficients of a node with rho and u frozen: K(phi) =
+// -u . grad phi + a1 lap phi - phi a2 with a1 = kappa/(rho c_v) and a2 = (R/c_v)
+// Z(eta) div u (Z = 0 for the ideal gas).
+struct ECoef {
+    double ux, uy, uz, a1, a2;
+};
+
+__device__ __forceinline__ ECoef energy_coef(const Phys &c, double ux, double uy, double uz, double rho, double divu)
+{
+    const double Z = c.eos == 0 ? cs_Z(c.b_quarter * rho) : 0.0;
+    return ECoef{ux, uy, uz, c.kappa_over_cv * rcp_pos(rho), c.R_over_cv * Z * divu};
+}
+
+__device__ __forceinline__ double energy_k(const ECoef &k, double phi0, double gx, double gy, double gz, double lap)
+{
+    return -(k.ux * gx + k.uy * gy + k.uz * gz) + k.a1 * lap - phi0 * k.a2;
+}
+
+template <bool WALLS>
+__global__ __launch_bounds__(kThreads) void d3q19_march_e(const double *__restrict__ Tin, double *__restrict__ Tout,
+                                                          const double *__restrict__ U, Phys c, Grid3 G, MarchG3 M)
+{
+    using R2 = Region<2>;
+    using R1 = Region<1>;
+    __shared__ double s_T[3][R2::N];     // T^n, planes a - 2 .. a
+    __shared__ double s_u[2][3][R2::N];  // u, planes a - 1 and a
+    __shared__ double s_Tt[3][R1::N];    // T~, planes a - 3 .. a - 1
+    const int t = threadIdx.x;
+    const unsigned N = G.N;
+    const Seg3 sg = block_segment(M, G.nz);
+    const int tx = t % kTX, ty = t / kTX;
+    const Col own = make_col(G, sg.x0, sg.y0, tx + 2, ty + 2, 2, R2::RX);
+    const int own_r1 = (ty + 1) * R1::RX + (tx + 1);
+    const bool mine = sg.x0 + tx < G.nx && sg.y0 + ty < G.ny;
+    // second column: ring 1 (threads 0..99, with a k1 and T~ of its own) or
+    // ring 2 (threads 100..207, loads only)
+    const bool ring1 = t < kRing1, ring2 = t >= kRing1 && t < kRing1 + kRing2;
+    int rx2 = 0, ry2 = 0;
+    if (ring1) ring_column(1, 2, t, rx2, ry2);
+    if (ring2) ring_column(2, 2, t - kRing1, rx2, ry2);
+    const Col two = make_col(G, sg.x0, sg.y0, rx2, ry2, 2, R2::RX);
+    const int two_r1 = (ry2 - 1) * R1::RX + (rx2 - 1);
+    const unsigned plane = (unsigned)G.nx * (unsigned)G.ny;
+
+    DivAcc dA = {0.0, 0.0, 0.0}, dB = {0.0, 0.0, 0.0};
+    double rhoA = 0.0, rhoB = 0.0;  // rho of plane a - 1
+    // the own column's second stage of plane a - 2: T, k1 and coefficients
+    double hT = 0.0, hk1 = 0.0;
+    ECoef hk = {0.0, 0.0, 0.0, 0.0, 0.0};
+    // loads of planes z0 - 2 .. z1 + 1, one plane ahead of their use; k1 and
+    // T~ of plane a - 1 (planes z0 - 1 .. z1); T^{n+1} of plane a - 2 (planes
+    // z0 .. z1 - 1)
+    EVals nA, nB = {0.0, 0.0, 0.0, 0.0, 0.0};
+    {
+        bool beyond;
+        const unsigned zo = (unsigned)plane_of<WALLS>(sg.z0 - 2, G.nz, beyond) * plane;
+        nA = load_e(Tin, U, N, zo + own.n0, beyond);
+        if (ring1 || ring2) nB = load_e(Tin, U, N, zo + two.n0, beyond);
+    }
+    for (int a = sg.z0 - 2; a <= sg.z1 + 1; ++a) {
+        const int sT = wrap_mod(a, 3), su = a & 1;
+        s_T[sT][own.r] = nA.T;
+        s_u[su][0][own.r] = nA.ux;
+        s_u[su][1][own.r] = nA.uy;
+        s_u[su][2][own.r] = nA.uz;
+        if (ring1 || ring2) {
+            s_T[sT][two.r] = nB.T;
+            s_u[su][0][two.r] = nB.ux;
+            s_u[su][1][two.r] = nB.uy;
+            s_u[su][2][two.r] = nB.uz;
+        }
+        const double rhoA0 = nA.rho, rhoB0 = nB.rho;
+        if (a <= sg.z1) {
+            bool beyond;
+            const unsigned zo = (unsigned)plane_of<WALLS>(a + 1, G.nz, beyond) * plane;
+            nA = load_e(Tin, U, N, zo + own.n0, beyond);
+            if (ring1 || ring2) nB = load_e(Tin, U, N, zo + two.n0, beyond);
+        }
+        __syncthreads();
+
+        // div u of plane b = a - 1 at the own and ring-1 columns, then the
+        // first stage there: k1 = K(T^n), T~ = T^n + k1 (wall planes and the
+        // planes beyond them keep T)
+        const int b = a - 1;
+        const double divA = dA.push(div_part<R2::RX>(s_u[su][0], s_u[su][1], s_u[su][2], own.r));
+        double divB = 0.0;
+        if (ring1) divB = dB.push(div_part<R2::RX>(s_u[su][0], s_u[su][1], s_u[su][2], two.r));
+        const bool bwall = WALLS && (b <= 0 || b >= G.nz - 1);
+        const int sb = wrap_mod(b, 3), ub = b & 1;
+        const double *Tm = s_T[wrap_mod(b - 1, 3)], *T0 = s_T[sb], *Tp = s_T[sT];
+        double k1b = 0.0, Tb = 0.0;
+        ECoef kb = {0.0, 0.0, 0.0, 0.0, 0.0};
+        if (b >= sg.z0 - 1) {
+            Tb = T0[own.r];
+            double Tt = Tb;
+            if (!bwall) {
+                kb = energy_coef(c, s_u[ub][0][own.r], s_u[ub][1][own.r], s_u[ub][2][own.r], rhoA, divA);
+                double gx, gy, gz, lap;
+                grad_lap_planes<R2::RX>(Tm, T0, Tp, own.r, gx, gy, gz, lap);
+                k1b = energy_k(kb, Tb, gx, gy, gz, lap);
+                Tt = Tb + k1b;
+            }
+            s_Tt[sb][own_r1] = Tt;
+            if (ring1) {
+                const double T2 = T0[two.r];
+                double Tt2 = T2;
+                if (!bwall) {
+                    const ECoef k2 = energy_coef(c, s_u[ub][0][two.r], s_u[ub][1][two.r], s_u[ub][2][two.r], rhoB, divB);
+                    double gx, gy, gz, lap;
+                    grad_lap_planes<R2::RX>(Tm, T0, Tp, two.r, gx, gy, gz, lap);
+                    Tt2 = T2 + energy_k(k2, T2, gx, gy, gz, lap);
+                }
+                s_Tt[sb][two_r1] = Tt2;
+            }
+        }
+        rhoA = rhoA0;
+        rhoB = rhoB0;
+        __syncthreads();
+
+        // second stage of plane q = a - 2 on the tile: k2 = K(T~),
+        // T^{n+1} = T^n + (k1 + k2)/2
+        const int q = a - 2;
+        if (q >= sg.z0 && q < sg.z1 && mine) {
+            double Tn = hT;
+            if (!(WALLS && (q == 0 || q == G.nz - 1))) {
+                const int sq = wrap_mod(q, 3);
+                double gx, gy, gz, lap;
+                grad_lap_planes<R1::RX>(s_Tt[wrap_mod(q - 1, 3)], s_Tt[sq], s_Tt[wrap_mod(q + 1, 3)], own_r1, gx, gy,
+                                        gz, lap);
+                const double k2 = energy_k(hk, s_Tt[sq][own_r1], gx, gy, gz, lap);
+                Tn = hT + 0.5 * (hk1 + k2);
+            }
+            Tout[(unsigned)q * plane + own.n0] = Tn;
+        }
+        hT = Tb;
+        hk1 = k1b;
+        hk = kb;
+    }
+}
+
+MarchG3 march_grid3(int nx, int ny, int nz, int cus)
+{
+    MarchG3 g;
+    g.ntx = (nx + kTX - 1) / kTX;
+    g.nty = (ny + kTY - 1) / kTY;
+    const long tiles = (long)g.ntx * g.nty;
+    long nseg = (cus + tiles - 1) / tiles;
+    const long maxseg = nz / 8 > 0 ? nz / 8 : 1;  // segments of at least 8 planes
+    if (nseg > maxseg) nseg = maxseg;
+    if (nseg < 1) nseg = 1;
+    g.nseg = (int)nseg;
+    g.nblocks = (int)(tiles * nseg);
+    return g;
+}
+
+template <class S, bool WALLS>
+hipError_t march_t(const LatticeLaunch &L, double *U)
+{
+    const Grid3 G{L.nx, L.ny, L.nz, (unsigned)((size_t)L.nx * L.ny * L.nz)};
+    const MarchG3 M = march_grid3(L.nx, L.ny, L.nz, L.resident);
+    hipLaunchKernelGGL((d3q19_march_l<S, WALLS>), dim3(M.nblocks), dim3(kThreads), 0, L.stream, (const S *)L.fin,
+                       (S *)L.fout, L.Tin, U, L.phys, G, M, L.partials, L.st, L.step, L.rref);
+    hipLaunchKernelGGL((d3q19_march_e<WALLS>), dim3(M.nblocks), dim3(kThreads), 0, L.stream, L.Tin, L.Tout,
+                       (const double *)U, L.phys, G, M);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int d3q19_march_blocks(int nx, int ny, int nz, int cus) { return march_grid3(nx, ny, nz, cus).nblocks; }
+
+hipError_t d3q19_march_step(const LatticeLaunch &L, double *U)
+{
+    if (L.fp32) return L.walls ? march_t<float, true>(L, U) : march_t<float, false>(L, U);
+    return L.walls ? march_t<double, true>(L, U) : march_t<double, false>(L, U);
+}
+
+}  // namespace tplbm

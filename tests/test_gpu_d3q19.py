@@ -85,6 +85,37 @@ def test_small_lattices_fp64(T, orc, crit, shape, walls, form):
     assert np.abs(got["p_nn"] - want["p_nn"]).max() / (0.5 * want["rho"].max() ** 2) < 1e-12
 
 
+@pytest.mark.parametrize("shape,walls,form", [((70, 9, 11), True, 2), ((33, 40, 7), False, 1),
+                                              ((40, 35, 12), True, 3), ((1, 1, 20), True, 2),
+                                              ((6, 5, 14), True, 1), ((65, 3, 9), False, 2)])
+def test_population_state_fp64(T, orc, crit, shape, walls, form):
+    """The nineteen-population state (the z-marching kernels) against the
+    oracle, on lattices with several 32 x 32 tiles, ragged tile edges, tiles
+    wider than the lattice, z segments and both boundary kinds."""
+    _log(f"case d3q19 fp64 populations {shape} walls={walls} form={form}")
+    rho0, T0 = _state(orc, crit, shape, 11, max(1, shape[2] // 3))
+    want = _oracle(orc, shape, walls, form, 2e-4, rho0, T0, 200)
+    got = _gpu(T, shape, walls, form, 2e-4, rho0, T0, 200, state=T.STATE_POPULATIONS)
+    for k in ("rho", "T"):
+        assert _rel(got[k], want[k]) < 1e-12, (k, _rel(got[k], want[k]))
+    for k in ("ux", "uy", "uz"):
+        assert np.abs(got[k] - want[k]).max() < 1e-13, k
+    assert np.abs(got["p_nn"] - want["p_nn"]).max() / (0.5 * want["rho"].max() ** 2) < 1e-12
+    assert got["diag"]["flags"] == 0
+
+
+def test_fp32_deviation_several_tiles(T, orc, crit):
+    """FP32 deviations on a lattice of several tiles and z segments."""
+    shape = (40, 36, 17)
+    rho0, T0 = _state(orc, crit, shape, 12, 6)
+    want = _oracle(orc, shape, True, 2, 1e-4, rho0, T0, 300)
+    got = _gpu(T, shape, True, 2, 1e-4, rho0, T0, 300, precision=1)
+    err = _rel(got["rho"], want["rho"])
+    _log(f"  fp32dev {shape} rho rel err {err:.3e}")
+    assert err < 1e-5
+    assert _rel(got["T"], want["T"]) < 1e-5
+
+
 @pytest.mark.parametrize("shape,walls,form", [((70, 9, 11), True, 2), ((33, 10, 7), False, 1),
                                               ((40, 12, 9), True, 3)])
 def test_moment_state_matches_population_state(T, orc, crit, shape, walls, form):
