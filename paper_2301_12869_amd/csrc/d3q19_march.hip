@@ -53,10 +53,12 @@ constexpr int kRing1 = 2 * (kTX + 2) + 2 * kTY;        // columns at distance 1:
 constexpr int kRing2 = 2 * (kTX + 4) + 2 * (kTY + 2);  // columns at distance 2: 108
 static_assert(kRing1 + kRing2 <= kThreads, "the halo rings are taken by one thread each");
 
-// Region of a tile with a halo of H columns: (kTX + 2H) x (kTY + 2H).
+// Region of a tile with a halo of H columns: (kTX + 2H) x (kTY + 2H), kept
+// in LDS with an odd row stride RX (in doubles), so that a run of columns down
+// the region's sides (the ring columns) falls into distinct banks.
 template <int H>
 struct Region {
-    static constexpr int RX = kTX + 2 * H, RY = kTY + 2 * H, N = RX * RY;
+    static constexpr int W = kTX + 2 * H, RY = kTY + 2 * H, RX = W + 1, N = RX * RY;
 };
 
 // Region coordinates of column k of the ring at distance r from the tile,
@@ -85,6 +87,65 @@ __device__ __forceinline__ int wrap_mod(int v, int n)
 {
     v %= n;
     return v < 0 ? v + n : v;
+}
+
+// Population-plane accesses through buffer resources: the base address of a
+// z layer of a population plane is uniform (scalar registers) and a lane's
+// column offset within the layer goes in the vector offset, so an access
+// costs no vector address arithmetic.  Offsets are in bytes within one layer.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr int kRsrcWord3 = 0x00020000;  // raw 32-bit dword access (gfx9 family)
+
+// one z layer (nx ny nodes) of a population plane; its base moves with the
+// layer, so the resources are formed per layer rather than held across the
+// march
+template <class S>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t layer_rsrc(const S *base, unsigned plane)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)(plane * (unsigned)sizeof(S)), kRsrcWord3);
+}
+// the same with an empty range when `none` (a layer beyond a wall): its
+// loads return zero without a memory access
+template <class S>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t layer_rsrc(const S *base, unsigned plane, bool none)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, none ? 0 : (int)(plane * (unsigned)sizeof(S)),
+                                             kRsrcWord3);
+}
+// added to a lane's byte offset, it puts the access out of every layer's
+// range (loads return zero, stores are dropped): lanes without a second
+// column
+constexpr unsigned kOut = 0x80000000u;
+__device__ __forceinline__ float buf_ld(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ double buf_ld(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, double)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, double v)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, (int)soff, 0);
+}
+// store a population value (as an FP32 deviation from wr, or FP64) and
+// return it as stored
+__device__ __forceinline__ double pop_st(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, double v, double wr,
+                                         float)
+{
+    const float d = (float)(v - wr);
+    buf_st(r, voff, soff, d);
+    return wr + (double)d;
+}
+__device__ __forceinline__ double pop_st(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, double v, double,
+                                         double)
+{
+    buf_st(r, voff, soff, v);
+    return v;
 }
 
 // Block -> tile and z segment.  Blocks are dealt to the eight XCDs in turn;
@@ -134,12 +195,15 @@ struct Col {
     unsigned xo[3];   // x + dx, wrapped
     unsigned yo[3];   // (y + dy, wrapped) * nx
     unsigned n0;      // yo[1] + xo[1]
+    unsigned oob;     // 0, or kOut for a lane that has no such column
     int r;            // region index
 };
 
-__device__ __forceinline__ Col make_col(const Grid3 &G, int x0, int y0, int rx, int ry, int H, int RX)
+__device__ __forceinline__ Col make_col(const Grid3 &G, int x0, int y0, int rx, int ry, int H, int RX,
+                                        bool exists = true)
 {
     Col c;
+    c.oob = exists ? 0u : kOut;
     const int gx = x0 + rx - H, gy = y0 + ry - H;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -165,14 +229,10 @@ template <class S, bool WALLS>
 __device__ __forceinline__ void pull_issue(PullLoads<S> &P, const S *__restrict__ fin,
                                            const double *__restrict__ Tin, const Grid3 &G, const Col &c, int a)
 {
+    // a plane beyond a wall reads zeros (an empty range): no branch, so the
+    // loads stay in flight across the step that issues them
     bool beyond;
     const int za = plane_of<WALLS>(a, G.nz, beyond);
-    if (beyond) {  // uniform: a plane beyond a wall is not read
-#pragma unroll
-        for (int i = 0; i < 19; ++i) P.f[i] = (S)0;
-        P.T = 0.0;
-        return;
-    }
     const unsigned plane = (unsigned)G.nx * (unsigned)G.ny;
     unsigned zoff[3];  // zoff[1 - c_z]: the plane a - c_z a population comes from
 #pragma unroll
@@ -183,9 +243,10 @@ __device__ __forceinline__ void pull_issue(PullLoads<S> &P, const S *__restrict_
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
         const V3 v = vel(i);
-        P.f[i] = Pop<S>::raw(fin, (size_t)i * G.N + (zoff[1 - v.z] + c.yo[1 - v.y] + c.xo[1 - v.x]));
+        P.f[i] = buf_ld(layer_rsrc(fin + (size_t)i * G.N + zoff[1 - v.z], plane, beyond),
+                        (c.yo[1 - v.y] + c.xo[1 - v.x]) * (unsigned)sizeof(S) + c.oob, 0u, S());
     }
-    P.T = Tin[zoff[1] + c.n0];
+    P.T = buf_ld(layer_rsrc(Tin + zoff[1], plane, beyond), c.n0 * 8u + c.oob, 0u, 0.0);
 }
 
 // rho, j (wall reconstruction on wall planes) and psi of a pulled column
@@ -196,10 +257,6 @@ __device__ __forceinline__ double pull_finish(const PullLoads<S> &P, const Phys 
 {
     bool beyond;
     const int za = plane_of<WALLS>(a, G.nz, beyond);
-    if (beyond) {
-        rho = jx = jy = jz = 0.0;
-        return 0.0;
-    }
     double rz[3] = {0.0, 0.0, 0.0};
     if (sizeof(S) == 4) {
 #pragma unroll
@@ -211,9 +268,49 @@ __device__ __forceinline__ double pull_finish(const PullLoads<S> &P, const Phys 
     double f[19];
 #pragma unroll
     for (int i = 0; i < 19; ++i) f[i] = Pop<S>::val(P.f[i], wgt(i) * rz[1 - vel(i).z]);
-    pulled_moments3<WALLS>(f, za, G.nz, rho, jx, jy, jz);
+    // the statements of pulled_moments3, written out here: passed to it by
+    // reference, the array would be kept in private memory, whose accesses
+    // share the wait counter of the loads in flight
+    if (WALLS && (za == 0 || za == G.nz - 1)) {
+        const int s = za == 0 ? 1 : -1;
+        double Nx = 0.0, Ny = 0.0;
+#pragma unroll
+        for (int i = 0; i < 19; ++i) {
+            const V3 v = vel(i);
+            if (v.z == 0) {
+                if (v.x) Nx += 0.5 * v.x * f[i];
+                if (v.y) Ny += 0.5 * v.y * f[i];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 19; ++i) {
+            const V3 v = vel(i);
+            if (v.z == s) {
+                double r = f[opp(i)];
+                if (v.x) r -= (double)v.x * Nx;
+                if (v.y) r -= (double)v.y * Ny;
+                f[i] = r;
+            }
+        }
+    }
+    rho = jx = jy = jz = 0.0;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+        const V3 v = vel(i);
+        rho += f[i];
+        if (v.x) jx += v.x * f[i];
+        if (v.y) jy += v.y * f[i];
+        if (v.z) jz += v.z * f[i];
+    }
     double Z;
-    return psi_and_Z(c, rho, P.T, Z);
+    const double psi = psi_and_Z(c, rho, P.T, Z);
+    // a plane beyond a wall holds nothing (its values feed no stencil that
+    // is evaluated)
+    rho = beyond ? 0.0 : rho;
+    jx = beyond ? 0.0 : jx;
+    jy = beyond ? 0.0 : jy;
+    jz = beyond ? 0.0 : jz;
+    return beyond ? 0.0 : psi;
 }
 
 template <class S, bool WALLS>
@@ -236,7 +333,7 @@ __global__ __launch_bounds__(kThreads) void d3q19_march_l(const S *__restrict__ 
     const bool has2 = t < kRing1;
     int rx2 = 0, ry2 = 0;
     if (has2) ring_column(1, 1, t, rx2, ry2);
-    const Col two = make_col(G, sg.x0, sg.y0, rx2, ry2, 1, R::RX);
+    const Col two = make_col(G, sg.x0, sg.y0, rx2, ry2, 1, R::RX, has2);
     const double sub = gravity_sub(c.form, st->mean[step & 1], c.rho_v);
     const unsigned plane = (unsigned)G.nx * (unsigned)G.ny;
 
@@ -247,12 +344,15 @@ __global__ __launch_bounds__(kThreads) void d3q19_march_l(const S *__restrict__ 
     PullLoads<S> pre;
     pull_issue<S, WALLS>(pre, fin, Tin, G, own, sg.z0 - 1);
     for (int a = sg.z0 - 1; a <= sg.z1; ++a) {
-        // the ring column's loads are issued first and waited for last
+        // the ring column's loads are issued first and waited for last (on
+        // lanes without one they are out of range); the own column's loads
+        // of plane a + 1 are issued before the plane's first use of memory
+        // results
         PullLoads<S> rg;
-        if (has2) pull_issue<S, WALLS>(rg, fin, Tin, G, two, a);
+        pull_issue<S, WALLS>(rg, fin, Tin, G, two, a);
         double rho, jx, jy, jz;
         const double psi = pull_finish<S, WALLS>(pre, c, G, a, rref, rho, jx, jy, jz);
-        if (a < sg.z1) pull_issue<S, WALLS>(pre, fin, Tin, G, own, a + 1);
+        pull_issue<S, WALLS>(pre, fin, Tin, G, own, a + 1);
         s_psi[a & 3][own.r] = psi;
         if (has2) {
             double r2, x2, y2, z2;
@@ -260,9 +360,15 @@ __global__ __launch_bounds__(kThreads) void d3q19_march_l(const S *__restrict__ 
         }
         __syncthreads();
 
+        // plane b = a - 1: force, velocity, collision.  Every lane computes;
+        // stores of a plane outside the segment (an empty range) and of
+        // lanes outside the lattice (an out-of-range offset) are dropped, so
+        // no memory access sits in a branch.
         const int b = a - 1;
-        if (b >= sg.z0 && mine) {
-            const unsigned n = (unsigned)b * plane + own.n0;
+        const bool live = b >= sg.z0;  // uniform
+        const bool keep = live && mine;
+        {
+            const int bz = live ? b : sg.z0;
             const bool wall = WALLS && (b == 0 || b == G.nz - 1);
             double Fx = 0.0, Fy = 0.0, Fz = 0.0, Xs2 = 0.0;
             const double psi0 = s_psi[b & 3][own.r];
@@ -285,43 +391,59 @@ __global__ __launch_bounds__(kThreads) void d3q19_march_l(const S *__restrict__ 
             }
             const double inv = rcp_pos(rho_b);
             const double ux = (jx_b + 0.5 * Fx) * inv, uy = (jy_b + 0.5 * Fy) * inv, uz = (jz_b + 0.5 * Fz) * inv;
-            U[n] = ux;
-            U[N + n] = uy;
-            U[2 * (size_t)N + n] = uz;
-            U[3 * (size_t)N + n] = rho_b;
+            const size_t zb = (size_t)bz * plane;
+            const unsigned vo = own.n0 * 8u + (mine ? 0u : kOut);
+            buf_st(layer_rsrc(U + zb, plane, !live), vo, 0u, ux);
+            buf_st(layer_rsrc(U + N + zb, plane, !live), vo, 0u, uy);
+            buf_st(layer_rsrc(U + 2 * (size_t)N + zb, plane, !live), vo, 0u, uz);
+            buf_st(layer_rsrc(U + 3 * (size_t)N + zb, plane, !live), vo, 0u, rho_b);
             const double uu = ux * ux + uy * uy + uz * uz;
             const double uF = ux * Fx + uy * Fy + uz * Fz;
-            // post-collision populations stored as they are formed; the rest
-            // population closes the mass
-            const double rr = sizeof(S) == 4 ? rref[b] : 0.0;  // this plane's reference (FP32)
+            // post-collision populations (f_eq + half of Guo's term + the
+            // sigma term) of each velocity pair c, -c from their even and odd
+            // parts, stored as they are formed; the rest population closes
+            // the mass
+            const double rr = sizeof(S) == 4 ? rref[bz] : 0.0;  // this plane's reference (FP32)
+            const unsigned pvo = own.n0 * (unsigned)sizeof(S) + (mine ? 0u : kOut);
+            const double even0 = rho_b * (1.0 - 1.5 * uu) - 1.5 * uF, sig2 = 0.75 * Xs2;
             double rest = 0.0, nm = 0.0, down = 0.0, up = 0.0;
 #pragma unroll
-            for (int i = 1; i < 19; ++i) {
-                const double fi = post_tau1(i, rho_b, ux, uy, uz, Fx, Fy, Fz, Xs2, uu, uF);
-                rest += fi;
-                const double v = Pop<S>::st(fout, (size_t)i * N + n, fi, wgt(i) * rr);
-                nm += v;
-                const int cz = vel(i).z;
-                if (cz < 0) down += v;
-                if (cz > 0) up += v;
+            for (int i = 1; i < 19; i += 2) {
+                const V3 v = vel(i);
+                const double w = wgt(i);
+                const double cu = cdot(v, ux, uy, uz), cF = cdot(v, Fx, Fy, Fz);
+                const double E = w * (even0 + 4.5 * cu * (rho_b * cu + cF) + (i < 7 ? 0.0 : sig2));
+                const double O = w * (3.0 * rho_b * cu + 1.5 * cF);
+                const double fp = E + O, fm = E - O;
+                rest += fp + fm;
+                const double sp =
+                    pop_st(layer_rsrc(fout + (size_t)i * N + zb, plane, !live), pvo, 0u, fp, w * rr, S());
+                const double sm =
+                    pop_st(layer_rsrc(fout + (size_t)(i + 1) * N + zb, plane, !live), pvo, 0u, fm, w * rr, S());
+                nm += sp + sm;
+                // i + 1 is the opposite velocity of i
+                if (v.z < 0) down += sp;
+                if (v.z > 0) up += sp;
+                if (v.z > 0) down += sm;
+                if (v.z < 0) up += sm;
             }
-            nm += Pop<S>::st(fout, n, rho_b - rest, wgt(0) * rr);
+            nm += pop_st(layer_rsrc(fout + zb, plane, !live), pvo, 0u, rho_b - rest, wgt(0) * rr, S());
             if (WALLS) {
-                if (b == 0) nm -= down;
-                if (b == 1) nm += down;
-                if (b == G.nz - 2) nm += up;
-                if (b == G.nz - 1) nm -= up;
+                nm = b == 0 ? nm - down : nm;
+                nm = b == 1 ? nm + down : nm;
+                nm = b == G.nz - 2 ? nm + up : nm;
+                nm = b == G.nz - 1 ? nm - up : nm;
             }
-            part.mass_n += rho_b;
-            part.mass_next += nm;
-            part.umax = fmax(part.umax, uu);
-            part.rmin = fmin(part.rmin, rho_b);
             unsigned fl = 0u;
             if (!(rho_b > 0.0)) fl |= kFlagRho;
             if (c.eos == 0 && c.b_quarter * rho_b >= 1.0) fl |= kFlagEta;
             if (psi0 != psi0) fl |= kFlagPsi;
             if (rho_b != rho_b || uu != uu || nm != nm) fl |= kFlagNaN;
-            part.flags |= fl;
+            part.mass_n += keep ? rho_b : 0.0;
+            part.mass_next += keep ? nm : 0.0;
+            part.umax = keep ? fmax(part.umax, uu) : part.umax;
+            part.rmin = keep ? fmin(part.rmin, rho_b) : part.rmin;
+            part.flags |= keep ? fl : 0u;
         }
         rho_b = rho;
         jx_b = jx;
@@ -392,16 +514,17 @@ struct EVals {
 };
 
 __device__ __forceinline__ EVals load_e(const double *__restrict__ Tin, const double *__restrict__ U, unsigned N,
-                                        unsigned n, bool beyond)
+                                        unsigned plane, unsigned zo, const Col &c, bool beyond)
 {
-    EVals v = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (!beyond) {
-        v.T = Tin[n];
-        v.ux = U[n];
-        v.uy = U[N + n];
-        v.uz = U[2 * (size_t)N + n];
-        v.rho = U[3 * (size_t)N + n];
-    }
+    // branch-free: a plane beyond a wall has an empty range, a lane without
+    // the column an out-of-range offset; both read zeros
+    const unsigned vo = c.n0 * 8u + c.oob;
+    EVals v;
+    v.T = buf_ld(layer_rsrc(Tin + zo, plane, beyond), vo, 0u, 0.0);
+    v.ux = buf_ld(layer_rsrc(U + zo, plane, beyond), vo, 0u, 0.0);
+    v.uy = buf_ld(layer_rsrc(U + N + zo, plane, beyond), vo, 0u, 0.0);
+    v.uz = buf_ld(layer_rsrc(U + 2 * (size_t)N + zo, plane, beyond), vo, 0u, 0.0);
+    v.rho = buf_ld(layer_rsrc(U + 3 * (size_t)N + zo, plane, beyond), vo, 0u, 0.0);
     return v;
 }
 
@@ -460,7 +583,7 @@ __global__ __launch_bounds__(kThreads) void d3q19_march_e(const double *__restri
     int rx2 = 0, ry2 = 0;
     if (ring1) ring_column(1, 2, t, rx2, ry2);
     if (ring2) ring_column(2, 2, t - kRing1, rx2, ry2);
-    const Col two = make_col(G, sg.x0, sg.y0, rx2, ry2, 2, R2::RX);
+    const Col two = make_col(G, sg.x0, sg.y0, rx2, ry2, 2, R2::RX, ring1 || ring2);
     const int two_r1 = (ry2 - 1) * R1::RX + (rx2 - 1);
     const unsigned plane = (unsigned)G.nx * (unsigned)G.ny;
 
@@ -472,12 +595,15 @@ __global__ __launch_bounds__(kThreads) void d3q19_march_e(const double *__restri
     // loads of planes z0 - 2 .. z1 + 1, one plane ahead of their use; k1 and
     // T~ of plane a - 1 (planes z0 - 1 .. z1); T^{n+1} of plane a - 2 (planes
     // z0 .. z1 - 1)
-    EVals nA, nB = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double pendT = 0.0;  // T^{n+1} of plane pendq (no plane: pendq < z0), not yet stored
+    int pendq = -1;
+    const unsigned pendvo = own.n0 * 8u + (mine ? 0u : kOut);
+    EVals nA, nB;
     {
         bool beyond;
         const unsigned zo = (unsigned)plane_of<WALLS>(sg.z0 - 2, G.nz, beyond) * plane;
-        nA = load_e(Tin, U, N, zo + own.n0, beyond);
-        if (ring1 || ring2) nB = load_e(Tin, U, N, zo + two.n0, beyond);
+        nA = load_e(Tin, U, N, plane, zo, own, beyond);
+        nB = load_e(Tin, U, N, plane, zo, two, beyond);
     }
     for (int a = sg.z0 - 2; a <= sg.z1 + 1; ++a) {
         const int sT = wrap_mod(a, 3), su = a & 1;
@@ -492,11 +618,15 @@ __global__ __launch_bounds__(kThreads) void d3q19_march_e(const double *__restri
             s_u[su][2][two.r] = nB.uz;
         }
         const double rhoA0 = nA.rho, rhoB0 = nB.rho;
-        if (a <= sg.z1) {
+        // the previous plane's T^{n+1}, stored ahead of this plane's loads so
+        // that waiting for those never waits for the store
+        buf_st(layer_rsrc(Tout + (size_t)(pendq >= sg.z0 ? pendq : sg.z0) * plane, plane, pendq < sg.z0), pendvo, 0u,
+               pendT);
+        {
             bool beyond;
             const unsigned zo = (unsigned)plane_of<WALLS>(a + 1, G.nz, beyond) * plane;
-            nA = load_e(Tin, U, N, zo + own.n0, beyond);
-            if (ring1 || ring2) nB = load_e(Tin, U, N, zo + two.n0, beyond);
+            nA = load_e(Tin, U, N, plane, zo, own, beyond);
+            nB = load_e(Tin, U, N, plane, zo, two, beyond);
         }
         __syncthreads();
 
@@ -540,24 +670,28 @@ __global__ __launch_bounds__(kThreads) void d3q19_march_e(const double *__restri
         __syncthreads();
 
         // second stage of plane q = a - 2 on the tile: k2 = K(T~),
-        // T^{n+1} = T^n + (k1 + k2)/2
+        // T^{n+1} = T^n + (k1 + k2)/2 (wall planes keep T), stored in the
+        // next step.  Stores of a plane outside the segment or of a lane
+        // outside the lattice are dropped (empty range, out-of-range offset),
+        // not branched around.
         const int q = a - 2;
-        if (q >= sg.z0 && q < sg.z1 && mine) {
-            double Tn = hT;
-            if (!(WALLS && (q == 0 || q == G.nz - 1))) {
-                const int sq = wrap_mod(q, 3);
-                double gx, gy, gz, lap;
-                grad_lap_planes<R1::RX>(s_Tt[wrap_mod(q - 1, 3)], s_Tt[sq], s_Tt[wrap_mod(q + 1, 3)], own_r1, gx, gy,
-                                        gz, lap);
-                const double k2 = energy_k(hk, s_Tt[sq][own_r1], gx, gy, gz, lap);
-                Tn = hT + 0.5 * (hk1 + k2);
-            }
-            Tout[(unsigned)q * plane + own.n0] = Tn;
+        {
+            const bool liveq = q >= sg.z0 && q < sg.z1;  // uniform
+            const int sq = wrap_mod(q, 3);
+            double gx, gy, gz, lap;
+            grad_lap_planes<R1::RX>(s_Tt[wrap_mod(q - 1, 3)], s_Tt[sq], s_Tt[wrap_mod(q + 1, 3)], own_r1, gx, gy, gz,
+                                    lap);
+            const double k2 = energy_k(hk, s_Tt[sq][own_r1], gx, gy, gz, lap);
+            const bool wq = WALLS && (q == 0 || q == G.nz - 1);
+            pendT = wq ? hT : hT + 0.5 * (hk1 + k2);
+            pendq = liveq ? q : -1;
         }
         hT = Tb;
         hk1 = k1b;
         hk = kb;
     }
+    buf_st(layer_rsrc(Tout + (size_t)(pendq >= sg.z0 ? pendq : sg.z0) * plane, plane, pendq < sg.z0), pendvo, 0u,
+           pendT);
 }
 
 MarchG3 march_grid3(int nx, int ny, int nz, int cus)

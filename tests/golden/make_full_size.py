@@ -24,8 +24,10 @@ Workloads (as the benchmark and the paper's parameters set them):
   in [1e-6, 1e-4], T/T_c in [0.6, 0.95], both forms, liquid below vapour at a
   mean density between the coexistence densities, 1e-3 noise).  Columns are
   tried shortest first (short columns relax fastest) until 64 of them
-  converge within the step budget; every tried column's status and stopping
-  level is kept, and the profiles of the converged ones.
+  converge within the step budget or COL_MAX_TRIED have been tried; every
+  tried column's status and stopping level is kept, and the profiles of the
+  converged ones.  The file is rewritten after every group of columns, so an
+  interrupted run leaves the columns finished so far.
 """
 from __future__ import annotations
 
@@ -47,6 +49,10 @@ import workloads as W  # noqa: E402
 
 C2_STEPS, C4_STEPS = 1000, 100
 COL_TOL, COL_CHECK, COL_MAX_STEPS, COL_WANT = 1e-9, 100, 2_000_000, 64
+# columns tried at most: converging columns thin out with height (55 of the
+# 832 shortest converge within the step budget, none of the next 240), so
+# the search stops there if 64 have not converged by then
+COL_MAX_TRIED = 832
 
 # sampled nodes: rows/planes across the walls, the interface and the bulk
 C2_ROWS = [0, 1, 2, 3, 31, 32, 62, 63, 64, 65, 66, 67, 68, 100, 511, 1024, 2000, 2045, 2046, 2047]
@@ -157,13 +163,19 @@ def columns(workers: int):
                 recs["Tend"].append(TT if st == "converged" else np.full(a[0], np.nan))
                 conv += st == "converged"
             print(f"columns: {len(recs['index'])} tried, {conv} converged, {time.time() - t0:.0f} s", flush=True)
-            if conv >= COL_WANT:
+            _write_columns(recs)
+            if conv >= COL_WANT or len(recs["index"]) >= COL_MAX_TRIED:
                 break
+
+
+def _write_columns(recs):
     out = {k: np.array(v) for k, v in recs.items() if k not in ("rho0", "rho", "Tend")}
     for k in ("rho0", "rho", "Tend"):
         out[k] = np.concatenate(recs[k])
     out.update(tol=COL_TOL, check_every=COL_CHECK, max_steps=COL_MAX_STEPS)
-    np.savez_compressed(path("c3_columns_seed3_to_steady.npz"), **out)
+    tmp = path("c3_columns_seed3_to_steady.tmp.npz")
+    np.savez_compressed(tmp, **out)
+    os.replace(tmp, path("c3_columns_seed3_to_steady.npz"))
 
 
 if __name__ == "__main__":
