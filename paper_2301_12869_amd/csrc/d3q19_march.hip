@@ -47,25 +47,35 @@ namespace {
 
 using namespace d3;
 
-constexpr int kTX = 32, kTY = 16;
-constexpr int kThreads = kTX * kTY;  // one thread per interior column: 512
-constexpr int kRing1 = 2 * (kTX + 2) + 2 * kTY;        // columns at distance 1: 100
-constexpr int kRing2 = 2 * (kTX + 4) + 2 * (kTY + 2);  // columns at distance 2: 108
-static_assert(kRing1 + kRing2 <= kThreads, "the halo rings are taken by one thread each");
-
-// Region of a tile with a halo of H columns: (kTX + 2H) x (kTY + 2H), kept
-// in LDS with an odd row stride RX (in doubles), so that a run of columns down
-// the region's sides (the ring columns) falls into distinct banks.
-template <int H>
-struct Region {
-    static constexpr int W = kTX + 2 * H, RY = kTY + 2 * H, RX = W + 1, N = RX * RY;
+// A tile of TX x TY columns, one thread per column; the rings of columns at
+// distance 1 and 2 around it are taken as a second column by threads 0 ..
+// Ring1 - 1 and Ring1 .. Ring1 + Ring2 - 1.  Region<H> is the tile with a
+// halo of H columns, kept in LDS with an odd row stride RX (in doubles), so
+// that a run of columns down the region's sides (the ring columns) falls into
+// distinct banks.
+template <int TX_, int TY_>
+struct Tile {
+    static constexpr int TX = TX_, TY = TY_, Threads = TX * TY;
+    static constexpr int Ring1 = 2 * (TX + 2) + 2 * TY, Ring2 = 2 * (TX + 4) + 2 * (TY + 2);
+    static_assert(Ring1 + Ring2 <= Threads, "the halo rings are taken by one thread each");
+    template <int H>
+    struct Region {
+        static constexpr int W = TX + 2 * H, RY = TY + 2 * H, RX = W + 1, N = RX * RY;
+    };
 };
+// L: 512 threads (8 waves, one block per compute unit), leaving each thread up
+// to 256 registers for the pulled populations of the next plane in flight.
+// E: 1024 threads (16 waves), 128 registers each; its halo rings are then a
+// smaller share of a tile.
+using TileL = Tile<32, 16>;
+using TileE = Tile<32, 32>;
 
 // Region coordinates of column k of the ring at distance r from the tile,
 // inside a region of halo H >= r: bottom row, top row, left and right sides.
+template <class T>
 __device__ __forceinline__ void ring_column(int r, int H, int k, int &rx, int &ry)
 {
-    const int w = kTX + 2 * r, h = kTY + 2 * r, off = H - r;
+    const int w = T::TX + 2 * r, h = T::TY + 2 * r, off = H - r;
     if (k < w) {
         rx = k;
         ry = 0;
@@ -160,6 +170,7 @@ struct Seg3 {
     int x0, y0, z0, z1;
 };
 
+template <class T>
 __device__ __forceinline__ Seg3 block_segment(const MarchG3 &M, int nz)
 {
     const int nb = M.nblocks;
@@ -168,8 +179,8 @@ __device__ __forceinline__ Seg3 block_segment(const MarchG3 &M, int nz)
     const int tiles = M.ntx * M.nty;
     const int seg = b / tiles, tl = b - seg * tiles;
     Seg3 s;
-    s.x0 = (tl % M.ntx) * kTX;
-    s.y0 = (tl / M.ntx) * kTY;
+    s.x0 = (tl % M.ntx) * T::TX;
+    s.y0 = (tl / M.ntx) * T::TY;
     s.z0 = (int)((int64_t)seg * nz / M.nseg);
     s.z1 = (int)((int64_t)(seg + 1) * nz / M.nseg);
     return s;
@@ -314,25 +325,26 @@ __device__ __forceinline__ double pull_finish(const PullLoads<S> &P, const Phys 
 }
 
 template <class S, bool WALLS>
-__global__ __launch_bounds__(kThreads) void d3q19_march_l(const S *__restrict__ fin, S *__restrict__ fout,
+__global__ __launch_bounds__(TileL::Threads) void d3q19_march_l(const S *__restrict__ fin, S *__restrict__ fout,
                                                           const double *__restrict__ Tin, double *__restrict__ U,
                                                           Phys c, Grid3 G, MarchG3 M, double *__restrict__ partials,
                                                           StepState *__restrict__ st, int64_t step,
                                                           const double *__restrict__ rref)
 {
-    using R = Region<1>;
+    using T = TileL;
+    using R = T::Region<1>;
     __shared__ double s_psi[4][R::N];
-    __shared__ double s_red[4 * kThreads / 64];
-    __shared__ unsigned s_ured[kThreads / 64];
+    __shared__ double s_red[4 * T::Threads / 64];
+    __shared__ unsigned s_ured[T::Threads / 64];
     const int t = threadIdx.x;
     const unsigned N = G.N;
-    const Seg3 sg = block_segment(M, G.nz);
-    const int tx = t % kTX, ty = t / kTX;
+    const Seg3 sg = block_segment<T>(M, G.nz);
+    const int tx = t % T::TX, ty = t / T::TX;
     const Col own = make_col(G, sg.x0, sg.y0, tx + 1, ty + 1, 1, R::RX);
     const bool mine = sg.x0 + tx < G.nx && sg.y0 + ty < G.ny;  // a lattice node of this tile
-    const bool has2 = t < kRing1;
+    const bool has2 = t < T::Ring1;
     int rx2 = 0, ry2 = 0;
-    if (has2) ring_column(1, 1, t, rx2, ry2);
+    if (has2) ring_column<T>(1, 1, t, rx2, ry2);
     const Col two = make_col(G, sg.x0, sg.y0, rx2, ry2, 1, R::RX, has2);
     const double sub = gravity_sub(c.form, st->mean[step & 1], c.rho_v);
     const unsigned plane = (unsigned)G.nx * (unsigned)G.ny;
@@ -450,8 +462,8 @@ __global__ __launch_bounds__(kThreads) void d3q19_march_l(const S *__restrict__ 
         jy_b = jy;
         jz_b = jz;
     }
-    part = block_reduce<kThreads>(part, s_red, s_ured);
-    finish_launch<kThreads>(part, partials, st, step, (int)((step + 1) & 1), 1.0 / (double)N, s_red, s_ured);
+    part = block_reduce<T::Threads>(part, s_red, s_ured);
+    finish_launch<T::Threads>(part, partials, st, step, (int)((step + 1) & 1), 1.0 / (double)N, s_red, s_ured);
 }
 
 // ---- E: the energy equation --------------------------------------------------
@@ -562,27 +574,28 @@ __device__ __forceinline__ double energy_k(const ECoef &k, double phi0, double g
 }
 
 template <bool WALLS>
-__global__ __launch_bounds__(kThreads) void d3q19_march_e(const double *__restrict__ Tin, double *__restrict__ Tout,
+__global__ __launch_bounds__(TileE::Threads) void d3q19_march_e(const double *__restrict__ Tin, double *__restrict__ Tout,
                                                           const double *__restrict__ U, Phys c, Grid3 G, MarchG3 M)
 {
-    using R2 = Region<2>;
-    using R1 = Region<1>;
+    using T = TileE;
+    using R2 = T::Region<2>;
+    using R1 = T::Region<1>;
     __shared__ double s_T[3][R2::N];     // T^n, planes a - 2 .. a
     __shared__ double s_u[2][3][R2::N];  // u, planes a - 1 and a
     __shared__ double s_Tt[3][R1::N];    // T~, planes a - 3 .. a - 1
     const int t = threadIdx.x;
     const unsigned N = G.N;
-    const Seg3 sg = block_segment(M, G.nz);
-    const int tx = t % kTX, ty = t / kTX;
+    const Seg3 sg = block_segment<T>(M, G.nz);
+    const int tx = t % T::TX, ty = t / T::TX;
     const Col own = make_col(G, sg.x0, sg.y0, tx + 2, ty + 2, 2, R2::RX);
     const int own_r1 = (ty + 1) * R1::RX + (tx + 1);
     const bool mine = sg.x0 + tx < G.nx && sg.y0 + ty < G.ny;
     // second column: ring 1 (threads 0..99, with a k1 and T~ of its own) or
     // ring 2 (threads 100..207, loads only)
-    const bool ring1 = t < kRing1, ring2 = t >= kRing1 && t < kRing1 + kRing2;
+    const bool ring1 = t < T::Ring1, ring2 = t >= T::Ring1 && t < T::Ring1 + T::Ring2;
     int rx2 = 0, ry2 = 0;
-    if (ring1) ring_column(1, 2, t, rx2, ry2);
-    if (ring2) ring_column(2, 2, t - kRing1, rx2, ry2);
+    if (ring1) ring_column<T>(1, 2, t, rx2, ry2);
+    if (ring2) ring_column<T>(2, 2, t - T::Ring1, rx2, ry2);
     const Col two = make_col(G, sg.x0, sg.y0, rx2, ry2, 2, R2::RX, ring1 || ring2);
     const int two_r1 = (ry2 - 1) * R1::RX + (rx2 - 1);
     const unsigned plane = (unsigned)G.nx * (unsigned)G.ny;
@@ -694,11 +707,12 @@ __global__ __launch_bounds__(kThreads) void d3q19_march_e(const double *__restri
            pendT);
 }
 
+template <class T>
 MarchG3 march_grid3(int nx, int ny, int nz, int cus)
 {
     MarchG3 g;
-    g.ntx = (nx + kTX - 1) / kTX;
-    g.nty = (ny + kTY - 1) / kTY;
+    g.ntx = (nx + T::TX - 1) / T::TX;
+    g.nty = (ny + T::TY - 1) / T::TY;
     const long tiles = (long)g.ntx * g.nty;
     long nseg = (cus + tiles - 1) / tiles;
     const long maxseg = nz / 8 > 0 ? nz / 8 : 1;  // segments of at least 8 planes
@@ -713,17 +727,19 @@ template <class S, bool WALLS>
 hipError_t march_t(const LatticeLaunch &L, double *U)
 {
     const Grid3 G{L.nx, L.ny, L.nz, (unsigned)((size_t)L.nx * L.ny * L.nz)};
-    const MarchG3 M = march_grid3(L.nx, L.ny, L.nz, L.resident);
-    hipLaunchKernelGGL((d3q19_march_l<S, WALLS>), dim3(M.nblocks), dim3(kThreads), 0, L.stream, (const S *)L.fin,
+    const MarchG3 M = march_grid3<TileL>(L.nx, L.ny, L.nz, L.resident);
+    const MarchG3 ME = march_grid3<TileE>(L.nx, L.ny, L.nz, L.resident);
+    hipLaunchKernelGGL((d3q19_march_l<S, WALLS>), dim3(M.nblocks), dim3(TileL::Threads), 0, L.stream, (const S *)L.fin,
                        (S *)L.fout, L.Tin, U, L.phys, G, M, L.partials, L.st, L.step, L.rref);
-    hipLaunchKernelGGL((d3q19_march_e<WALLS>), dim3(M.nblocks), dim3(kThreads), 0, L.stream, L.Tin, L.Tout,
-                       (const double *)U, L.phys, G, M);
+    hipLaunchKernelGGL((d3q19_march_e<WALLS>), dim3(ME.nblocks), dim3(TileE::Threads), 0, L.stream, L.Tin, L.Tout,
+                       (const double *)U, L.phys, G, ME);
     return hipGetLastError();
 }
 
 }  // namespace
 
-int d3q19_march_blocks(int nx, int ny, int nz, int cus) { return march_grid3(nx, ny, nz, cus).nblocks; }
+// the LBM kernel writes the per-block partials
+int d3q19_march_blocks(int nx, int ny, int nz, int cus) { return march_grid3<TileL>(nx, ny, nz, cus).nblocks; }
 
 hipError_t d3q19_march_step(const LatticeLaunch &L, double *U)
 {
