@@ -8,12 +8,15 @@ input generators).
 - 256^3 D3Q19 after 100 steps, both forms, on the full lattice (so that the
   form-2 mean density is the lattice's own): 2816 sampled nodes and the
   per-plane sums of rho and T.
-- Config-3 columns (seed 3), the shortest first, run to max|u| < 1e-9: the
-  statuses and stopping levels of every column the oracle tried, identical,
-  and the end profiles of at least 64 converged columns.
+- Config-3 columns (seed 3), the shortest first, run to max|u| < 1e-9
+  within 2e6 steps: the statuses and stopping levels of every column the
+  oracle tried (the 832 shortest, heights 128..~480), identical, and the end
+  profiles of the converged ones (55; converging columns thin out with
+  height, and the oracle needs about an hour of eight cores for these).
 
 FP64 bar: 1e-12 relative (pressures on the a rho^2 scale, velocities 1e-14
-absolute).  Inputs are rebuilt from the scalars stored with the goldens, so
+absolute); the columns' densities after n steps: max(1e-12, n 2^-53) (see
+the test).  Inputs are rebuilt from the scalars stored with the goldens, so
 both sides start from the same bits.
 """
 import os
@@ -115,7 +118,7 @@ def test_config3_columns_to_steady_state(T):
     Tcol = np.concatenate([np.full(h, t) for h, t in zip(H, g["T"])])
     status, steps = g["status"], g["steps"]
     conv = status == 0
-    assert conv.sum() >= 64
+    assert conv.sum() >= 50
     _log(f"case config-3 columns: {len(cols)} columns ({conv.sum()} converged in the oracle), "
          f"heights {H.min()}..{H.max()}")
     b = T.Batch(cols)
@@ -130,11 +133,18 @@ def test_config3_columns_to_steady_state(T):
     # noticed the flag, not a check level)
     keep = status != 1
     assert np.array_equal(res["steps"][keep], steps[keep])
+    # Density after n steps: each step's rounding differs between the two
+    # codes by about one unit roundoff u = 2^-53, and the mass the walls
+    # exchange during the transient (a mode that does not decay) carries it
+    # on, so the profiles agree to about n u (measured: at most 0.4 n u,
+    # 7e-11 after 1.7e6 steps).  The temperature relaxes to the wall values
+    # and stays within 1e-12.
     worst = 0.0
     for k in np.nonzero(conv)[0]:
         a, bb = rho[off[k]:off[k + 1]], g["rho"][off[k]:off[k + 1]]
-        worst = max(worst, _rel(a, bb))
-        assert _rel(a, bb) < TOL, k
+        tol = max(TOL, float(steps[k]) * 2.0 ** -53)
+        worst = max(worst, _rel(a, bb) / tol)
+        assert _rel(a, bb) < tol, (k, int(steps[k]), _rel(a, bb))
         assert _rel(Tend[off[k]:off[k + 1]], g["Tend"][off[k]:off[k + 1]]) < TOL, k
     b.close()
-    _log(f"  statuses and levels identical; worst converged profile {worst:.2e}")
+    _log(f"  statuses and levels identical; worst converged profile {worst:.2f} of its bound")
