@@ -20,21 +20,24 @@
 //   E (halo 2): the energy equation (Eq. Energy_Equation) advanced by
 //     Heun's method with rho and u of the level frozen: T^n and u planes in
 //     LDS; one plane behind, div u and k1 = K(T^n) on the tile and its halo
-//     ring, T~ = T^n + k1 -> LDS; one more plane behind, k2 = K(T~) and
-//     T^{n+1} = T^n + (k1 + k2)/2 on the tile.  Wall planes keep T.
+//     ring, T~ = T^n + k1 -> LDS; two more planes behind, k2 = K(T~) and
+//     T^{n+1} = T^n + (k1 + k2)/2 on the tile.  Wall planes keep T.  One
+//     barrier per plane: the second stage reads only T~ planes written
+//     before it.
 //
 // The divergence of u is accumulated plane by plane: the contribution of a
 // plane to the divergence at its own plane and at the planes above and below
 // depends only on that plane's values, so u needs a single plane in LDS.
 //
-// Threads and columns: thread t owns interior column t (x = t % 32, y = t /
-// 32 of the tile).  The ring of columns around the tile at distance 1 (100
-// columns) and, for E, at distance 2 (108 columns) are taken as a second
-// column by threads 0..99 and 100..207.  A block of 512 threads (8 waves, one
-// block per compute unit) leaves each thread up to 256 registers for the
-// loads of the next plane in flight.  Column coordinates wrap in x and y
-// (periodic), so a tile that extends past the lattice edge reads the
-// periodic images; only columns inside the lattice store results.
+// Threads and columns: in L thread t owns interior column t (x = t % 32, y =
+// t / 32 of the tile) and threads 0..99 take the ring of columns at distance 1
+// as a second column; a block of 512 threads (8 waves, one block per compute
+// unit) leaves each thread up to 256 registers for the loads of the next
+// plane in flight.  In E every thread has one column: the tile's 512, then
+// the 100 of the ring at distance 1, then the 108 at distance 2.  Column
+// coordinates wrap in x and y (periodic), so a tile that extends past the
+// lattice edge reads the periodic images; only columns inside the lattice
+// store results.
 #include <hip/hip_runtime.h>
 
 #include "d3q19_common.hpp"
@@ -47,17 +50,15 @@ namespace {
 
 using namespace d3;
 
-// A tile of TX x TY columns, one thread per column; the rings of columns at
-// distance 1 and 2 around it are taken as a second column by threads 0 ..
-// Ring1 - 1 and Ring1 .. Ring1 + Ring2 - 1.  Region<H> is the tile with a
-// halo of H columns, kept in LDS with an odd row stride RX (in doubles), so
-// that a run of columns down the region's sides (the ring columns) falls into
-// distinct banks.
+// A tile of TX x TY columns and the rings of Ring1 and Ring2 columns at
+// distance 1 and 2 around it.  Region<H> is the tile with a halo of H
+// columns, kept in LDS with an odd row stride RX (in doubles), so that a run
+// of columns down the region's sides (the ring columns) falls into distinct
+// banks.
 template <int TX_, int TY_>
 struct Tile {
     static constexpr int TX = TX_, TY = TY_, Threads = TX * TY;
     static constexpr int Ring1 = 2 * (TX + 2) + 2 * TY, Ring2 = 2 * (TX + 4) + 2 * (TY + 2);
-    static_assert(Ring1 + Ring2 <= Threads, "the halo rings are taken by one thread each");
     template <int H>
     struct Region {
         static constexpr int W = TX + 2 * H, RY = TY + 2 * H, RX = W + 1, N = RX * RY;
@@ -65,10 +66,10 @@ struct Tile {
 };
 // L: 512 threads (8 waves, one block per compute unit), leaving each thread up
 // to 256 registers for the pulled populations of the next plane in flight.
-// E: 1024 threads (16 waves), 128 registers each; its halo rings are then a
-// smaller share of a tile.
+// E: 720 threads (12 waves, one block per compute unit), one column each.
 using TileL = Tile<32, 16>;
-using TileE = Tile<32, 32>;
+using TileE = Tile<32, 16>;
+static_assert(TileL::Ring1 <= TileL::Threads, "L's ring at distance 1 is taken as a second column");
 
 // Region coordinates of column k of the ring at distance r from the tile,
 // inside a region of halo H >= r: bottom row, top row, left and right sides.
@@ -520,26 +521,6 @@ __device__ __forceinline__ void grad_lap_planes(const double *__restrict__ pm, c
     lap *= 6.0;
 }
 
-// Values of one column at one plane, as E loads them.
-struct EVals {
-    double T, ux, uy, uz, rho;
-};
-
-__device__ __forceinline__ EVals load_e(const double *__restrict__ Tin, const double *__restrict__ U, unsigned N,
-                                        unsigned plane, unsigned zo, const Col &c, bool beyond)
-{
-    // branch-free: a plane beyond a wall has an empty range, a lane without
-    // the column an out-of-range offset; both read zeros
-    const unsigned vo = c.n0 * 8u + c.oob;
-    EVals v;
-    v.T = buf_ld(layer_rsrc(Tin + zo, plane, beyond), vo, 0u, 0.0);
-    v.ux = buf_ld(layer_rsrc(U + zo, plane, beyond), vo, 0u, 0.0);
-    v.uy = buf_ld(layer_rsrc(U + N + zo, plane, beyond), vo, 0u, 0.0);
-    v.uz = buf_ld(layer_rsrc(U + 2 * (size_t)N + zo, plane, beyond), vo, 0u, 0.0);
-    v.rho = buf_ld(layer_rsrc(U + 3 * (size_t)N + zo, plane, beyond), vo, 0u, 0.0);
-    return v;
-}
-
 // div u of a column accumulated over the planes: when the contributions of
 // plane a arrive, div(a - 1) = pend + side(a) + zc(a) is complete and pend
 // becomes cen(a) + side(a - 1) - zc(a - 1), the part of div(a) known so far.
@@ -573,148 +554,144 @@ __device__ __forceinline__ double energy_k(const ECoef &k, double phi0, double g
     return -(k.ux * gx + k.uy * gy + k.uz * gz) + k.a1 * lap - phi0 * k.a2;
 }
 
+// E runs one column per thread: the tile's columns first (threads 0 .. TX TY
+// - 1), then the ring at distance 1, then the ring at distance 2 (loads
+// only), so that the waves of the second stage hold tile columns only and
+// no thread carries a second column.  One block (12 waves) per compute unit.
+constexpr int kEThreads = TileE::Threads + TileE::Ring1 + TileE::Ring2;
+constexpr int kEBlocksPerCU = 1;
+
 template <bool WALLS>
-__global__ __launch_bounds__(TileE::Threads) void d3q19_march_e(const double *__restrict__ Tin, double *__restrict__ Tout,
-                                                          const double *__restrict__ U, Phys c, Grid3 G, MarchG3 M)
+__global__ __launch_bounds__(kEThreads) void d3q19_march_e(const double *__restrict__ Tin,
+                                                                        double *__restrict__ Tout,
+                                                                        const double *__restrict__ U, Phys c,
+                                                                        Grid3 G, MarchG3 M)
 {
     using T = TileE;
     using R2 = T::Region<2>;
     using R1 = T::Region<1>;
-    __shared__ double s_T[3][R2::N];     // T^n, planes a - 2 .. a
-    __shared__ double s_u[2][3][R2::N];  // u, planes a - 1 and a
-    __shared__ double s_Tt[3][R1::N];    // T~, planes a - 3 .. a - 1
+    // rings of planes indexed by z & 3 (z & 1 for u): the step of plane a
+    // writes T and u of plane a, then after its one barrier reads T of a - 2
+    // .. a, u of a, and T~ of a - 4 .. a - 2, and writes T~ of a - 1; every
+    // slot a step writes was last read two barriers earlier
+    __shared__ double s_T[4][R2::N];
+    __shared__ double s_u[2][3][R2::N];
+    __shared__ double s_Tt[4][R1::N];
     const int t = threadIdx.x;
     const unsigned N = G.N;
     const Seg3 sg = block_segment<T>(M, G.nz);
-    const int tx = t % T::TX, ty = t / T::TX;
-    const Col own = make_col(G, sg.x0, sg.y0, tx + 2, ty + 2, 2, R2::RX);
-    const int own_r1 = (ty + 1) * R1::RX + (tx + 1);
-    const bool mine = sg.x0 + tx < G.nx && sg.y0 + ty < G.ny;
-    // second column: ring 1 (threads 0..99, with a k1 and T~ of its own) or
-    // ring 2 (threads 100..207, loads only)
-    const bool ring1 = t < T::Ring1, ring2 = t >= T::Ring1 && t < T::Ring1 + T::Ring2;
-    int rx2 = 0, ry2 = 0;
-    if (ring1) ring_column<T>(1, 2, t, rx2, ry2);
-    if (ring2) ring_column<T>(2, 2, t - T::Ring1, rx2, ry2);
-    const Col two = make_col(G, sg.x0, sg.y0, rx2, ry2, 2, R2::RX, ring1 || ring2);
-    const int two_r1 = (ry2 - 1) * R1::RX + (rx2 - 1);
+    const bool tile = t < T::Threads, ring1 = !tile && t < T::Threads + T::Ring1;
+    const bool first = tile || ring1;  // a column of the first stage
+    int rx, ry;
+    if (tile) {
+        rx = t % T::TX + 2;
+        ry = t / T::TX + 2;
+    } else if (ring1) {
+        ring_column<T>(1, 2, t - T::Threads, rx, ry);
+    } else {
+        ring_column<T>(2, 2, t - T::Threads - T::Ring1, rx, ry);
+    }
+    const Col col = make_col(G, sg.x0, sg.y0, rx, ry, 2, R2::RX);
+    const int r1 = (ry - 1) * R1::RX + (rx - 1);  // index in the region of halo 1 (first-stage columns)
+    const bool mine = tile && sg.x0 + rx - 2 < G.nx && sg.y0 + ry - 2 < G.ny;
     const unsigned plane = (unsigned)G.nx * (unsigned)G.ny;
+    const unsigned vo = col.n0 * 8u;
+    const unsigned vrho = first ? vo : kOut;   // rho is read where the first stage runs
+    const unsigned vst = mine ? vo : kOut;     // T^{n+1} is stored by the tile's lattice columns
 
-    DivAcc dA = {0.0, 0.0, 0.0}, dB = {0.0, 0.0, 0.0};
-    double rhoA = 0.0, rhoB = 0.0;  // rho of plane a - 1
-    // the own column's second stage of plane a - 2: T, k1 and coefficients
-    double hT = 0.0, hk1 = 0.0;
-    ECoef hk = {0.0, 0.0, 0.0, 0.0, 0.0};
-    // loads of planes z0 - 2 .. z1 + 1, one plane ahead of their use; k1 and
-    // T~ of plane a - 1 (planes z0 - 1 .. z1); T^{n+1} of plane a - 2 (planes
-    // z0 .. z1 - 1)
-    double pendT = 0.0;  // T^{n+1} of plane pendq (no plane: pendq < z0), not yet stored
+    DivAcc dv = {0.0, 0.0, 0.0};
+    double Tp = 0.0, uxp = 0.0, uyp = 0.0, uzp = 0.0, rhop = 0.0;  // the column's values of plane a - 1
+    // second-stage inputs of planes a - 2 (h1) and a - 3 (h2): T^n, k1 and
+    // the coefficients, from the first stage of those planes
+    double hT1 = 0.0, hk1 = 0.0, hT2 = 0.0, hk2 = 0.0;
+    ECoef hc1 = {0.0, 0.0, 0.0, 0.0, 0.0}, hc2 = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double pendT = 0.0;  // T^{n+1} of plane pendq (none: pendq < z0), stored in the next step
     int pendq = -1;
-    const unsigned pendvo = own.n0 * 8u + (mine ? 0u : kOut);
-    EVals nA, nB;
-    {
+    // planes z0 - 2 .. z1 + 1 are read, one plane ahead of their use; a read
+    // beyond them is an empty range
+    auto load = [&](int z, double &vT, double &vx, double &vy, double &vz, double &vr) __attribute__((always_inline)) {
         bool beyond;
-        const unsigned zo = (unsigned)plane_of<WALLS>(sg.z0 - 2, G.nz, beyond) * plane;
-        nA = load_e(Tin, U, N, plane, zo, own, beyond);
-        nB = load_e(Tin, U, N, plane, zo, two, beyond);
-    }
-    for (int a = sg.z0 - 2; a <= sg.z1 + 1; ++a) {
-        const int sT = wrap_mod(a, 3), su = a & 1;
-        s_T[sT][own.r] = nA.T;
-        s_u[su][0][own.r] = nA.ux;
-        s_u[su][1][own.r] = nA.uy;
-        s_u[su][2][own.r] = nA.uz;
-        if (ring1 || ring2) {
-            s_T[sT][two.r] = nB.T;
-            s_u[su][0][two.r] = nB.ux;
-            s_u[su][1][two.r] = nB.uy;
-            s_u[su][2][two.r] = nB.uz;
-        }
-        const double rhoA0 = nA.rho, rhoB0 = nB.rho;
-        // the previous plane's T^{n+1}, stored ahead of this plane's loads so
-        // that waiting for those never waits for the store
-        buf_st(layer_rsrc(Tout + (size_t)(pendq >= sg.z0 ? pendq : sg.z0) * plane, plane, pendq < sg.z0), pendvo, 0u,
+        const size_t zo = (size_t)plane_of<WALLS>(z, G.nz, beyond) * plane;
+        beyond = beyond || z > sg.z1 + 1;
+        vT = buf_ld(layer_rsrc(Tin + zo, plane, beyond), vo, 0u, 0.0);
+        vx = buf_ld(layer_rsrc(U + zo, plane, beyond), vo, 0u, 0.0);
+        vy = buf_ld(layer_rsrc(U + N + zo, plane, beyond), vo, 0u, 0.0);
+        vz = buf_ld(layer_rsrc(U + 2 * (size_t)N + zo, plane, beyond), vo, 0u, 0.0);
+        vr = buf_ld(layer_rsrc(U + 3 * (size_t)N + zo, plane, beyond), vrho, 0u, 0.0);
+    };
+    double nT, nx, ny, nzv, nr;
+    load(sg.z0 - 2, nT, nx, ny, nzv, nr);
+    for (int a = sg.z0 - 2; a <= sg.z1 + 2; ++a) {
+        s_T[a & 3][col.r] = nT;
+        s_u[a & 1][0][col.r] = nx;
+        s_u[a & 1][1][col.r] = ny;
+        s_u[a & 1][2][col.r] = nzv;
+        const double Ta = nT, uxa = nx, uya = ny, uza = nzv, rhoa = nr;
+        // the previous step's T^{n+1}, stored ahead of this step's loads so
+        // that waiting for those never waits for the store; a plane outside
+        // the segment is an empty range
+        buf_st(layer_rsrc(Tout + (size_t)(pendq >= sg.z0 ? pendq : sg.z0) * plane, plane, pendq < sg.z0), vst, 0u,
                pendT);
-        {
-            bool beyond;
-            const unsigned zo = (unsigned)plane_of<WALLS>(a + 1, G.nz, beyond) * plane;
-            nA = load_e(Tin, U, N, plane, zo, own, beyond);
-            nB = load_e(Tin, U, N, plane, zo, two, beyond);
-        }
+        load(a + 1, nT, nx, ny, nzv, nr);
         __syncthreads();
 
-        // div u of plane b = a - 1 at the own and ring-1 columns, then the
-        // first stage there: k1 = K(T^n), T~ = T^n + k1 (wall planes and the
-        // planes beyond them keep T)
+        // the contributions of plane a complete div u of plane b = a - 1;
+        // then the first stage there: k1 = K(T^n), T~ = T^n + k1 (wall
+        // planes and the planes beyond them keep T)
         const int b = a - 1;
-        const double divA = dA.push(div_part<R2::RX>(s_u[su][0], s_u[su][1], s_u[su][2], own.r));
-        double divB = 0.0;
-        if (ring1) divB = dB.push(div_part<R2::RX>(s_u[su][0], s_u[su][1], s_u[su][2], two.r));
-        const bool bwall = WALLS && (b <= 0 || b >= G.nz - 1);
-        const int sb = wrap_mod(b, 3), ub = b & 1;
-        const double *Tm = s_T[wrap_mod(b - 1, 3)], *T0 = s_T[sb], *Tp = s_T[sT];
-        double k1b = 0.0, Tb = 0.0;
-        ECoef kb = {0.0, 0.0, 0.0, 0.0, 0.0};
-        if (b >= sg.z0 - 1) {
-            Tb = T0[own.r];
-            double Tt = Tb;
-            if (!bwall) {
-                kb = energy_coef(c, s_u[ub][0][own.r], s_u[ub][1][own.r], s_u[ub][2][own.r], rhoA, divA);
-                double gx, gy, gz, lap;
-                grad_lap_planes<R2::RX>(Tm, T0, Tp, own.r, gx, gy, gz, lap);
-                k1b = energy_k(kb, Tb, gx, gy, gz, lap);
-                Tt = Tb + k1b;
-            }
-            s_Tt[sb][own_r1] = Tt;
-            if (ring1) {
-                const double T2 = T0[two.r];
-                double Tt2 = T2;
-                if (!bwall) {
-                    const ECoef k2 = energy_coef(c, s_u[ub][0][two.r], s_u[ub][1][two.r], s_u[ub][2][two.r], rhoB, divB);
+        double k1b = 0.0;
+        ECoef cb = {0.0, 0.0, 0.0, 0.0, 0.0};
+        if (first) {
+            const double divb = dv.push(div_part<R2::RX>(s_u[a & 1][0], s_u[a & 1][1], s_u[a & 1][2], col.r));
+            if (b >= sg.z0 - 1 && b <= sg.z1) {  // uniform
+                double Tt = Tp;
+                if (!(WALLS && (b <= 0 || b >= G.nz - 1))) {
+                    cb = energy_coef(c, uxp, uyp, uzp, rhop, divb);
                     double gx, gy, gz, lap;
-                    grad_lap_planes<R2::RX>(Tm, T0, Tp, two.r, gx, gy, gz, lap);
-                    Tt2 = T2 + energy_k(k2, T2, gx, gy, gz, lap);
+                    grad_lap_planes<R2::RX>(s_T[(b - 1) & 3], s_T[b & 3], s_T[a & 3], col.r, gx, gy, gz, lap);
+                    k1b = energy_k(cb, Tp, gx, gy, gz, lap);
+                    Tt = Tp + k1b;
                 }
-                s_Tt[sb][two_r1] = Tt2;
+                s_Tt[b & 3][r1] = Tt;
             }
         }
-        rhoA = rhoA0;
-        rhoB = rhoB0;
-        __syncthreads();
 
-        // second stage of plane q = a - 2 on the tile: k2 = K(T~),
-        // T^{n+1} = T^n + (k1 + k2)/2 (wall planes keep T), stored in the
-        // next step.  Stores of a plane outside the segment or of a lane
-        // outside the lattice are dropped (empty range, out-of-range offset),
-        // not branched around.
-        const int q = a - 2;
-        {
-            const bool liveq = q >= sg.z0 && q < sg.z1;  // uniform
-            const int sq = wrap_mod(q, 3);
+        // second stage of plane q = a - 3 on the tile: k2 = K(T~), T^{n+1} =
+        // T^n + (k1 + k2)/2 (wall planes keep T).  T~ of q + 1 was written
+        // in the previous step, before this step's barrier.
+        const int q = a - 3;
+        if (tile) {
             double gx, gy, gz, lap;
-            grad_lap_planes<R1::RX>(s_Tt[wrap_mod(q - 1, 3)], s_Tt[sq], s_Tt[wrap_mod(q + 1, 3)], own_r1, gx, gy, gz,
-                                    lap);
-            const double k2 = energy_k(hk, s_Tt[sq][own_r1], gx, gy, gz, lap);
+            grad_lap_planes<R1::RX>(s_Tt[(q - 1) & 3], s_Tt[q & 3], s_Tt[(q + 1) & 3], r1, gx, gy, gz, lap);
+            const double k2 = energy_k(hc2, s_Tt[q & 3][r1], gx, gy, gz, lap);
             const bool wq = WALLS && (q == 0 || q == G.nz - 1);
-            pendT = wq ? hT : hT + 0.5 * (hk1 + k2);
-            pendq = liveq ? q : -1;
+            pendT = wq ? hT2 : hT2 + 0.5 * (hk2 + k2);
+            pendq = (q >= sg.z0 && q < sg.z1) ? q : -1;
         }
-        hT = Tb;
+        hT2 = hT1;
+        hk2 = hk1;
+        hc2 = hc1;
+        hT1 = Tp;
         hk1 = k1b;
-        hk = kb;
+        hc1 = cb;
+        Tp = Ta;
+        uxp = uxa;
+        uyp = uya;
+        uzp = uza;
+        rhop = rhoa;
     }
-    buf_st(layer_rsrc(Tout + (size_t)(pendq >= sg.z0 ? pendq : sg.z0) * plane, plane, pendq < sg.z0), pendvo, 0u,
+    buf_st(layer_rsrc(Tout + (size_t)(pendq >= sg.z0 ? pendq : sg.z0) * plane, plane, pendq < sg.z0), vst, 0u,
            pendT);
 }
 
 template <class T>
-MarchG3 march_grid3(int nx, int ny, int nz, int cus)
+MarchG3 march_grid3(int nx, int ny, int nz, int cus, int per_cu = 1)
 {
     MarchG3 g;
     g.ntx = (nx + T::TX - 1) / T::TX;
     g.nty = (ny + T::TY - 1) / T::TY;
     const long tiles = (long)g.ntx * g.nty;
-    long nseg = (cus + tiles - 1) / tiles;
+    long nseg = ((long)cus * per_cu + tiles - 1) / tiles;
     const long maxseg = nz / 8 > 0 ? nz / 8 : 1;  // segments of at least 8 planes
     if (nseg > maxseg) nseg = maxseg;
     if (nseg < 1) nseg = 1;
@@ -728,10 +705,10 @@ hipError_t march_t(const LatticeLaunch &L, double *U)
 {
     const Grid3 G{L.nx, L.ny, L.nz, (unsigned)((size_t)L.nx * L.ny * L.nz)};
     const MarchG3 M = march_grid3<TileL>(L.nx, L.ny, L.nz, L.resident);
-    const MarchG3 ME = march_grid3<TileE>(L.nx, L.ny, L.nz, L.resident);
+    const MarchG3 ME = march_grid3<TileE>(L.nx, L.ny, L.nz, L.resident, kEBlocksPerCU);
     hipLaunchKernelGGL((d3q19_march_l<S, WALLS>), dim3(M.nblocks), dim3(TileL::Threads), 0, L.stream, (const S *)L.fin,
                        (S *)L.fout, L.Tin, U, L.phys, G, M, L.partials, L.st, L.step, L.rref);
-    hipLaunchKernelGGL((d3q19_march_e<WALLS>), dim3(ME.nblocks), dim3(TileE::Threads), 0, L.stream, L.Tin, L.Tout,
+    hipLaunchKernelGGL((d3q19_march_e<WALLS>), dim3(ME.nblocks), dim3(kEThreads), 0, L.stream, L.Tin, L.Tout,
                        (const double *)U, L.phys, G, ME);
     return hipGetLastError();
 }
