@@ -43,9 +43,11 @@ struct PopIO<double> {
     {
         return p[i];
     }
+    template <bool STREAM>
     __device__ static __forceinline__ double store(double *p, size_t i, double v, double)
     {
-        p[i] = v;
+        if (STREAM) __builtin_nontemporal_store(v, &p[i]);
+        else p[i] = v;
         return v;
     }
 };
@@ -57,10 +59,12 @@ struct PopIO<float> {
     {
         return wref + (double)p[i];
     }
+    template <bool STREAM>
     __device__ static __forceinline__ double store(float *p, size_t i, double v, double wref)
     {
         const float d = (float)(v - wref);
-        p[i] = d;
+        if (STREAM) __builtin_nontemporal_store(d, &p[i]);
+        else p[i] = d;
         return wref + (double)d;  // the value the next step will read
     }
 };
@@ -316,7 +320,7 @@ __device__ __forceinline__ void pull_loads(const S *__restrict__ fin, const doub
     if (9 >= i0 && 9 < i1) T = Tin[q.row + gx];
 }
 
-template <class S, bool TAU1, bool WALLS, int TX, int TY, int NT, int MIN_WAVES_PER_EU, int PFP>
+template <class S, bool TAU1, bool WALLS, int TX, int TY, int NT, int MIN_WAVES_PER_EU, int PFP, bool STREAM>
 __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step(const S *__restrict__ fin,
                                                          S *__restrict__ fout,
                                                          const double *__restrict__ Tin,
@@ -602,7 +606,8 @@ __global__ __launch_bounds__(NT, MIN_WAVES_PER_EU) void d2q9_step(const S *__res
                                    kW5 * ry_ref, kW5 * ry_ref, kW5 * ry_ref, kW5 * ry_ref};
             double v[9];
 #pragma unroll
-            for (int i = 0; i < 9; ++i) v[i] = PopIO<S>::store(fout, (size_t)i * N + g, fs[i], wst[i]);
+            for (int i = 0; i < 9; ++i)
+                v[i] = PopIO<S>::template store<STREAM>(fout, (size_t)i * N + g, fs[i], wst[i]);
             const double nm = next_mass<WALLS>(v, gy, ny);
             part.mass_n += rho;
             part.mass_next += nm;
@@ -772,9 +777,16 @@ hipError_t launch_t(const LatticeLaunch &L)
     // first three populations do, more would spill.  The general-relaxation
     // collision needs those registers itself.
     constexpr int PFP = TAU1 ? (sizeof(S) == 4 ? 10 : 3) : 0;
-    hipLaunchKernelGGL((d2q9_step<S, TAU1, WALLS, kTX, kTY, kNT, 4, PFP>), dim3(nb), dim3(kNT), 0, L.stream,
-                       (const S *)L.fin, (S *)L.fout, L.Tin, L.Tout, L.phys, L.nx, L.ny, tiles_x,
-                       ntiles, L.partials, L.st, L.step, L.rref);
+    // Populations are stored with the non-temporal policy when the two levels
+    // do not fit in three quarters of the 256 MiB last-level (infinity) cache:
+    // the next step then reads them from HBM anyway (1024 x 2048 FP64: 94 ->
+    // 87 us per step); a state that fits is re-read from that cache, and
+    // streaming its stores past it measured slower (FP32: 66 -> 72 us).
+    const bool stream = 2 * 9 * (size_t)L.nx * L.ny * sizeof(S) > (size_t(192) << 20);
+    auto kern = stream ? d2q9_step<S, TAU1, WALLS, kTX, kTY, kNT, 4, PFP, true>
+                       : d2q9_step<S, TAU1, WALLS, kTX, kTY, kNT, 4, PFP, false>;
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(kNT), 0, L.stream, (const S *)L.fin, (S *)L.fout, L.Tin, L.Tout, L.phys,
+                       L.nx, L.ny, tiles_x, ntiles, L.partials, L.st, L.step, L.rref);
     return hipGetLastError();
 }
 
