@@ -182,7 +182,7 @@ def run_d3q19(T, torch, steps, warmup):
         lat.close()
         # the same steps with FP64 populations: the error of the FP32 storage
         p64 = T.make_params(T.D3Q19, nx=n, ny=n, nz=n, walls=True, precision=T.FP64,
-                            gravity_form=form, g=1e-5)
+                            gravity_form=form, g=1e-5, state=T.STATE_MOMENTS)
         lat = T.Lattice(p64)
         lat.set_state(rho0, T0)
         lat.step(warmup)

@@ -68,12 +68,14 @@ extern "C" {
  * force-corrected velocity and force (Eq. LiFS with Eq. OperatorMRT at
  * Lambda = I), so an FP64 lattice can carry its moments instead of the
  * populations: rho and j (D2Q9, 3 planes instead of 9) or rho, j and psi
- * (D3Q19, 5 planes instead of 19), plus T.  AUTO does that where it applies
- * (FP64, every tau = 1; the same arithmetic as the population state, equal to
- * rounding) and stores populations everywhere else; POPULATIONS always stores
- * populations. */
+ * (D3Q19, 5 planes instead of 19), plus T; the same arithmetic as the
+ * population state, equal to rounding.  MOMENTS carries the moments (FP64,
+ * every tau = 1 only: TPLBM_EINVAL otherwise); POPULATIONS always stores
+ * populations; AUTO takes the faster of the two where both apply: the
+ * moments on D2Q9, the populations on D3Q19. */
 #define TPLBM_STATE_AUTO 0
 #define TPLBM_STATE_POPULATIONS 1
+#define TPLBM_STATE_MOMENTS 2
 
 #define TPLBM_EOS_CARNAHAN_STARLING 0
 #define TPLBM_EOS_IDEAL_LATTICE 1 /* p = rho/3, psi = 0: for tests of the closed forms */

@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ESHAPE", 3: "EUNSUPPORTED", 4: "EHIP",
                 5: "EUNPHYSICAL", 6: "ENOTCONVERGED", 7: "ENOSOLUTION"}
 D1Q3, D2Q9, D3Q19 = 1, 2, 3
 FP64, FP32_DEV = 0, 1
-STATE_AUTO, STATE_POPULATIONS = 0, 1
+STATE_AUTO, STATE_POPULATIONS, STATE_MOMENTS = 0, 1, 2
 FIELDS = {"rho": 0, "ux": 1, "uy": 2, "uz": 3, "T": 4, "p_eos": 5, "p_nn": 6}
 FLAG_NAMES = {1: "nan", 2: "rho<=0", 4: "eta>=1", 8: "psi undefined"}
 

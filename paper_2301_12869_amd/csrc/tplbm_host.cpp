@@ -80,10 +80,18 @@ bool tau_one(const tplbm_params &p)
 // The moment state applies where the post-collision set is a closed function
 // of (rho, u, F): every rate 1 (D2Q9 with all rates 1, D3Q19 always); FP64 so
 // that it carries exactly what the population state would.
+bool moments_apply(const tplbm_params &p)
+{
+    return (p.lattice == TPLBM_D2Q9 || p.lattice == TPLBM_D3Q19) && p.precision == TPLBM_FP64 && tau_one(p);
+}
+
+// AUTO takes the faster state: the moment state on D2Q9 (its row-marching
+// kernel), the populations on D3Q19 (its z-marching kernels beat the moment
+// passes); MOMENTS asks for the moment state wherever it applies.
 bool uses_moments(const tplbm_params &p)
 {
-    return (p.lattice == TPLBM_D2Q9 || p.lattice == TPLBM_D3Q19) && p.precision == TPLBM_FP64 && tau_one(p) &&
-           p.state == TPLBM_STATE_AUTO;
+    if (p.state == TPLBM_STATE_MOMENTS) return moments_apply(p);
+    return p.state == TPLBM_STATE_AUTO && p.lattice == TPLBM_D2Q9 && moments_apply(p);
 }
 
 int validate(const tplbm_params *p)
@@ -118,8 +126,12 @@ int validate(const tplbm_params *p)
     }
     if (!(p->cv > 0) || !(p->kappa >= 0)) return fail(nullptr, TPLBM_EINVAL, "need c_v > 0, kappa >= 0");
     if (!std::isfinite(p->g) || !std::isfinite(p->sigma)) return fail(nullptr, TPLBM_EINVAL, "g and sigma must be finite");
-    if (p->state != TPLBM_STATE_AUTO && p->state != TPLBM_STATE_POPULATIONS)
-        return fail(nullptr, TPLBM_EINVAL, "state must be TPLBM_STATE_AUTO or TPLBM_STATE_POPULATIONS");
+    if (p->state != TPLBM_STATE_AUTO && p->state != TPLBM_STATE_POPULATIONS && p->state != TPLBM_STATE_MOMENTS)
+        return fail(nullptr, TPLBM_EINVAL,
+                    "state must be TPLBM_STATE_AUTO, TPLBM_STATE_POPULATIONS or TPLBM_STATE_MOMENTS");
+    if (p->state == TPLBM_STATE_MOMENTS && !moments_apply(*p))
+        return fail(nullptr, TPLBM_EINVAL,
+                    "the moment state needs a D2Q9 or D3Q19 lattice in FP64 with every relaxation time 1");
     if (p->precision == TPLBM_FP32_DEV && p->ref_interval < 0 && !std::isfinite(p->rho_ref))
         return fail(nullptr, TPLBM_EINVAL, "rho_ref must be finite");
     return TPLBM_OK;

@@ -65,8 +65,12 @@ def test_invalid_parameters_are_rejected_on_the_host(lib):
     pop = T.make_params(T.D2Q9, nx=4, ny=8, state=T.STATE_POPULATIONS)
     assert lib.tplbm_workspace_bytes(ctypes.byref(pop), ctypes.byref(nb)) == T.OK
     assert nb.value > 2 * 9 * 32 * 8
+    mom = T.make_params(T.D2Q9, nx=4, ny=8, state=T.STATE_MOMENTS)
+    assert lib.tplbm_workspace_bytes(ctypes.byref(mom), ctypes.byref(nb)) == T.OK
     cases = [dict(ny=2), dict(tau=(1, 1, 1, 1, 1, 0.5)), dict(G=1.0), dict(gravity_form=4),
-             dict(gravity_form=3, rho_v=float("inf")), dict(precision=7), dict(lattice=5), dict(state=2)]
+             dict(gravity_form=3, rho_v=float("inf")), dict(precision=7), dict(lattice=5), dict(state=3),
+             dict(state=T.STATE_MOMENTS, precision=T.FP32_DEV), dict(state=T.STATE_MOMENTS, tau=(1, 1, 1, 0.8, 1, 1)),
+             dict(state=T.STATE_MOMENTS, lattice=T.D1Q3)]
     for over in cases:
         kw = dict(lattice=T.D2Q9, nx=4, ny=8)
         kw.update(over)

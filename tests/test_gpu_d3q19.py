@@ -74,10 +74,12 @@ def _state(orc, crit, shape, seed, layers):
                                               ((7, 4, 9), False, 2), ((1, 1, 20), True, 2),
                                               ((5, 6, 13), True, 3)])
 def test_small_lattices_fp64(T, orc, crit, shape, walls, form):
-    _log(f"case d3q19 fp64 {shape} walls={walls} form={form}")
+    """The moment state (rho, j, psi and T carried between steps) against the
+    oracle."""
+    _log(f"case d3q19 fp64 moment state {shape} walls={walls} form={form}")
     rho0, T0 = _state(orc, crit, shape, 5, shape[2] // 3)
     want = _oracle(orc, shape, walls, form, 2e-4, rho0, T0, 200)
-    got = _gpu(T, shape, walls, form, 2e-4, rho0, T0, 200)
+    got = _gpu(T, shape, walls, form, 2e-4, rho0, T0, 200, state=T.STATE_MOMENTS)
     for k in ("rho", "T"):
         assert _rel(got[k], want[k]) < 1e-12, (k, _rel(got[k], want[k]))
     for k in ("ux", "uy", "uz"):
@@ -119,14 +121,15 @@ def test_fp32_deviation_several_tiles(T, orc, crit):
 @pytest.mark.parametrize("shape,walls,form", [((70, 9, 11), True, 2), ((33, 10, 7), False, 1),
                                               ((40, 12, 9), True, 3)])
 def test_moment_state_matches_population_state(T, orc, crit, shape, walls, form):
-    """FP64 D3Q19 carries (rho, j, psi) and T between steps by default; the
-    nineteen-population state computes the same expressions, so the two agree
-    to rounding (differently fused multiply-adds), on lattices spanning
-    several tiles of both kernels with ragged edges."""
+    """The moment state carries (rho, j, psi) and T between steps; the
+    nineteen-population state (the default for FP64 D3Q19) computes the same
+    expressions, so the two agree to rounding (differently fused
+    multiply-adds), on lattices spanning several tiles of both kernels with
+    ragged edges."""
     _log(f"case d3q19 moment vs population {shape} walls={walls} form={form}")
     rho0, T0 = _state(orc, crit, shape, 8, shape[2] // 3)
-    pop = _gpu(T, shape, walls, form, 2e-4, rho0, T0, 300, state=T.STATE_POPULATIONS)
-    mom = _gpu(T, shape, walls, form, 2e-4, rho0, T0, 300)
+    pop = _gpu(T, shape, walls, form, 2e-4, rho0, T0, 300)
+    mom = _gpu(T, shape, walls, form, 2e-4, rho0, T0, 300, state=T.STATE_MOMENTS)
     for k in ("rho", "T"):
         assert _rel(mom[k], pop[k]) < 1e-13, (k, _rel(mom[k], pop[k]))
     for k in ("ux", "uy", "uz"):
@@ -138,7 +141,7 @@ def test_moment_state_matches_population_state(T, orc, crit, shape, walls, form)
 def test_moment_state_checkpoint_is_bitwise(T, orc, crit):
     shape = (34, 9, 10)
     rho0, T0 = _state(orc, crit, shape, 9, 3)
-    p = T.make_params(T.D3Q19, nx=34, ny=9, nz=10, walls=True, gravity_form=2, g=2e-4)
+    p = T.make_params(T.D3Q19, nx=34, ny=9, nz=10, walls=True, gravity_form=2, g=2e-4, state=T.STATE_MOMENTS)
     a = T.Lattice(p)
     a.set_state(rho0, T0)
     a.step(40)

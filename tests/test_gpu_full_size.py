@@ -85,15 +85,17 @@ def test_d2q9_1024x2048_after_1000_steps(T, form):
          f"{_rel(out['rho'].sum(axis=1), g[f'form{form}_row_rho']):.2e}")
 
 
+@pytest.mark.parametrize("state", ["populations", "moments"])
 @pytest.mark.parametrize("form", [1, 2])
-def test_d3q19_256cubed_after_100_steps(T, form):
+def test_d3q19_256cubed_after_100_steps(T, form, state):
     g = _golden("c4_d3q19_256cubed_100_steps.npz")
     n = 256
     rl, rv, T_c = float(g["rho_l"]), float(g["rho_v"]), float(g["T_c"])
     rho0 = W.layered_density((n, n, n), 64, rl, rv, 1e-3, seed=4)
     T0 = W.wall_temperature_field((n, n, n), 0.8 * T_c, 0.9 * T_c, 0.8 * T_c)
-    _log(f"case d3q19 256^3 form {form}, {int(g['steps'])} steps against the oracle's golden")
-    lat = T.Lattice(T.make_params(T.D3Q19, nx=n, ny=n, nz=n, walls=True, gravity_form=form, g=1e-5))
+    _log(f"case d3q19 256^3 form {form}, {state} state, {int(g['steps'])} steps against the oracle's golden")
+    st = T.STATE_POPULATIONS if state == "populations" else T.STATE_MOMENTS
+    lat = T.Lattice(T.make_params(T.D3Q19, nx=n, ny=n, nz=n, walls=True, gravity_form=form, g=1e-5, state=st))
     lat.set_state(rho0, T0)
     lat.step(int(g["steps"]))
     planes, ys, xs = g["planes"], g["ys"], g["xs"]
