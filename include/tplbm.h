@@ -538,7 +538,7 @@ int tplbm_net_predict(tplbm_net *n, int32_t ncols, const tplbm_net_column *cols,
 int tplbm_net_predict_device(tplbm_net *n, int32_t ncols, const tplbm_net_column *cols, double *dev_rho,
                              double *dev_T);
 
-/* One v_mfma_f32_32x32x8_bf16 on host operands: a and b hold 64 lanes x 4
+/* One v_mfma_f32_32x32x16_bf16 on host operands: a and b hold 64 lanes x 8
  * bf16 values each (lane-major), d receives 64 lanes x 16 FP32 results.  For
  * checking the matrix-core lane layout the kernels assume. */
 int tplbm_net_mfma_check(tplbm_net *n, const uint16_t *a, const uint16_t *b, float *d);

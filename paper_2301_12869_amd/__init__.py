@@ -679,8 +679,8 @@ class Net:
     def mfma_check(self, a, b) -> np.ndarray:
         a = np.ascontiguousarray(a, dtype=np.uint16)
         b = np.ascontiguousarray(b, dtype=np.uint16)
-        if a.size != 256 or b.size != 256:
-            raise ValueError("a and b hold 64 lanes x 4 bf16 values")
+        if a.size != 512 or b.size != 512:
+            raise ValueError("a and b hold 64 lanes x 8 bf16 values")
         d = np.empty(1024, dtype=np.float32)
         _ncheck(load_library().tplbm_net_mfma_check(self._h, a.ctypes.data_as(_U16P),
                                                     b.ctypes.data_as(_U16P), _fp(d)), self._h)

@@ -1,5 +1,7 @@
 // Warm-start network kernels for gfx950: 1-D convolutions as implicit GEMMs
-// on the BF16 matrix cores (v_mfma_f32_32x32x8_bf16, FP32 accumulation).
+// on the BF16 matrix cores (gfx950's v_mfma_f32_32x32x16_bf16, FP32
+// accumulation: K = 16 per instruction, lanes 0..31 and 32..63 each holding
+// eight consecutive k of their row or column).
 //
 // A batch of columns is laid out position-major, channels fastest, with two
 // all-zero guard positions between columns (and at both ends): a width-5
@@ -24,8 +26,10 @@ namespace tplbm {
 
 namespace {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ __bf16 as_bf(uint16_t h) { return __builtin_bit_cast(__bf16, h); }
 
 __device__ __forceinline__ uint16_t f2bf(float f)
 {
@@ -44,9 +48,11 @@ __device__ __forceinline__ int acc_row(int r, int lane) { return 8 * (r >> 2) + 
 // MODE 1: output layer:         out_f32[p][o] = acc + bias for o < NOUT
 // MODE 2: input gradient:       g = acc * (mask[p][o] > 0); out_f32 = g, out_bf16 = bf16(g)
 // Persistent blocks of 4 waves: the layer's BF16 weights are staged in LDS
-// once per block (rows padded by 4 elements against bank conflicts), then
-// the block walks 128-position tiles; each wave owns 32 positions and all
-// 32 NTILES output channels, so one activation fragment feeds NTILES MFMAs.
+// once per block (rows padded by 8 elements: 16-byte rows for the 8-element
+// fragments), then the block walks 128-position tiles; each wave owns 32
+// positions and all 32 NTILES output channels, so one activation fragment
+// feeds NTILES MFMAs.  K runs over (tap, input channel), 16 at a time; with
+// 8 input channels the last step's upper half (a sixth tap) is zero.
 template <int CIN, int NTILES, int MODE, int NOUT>
 __global__ __launch_bounds__(256) void conv_mfma(const uint16_t *__restrict__ in, const uint16_t *__restrict__ W,
                                                  const float *__restrict__ bias, int P,
@@ -56,8 +62,10 @@ __global__ __launch_bounds__(256) void conv_mfma(const uint16_t *__restrict__ in
 {
     constexpr int COUT = 32 * NTILES;
     constexpr int ROW = 5 * CIN;       // weights of one output channel
-    constexpr int RS = ROW + 4;        // padded LDS row
-    __shared__ uint16_t sW[COUT * RS];
+    constexpr int RS = ROW + 8;        // padded LDS row
+    constexpr int KS = (ROW + 15) / 16;  // K steps
+    static_assert(CIN % 8 == 0, "a lane's eight k lie in one tap");
+    __shared__ __attribute__((aligned(16))) uint16_t sW[COUT * RS];
     for (int e = threadIdx.x; e < COUT * ROW / 4; e += 256) {
         const int o = (4 * e) / ROW, k = (4 * e) % ROW;
         *reinterpret_cast<uint2 *>(&sW[o * RS + k]) = *reinterpret_cast<const uint2 *>(W + 4 * (size_t)e);
@@ -75,17 +83,20 @@ __global__ __launch_bounds__(256) void conv_mfma(const uint16_t *__restrict__ in
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[nt][r] = 0.0f;
 #pragma unroll
-        for (int t = 0; t < 5; ++t) {
-            int q = p0 + i + t - 2;
+        for (int m = 0; m < KS; ++m) {
+            // this half-wave's eight k: tap t, input channels c .. c + 7
+            const int k0 = 16 * m + 8 * kq, t = k0 / CIN, c = k0 % CIN;
+            const bool tap = t < 5;
+            int q = p0 + i + (tap ? t : 0) - 2;
             q = q < 0 ? 0 : (q >= P ? P - 1 : q);  // both ends are guard positions (zero)
+            const bf16x8 zero = {};
+            const bf16x8 la = *reinterpret_cast<const bf16x8 *>(in + (size_t)q * CIN + c);
+            const bf16x8 a = tap ? la : zero;
 #pragma unroll
-            for (int c0 = 0; c0 < CIN; c0 += 8) {
-                const bf16x4 a = *reinterpret_cast<const bf16x4 *>(in + (size_t)q * CIN + c0 + 4 * kq);
-#pragma unroll
-                for (int nt = 0; nt < NTILES; ++nt) {
-                    const bf16x4 b = *reinterpret_cast<const bf16x4 *>(&sW[(32 * nt + i) * RS + t * CIN + c0 + 4 * kq]);
-                    acc[nt] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc[nt], 0, 0, 0);
-                }
+            for (int nt = 0; nt < NTILES; ++nt) {
+                const bf16x8 lb = *reinterpret_cast<const bf16x8 *>(&sW[(32 * nt + i) * RS + (tap ? k0 : 0)]);
+                const bf16x8 b = tap ? lb : zero;
+                acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[nt], 0, 0, 0);
             }
         }
 #pragma unroll
@@ -155,32 +166,26 @@ __global__ __launch_bounds__(256) void dw_mfma(const uint16_t *__restrict__ dZ, 
         }
         __syncthreads();
 #pragma unroll 2
-        for (int k8 = 0; k8 < CH; k8 += 8) {
-            const int pk = k8 + 4 * kq;
+        for (int k16 = 0; k16 < CH; k16 += 16) {
+            const int pk = k16 + 8 * kq;
 #pragma unroll
             for (int k = 0; k < TPW; ++k) {
                 const int tile = wave + 4 * k;
                 if (tile >= TILES) break;
                 const int mt = tile % MT, nt = tile / MT;
                 const int o = 32 * mt + i;
-                bf16x4 a;
-                a[0] = (short)sZ[o][pk];
-                a[1] = (short)sZ[o][pk + 1];
-                a[2] = (short)sZ[o][pk + 2];
-                a[3] = (short)sZ[o][pk + 3];
+                bf16x8 a;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) a[e] = as_bf(sZ[o][pk + e]);
                 const int n = 32 * nt + i;
-                bf16x4 b;
+                bf16x8 b = {};
                 if (n < NN) {
                     const int t = n / CIN, c = n % CIN;
                     // X[p + t - 2] for p = p0 + pk + j  ->  sX index pk + j + t
-                    b[0] = (short)sX[c][pk + t];
-                    b[1] = (short)sX[c][pk + t + 1];
-                    b[2] = (short)sX[c][pk + t + 2];
-                    b[3] = (short)sX[c][pk + t + 3];
-                } else {
-                    b[0] = b[1] = b[2] = b[3] = 0;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) b[e] = as_bf(sX[c][pk + t + e]);
                 }
-                acc[k] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc[k], 0, 0, 0);
+                acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[k], 0, 0, 0);
             }
         }
     }
@@ -399,16 +404,16 @@ __global__ void raw_out(const NetCol *__restrict__ cols, const NetEntry *__restr
 __global__ void mfma_probe(const uint16_t *__restrict__ a, const uint16_t *__restrict__ b, float *__restrict__ d)
 {
     const int lane = threadIdx.x;
-    bf16x4 av, bv;
+    bf16x8 av, bv;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        av[k] = (short)a[lane * 4 + k];
-        bv[k] = (short)b[lane * 4 + k];
+    for (int k = 0; k < 8; ++k) {
+        av[k] = as_bf(a[lane * 8 + k]);
+        bv[k] = as_bf(b[lane * 8 + k]);
     }
     f32x16 acc;
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bv, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
 #pragma unroll
     for (int r = 0; r < 16; ++r) d[lane * 16 + r] = acc[r];
 }

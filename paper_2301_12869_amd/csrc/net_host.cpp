@@ -529,10 +529,10 @@ int tplbm_net_mfma_check(tplbm_net *n, const uint16_t *a, const uint16_t *b, flo
     if (!n || !a || !b || !d) return nfail(n, TPLBM_EINVAL, "NULL argument");
     // operands and result are staged in the partial-sum area (free between calls)
     uint16_t *da = (uint16_t *)n->partial;
-    uint16_t *db = da + 256;
-    float *dd = (float *)(db + 256);
-    NHIP(n, hipMemcpyAsync(da, a, 2 * 256, hipMemcpyHostToDevice, n->stream));
-    NHIP(n, hipMemcpyAsync(db, b, 2 * 256, hipMemcpyHostToDevice, n->stream));
+    uint16_t *db = da + 512;
+    float *dd = (float *)(db + 512);
+    NHIP(n, hipMemcpyAsync(da, a, 2 * 512, hipMemcpyHostToDevice, n->stream));
+    NHIP(n, hipMemcpyAsync(db, b, 2 * 512, hipMemcpyHostToDevice, n->stream));
     NHIP(n, net_mfma_probe(da, db, dd, n->stream));
     NHIP(n, hipMemcpyAsync(d, dd, sizeof(float) * 1024, hipMemcpyDeviceToHost, n->stream));
     NHIP(n, hipStreamSynchronize(n->stream));

@@ -69,21 +69,21 @@ def _net(T, consts, max_cols=16, max_nodes=8192, dataset_cols=0, dataset_nodes=0
 
 
 def test_mfma_lane_layout(T, consts):
-    """One 32x32x8 BF16 product on small integers (exact in FP32) against the
-    lane layout the kernels assume: A[i][k] in lane i + 32 (k / 4), element
-    k % 4; B[k][j] likewise with j; D[row][col] in lane col + 32 q, element r
-    with row = 8 (r / 4) + 4 q + r % 4."""
+    """One 32x32x16 BF16 product on small integers (exact in FP32) against
+    the lane layout the kernels assume: A[i][k] in lane i + 32 (k / 8),
+    element k % 8; B[k][j] likewise with j; D[row][col] in lane col + 32 q,
+    element r with row = 8 (r / 4) + 4 q + r % 4."""
     net = _net(T, consts)
-    ra = np.round(4 * W.uniform_pm1(1, 256)).astype(np.float32)
-    rb = np.round(4 * W.uniform_pm1(2, 256)).astype(np.float32)
+    ra = np.round(4 * W.uniform_pm1(1, 512)).astype(np.float32)
+    rb = np.round(4 * W.uniform_pm1(2, 512)).astype(np.float32)
     a16 = (ra.view(np.uint32) >> 16).astype(np.uint16)
     b16 = (rb.view(np.uint32) >> 16).astype(np.uint16)
-    A = np.zeros((32, 8)); B = np.zeros((8, 32))
+    A = np.zeros((32, 16)); B = np.zeros((16, 32))
     for lane in range(64):
-        for e in range(4):
-            k = 4 * (lane // 32) + e
-            A[lane % 32, k] = ra[4 * lane + e]
-            B[k, lane % 32] = rb[4 * lane + e]
+        for e in range(8):
+            k = 8 * (lane // 32) + e
+            A[lane % 32, k] = ra[8 * lane + e]
+            B[k, lane % 32] = rb[8 * lane + e]
     D = A @ B
     d = net.mfma_check(a16, b16)
     for lane in range(64):
