@@ -578,7 +578,8 @@ __global__ __launch_bounds__(kEThreads) void d3q19_march_e(const double *__restr
     // rings of planes indexed by z & 3 (z & 1 for u): the step of plane a
     // writes T and u of plane a, then after its one barrier reads T of a - 2
     // .. a, u of a, and T~ of a - 4 .. a - 2, and writes T~ of a - 1; every
-    // slot a step writes was last read two barriers earlier
+    // slot a step writes was last read before a barrier that lies between
+    // that read and the write
     __shared__ double s_T[4][R2::N];
     __shared__ double s_u[2][3][R2::N];
     __shared__ double s_Tt[4][R1::N];
