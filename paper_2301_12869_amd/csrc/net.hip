@@ -128,7 +128,9 @@ __global__ __launch_bounds__(256) void conv_mfma(const uint16_t *__restrict__ in
 // N = 5 CIN (t, i) and K = positions.  dZ has ZS channels per position
 // (rows o >= ZS are zero).  Each 64-position chunk of dZ and of X (with a
 // 2-position halo on each side) is staged transposed in LDS, so a lane's
-// four consecutive positions are adjacent.
+// eight consecutive positions are adjacent; the chunk is read with 16-byte
+// loads (eight channels of a position) one chunk ahead, into registers,
+// while the matrix cores work on the current one.
 template <int CIN, int COUT, int ZS>
 __global__ __launch_bounds__(256) void dw_mfma(const uint16_t *__restrict__ dZ, const uint16_t *__restrict__ X,
                                                int P, int span, float *__restrict__ partial)
@@ -139,7 +141,11 @@ __global__ __launch_bounds__(256) void dw_mfma(const uint16_t *__restrict__ dZ, 
     constexpr int NT = (NN + 31) / 32;
     constexpr int TILES = MT * NT;
     constexpr int TPW = (TILES + 3) / 4;
-    __shared__ uint16_t sZ[COUT][CH + 4];
+    constexpr int ZV = COUT / 8, XV = CIN / 8;            // 8-channel groups
+    constexpr int NZ = (ZV * CH + 255) / 256;             // 16-byte loads per thread and chunk: dZ
+    constexpr int NXL = (XV * (CH + 4) + 255) / 256;      // and X
+    static_assert(ZS % 8 == 0 && CIN % 8 == 0, "16-byte groups of channels");
+    __shared__ __attribute__((aligned(16))) uint16_t sZ[COUT][CH + 8];
     __shared__ uint16_t sX[CIN][CH + 8];  // positions p0 - 2 .. p0 + CH + 1
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -151,20 +157,48 @@ __global__ __launch_bounds__(256) void dw_mfma(const uint16_t *__restrict__ dZ, 
         for (int r = 0; r < 16; ++r) acc[k][r] = 0.0f;
 
     const int pbeg = blockIdx.x * span, pend = min(P, pbeg + span);
-    for (int p0 = pbeg; p0 < pend; p0 += CH) {
-        __syncthreads();
-        for (int e = threadIdx.x; e < COUT * CH; e += 256) {
-            const int o = e % COUT, pp = e / COUT;
-            const int p = p0 + pp;
-            sZ[o][pp] = (o < ZS && p < pend) ? dZ[(size_t)p * ZS + o] : (uint16_t)0;
+    uint4 vz[NZ], vx[NXL];
+    auto fetch = [&](int p0) {
+#pragma unroll
+        for (int j = 0; j < NZ; ++j) {
+            const int e = threadIdx.x + 256 * j;
+            const int g = e % ZV, pp = e / ZV, p = p0 + pp;
+            const bool ok = e < ZV * CH && 8 * g < ZS && p < pend;
+            vz[j] = ok ? *reinterpret_cast<const uint4 *>(dZ + (size_t)p * ZS + 8 * g) : make_uint4(0, 0, 0, 0);
         }
-        for (int e = threadIdx.x; e < CIN * (CH + 4); e += 256) {
-            const int c = e % CIN, pp = e / CIN;
+#pragma unroll
+        for (int j = 0; j < NXL; ++j) {
+            const int e = threadIdx.x + 256 * j;
+            const int g = e % XV, pp = e / XV;
             int p = p0 - 2 + pp;
             p = p < 0 ? 0 : (p >= P ? P - 1 : p);
-            sX[c][pp] = X[(size_t)p * CIN + c];
+            vx[j] = e < XV * (CH + 4) ? *reinterpret_cast<const uint4 *>(X + (size_t)p * CIN + 8 * g)
+                                      : make_uint4(0, 0, 0, 0);
+        }
+    };
+    auto unpack = [](uint16_t *col, int stride, const uint4 &v) {
+        const unsigned w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            col[(2 * m) * stride] = (uint16_t)(w[m] & 0xffffu);
+            col[(2 * m + 1) * stride] = (uint16_t)(w[m] >> 16);
+        }
+    };
+    if (pbeg < pend) fetch(pbeg);
+    for (int p0 = pbeg; p0 < pend; p0 += CH) {
+        __syncthreads();  // the previous chunk's products have read the LDS tiles
+#pragma unroll
+        for (int j = 0; j < NZ; ++j) {
+            const int e = threadIdx.x + 256 * j;
+            if (e < ZV * CH) unpack(&sZ[8 * (e % ZV)][e / ZV], CH + 8, vz[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < NXL; ++j) {
+            const int e = threadIdx.x + 256 * j;
+            if (e < XV * (CH + 4)) unpack(&sX[8 * (e % XV)][e / XV], CH + 8, vx[j]);
         }
         __syncthreads();
+        if (p0 + CH < pend) fetch(p0 + CH);
 #pragma unroll 2
         for (int k16 = 0; k16 < CH; k16 += 16) {
             const int pk = k16 + 8 * kq;
@@ -174,9 +208,7 @@ __global__ __launch_bounds__(256) void dw_mfma(const uint16_t *__restrict__ dZ, 
                 if (tile >= TILES) break;
                 const int mt = tile % MT, nt = tile / MT;
                 const int o = 32 * mt + i;
-                bf16x8 a;
-#pragma unroll
-                for (int e = 0; e < 8; ++e) a[e] = as_bf(sZ[o][pk + e]);
+                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&sZ[o][pk]);
                 const int n = 32 * nt + i;
                 bf16x8 b = {};
                 if (n < NN) {
