@@ -52,7 +52,10 @@ __device__ __forceinline__ int acc_row(int r, int lane) { return 8 * (r >> 2) + 
 // fragments), then the block walks 128-position tiles; each wave owns 32
 // positions and all 32 NTILES output channels, so one activation fragment
 // feeds NTILES MFMAs.  K runs over (tap, input channel), 16 at a time; with
-// 8 input channels the last step's upper half (a sixth tap) is zero.
+// 8 input channels the last step's upper half (a sixth tap) is zero.  A
+// tile's 132 input positions (2 on each side for the taps) are staged in LDS
+// too, read with 16-byte loads one tile ahead, so each activation is read
+// from memory once per tile rather than once per tap.
 template <int CIN, int NTILES, int MODE, int NOUT>
 __global__ __launch_bounds__(256) void conv_mfma(const uint16_t *__restrict__ in, const uint16_t *__restrict__ W,
                                                  const float *__restrict__ bias, int P,
@@ -64,19 +67,45 @@ __global__ __launch_bounds__(256) void conv_mfma(const uint16_t *__restrict__ in
     constexpr int ROW = 5 * CIN;       // weights of one output channel
     constexpr int RS = ROW + 8;        // padded LDS row
     constexpr int KS = (ROW + 15) / 16;  // K steps
+    constexpr int TP = 128 + 4;        // staged positions of a tile
+    constexpr int AS = CIN + 8;        // padded LDS row of a staged position
+    constexpr int AV = CIN / 8;        // 16-byte groups of a position
+    constexpr int NA = (TP * AV + 255) / 256;  // 16-byte loads per thread and tile
     static_assert(CIN % 8 == 0, "a lane's eight k lie in one tap");
     __shared__ __attribute__((aligned(16))) uint16_t sW[COUT * RS];
+    __shared__ __attribute__((aligned(16))) uint16_t sA[TP * AS];
     for (int e = threadIdx.x; e < COUT * ROW / 4; e += 256) {
         const int o = (4 * e) / ROW, k = (4 * e) % ROW;
         *reinterpret_cast<uint2 *>(&sW[o * RS + k]) = *reinterpret_cast<const uint2 *>(W + 4 * (size_t)e);
     }
-    __syncthreads();
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i = lane & 31, kq = lane >> 5;
+    // positions tile * 128 - 2 .. tile * 128 + 129, clamped (both ends of the
+    // batch are guard positions, zero)
+    uint4 va[NA];
+    auto fetch = [&](int tile) {
+#pragma unroll
+        for (int j = 0; j < NA; ++j) {
+            const int e = threadIdx.x + 256 * j;
+            const int g = e % AV, pp = e / AV;
+            int q = tile * 128 - 2 + pp;
+            q = q < 0 ? 0 : (q >= P ? P - 1 : q);
+            va[j] = e < TP * AV ? *reinterpret_cast<const uint4 *>(in + (size_t)q * CIN + 8 * g)
+                                : make_uint4(0, 0, 0, 0);
+        }
+    };
+    if (blockIdx.x * 128 < P) fetch(blockIdx.x);
     for (int tile = blockIdx.x; tile * 128 < P; tile += gridDim.x) {
+        __syncthreads();  // the previous tile's products have read sA (and sW is staged)
+#pragma unroll
+        for (int j = 0; j < NA; ++j) {
+            const int e = threadIdx.x + 256 * j;
+            if (e < TP * AV) *reinterpret_cast<uint4 *>(&sA[(e / AV) * AS + 8 * (e % AV)]) = va[j];
+        }
+        __syncthreads();
+        if ((tile + (int)gridDim.x) * 128 < P) fetch(tile + gridDim.x);
         const int p0 = tile * 128 + wave * 32;
-        if (p0 >= P) continue;
         f32x16 acc[NTILES];
 #pragma unroll
         for (int nt = 0; nt < NTILES; ++nt)
@@ -84,13 +113,12 @@ __global__ __launch_bounds__(256) void conv_mfma(const uint16_t *__restrict__ in
             for (int r = 0; r < 16; ++r) acc[nt][r] = 0.0f;
 #pragma unroll
         for (int m = 0; m < KS; ++m) {
-            // this half-wave's eight k: tap t, input channels c .. c + 7
+            // this half-wave's eight k: tap t, input channels c .. c + 7 of
+            // position p0 + i + t - 2, staged at wave * 32 + i + t
             const int k0 = 16 * m + 8 * kq, t = k0 / CIN, c = k0 % CIN;
             const bool tap = t < 5;
-            int q = p0 + i + (tap ? t : 0) - 2;
-            q = q < 0 ? 0 : (q >= P ? P - 1 : q);  // both ends are guard positions (zero)
             const bf16x8 zero = {};
-            const bf16x8 la = *reinterpret_cast<const bf16x8 *>(in + (size_t)q * CIN + c);
+            const bf16x8 la = *reinterpret_cast<const bf16x8 *>(&sA[(wave * 32 + i + (tap ? t : 0)) * AS + c]);
             const bf16x8 a = tap ? la : zero;
 #pragma unroll
             for (int nt = 0; nt < NTILES; ++nt) {
@@ -99,6 +127,7 @@ __global__ __launch_bounds__(256) void conv_mfma(const uint16_t *__restrict__ in
                 acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[nt], 0, 0, 0);
             }
         }
+        if (p0 >= P) continue;
 #pragma unroll
         for (int nt = 0; nt < NTILES; ++nt) {
             const int o = 32 * nt + i;
