@@ -74,6 +74,12 @@ __global__ __launch_bounds__(256) void conv_mfma(const uint16_t *__restrict__ in
     static_assert(CIN % 8 == 0, "a lane's eight k lie in one tap");
     __shared__ __attribute__((aligned(16))) uint16_t sW[COUT * RS];
     __shared__ __attribute__((aligned(16))) uint16_t sA[TP * AS];
+    // per-wave transpose of a 32-position output tile (bf16 rows of COUT
+    // channels, or f32 rows of 32 channels), so that outputs leave with
+    // 16-byte stores of consecutive channels; guard flags of the tile
+    constexpr int OS = 64 + 8;
+    __shared__ __attribute__((aligned(16))) uint16_t sO[4][32 * OS];
+    __shared__ uint8_t sG[128];
     for (int e = threadIdx.x; e < COUT * ROW / 4; e += 256) {
         const int o = (4 * e) / ROW, k = (4 * e) % ROW;
         *reinterpret_cast<uint2 *>(&sW[o * RS + k]) = *reinterpret_cast<const uint2 *>(W + 4 * (size_t)e);
@@ -84,7 +90,10 @@ __global__ __launch_bounds__(256) void conv_mfma(const uint16_t *__restrict__ in
     // positions tile * 128 - 2 .. tile * 128 + 129, clamped (both ends of the
     // batch are guard positions, zero)
     uint4 va[NA];
+    int vg = 1;
     auto fetch = [&](int tile) {
+        const int pg = tile * 128 + (int)threadIdx.x;
+        vg = threadIdx.x < 128 && pg < P ? guard[pg] : 1;
 #pragma unroll
         for (int j = 0; j < NA; ++j) {
             const int e = threadIdx.x + 256 * j;
@@ -103,6 +112,7 @@ __global__ __launch_bounds__(256) void conv_mfma(const uint16_t *__restrict__ in
             const int e = threadIdx.x + 256 * j;
             if (e < TP * AV) *reinterpret_cast<uint4 *>(&sA[(e / AV) * AS + 8 * (e % AV)]) = va[j];
         }
+        if (threadIdx.x < 128) sG[threadIdx.x] = (uint8_t)vg;
         __syncthreads();
         if ((tile + (int)gridDim.x) * 128 < P) fetch(tile + gridDim.x);
         const int p0 = tile * 128 + wave * 32;
@@ -128,24 +138,66 @@ __global__ __launch_bounds__(256) void conv_mfma(const uint16_t *__restrict__ in
             }
         }
         if (p0 >= P) continue;
-#pragma unroll
-        for (int nt = 0; nt < NTILES; ++nt) {
-            const int o = 32 * nt + i;
+        if constexpr (MODE == 1) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const int p = p0 + acc_row(r, lane);
-                if (p >= P) continue;
-                const bool g = guard[p] != 0;
-                float v = acc[nt][r];
-                if (MODE == 0) {
-                    v = g ? 0.0f : fmaxf(v + bias[o], 0.0f);
-                    out_bf16[(size_t)p * COUT + o] = f2bf(v);
-                } else if (MODE == 1) {
-                    if (o < NOUT) out_f32[(size_t)p * NOUT + o] = g ? 0.0f : v + bias[o];
-                } else {
-                    v = (g || !(bf2f(mask[(size_t)p * COUT + o]) > 0.0f)) ? 0.0f : v;
-                    out_f32[(size_t)p * COUT + o] = v;
-                    out_bf16[(size_t)p * COUT + o] = f2bf(v);
+                const int pr = acc_row(r, lane), p = p0 + pr;
+                if (p < P && i < NOUT) out_f32[(size_t)p * NOUT + i] = sG[wave * 32 + pr] ? 0.0f : acc[0][r] + bias[i];
+            }
+        } else {
+            // 16-byte pieces of the wave's 32 x COUT tile: lane l takes pieces
+            // l, l + 64, ... (position piece / 8, channels 8 (piece % 8) ..)
+            static_assert(COUT == 64, "the transposed epilogue assumes 64 output channels");
+            uint16_t *ow = sO[wave];
+            if constexpr (MODE == 2) {
+                // the layer input (its ReLU mask) of the tile, as rows of channels
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int c = lane + 64 * j, pp = c >> 3, part = c & 7;
+                    const int p = min(p0 + pp, P - 1);
+                    *reinterpret_cast<uint4 *>(&ow[pp * OS + 8 * part]) =
+                        *reinterpret_cast<const uint4 *>(mask + (size_t)p * COUT + 8 * part);
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+#pragma unroll
+            for (int nt = 0; nt < NTILES; ++nt) {
+                const int o = 32 * nt + i;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int pr = acc_row(r, lane);
+                    const bool g = sG[wave * 32 + pr] != 0;
+                    float v = acc[nt][r];
+                    if (MODE == 0) v = g ? 0.0f : fmaxf(v + bias[o], 0.0f);
+                    else v = (g || !(bf2f(ow[pr * OS + o]) > 0.0f)) ? 0.0f : v;
+                    acc[nt][r] = v;
+                    ow[pr * OS + o] = f2bf(v);  // (pr, o) is this lane's alone
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int c = lane + 64 * j, pp = c >> 3, part = c & 7, p = p0 + pp;
+                if (p < P)
+                    *reinterpret_cast<uint4 *>(out_bf16 + (size_t)p * COUT + 8 * part) =
+                        *reinterpret_cast<const uint4 *>(&ow[pp * OS + 8 * part]);
+            }
+            if constexpr (MODE == 2) {
+                // FP32 copy, 32 channels at a time in the same buffer
+                float *of = reinterpret_cast<float *>(ow);
+#pragma unroll
+                for (int h = 0; h < NTILES; ++h) {
+                    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) of[acc_row(r, lane) * 36 + i] = acc[h][r];
+                    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int c = lane + 64 * j, pp = c >> 3, part = c & 7, p = p0 + pp;
+                        if (p < P)
+                            *reinterpret_cast<float4 *>(out_f32 + (size_t)p * COUT + 32 * h + 4 * part) =
+                                *reinterpret_cast<const float4 *>(&of[pp * 36 + 4 * part]);
+                    }
                 }
             }
         }
