@@ -46,7 +46,9 @@ __device__ __forceinline__ int acc_row(int r, int lane) { return 8 * (r >> 2) + 
 
 // MODE 0: hidden forward layer: out_bf16 = bf16(relu(acc + bias))
 // MODE 1: output layer:         out_f32[p][o] = acc + bias for o < NOUT
-// MODE 2: input gradient:       g = acc * (mask[p][o] > 0); out_f32 = g, out_bf16 = bf16(g)
+// MODE 2: input gradient:       g = acc * (mask[p][o] > 0); out_bf16 = bf16(g), and the
+//                               block's sums of g over its positions per channel (the
+//                               previous layer's bias gradient) into bsum[block][o]
 // Persistent blocks of 4 waves: the layer's BF16 weights are staged in LDS
 // once per block (rows padded by 8 elements: 16-byte rows for the 8-element
 // fragments), then the block walks 128-position tiles; each wave owns 32
@@ -61,7 +63,7 @@ __global__ __launch_bounds__(256) void conv_mfma(const uint16_t *__restrict__ in
                                                  const float *__restrict__ bias, int P,
                                                  const uint8_t *__restrict__ guard,
                                                  const uint16_t *__restrict__ mask, float *__restrict__ out_f32,
-                                                 uint16_t *__restrict__ out_bf16)
+                                                 uint16_t *__restrict__ out_bf16, float *__restrict__ bsum)
 {
     constexpr int COUT = 32 * NTILES;
     constexpr int ROW = 5 * CIN;       // weights of one output channel
@@ -91,6 +93,7 @@ __global__ __launch_bounds__(256) void conv_mfma(const uint16_t *__restrict__ in
     // batch are guard positions, zero)
     uint4 va[NA];
     int vg = 1;
+    float gsum[NTILES] = {};  // MODE 2: this lane's sum of g over its rows of every tile, in tile order
     auto fetch = [&](int tile) {
         const int pg = tile * 128 + (int)threadIdx.x;
         vg = threadIdx.x < 128 && pg < P ? guard[pg] : 1;
@@ -170,7 +173,7 @@ __global__ __launch_bounds__(256) void conv_mfma(const uint16_t *__restrict__ in
                     float v = acc[nt][r];
                     if (MODE == 0) v = g ? 0.0f : fmaxf(v + bias[o], 0.0f);
                     else v = (g || !(bf2f(ow[pr * OS + o]) > 0.0f)) ? 0.0f : v;
-                    acc[nt][r] = v;
+                    if (MODE == 2) gsum[nt] += v;  // zero at guards and past the batch
                     ow[pr * OS + o] = f2bf(v);  // (pr, o) is this lane's alone
                 }
             }
@@ -182,24 +185,24 @@ __global__ __launch_bounds__(256) void conv_mfma(const uint16_t *__restrict__ in
                     *reinterpret_cast<uint4 *>(out_bf16 + (size_t)p * COUT + 8 * part) =
                         *reinterpret_cast<const uint4 *>(&ow[pp * OS + 8 * part]);
             }
-            if constexpr (MODE == 2) {
-                // FP32 copy, 32 channels at a time in the same buffer
-                float *of = reinterpret_cast<float *>(ow);
+        }
+    }
+    if constexpr (MODE == 2) {
+        // the block's channel sums: lanes of both halves of each wave, then
+        // the waves, added in a fixed order (each wave's transpose buffer,
+        // free after the last tile, holds its two halves' sums)
+        float *red = reinterpret_cast<float *>(sO[wave]);
 #pragma unroll
-                for (int h = 0; h < NTILES; ++h) {
-                    __builtin_amdgcn_wave_barrier();
+        for (int nt = 0; nt < NTILES; ++nt) red[kq * COUT + 32 * nt + i] = gsum[nt];
+        __syncthreads();
+        if (threadIdx.x < COUT) {
+            float t = 0.0f;
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) of[acc_row(r, lane) * 36 + i] = acc[h][r];
-                    __builtin_amdgcn_wave_barrier();
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int c = lane + 64 * j, pp = c >> 3, part = c & 7, p = p0 + pp;
-                        if (p < P)
-                            *reinterpret_cast<float4 *>(out_f32 + (size_t)p * COUT + 32 * h + 4 * part) =
-                                *reinterpret_cast<const float4 *>(&of[pp * 36 + 4 * part]);
-                    }
-                }
+            for (int w = 0; w < 4; ++w) {
+                const float *rw = reinterpret_cast<const float *>(sO[w]);
+                t += rw[threadIdx.x] + rw[COUT + threadIdx.x];
             }
+            bsum[(size_t)blockIdx.x * COUT + threadIdx.x] = t;
         }
     }
 }
@@ -335,11 +338,27 @@ __device__ __forceinline__ float ordered_sum(const float *__restrict__ a, int co
     return s;
 }
 
-// dst[e] = sum_b src[b][e] over b in increasing order
-__global__ void reduce_partials(const float *__restrict__ src, int nb, int stride, int n, float *__restrict__ dst)
+// dst[e] = sum_b src[b][e], deterministic: the nb slices form kRedGroups
+// consecutive groups, each summed in increasing order by its own thread, and
+// the group sums are added in group order.  A block holds 256 / kRedGroups
+// outputs (consecutive e, so every slice is read coalesced).
+constexpr int kRedGroups = 8, kRedOutputs = 256 / kRedGroups;
+__global__ __launch_bounds__(256) void reduce_partials(const float *__restrict__ src, int nb, int stride, int n,
+                                                       float *__restrict__ dst)
 {
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x)
-        dst[e] = ordered_sum(src + e, nb, (size_t)stride);
+    __shared__ float part[kRedGroups][kRedOutputs];
+    const int lo = threadIdx.x % kRedOutputs, g = threadIdx.x / kRedOutputs;
+    const int e = blockIdx.x * kRedOutputs + lo;
+    const int per = (nb + kRedGroups - 1) / kRedGroups;
+    const int b0 = min(nb, g * per), b1 = min(nb, b0 + per);
+    part[g][lo] = e < n ? ordered_sum(src + (size_t)b0 * stride + e, b1 - b0, (size_t)stride) : 0.0f;
+    __syncthreads();
+    if (g == 0 && e < n) {
+        float t = 0.0f;
+#pragma unroll
+        for (int k = 0; k < kRedGroups; ++k) t += part[k][lo];
+        dst[e] = t;
+    }
 }
 
 // bias-gradient partials: per-channel sums of dZ over position slices.  The
@@ -576,25 +595,35 @@ hipError_t net_conv_forward(int layer, const uint16_t *in, const uint16_t *W, co
     const dim3 g(conv_blocks(P)), b(256);
     const int p = (int)P;
     if (layer == 0)
-        hipLaunchKernelGGL((conv_mfma<8, 2, 0, 64>), g, b, 0, s, in, W, bias, p, guard, nullptr, nullptr, out_bf16);
+        hipLaunchKernelGGL((conv_mfma<8, 2, 0, 64>), g, b, 0, s, in, W, bias, p, guard, nullptr, nullptr, out_bf16,
+                           nullptr);
     else if (layer < 5)
-        hipLaunchKernelGGL((conv_mfma<64, 2, 0, 64>), g, b, 0, s, in, W, bias, p, guard, nullptr, nullptr, out_bf16);
+        hipLaunchKernelGGL((conv_mfma<64, 2, 0, 64>), g, b, 0, s, in, W, bias, p, guard, nullptr, nullptr, out_bf16,
+                           nullptr);
     else
-        hipLaunchKernelGGL((conv_mfma<64, 1, 1, 2>), g, b, 0, s, in, W, bias, p, guard, nullptr, out_f32, nullptr);
+        hipLaunchKernelGGL((conv_mfma<64, 1, 1, 2>), g, b, 0, s, in, W, bias, p, guard, nullptr, out_f32, nullptr,
+                           nullptr);
     return hipGetLastError();
 }
 
 hipError_t net_conv_input_grad(int layer, const uint16_t *dZ, const uint16_t *Wg, int64_t P, const uint8_t *guard,
-                               const uint16_t *act_in, float *dprev_f32, uint16_t *dprev_bf16, hipStream_t s)
+                               const uint16_t *act_in, uint16_t *dprev_bf16, float *bsum, float *db_prev,
+                               hipStream_t s)
 {
-    const dim3 g(conv_blocks(P)), b(256);
+    const unsigned nb = conv_blocks(P);
+    const dim3 g(nb), b(256);
     const int p = (int)P;
     if (layer == 5)
-        hipLaunchKernelGGL((conv_mfma<8, 2, 2, 64>), g, b, 0, s, dZ, Wg, nullptr, p, guard, act_in, dprev_f32,
-                           dprev_bf16);
+        hipLaunchKernelGGL((conv_mfma<8, 2, 2, 64>), g, b, 0, s, dZ, Wg, nullptr, p, guard, act_in, nullptr,
+                           dprev_bf16, bsum);
     else
-        hipLaunchKernelGGL((conv_mfma<64, 2, 2, 64>), g, b, 0, s, dZ, Wg, nullptr, p, guard, act_in, dprev_f32,
-                           dprev_bf16);
+        hipLaunchKernelGGL((conv_mfma<64, 2, 2, 64>), g, b, 0, s, dZ, Wg, nullptr, p, guard, act_in, nullptr,
+                           dprev_bf16, bsum);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // the previous layer's bias gradient from the blocks' channel sums
+    hipLaunchKernelGGL(reduce_partials, dim3((kNetCout[layer - 1] + kRedOutputs - 1) / kRedOutputs), dim3(256), 0,
+                       s, bsum, (int)nb, 64, kNetCout[layer - 1], db_prev);
     return hipGetLastError();
 }
 
@@ -618,7 +647,8 @@ hipError_t net_weight_grad(int layer, const uint16_t *dZ, const uint16_t *X, int
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int n = kNetCout[layer] * 5 * kNetCin[layer];
-    hipLaunchKernelGGL(reduce_partials, dim3((n + 255) / 256), dim3(256), 0, s, partial, nb, stride, n, dW);
+    hipLaunchKernelGGL(reduce_partials, dim3((n + kRedOutputs - 1) / kRedOutputs), dim3(256), 0, s, partial, nb,
+                       stride, n, dW);
     return hipGetLastError();
 }
 
@@ -631,7 +661,8 @@ hipError_t net_bias_grad(int layer, const float *dZ, int64_t P, int nblocks, flo
     hipLaunchKernelGGL(db_partial, dim3(nb), dim3(256), 0, s, dZ, zs, (int)P, span, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(64), 0, s, partial, nb, zs, kNetCout[layer], db);
+    hipLaunchKernelGGL(reduce_partials, dim3((kNetCout[layer] + kRedOutputs - 1) / kRedOutputs), dim3(256), 0, s,
+                       partial, nb, zs, kNetCout[layer], db);
     return hipGetLastError();
 }
 

@@ -43,7 +43,7 @@ int64_t b_offset(int layer) { return w_offset(layer) + (int64_t)kNetCout[layer] 
 
 struct NLayout {
     size_t theta, wb[kNetLayers], wg[kNetLayers], dcols, dfield, cols, entries;
-    size_t x, act, out2, guard, dz8f, dz8b, daf, dab, partial, loss, pred, raw;
+    size_t x, act, out2, guard, dz8f, dz8b, dab, partial, loss, pred, raw;
     size_t total;
     int64_t P;
 };
@@ -69,7 +69,6 @@ NLayout nlayout(const tplbm_net_config &c)
     L.guard = al(P);
     L.dz8f = al(4 * 8 * P);
     L.dz8b = al(2 * 8 * P);
-    L.daf = al(4 * 64 * P);
     L.dab = al(2 * 64 * P);
     L.partial = al(sizeof(float) * (size_t)kSlices * kPartialStride);
     L.loss = al(sizeof(float) * kLossBlocks);
@@ -78,7 +77,7 @@ NLayout nlayout(const tplbm_net_config &c)
     size_t t = 4 * L.theta;
     for (int l = 0; l < kNetLayers; ++l) t += L.wb[l] + L.wg[l];
     t += L.dcols + 2 * L.dfield + L.cols + L.entries + L.x + 5 * L.act + 2 * L.out2 + L.guard + L.dz8f + L.dz8b +
-         2 * L.daf + 2 * L.dab + L.partial + L.loss + 2 * L.pred + L.raw;
+         2 * L.dab + L.partial + L.loss + 2 * L.pred + L.raw;
     L.total = t;
     return L;
 }
@@ -99,7 +98,7 @@ struct tplbm_net {
     uint16_t *x = nullptr, *act[kNetLayers] = {};  // act[0] = x
     float *out = nullptr, *tgt = nullptr;
     uint8_t *guard = nullptr;
-    float *dz8f = nullptr, *daf[2] = {};
+    float *dz8f = nullptr;
     uint16_t *dz8b = nullptr, *dab[2] = {};
     float *partial = nullptr, *loss = nullptr;
     double *pred_rho = nullptr, *pred_T = nullptr;
@@ -204,11 +203,14 @@ int loss_and_grad(tplbm_net *n, int64_t P, int64_t nodes, double *loss)
     int cur = 0;
     for (int l = kNetLayers - 1; l >= 0; --l) {
         NHIP(n, net_weight_grad(l, dzb, n->act[l], P, kSlices, n->partial, n->grad + w_offset(l), n->stream));
-        NHIP(n, net_bias_grad(l, dzf, P, kSlices, n->partial, n->grad + b_offset(l), n->stream));
+        // the output layer's bias gradient from its FP32 dZ; every other
+        // layer's comes with the input gradient that produces its dZ
+        if (l == kNetLayers - 1)
+            NHIP(n, net_bias_grad(l, dzf, P, kSlices, n->partial, n->grad + b_offset(l), n->stream));
         if (l == 0) break;
-        NHIP(n, net_conv_input_grad(l, dzb, n->wg[l], P, n->guard, n->act[l], n->daf[cur], n->dab[cur], n->stream));
+        NHIP(n, net_conv_input_grad(l, dzb, n->wg[l], P, n->guard, n->act[l], n->dab[cur], n->partial,
+                                    n->grad + b_offset(l - 1), n->stream));
         dzb = n->dab[cur];
-        dzf = n->daf[cur];
         cur ^= 1;
     }
     if (loss) {
@@ -352,7 +354,6 @@ int tplbm_net_create(const tplbm_net_config *c, void *dev_workspace, size_t byte
     n->guard = (uint8_t *)q; q += L.guard;
     n->dz8f = (float *)q; q += L.dz8f;
     n->dz8b = (uint16_t *)q; q += L.dz8b;
-    for (int k = 0; k < 2; ++k) { n->daf[k] = (float *)q; q += L.daf; }
     for (int k = 0; k < 2; ++k) { n->dab[k] = (uint16_t *)q; q += L.dab; }
     n->partial = (float *)q; q += L.partial;
     n->loss = (float *)q; q += L.loss;

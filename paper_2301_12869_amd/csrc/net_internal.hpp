@@ -38,8 +38,12 @@ hipError_t net_raw_out(const NetCol *cols, const NetEntry *entries, int n, const
                        hipStream_t s);
 hipError_t net_conv_forward(int layer, const uint16_t *in, const uint16_t *W, const float *bias, int64_t P,
                             const uint8_t *guard, uint16_t *out_bf16, float *out_f32, hipStream_t s);
+// input gradient of layer `layer` (masked by its input act_in) in BF16, and
+// the bias gradient of layer - 1 (its channel sums) into db_prev; bsum holds
+// the launch's per-block sums (1024 x 64 floats)
 hipError_t net_conv_input_grad(int layer, const uint16_t *dZ, const uint16_t *Wg, int64_t P, const uint8_t *guard,
-                               const uint16_t *act_in, float *dprev_f32, uint16_t *dprev_bf16, hipStream_t s);
+                               const uint16_t *act_in, uint16_t *dprev_bf16, float *bsum, float *db_prev,
+                               hipStream_t s);
 hipError_t net_weight_grad(int layer, const uint16_t *dZ, const uint16_t *X, int64_t P, int nblocks,
                            float *partial, float *dW, hipStream_t s);
 hipError_t net_bias_grad(int layer, const float *dZ, int64_t P, int nblocks, float *partial, float *db,
