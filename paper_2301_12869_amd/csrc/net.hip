@@ -12,7 +12,9 @@
 // Kernels:
 //   conv_mfma   out[p][o] = sum_{t,i} W[o][t][i] in[p + t - 2][i]  (+ bias
 //               and ReLU, or a mask by the layer input) -- forward layers
-//               and, with flipped transposed weights, the input gradient
+//               and, with flipped transposed weights, the input gradient,
+//               whose per-block channel sums give the previous layer's bias
+//               gradient
 //   dw_mfma     partial dW[o][t][i] = sum_p dZ[p][o] X[p + t - 2][i] over a
 //               slice of positions (operands staged transposed in LDS),
 //               reduced in a fixed order afterwards (deterministic)
