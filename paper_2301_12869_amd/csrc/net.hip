@@ -79,21 +79,18 @@ __global__ __launch_bounds__(256) void conv_mfma(const uint16_t *__restrict__ in
     __shared__ __attribute__((aligned(16))) uint16_t sW[COUT * RS];
     __shared__ __attribute__((aligned(16))) uint16_t sA[TP * AS];
     // per-wave transpose of a 32-position output tile (bf16 rows of COUT
-    // channels, or f32 rows of 32 channels), so that outputs leave with
-    // 16-byte stores of consecutive channels; guard flags of the tile
+    // channels), so that outputs leave with 16-byte stores of consecutive
+    // channels (after the last tile, the input gradient's channel sums);
+    // guard flags of the tile
     constexpr int OS = 64 + 8;
     __shared__ __attribute__((aligned(16))) uint16_t sO[4][32 * OS];
     __shared__ uint8_t sG[128];
-    for (int e = threadIdx.x; e < COUT * ROW / 4; e += 256) {
-        const int o = (4 * e) / ROW, k = (4 * e) % ROW;
-        *reinterpret_cast<uint2 *>(&sW[o * RS + k]) = *reinterpret_cast<const uint2 *>(W + 4 * (size_t)e);
-    }
-
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i = lane & 31, kq = lane >> 5;
     // positions tile * 128 - 2 .. tile * 128 + 129, clamped (both ends of the
     // batch are guard positions, zero)
     uint4 va[NA];
+    uint4 vm[MODE == 2 ? 4 : 1];  // MODE 2: the ReLU mask of this wave's 32 positions, 16 bytes a lane
     int vg = 1;
     float gsum[NTILES] = {};  // MODE 2: this lane's sum of g over its rows of every tile, in tile order
     auto fetch = [&](int tile) {
@@ -108,8 +105,33 @@ __global__ __launch_bounds__(256) void conv_mfma(const uint16_t *__restrict__ in
             va[j] = e < TP * AV ? *reinterpret_cast<const uint4 *>(in + (size_t)q * CIN + 8 * g)
                                 : make_uint4(0, 0, 0, 0);
         }
+        if constexpr (MODE == 2) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int c = lane + 64 * j, pp = c >> 3, part = c & 7;
+                const int p = min(tile * 128 + wave * 32 + pp, P - 1);
+                vm[j] = *reinterpret_cast<const uint4 *>(mask + (size_t)p * 64 + 8 * part);
+            }
+        }
     };
-    if (blockIdx.x * 128 < P) fetch(blockIdx.x);
+    if (blockIdx.x * 128 < P) fetch(blockIdx.x);  // in flight while the weights are staged
+    // the weights: every 16-byte load issued before the first LDS write
+    constexpr int WV = COUT * ROW / 8, NWV = (WV + 255) / 256;
+    static_assert(ROW % 8 == 0, "a 16-byte piece of weights lies in one row");
+    {
+        uint4 wv[NWV];
+#pragma unroll
+        for (int j = 0; j < NWV; ++j) {
+            const int e = threadIdx.x + 256 * j;
+            wv[j] = e < WV ? *reinterpret_cast<const uint4 *>(W + 8 * (size_t)e) : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < NWV; ++j) {
+            const int e = threadIdx.x + 256 * j;
+            if (e < WV) *reinterpret_cast<uint4 *>(&sW[((8 * e) / ROW) * RS + (8 * e) % ROW]) = wv[j];
+        }
+    }
+
     for (int tile = blockIdx.x; tile * 128 < P; tile += gridDim.x) {
         __syncthreads();  // the previous tile's products have read sA (and sW is staged)
 #pragma unroll
@@ -118,6 +140,15 @@ __global__ __launch_bounds__(256) void conv_mfma(const uint16_t *__restrict__ in
             if (e < TP * AV) *reinterpret_cast<uint4 *>(&sA[(e / AV) * AS + 8 * (e % AV)]) = va[j];
         }
         if (threadIdx.x < 128) sG[threadIdx.x] = (uint8_t)vg;
+        if constexpr (MODE == 2) {
+            // the tile's ReLU mask into this wave's transpose buffer (free since
+            // its previous epilogue), as rows of channels
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int c = lane + 64 * j, pp = c >> 3, part = c & 7;
+                *reinterpret_cast<uint4 *>(&sO[wave][pp * OS + 8 * part]) = vm[j];
+            }
+        }
         __syncthreads();
         if ((tile + (int)gridDim.x) * 128 < P) fetch(tile + gridDim.x);
         const int p0 = tile * 128 + wave * 32;
@@ -154,17 +185,6 @@ __global__ __launch_bounds__(256) void conv_mfma(const uint16_t *__restrict__ in
             // l, l + 64, ... (position piece / 8, channels 8 (piece % 8) ..)
             static_assert(COUT == 64, "the transposed epilogue assumes 64 output channels");
             uint16_t *ow = sO[wave];
-            if constexpr (MODE == 2) {
-                // the layer input (its ReLU mask) of the tile, as rows of channels
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int c = lane + 64 * j, pp = c >> 3, part = c & 7;
-                    const int p = min(p0 + pp, P - 1);
-                    *reinterpret_cast<uint4 *>(&ow[pp * OS + 8 * part]) =
-                        *reinterpret_cast<const uint4 *>(mask + (size_t)p * COUT + 8 * part);
-                }
-                __builtin_amdgcn_wave_barrier();
-            }
 #pragma unroll
             for (int nt = 0; nt < NTILES; ++nt) {
                 const int o = 32 * nt + i;
