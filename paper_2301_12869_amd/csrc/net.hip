@@ -252,7 +252,7 @@ __global__ __launch_bounds__(256) void dw_mfma(const uint16_t *__restrict__ dZ, 
     constexpr int NXL = (XV * (CH + 4) + 255) / 256;      // and X
     static_assert(ZS % 8 == 0 && CIN % 8 == 0, "16-byte groups of channels");
     __shared__ __attribute__((aligned(16))) uint16_t sZ[COUT][CH + 8];
-    __shared__ uint16_t sX[CIN][CH + 8];  // positions p0 - 2 .. p0 + CH + 1
+    __shared__ __attribute__((aligned(16))) uint16_t sX[CIN][CH + 8];  // positions p0 - 2 .. p0 + CH + 1
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i = lane & 31, kq = lane >> 5;
@@ -317,7 +317,40 @@ __global__ __launch_bounds__(256) void dw_mfma(const uint16_t *__restrict__ dZ, 
                 const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&sZ[o][pk]);
                 const int n = 32 * nt + i;
                 bf16x8 b = {};
-                if (n < NN) {
+                if constexpr (CIN % 32 == 0) {
+                    // the tile's 32 columns n lie in one tap t (the same for
+                    // the whole wave): two aligned 16-byte reads hold
+                    // positions pk .. pk + 15, from which the eight at pk + t
+                    // are taken by whole or half-dword shifts
+                    const int t = (32 * nt) / CIN, c = n % CIN;
+                    const uint4 w0 = *reinterpret_cast<const uint4 *>(&sX[c][pk]);
+                    const uint4 w1 = *reinterpret_cast<const uint4 *>(&sX[c][pk + 8]);
+                    const unsigned W[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+                    unsigned r[4];
+                    switch (t) {
+                    case 0:
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) r[q] = W[q];
+                        break;
+                    case 1:
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) r[q] = __builtin_amdgcn_alignbyte(W[q + 1], W[q], 2);
+                        break;
+                    case 2:
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) r[q] = W[q + 1];
+                        break;
+                    case 3:
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) r[q] = __builtin_amdgcn_alignbyte(W[q + 2], W[q + 1], 2);
+                        break;
+                    default:
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) r[q] = W[q + 2];
+                        break;
+                    }
+                    b = __builtin_bit_cast(bf16x8, make_uint4(r[0], r[1], r[2], r[3]));
+                } else if (n < NN) {
                     const int t = n / CIN, c = n % CIN;
                     // X[p + t - 2] for p = p0 + pk + j  ->  sX index pk + j + t
 #pragma unroll
