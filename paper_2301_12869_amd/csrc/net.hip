@@ -247,9 +247,13 @@ __global__ __launch_bounds__(256) void dw_mfma(const uint16_t *__restrict__ dZ, 
     constexpr int NT = (NN + 31) / 32;
     constexpr int TILES = MT * NT;
     constexpr int TPW = (TILES + 3) / 4;
-    constexpr int ZV = COUT / 8, XV = CIN / 8;            // 8-channel groups
-    constexpr int NZ = (ZV * CH + 255) / 256;             // 16-byte loads per thread and chunk: dZ
-    constexpr int NXL = (XV * (CH + 4) + 255) / 256;      // and X
+    constexpr int ZV = COUT / 8, XV = CIN / 8;  // 8-channel groups
+    // staging items: four consecutive positions of one 8-channel group (four
+    // 16-byte loads), written as one 8-byte LDS store per channel; the
+    // position quads vary fastest across lanes, so that a store instruction
+    // covers consecutive positions of a channel row (no bank conflicts)
+    constexpr int ZQ = CH / 4, XQ = (CH + 4) / 4;  // position quads: dZ, X (with the halo)
+    constexpr int ZI = ZV * ZQ, XI = XV * XQ, NI = (ZI + XI + 255) / 256;
     static_assert(ZS % 8 == 0 && CIN % 8 == 0, "16-byte groups of channels");
     __shared__ __attribute__((aligned(16))) uint16_t sZ[COUT][CH + 8];
     __shared__ __attribute__((aligned(16))) uint16_t sX[CIN][CH + 8];  // positions p0 - 2 .. p0 + CH + 1
@@ -263,45 +267,52 @@ __global__ __launch_bounds__(256) void dw_mfma(const uint16_t *__restrict__ dZ, 
         for (int r = 0; r < 16; ++r) acc[k][r] = 0.0f;
 
     const int pbeg = blockIdx.x * span, pend = min(P, pbeg + span);
-    uint4 vz[NZ], vx[NXL];
+    uint4 vv[NI][4];
     auto fetch = [&](int p0) {
 #pragma unroll
-        for (int j = 0; j < NZ; ++j) {
-            const int e = threadIdx.x + 256 * j;
-            const int g = e % ZV, pp = e / ZV, p = p0 + pp;
-            const bool ok = e < ZV * CH && 8 * g < ZS && p < pend;
-            vz[j] = ok ? *reinterpret_cast<const uint4 *>(dZ + (size_t)p * ZS + 8 * g) : make_uint4(0, 0, 0, 0);
-        }
+        for (int j = 0; j < NI; ++j) {
+            const int u = threadIdx.x + 256 * j;
+            if (u < ZI) {
+                const int g = u / ZQ, pq = 4 * (u % ZQ);
 #pragma unroll
-        for (int j = 0; j < NXL; ++j) {
-            const int e = threadIdx.x + 256 * j;
-            const int g = e % XV, pp = e / XV;
-            int p = p0 - 2 + pp;
-            p = p < 0 ? 0 : (p >= P ? P - 1 : p);
-            vx[j] = e < XV * (CH + 4) ? *reinterpret_cast<const uint4 *>(X + (size_t)p * CIN + 8 * g)
-                                      : make_uint4(0, 0, 0, 0);
+                for (int q = 0; q < 4; ++q) {
+                    const int p = p0 + pq + q;
+                    vv[j][q] = 8 * g < ZS && p < pend
+                                   ? *reinterpret_cast<const uint4 *>(dZ + (size_t)p * ZS + 8 * g)
+                                   : make_uint4(0, 0, 0, 0);
+                }
+            } else if (u < ZI + XI) {
+                const int g = (u - ZI) / XQ, pq = 4 * ((u - ZI) % XQ);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    int p = p0 - 2 + pq + q;
+                    p = p < 0 ? 0 : (p >= P ? P - 1 : p);
+                    vv[j][q] = *reinterpret_cast<const uint4 *>(X + (size_t)p * CIN + 8 * g);
+                }
+            }
         }
     };
-    auto unpack = [](uint16_t *col, int stride, const uint4 &v) {
-        const unsigned w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            col[(2 * m) * stride] = (uint16_t)(w[m] & 0xffffu);
-            col[(2 * m + 1) * stride] = (uint16_t)(w[m] >> 16);
-        }
+    // channel m of four position vectors -> the row's four consecutive values
+    auto quad = [](const uint4 *v, int m) {
+        auto word = [&](const uint4 &x) {
+            const unsigned d = (m >> 1) == 0 ? x.x : ((m >> 1) == 1 ? x.y : ((m >> 1) == 2 ? x.z : x.w));
+            return (m & 1) ? d >> 16 : d & 0xffffu;
+        };
+        return make_uint2(word(v[0]) | (word(v[1]) << 16), word(v[2]) | (word(v[3]) << 16));
     };
     if (pbeg < pend) fetch(pbeg);
     for (int p0 = pbeg; p0 < pend; p0 += CH) {
         __syncthreads();  // the previous chunk's products have read the LDS tiles
 #pragma unroll
-        for (int j = 0; j < NZ; ++j) {
-            const int e = threadIdx.x + 256 * j;
-            if (e < ZV * CH) unpack(&sZ[8 * (e % ZV)][e / ZV], CH + 8, vz[j]);
-        }
+        for (int j = 0; j < NI; ++j) {
+            const int u = threadIdx.x + 256 * j;
+            uint16_t *row = nullptr;
+            if (u < ZI) row = &sZ[8 * (u / ZQ)][4 * (u % ZQ)];
+            else if (u < ZI + XI) row = &sX[8 * ((u - ZI) / XQ)][4 * ((u - ZI) % XQ)];
+            if (row) {
 #pragma unroll
-        for (int j = 0; j < NXL; ++j) {
-            const int e = threadIdx.x + 256 * j;
-            if (e < XV * (CH + 4)) unpack(&sX[8 * (e % XV)][e / XV], CH + 8, vx[j]);
+                for (int m = 0; m < 8; ++m) *reinterpret_cast<uint2 *>(row + m * (CH + 8)) = quad(vv[j], m);
+            }
         }
         __syncthreads();
         if (p0 + CH < pend) fetch(p0 + CH);
