@@ -158,6 +158,39 @@ def test_gradient_matches_the_bf16_reference(T, consts):
     net.close()
 
 
+def test_large_batch_gradient_equals_the_mean_of_its_columns(T, consts):
+    """A 64 x 2048-position batch gives the weight-gradient kernel slices of
+    at least 512 positions, which it stages in 128-position chunks; its
+    gradient must equal the mean of its columns' gradients taken one column
+    at a time (64-position chunks, the path the reference test pins), up to
+    the order of the FP32 sums.  Equal heights put the per-column loss scale
+    a power of two (64) from the batch's, so dZ rounds to BF16 alike."""
+    nc, h = 64, 2048
+    cols = [(h, 1 + k % 2, 0.7 + 0.2 * k / nc, 10 ** (-6 + 2 * k / nc), 0.8 + k / nc, h / 2) for k in range(nc)]
+    theta = _theta(11)
+    tg, rho, TT = _dataset(consts, cols, 12)
+    net = _net(T, consts, max_cols=nc, max_nodes=nc * h, dataset_cols=nc, dataset_nodes=nc * h)
+    net.set_params(theta)
+    net.set_dataset(cols, rho, TT)
+    L, g = net.loss_grad(np.arange(nc))
+    acc, Ls = np.zeros(g.size), 0.0
+    for k in range(nc):
+        Lk, gk = net.loss_grad([k])
+        acc += gk.astype(np.float64)
+        Ls += Lk
+    acc /= nc
+    Ls /= nc
+    _log(f"batch loss {L:.10e}, mean of columns {Ls:.10e}")
+    assert L == pytest.approx(Ls, rel=1e-6)
+    Ws, bs = N.unflatten(np.arange(theta.size))
+    for l in range(N.N_LAYERS):
+        for name, sel in (("W", Ws[l].ravel()), ("b", bs[l].ravel())):
+            e = _rel(g[sel].astype(np.float64), acc[sel])
+            _log(f"layer {l} d{name}: batch vs mean of columns {e:.2e}")
+            assert e < 1e-4, (l, name)
+    net.close()
+
+
 def test_adam_step_matches_the_reference_and_training_lowers_the_loss(T, consts):
     cols = [(96, 1, 0.8, 1e-5, 1.3, 40.0), (200, 2, 0.7, 5e-5, 1.1, 60.5), (57, 1, 0.9, 2e-6, 1.5, 30.0)]
     theta = _theta(9)
