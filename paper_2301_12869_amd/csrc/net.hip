@@ -498,12 +498,16 @@ __global__ void adam(float *__restrict__ theta, const float *__restrict__ grad, 
     }
 }
 
-// BF16 copies of one layer's weights: forward Wb[o][t][i] with rows padded
-// to cout_pad, and input-gradient weights Wg[i][t][o] = W[o][4 - t][i] with
-// o padded to cin_g.
-__global__ void prep_weights(const float *__restrict__ Wf, int cout, int cin, int cout_pad, int cin_g,
-                             uint16_t *__restrict__ Wb, uint16_t *__restrict__ Wg)
+// BF16 copies of every layer's weights (layer blockIdx.y): forward
+// Wb[o][t][i] with rows padded to cout_pad, and input-gradient weights
+// Wg[i][t][o] = W[o][4 - t][i] with o padded to cin_g (not for layer 0).
+__global__ void prep_weights(NetWeightSet w)
 {
+    const int l = blockIdx.y;
+    const float *__restrict__ Wf = w.Wf[l];
+    uint16_t *__restrict__ Wb = w.Wb[l];
+    uint16_t *__restrict__ Wg = w.Wg[l];
+    const int cout = kNetCout[l], cin = kNetCin[l], cout_pad = kNetCoutPad[l], cin_g = kNetGradCin[l];
     const int nf = cout_pad * 5 * cin;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nf; e += gridDim.x * blockDim.x) {
         const int o = e / (5 * cin), rem = e % (5 * cin);
@@ -754,10 +758,9 @@ hipError_t net_adam(float *theta, const float *grad, float *m, float *v, int n, 
     return hipGetLastError();
 }
 
-hipError_t net_prep_weights(const float *Wf, int layer, uint16_t *Wb, uint16_t *Wg, hipStream_t s)
+hipError_t net_prep_weights(const NetWeightSet &w, hipStream_t s)
 {
-    hipLaunchKernelGGL(prep_weights, dim3(80), dim3(256), 0, s, Wf, kNetCout[layer], kNetCin[layer],
-                       kNetCoutPad[layer], kNetGradCin[layer], Wb, Wg);
+    hipLaunchKernelGGL(prep_weights, dim3(80, kNetLayers), dim3(256), 0, s, w);
     return hipGetLastError();
 }
 

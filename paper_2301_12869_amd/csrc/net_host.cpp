@@ -226,8 +226,13 @@ int loss_and_grad(tplbm_net *n, int64_t P, int64_t nodes, double *loss)
 
 int prep_weights(tplbm_net *n)
 {
-    for (int l = 0; l < kNetLayers; ++l)
-        NHIP(n, net_prep_weights(n->theta + w_offset(l), l, n->wb[l], l ? n->wg[l] : nullptr, n->stream));
+    NetWeightSet w;
+    for (int l = 0; l < kNetLayers; ++l) {
+        w.Wf[l] = n->theta + w_offset(l);
+        w.Wb[l] = n->wb[l];
+        w.Wg[l] = l ? n->wg[l] : nullptr;
+    }
+    NHIP(n, net_prep_weights(w, n->stream));
     return TPLBM_OK;
 }
 

@@ -52,7 +52,13 @@ hipError_t net_loss(const float *out, const float *tgt, const uint8_t *guard, in
                     uint16_t *dZb, float *partial, int nblocks, hipStream_t s);
 hipError_t net_adam(float *theta, const float *grad, float *m, float *v, int n, float lr, float b1, float b2,
                     float eps, float c1, float c2, hipStream_t s);
-hipError_t net_prep_weights(const float *Wf, int layer, uint16_t *Wb, uint16_t *Wg, hipStream_t s);
+// the FP32 weights of every layer and their BF16 copies (Wg[0] unused)
+struct NetWeightSet {
+    const float *Wf[kNetLayers];
+    uint16_t *Wb[kNetLayers];
+    uint16_t *Wg[kNetLayers];
+};
+hipError_t net_prep_weights(const NetWeightSet &w, hipStream_t s);
 hipError_t net_mfma_probe(const uint16_t *a, const uint16_t *b, float *d, hipStream_t s);
 
 }  // namespace tplbm
