@@ -60,8 +60,8 @@ __device__ __forceinline__ int acc_row(int r, int lane) { return 8 * (r >> 2) + 
 // tile's 132 input positions (2 on each side for the taps) are staged in LDS
 // too, read with 16-byte loads one tile ahead, so each activation is read
 // from memory once per tile rather than once per tap.
-template <int CIN, int NTILES, int MODE, int NOUT>
-__global__ __launch_bounds__(256) void conv_mfma(const uint16_t *__restrict__ in, const uint16_t *__restrict__ W,
+template <int CIN, int NTILES, int MODE, int NOUT, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void conv_mfma(const uint16_t *__restrict__ in, const uint16_t *__restrict__ W,
                                                  const float *__restrict__ bias, int P,
                                                  const uint8_t *__restrict__ guard,
                                                  const uint16_t *__restrict__ mask, float *__restrict__ out_f32,
@@ -71,87 +71,92 @@ __global__ __launch_bounds__(256) void conv_mfma(const uint16_t *__restrict__ in
     constexpr int ROW = 5 * CIN;       // weights of one output channel
     constexpr int RS = ROW + 8;        // padded LDS row
     constexpr int KS = (ROW + 15) / 16;  // K steps
-    constexpr int TP = 128 + 4;        // staged positions of a tile
+    constexpr int NTHR = 64 * WAVES;   // threads of a block
+    constexpr int TPOS = 32 * WAVES;   // positions of a tile (32 a wave)
+    constexpr int TP = TPOS + 4;       // staged positions of a tile
     constexpr int AS = CIN + 8;        // padded LDS row of a staged position
     constexpr int AV = CIN / 8;        // 16-byte groups of a position
-    constexpr int NA = (TP * AV + 255) / 256;  // 16-byte loads per thread and tile
+    constexpr int NA = (TP * AV + NTHR - 1) / NTHR;  // 16-byte loads per thread and tile
     static_assert(CIN % 8 == 0, "a lane's eight k lie in one tap");
-    __shared__ __attribute__((aligned(16))) uint16_t sW[COUT * RS];
-    __shared__ __attribute__((aligned(16))) uint16_t sA[TP * AS];
-    // per-wave transpose of a 32-position output tile (bf16 rows of COUT
-    // channels), so that outputs leave with 16-byte stores of consecutive
-    // channels (after the last tile, the input gradient's channel sums);
-    // guard flags of the tile
+    // The staged inputs share their LDS with the per-wave transposes of the
+    // output tiles (bf16 rows of COUT channels, so that outputs leave with
+    // 16-byte stores of consecutive channels; after the last tile, the input
+    // gradient's channel sums), which take over once every wave's products
+    // have read the inputs.  Guard flags of the tile.
     constexpr int OS = 64 + 8;
-    __shared__ __attribute__((aligned(16))) uint16_t sO[4][32 * OS];
-    __shared__ uint8_t sG[128];
+    constexpr int SAO = TP * AS > WAVES * 32 * OS ? TP * AS : WAVES * 32 * OS;
+    __shared__ __attribute__((aligned(16))) uint16_t sW[COUT * RS];
+    __shared__ __attribute__((aligned(16))) uint16_t sA[SAO];
+    __shared__ uint8_t sG[TPOS];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i = lane & 31, kq = lane >> 5;
-    // positions tile * 128 - 2 .. tile * 128 + 129, clamped (both ends of the
-    // batch are guard positions, zero)
+    uint16_t *const ow = sA + wave * 32 * OS;  // this wave's output transpose
+    // positions tile * TPOS - 2 .. tile * TPOS + TPOS + 1, clamped (both ends
+    // of the batch are guard positions, zero)
     uint4 va[NA];
-    uint4 vm[MODE == 2 ? 4 : 1];  // MODE 2: the ReLU mask of this wave's 32 positions, 16 bytes a lane
+    uint4 vm0, vm1, vm2, vm3;  // MODE 2: the ReLU mask of this wave's 32 positions, 16 bytes a lane
     int vg = 1;
     float gsum[NTILES] = {};  // MODE 2: this lane's sum of g over its rows of every tile, in tile order
-    auto fetch = [&](int tile) {
-        const int pg = tile * 128 + (int)threadIdx.x;
-        vg = threadIdx.x < 128 && pg < P ? guard[pg] : 1;
+    auto fetch = [&](int tile) __attribute__((always_inline)) {
+        const int pg = tile * TPOS + (int)threadIdx.x;
+        vg = threadIdx.x < TPOS && pg < P ? guard[pg] : 1;
 #pragma unroll
         for (int j = 0; j < NA; ++j) {
-            const int e = threadIdx.x + 256 * j;
+            const int e = threadIdx.x + NTHR * j;
             const int g = e % AV, pp = e / AV;
-            int q = tile * 128 - 2 + pp;
+            int q = tile * TPOS - 2 + pp;
             q = q < 0 ? 0 : (q >= P ? P - 1 : q);
             va[j] = e < TP * AV ? *reinterpret_cast<const uint4 *>(in + (size_t)q * CIN + 8 * g)
                                 : make_uint4(0, 0, 0, 0);
         }
+    };
+    // MODE 2: the ReLU mask of this wave's 32 positions of a tile, fetched
+    // when the previous tile's epilogue has consumed the last one
+    auto fetch_mask = [&](int tile) __attribute__((always_inline)) {
         if constexpr (MODE == 2) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            auto ld = [&](int j) {
                 const int c = lane + 64 * j, pp = c >> 3, part = c & 7;
-                const int p = min(tile * 128 + wave * 32 + pp, P - 1);
-                vm[j] = *reinterpret_cast<const uint4 *>(mask + (size_t)p * 64 + 8 * part);
-            }
+                const int p = min(tile * TPOS + wave * 32 + pp, P - 1);
+                return *reinterpret_cast<const uint4 *>(mask + (size_t)p * 64 + 8 * part);
+            };
+            vm0 = ld(0);
+            vm1 = ld(1);
+            vm2 = ld(2);
+            vm3 = ld(3);
         }
     };
-    if (blockIdx.x * 128 < P) fetch(blockIdx.x);  // in flight while the weights are staged
+    if (blockIdx.x * TPOS < P) {  // in flight while the weights are staged
+        fetch(blockIdx.x);
+        fetch_mask(blockIdx.x);
+    }
     // the weights: every 16-byte load issued before the first LDS write
-    constexpr int WV = COUT * ROW / 8, NWV = (WV + 255) / 256;
+    constexpr int WV = COUT * ROW / 8, NWV = (WV + NTHR - 1) / NTHR;
     static_assert(ROW % 8 == 0, "a 16-byte piece of weights lies in one row");
     {
         uint4 wv[NWV];
 #pragma unroll
         for (int j = 0; j < NWV; ++j) {
-            const int e = threadIdx.x + 256 * j;
+            const int e = threadIdx.x + NTHR * j;
             wv[j] = e < WV ? *reinterpret_cast<const uint4 *>(W + 8 * (size_t)e) : make_uint4(0, 0, 0, 0);
         }
 #pragma unroll
         for (int j = 0; j < NWV; ++j) {
-            const int e = threadIdx.x + 256 * j;
+            const int e = threadIdx.x + NTHR * j;
             if (e < WV) *reinterpret_cast<uint4 *>(&sW[((8 * e) / ROW) * RS + (8 * e) % ROW]) = wv[j];
         }
     }
 
-    for (int tile = blockIdx.x; tile * 128 < P; tile += gridDim.x) {
-        __syncthreads();  // the previous tile's products have read sA (and sW is staged)
+    for (int tile = blockIdx.x; tile * TPOS < P; tile += gridDim.x) {
+        __syncthreads();  // the previous tile's epilogues are done with sA (and sW is staged)
 #pragma unroll
         for (int j = 0; j < NA; ++j) {
-            const int e = threadIdx.x + 256 * j;
+            const int e = threadIdx.x + NTHR * j;
             if (e < TP * AV) *reinterpret_cast<uint4 *>(&sA[(e / AV) * AS + 8 * (e % AV)]) = va[j];
         }
-        if (threadIdx.x < 128) sG[threadIdx.x] = (uint8_t)vg;
-        if constexpr (MODE == 2) {
-            // the tile's ReLU mask into this wave's transpose buffer (free since
-            // its previous epilogue), as rows of channels
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int c = lane + 64 * j, pp = c >> 3, part = c & 7;
-                *reinterpret_cast<uint4 *>(&sO[wave][pp * OS + 8 * part]) = vm[j];
-            }
-        }
+        if (threadIdx.x < TPOS) sG[threadIdx.x] = (uint8_t)vg;
         __syncthreads();
-        if ((tile + (int)gridDim.x) * 128 < P) fetch(tile + gridDim.x);
-        const int p0 = tile * 128 + wave * 32;
+        if ((tile + (int)gridDim.x) * TPOS < P) fetch(tile + gridDim.x);
+        const int p0 = tile * TPOS + wave * 32;
         f32x16 acc[NTILES];
 #pragma unroll
         for (int nt = 0; nt < NTILES; ++nt)
@@ -173,18 +178,31 @@ __global__ __launch_bounds__(256) void conv_mfma(const uint16_t *__restrict__ in
                 acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[nt], 0, 0, 0);
             }
         }
-        if (p0 >= P) continue;
         if constexpr (MODE == 1) {
+            if (p0 >= P) continue;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int pr = acc_row(r, lane), p = p0 + pr;
                 if (p < P && i < NOUT) out_f32[(size_t)p * NOUT + i] = sG[wave * 32 + pr] ? 0.0f : acc[0][r] + bias[i];
             }
         } else {
+            __syncthreads();  // every wave's products have read the staged inputs
+            if (p0 >= P) continue;
             // 16-byte pieces of the wave's 32 x COUT tile: lane l takes pieces
             // l, l + 64, ... (position piece / 8, channels 8 (piece % 8) ..)
             static_assert(COUT == 64, "the transposed epilogue assumes 64 output channels");
-            uint16_t *ow = sO[wave];
+            if constexpr (MODE == 2) {
+                // the tile's ReLU mask, as rows of channels
+                auto st = [&](int j, const uint4 &v) {
+                    const int c = lane + 64 * j, pp = c >> 3, part = c & 7;
+                    *reinterpret_cast<uint4 *>(&ow[pp * OS + 8 * part]) = v;
+                };
+                st(0, vm0);
+                st(1, vm1);
+                st(2, vm2);
+                st(3, vm3);
+                __builtin_amdgcn_wave_barrier();
+            }
 #pragma unroll
             for (int nt = 0; nt < NTILES; ++nt) {
                 const int o = 32 * nt + i;
@@ -207,21 +225,23 @@ __global__ __launch_bounds__(256) void conv_mfma(const uint16_t *__restrict__ in
                     *reinterpret_cast<uint4 *>(out_bf16 + (size_t)p * COUT + 8 * part) =
                         *reinterpret_cast<const uint4 *>(&ow[pp * OS + 8 * part]);
             }
+            if ((tile + (int)gridDim.x) * TPOS < P) fetch_mask(tile + gridDim.x);
         }
     }
     if constexpr (MODE == 2) {
         // the block's channel sums: lanes of both halves of each wave, then
-        // the waves, added in a fixed order (each wave's transpose buffer,
-        // free after the last tile, holds its two halves' sums)
-        float *red = reinterpret_cast<float *>(sO[wave]);
+        // the waves, added in a fixed order (each wave's transpose buffer
+        // holds its two halves' sums)
+        __syncthreads();
+        float *red = reinterpret_cast<float *>(ow);
 #pragma unroll
         for (int nt = 0; nt < NTILES; ++nt) red[kq * COUT + 32 * nt + i] = gsum[nt];
         __syncthreads();
         if (threadIdx.x < COUT) {
             float t = 0.0f;
 #pragma unroll
-            for (int w = 0; w < 4; ++w) {
-                const float *rw = reinterpret_cast<const float *>(sO[w]);
+            for (int w = 0; w < WAVES; ++w) {
+                const float *rw = reinterpret_cast<const float *>(sA + w * 32 * OS);
                 t += rw[threadIdx.x] + rw[COUT + threadIdx.x];
             }
             bsum[(size_t)blockIdx.x * COUT + threadIdx.x] = t;
@@ -620,11 +640,13 @@ __global__ void mfma_probe(const uint16_t *__restrict__ a, const uint16_t *__res
     for (int r = 0; r < 16; ++r) d[lane * 16 + r] = acc[r];
 }
 
-// persistent convolution grid: one block per 128-position tile, at most 1024
+// persistent convolution grid: blocks of kConvWaves waves on tiles of
+// 32 kConvWaves positions, at most two blocks per compute unit
+constexpr int kConvWaves = 8, kConvTile = 32 * kConvWaves, kConvBlocks = 512;
 unsigned conv_blocks(int64_t P)
 {
-    const int64_t t = (P + 127) / 128;
-    return (unsigned)(t < 1024 ? t : 1024);
+    const int64_t t = (P + kConvTile - 1) / kConvTile;
+    return (unsigned)(t < kConvBlocks ? t : kConvBlocks);
 }
 
 // slice length (a multiple of 64 positions) and slice count for nblocks
@@ -662,16 +684,16 @@ hipError_t net_raw_out(const NetCol *cols, const NetEntry *entries, int n, const
 hipError_t net_conv_forward(int layer, const uint16_t *in, const uint16_t *W, const float *bias, int64_t P,
                             const uint8_t *guard, uint16_t *out_bf16, float *out_f32, hipStream_t s)
 {
-    const dim3 g(conv_blocks(P)), b(256);
+    const dim3 g(conv_blocks(P)), b(64 * kConvWaves);
     const int p = (int)P;
     if (layer == 0)
-        hipLaunchKernelGGL((conv_mfma<8, 2, 0, 64>), g, b, 0, s, in, W, bias, p, guard, nullptr, nullptr, out_bf16,
+        hipLaunchKernelGGL((conv_mfma<8, 2, 0, 64, kConvWaves>), g, b, 0, s, in, W, bias, p, guard, nullptr, nullptr, out_bf16,
                            nullptr);
     else if (layer < 5)
-        hipLaunchKernelGGL((conv_mfma<64, 2, 0, 64>), g, b, 0, s, in, W, bias, p, guard, nullptr, nullptr, out_bf16,
+        hipLaunchKernelGGL((conv_mfma<64, 2, 0, 64, kConvWaves>), g, b, 0, s, in, W, bias, p, guard, nullptr, nullptr, out_bf16,
                            nullptr);
     else
-        hipLaunchKernelGGL((conv_mfma<64, 1, 1, 2>), g, b, 0, s, in, W, bias, p, guard, nullptr, out_f32, nullptr,
+        hipLaunchKernelGGL((conv_mfma<64, 1, 1, 2, kConvWaves>), g, b, 0, s, in, W, bias, p, guard, nullptr, out_f32, nullptr,
                            nullptr);
     return hipGetLastError();
 }
@@ -681,13 +703,13 @@ hipError_t net_conv_input_grad(int layer, const uint16_t *dZ, const uint16_t *Wg
                                hipStream_t s)
 {
     const unsigned nb = conv_blocks(P);
-    const dim3 g(nb), b(256);
+    const dim3 g(nb), b(64 * kConvWaves);
     const int p = (int)P;
     if (layer == 5)
-        hipLaunchKernelGGL((conv_mfma<8, 2, 2, 64>), g, b, 0, s, dZ, Wg, nullptr, p, guard, act_in, nullptr,
+        hipLaunchKernelGGL((conv_mfma<8, 2, 2, 64, kConvWaves>), g, b, 0, s, dZ, Wg, nullptr, p, guard, act_in, nullptr,
                            dprev_bf16, bsum);
     else
-        hipLaunchKernelGGL((conv_mfma<64, 2, 2, 64>), g, b, 0, s, dZ, Wg, nullptr, p, guard, act_in, nullptr,
+        hipLaunchKernelGGL((conv_mfma<64, 2, 2, 64, kConvWaves>), g, b, 0, s, dZ, Wg, nullptr, p, guard, act_in, nullptr,
                            dprev_bf16, bsum);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
