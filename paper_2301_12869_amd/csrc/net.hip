@@ -257,8 +257,8 @@ __global__ __launch_bounds__(64 * WAVES) void conv_mfma(const uint16_t *__restri
 // eight consecutive positions are adjacent; the chunk is read with 16-byte
 // loads (eight channels of a position) one chunk ahead, into registers,
 // while the matrix cores work on the current one.
-template <int CIN, int COUT, int ZS, int CH>
-__global__ __launch_bounds__(256) void dw_mfma(const uint16_t *__restrict__ dZ, const uint16_t *__restrict__ X,
+template <int CIN, int COUT, int ZS, int CH, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void dw_mfma(const uint16_t *__restrict__ dZ, const uint16_t *__restrict__ X,
                                                int P, int span, float *__restrict__ partial)
 {
     static_assert(CH % 64 == 0, "chunks of whole 16-position steps for both half-waves");
@@ -266,14 +266,15 @@ __global__ __launch_bounds__(256) void dw_mfma(const uint16_t *__restrict__ dZ, 
     constexpr int NN = 5 * CIN;
     constexpr int NT = (NN + 31) / 32;
     constexpr int TILES = MT * NT;
-    constexpr int TPW = (TILES + 3) / 4;
+    constexpr int NTHR = 64 * WAVES;
+    constexpr int TPW = (TILES + WAVES - 1) / WAVES;  // output tiles of a wave
     constexpr int ZV = COUT / 8, XV = CIN / 8;  // 8-channel groups
     // staging items: four consecutive positions of one 8-channel group (four
     // 16-byte loads), written as one 8-byte LDS store per channel; the
     // position quads vary fastest across lanes, so that a store instruction
     // covers consecutive positions of a channel row (no bank conflicts)
     constexpr int ZQ = CH / 4, XQ = (CH + 4) / 4;  // position quads: dZ, X (with the halo)
-    constexpr int ZI = ZV * ZQ, XI = XV * XQ, NI = (ZI + XI + 255) / 256;
+    constexpr int ZI = ZV * ZQ, XI = XV * XQ, NI = (ZI + XI + NTHR - 1) / NTHR;
     static_assert(ZS % 8 == 0 && CIN % 8 == 0, "16-byte groups of channels");
     __shared__ __attribute__((aligned(16))) uint16_t sZ[COUT][CH + 8];
     __shared__ __attribute__((aligned(16))) uint16_t sX[CIN][CH + 8];  // positions p0 - 2 .. p0 + CH + 1
@@ -291,7 +292,7 @@ __global__ __launch_bounds__(256) void dw_mfma(const uint16_t *__restrict__ dZ, 
     auto fetch = [&](int p0) {
 #pragma unroll
         for (int j = 0; j < NI; ++j) {
-            const int u = threadIdx.x + 256 * j;
+            const int u = threadIdx.x + NTHR * j;
             if (u < ZI) {
                 const int g = u / ZQ, pq = 4 * (u % ZQ);
 #pragma unroll
@@ -325,7 +326,7 @@ __global__ __launch_bounds__(256) void dw_mfma(const uint16_t *__restrict__ dZ, 
         __syncthreads();  // the previous chunk's products have read the LDS tiles
 #pragma unroll
         for (int j = 0; j < NI; ++j) {
-            const int u = threadIdx.x + 256 * j;
+            const int u = threadIdx.x + NTHR * j;
             uint16_t *row = nullptr;
             if (u < ZI) row = &sZ[8 * (u / ZQ)][4 * (u % ZQ)];
             else if (u < ZI + XI) row = &sX[8 * ((u - ZI) / XQ)][4 * ((u - ZI) % XQ)];
@@ -341,7 +342,7 @@ __global__ __launch_bounds__(256) void dw_mfma(const uint16_t *__restrict__ dZ, 
             const int pk = k16 + 8 * kq;
 #pragma unroll
             for (int k = 0; k < TPW; ++k) {
-                const int tile = wave + 4 * k;
+                const int tile = wave + WAVES * k;
                 if (tile >= TILES) break;
                 const int mt = tile % MT, nt = tile / MT;
                 const int o = 32 * mt + i;
@@ -394,7 +395,7 @@ __global__ __launch_bounds__(256) void dw_mfma(const uint16_t *__restrict__ dZ, 
     float *dst = partial + (size_t)blockIdx.x * COUT * NN;
 #pragma unroll
     for (int k = 0; k < TPW; ++k) {
-        const int tile = wave + 4 * k;
+        const int tile = wave + WAVES * k;
         if (tile >= TILES) break;
         const int mt = tile % MT, nt = tile / MT;
         const int n = 32 * nt + i;
@@ -649,6 +650,10 @@ unsigned conv_blocks(int64_t P)
     return (unsigned)(t < kConvBlocks ? t : kConvBlocks);
 }
 
+// waves of a weight-gradient block (they share the staged chunks and split
+// the output tiles)
+constexpr int kDwWaves = 8;
+
 // slice length (a multiple of 64 positions) and slice count for nblocks
 void slices(int64_t P, int nblocks, int *span, int *nb)
 {
@@ -732,16 +737,16 @@ hipError_t net_weight_grad(int layer, const uint16_t *dZ, const uint16_t *X, int
     int stride;
     if (layer == 0) {
         stride = 64 * 5 * 8;
-        auto k = big ? dw_mfma<8, 64, 64, 128> : dw_mfma<8, 64, 64, 64>;
-        hipLaunchKernelGGL(k, dim3(nb), dim3(256), 0, s, dZ, X, p, span, partial);
+        auto k = big ? dw_mfma<8, 64, 64, 128, kDwWaves> : dw_mfma<8, 64, 64, 64, kDwWaves>;
+        hipLaunchKernelGGL(k, dim3(nb), dim3(64 * kDwWaves), 0, s, dZ, X, p, span, partial);
     } else if (layer < 5) {
         stride = 64 * 5 * 64;
-        auto k = big ? dw_mfma<64, 64, 64, 128> : dw_mfma<64, 64, 64, 64>;
-        hipLaunchKernelGGL(k, dim3(nb), dim3(256), 0, s, dZ, X, p, span, partial);
+        auto k = big ? dw_mfma<64, 64, 64, 128, kDwWaves> : dw_mfma<64, 64, 64, 64, kDwWaves>;
+        hipLaunchKernelGGL(k, dim3(nb), dim3(64 * kDwWaves), 0, s, dZ, X, p, span, partial);
     } else {
         stride = 32 * 5 * 64;  // rows 2..31 are zero padding
-        auto k = big ? dw_mfma<64, 32, 8, 128> : dw_mfma<64, 32, 8, 64>;
-        hipLaunchKernelGGL(k, dim3(nb), dim3(256), 0, s, dZ, X, p, span, partial);
+        auto k = big ? dw_mfma<64, 32, 8, 128, kDwWaves> : dw_mfma<64, 32, 8, 64, kDwWaves>;
+        hipLaunchKernelGGL(k, dim3(nb), dim3(64 * kDwWaves), 0, s, dZ, X, p, span, partial);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
