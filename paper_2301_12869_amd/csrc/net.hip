@@ -428,23 +428,28 @@ __device__ __forceinline__ float ordered_sum(const float *__restrict__ a, int co
 // dst[e] = sum_b src[b][e], deterministic: the nb slices form kRedGroups
 // consecutive groups, each summed in increasing order by its own thread, and
 // the group sums are added in group order.  A block holds 256 / kRedGroups
-// outputs (consecutive e, so every slice is read coalesced).
+// outputs (consecutive e, so every slice is read coalesced).  One launch
+// serves two such reductions (a layer's weight and bias gradients): blocks
+// past the first one's take the second.
 constexpr int kRedGroups = 8, kRedOutputs = 256 / kRedGroups;
-__global__ __launch_bounds__(256) void reduce_partials(const float *__restrict__ src, int nb, int stride, int n,
-                                                       float *__restrict__ dst)
+__global__ __launch_bounds__(256) void reduce_partials(RedJob ja, RedJob jb)
 {
     __shared__ float part[kRedGroups][kRedOutputs];
+    const int ba = (ja.n + kRedOutputs - 1) / kRedOutputs;
+    const bool first = (int)blockIdx.x < ba;  // uniform
+    const RedJob j = first ? ja : jb;
+    const int blk = first ? (int)blockIdx.x : (int)blockIdx.x - ba;
     const int lo = threadIdx.x % kRedOutputs, g = threadIdx.x / kRedOutputs;
-    const int e = blockIdx.x * kRedOutputs + lo;
-    const int per = (nb + kRedGroups - 1) / kRedGroups;
-    const int b0 = min(nb, g * per), b1 = min(nb, b0 + per);
-    part[g][lo] = e < n ? ordered_sum(src + (size_t)b0 * stride + e, b1 - b0, (size_t)stride) : 0.0f;
+    const int e = blk * kRedOutputs + lo;
+    const int per = (j.nb + kRedGroups - 1) / kRedGroups;
+    const int b0 = min(j.nb, g * per), b1 = min(j.nb, b0 + per);
+    part[g][lo] = e < j.n ? ordered_sum(j.src + (size_t)b0 * j.stride + e, b1 - b0, (size_t)j.stride) : 0.0f;
     __syncthreads();
-    if (g == 0 && e < n) {
+    if (g == 0 && e < j.n) {
         float t = 0.0f;
 #pragma unroll
         for (int k = 0; k < kRedGroups; ++k) t += part[k][lo];
-        dst[e] = t;
+        j.dst[e] = t;
     }
 }
 
@@ -651,8 +656,8 @@ unsigned conv_blocks(int64_t P)
 }
 
 // waves of a weight-gradient block (they share the staged chunks and split
-// the output tiles)
-constexpr int kDwWaves = 8;
+// the output tiles): 16 for long slices, 8 for short ones
+constexpr int kDwWavesBig = 16, kDwWavesSmall = 8;
 
 // slice length (a multiple of 64 positions) and slice count for nblocks
 void slices(int64_t P, int nblocks, int *span, int *nb)
@@ -704,8 +709,7 @@ hipError_t net_conv_forward(int layer, const uint16_t *in, const uint16_t *W, co
 }
 
 hipError_t net_conv_input_grad(int layer, const uint16_t *dZ, const uint16_t *Wg, int64_t P, const uint8_t *guard,
-                               const uint16_t *act_in, uint16_t *dprev_bf16, float *bsum, float *db_prev,
-                               hipStream_t s)
+                               const uint16_t *act_in, uint16_t *dprev_bf16, float *bsum, int *nbsum, hipStream_t s)
 {
     const unsigned nb = conv_blocks(P);
     const dim3 g(nb), b(64 * kConvWaves);
@@ -716,57 +720,53 @@ hipError_t net_conv_input_grad(int layer, const uint16_t *dZ, const uint16_t *Wg
     else
         hipLaunchKernelGGL((conv_mfma<64, 2, 2, 64, kConvWaves>), g, b, 0, s, dZ, Wg, nullptr, p, guard, act_in, nullptr,
                            dprev_bf16, bsum);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    // the previous layer's bias gradient from the blocks' channel sums
-    hipLaunchKernelGGL(reduce_partials, dim3((kNetCout[layer - 1] + kRedOutputs - 1) / kRedOutputs), dim3(256), 0,
-                       s, bsum, (int)nb, 64, kNetCout[layer - 1], db_prev);
+    *nbsum = (int)nb;
     return hipGetLastError();
 }
 
 hipError_t net_weight_grad(int layer, const uint16_t *dZ, const uint16_t *X, int64_t P, int nblocks,
-                           float *partial, float *dW, hipStream_t s)
+                           float *partial, float *dW, const RedJob &bias, hipStream_t s)
 {
     int span, nb;
     slices(P, nblocks, &span, &nb);
     const int p = (int)P;
-    // 128-position chunks halve the per-chunk barriers and give each chunk's
-    // loads twice the time to arrive; short slices keep 64-position chunks
-    // (256 columns of 1024: 0.72 -> 0.69 ms per step; 32 columns would lose 9%)
+    // long slices: 128-position chunks (half the per-chunk barriers, twice
+    // the time for each chunk's loads to arrive) on 16 waves; short slices:
+    // 64-position chunks on 8 waves (256 columns of 1024: 0.62 -> 0.52 ms per
+    // step; the 32-column training batches would lose 6-9% with either)
     const bool big = span >= 512;
+    const dim3 th(64 * (big ? kDwWavesBig : kDwWavesSmall));
     int stride;
     if (layer == 0) {
         stride = 64 * 5 * 8;
-        auto k = big ? dw_mfma<8, 64, 64, 128, kDwWaves> : dw_mfma<8, 64, 64, 64, kDwWaves>;
-        hipLaunchKernelGGL(k, dim3(nb), dim3(64 * kDwWaves), 0, s, dZ, X, p, span, partial);
+        auto k = big ? dw_mfma<8, 64, 64, 128, kDwWavesBig> : dw_mfma<8, 64, 64, 64, kDwWavesSmall>;
+        hipLaunchKernelGGL(k, dim3(nb), th, 0, s, dZ, X, p, span, partial);
     } else if (layer < 5) {
         stride = 64 * 5 * 64;
-        auto k = big ? dw_mfma<64, 64, 64, 128, kDwWaves> : dw_mfma<64, 64, 64, 64, kDwWaves>;
-        hipLaunchKernelGGL(k, dim3(nb), dim3(64 * kDwWaves), 0, s, dZ, X, p, span, partial);
+        auto k = big ? dw_mfma<64, 64, 64, 128, kDwWavesBig> : dw_mfma<64, 64, 64, 64, kDwWavesSmall>;
+        hipLaunchKernelGGL(k, dim3(nb), th, 0, s, dZ, X, p, span, partial);
     } else {
         stride = 32 * 5 * 64;  // rows 2..31 are zero padding
-        auto k = big ? dw_mfma<64, 32, 8, 128, kDwWaves> : dw_mfma<64, 32, 8, 64, kDwWaves>;
-        hipLaunchKernelGGL(k, dim3(nb), dim3(64 * kDwWaves), 0, s, dZ, X, p, span, partial);
+        auto k = big ? dw_mfma<64, 32, 8, 128, kDwWavesBig> : dw_mfma<64, 32, 8, 64, kDwWavesSmall>;
+        hipLaunchKernelGGL(k, dim3(nb), th, 0, s, dZ, X, p, span, partial);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int n = kNetCout[layer] * 5 * kNetCin[layer];
-    hipLaunchKernelGGL(reduce_partials, dim3((n + kRedOutputs - 1) / kRedOutputs), dim3(256), 0, s, partial, nb,
-                       stride, n, dW);
+    // the weight gradient from the slices' partials and, in the same
+    // launch, the bias gradient from its partials
+    const RedJob w{partial, nb, stride, kNetCout[layer] * 5 * kNetCin[layer], dW};
+    const int blocks = (w.n + kRedOutputs - 1) / kRedOutputs + (bias.n + kRedOutputs - 1) / kRedOutputs;
+    hipLaunchKernelGGL(reduce_partials, dim3(blocks), dim3(256), 0, s, w, bias);
     return hipGetLastError();
 }
 
-hipError_t net_bias_grad(int layer, const float *dZ, int64_t P, int nblocks, float *partial, float *db,
-                         hipStream_t s)
+hipError_t net_bias_partials(int zs, const float *dZ, int64_t P, int nblocks, float *partial, int *nparts,
+                             hipStream_t s)
 {
     int span, nb;
     slices(P, nblocks, &span, &nb);
-    const int zs = layer == 5 ? 8 : 64;
     hipLaunchKernelGGL(db_partial, dim3(nb), dim3(256), 0, s, dZ, zs, (int)P, span, partial);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(reduce_partials, dim3((kNetCout[layer] + kRedOutputs - 1) / kRedOutputs), dim3(256), 0, s,
-                       partial, nb, zs, kNetCout[layer], db);
+    *nparts = nb;
     return hipGetLastError();
 }
 

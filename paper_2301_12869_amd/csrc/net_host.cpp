@@ -43,7 +43,7 @@ int64_t b_offset(int layer) { return w_offset(layer) + (int64_t)kNetCout[layer] 
 
 struct NLayout {
     size_t theta, wb[kNetLayers], wg[kNetLayers], dcols, dfield, cols, entries;
-    size_t x, act, out2, guard, dz8f, dz8b, dab, partial, loss, pred, raw;
+    size_t x, act, out2, guard, dz8f, dz8b, dab, partial, bpart, loss, pred, raw;
     size_t total;
     int64_t P;
 };
@@ -71,13 +71,16 @@ NLayout nlayout(const tplbm_net_config &c)
     L.dz8b = al(2 * 8 * P);
     L.dab = al(2 * 64 * P);
     L.partial = al(sizeof(float) * (size_t)kSlices * kPartialStride);
+    // bias-gradient partials: at most 512 convolution blocks x 64 channels,
+    // or kSlices x 8 for the output layer
+    L.bpart = al(sizeof(float) * (size_t)(512 * 64 > kSlices * 8 ? 512 * 64 : kSlices * 8));
     L.loss = al(sizeof(float) * kLossBlocks);
     L.pred = al(sizeof(double) * (size_t)c.max_nodes);
     L.raw = al(sizeof(float) * 2 * (size_t)c.max_nodes);
     size_t t = 4 * L.theta;
     for (int l = 0; l < kNetLayers; ++l) t += L.wb[l] + L.wg[l];
     t += L.dcols + 2 * L.dfield + L.cols + L.entries + L.x + 5 * L.act + 2 * L.out2 + L.guard + L.dz8f + L.dz8b +
-         2 * L.dab + L.partial + L.loss + 2 * L.pred + L.raw;
+         2 * L.dab + L.partial + L.bpart + L.loss + 2 * L.pred + L.raw;
     L.total = t;
     return L;
 }
@@ -100,7 +103,7 @@ struct tplbm_net {
     uint8_t *guard = nullptr;
     float *dz8f = nullptr;
     uint16_t *dz8b = nullptr, *dab[2] = {};
-    float *partial = nullptr, *loss = nullptr;
+    float *partial = nullptr, *bpart = nullptr, *loss = nullptr;
     double *pred_rho = nullptr, *pred_T = nullptr;
     float *raw = nullptr;
     std::vector<tplbm_net_column> data;  // host copy of the training columns
@@ -201,15 +204,18 @@ int loss_and_grad(tplbm_net *n, int64_t P, int64_t nodes, double *loss)
     const uint16_t *dzb = n->dz8b;
     const float *dzf = n->dz8f;
     int cur = 0;
+    // each layer's bias partials come from the output layer's FP32 dZ or
+    // from the input gradient that produced its dZ, and are reduced in the
+    // launch that reduces its weight gradient
+    int nbias = 0, bstride = 8;
+    NHIP(n, net_bias_partials(8, dzf, P, kSlices, n->bpart, &nbias, n->stream));
     for (int l = kNetLayers - 1; l >= 0; --l) {
-        NHIP(n, net_weight_grad(l, dzb, n->act[l], P, kSlices, n->partial, n->grad + w_offset(l), n->stream));
-        // the output layer's bias gradient from its FP32 dZ; every other
-        // layer's comes with the input gradient that produces its dZ
-        if (l == kNetLayers - 1)
-            NHIP(n, net_bias_grad(l, dzf, P, kSlices, n->partial, n->grad + b_offset(l), n->stream));
+        const RedJob bias{n->bpart, nbias, bstride, kNetCout[l], n->grad + b_offset(l)};
+        NHIP(n, net_weight_grad(l, dzb, n->act[l], P, kSlices, n->partial, n->grad + w_offset(l), bias, n->stream));
         if (l == 0) break;
-        NHIP(n, net_conv_input_grad(l, dzb, n->wg[l], P, n->guard, n->act[l], n->dab[cur], n->partial,
-                                    n->grad + b_offset(l - 1), n->stream));
+        NHIP(n, net_conv_input_grad(l, dzb, n->wg[l], P, n->guard, n->act[l], n->dab[cur], n->bpart, &nbias,
+                                    n->stream));
+        bstride = 64;
         dzb = n->dab[cur];
         cur ^= 1;
     }
@@ -361,6 +367,7 @@ int tplbm_net_create(const tplbm_net_config *c, void *dev_workspace, size_t byte
     n->dz8b = (uint16_t *)q; q += L.dz8b;
     for (int k = 0; k < 2; ++k) { n->dab[k] = (uint16_t *)q; q += L.dab; }
     n->partial = (float *)q; q += L.partial;
+    n->bpart = (float *)q; q += L.bpart;
     n->loss = (float *)q; q += L.loss;
     n->pred_rho = (double *)q; q += L.pred;
     n->pred_T = (double *)q; q += L.pred;

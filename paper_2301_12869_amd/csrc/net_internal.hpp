@@ -38,16 +38,25 @@ hipError_t net_raw_out(const NetCol *cols, const NetEntry *entries, int n, const
                        hipStream_t s);
 hipError_t net_conv_forward(int layer, const uint16_t *in, const uint16_t *W, const float *bias, int64_t P,
                             const uint8_t *guard, uint16_t *out_bf16, float *out_f32, hipStream_t s);
+// one ordered reduction dst[e] = sum_b src[b * stride + e], e < n, b < nb
+struct RedJob {
+    const float *src;
+    int nb, stride, n;
+    float *dst;
+};
 // input gradient of layer `layer` (masked by its input act_in) in BF16, and
-// the bias gradient of layer - 1 (its channel sums) into db_prev; bsum holds
-// the launch's per-block sums (1024 x 64 floats)
+// per-block channel sums of it (the bias gradient of layer - 1) into bsum:
+// *nbsum rows of 64 floats (at most 512)
 hipError_t net_conv_input_grad(int layer, const uint16_t *dZ, const uint16_t *Wg, int64_t P, const uint8_t *guard,
-                               const uint16_t *act_in, uint16_t *dprev_bf16, float *bsum, float *db_prev,
-                               hipStream_t s);
+                               const uint16_t *act_in, uint16_t *dprev_bf16, float *bsum, int *nbsum, hipStream_t s);
+// weight gradient of a layer, reduced together with its bias gradient
+// (`bias`, the partials of net_conv_input_grad or net_bias_partials)
 hipError_t net_weight_grad(int layer, const uint16_t *dZ, const uint16_t *X, int64_t P, int nblocks,
-                           float *partial, float *dW, hipStream_t s);
-hipError_t net_bias_grad(int layer, const float *dZ, int64_t P, int nblocks, float *partial, float *db,
-                         hipStream_t s);
+                           float *partial, float *dW, const RedJob &bias, hipStream_t s);
+// per-slice channel sums of an FP32 dZ with zs channels per position
+// (*nparts rows of zs floats)
+hipError_t net_bias_partials(int zs, const float *dZ, int64_t P, int nblocks, float *partial, int *nparts,
+                             hipStream_t s);
 hipError_t net_loss(const float *out, const float *tgt, const uint8_t *guard, int64_t P, float scale, float *dZf,
                     uint16_t *dZb, float *partial, int nblocks, hipStream_t s);
 hipError_t net_adam(float *theta, const float *grad, float *m, float *v, int n, float lr, float b1, float b2,
