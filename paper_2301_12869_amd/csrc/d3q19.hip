@@ -642,7 +642,6 @@ int d3q19_num_blocks(int nx, int ny, int nz, int cus)
 
 hipError_t d3q19_launch_step(const LatticeLaunch &L, double *M, double *U, double *K1)
 {
-    if (L.moments) return L.walls ? step_mom_t<true>(L, U, K1) : step_mom_t<false>(L, U, K1);
     return d3q19_march_step(L, U);
 }
 
@@ -660,7 +659,10 @@ hipError_t d3q19_launch_readout(const LatticeLaunch &L, int field, double *M, do
     const Grid3 G{L.nx, L.ny, L.nz, (unsigned)((size_t)L.nx * L.ny * L.nz)};
     const int g = grid_rows(L.ny, L.nz, L.resident);
     if (L.moments) {
-        M = (double *)L.fin;  // the state is M itself
+        // the state is M itself; its psi plane is the readout's to fill
+        M = (double *)L.fin;
+        const hipError_t e = d3q19_launch_psi_init(L, M);
+        if (e != hipSuccess) return e;
     } else if (L.fp32) {
         if (L.walls)
             hipLaunchKernelGGL((d3q19_pass_a<float, true>), dim3(g), dim3(256), 0, L.stream, (const float *)L.fin, L.Tin, M, L.phys, G, L.rref);

@@ -690,6 +690,308 @@ __global__ __launch_bounds__(kEThreads) void d3q19_march_e(const double *__restr
            pendT);
 }
 
+// ---- LM: the moment-state step (FP64, every tau = 1) --------------------------
+
+// With every relaxation time 1 the post-collision set of a node is a closed
+// function of its (rho, u, F, X), so the state carried between steps can be
+// (rho, j) and T instead of the nineteen populations.  LM takes the LBM part
+// of a step on that state and hands u and rho to E through U, as L does.  One
+// column per thread (the tile, the ring at distance 1, the ring at distance
+// 2); per plane a:
+//   psi of plane a on every column (rho and T read one plane ahead) -> a ring
+//     of four psi planes;
+//   two planes behind, on the tile and the first ring: the Shan-Chen force
+//     and gravity of plane b = a - 2 (zero on wall planes), u = (j + F/2)/rho
+//     and X = sigma |F_int|^2 / psi^2 -> (rho, u, F, X) of plane b in one of
+//     two LDS plane slots; the tile stores u and rho for E and reduces the
+//     level's diagnostics;
+//   three planes behind, on the tile: a column evaluates, for each of the 3 x
+//     3 nodes around it on plane p = a - 3, the post-collision populations
+//     whose velocity carries them to this column -- down to plane p - 1, along
+//     plane p, up to plane p + 1 -- and adds them to the density and momentum
+//     it accumulates for those planes.  Plane p - 1 then has all nineteen: on
+//     a wall plane the populations from beyond the wall are the wet-node
+//     reconstruction, whose sums are closed forms (below); the column stores
+//     the next level's (rho, j).
+// Each node's (rho, u, F, X) is read from LDS once per neighbour column
+// rather than once per population, and nothing but (rho, j, T) in and (rho,
+// j) and U out touches memory.  One barrier per plane: the psi slot and the
+// (rho, u, F, X) slot a plane writes were last read before the previous
+// barrier.
+//
+// Wall planes: the unknown populations of the wet-node reconstruction are f_i
+// = f_opp(i) - c_x N_x - c_y N_y with N = half the in-plane momentum.  Summed
+// over the five unknown velocities they add the density D of the known
+// populations that cross the plane from the lattice side, and cancel the
+// momentum exactly: rho' = rho_in + 2 D and j' = 0, the no-slip wall.
+//
+// The rest population is its closed form w_0 (rho (1 - 3/2 u.u) - 3/2 u.F -
+// 3/4 X), which the other populations' sum equals in exact arithmetic.
+
+// (rho, u, F, X) of a node as LM stages them: one LDS plane slot holds eight
+// planes of the region of halo 1
+constexpr int kLmVals = 8;
+// 720 columns in 12 full waves: threads 720 .. 767 hold no column and take
+// part in the barriers and the block reduction only
+constexpr int kLmColumns = TileE::Threads + TileE::Ring1 + TileE::Ring2;
+constexpr int kLmThreads = (kLmColumns + 63) / 64 * 64;
+
+struct Acc4 {
+    double r, x, y, z;
+};
+
+// the node terms of a post-collision population (Eqs. Equilibrium, Guo, with
+// the sigma term) that do not depend on the velocity
+struct SrcNode {
+    double rho, ux, uy, uz, Fx, Fy, Fz, even0, sig2;
+};
+
+template <int RN>
+__device__ __forceinline__ SrcNode src_node(const double (&q)[kLmVals][RN], int k)
+{
+    SrcNode s;
+    s.rho = q[0][k];
+    s.ux = q[1][k];
+    s.uy = q[2][k];
+    s.uz = q[3][k];
+    s.Fx = q[4][k];
+    s.Fy = q[5][k];
+    s.Fz = q[6][k];
+    const double X = q[7][k];
+    const double uu = s.ux * s.ux + s.uy * s.uy + s.uz * s.uz;
+    const double uF = s.ux * s.Fx + s.uy * s.Fy + s.uz * s.Fz;
+    s.even0 = s.rho * (1.0 - 1.5 * uu) - 1.5 * uF;
+    s.sig2 = 0.75 * X;
+    return s;
+}
+
+// post-collision population of velocity (CX, CY, CZ) at tau = 1: f_eq + half
+// of Guo's term + the isotropic sigma term, added to an accumulator with its
+// momentum
+template <int CX, int CY, int CZ>
+__device__ __forceinline__ void add_post(Acc4 &a, const SrcNode &s)
+{
+    constexpr V3 v{CX, CY, CZ};
+    constexpr int c2 = CX * CX + CY * CY + CZ * CZ;
+    constexpr double w = c2 == 1 ? 1.0 / 18.0 : 1.0 / 36.0;
+    const double cu = cdot(v, s.ux, s.uy, s.uz), cF = cdot(v, s.Fx, s.Fy, s.Fz);
+    double e = s.even0 + 4.5 * cu * (s.rho * cu + cF) + (3.0 * s.rho * cu + 1.5 * cF);
+    if (c2 == 2) e += s.sig2;
+    const double f = w * e;
+    a.r += f;
+    if (CX) a.x += CX * f;
+    if (CY) a.y += CY * f;
+    if (CZ) a.z += CZ * f;
+}
+
+// the populations a column at region index k pulls from its neighbour at
+// offset (OX, OY) on plane p: velocity (-OX, -OY, c_z) lands on plane p +
+// c_z, c_z = -1 (lo), 0 (mid), +1 (hi) where the velocity set has it
+template <int OX, int OY, int RN, int RX>
+__device__ __forceinline__ void pull_from(const double (&q)[kLmVals][RN], int k, Acc4 &lo, Acc4 &mid, Acc4 &hi)
+{
+    // one neighbour at a time: the scheduler would otherwise hoist all the
+    // neighbours' LDS reads (72 values) and spill
+    __builtin_amdgcn_sched_barrier(0);
+    const SrcNode s = src_node<RN>(q, k + OY * RX + OX);
+    constexpr int cxy2 = OX * OX + OY * OY;
+    if (cxy2 == 0) {
+        mid.r += (1.0 / 3.0) * (s.even0 - s.sig2);
+        add_post<0, 0, 1>(hi, s);
+        add_post<0, 0, -1>(lo, s);
+    } else if (cxy2 == 1) {
+        add_post<-OX, -OY, 0>(mid, s);
+        add_post<-OX, -OY, 1>(hi, s);
+        add_post<-OX, -OY, -1>(lo, s);
+    } else {
+        add_post<-OX, -OY, 0>(mid, s);
+    }
+}
+
+template <bool WALLS>
+__global__ __launch_bounds__(kLmThreads) void d3q19_march_lm(const double *__restrict__ Min,
+                                                            double *__restrict__ Mout,
+                                                            const double *__restrict__ Tin, double *__restrict__ U,
+                                                            Phys c, Grid3 G, MarchG3 M,
+                                                            double *__restrict__ partials,
+                                                            StepState *__restrict__ st, int64_t step)
+{
+    using T = TileE;
+    using R2 = T::Region<2>;
+    using R1 = T::Region<1>;
+    __shared__ double s_psi[4][R2::N];
+    __shared__ double s_q[2][kLmVals][R1::N];
+    __shared__ double s_red[4 * kLmThreads / 64];
+    __shared__ unsigned s_ured[kLmThreads / 64];
+    const int t = threadIdx.x;
+    const unsigned N = G.N;
+    const Seg3 sg = block_segment<T>(M, G.nz);
+    const bool tile = t < T::Threads, ring1 = !tile && t < T::Threads + T::Ring1;
+    const bool has = t < kLmColumns;
+    const bool first = tile || ring1;  // a column of the force stage
+    int rx = 2, ry = 2;
+    if (tile) {
+        rx = t % T::TX + 2;
+        ry = t / T::TX + 2;
+    } else if (ring1) {
+        ring_column<T>(1, 2, t - T::Threads, rx, ry);
+    } else if (has) {
+        ring_column<T>(2, 2, t - T::Threads - T::Ring1, rx, ry);
+    }
+    const Col col = make_col(G, sg.x0, sg.y0, rx, ry, 2, R2::RX, has);
+    const int r1 = (ry - 1) * R1::RX + (rx - 1);  // index in the region of halo 1 (force-stage columns)
+    const bool mine = tile && sg.x0 + rx - 2 < G.nx && sg.y0 + ry - 2 < G.ny;
+    const unsigned plane = (unsigned)G.nx * (unsigned)G.ny;
+    const unsigned vo = col.n0 * 8u + col.oob;
+    const unsigned vj = first ? vo : kOut;   // j is read where the force stage runs
+    const unsigned vst = mine ? vo : kOut;   // the tile's lattice columns store
+    const double sub = gravity_sub(c.form, st->mean[step & 1], c.rho_v);
+
+    Partial part = {0.0, 0.0, 0.0, 1e300, 0u};
+    // rho, j of the column at planes a - 1 (p1) and a - 2 (p2)
+    double r_1 = 0.0, x_1 = 0.0, y_1 = 0.0, z_1 = 0.0, r_2 = 0.0, x_2 = 0.0, y_2 = 0.0, z_2 = 0.0;
+    // density and momentum pulled so far for planes p - 1, p, p + 1 of the
+    // pull of plane p; uplo, upmid: the density of the populations from below
+    // (the top wall's reconstruction needs it)
+    Acc4 lo = {0.0, 0.0, 0.0, 0.0}, mid = lo;
+    double uplo = 0.0, upmid = 0.0;
+    // planes z0 - 2 .. z1 + 1 are read, one plane ahead of their use; a read
+    // beyond them, or beyond a wall, is an empty range (zeros)
+    auto load = [&](int z, double &vr, double &vx, double &vy, double &vz, double &vT) __attribute__((always_inline)) {
+        bool beyond;
+        const size_t zo = (size_t)plane_of<WALLS>(z, G.nz, beyond) * plane;
+        beyond = beyond || z > sg.z1 + 1;
+        vr = buf_ld(layer_rsrc(Min + zo, plane, beyond), vo, 0u, 0.0);
+        vx = buf_ld(layer_rsrc(Min + N + zo, plane, beyond), vj, 0u, 0.0);
+        vy = buf_ld(layer_rsrc(Min + 2 * (size_t)N + zo, plane, beyond), vj, 0u, 0.0);
+        vz = buf_ld(layer_rsrc(Min + 3 * (size_t)N + zo, plane, beyond), vj, 0u, 0.0);
+        vT = buf_ld(layer_rsrc(Tin + zo, plane, beyond), vo, 0u, 0.0);
+    };
+    double nr, nx, ny, nzv, nT;
+    load(sg.z0 - 2, nr, nx, ny, nzv, nT);
+    for (int a = sg.z0 - 2; a <= sg.z1 + 3; ++a) {
+        const double ra = nr, xa = nx, ya = ny, za = nzv, Ta = nT;
+        load(a + 1, nr, nx, ny, nzv, nT);
+
+        // psi of plane a (nothing beyond a wall)
+        {
+            bool beyond;
+            plane_of<WALLS>(a, G.nz, beyond);
+            double Z;
+            const double psi = psi_and_Z(c, ra, Ta, Z);
+            if (has) s_psi[a & 3][col.r] = beyond ? 0.0 : psi;
+        }
+
+        // force stage of plane b = a - 2; the psi planes b - 1 .. b + 1 were
+        // written before the previous barrier
+        const int b = a - 2;
+        if (first && b >= sg.z0 - 1) {  // the first test is per wave, the second uniform
+            bool beyond;
+            plane_of<WALLS>(b, G.nz, beyond);
+            const bool wall = WALLS && (b == 0 || b == G.nz - 1);
+            const double psi0 = s_psi[b & 3][col.r];
+            // evaluated everywhere and zeroed on wall planes and beyond them
+            // (psi there is finite): no branch around the LDS reads
+            double sx = 0.0, sy = 0.0, sz = 0.0;
+#pragma unroll
+            for (int i = 1; i < 19; ++i) {
+                const V3 v = vel(i);
+                const double w = i < 7 ? 1.0 / 6.0 : 1.0 / 12.0;
+                const double p = s_psi[(b + v.z) & 3][col.r + v.y * R2::RX + v.x];
+                if (v.x) sx += w * v.x * p;
+                if (v.y) sy += w * v.y * p;
+                if (v.z) sz += w * v.z * p;
+            }
+            const bool off = wall || beyond;
+            const double mg = off ? 0.0 : -c.G * psi0;
+            const double Fx = mg * sx, Fy = mg * sy;
+            const double Fz = mg * sz + (off ? 0.0 : gravity_force(r_2, sub, c.g));
+            const double Xs2 = off ? 0.0 : c.sigma * c.G2 * (sx * sx + sy * sy + sz * sz);  // sigma |F_int|^2 / psi^2
+            const double inv = rcp_pos(r_2);
+            const double ux = beyond ? 0.0 : (x_2 + 0.5 * Fx) * inv;
+            const double uy = beyond ? 0.0 : (y_2 + 0.5 * Fy) * inv;
+            const double uz = beyond ? 0.0 : (z_2 + 0.5 * Fz) * inv;
+            double(&q)[kLmVals][R1::N] = s_q[b & 1];
+            q[0][r1] = r_2;
+            q[1][r1] = ux;
+            q[2][r1] = uy;
+            q[3][r1] = uz;
+            q[4][r1] = Fx;
+            q[5][r1] = Fy;
+            q[6][r1] = Fz;
+            q[7][r1] = Xs2;
+            if (tile) {
+                const bool live = b >= sg.z0 && b < sg.z1;  // uniform
+                const size_t zb = (size_t)(live ? b : sg.z0) * plane;
+                buf_st(layer_rsrc(U + zb, plane, !live), vst, 0u, ux);
+                buf_st(layer_rsrc(U + N + zb, plane, !live), vst, 0u, uy);
+                buf_st(layer_rsrc(U + 2 * (size_t)N + zb, plane, !live), vst, 0u, uz);
+                buf_st(layer_rsrc(U + 3 * (size_t)N + zb, plane, !live), vst, 0u, r_2);
+                const bool keep = live && mine;
+                const double uu = ux * ux + uy * uy + uz * uz;
+                unsigned fl = 0u;
+                if (!(r_2 > 0.0)) fl |= kFlagRho;
+                if (c.eos == 0 && c.b_quarter * r_2 >= 1.0) fl |= kFlagEta;
+                if (psi0 != psi0) fl |= kFlagPsi;
+                if (r_2 != r_2 || uu != uu) fl |= kFlagNaN;
+                part.mass_n += keep ? r_2 : 0.0;
+                part.umax = keep ? fmax(part.umax, uu) : part.umax;
+                part.rmin = keep ? fmin(part.rmin, r_2) : part.rmin;
+                part.flags |= keep ? fl : 0u;
+            }
+        }
+
+        // pull from plane p = a - 3 (written before the previous barrier);
+        // plane p - 1 is then complete
+        const int p = a - 3;
+        if (tile && p >= sg.z0 - 1) {
+            const double(&q)[kLmVals][R1::N] = s_q[p & 1];
+            Acc4 dlo = {0.0, 0.0, 0.0, 0.0}, hi = dlo;
+            pull_from<-1, -1, R1::N, R1::RX>(q, r1, dlo, mid, hi);
+            pull_from<0, -1, R1::N, R1::RX>(q, r1, dlo, mid, hi);
+            pull_from<1, -1, R1::N, R1::RX>(q, r1, dlo, mid, hi);
+            pull_from<-1, 0, R1::N, R1::RX>(q, r1, dlo, mid, hi);
+            pull_from<0, 0, R1::N, R1::RX>(q, r1, dlo, mid, hi);
+            pull_from<1, 0, R1::N, R1::RX>(q, r1, dlo, mid, hi);
+            pull_from<-1, 1, R1::N, R1::RX>(q, r1, dlo, mid, hi);
+            pull_from<0, 1, R1::N, R1::RX>(q, r1, dlo, mid, hi);
+            pull_from<1, 1, R1::N, R1::RX>(q, r1, dlo, mid, hi);
+            const int qz = p - 1;
+            // on a wall plane nothing has arrived from beyond the wall (its
+            // planes hold zeros); selects rather than a branch, which the
+            // compiler would turn into a second copy of the march
+            const bool wq = WALLS && (qz == 0 || qz == G.nz - 1);
+            const double back = WALLS && qz == 0 ? dlo.r : (WALLS && qz == G.nz - 1 ? uplo : 0.0);
+            const double rn = (lo.r + dlo.r) + back;
+            const double jx = wq ? 0.0 : lo.x + dlo.x, jy = wq ? 0.0 : lo.y + dlo.y, jz = wq ? 0.0 : lo.z + dlo.z;
+            const bool live = qz >= sg.z0 && qz < sg.z1;  // uniform
+            const size_t zq = (size_t)(live ? qz : sg.z0) * plane;
+            buf_st(layer_rsrc(Mout + zq, plane, !live), vst, 0u, rn);
+            buf_st(layer_rsrc(Mout + N + zq, plane, !live), vst, 0u, jx);
+            buf_st(layer_rsrc(Mout + 2 * (size_t)N + zq, plane, !live), vst, 0u, jy);
+            buf_st(layer_rsrc(Mout + 3 * (size_t)N + zq, plane, !live), vst, 0u, jz);
+            const bool keep = live && mine;
+            part.mass_next += keep ? rn : 0.0;
+            part.flags |= (keep && rn != rn) ? kFlagNaN : 0u;
+            lo = mid;
+            mid = hi;
+            uplo = upmid;
+            upmid = hi.r;
+        }
+        r_2 = r_1;
+        x_2 = x_1;
+        y_2 = y_1;
+        z_2 = z_1;
+        r_1 = ra;
+        x_1 = xa;
+        y_1 = ya;
+        z_1 = za;
+        __syncthreads();
+    }
+    part = block_reduce<kLmThreads>(part, s_red, s_ured);
+    finish_launch<kLmThreads>(part, partials, st, step, (int)((step + 1) & 1), 1.0 / (double)N, s_red, s_ured);
+}
+
 template <class T>
 MarchG3 march_grid3(int nx, int ny, int nz, int cus, int per_cu = 1)
 {
@@ -719,6 +1021,19 @@ hipError_t march_t(const LatticeLaunch &L, double *U)
     return hipGetLastError();
 }
 
+// moment state: LM, then E on the same grid of tiles and segments
+template <bool WALLS>
+hipError_t march_mom_t(const LatticeLaunch &L, double *U)
+{
+    const Grid3 G{L.nx, L.ny, L.nz, (unsigned)((size_t)L.nx * L.ny * L.nz)};
+    const MarchG3 M = march_grid3<TileE>(L.nx, L.ny, L.nz, L.resident, kEBlocksPerCU);
+    hipLaunchKernelGGL((d3q19_march_lm<WALLS>), dim3(M.nblocks), dim3(kLmThreads), 0, L.stream,
+                       (const double *)L.fin, (double *)L.fout, L.Tin, U, L.phys, G, M, L.partials, L.st, L.step);
+    hipLaunchKernelGGL((d3q19_march_e<WALLS>), dim3(M.nblocks), dim3(kEThreads), 0, L.stream, L.Tin, L.Tout,
+                       (const double *)U, L.phys, G, M);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 // the LBM kernel writes the per-block partials
@@ -726,6 +1041,7 @@ int d3q19_march_blocks(int nx, int ny, int nz, int cus) { return march_grid3<Til
 
 hipError_t d3q19_march_step(const LatticeLaunch &L, double *U)
 {
+    if (L.moments) return L.walls ? march_mom_t<true>(L, U) : march_mom_t<false>(L, U);
     if (L.fp32) return L.walls ? march_t<float, true>(L, U) : march_t<float, false>(L, U);
     return L.walls ? march_t<double, true>(L, U) : march_t<double, false>(L, U);
 }
