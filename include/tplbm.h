@@ -67,12 +67,12 @@ extern "C" {
  * the post-collision populations are a closed function of the node's density,
  * force-corrected velocity and force (Eq. LiFS with Eq. OperatorMRT at
  * Lambda = I), so an FP64 lattice can carry its moments instead of the
- * populations: rho and j (D2Q9, 3 planes instead of 9) or rho, j and psi
- * (D3Q19, 5 planes instead of 19), plus T; the same arithmetic as the
- * population state, equal to rounding.  MOMENTS carries the moments (FP64,
- * every tau = 1 only: TPLBM_EINVAL otherwise); POPULATIONS always stores
- * populations; AUTO takes the faster of the two where both apply: the
- * moments on D2Q9, the populations on D3Q19. */
+ * populations: rho and j (D2Q9, 3 planes instead of 9; D3Q19, 4 planes
+ * and a fifth that a readout fills with psi, instead of 19), plus T; the
+ * same arithmetic as the population state, equal to rounding.  MOMENTS
+ * carries the moments (FP64, every tau = 1 only: TPLBM_EINVAL otherwise);
+ * POPULATIONS always stores populations; AUTO takes the moments wherever they
+ * apply (they are the faster state on both lattices). */
 #define TPLBM_STATE_AUTO 0
 #define TPLBM_STATE_POPULATIONS 1
 #define TPLBM_STATE_MOMENTS 2

@@ -8,23 +8,15 @@
 // Guo's term plus the isotropic sigma term w_i (|c_i|^2 - 1)(3/4) sigma X',
 // the D2Q9 sigma term of Li's scheme written without the 2-D moment basis.
 //
-// This file holds the pass kernels.  The population state (FP32 deviations
-// or FP64 populations) is advanced by the z-marching kernels of
-// d3q19_march.hip; the passes here serve the readout and the moment state:
-//   A: pull-stream with Zou-He wall reconstruction, rho, j, psi -> M
+// This file holds the readout passes.  Both states (the populations, FP32
+// deviations or FP64, and the FP64 moment state) are advanced by the
+// z-marching kernels of d3q19_march.hip; a readout rebuilds the level's
+// fields here:
+//   A: pull-stream with Zou-He wall reconstruction, rho, j, psi -> M (the
+//      moment state is M itself, whose psi plane the readout fills)
 //   B: Shan-Chen force (zero at walls), gravity, u = (j + F/2)/rho, and
 //      sigma |F_int|^2 / psi^2                               -> U (u, F, X)
-//   C: div u and the first Heun stage of the energy equation, k1 = K(T^n)
-//                                                             -> K1 (k1, div u)
-// Every stencil is evaluated once per node and step; the passes hand the
-// results on instead of recomputing them.
-//
-// FP64 lattices carry M and T between steps instead of the populations (the
-// moment state): a step is then B, C and M, where M takes the second Heun
-// stage and the collision (T^{n+1} = T^n + (k1 + K(T^n + k1))/2, f* = f_eq +
-// F') fused with the next step's A -- the post-collision populations of each
-// node's neighbours evaluated from their (rho, u, F, X), the pull, Zou-He and
-// psi -> M^{n+1}.
+// and the readout kernel forms the requested field from M, U and T.
 #include <hip/hip_runtime.h>
 
 #include "d3q19_common.hpp"
@@ -194,7 +186,7 @@ __global__ __launch_bounds__(256) void d3q19_pass_a(const S *__restrict__ fin, c
 }
 
 // ---- tiles for the stencil passes -------------------------------------------
-// Passes B, C and D evaluate 18-neighbour stencils.  A block takes a tile of
+// Pass B evaluates 18-neighbour stencils.  A block takes a tile of
 // TX x TY x TZ nodes, stages the stencil fields of the tile plus a one-node
 // halo ((TX + 2) x (TY + 2) x (TZ + 2), the region) in LDS once, and
 // evaluates every stencil from there.  Tiles are walked persistently; XCD k
@@ -210,17 +202,10 @@ struct TileShape {
         return ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY) * ((nz + TZ - 1) / TZ);
     }
 };
-// Passes B and D stage one field each (the region of a 64 x 8 x 4 tile:
-// 66 x 10 x 6 nodes, 31.7 KB).  Pass C stages four; with a 32 x 8 x 4 tile
-// (34 x 10 x 6 nodes, 65 KB) two of its 512-thread blocks share a compute
-// unit.
+// Pass B stages one field (the region of a 64 x 8 x 4 tile: 66 x 10 x 6
+// nodes, 31.7 KB).
 using TileBD = TileShape<64, 8, 4>;
-using TileC = TileShape<32, 8, 4>;
 constexpr int kStencilThreads = 512;
-// The moment-state pass stages nine fields of a 32 x 8 x 4 tile's region
-// (34 x 10 x 6 nodes, 147 KB): one block per compute unit, 1024 threads.
-using TileM = TileShape<32, 8, 4>;
-constexpr int kMomThreads = 1024;
 
 struct TileIter {
     int first, end, step;
@@ -342,207 +327,6 @@ __global__ __launch_bounds__(kStencilThreads) void d3q19_pass_b(const double *__
     }
 }
 
-// isotropic differences on the D3Q19 stencil from a region field:
-// grad = 3 sum w c phi, lap = 6 sum w (phi_i - phi_0)
-template <class Sh>
-__device__ __forceinline__ void grad_lap(const double *__restrict__ a, int tx, int ty, int tz, double c0, double &gx,
-                                         double &gy, double &gz, double &lap)
-{
-    gx = gy = gz = lap = 0.0;
-#pragma unroll
-    for (int i = 1; i < 19; ++i) {
-        const V3 v = vel(i);
-        const double p = a[rnb<Sh>(tx, ty, tz, v.x, v.y, v.z)];
-        const double w = wgt(i);
-        if (v.x) gx += w * v.x * p;
-        if (v.y) gy += w * v.y * p;
-        if (v.z) gz += w * v.z * p;
-        lap += w * (p - c0);
-    }
-    gx *= 3.0;
-    gy *= 3.0;
-    gz *= 3.0;
-    lap *= 6.0;
-}
-
-// div u = 3 sum w c.u_i from the region fields of u
-template <class Sh>
-__device__ __forceinline__ double div3(const double *__restrict__ ux, const double *__restrict__ uy,
-                                       const double *__restrict__ uz, int tx, int ty, int tz)
-{
-    double d = 0.0;
-#pragma unroll
-    for (int i = 1; i < 19; ++i) {
-        const V3 v = vel(i);
-        const int m = rnb<Sh>(tx, ty, tz, v.x, v.y, v.z);
-        d += wgt(i) * cdot(v, v.x ? ux[m] : 0.0, v.y ? uy[m] : 0.0, v.z ? uz[m] : 0.0);
-    }
-    return 3.0 * d;
-}
-
-// ---- pass C: div u and the first Heun stage ------------------------------------
-template <bool WALLS>
-__global__ __launch_bounds__(kStencilThreads) void d3q19_pass_c(const double *__restrict__ Tin,
-                                                                const double *__restrict__ M,
-                                                                const double *__restrict__ U,
-                                                                double *__restrict__ K1, Phys c, Grid3 G)
-{
-    using Sh = TileC;
-    __shared__ double s_T[Sh::Region], s_ux[Sh::Region], s_uy[Sh::Region], s_uz[Sh::Region];
-    const unsigned N = G.N;
-    const int ntiles = Sh::count(G.nx, G.ny, G.nz);
-    const TileIter it = tile_iter(ntiles);
-    for (int t = it.first; t < it.end; t += it.step) {
-        const Tile3 o = tile_origin<Sh>(G, t);
-        __syncthreads();
-        for (int r = threadIdx.x; r < Sh::Region; r += kStencilThreads) {
-            const unsigned m = region_index<WALLS, Sh>(G, o, r);
-            s_T[r] = Tin[m];
-            s_ux[r] = U[m];
-            s_uy[r] = U[N + m];
-            s_uz[r] = U[2 * (size_t)N + m];
-        }
-        __syncthreads();
-        for (int k = threadIdx.x; k < Sh::Nodes; k += kStencilThreads) {
-            const int tx = k % Sh::TX, ty = (k / Sh::TX) % Sh::TY, tz = k / (Sh::TX * Sh::TY);
-            const int x = o.x0 + tx, y = o.y0 + ty, z = o.z0 + tz;
-            if (x >= G.nx || y >= G.ny || z >= G.nz) continue;
-            const unsigned n = ((unsigned)z * (unsigned)G.ny + (unsigned)y) * (unsigned)G.nx + (unsigned)x;
-            if (WALLS && (z == 0 || z == G.nz - 1)) {
-                K1[n] = 0.0;
-                K1[N + n] = 0.0;
-                continue;
-            }
-            const int c0 = rnb<Sh>(tx, ty, tz, 0, 0, 0);
-            const double rho = M[n], T0 = s_T[c0];
-            double gx, gy, gz, lap;
-            grad_lap<Sh>(s_T, tx, ty, tz, T0, gx, gy, gz, lap);
-            const double divu = div3<Sh>(s_ux, s_uy, s_uz, tx, ty, tz);
-            const double Z = c.eos == 0 ? cs_Z(c.b_quarter * rho) : 0.0;
-            K1[n] = -(s_ux[c0] * gx + s_uy[c0] * gy + s_uz[c0] * gz) + c.kappa_over_cv * rcp_pos(rho) * lap -
-                    T0 * c.R_over_cv * Z * divu;
-            K1[N + n] = divu;
-        }
-    }
-}
-
-// ---- moment-state pass (every tau = 1, FP64) ----------------------------------
-// With every relaxation time 1 the post-collision set of a node is a closed
-// function of its (rho, u, F, X) (post_tau1), so the state between steps can
-// be the level's M = (rho, j, psi) and T instead of the 19 populations.  This
-// pass takes the second Heun stage and the collision, fused with the next
-// step's pass A: it stages rho, u, F, X and
-// T~ = T^n + k1 on the region of a tile; every tile node
-//   * takes the second Heun stage (T^{n+1}, stored),
-//   * closes its own rest population, f*_0 = rho - sum_{i>0} f*_i, as the
-//     population state's collision does,
-//   * pulls f_i(x) = f*_i(x - c_i), evaluating post_tau1 at the neighbour x - c_i,
-//   * reconstructs the wall populations, sums rho' and j', and evaluates
-//     psi(rho', T^{n+1}): M^{n+1}.
-// It evaluates the same expressions as the population state's collision and
-// pass A, so the two states agree
-// to rounding (the compiler may fuse multiply-adds differently in the two).
-template <bool WALLS>
-__global__ __launch_bounds__(kMomThreads) void d3q19_pass_m(const double *__restrict__ Tin,
-                                                            double *__restrict__ Tout,
-                                                            const double *__restrict__ Min,
-                                                            const double *__restrict__ U,
-                                                            const double *__restrict__ K1,
-                                                            double *__restrict__ Mout, Phys c, Grid3 G,
-                                                            double *__restrict__ partials,
-                                                            StepState *__restrict__ st, int64_t step)
-{
-    using Sh = TileM;
-    __shared__ double s_rho[Sh::Region], s_ux[Sh::Region], s_uy[Sh::Region], s_uz[Sh::Region];
-    __shared__ double s_Fx[Sh::Region], s_Fy[Sh::Region], s_Fz[Sh::Region], s_X[Sh::Region];
-    __shared__ double s_Tt[Sh::Region];  // T~ = T^n + k1
-    __shared__ double s_red[4 * kMomThreads / 64];
-    __shared__ unsigned s_ured[kMomThreads / 64];
-    const unsigned N = G.N;
-    Partial part = {0.0, 0.0, 0.0, 1e300, 0u};
-    const int ntiles = Sh::count(G.nx, G.ny, G.nz);
-    const TileIter it = tile_iter(ntiles);
-    for (int t = it.first; t < it.end; t += it.step) {
-        const Tile3 o = tile_origin<Sh>(G, t);
-        __syncthreads();
-        for (int r = threadIdx.x; r < Sh::Region; r += kMomThreads) {
-            const unsigned m = region_index<WALLS, Sh>(G, o, r);
-            s_rho[r] = Min[m];
-            s_ux[r] = U[m];
-            s_uy[r] = U[N + m];
-            s_uz[r] = U[2 * (size_t)N + m];
-            s_Fx[r] = U[3 * (size_t)N + m];
-            s_Fy[r] = U[4 * (size_t)N + m];
-            s_Fz[r] = U[5 * (size_t)N + m];
-            s_X[r] = U[6 * (size_t)N + m];
-            s_Tt[r] = Tin[m] + K1[m];
-        }
-        __syncthreads();
-        for (int k = threadIdx.x; k < Sh::Nodes; k += kMomThreads) {
-            const int tx = k % Sh::TX, ty = (k / Sh::TX) % Sh::TY, tz = k / (Sh::TX * Sh::TY);
-            const int x = o.x0 + tx, y = o.y0 + ty, z = o.z0 + tz;
-            if (x >= G.nx || y >= G.ny || z >= G.nz) continue;
-            const unsigned n = ((unsigned)z * (unsigned)G.ny + (unsigned)y) * (unsigned)G.nx + (unsigned)x;
-            const bool wall = WALLS && (z == 0 || z == G.nz - 1);
-            const int c0 = rnb<Sh>(tx, ty, tz, 0, 0, 0);
-            const double rho = s_rho[c0], ux = s_ux[c0], uy = s_uy[c0], uz = s_uz[c0], T0 = Tin[n];
-            double Tn = T0;
-            if (!wall) {
-                const double k1 = K1[n];
-                double gx, gy, gz, lap;
-                grad_lap<Sh>(s_Tt, tx, ty, tz, T0 + k1, gx, gy, gz, lap);
-                const double divu = K1[N + n];
-                const double Z = c.eos == 0 ? cs_Z(c.b_quarter * rho) : 0.0;
-                const double k2 = -(ux * gx + uy * gy + uz * gz) + c.kappa_over_cv * rcp_pos(rho) * lap -
-                                  (T0 + k1) * c.R_over_cv * Z * divu;
-                Tn = T0 + 0.5 * (k1 + k2);
-            }
-            Tout[n] = Tn;
-            const double uu = ux * ux + uy * uy + uz * uz;
-            double f[19];
-            {
-                const double Fx = s_Fx[c0], Fy = s_Fy[c0], Fz = s_Fz[c0];
-                const double uF = ux * Fx + uy * Fy + uz * Fz;
-                double rest = 0.0;
-#pragma unroll
-                for (int i = 1; i < 19; ++i) rest += post_tau1(i, rho, ux, uy, uz, Fx, Fy, Fz, s_X[c0], uu, uF);
-                f[0] = rho - rest;
-            }
-#pragma unroll
-            for (int i = 1; i < 19; ++i) {
-                const V3 v = vel(i);
-                const int q = rnb<Sh>(tx, ty, tz, -v.x, -v.y, -v.z);
-                const double qx = s_ux[q], qy = s_uy[q], qz = s_uz[q];
-                const double Fx = s_Fx[q], Fy = s_Fy[q], Fz = s_Fz[q];
-                f[i] = post_tau1(i, s_rho[q], qx, qy, qz, Fx, Fy, Fz, s_X[q], qx * qx + qy * qy + qz * qz,
-                                 qx * Fx + qy * Fy + qz * Fz);
-            }
-            double rn, jx, jy, jz;
-            pulled_moments3<WALLS>(f, z, G.nz, rn, jx, jy, jz);
-            double Z;
-            const double psin = psi_and_Z(c, rn, Tn, Z);
-            Mout[n] = rn;
-            Mout[N + n] = jx;
-            Mout[2 * (size_t)N + n] = jy;
-            Mout[3 * (size_t)N + n] = jz;
-            Mout[4 * (size_t)N + n] = psin;
-            const double psi0 = Min[4 * (size_t)N + n];
-            part.mass_n += rho;
-            part.mass_next += rn;
-            part.umax = fmax(part.umax, uu);
-            part.rmin = fmin(part.rmin, rho);
-            unsigned fl = 0u;
-            if (!(rho > 0.0)) fl |= kFlagRho;
-            if (c.eos == 0 && c.b_quarter * rho >= 1.0) fl |= kFlagEta;
-            if (psi0 != psi0) fl |= kFlagPsi;
-            if (rho != rho || uu != uu || Tn != Tn || rn != rn) fl |= kFlagNaN;
-            part.flags |= fl;
-        }
-    }
-    part = block_reduce<kMomThreads>(part, s_red, s_ured);
-    finish_launch<kMomThreads>(part, partials, st, step, (int)((step + 1) & 1), 1.0 / (double)N, s_red, s_ured);
-}
-
 // psi of level 0 for the moment state (rho and j come from the host)
 __global__ void d3q19_psi_init(double *__restrict__ M, const double *__restrict__ Tin, Phys c, unsigned N)
 {
@@ -612,38 +396,12 @@ int grid_tiles(int nx, int ny, int nz, int cus)
     return (int)(t < cap ? t : cap);
 }
 
-// Moment state: M^n is the state buffer fin, M^{n+1} goes to fout.
-template <bool WALLS>
-hipError_t step_mom_t(const LatticeLaunch &L, double *U, double *K1)
-{
-    const Grid3 G{L.nx, L.ny, L.nz, (unsigned)((size_t)L.nx * L.ny * L.nz)};
-    const double *Min = (const double *)L.fin;
-    const int gT = grid_tiles<TileBD>(L.nx, L.ny, L.nz, L.resident);
-    const int gC = grid_tiles<TileC>(L.nx, L.ny, L.nz, L.resident);
-    const int gM = grid_tiles<TileM>(L.nx, L.ny, L.nz, L.resident);
-    hipLaunchKernelGGL((d3q19_pass_b<WALLS>), dim3(gT), dim3(kStencilThreads), 0, L.stream, Min, U, L.phys, G, L.st,
-                       (int)(L.step & 1));
-    hipLaunchKernelGGL((d3q19_pass_c<WALLS>), dim3(gC), dim3(kStencilThreads), 0, L.stream, L.Tin, Min, U, K1,
-                       L.phys, G);
-    hipLaunchKernelGGL((d3q19_pass_m<WALLS>), dim3(gM), dim3(kMomThreads), 0, L.stream, L.Tin, L.Tout, Min, U, K1,
-                       (double *)L.fout, L.phys, G, L.partials, L.st, L.step);
-    return hipGetLastError();
-}
-
 }  // namespace
 
-// the larger of the grids that write per-block partials (the moment-state
-// pass, or the z-marching LBM kernel)
-int d3q19_num_blocks(int nx, int ny, int nz, int cus)
-{
-    const int m = grid_tiles<TileM>(nx, ny, nz, cus), z = d3q19_march_blocks(nx, ny, nz, cus);
-    return m > z ? m : z;
-}
+// the grid that writes per-block partials (the z-marching LBM kernel)
+int d3q19_num_blocks(int nx, int ny, int nz, int cus) { return d3q19_march_blocks(nx, ny, nz, cus); }
 
-hipError_t d3q19_launch_step(const LatticeLaunch &L, double *M, double *U, double *K1)
-{
-    return d3q19_march_step(L, U);
-}
+hipError_t d3q19_launch_step(const LatticeLaunch &L, double *U) { return d3q19_march_step(L, U); }
 
 hipError_t d3q19_launch_psi_init(const LatticeLaunch &L, double *M)
 {

@@ -1,8 +1,6 @@
 // D3Q19 building blocks shared by the pass kernels (d3q19.hip) and the
 // z-marching update (d3q19_march.hip): the velocity set and its weights,
-// population storage (FP64, or FP32 deviations from w_i rho_ref), the wet-node
-// wall reconstruction, and the post-collision population at every
-// relaxation time 1.
+// and population storage (FP64, or FP32 deviations from w_i rho_ref).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -74,65 +72,6 @@ struct Pop<float> {
         return wr + (double)d;
     }
 };
-
-// Zero-velocity wet-node reconstruction of the populations of a wall node
-// (z = 0 or nz - 1) that come from beyond the wall, with transverse momentum
-// corrections, then the density and momentum of the pulled set, for the
-// moment-state pass.  Pass A spells out the same statements in its body
-// (called from there, the array is not kept in registers).
-template <bool WALLS>
-__device__ __forceinline__ void pulled_moments3(double (&f)[19], int z, int nz, double &rho, double &jx,
-                                                double &jy, double &jz)
-{
-    if (WALLS && (z == 0 || z == nz - 1)) {
-        const int s = z == 0 ? 1 : -1;
-        double Nx = 0.0, Ny = 0.0;
-#pragma unroll
-        for (int i = 0; i < 19; ++i) {
-            const V3 v = vel(i);
-            if (v.z == 0) {
-                if (v.x) Nx += 0.5 * v.x * f[i];
-                if (v.y) Ny += 0.5 * v.y * f[i];
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < 19; ++i) {
-            const V3 v = vel(i);
-            if (v.z == s) {
-                double r = f[opp(i)];
-                if (v.x) r -= (double)v.x * Nx;
-                if (v.y) r -= (double)v.y * Ny;
-                f[i] = r;
-            }
-        }
-    }
-    rho = jx = jy = jz = 0.0;
-#pragma unroll
-    for (int i = 0; i < 19; ++i) {
-        const V3 v = vel(i);
-        rho += f[i];
-        if (v.x) jx += v.x * f[i];
-        if (v.y) jy += v.y * f[i];
-        if (v.z) jz += v.z * f[i];
-    }
-}
-
-// Post-collision population i at every relaxation time 1 of a node with
-// density rho, force-corrected velocity u, force F and sigma |F_int|^2 /
-// psi^2 = Xs2 (uu = u.u, uF = u.F): f_eq + half of Guo's term + the
-// isotropic sigma term.  Pass D closes the rest population instead, f*_0 =
-// rho - sum_{i>0} f*_i, which equals the i = 0 value in exact arithmetic.
-__device__ __forceinline__ double post_tau1(int i, double rho, double ux, double uy, double uz, double Fx, double Fy,
-                                            double Fz, double Xs2, double uu, double uF)
-{
-    const V3 v = vel(i);
-    const double w = wgt(i);
-    const double cu = cdot(v, ux, uy, uz);
-    const double cF = cdot(v, Fx, Fy, Fz);
-    const double c2 = (double)(v.x * v.x + v.y * v.y + v.z * v.z);
-    return w * (rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu) + 1.5 * (cF - uF) + 4.5 * cu * cF +
-                (c2 - 1.0) * 0.75 * Xs2);
-}
 
 }  // namespace d3
 }  // namespace tplbm

@@ -1,5 +1,6 @@
-// D3Q19 population-state update (FP32 deviations or FP64 populations, every
-// relaxation time 1) as two z-marching kernels.
+// D3Q19 update (every relaxation time 1) as two z-marching kernels: L (the
+// population state: FP32 deviations or FP64 populations) or LM (the FP64
+// moment state, described above its kernel), then E.
 //
 // A block owns a 32 x 16 tile of (x, y) columns and a range of z planes (a
 // segment), and walks the planes upwards keeping one thread per column.  The
@@ -14,7 +15,7 @@
 //     ShanChenForce, zero on wall planes) and gravity (Eqs. Gravity_*), u =
 //     (j + F/2)/rho, and the tau = 1 collision (f_eq plus half of Guo's term
 //     plus the isotropic sigma term), stored as the next level's f*; u and
-//     rho go to U for E; the diagnostics of the level (mass with wall
+//     rho go to U for E (LM: u only); the diagnostics of the level (mass with wall
 //     multiplicities for <rho>, max |u|, min rho, flags) are reduced as in
 //     the other lattice kernels.
 //   E (halo 2): the energy equation (Eq. Energy_Equation) advanced by
@@ -285,9 +286,10 @@ __device__ __forceinline__ double pull_finish(const PullLoads<S> &P, const Phys 
     double f[19];
 #pragma unroll
     for (int i = 0; i < 19; ++i) f[i] = Pop<S>::val(P.f[i], wgt(i) * rz[1 - vel(i).z]);
-    // the statements of pulled_moments3, written out here: passed to it by
-    // reference, the array would be kept in private memory, whose accesses
-    // share the wait counter of the loads in flight
+    // the zero-velocity wet-node reconstruction of the populations from
+    // beyond a wall (with transverse momentum corrections), written out here:
+    // passed to a function by reference, the array would be kept in private
+    // memory, whose accesses share the wait counter of the loads in flight
     if (WALLS && (za == 0 || za == G.nz - 1)) {
         const int s = za == 0 ? 1 : -1;
         double Nx = 0.0, Ny = 0.0;
@@ -569,7 +571,8 @@ constexpr int kEBlocksPerCU = 1;
 template <bool WALLS>
 __global__ __launch_bounds__(kEThreads) void d3q19_march_e(const double *__restrict__ Tin,
                                                                         double *__restrict__ Tout,
-                                                                        const double *__restrict__ U, Phys c,
+                                                                        const double *__restrict__ U,
+                                                                        const double *__restrict__ Rho, Phys c,
                                                                         Grid3 G, MarchG3 M)
 {
     using T = TileE;
@@ -623,7 +626,7 @@ __global__ __launch_bounds__(kEThreads) void d3q19_march_e(const double *__restr
         vx = buf_ld(layer_rsrc(U + zo, plane, beyond), vo, 0u, 0.0);
         vy = buf_ld(layer_rsrc(U + N + zo, plane, beyond), vo, 0u, 0.0);
         vz = buf_ld(layer_rsrc(U + 2 * (size_t)N + zo, plane, beyond), vo, 0u, 0.0);
-        vr = buf_ld(layer_rsrc(U + 3 * (size_t)N + zo, plane, beyond), vrho, 0u, 0.0);
+        vr = buf_ld(layer_rsrc(Rho + zo, plane, beyond), vrho, 0u, 0.0);
     };
     double nT, nx, ny, nzv, nr;
     load(sg.z0 - 2, nT, nx, ny, nzv, nr);
@@ -695,16 +698,18 @@ __global__ __launch_bounds__(kEThreads) void d3q19_march_e(const double *__restr
 // With every relaxation time 1 the post-collision set of a node is a closed
 // function of its (rho, u, F, X), so the state carried between steps can be
 // (rho, j) and T instead of the nineteen populations.  LM takes the LBM part
-// of a step on that state and hands u and rho to E through U, as L does.  One
+// of a step on that state and hands u to E through U (E reads rho from the
+// state itself, which L's populations cannot give it).  One
 // column per thread (the tile, the ring at distance 1, the ring at distance
 // 2); per plane a:
 //   psi of plane a on every column (rho and T read one plane ahead) -> a ring
 //     of four psi planes;
 //   two planes behind, on the tile and the first ring: the Shan-Chen force
 //     and gravity of plane b = a - 2 (zero on wall planes), u = (j + F/2)/rho
-//     and X = sigma |F_int|^2 / psi^2 -> (rho, u, F, X) of plane b in one of
-//     two LDS plane slots; the tile stores u and rho for E and reduces the
-//     level's diagnostics;
+//     and X = sigma |F_int|^2 / psi^2 -> the velocity-independent terms of
+//     the node's post-collision populations (LmVal) in one of two LDS plane
+//     slots; the tile stores u for E and reduces the level's
+//     diagnostics;
 //   three planes behind, on the tile: a column evaluates, for each of the 3 x
 //     3 nodes around it on plane p = a - 3, the post-collision populations
 //     whose velocity carries them to this column -- down to plane p - 1, along
@@ -713,11 +718,10 @@ __global__ __launch_bounds__(kEThreads) void d3q19_march_e(const double *__restr
 //     a wall plane the populations from beyond the wall are the wet-node
 //     reconstruction, whose sums are closed forms (below); the column stores
 //     the next level's (rho, j).
-// Each node's (rho, u, F, X) is read from LDS once per neighbour column
-// rather than once per population, and nothing but (rho, j, T) in and (rho,
-// j) and U out touches memory.  One barrier per plane: the psi slot and the
-// (rho, u, F, X) slot a plane writes were last read before the previous
-// barrier.
+// A node's staged terms are read from LDS once per neighbour column rather
+// than once per population, and nothing but (rho, j, T) in and (rho, j) and U
+// out touches memory.  One barrier per plane: the psi slot and the staged
+// slot a plane writes were last read before the previous barrier.
 //
 // Wall planes: the unknown populations of the wet-node reconstruction are f_i
 // = f_opp(i) - c_x N_x - c_y N_y with N = half the in-plane momentum.  Summed
@@ -726,11 +730,32 @@ __global__ __launch_bounds__(kEThreads) void d3q19_march_e(const double *__restr
 // momentum exactly: rho' = rho_in + 2 D and j' = 0, the no-slip wall.
 //
 // The rest population is its closed form w_0 (rho (1 - 3/2 u.u) - 3/2 u.F -
-// 3/4 X), which the other populations' sum equals in exact arithmetic.
+// 3/4 X), which rho less the other populations' sum equals in exact
+// arithmetic.
 
-// (rho, u, F, X) of a node as LM stages them: one LDS plane slot holds eight
-// planes of the region of halo 1
-constexpr int kLmVals = 8;
+// What LM stages per node of a plane (one LDS slot holds kLmVals planes of
+// the region of halo 1): the terms of the node's post-collision populations
+// (Eqs. Equilibrium and Guo at tau = 1, with the sigma term) that do not
+// depend on the velocity, formed once where the node's force is evaluated.
+// For a velocity c = (c_xy, c_z) with a = c_xy . u, b = c_xy . F, A = rho a +
+// b, the population is w (e0 + 4.5 (c.u)(rho c.u + c.F) + 3 rho c.u + 1.5 c.F
+// + [|c|^2 = 2] s2), and for c_z = +-1 that splits into an even part T0 + Kz
+// + s2 and an odd part 4.5 (a B + u_z A) + L, with T0 the value of the c_z =
+// 0 bracket.
+enum LmVal {
+    kRho,
+    kUx,
+    kUy,
+    kUz,
+    kFx,
+    kFy,
+    kB,    // rho u_z + F_z
+    kL,    // 3 rho u_z + 3/2 F_z
+    kE0,   // rho (1 - 3/2 u.u) - 3/2 u.F
+    kS2,   // 3/4 sigma |F_int|^2 / psi^2
+    kKz,   // 9/2 u_z (rho u_z + F_z)
+    kLmVals
+};
 // 720 columns in 12 full waves: threads 720 .. 767 hold no column and take
 // part in the barriers and the block reduction only
 constexpr int kLmColumns = TileE::Threads + TileE::Ring1 + TileE::Ring2;
@@ -740,72 +765,106 @@ struct Acc4 {
     double r, x, y, z;
 };
 
-// the node terms of a post-collision population (Eqs. Equilibrium, Guo, with
-// the sigma term) that do not depend on the velocity
-struct SrcNode {
-    double rho, ux, uy, uz, Fx, Fy, Fz, even0, sig2;
+// a neighbour's staged terms, read from LDS (the fields a velocity group
+// does not use are never read: the loads are dead code there)
+struct NbVals {
+    double rho, ux, uy, uz, Fx, Fy, B, L, e0, s2, Kz;
 };
-
 template <int RN>
-__device__ __forceinline__ SrcNode src_node(const double (&q)[kLmVals][RN], int k)
+__device__ __forceinline__ NbVals nb_load(const double (&q)[kLmVals][RN], int m)
 {
-    SrcNode s;
-    s.rho = q[0][k];
-    s.ux = q[1][k];
-    s.uy = q[2][k];
-    s.uz = q[3][k];
-    s.Fx = q[4][k];
-    s.Fy = q[5][k];
-    s.Fz = q[6][k];
-    const double X = q[7][k];
-    const double uu = s.ux * s.ux + s.uy * s.uy + s.uz * s.uz;
-    const double uF = s.ux * s.Fx + s.uy * s.Fy + s.uz * s.Fz;
-    s.even0 = s.rho * (1.0 - 1.5 * uu) - 1.5 * uF;
-    s.sig2 = 0.75 * X;
-    return s;
+    return NbVals{q[kRho][m], q[kUx][m], q[kUy][m], q[kUz][m], q[kFx][m], q[kFy][m],
+                  q[kB][m],   q[kL][m],  q[kE0][m], q[kS2][m], q[kKz][m]};
 }
 
-// post-collision population of velocity (CX, CY, CZ) at tau = 1: f_eq + half
-// of Guo's term + the isotropic sigma term, added to an accumulator with its
-// momentum
-template <int CX, int CY, int CZ>
-__device__ __forceinline__ void add_post(Acc4 &a, const SrcNode &s)
+// the populations a column pulls from its neighbour at offset (OX, OY) on
+// plane p: velocity (-OX, -OY, c_z) lands on plane p + c_z, c_z = -1 (lo), 0
+// (mid), +1 (hi) where the velocity set has it
+template <int OX, int OY>
+__device__ __forceinline__ void nb_add(const NbVals &v, Acc4 &lo, Acc4 &mid, Acc4 &hi)
 {
-    constexpr V3 v{CX, CY, CZ};
-    constexpr int c2 = CX * CX + CY * CY + CZ * CZ;
-    constexpr double w = c2 == 1 ? 1.0 / 18.0 : 1.0 / 36.0;
-    const double cu = cdot(v, s.ux, s.uy, s.uz), cF = cdot(v, s.Fx, s.Fy, s.Fz);
-    double e = s.even0 + 4.5 * cu * (s.rho * cu + cF) + (3.0 * s.rho * cu + 1.5 * cF);
-    if (c2 == 2) e += s.sig2;
-    const double f = w * e;
-    a.r += f;
-    if (CX) a.x += CX * f;
-    if (CY) a.y += CY * f;
-    if (CZ) a.z += CZ * f;
-}
-
-// the populations a column at region index k pulls from its neighbour at
-// offset (OX, OY) on plane p: velocity (-OX, -OY, c_z) lands on plane p +
-// c_z, c_z = -1 (lo), 0 (mid), +1 (hi) where the velocity set has it
-template <int OX, int OY, int RN, int RX>
-__device__ __forceinline__ void pull_from(const double (&q)[kLmVals][RN], int k, Acc4 &lo, Acc4 &mid, Acc4 &hi)
-{
-    // one neighbour at a time: the scheduler would otherwise hoist all the
-    // neighbours' LDS reads (72 values) and spill
-    __builtin_amdgcn_sched_barrier(0);
-    const SrcNode s = src_node<RN>(q, k + OY * RX + OX);
-    constexpr int cxy2 = OX * OX + OY * OY;
-    if (cxy2 == 0) {
-        mid.r += (1.0 / 3.0) * (s.even0 - s.sig2);
-        add_post<0, 0, 1>(hi, s);
-        add_post<0, 0, -1>(lo, s);
-    } else if (cxy2 == 1) {
-        add_post<-OX, -OY, 0>(mid, s);
-        add_post<-OX, -OY, 1>(hi, s);
-        add_post<-OX, -OY, -1>(lo, s);
+    constexpr int cx = -OX, cy = -OY;
+    constexpr double w1 = 1.0 / 18.0, w2 = 1.0 / 36.0;
+    if (cx == 0 && cy == 0) {
+        // rest (its closed form) and the two z-axis velocities
+        mid.r += (1.0 / 3.0) * (v.e0 - v.s2);
+        const double wE = w1 * (v.e0 + v.Kz), wO = w1 * v.L;
+        const double fp = wE + wO, fm = wE - wO;
+        hi.r += fp;
+        hi.z += fp;
+        lo.r += fm;
+        lo.z -= fm;
+    } else if (cx * cx + cy * cy == 1) {
+        // an axis velocity in the plane and the two edges above and below it
+        const double a = cx ? cx * v.ux : cy * v.uy;
+        const double b = cx ? cx * v.Fx : cy * v.Fy;
+        const double A = v.rho * a + b;
+        const double T0 = v.e0 + 4.5 * a * A + (3.0 * v.rho * a + 1.5 * b);
+        const double f0 = w1 * T0;
+        const double wE = w2 * (T0 + (v.Kz + v.s2));
+        const double wO = w2 * (4.5 * (a * v.B + v.uz * A) + v.L);
+        const double fp = wE + wO, fm = wE - wO;
+        mid.r += f0;
+        hi.r += fp;
+        lo.r += fm;
+        if (cx) {
+            mid.x += cx * f0;
+            hi.x += cx * fp;
+            lo.x += cx * fm;
+        } else {
+            mid.y += cy * f0;
+            hi.y += cy * fp;
+            lo.y += cy * fm;
+        }
+        hi.z += fp;
+        lo.z -= fm;
     } else {
-        add_post<-OX, -OY, 0>(mid, s);
+        // an edge velocity in the plane
+        const double a = cx * v.ux + cy * v.uy;
+        const double b = cx * v.Fx + cy * v.Fy;
+        const double A = v.rho * a + b;
+        const double f = w2 * ((v.e0 + v.s2) + 4.5 * a * A + (3.0 * v.rho * a + 1.5 * b));
+        mid.r += f;
+        mid.x += cx * f;
+        mid.y += cy * f;
     }
+}
+
+// the pull of a column at region index k from the 3 x 3 neighbours on one
+// staged plane, software-pipelined: each neighbour's LDS reads are issued
+// before the previous neighbour's arithmetic (the scheduling barriers keep
+// the compiler from hoisting all nine neighbours' reads, which would not fit
+// in the registers)
+template <int RN, int RX>
+__device__ __forceinline__ void pull_plane(const double (&q)[kLmVals][RN], int k, Acc4 &lo, Acc4 &mid, Acc4 &hi)
+{
+    NbVals v0 = nb_load<RN>(q, k - RX - 1);
+    __builtin_amdgcn_sched_barrier(0);
+    NbVals v1 = nb_load<RN>(q, k - RX);
+    nb_add<-1, -1>(v0, lo, mid, hi);
+    __builtin_amdgcn_sched_barrier(0);
+    v0 = nb_load<RN>(q, k - RX + 1);
+    nb_add<0, -1>(v1, lo, mid, hi);
+    __builtin_amdgcn_sched_barrier(0);
+    v1 = nb_load<RN>(q, k - 1);
+    nb_add<1, -1>(v0, lo, mid, hi);
+    __builtin_amdgcn_sched_barrier(0);
+    v0 = nb_load<RN>(q, k);
+    nb_add<-1, 0>(v1, lo, mid, hi);
+    __builtin_amdgcn_sched_barrier(0);
+    v1 = nb_load<RN>(q, k + 1);
+    nb_add<0, 0>(v0, lo, mid, hi);
+    __builtin_amdgcn_sched_barrier(0);
+    v0 = nb_load<RN>(q, k + RX - 1);
+    nb_add<1, 0>(v1, lo, mid, hi);
+    __builtin_amdgcn_sched_barrier(0);
+    v1 = nb_load<RN>(q, k + RX);
+    nb_add<-1, 1>(v0, lo, mid, hi);
+    __builtin_amdgcn_sched_barrier(0);
+    v0 = nb_load<RN>(q, k + RX + 1);
+    nb_add<0, 1>(v1, lo, mid, hi);
+    __builtin_amdgcn_sched_barrier(0);
+    nb_add<1, 1>(v0, lo, mid, hi);
 }
 
 template <bool WALLS>
@@ -911,24 +970,28 @@ __global__ __launch_bounds__(kLmThreads) void d3q19_march_lm(const double *__res
             const double ux = beyond ? 0.0 : (x_2 + 0.5 * Fx) * inv;
             const double uy = beyond ? 0.0 : (y_2 + 0.5 * Fy) * inv;
             const double uz = beyond ? 0.0 : (z_2 + 0.5 * Fz) * inv;
+            const double uu = ux * ux + uy * uy + uz * uz;
+            const double uF = ux * Fx + uy * Fy + uz * Fz;
+            const double Bz = r_2 * uz + Fz;
             double(&q)[kLmVals][R1::N] = s_q[b & 1];
-            q[0][r1] = r_2;
-            q[1][r1] = ux;
-            q[2][r1] = uy;
-            q[3][r1] = uz;
-            q[4][r1] = Fx;
-            q[5][r1] = Fy;
-            q[6][r1] = Fz;
-            q[7][r1] = Xs2;
+            q[kRho][r1] = r_2;
+            q[kUx][r1] = ux;
+            q[kUy][r1] = uy;
+            q[kUz][r1] = uz;
+            q[kFx][r1] = Fx;
+            q[kFy][r1] = Fy;
+            q[kB][r1] = Bz;
+            q[kL][r1] = 3.0 * r_2 * uz + 1.5 * Fz;
+            q[kE0][r1] = r_2 * (1.0 - 1.5 * uu) - 1.5 * uF;
+            q[kS2][r1] = 0.75 * Xs2;
+            q[kKz][r1] = 4.5 * uz * Bz;
             if (tile) {
                 const bool live = b >= sg.z0 && b < sg.z1;  // uniform
                 const size_t zb = (size_t)(live ? b : sg.z0) * plane;
                 buf_st(layer_rsrc(U + zb, plane, !live), vst, 0u, ux);
                 buf_st(layer_rsrc(U + N + zb, plane, !live), vst, 0u, uy);
                 buf_st(layer_rsrc(U + 2 * (size_t)N + zb, plane, !live), vst, 0u, uz);
-                buf_st(layer_rsrc(U + 3 * (size_t)N + zb, plane, !live), vst, 0u, r_2);
                 const bool keep = live && mine;
-                const double uu = ux * ux + uy * uy + uz * uz;
                 unsigned fl = 0u;
                 if (!(r_2 > 0.0)) fl |= kFlagRho;
                 if (c.eos == 0 && c.b_quarter * r_2 >= 1.0) fl |= kFlagEta;
@@ -947,15 +1010,7 @@ __global__ __launch_bounds__(kLmThreads) void d3q19_march_lm(const double *__res
         if (tile && p >= sg.z0 - 1) {
             const double(&q)[kLmVals][R1::N] = s_q[p & 1];
             Acc4 dlo = {0.0, 0.0, 0.0, 0.0}, hi = dlo;
-            pull_from<-1, -1, R1::N, R1::RX>(q, r1, dlo, mid, hi);
-            pull_from<0, -1, R1::N, R1::RX>(q, r1, dlo, mid, hi);
-            pull_from<1, -1, R1::N, R1::RX>(q, r1, dlo, mid, hi);
-            pull_from<-1, 0, R1::N, R1::RX>(q, r1, dlo, mid, hi);
-            pull_from<0, 0, R1::N, R1::RX>(q, r1, dlo, mid, hi);
-            pull_from<1, 0, R1::N, R1::RX>(q, r1, dlo, mid, hi);
-            pull_from<-1, 1, R1::N, R1::RX>(q, r1, dlo, mid, hi);
-            pull_from<0, 1, R1::N, R1::RX>(q, r1, dlo, mid, hi);
-            pull_from<1, 1, R1::N, R1::RX>(q, r1, dlo, mid, hi);
+            pull_plane<R1::N, R1::RX>(q, r1, dlo, mid, hi);
             const int qz = p - 1;
             // on a wall plane nothing has arrived from beyond the wall (its
             // planes hold zeros); selects rather than a branch, which the
@@ -1017,7 +1072,7 @@ hipError_t march_t(const LatticeLaunch &L, double *U)
     hipLaunchKernelGGL((d3q19_march_l<S, WALLS>), dim3(M.nblocks), dim3(TileL::Threads), 0, L.stream, (const S *)L.fin,
                        (S *)L.fout, L.Tin, U, L.phys, G, M, L.partials, L.st, L.step, L.rref);
     hipLaunchKernelGGL((d3q19_march_e<WALLS>), dim3(ME.nblocks), dim3(kEThreads), 0, L.stream, L.Tin, L.Tout,
-                       (const double *)U, L.phys, G, ME);
+                       (const double *)U, (const double *)U + 3 * (size_t)G.N, L.phys, G, ME);
     return hipGetLastError();
 }
 
@@ -1030,7 +1085,7 @@ hipError_t march_mom_t(const LatticeLaunch &L, double *U)
     hipLaunchKernelGGL((d3q19_march_lm<WALLS>), dim3(M.nblocks), dim3(kLmThreads), 0, L.stream,
                        (const double *)L.fin, (double *)L.fout, L.Tin, U, L.phys, G, M, L.partials, L.st, L.step);
     hipLaunchKernelGGL((d3q19_march_e<WALLS>), dim3(M.nblocks), dim3(kEThreads), 0, L.stream, L.Tin, L.Tout,
-                       (const double *)U, L.phys, G, M);
+                       (const double *)U, (const double *)L.fin, L.phys, G, M);
     return hipGetLastError();
 }
 

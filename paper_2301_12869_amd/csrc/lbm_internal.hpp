@@ -46,13 +46,13 @@ constexpr int kD3Q19z[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, 
 
 int d2q9_num_blocks(int nx, int ny, int resident, bool moments = false);
 int d3q19_num_blocks(int nx, int ny, int nz, int cus);
-hipError_t d3q19_launch_step(const LatticeLaunch &L, double *M, double *U, double *K1);
+hipError_t d3q19_launch_step(const LatticeLaunch &L, double *U);
 hipError_t d3q19_launch_readout(const LatticeLaunch &L, int field, double *M, double *U, double *out);
 // psi plane of a level-0 moment state M (rho and j set) from rho and L.Tin
 hipError_t d3q19_launch_psi_init(const LatticeLaunch &L, double *M);
-// population-state D3Q19 update by z marching (d3q19_march.hip); U holds at
-// least 4 planes of N doubles (u and rho of the level, handed from the LBM
-// kernel to the energy kernel)
+// D3Q19 update by z marching (d3q19_march.hip), population or moment state;
+// U holds at least 4 planes of N doubles (u and rho of the level, handed
+// from the LBM kernel to the energy kernel)
 int d3q19_march_blocks(int nx, int ny, int nz, int cus);
 hipError_t d3q19_march_step(const LatticeLaunch &L, double *U);
 hipError_t d2q9_launch_step(const LatticeLaunch &L);

@@ -25,7 +25,7 @@ struct tplbm_ctx {
     double *T[2] = {nullptr, nullptr};
     double *partials = nullptr;
     StepState *st = nullptr;
-    double *M = nullptr, *U = nullptr, *K1 = nullptr;  // D3Q19 pass buffers
+    double *M = nullptr, *U = nullptr;  // D3Q19 readout buffers (U also hands u, rho to the energy kernel)
     double *rref = nullptr;   // FP32 deviations: reference density per wall-normal layer
     double *lmass = nullptr;  // per-layer next-level mass of a re-centring
     int nlayers = 0;          // wall-normal layers (ny in 2-D, nz in 3-D)
@@ -85,13 +85,12 @@ bool moments_apply(const tplbm_params &p)
     return (p.lattice == TPLBM_D2Q9 || p.lattice == TPLBM_D3Q19) && p.precision == TPLBM_FP64 && tau_one(p);
 }
 
-// AUTO takes the faster state: the moment state on D2Q9 (its row-marching
-// kernel), the populations on D3Q19 (its z-marching kernels beat the moment
-// passes); MOMENTS asks for the moment state wherever it applies.
+// AUTO takes the faster state, the moments wherever they apply (D2Q9's row
+// march and D3Q19's z march move 64 and 80 B per node-step against 160 and
+// 320 for the FP64 populations); MOMENTS asks for them, POPULATIONS not.
 bool uses_moments(const tplbm_params &p)
 {
-    if (p.state == TPLBM_STATE_MOMENTS) return moments_apply(p);
-    return p.state == TPLBM_STATE_AUTO && p.lattice == TPLBM_D2Q9 && moments_apply(p);
+    return (p.state == TPLBM_STATE_MOMENTS || p.state == TPLBM_STATE_AUTO) && moments_apply(p);
 }
 
 int validate(const tplbm_params *p)
@@ -183,11 +182,13 @@ Layout layout_of(const tplbm_params &p)
     L.f_bytes = align256(q_of(p) * N * elem);
     L.T_bytes = align256(N * 8);
     if (p.lattice == TPLBM_D3Q19) {
-        // pass buffers: M (rho, j, psi), U (u, F, sigma |F_int|^2 / psi^2), K1 (k1, div u);
-        // the moment state is M itself (5 planes) and needs no separate M
+        // readout buffers: M (rho, j, psi), U (u, F, sigma |F_int|^2 / psi^2;
+        // a step hands u and rho from the LBM kernel to the energy kernel in
+        // its first 4 planes); the moment state is M itself (5 planes: rho,
+        // j and the readout's psi) and needs no separate M
         const bool mom = uses_moments(p);
         if (mom) L.f_bytes = align256(5 * N * 8);
-        L.pass_bytes = (mom ? 0 : align256(5 * N * 8)) + align256(7 * N * 8) + align256(2 * N * 8);
+        L.pass_bytes = (mom ? 0 : align256(5 * N * 8)) + align256(7 * N * 8);
         L.nblocks = d3q19_num_blocks(p.nx, p.ny, p.nz, 1 << 20);
     } else {
         // the moment state holds 3 planes; the readout scratch reuses the
@@ -313,7 +314,6 @@ int tplbm_create(const tplbm_params *p, void *dev_workspace, size_t bytes, void 
     if (p->lattice == TPLBM_D3Q19) {
         if (!c->mom) { c->M = (double *)q; q += align256(5 * c->N * 8); }
         c->U = (double *)q; q += align256(7 * c->N * 8);
-        c->K1 = (double *)q; q += align256(2 * c->N * 8);
     }
     c->nlayers = layers_of(*p);
     if (p->precision == TPLBM_FP32_DEV) {
@@ -487,7 +487,7 @@ int tplbm_step_async(tplbm_ctx *c, int64_t nsteps)
                                              c->stream));
         LatticeLaunch L = launch_of(c);
         if (c->p.lattice == TPLBM_D3Q19)
-            HIP_OK(c, d3q19_launch_step(L, c->M, c->U, c->K1));
+            HIP_OK(c, d3q19_launch_step(L, c->U));
         else
             HIP_OK(c, d2q9_launch_step(L));
         c->cur = 1 - c->cur;
