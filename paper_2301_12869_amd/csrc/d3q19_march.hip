@@ -233,6 +233,25 @@ __device__ __forceinline__ Col make_col(const Grid3 &G, int x0, int y0, int rx, 
     return c;
 }
 
+// Shan-Chen sum s = sum_i w(|c_i|^2) psi(x + c_i) c_i (w(1) = 1/6, w(2) =
+// 1/12) from three LDS planes of psi (below, own, above) at region index r,
+// the neighbours grouped as in grad_lap_planes
+template <int RX>
+__device__ __forceinline__ void sc_sum_planes(const double *__restrict__ pm, const double *__restrict__ p0,
+                                              const double *__restrict__ pp, int r, double &sx, double &sy,
+                                              double &sz)
+{
+    const double ea = p0[r + 1 + RX], eb = p0[r + 1 - RX], ec = p0[r - 1 + RX], ed = p0[r - 1 - RX];
+    const double bxp = pm[r + 1], bxm = pm[r - 1], byp = pm[r + RX], bym = pm[r - RX];
+    const double axp = pp[r + 1], axm = pp[r - 1], ayp = pp[r + RX], aym = pp[r - RX];
+    const double ex = ((ea + eb) - (ec + ed)) + ((bxp - bxm) + (axp - axm));
+    const double ey = ((ea - eb) + (ec - ed)) + ((byp - bym) + (ayp - aym));
+    const double ez = ((axp + axm) + (ayp + aym)) - ((bxp + bxm) + (byp + bym));
+    sx = (1.0 / 6.0) * (p0[r + 1] - p0[r - 1]) + (1.0 / 12.0) * ex;
+    sy = (1.0 / 6.0) * (p0[r + RX] - p0[r - RX]) + (1.0 / 12.0) * ey;
+    sz = (1.0 / 6.0) * (pp[r] - pm[r]) + (1.0 / 12.0) * ez;
+}
+
 // ---- L: pull, psi, force, u, collision -------------------------------------
 
 // Loads of one column at one plane: the nineteen pulled values f*_i(x - c_i)
@@ -393,16 +412,8 @@ __global__ __launch_bounds__(TileL::Threads) void d3q19_march_l(const S *__restr
             double Fx = 0.0, Fy = 0.0, Fz = 0.0, Xs2 = 0.0;
             const double psi0 = s_psi[b & 3][own.r];
             if (!wall) {
-                double sx = 0.0, sy = 0.0, sz = 0.0;
-#pragma unroll
-                for (int i = 1; i < 19; ++i) {
-                    const V3 v = vel(i);
-                    const double w = i < 7 ? 1.0 / 6.0 : 1.0 / 12.0;
-                    const double p = s_psi[(b + v.z) & 3][own.r + v.y * R::RX + v.x];
-                    if (v.x) sx += w * v.x * p;
-                    if (v.y) sy += w * v.y * p;
-                    if (v.z) sz += w * v.z * p;
-                }
+                double sx, sy, sz;
+                sc_sum_planes<R::RX>(s_psi[(b - 1) & 3], s_psi[b & 3], s_psi[(b + 1) & 3], own.r, sx, sy, sz);
                 const double mg = -c.G * psi0;
                 Fx = mg * sx;
                 Fy = mg * sy;
@@ -503,29 +514,33 @@ __device__ __forceinline__ DivPart div_part(const double *__restrict__ ux, const
 
 // Isotropic gradient and Laplacian of a field from three LDS planes (below,
 // own, above) at region index r: grad = 3 sum w c phi, lap = 6 sum w (phi_i -
-// phi_0), in the order of the velocity set.
+// phi_0).  The eighteen neighbours are grouped so that the components share
+// their partial sums: the four in-plane edges through (a + b) -+ (c + d) and
+// (a - b) + (c - d), the four edges above and below through their x and y
+// differences and their sum, the six axis neighbours through differences
+// and one sum (6 w_1 + 12 w_2 = 2/3 multiplies phi_0).
 template <int RX>
 __device__ __forceinline__ void grad_lap_planes(const double *__restrict__ pm, const double *__restrict__ p0,
                                                 const double *__restrict__ pp, int r, double &gx, double &gy,
                                                 double &gz, double &lap)
 {
+    constexpr double w1 = 1.0 / 18.0, w2 = 1.0 / 36.0;
     const double c0 = p0[r];
-    gx = gy = gz = lap = 0.0;
-#pragma unroll
-    for (int i = 1; i < 19; ++i) {
-        const V3 v = vel(i);
-        const double *pl = v.z < 0 ? pm : (v.z > 0 ? pp : p0);
-        const double p = pl[r + v.y * RX + v.x];
-        const double w = wgt(i);
-        if (v.x) gx += w * v.x * p;
-        if (v.y) gy += w * v.y * p;
-        if (v.z) gz += w * v.z * p;
-        lap += w * (p - c0);
-    }
-    gx *= 3.0;
-    gy *= 3.0;
-    gz *= 3.0;
-    lap *= 6.0;
+    // in-plane edges (+1, +1), (+1, -1), (-1, +1), (-1, -1)
+    const double ea = p0[r + 1 + RX], eb = p0[r + 1 - RX], ec = p0[r - 1 + RX], ed = p0[r - 1 - RX];
+    const double s1 = ea + eb, s2 = ec + ed;
+    const double exy_x = s1 - s2, exy_y = (ea - eb) + (ec - ed), exy_s = s1 + s2;
+    // edges below and above: (+-1, 0, -+1) and (0, +-1, -+1)
+    const double bxp = pm[r + 1], bxm = pm[r - 1], byp = pm[r + RX], bym = pm[r - RX];
+    const double axp = pp[r + 1], axm = pp[r - 1], ayp = pp[r + RX], aym = pp[r - RX];
+    const double bs = (bxp + bxm) + (byp + bym), as = (axp + axm) + (ayp + aym);
+    // axis neighbours
+    const double xp = p0[r + 1], xm = p0[r - 1], yp = p0[r + RX], ym = p0[r - RX], zp = pp[r], zm = pm[r];
+    const double ax_s = ((xp + xm) + (yp + ym)) + (zp + zm);
+    gx = (3.0 * w1) * (xp - xm) + (3.0 * w2) * (exy_x + ((bxp - bxm) + (axp - axm)));
+    gy = (3.0 * w1) * (yp - ym) + (3.0 * w2) * (exy_y + ((byp - bym) + (ayp - aym)));
+    gz = (3.0 * w1) * (zp - zm) + (3.0 * w2) * (as - bs);
+    lap = (6.0 * w1) * ax_s + (6.0 * w2) * (exy_s + (bs + as)) - 4.0 * c0;
 }
 
 // div u of a column accumulated over the planes: when the contributions of
@@ -951,16 +966,8 @@ __global__ __launch_bounds__(kLmThreads) void d3q19_march_lm(const double *__res
             const double psi0 = s_psi[b & 3][col.r];
             // evaluated everywhere and zeroed on wall planes and beyond them
             // (psi there is finite): no branch around the LDS reads
-            double sx = 0.0, sy = 0.0, sz = 0.0;
-#pragma unroll
-            for (int i = 1; i < 19; ++i) {
-                const V3 v = vel(i);
-                const double w = i < 7 ? 1.0 / 6.0 : 1.0 / 12.0;
-                const double p = s_psi[(b + v.z) & 3][col.r + v.y * R2::RX + v.x];
-                if (v.x) sx += w * v.x * p;
-                if (v.y) sy += w * v.y * p;
-                if (v.z) sz += w * v.z * p;
-            }
+            double sx, sy, sz;
+            sc_sum_planes<R2::RX>(s_psi[(b - 1) & 3], s_psi[b & 3], s_psi[(b + 1) & 3], col.r, sx, sy, sz);
             const bool off = wall || beyond;
             const double mg = off ? 0.0 : -c.G * psi0;
             const double Fx = mg * sx, Fy = mg * sy;
