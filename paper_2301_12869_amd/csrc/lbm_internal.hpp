@@ -16,7 +16,7 @@ struct LatticeLaunch {
     Phys phys;
     int nx, ny, nz;
     bool fp32, tau1, walls;
-    bool moments;         // the state is moments (D2Q9: rho, j_x, j_y; D3Q19: rho, j, psi), not populations
+    bool moments;         // the state is moments (D2Q9: rho, j_x, j_y; D3Q19: rho, j and the readout's psi plane), not populations
     int resident;         // blocks of the persistent grid (two per compute unit)
     double *partials;     // 5 doubles per block
     StepState *st;

@@ -36,7 +36,7 @@ struct tplbm_ctx {
     int resident = 0;
     size_t N = 0;
     int Q = 9;
-    bool mom = false;  // state carried as moments: D2Q9 (rho, j_x, j_y), D3Q19 (rho, j, psi)
+    bool mom = false;  // state carried as moments: D2Q9 (rho, j_x, j_y), D3Q19 (rho, j; a fifth plane for the readout's psi)
     int planes = 9;    // state planes per node between steps (Q, or 3 / 5 with mom)
     Phys phys;
     bool have_state = false;

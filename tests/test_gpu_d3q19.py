@@ -124,11 +124,11 @@ def test_fp32_deviation_several_tiles(T, orc, crit):
 @pytest.mark.parametrize("shape,walls,form", [((70, 9, 11), True, 2), ((33, 10, 7), False, 1),
                                               ((40, 12, 9), True, 3)])
 def test_moment_state_matches_population_state(T, orc, crit, shape, walls, form):
-    """The moment state carries (rho, j, psi) and T between steps; the
-    nineteen-population state (the default for FP64 D3Q19) computes the same
-    expressions, so the two agree to rounding (differently fused
-    multiply-adds), on lattices spanning several tiles of both kernels with
-    ragged edges."""
+    """The moment state (the FP64 default) carries (rho, j) and T between
+    steps; the nineteen-population state evaluates the same post-collision
+    populations, so the two agree to rounding (differently grouped sums, the
+    rest population closed by mass or by its closed form), on lattices
+    spanning several tiles of both kernels with ragged edges."""
     _log(f"case d3q19 moment vs population {shape} walls={walls} form={form}")
     rho0, T0 = _state(orc, crit, shape, 8, shape[2] // 3)
     pop = _gpu(T, shape, walls, form, 2e-4, rho0, T0, 300)
