@@ -712,6 +712,7 @@ static int d3q19_run(const orc_params *P, double *f, double *T, int64_t nsteps, 
                      orc_diag *dg);
 static int d3q19_macro_out(const orc_params *P, const double *f, const double *T, double *rho,
                            double *ux, double *uy, double *uz, double *peos, double *pnn);
+static int d3q19_collide_out(const orc_params *P, const double *f, const double *T, double *fstar);
 
 /* ======================================================================
  * Public entry points
@@ -892,7 +893,7 @@ int orc_macro(const orc_params *P, const double *f, const double *T, double *rho
 }
 
 /* One collision without streaming, for the algebra tests: fstar receives the
- * post-collision populations of every node (D2Q9 and D1Q3). */
+ * post-collision populations of every node (D2Q9, D1Q3 and D3Q19). */
 int orc_collide(const orc_params *P, const double *f, const double *T, double *fstar)
 {
     int rc = validate(P);
@@ -929,6 +930,7 @@ int orc_collide(const orc_params *P, const double *f, const double *T, double *f
         d1q3_free(&w);
         return ORC_OK;
     }
+    if (P->lattice == 3) return d3q19_collide_out(P, f, T, fstar);
     return ORC_EUNSUPPORTED;
 }
 
@@ -1205,6 +1207,28 @@ static int d3q19_run(const orc_params *P, double *f, double *T, int64_t nsteps, 
     memset(&w, 0, sizeof w);
     if (d3q19_alloc(P, &w)) { d3q19_free(&w); return ORC_EINVAL; }
     for (int64_t s = 0; s < nsteps; ++s) d3q19_step_once(P, f, T, &w, flags, dg);
+    d3q19_free(&w);
+    return ORC_OK;
+}
+
+/* the post-collision populations of one step (the step's own intermediate,
+ * taken on copies of f and T) */
+static int d3q19_collide_out(const orc_params *P, const double *f, const double *T, double *fstar)
+{
+    d3_init();
+    size_t N = (size_t)P->nx * P->ny * P->nz;
+    int flags = 0;
+    orc_diag dg;
+    d3_work w;
+    memset(&w, 0, sizeof w);
+    if (d3q19_alloc(P, &w)) { d3q19_free(&w); return ORC_EINVAL; }
+    double *fc = (double *)malloc(sizeof(double) * 19 * N);
+    double *Tc = (double *)malloc(sizeof(double) * N);
+    memcpy(fc, f, sizeof(double) * 19 * N);
+    memcpy(Tc, T, sizeof(double) * N);
+    d3q19_step_once(P, fc, Tc, &w, &flags, &dg);
+    memcpy(fstar, w.fs, sizeof(double) * 19 * N);
+    free(fc); free(Tc);
     d3q19_free(&w);
     return ORC_OK;
 }

@@ -397,3 +397,46 @@ def test_bulk_normal_pressure_gradient_balances_gravity(orc, crit):
     for y in list(range(8, 24)) + list(range(42, 56)):
         dp = (pyy[y + 1] - pyy[y - 1]) / 2
         assert dp == pytest.approx(-rho[y] * g, rel=2e-2)
+
+
+def test_d3q19_wall_planes_close_in_form(orc, crit):
+    """Zou-He no-slip wet-node walls on D3Q19: the five reconstructed
+    populations of a wall node add the density D of the known populations
+    that cross the wall plane from the lattice side and cancel the momentum,
+    so after the step rho = rho_in + 2 D (rho_in: the populations along the
+    plane) and j = 0.  The moment-state kernel takes these sums instead of
+    forming the populations; here the oracle's own reconstruction must give
+    them from its post-collision populations."""
+    _, T_c, _ = crit
+    nx, ny, nz = 5, 4, 7
+    P = orc.make_params("D3Q19", nx=nx, ny=ny, nz=nz, walls=True, gravity_form=2, g=2e-4)
+    rv, rl, _ = orc.coexistence(P, 0.8 * T_c)
+    rho0 = W.layered_density((nz, ny, nx), 3, rl, rv, 2e-2, seed=3)
+    T0 = W.wall_temperature_field((nz, ny, nx), 0.8 * T_c, 0.86 * T_c, 0.79 * T_c)
+    f = orc.init_rest(P, rho0.ravel())
+    T = T0.ravel().copy()
+    orc.step(P, f, T, 20)  # away from rest: the populations crossing the walls differ
+    c, _ = orc.d3q19_velocities()
+    fs = orc.collide(P, f, T).reshape(19, nz, ny, nx)
+    orc.step(P, f, T, 1)
+    m = orc.macro(P, f, T)
+    rho = m["rho"].reshape(nz, ny, nx)
+    for z, s in ((0, 1), (nz - 1, -1)):
+        rin = np.zeros((ny, nx))
+        D = np.zeros((ny, nx))
+        jin = np.zeros((ny, nx))  # the in-plane x momentum, which the reconstruction cancels
+        for i in range(19):
+            cx, cy, cz = (int(v) for v in c[i])
+            if cz == s:
+                continue  # comes from beyond the wall: reconstructed
+            src = np.roll(np.roll(fs[i, z - cz], cy, axis=0), cx, axis=1)  # f*_i(x - c_i)
+            if cz == 0:
+                rin += src
+                jin += cx * src
+            else:
+                D += src
+        assert np.abs(rho[z] - (rin + 2.0 * D)).max() < 1e-14 * rho.max(), z
+        # the momentum to cancel is not trivially zero (about 5e-6 here)
+        assert np.abs(jin).max() > 1e-7
+        for k in ("ux", "uy", "uz"):
+            assert np.abs(m[k].reshape(nz, ny, nx)[z]).max() < 1e-14, (z, k)
