@@ -73,12 +73,14 @@ def _state(orc, crit, shape, seed, layers):
 @pytest.mark.parametrize("shape,walls,form", [((6, 5, 14), True, 1), ((6, 5, 14), True, 2),
                                               ((7, 4, 9), False, 2), ((1, 1, 20), True, 2),
                                               ((5, 6, 13), True, 3), ((70, 9, 11), True, 2),
-                                              ((40, 35, 24), True, 2), ((33, 20, 17), False, 2)])
+                                              ((40, 35, 24), True, 2), ((33, 20, 17), False, 2),
+                                              ((4, 3, 3), True, 2), ((3, 2, 3), False, 2)])
 def test_small_lattices_fp64(T, orc, crit, shape, walls, form):
     """The moment state (rho, j and T carried between steps) against the
     oracle, on tiles wider than the lattice, several 32 x 16 tiles with ragged
-    edges, and z segments (24 and 17 planes make three and two) with walls
-    and periodic in z."""
+    edges, z segments (24 and 17 planes make three and two) with walls and
+    periodic in z, and the shallowest lattices (3 planes: one interior plane
+    between two walls, or a periodic stack the march wraps around)."""
     _log(f"case d3q19 fp64 moment state {shape} walls={walls} form={form}")
     rho0, T0 = _state(orc, crit, shape, 5, shape[2] // 3)
     want = _oracle(orc, shape, walls, form, 2e-4, rho0, T0, 200)
