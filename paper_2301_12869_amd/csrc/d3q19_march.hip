@@ -1098,8 +1098,14 @@ hipError_t march_mom_t(const LatticeLaunch &L, double *U)
 
 }  // namespace
 
-// the LBM kernel writes the per-block partials
-int d3q19_march_blocks(int nx, int ny, int nz, int cus) { return march_grid3<TileL>(nx, ny, nz, cus).nblocks; }
+// the LBM kernel (L, or LM on E's grid) writes the per-block partials: room
+// for the larger grid
+int d3q19_march_blocks(int nx, int ny, int nz, int cus)
+{
+    const int l = march_grid3<TileL>(nx, ny, nz, cus).nblocks;
+    const int lm = march_grid3<TileE>(nx, ny, nz, cus, kEBlocksPerCU).nblocks;
+    return l > lm ? l : lm;
+}
 
 hipError_t d3q19_march_step(const LatticeLaunch &L, double *U)
 {
